@@ -1,0 +1,177 @@
+/*
+ * gg.h -- C ABI of the MI355X (gfx950) indexed similar-DNA-sequence search.
+ *
+ * The method is Genoogle's (F. F. Albrecht, arXiv 1507.02987): an inverted index
+ * of a data bank's non-overlapping k-base windows (Sections 2 and 2.1) is probed
+ * with every overlapping window of a query; index hits are grouped, chained into
+ * HSPs, extended, merged, selected by length, aligned with a banded
+ * Smith-Waterman and reported by score (Section 2.2, seven phases).
+ *
+ * Every stage of a search runs as a HIP kernel on the GPU.  All integers are
+ * little-endian; coordinates are 0-based and intervals half-open.  The library
+ * allocates its own device memory and streams; no torch type appears here.
+ *
+ * Ownership: the caller owns every input and output buffer and may reuse it as
+ * soon as a call returns (inputs are copied before return).  Handles are owned by
+ * the library until the matching _free/_destroy call.
+ *
+ * Thread safety: a gg_index is read-only after build and may be shared by any
+ * number of threads; concurrent gg_search / gg_search_batch calls on one index
+ * each take their own stream and workspace.  A gg_server may be used from many
+ * threads.
+ */
+#ifndef GG_H
+#define GG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GG_OK = 0,
+    GG_EINVAL = 1,    /* bad argument, byte outside {A,C,G,T,U} (either case), k outside 1..16 */
+    GG_ENOMEM = 2,    /* host or device allocation failed */
+    GG_EDEVICE = 3,   /* a HIP call failed, or no usable GPU */
+    GG_EAGAIN = 4,    /* served query not finished yet */
+    GG_ETRUNC = 5,    /* more hits than `cap`: the first `cap` are written, *n_out is the count */
+    GG_ENOTFOUND = 6, /* unknown or already collected ticket */
+    GG_EBUDGET = 7    /* one query's hits do not fit the hit-buffer budget */
+} gg_status;
+
+typedef struct gg_index gg_index;   /* device-resident data bank and inverted index */
+typedef struct gg_server gg_server; /* continuous-batching request loop */
+
+/*
+ * Run-time parameters (Section 2, last paragraph: the maximum distance between
+ * index entries of one HSP, the minimum HSP size and the extension drop-off;
+ * Section 2.2 phase 5: the maximum number of alignments).  Penalties are positive
+ * numbers that are subtracted.  A gap of length g costs gap_open + g * gap_extend.
+ */
+typedef struct {
+    int32_t match;       /* +1 in the paper's workloads */
+    int32_t mismatch;    /* 3 */
+    int32_t gap_open;    /* 5 */
+    int32_t gap_extend;  /* 2 */
+    int32_t band;        /* W: half-width of the Smith-Waterman band, 0..63 (32) */
+    int32_t xdrop;       /* X: extension stops when the running sum is > X below its best (20) */
+    int32_t max_gap;     /* G: hits chain when qpos_next - (qpos_last + k) <= G (22) */
+    int32_t min_hsp_len; /* M: a chained run [qs, qe) is kept when qe - qs >= M (22) */
+    int32_t max_hits;    /* N: HSPs kept by length before alignment; <= 0 keeps all */
+} gg_params;
+
+/* One reported alignment (Section 2.2 phase 7): its score, its span in the query
+ * and in data-bank sequence seq_id, and the HSP box it was aligned in. */
+typedef struct {
+    int32_t seq_id, score, q_start, q_end, d_start, d_end;
+    int32_t box_q_start, box_q_end, box_d_start, box_d_end, box_len;
+} gg_hit;
+
+/* Per-query work counts of one search. */
+typedef struct {
+    int64_t n_kmers;    /* query windows probed */
+    int64_t n_hits;     /* index hits gathered */
+    int64_t n_cands;    /* chained runs kept by the length filter */
+    int64_t n_merged;   /* HSP boxes after extension and merging */
+    int64_t n_selected; /* boxes aligned */
+    int64_t n_cells;    /* banded Smith-Waterman cells computed */
+    int64_t n_out;      /* alignments with score > 0 */
+} gg_stats;
+
+/*
+ * Format a data bank and build its inverted index on GPU `device` (Sections 2,
+ * 2.1): every base is coded in 2 bits; each sequence is cut into
+ * non-overlapping windows of k bases (a shorter tail is not indexed); list c of
+ * the 4^k-entry main vector holds every (sequence id, position) whose window has
+ * code c, in ascending (sequence, position) order.
+ *
+ * seqs     : all sequences' ASCII bytes, concatenated (host memory)
+ * seq_off  : n_seqs + 1 non-decreasing offsets into seqs; sequence s is
+ *            seqs[seq_off[s] .. seq_off[s+1])
+ * k        : window length, 1..16; 4^k list heads are kept on the device
+ * device   : HIP device ordinal
+ * Errors   : GG_EINVAL (bad byte, bad offsets, k, more than 2^31-1 sequences or a
+ *            sequence longer than 2^31-1, more than 2^32-1 windows), GG_ENOMEM,
+ *            GG_EDEVICE.  Nothing is left allocated on error.
+ */
+gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
+                         int32_t device, gg_index **out);
+void gg_index_free(gg_index *index);
+
+/* Sizes of a built index: windows indexed, bases, sequences, k. */
+gg_status gg_index_info(const gg_index *index, int64_t *n_postings, int64_t *n_bases,
+                        int64_t *n_seqs, int32_t *k);
+
+/*
+ * Device bytes the batched search may use for index hits at once (two 8-byte
+ * keys per hit).  Queries are processed in waves that fit it; a single query
+ * whose hits exceed it fails with GG_EBUDGET.  0 restores the default.
+ */
+gg_status gg_index_set_hit_budget(gg_index *index, uint64_t bytes);
+
+/*
+ * Search one ASCII query (Section 2.2, all seven phases; forward strand only).
+ * out/cap  : room for `cap` hits; *n_out receives the number found.  Hits are in
+ *            descending score, then ascending (seq_id, q_start, d_start, q_end,
+ *            d_end, box_q_start, box_d_start, box_q_end, box_d_end).
+ * A query shorter than k has no hits (GG_OK, *n_out = 0).
+ * Errors   : GG_EINVAL, GG_ETRUNC (first `cap` written), GG_EBUDGET, GG_ENOMEM,
+ *            GG_EDEVICE.
+ */
+gg_status gg_search(const gg_index *index, const char *query, int64_t qlen,
+                    const gg_params *params, gg_hit *out, int32_t cap, int32_t *n_out);
+
+/*
+ * Search n_q queries in one batched pass of the same kernels: the results are
+ * those of n_q separate gg_search calls.
+ * qbuf/qoff: queries' ASCII bytes concatenated, n_q + 1 non-decreasing offsets
+ * out      : n_q * cap hits; query q's go to out[q * cap ..]
+ * n_out    : n_q counts (each may exceed cap: then that query is truncated and the
+ *            call returns GG_ETRUNC after filling every query)
+ * stats    : n_q work counts, or NULL
+ */
+gg_status gg_search_batch(const gg_index *index, const char *qbuf, const int64_t *qoff,
+                          int64_t n_q, const gg_params *params, gg_hit *out, int32_t cap,
+                          int32_t *n_out, gg_stats *stats);
+
+/*
+ * Per-stage GPU timing of batched searches on this index, for roofline reports.
+ * Enabling records HIP events around each stage on the stream it runs on.
+ * stage names: "encode", "scan", "gather", "sort", "chain", "extend", "merge",
+ * "select", "align", "report".  ms is the summed kernel time, launches the number
+ * of timed stage runs, units the stage's work units (hits for gather/chain, key
+ * passes x keys for sort, cells for align, ...).
+ */
+gg_status gg_profile_enable(gg_index *index, int32_t on);
+gg_status gg_profile_read(const gg_index *index, const char *stage, double *ms,
+                          int64_t *launches, int64_t *units);
+
+/*
+ * Served form: a request loop that admits queries as they arrive, within a
+ * device hit-buffer budget and a number of in-flight slots, and runs the
+ * admitted ones together on the GPU while new requests keep arriving.  Each
+ * query's result equals its gg_search result.
+ * hit_budget_bytes : device bytes for hit keys of all in-flight queries (0: default)
+ * max_slots        : queries in flight at once (>= 1)
+ */
+gg_status gg_server_create(const gg_index *index, const gg_params *params,
+                           uint64_t hit_budget_bytes, int32_t max_slots, gg_server **out);
+/* Queue one query (copied before return); *ticket identifies it for gg_serve_poll. */
+gg_status gg_serve_submit(gg_server *server, const char *query, int64_t qlen, uint64_t *ticket);
+/*
+ * Wait up to timeout_us (0: do not wait, < 0: wait until done) for a ticket.
+ * GG_EAGAIN while it is pending; otherwise its status (GG_OK, GG_ETRUNC, ...) with
+ * its hits written as for gg_search, and the ticket is released.
+ */
+gg_status gg_serve_poll(gg_server *server, uint64_t ticket, gg_hit *out, int32_t cap,
+                        int32_t *n_out, int32_t timeout_us);
+/* Stop the loop; pending tickets are cancelled. */
+void gg_server_destroy(gg_server *server);
+
+const char *gg_strerror(gg_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,116 @@
+// Internal declarations shared by the GPU library's own sources (kernels and
+// host runtime).  Nothing here is part of the public ABI in include/gg.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gg {
+
+constexpr int32_t kNegInf = -(1 << 30);  // minus infinity of the alignment DP
+constexpr int kBlock = 256;              // threads per block for the stream kernels
+constexpr int kItems = 8;                // keys per thread in the radix passes
+constexpr int kTile = kBlock * kItems;   // keys per radix tile
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kGatherCap = 4096;         // positions of one gather tile kept in LDS
+constexpr int kMaxBand = 63;             // band half-width supported by one wave
+
+// A chained run of hits: query (local to the wave), sequence, diagonal, [qs, qe).
+struct Cand {
+    int32_t q, s, d, qs, qe;
+};
+
+// An HSP box: query-local index, sequence, query and data-bank intervals and the
+// extreme diagonals of the runs merged into it.  q < 0 marks an empty slot.
+struct Box {
+    int32_t q, s, qs, qe, ds, de, dmin, dmax;
+};
+
+// One alignment; same layout as gg_hit, plus the query-local index in front.
+struct Align {
+    int32_t q;
+    int32_t seq_id, score, q_start, q_end, d_start, d_end;
+    int32_t box_q_start, box_q_end, box_d_start, box_d_end, box_len;
+};
+
+// Bit layout of the 64-bit hit key: [q | s | diag + bias | qpos], most
+// significant first.  Sorting the keys orders hits by (q, s, diag, qpos).
+struct HitKeyLayout {
+    int bq, bs, bd, bp;  // field widths
+    int32_t bias;        // added to the diagonal so that it is >= 0
+};
+
+// Which box field feeds a sort-key field.
+enum BoxField : int32_t {
+    F_Q = 0, F_S, F_QS, F_QE, F_DS, F_DE, F_LEN_DESC
+};
+enum AlignField : int32_t {
+    A_Q = 0, A_SCORE_DESC, A_SEQ, A_QS, A_QE, A_DS, A_DE, A_BQS, A_BQE, A_BDS, A_BDE
+};
+
+// Up to 8 fields packed into one 64-bit key word.
+struct KeyWord {
+    int32_t n;
+    int32_t field[8];
+    int32_t shift[8];
+    int32_t bits;        // width of the whole word
+    int32_t desc_max[8]; // for *_DESC fields: value stored is desc_max - v
+};
+
+// ---------------------------------------------------------------- launchers
+// Every launcher only enqueues work on `st`; sizes are checked by the caller.
+
+void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
+                         int32_t k, const uint32_t *list_off, uint8_t *qcode, uint32_t *kcode,
+                         uint32_t *cnt, int32_t *qid, int32_t *err, hipStream_t st);
+// out[i] = sum of in[0..i) for i in [0, n]; in is u32, out u64.
+void launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *partials,
+                            hipStream_t st);
+// in-place style exclusive scan of u32 (out may equal in), n + 1 outputs.
+void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
+                     hipStream_t st);
+size_t scan_partials_needed(int64_t n);
+void launch_query_totals(const uint64_t *hoff, const int64_t *qoff, int32_t nq, uint64_t *qtot,
+                         hipStream_t st);
+void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
+                      const int32_t *qid, const uint32_t *list_off, int32_t qa, int64_t g0,
+                      int64_t g1, HitKeyLayout lay, uint32_t *hrel, uint32_t *pbase, uint64_t *akey,
+                      hipStream_t st);
+void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
+                   int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
+                   uint64_t *keys, hipStream_t st);
+// Stable LSD radix sort of n keys (and optional u32 values) on bits [lo, hi).
+// Returns which buffer holds the result: 0 = keys/vals, 1 = keys_alt/vals_alt.
+int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
+               uint32_t n, int lo, int hi, uint32_t *hist, uint32_t *partials, hipStream_t st);
+size_t radix_hist_needed(uint32_t n);
+void launch_chain(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k, int32_t max_gap,
+                  int32_t min_len, Cand *out, uint32_t cap, uint32_t *count,
+                  uint32_t *cand_per_q, hipStream_t st);
+void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
+                   int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
+                   int32_t mismatch, int32_t xdrop, Box *out, hipStream_t st);
+void launch_box_keys(const Box *b, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
+                     const uint32_t *perm, hipStream_t st);
+void launch_align_keys(const Align *a, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
+                       const uint32_t *perm, hipStream_t st);
+void launch_iota(uint32_t *v, uint32_t n, hipStream_t st);
+void launch_gather_boxes(const Box *in, const uint32_t *perm, uint32_t n, Box *out,
+                         hipStream_t st);
+void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Align *out,
+                          hipStream_t st);
+void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st);
+void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
+                         uint32_t *qend, hipStream_t st);
+void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
+                           uint32_t *qend, hipStream_t st);
+void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
+                          int32_t max_hits, uint32_t *nsel, hipStream_t st);
+void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_off, int32_t nq,
+                uint32_t nsel_total, const uint8_t *qcode, const int64_t *qoff, int32_t qa,
+                const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
+                int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
+                unsigned long long *cells_per_q, hipStream_t st);
+
+}  // namespace gg

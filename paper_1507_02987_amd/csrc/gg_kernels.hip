@@ -1,0 +1,925 @@
+// GPU kernels of the indexed similar-sequence search (Genoogle, arXiv
+// 1507.02987, Sections 2, 2.1 and 2.2), written for gfx950 (CDNA4, wave64).
+//
+// Work is batched: every kernel handles all queries of a wave at once, so one
+// query is just a batch of one.  Nothing here is a dense contraction, so there is
+// no MFMA: the gather and sort stages are bound by HBM bandwidth and the banded
+// Smith-Waterman by the integer vector ALUs.
+#include "gg_internal.h"
+
+namespace gg {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int32_t base_code(uint32_t ch)
+{
+    // Section 2: DNA {A,C,G,T} or RNA {A,C,G,U}, 2 bits per base; A=0 C=1 G=2 T=U=3
+    switch (ch) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': case 'U': case 'u': return 3;
+    default: return -1;
+    }
+}
+
+__device__ __forceinline__ uint64_t shr64(uint64_t x, int n) { return n >= 64 ? 0ull : (x >> n); }
+__device__ __forceinline__ uint64_t low_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+__device__ __forceinline__ int32_t floor_half(int32_t x) { return x >> 1; }  // arithmetic shift
+
+// 2-bit packed data bank: base of global index g sits in word g / 16 at bit 2 (g % 16)
+__device__ __forceinline__ int32_t db_base(const uint32_t *__restrict__ dbw, int64_t g)
+{
+    return (int32_t)((dbw[g >> 4] >> ((uint32_t)(g & 15) << 1)) & 3u);
+}
+
+// Exclusive scan over the 256 threads of a block; *total receives the block sum.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *total)
+{
+    __shared__ T s_w[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        T t = s_w[i];
+        if (i < w) before += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+// ------------------------------------------------------------------ S1/S2: encode + count
+// One thread per query base g of the batch: code the base (flagging bytes outside
+// the alphabet), find its query, and if a whole window of k bases starts here,
+// code the window (first base most significant) and count its postings.
+__global__ __launch_bounds__(kBlock) void k_encode_kmers(
+    const uint8_t *__restrict__ ascii, const int64_t *__restrict__ qoff, int32_t nq, int64_t T,
+    int32_t k, const uint32_t *__restrict__ list_off, uint8_t *__restrict__ qcode,
+    uint32_t *__restrict__ kcode, uint32_t *__restrict__ cnt, int32_t *__restrict__ qid,
+    int32_t *__restrict__ err)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= T) return;
+    int32_t c = base_code(ascii[g]);
+    if (c < 0) {
+        atomicOr(err, 1);
+        c = 0;
+    }
+    qcode[g] = (uint8_t)c;
+    int32_t lo = 0, hi = nq - 1;  // last query whose first base is <= g
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (qoff[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    qid[g] = lo;
+    uint32_t code = 0, n = 0;
+    if (g + k <= qoff[lo + 1]) {
+        for (int32_t t = 0; t < k; ++t) {
+            const int32_t b = base_code(ascii[g + t]);
+            code = code * 4u + (uint32_t)(b < 0 ? 0 : b);
+        }
+        n = list_off[code + 1] - list_off[code];
+    }
+    kcode[g] = code;
+    cnt[g] = n;
+}
+
+void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
+                         int32_t k, const uint32_t *list_off, uint8_t *qcode, uint32_t *kcode,
+                         uint32_t *cnt, int32_t *qid, int32_t *err, hipStream_t st)
+{
+    if (T <= 0) return;
+    const int64_t nb = (T + kBlock - 1) / kBlock;
+    k_encode_kmers<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(ascii, qoff, nq, T, k, list_off,
+                                                                qcode, kcode, cnt, qid, err);
+}
+
+// ------------------------------------------------------------------ scans
+// Three passes: per-tile sums, one block scanning the tile sums, per-tile scan.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI *__restrict__ in, int64_t n,
+                                                        TO *__restrict__ partials)
+{
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    TO s = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < n) s += (TO)in[i];
+    }
+    TO tot;
+    block_excl_scan<TO>(s, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_partials(TO *__restrict__ partials, int64_t nb)
+{
+    TO carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const int64_t i = b0 + threadIdx.x;
+        const TO v = (i < nb) ? partials[i] : (TO)0;
+        TO tot;
+        const TO ex = block_excl_scan<TO>(v, &tot);
+        if (i < nb) partials[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) partials[nb] = carry;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in, int64_t n,
+                                                      const TO *__restrict__ partials,
+                                                      TO *__restrict__ out, int64_t nb)
+{
+    __shared__ TO s_v[kTile];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        s_v[r * kBlock + threadIdx.x] = (i < n) ? (TO)in[i] : (TO)0;
+    }
+    __syncthreads();
+    TO v[kItems];
+    TO s = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        v[r] = s_v[threadIdx.x * kItems + r];
+        s += v[r];
+    }
+    TO tot;
+    TO run = block_excl_scan<TO>(s, &tot) + partials[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        s_v[threadIdx.x * kItems + r] = run;
+        run += v[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < n) out[i] = s_v[r * kBlock + threadIdx.x];
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = partials[nb];
+}
+
+size_t scan_partials_needed(int64_t n) { return (size_t)((n + kTile - 1) / kTile + 1); }
+
+template <typename TI, typename TO>
+static void scan_impl(const TI *in, TO *out, int64_t n, TO *partials, hipStream_t st)
+{
+    if (n <= 0) {
+        (void)hipMemsetAsync(out, 0, sizeof(TO), st);
+        return;
+    }
+    const int64_t nb = (n + kTile - 1) / kTile;
+    k_scan_reduce<TI, TO><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials);
+    k_scan_partials<TO><<<1, kBlock, 0, st>>>(partials, nb);
+    k_scan_down<TI, TO><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials, out, nb);
+}
+
+void launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *partials,
+                            hipStream_t st)
+{
+    scan_impl<uint32_t, uint64_t>(in, out, n, partials, st);
+}
+
+void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
+                     hipStream_t st)
+{
+    scan_impl<uint32_t, uint32_t>(in, out, n, partials, st);
+}
+
+__global__ void k_query_totals(const uint64_t *__restrict__ hoff, const int64_t *__restrict__ qoff,
+                               int32_t nq, uint64_t *__restrict__ qtot)
+{
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq) qtot[q] = hoff[qoff[q + 1]] - hoff[qoff[q]];
+}
+
+void launch_query_totals(const uint64_t *hoff, const int64_t *qoff, int32_t nq, uint64_t *qtot,
+                         hipStream_t st)
+{
+    if (nq <= 0) return;
+    k_query_totals<<<(nq + kBlock - 1) / kBlock, kBlock, 0, st>>>(hoff, qoff, nq, qtot);
+}
+
+// ------------------------------------------------------------------ S3: gather
+// Per position of the wave: its first hit (relative to the wave), the index of its
+// posting list's head, and the constant part of its hits' keys
+// (q << sh_q) + ((bias - qpos) << sh_d) + qpos.
+__global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__restrict__ qoff,
+                            const uint32_t *__restrict__ kcode, const int32_t *__restrict__ qid,
+                            const uint32_t *__restrict__ list_off, int32_t qa, int64_t g0,
+                            int64_t np, HitKeyLayout lay, uint32_t *__restrict__ hrel,
+                            uint32_t *__restrict__ pbase, uint64_t *__restrict__ akey)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > np) return;
+    const uint64_t hb = hoff[g0];
+    hrel[p] = (uint32_t)(hoff[g0 + p] - hb);
+    if (p == np) return;
+    const int64_t g = g0 + p;
+    const int32_t q = qid[g];
+    const int32_t qpos = (int32_t)(g - qoff[q]);
+    pbase[p] = list_off[kcode[g]];
+    const int sh_d = lay.bp, sh_q = lay.bp + lay.bd + lay.bs;
+    const uint64_t qpart = sh_q >= 64 ? 0ull : ((uint64_t)(uint32_t)(q - qa) << sh_q);
+    akey[p] = qpart + ((uint64_t)(uint32_t)(lay.bias - qpos) << sh_d) + (uint64_t)(uint32_t)qpos;
+}
+
+void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
+                      const int32_t *qid, const uint32_t *list_off, int32_t qa, int64_t g0,
+                      int64_t g1, HitKeyLayout lay, uint32_t *hrel, uint32_t *pbase, uint64_t *akey,
+                      hipStream_t st)
+{
+    const int64_t np = g1 - g0;
+    const int64_t nb = (np + 1 + kBlock - 1) / kBlock;
+    k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, kcode, qid, list_off, qa,
+                                                             g0, np, lay, hrel, pbase, akey);
+}
+
+// Load-balanced over hits: block b owns hits [b*kTile, (b+1)*kTile) of the wave.
+// Consecutive threads take consecutive hits, so reads of one posting run and the
+// key writes are coalesced.  The owning position of hit j is the last p with
+// hrel[p] <= j, searched in LDS when the tile spans few positions.
+__global__ __launch_bounds__(kBlock) void k_gather(const uint32_t *__restrict__ hrel,
+                                                   const uint32_t *__restrict__ pbase,
+                                                   const uint64_t *__restrict__ akey, int64_t np,
+                                                   const int2 *__restrict__ post, uint32_t nhits,
+                                                   int sh_s, int sh_d, uint64_t *__restrict__ keys)
+{
+    __shared__ uint32_t s_h[kGatherCap + 1];
+    __shared__ int64_t s_lo, s_hi;
+    const uint32_t t0 = blockIdx.x * (uint32_t)kTile;
+    const uint32_t t1 = min(t0 + (uint32_t)kTile, nhits);
+    if (threadIdx.x == 0) {
+        int64_t a = 0, b = np - 1;
+        while (a < b) {
+            const int64_t m = (a + b + 1) >> 1;
+            if (hrel[m] <= t0) a = m;
+            else b = m - 1;
+        }
+        s_lo = a;
+        b = np - 1;
+        while (a < b) {
+            const int64_t m = (a + b + 1) >> 1;
+            if (hrel[m] <= t1 - 1) a = m;
+            else b = m - 1;
+        }
+        s_hi = a;
+    }
+    __syncthreads();
+    const int64_t lo = s_lo, hi = s_hi;
+    const bool in_lds = (hi - lo + 2) <= (int64_t)(kGatherCap + 1);
+    if (in_lds)
+        for (int64_t p = lo + threadIdx.x; p <= hi + 1; p += blockDim.x) s_h[p - lo] = hrel[p];
+    __syncthreads();
+    for (uint32_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
+        int64_t p;
+        uint32_t first;
+        if (in_lds) {
+            int32_t a = 0, b = (int32_t)(hi - lo);
+            while (a < b) {
+                const int32_t m = (a + b + 1) >> 1;
+                if (s_h[m] <= j) a = m;
+                else b = m - 1;
+            }
+            p = lo + a;
+            first = s_h[a];
+        } else {
+            int64_t a = lo, b = hi;
+            while (a < b) {
+                const int64_t m = (a + b + 1) >> 1;
+                if (hrel[m] <= j) a = m;
+                else b = m - 1;
+            }
+            p = a;
+            first = hrel[a];
+        }
+        const int2 e = post[pbase[p] + (j - first)];
+        keys[j] = akey[p] + ((uint64_t)(uint32_t)e.x << sh_s) + ((uint64_t)(uint32_t)e.y << sh_d);
+    }
+}
+
+void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
+                   int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
+                   uint64_t *keys, hipStream_t st)
+{
+    if (nhits == 0) return;
+    const uint32_t nb = (nhits + kTile - 1) / kTile;
+    k_gather<<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd, lay.bp,
+                                    keys);
+}
+
+// ------------------------------------------------------------------ S4: radix sort
+// Stable LSD radix sort, 8 bits per pass: digit histogram per tile, one scan of the
+// digit-major histogram matrix, then a stable scatter.  In the scatter, each wave
+// ranks its keys with ballot-built peer masks (lanes holding the same digit) and
+// per-wave digit counters in LDS; the tile is then reordered in LDS so that the
+// global writes of each digit run are contiguous.
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys, uint32_t n,
+                                                    int shift, uint32_t *__restrict__ hist,
+                                                    uint32_t nb)
+{
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * (uint32_t)kTile;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = base + r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+template <bool VALS>
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                       const uint32_t *__restrict__ vin,
+                                                       uint64_t *__restrict__ kout,
+                                                       uint32_t *__restrict__ vout, uint32_t n,
+                                                       int shift, const uint32_t *__restrict__ hist,
+                                                       uint32_t nb)
+{
+    __shared__ uint64_t s_k[kTile];
+    __shared__ uint32_t s_v[VALS ? kTile : 1];
+    __shared__ uint32_t s_wc[kBlock / 64][kRadix];
+    __shared__ uint32_t s_start[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s_wc[i][threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t sub = blockIdx.x * (uint32_t)kTile + w * 64 * kItems;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t k[kItems];
+    uint32_t v[kItems], rank[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t idx = sub + r * 64 + lane;
+        const bool ok = idx < n;
+        k[r] = ok ? kin[idx] : 0ull;
+        if (VALS) v[r] = ok ? vin[idx] : 0u;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const uint64_t bb = __ballot(ok && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t before = s_wc[w][d];
+        rank[r] = before + (uint32_t)__popcll(peers & below);
+        __builtin_amdgcn_wave_barrier();
+        if (ok && (peers & below) == 0) s_wc[w][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        const uint32_t d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) {
+            const uint32_t c = s_wc[i][d];
+            s_wc[i][d] = run;
+            run += c;
+        }
+        uint32_t tot;
+        s_start[d] = block_excl_scan<uint32_t>(run, &tot);
+        s_gbase[d] = hist[(size_t)d * nb + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t idx = sub + r * 64 + lane;
+        if (idx < n) {
+            const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
+            const uint32_t pos = s_start[d] + s_wc[w][d] + rank[r];
+            s_k[pos] = k[r];
+            if (VALS) s_v[pos] = v[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t tn = min((uint32_t)kTile, n - blockIdx.x * (uint32_t)kTile);
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = r * kBlock + threadIdx.x;
+        if (i < tn) {
+            const uint64_t key = s_k[i];
+            const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+            const uint32_t o = s_gbase[d] + (i - s_start[d]);
+            kout[o] = key;
+            if (VALS) vout[o] = s_v[i];
+        }
+    }
+}
+
+size_t radix_hist_needed(uint32_t n)
+{
+    const size_t nb = (n + kTile - 1) / kTile;
+    return nb * kRadix + 1;
+}
+
+int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
+               uint32_t n, int lo, int hi, uint32_t *hist, uint32_t *partials, hipStream_t st)
+{
+    int cur = 0;
+    if (n <= 1 || hi <= lo) return 0;
+    const uint32_t nb = (n + kTile - 1) / kTile;
+    for (int shift = lo; shift < hi; shift += kRadixBits) {
+        uint64_t *kin = cur ? keys_alt : keys, *kout = cur ? keys : keys_alt;
+        uint32_t *vin = cur ? vals_alt : vals, *vout = cur ? vals : vals_alt;
+        k_rs_hist<<<nb, kBlock, 0, st>>>(kin, n, shift, hist, nb);
+        scan_impl<uint32_t, uint32_t>(hist, hist, (int64_t)nb * kRadix, partials, st);
+        if (vals)
+            k_rs_scatter<true><<<nb, kBlock, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nb);
+        else
+            k_rs_scatter<false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n, shift, hist,
+                                                       nb);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+// ------------------------------------------------------------------ S5: chain + filter
+// One thread per sorted hit.  A hit ends a run when the next hit is in another
+// (q, s, diag) group or further than G past this hit's window; the run's first
+// hit is found by walking back while the chaining rule holds.  Runs with
+// qe - qs >= M are appended (one atomic per wave).
+__global__ __launch_bounds__(kBlock) void k_chain(const uint64_t *__restrict__ keys, uint32_t n,
+                                                  HitKeyLayout lay, int32_t k, int32_t G,
+                                                  int32_t M, Cand *__restrict__ out,
+                                                  uint32_t cap, uint32_t *__restrict__ count,
+                                                  uint32_t *__restrict__ cand_per_q)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t pmask = low_mask(lay.bp);
+    bool emit = false;
+    Cand c{0, 0, 0, 0, 0};
+    if (i < n) {
+        const uint64_t key = keys[i];
+        const uint64_t grp = key >> lay.bp;
+        const int32_t qp = (int32_t)(key & pmask);
+        bool end = true;
+        if (i + 1 < n) {
+            const uint64_t nx = keys[i + 1];
+            end = ((nx >> lay.bp) != grp) || ((int32_t)(nx & pmask) - (qp + k) > G);
+        }
+        if (end) {
+            uint32_t j = i;
+            int32_t qj = qp;
+            while (j > 0) {
+                const uint64_t pv = keys[j - 1];
+                if ((pv >> lay.bp) != grp) break;
+                const int32_t qv = (int32_t)(pv & pmask);
+                if (qj - (qv + k) > G) break;
+                --j;
+                qj = qv;
+            }
+            if (qp + k - qj >= M) {
+                emit = true;
+                c.d = (int32_t)(grp & low_mask(lay.bd)) - lay.bias;
+                c.s = (int32_t)(shr64(grp, lay.bd) & low_mask(lay.bs));
+                c.q = (int32_t)shr64(grp, lay.bd + lay.bs);
+                c.qs = qj;
+                c.qe = qp + k;
+            }
+        }
+    }
+    const uint64_t m = __ballot(emit);
+    if (m) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if (emit) {
+            const uint32_t at = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            if (at < cap) out[at] = c;  // past cap: only counted, the caller grows and reruns
+            atomicAdd(&cand_per_q[c.q], 1u);
+        }
+    }
+}
+
+void launch_chain(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k, int32_t max_gap,
+                  int32_t min_len, Cand *out, uint32_t cap, uint32_t *count,
+                  uint32_t *cand_per_q, hipStream_t st)
+{
+    if (n == 0) return;
+    k_chain<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(keys, n, lay, k, max_gap, min_len, out,
+                                                           cap, count, cand_per_q);
+}
+
+// ------------------------------------------------------------------ S6: X-drop extension
+// One thread per run: ungapped walk right from qe and left from qs - 1 along the
+// run's diagonal; each side stops at a sequence end or when the running sum drops
+// more than X below its best, and extends to the first position of that best.
+__global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cands, uint32_t n,
+                                                   const uint8_t *__restrict__ qcode,
+                                                   const int64_t *__restrict__ qoff, int32_t qa,
+                                                   const uint32_t *__restrict__ dbw,
+                                                   const int64_t *__restrict__ seq_start,
+                                                   int32_t match, int32_t mismatch, int32_t X,
+                                                   Box *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Cand c = cands[i];
+    const int64_t q0 = qoff[qa + c.q];
+    const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
+    const uint8_t *__restrict__ q = qcode + q0;
+    const int64_t s0 = seq_start[c.s];
+    const int32_t ns = (int32_t)(seq_start[c.s + 1] - s0);
+    const int32_t d = c.d;
+    int32_t run = 0, best = 0, bl = 0, t = 0;
+    while (c.qe + t < L && c.qe + d + t < ns) {
+        run += ((int32_t)q[c.qe + t] == db_base(dbw, s0 + c.qe + d + t)) ? match : -mismatch;
+        ++t;
+        if (run > best) {
+            best = run;
+            bl = t;
+        }
+        if (best - run > X) break;
+    }
+    const int32_t qe = c.qe + bl;
+    run = 0, best = 0, bl = 0, t = 0;
+    while (c.qs - 1 - t >= 0 && c.qs - 1 - t + d >= 0) {
+        run += ((int32_t)q[c.qs - 1 - t] == db_base(dbw, s0 + c.qs - 1 - t + d)) ? match : -mismatch;
+        ++t;
+        if (run > best) {
+            best = run;
+            bl = t;
+        }
+        if (best - run > X) break;
+    }
+    const int32_t qs = c.qs - bl;
+    out[i] = Box{c.q, c.s, qs, qe, qs + d, qe + d, d, d};
+}
+
+void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
+                   int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
+                   int32_t mismatch, int32_t xdrop, Box *out, hipStream_t st)
+{
+    if (n == 0) return;
+    k_extend<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start,
+                                                            match, mismatch, xdrop, out);
+}
+
+// ------------------------------------------------------------------ record sort keys
+__device__ __forceinline__ uint64_t box_field(const Box &b, int32_t f, int32_t desc_max)
+{
+    switch (f) {
+    case F_Q: return (uint32_t)b.q;
+    case F_S: return (uint32_t)b.s;
+    case F_QS: return (uint32_t)b.qs;
+    case F_QE: return (uint32_t)b.qe;
+    case F_DS: return (uint32_t)b.ds;
+    case F_DE: return (uint32_t)b.de;
+    default: return (uint32_t)(desc_max - min(b.qe - b.qs, b.de - b.ds));
+    }
+}
+
+__global__ void k_box_keys(const Box *__restrict__ b, uint32_t n, KeyWord w, int32_t q_invalid,
+                           uint64_t *__restrict__ out, const uint32_t *__restrict__ perm)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Box x = b[perm ? perm[i] : i];
+    if (x.q < 0) x = Box{q_invalid, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t key = 0;
+    for (int f = 0; f < w.n; ++f) key |= box_field(x, w.field[f], w.desc_max[f]) << w.shift[f];
+    out[i] = key;
+}
+
+void launch_box_keys(const Box *b, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
+                     const uint32_t *perm, hipStream_t st)
+{
+    if (n == 0) return;
+    k_box_keys<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(b, n, w, q_invalid, out, perm);
+}
+
+__device__ __forceinline__ uint64_t align_field(const Align &a, int32_t f, int32_t desc_max)
+{
+    switch (f) {
+    case A_Q: return (uint32_t)a.q;
+    case A_SCORE_DESC: return (uint32_t)(desc_max - a.score);
+    case A_SEQ: return (uint32_t)a.seq_id;
+    case A_QS: return (uint32_t)a.q_start;
+    case A_QE: return (uint32_t)a.q_end;
+    case A_DS: return (uint32_t)a.d_start;
+    case A_DE: return (uint32_t)a.d_end;
+    case A_BQS: return (uint32_t)a.box_q_start;
+    case A_BQE: return (uint32_t)a.box_q_end;
+    case A_BDS: return (uint32_t)a.box_d_start;
+    default: return (uint32_t)a.box_d_end;
+    }
+}
+
+__global__ void k_align_keys(const Align *__restrict__ a, uint32_t n, KeyWord w, int32_t q_invalid,
+                             uint64_t *__restrict__ out, const uint32_t *__restrict__ perm)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Align x = a[perm ? perm[i] : i];
+    uint64_t key = 0;
+    if (x.score <= 0) {
+        for (int f = 0; f < w.n; ++f)
+            if (w.field[f] == A_Q) key |= (uint64_t)(uint32_t)q_invalid << w.shift[f];
+    } else {
+        for (int f = 0; f < w.n; ++f) key |= align_field(x, w.field[f], w.desc_max[f]) << w.shift[f];
+    }
+    out[i] = key;
+}
+
+void launch_align_keys(const Align *a, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
+                       const uint32_t *perm, hipStream_t st)
+{
+    if (n == 0) return;
+    k_align_keys<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(a, n, w, q_invalid, out, perm);
+}
+
+__global__ void k_iota(uint32_t *__restrict__ v, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = i;
+}
+
+void launch_iota(uint32_t *v, uint32_t n, hipStream_t st)
+{
+    if (n) k_iota<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(v, n);
+}
+
+template <typename R>
+__global__ void k_gather_rec(const R *__restrict__ in, const uint32_t *__restrict__ perm,
+                             uint32_t n, R *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[perm[i]];
+}
+
+void launch_gather_boxes(const Box *in, const uint32_t *perm, uint32_t n, Box *out,
+                         hipStream_t st)
+{
+    if (n) k_gather_rec<Box><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(in, perm, n, out);
+}
+
+void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Align *out,
+                          hipStream_t st)
+{
+    if (n) k_gather_rec<Align><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(in, perm, n, out);
+}
+
+// ------------------------------------------------------------------ S7: merge overlaps
+// Boxes sorted by (q, s, qs, ds, qe, de).  The thread at the start of each (q, s)
+// group sweeps it once, merging the next box into the open one when both their
+// query and data-bank intervals intersect; the merged boxes are written from the
+// group's start and its remaining slots are marked empty (q = -1).
+__global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Box first = s[i];
+    if (i > 0) {
+        const Box p = s[i - 1];
+        if (p.q == first.q && p.s == first.s) return;
+    }
+    Box cur = first;
+    uint32_t w = i, j = i + 1;
+    for (; j < n; ++j) {
+        const Box h = s[j];
+        if (h.q != first.q || h.s != first.s) break;
+        if (h.qs < cur.qe && h.ds < cur.de && cur.ds < h.de) {
+            cur.qs = min(cur.qs, h.qs);
+            cur.qe = max(cur.qe, h.qe);
+            cur.ds = min(cur.ds, h.ds);
+            cur.de = max(cur.de, h.de);
+            cur.dmin = min(cur.dmin, h.dmin);
+            cur.dmax = max(cur.dmax, h.dmax);
+        } else {
+            out[w++] = cur;
+            cur = h;
+        }
+    }
+    out[w++] = cur;
+    for (; w < j; ++w) out[w].q = -1;
+}
+
+void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st)
+{
+    if (n) k_merge_sweep<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(sorted, n, out);
+}
+
+// ------------------------------------------------------------------ S8: select
+// Records sorted by query first (empty ones last): each query's run [qstart, qend).
+__global__ void k_segments_box(const Box *__restrict__ s, uint32_t n, int32_t nq,
+                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t q = s[i].q;
+    if (q < 0 || q >= nq) return;
+    if (i == 0 || s[i - 1].q != q) qstart[q] = i;
+    if (i + 1 == n || s[i + 1].q != q) qend[q] = i + 1;
+}
+
+void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
+                         uint32_t *qend, hipStream_t st)
+{
+    if (n) k_segments_box<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(sorted, n, nq, qstart, qend);
+}
+
+__global__ void k_segments_align(const Align *__restrict__ s, uint32_t n, int32_t nq,
+                                  uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (s[i].score <= 0) return;
+    const int32_t q = s[i].q;
+    if (i == 0 || s[i - 1].score <= 0 || s[i - 1].q != q) qstart[q] = i;
+    if (i + 1 == n || s[i + 1].score <= 0 || s[i + 1].q != q) qend[q] = i + 1;
+}
+
+void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
+                           uint32_t *qend, hipStream_t st)
+{
+    if (n)
+        k_segments_align<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(sorted, n, nq, qstart, qend);
+}
+
+__global__ void k_select_counts(const uint32_t *__restrict__ qstart,
+                                const uint32_t *__restrict__ qend, int32_t nq, int32_t N,
+                                uint32_t *__restrict__ nsel)
+{
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const uint32_t c = qend[q] - qstart[q];
+    nsel[q] = (N > 0 && c > (uint32_t)N) ? (uint32_t)N : c;
+}
+
+void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
+                          int32_t max_hits, uint32_t *nsel, hipStream_t st)
+{
+    if (nq > 0)
+        k_select_counts<<<(nq + kBlock - 1) / kBlock, kBlock, 0, st>>>(qstart, qend, nq, max_hits,
+                                                                        nsel);
+}
+
+// ------------------------------------------------------------------ S9: banded Smith-Waterman
+// One wave per selected box.  Cells are swept by anti-diagonal a = i + j.  On
+// anti-diagonal a the band holds every other band diagonal t = j - i - c0 + W, all
+// of one parity p; lane u owns t = p + 2u, so at most W + 1 lanes are busy.  The
+// left neighbour (t - 1) and the upper neighbour (t + 1) were on anti-diagonal
+// a - 1, in this lane or the next one over; the diagonal neighbour (same t) was
+// this lane's own cell on a - 2.  Starts are packed as i * 128 + t.
+__global__ __launch_bounds__(kBlock) void k_bsw(
+    const Box *__restrict__ sorted, const uint32_t *__restrict__ qstart,
+    const uint32_t *__restrict__ sel_off, int32_t nq, uint32_t total,
+    const uint8_t *__restrict__ qcode, const int64_t *__restrict__ qoff, int32_t qa,
+    const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t match,
+    int32_t mismatch, int32_t o1, int32_t ext, int32_t W, Align *__restrict__ out,
+    unsigned long long *__restrict__ cells_q)
+{
+    const uint32_t b = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (b >= total) return;  // whole wave
+    const int32_t lane = threadIdx.x & 63;
+    int32_t lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (sel_off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const int32_t q = lo;
+    const Box bx = sorted[qstart[q] + (b - sel_off[q])];
+    const int32_t R = bx.qe - bx.qs, C = bx.de - bx.ds;
+    const int32_t d0 = floor_half(bx.dmin + bx.dmax);
+    const int32_t c0 = d0 - (bx.ds - bx.qs);  // cell (i, j) in band iff |j - i - c0| <= W
+    const uint8_t *__restrict__ qp = qcode + qoff[qa + q] + bx.qs;
+    const int64_t dbase = seq_start[bx.s] + bx.ds;
+    const int32_t clo = max(c0 - W, -(R - 1)), chi = min(c0 + W, C - 1);
+    int32_t best = 0, bcell = 0x7fffffff, bstart = 0;
+    unsigned long long cells = 0;
+    if (R > 0 && C > 0 && clo <= chi) {
+        const int32_t a_lo = (clo <= 0 && chi >= 0) ? 0 : (clo > 0 ? clo : -chi);
+        const int32_t cs = min(max(C - R, clo), chi);
+        const int32_t a_hi = (cs <= C - R) ? 2 * (R - 1) + cs : 2 * (C - 1) - cs;
+        int32_t H1 = kNegInf, E1 = kNegInf, F1 = kNegInf, S1 = 0, SE1 = 0, SF1 = 0;
+        int32_t H2 = kNegInf, S2 = 0;
+        for (int32_t a = a_lo; a <= a_hi; ++a) {
+            const int32_t p = (a - c0 + W) & 1;
+            const int32_t t = p + 2 * lane;
+            const int32_t c = t - W + c0;
+            const int32_t i = (a - c) >> 1;
+            const int32_t j = a - i;
+            const bool valid = (t <= 2 * W) && i >= 0 && i < R && j >= 0 && j < C;
+            int32_t hl, el, sl, sel, hu, fu, su, sfu;
+            if (p == 0) {
+                hl = __shfl_up(H1, 1, 64);
+                el = __shfl_up(E1, 1, 64);
+                sl = __shfl_up(S1, 1, 64);
+                sel = __shfl_up(SE1, 1, 64);
+                hu = H1; fu = F1; su = S1; sfu = SF1;
+            } else {
+                hl = H1; el = E1; sl = S1; sel = SE1;
+                hu = __shfl_down(H1, 1, 64);
+                fu = __shfl_down(F1, 1, 64);
+                su = __shfl_down(S1, 1, 64);
+                sfu = __shfl_down(SF1, 1, 64);
+            }
+            int32_t H = kNegInf, E = kNegInf, F = kNegInf, S = 0, SE = 0, SF = 0;
+            if (valid) {
+                if (j == 0) { hl = 0; el = kNegInf; }
+                else if (t == 0) { hl = kNegInf; el = kNegInf; }
+                if (i == 0) { hu = 0; fu = kNegInf; }
+                else if (t == 2 * W) { hu = kNegInf; fu = kNegInf; }
+                const bool border = (i == 0 || j == 0);
+                const int32_t hd = border ? 0 : H2;
+                const int32_t sd = S2;
+                const int32_t eo = hl - o1, ee = el - ext;
+                if (eo >= ee) { E = eo; SE = sl; } else { E = ee; SE = sel; }
+                const int32_t fo = hu - o1, fe = fu - ext;
+                if (fo >= fe) { F = fo; SF = su; } else { F = fe; SF = sfu; }
+                const int32_t g = hd + (((int32_t)qp[i] == db_base(dbw, dbase + j)) ? match : -mismatch);
+                H = max(max(0, g), max(E, F));
+                const int32_t here = i * 128 + t;
+                if (H > 0) {
+                    if (g == H) S = (hd > 0) ? sd : here;
+                    else if (E == H) S = SE;
+                    else S = SF;
+                } else {
+                    S = here;
+                }
+                if (H > best) {
+                    best = H;
+                    bcell = here;
+                    bstart = S;
+                }
+                ++cells;
+            }
+            H2 = H1; S2 = S1;
+            H1 = H; E1 = E; F1 = F; S1 = S; SE1 = SE; SF1 = SF;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int32_t ob = __shfl_xor(best, off, 64);
+        const int32_t oc = __shfl_xor(bcell, off, 64);
+        const int32_t os = __shfl_xor(bstart, off, 64);
+        cells += __shfl_xor(cells, off, 64);
+        if (ob > best || (ob == best && oc < bcell)) {
+            best = ob;
+            bcell = oc;
+            bstart = os;
+        }
+    }
+    if (lane == 0) {
+        Align r;
+        r.q = q;
+        r.seq_id = bx.s;
+        r.score = best;
+        if (best > 0) {
+            const int32_t si = bstart >> 7, st = bstart & 127, bi = bcell >> 7, bt = bcell & 127;
+            r.q_start = bx.qs + si;
+            r.q_end = bx.qs + bi + 1;
+            r.d_start = bx.ds + si + st - W + c0;
+            r.d_end = bx.ds + bi + bt - W + c0 + 1;
+        } else {
+            r.q_start = r.q_end = r.d_start = r.d_end = -1;
+        }
+        r.box_q_start = bx.qs;
+        r.box_q_end = bx.qe;
+        r.box_d_start = bx.ds;
+        r.box_d_end = bx.de;
+        r.box_len = min(R, C);
+        out[b] = r;
+        atomicAdd(&cells_q[q], cells);
+    }
+}
+
+void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_off, int32_t nq,
+                uint32_t nsel_total, const uint8_t *qcode, const int64_t *qoff, int32_t qa,
+                const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
+                int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
+                unsigned long long *cells_per_q, hipStream_t st)
+{
+    if (nsel_total == 0) return;
+    const uint32_t per = kBlock / 64;
+    k_bsw<<<(nsel_total + per - 1) / per, kBlock, 0, st>>>(
+        sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw, seq_start, match, mismatch,
+        gap_open + gap_extend, gap_extend, band, out, cells_per_q);
+}
+
+}  // namespace gg

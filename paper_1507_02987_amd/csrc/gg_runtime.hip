@@ -1,0 +1,917 @@
+// Host runtime and C ABI of the MI355X indexed similar-sequence search.
+//
+// Owns the device-resident index, per-call workspaces (stream + growable device
+// buffers), the batch orchestration of the GPU stages, per-stage timing and the
+// continuous-batching server.  Every stage of a search is a kernel in
+// gg_kernels.hip; this file only sizes buffers, launches, and copies results.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "gg.h"
+#include "gg_internal.h"
+
+using namespace gg;
+
+namespace {
+
+int bits_for(uint64_t x)  // bits to hold every value in [0, x)
+{
+    int b = 0;
+    while (b < 64 && (x > (1ull << b))) ++b;
+    return b;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct Err {
+    gg_status st = GG_OK;
+};
+
+#define HIPCHK(expr)                                  \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) {                       \
+            if (e_ == hipErrorOutOfMemory) return GG_ENOMEM; \
+            return GG_EDEVICE;                        \
+        }                                             \
+    } while (0)
+
+#define TRY(expr)                     \
+    do {                              \
+        gg_status s_ = (expr);        \
+        if (s_ != GG_OK) return s_;   \
+    } while (0)
+
+gg_status ensure(DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 1;
+    if (bytes <= b.cap) return GG_OK;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 4 + 256;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return GG_ENOMEM;
+        }
+        want = bytes;
+    }
+    b.cap = want;
+    return GG_OK;
+}
+
+template <typename T>
+T *as(DevBuf &b) { return reinterpret_cast<T *>(b.p); }
+
+struct StageTime {
+    double ms = 0;
+    int64_t launches = 0;
+    int64_t units = 0;
+};
+
+struct Workspace {
+    int device = 0;
+    hipStream_t st = nullptr;
+    DevBuf ascii, qoff, qcode, kcode, cnt, qid, hoff, partials, qtot, err;
+    DevBuf hrel, pbase, akey, keys, keys_alt, hist, rs_partials;
+    DevBuf cands, ccount, cand_q, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
+    DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
+    void *pinned = nullptr;  // small pinned staging for counts
+    size_t pinned_cap = 0;
+    std::vector<hipEvent_t> events;
+    size_t ev_used = 0;
+    struct Mark {
+        std::string name;
+        int e0, e1;
+        int64_t units;
+    };
+    std::vector<Mark> marks;
+
+    ~Workspace()
+    {
+        if (st) (void)hipSetDevice(device);
+        DevBuf *all[] = {&ascii, &qoff, &qcode, &kcode, &cnt, &qid, &hoff, &partials, &qtot, &err,
+                         &hrel, &pbase, &akey, &keys, &keys_alt, &hist, &rs_partials, &cands,
+                         &ccount, &cand_q, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
+                         &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
+                         &cells_q};
+        for (DevBuf *b : all)
+            if (b->p) (void)hipFree(b->p);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (pinned) (void)hipHostFree(pinned);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
+}  // namespace
+
+struct gg_index {
+    int device = 0;
+    int32_t k = 0;
+    int64_t n_seqs = 0, n_bases = 0;
+    uint64_t n_post = 0;
+    int64_t max_seq_len = 0;
+    uint32_t *d_list_off = nullptr;
+    int2 *d_post = nullptr;
+    uint32_t *d_dbw = nullptr;
+    int64_t *d_seq_start = nullptr;
+    uint64_t hit_budget = 0;
+    uint64_t default_budget = 0;
+    mutable std::mutex ws_mu;
+    mutable std::vector<Workspace *> ws_free;
+    std::atomic<int> prof_on{0};
+    mutable std::mutex prof_mu;
+    mutable std::map<std::string, StageTime> prof;
+};
+
+namespace {
+
+gg_status get_ws(const gg_index *ix, Workspace **out)
+{
+    {
+        std::lock_guard<std::mutex> g(ix->ws_mu);
+        if (!ix->ws_free.empty()) {
+            *out = ix->ws_free.back();
+            ix->ws_free.pop_back();
+            return GG_OK;
+        }
+    }
+    auto *ws = new (std::nothrow) Workspace();
+    if (!ws) return GG_ENOMEM;
+    ws->device = ix->device;
+    if (hipStreamCreateWithFlags(&ws->st, hipStreamNonBlocking) != hipSuccess) {
+        delete ws;
+        return GG_EDEVICE;
+    }
+    *out = ws;
+    return GG_OK;
+}
+
+void put_ws(const gg_index *ix, Workspace *ws)
+{
+    std::lock_guard<std::mutex> g(ix->ws_mu);
+    ix->ws_free.push_back(ws);
+}
+
+gg_status pinned(Workspace *ws, size_t bytes, void **p)
+{
+    if (bytes > ws->pinned_cap) {
+        if (ws->pinned) (void)hipHostFree(ws->pinned);
+        ws->pinned = nullptr;
+        ws->pinned_cap = 0;
+        size_t want = std::max<size_t>(bytes, 1 << 16);
+        HIPCHK(hipHostMalloc(&ws->pinned, want, hipHostMallocDefault));
+        ws->pinned_cap = want;
+    }
+    *p = ws->pinned;
+    return GG_OK;
+}
+
+// ---- per-stage timing with events on the workspace's own stream
+struct Prof {
+    const gg_index *ix;
+    Workspace *ws;
+    bool on;
+    int open = -1;
+    std::string name;
+    Prof(const gg_index *i, Workspace *w) : ix(i), ws(w), on(i->prof_on.load() != 0)
+    {
+        ws->marks.clear();
+        ws->ev_used = 0;
+    }
+    int ev()
+    {
+        if (ws->ev_used == ws->events.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            ws->events.push_back(e);
+        }
+        return (int)ws->ev_used++;
+    }
+    void begin(const char *n)
+    {
+        if (!on) return;
+        open = ev();
+        name = n;
+        if (open >= 0) (void)hipEventRecord(ws->events[open], ws->st);
+    }
+    void end(int64_t units)
+    {
+        if (!on || open < 0) return;
+        int e1 = ev();
+        if (e1 < 0) return;
+        (void)hipEventRecord(ws->events[e1], ws->st);
+        ws->marks.push_back({name, open, e1, units});
+        open = -1;
+    }
+    void collect()  // after the stream has been synchronised
+    {
+        if (!on || ws->marks.empty()) return;
+        std::lock_guard<std::mutex> g(ix->prof_mu);
+        for (auto &m : ws->marks) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, ws->events[m.e0], ws->events[m.e1]) == hipSuccess) {
+                auto &s = ix->prof[m.name];
+                s.ms += ms;
+                s.launches += 1;
+                s.units += m.units;
+            }
+        }
+        ws->marks.clear();
+        ws->ev_used = 0;
+    }
+};
+
+// ---- multi-word record keys: fields packed most-significant first, never split
+struct FieldSpec {
+    int32_t field;
+    int bits;
+    int32_t desc_max;
+};
+
+gg_status make_words(const std::vector<FieldSpec> &fields, std::vector<KeyWord> &words)
+{
+    words.clear();
+    KeyWord cur{};
+    std::vector<FieldSpec> pend;
+    auto flush = [&]() {
+        KeyWord w{};
+        int sh = 0;
+        for (int i = (int)pend.size() - 1; i >= 0; --i) {
+            w.field[w.n] = pend[i].field;
+            w.shift[w.n] = sh;
+            w.desc_max[w.n] = pend[i].desc_max;
+            w.n++;
+            sh += pend[i].bits;
+        }
+        w.bits = sh;
+        words.push_back(w);
+        pend.clear();
+    };
+    int used = 0;
+    for (const auto &f : fields) {
+        if (f.bits > 64) return GG_EINVAL;
+        if (used + f.bits > 64 || (int)pend.size() == 8) {
+            flush();
+            used = 0;
+        }
+        pend.push_back(f);
+        used += f.bits;
+    }
+    if (!pend.empty()) flush();
+    (void)cur;
+    return GG_OK;
+}
+
+// Sort n records by a multi-word key; returns the device permutation (sorted
+// position -> record index) in ws->perm.
+template <typename KeyFn>
+gg_status sort_records(Workspace *ws, uint32_t n, const std::vector<KeyWord> &words, KeyFn keyfn,
+                       uint32_t **perm_out)
+{
+    TRY(ensure(ws->perm, sizeof(uint32_t) * n));
+    TRY(ensure(ws->perm_alt, sizeof(uint32_t) * n));
+    TRY(ensure(ws->wkeys, sizeof(uint64_t) * n));
+    TRY(ensure(ws->wkeys_alt, sizeof(uint64_t) * n));
+    TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(n)));
+    TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(n))));
+    uint32_t *perm = as<uint32_t>(ws->perm), *perm_alt = as<uint32_t>(ws->perm_alt);
+    launch_iota(perm, n, ws->st);
+    bool first = true;
+    for (int w = (int)words.size() - 1; w >= 0; --w) {
+        keyfn(words[w], first ? nullptr : perm, as<uint64_t>(ws->wkeys));
+        first = false;
+        if (words[w].bits == 0) continue;
+        int where = radix_sort(as<uint64_t>(ws->wkeys), as<uint64_t>(ws->wkeys_alt), perm, perm_alt,
+                               n, 0, words[w].bits, as<uint32_t>(ws->hist),
+                               as<uint32_t>(ws->rs_partials), ws->st);
+        if (where) std::swap(perm, perm_alt);
+    }
+    *perm_out = perm;
+    return GG_OK;
+}
+
+gg_status check_params(const gg_params *p)
+{
+    if (!p) return GG_EINVAL;
+    if (p->match <= 0 || p->mismatch < 0 || p->gap_open < 0 || p->gap_extend < 0) return GG_EINVAL;
+    if (p->band < 0 || p->band > kMaxBand || p->xdrop < 0 || p->max_gap < 0 ||
+        p->min_hsp_len < 0)
+        return GG_EINVAL;
+    if ((int64_t)p->gap_open + p->gap_extend > (1 << 20) || p->match > (1 << 20) ||
+        p->mismatch > (1 << 20) || p->xdrop > (1 << 28))
+        return GG_EINVAL;
+    return GG_OK;
+}
+
+struct BatchOut {
+    gg_hit *out;
+    int32_t cap;
+    int32_t *n_out;
+    gg_stats *stats;
+    bool truncated = false;
+};
+
+// Run every GPU stage for queries [qa, qb) of the batch (one wave).
+gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
+                   const std::vector<int64_t> &qoff_h, const std::vector<uint64_t> &qtot,
+                   int32_t qa, int32_t qb, BatchOut &bo)
+{
+    hipStream_t st = ws->st;
+    const int32_t nqw = qb - qa;
+    const int64_t g0 = qoff_h[qa], g1 = qoff_h[qb];
+    uint64_t H64 = 0;
+    int64_t maxL = 0;
+    for (int32_t q = qa; q < qb; ++q) {
+        H64 += qtot[q];
+        maxL = std::max<int64_t>(maxL, qoff_h[q + 1] - qoff_h[q]);
+    }
+    for (int32_t q = qa; q < qb; ++q) {
+        const int64_t L = qoff_h[q + 1] - qoff_h[q];
+        if (bo.stats) {
+            gg_stats &s = bo.stats[q];
+            s = gg_stats{};
+            s.n_kmers = L >= ix->k ? L - ix->k + 1 : 0;
+            s.n_hits = (int64_t)qtot[q];
+        }
+        bo.n_out[q] = 0;
+    }
+    if (H64 == 0) return GG_OK;
+    const uint32_t H = (uint32_t)H64;
+
+    HitKeyLayout lay;
+    lay.bp = bits_for((uint64_t)maxL);
+    lay.bias = (int32_t)maxL;
+    lay.bd = bits_for((uint64_t)ix->max_seq_len + (uint64_t)maxL);
+    lay.bs = bits_for((uint64_t)ix->n_seqs);
+    lay.bq = bits_for((uint64_t)nqw);
+    if (lay.bp + lay.bd + lay.bs + lay.bq > 64) return GG_EINVAL;
+    if ((uint64_t)maxL * (uint64_t)p->match >= (1ull << 30)) return GG_EINVAL;  // int32 scores
+
+    // ---- S3 gather
+    const int64_t np = g1 - g0;
+    TRY(ensure(ws->hrel, sizeof(uint32_t) * (np + 1)));
+    TRY(ensure(ws->pbase, sizeof(uint32_t) * (np + 1)));
+    TRY(ensure(ws->akey, sizeof(uint64_t) * (np + 1)));
+    TRY(ensure(ws->keys, sizeof(uint64_t) * H));
+    TRY(ensure(ws->keys_alt, sizeof(uint64_t) * H));
+    TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(H)));
+    TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(H))));
+    prof.begin("gather");
+    launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
+                     as<int32_t>(ws->qid), ix->d_list_off, qa, g0, g1, lay, as<uint32_t>(ws->hrel),
+                     as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), st);
+    launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), np,
+                  ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
+    prof.end(H);
+
+    // ---- S4 group: order hits by (q, s, diag); qpos order is kept by stability
+    prof.begin("sort");
+    const int sort_lo = lay.bp, sort_hi = lay.bp + lay.bd + lay.bs + lay.bq;
+    const int where = radix_sort(as<uint64_t>(ws->keys), as<uint64_t>(ws->keys_alt), nullptr,
+                                 nullptr, H, sort_lo, sort_hi, as<uint32_t>(ws->hist),
+                                 as<uint32_t>(ws->rs_partials), st);
+    const uint64_t *sorted = where ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys);
+    const int passes = (sort_hi - sort_lo + kRadixBits - 1) / kRadixBits;
+    prof.end((int64_t)H * passes);
+
+    // ---- S5 chain + filter (runs past the buffer are counted, then the buffer grows)
+    uint32_t ccap = (uint32_t)std::min<uint64_t>(H, std::max<uint64_t>(1u << 20, H / 8));
+    TRY(ensure(ws->ccount, sizeof(uint32_t) * 4));
+    TRY(ensure(ws->cand_q, sizeof(uint32_t) * nqw));
+    void *pin;
+    TRY(pinned(ws, sizeof(uint32_t) * 4, &pin));
+    uint32_t nc = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        TRY(ensure(ws->cands, sizeof(Cand) * ccap));
+        HIPCHK(hipMemsetAsync(ws->ccount.p, 0, sizeof(uint32_t), st));
+        HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
+        prof.begin("chain");
+        launch_chain(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len, as<Cand>(ws->cands), ccap,
+                     as<uint32_t>(ws->ccount), as<uint32_t>(ws->cand_q), st);
+        prof.end(H);
+        HIPCHK(hipMemcpyAsync(pin, ws->ccount.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        nc = *reinterpret_cast<uint32_t *>(pin);
+        if (nc <= ccap) break;
+        ccap = nc;
+    }
+    if (nc == 0) return GG_OK;
+
+    // ---- S6 extend
+    TRY(ensure(ws->boxes, sizeof(Box) * nc));
+    TRY(ensure(ws->boxes2, sizeof(Box) * nc));
+    TRY(ensure(ws->boxes3, sizeof(Box) * nc));
+    prof.begin("extend");
+    launch_extend(as<Cand>(ws->cands), nc, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), qa,
+                  ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop, as<Box>(ws->boxes),
+                  st);
+    prof.end(nc);
+
+    const int bq = bits_for((uint64_t)nqw + 1);  // room for the "empty" query value nqw
+    const int bs = lay.bs;
+    const int bl = bits_for((uint64_t)maxL + 1);
+    const int bsl = bits_for((uint64_t)ix->max_seq_len + 1);
+
+    // ---- S7 merge: sort by (q, s, qs, ds, qe, de), sweep each (q, s) group
+    prof.begin("merge");
+    std::vector<KeyWord> words;
+    TRY(make_words({{F_Q, bq, 0}, {F_S, bs, 0}, {F_QS, bl, 0}, {F_DS, bsl, 0}, {F_QE, bl, 0},
+                    {F_DE, bsl, 0}},
+                   words));
+    uint32_t *perm = nullptr;
+    Box *boxes = as<Box>(ws->boxes);
+    TRY(sort_records(ws, nc, words,
+                     [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
+                         launch_box_keys(boxes, nc, w, nqw, out, pm, st);
+                     },
+                     &perm));
+    launch_gather_boxes(boxes, perm, nc, as<Box>(ws->boxes2), st);
+    launch_merge_sweep(as<Box>(ws->boxes2), nc, as<Box>(ws->boxes3), st);
+    prof.end(nc);
+
+    // ---- S8 select by length: sort by (q, len desc, s, qs, ds, qe, de), keep N per query
+    prof.begin("select");
+    TRY(make_words({{F_Q, bq, 0}, {F_LEN_DESC, bl, (int32_t)maxL}, {F_S, bs, 0}, {F_QS, bl, 0},
+                    {F_DS, bsl, 0}, {F_QE, bl, 0}, {F_DE, bsl, 0}},
+                   words));
+    Box *merged = as<Box>(ws->boxes3);
+    TRY(sort_records(ws, nc, words,
+                     [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
+                         launch_box_keys(merged, nc, w, nqw, out, pm, st);
+                     },
+                     &perm));
+    launch_gather_boxes(merged, perm, nc, as<Box>(ws->boxes2), st);
+    TRY(ensure(ws->qstart, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->qend, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->nsel, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->sel_off, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(nqw + 1)));
+    HIPCHK(hipMemsetAsync(ws->qstart.p, 0, sizeof(uint32_t) * nqw, st));
+    HIPCHK(hipMemsetAsync(ws->qend.p, 0, sizeof(uint32_t) * nqw, st));
+    launch_segments_box(as<Box>(ws->boxes2), nc, nqw, as<uint32_t>(ws->qstart),
+                        as<uint32_t>(ws->qend), st);
+    launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nqw, p->max_hits,
+                         as<uint32_t>(ws->nsel), st);
+    launch_scan_u32(as<uint32_t>(ws->nsel), as<uint32_t>(ws->sel_off), nqw,
+                    as<uint32_t>(ws->partials), st);
+    prof.end(nc);
+    // pinned staging: sel_off[nqw+1] | sel start[nqw] | sel end[nqw] | report start[nqw] |
+    // report end[nqw] | runs per query[nqw] | (8-aligned) cells per query[nqw]
+    const size_t n1 = (size_t)nqw + 1;
+    const size_t u32s = n1 + 5 * (size_t)nqw;
+    TRY(pinned(ws, ((u32s * 4 + 7) / 8) * 8 + 8 * (size_t)nqw + 64, &pin));
+    uint32_t *h_sel_off = reinterpret_cast<uint32_t *>(pin);
+    uint32_t *h_ss = h_sel_off + n1, *h_se = h_ss + nqw, *h_rs = h_se + nqw, *h_re = h_rs + nqw;
+    uint32_t *h_cq = h_re + nqw;
+    unsigned long long *h_cells = reinterpret_cast<unsigned long long *>(
+        reinterpret_cast<char *>(pin) + ((u32s * 4 + 7) / 8) * 8);
+    HIPCHK(hipMemcpyAsync(h_sel_off, ws->sel_off.p, sizeof(uint32_t) * n1, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_ss, ws->qstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_se, ws->qend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint32_t nsel = h_sel_off[nqw];
+    if (bo.stats)
+        for (int32_t ql = 0; ql < nqw; ++ql) bo.stats[qa + ql].n_merged = h_se[ql] - h_ss[ql];
+    if (nsel == 0) {
+        if (bo.stats) {
+            HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int32_t ql = 0; ql < nqw; ++ql) bo.stats[qa + ql].n_cands = h_cq[ql];
+        }
+        return GG_OK;
+    }
+
+    // ---- S9 banded Smith-Waterman
+    TRY(ensure(ws->aligns, sizeof(Align) * nsel));
+    TRY(ensure(ws->aligns2, sizeof(Align) * nsel));
+    TRY(ensure(ws->cells_q, sizeof(unsigned long long) * nqw));
+    HIPCHK(hipMemsetAsync(ws->cells_q.p, 0, sizeof(unsigned long long) * nqw, st));
+    prof.begin("align");
+    launch_bsw(as<Box>(ws->boxes2), as<uint32_t>(ws->qstart), as<uint32_t>(ws->sel_off), nqw, nsel,
+               as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), qa, ix->d_dbw, ix->d_seq_start,
+               p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, as<Align>(ws->aligns),
+               as<unsigned long long>(ws->cells_q), st);
+    prof.end(nsel);
+
+    // ---- S10 report: drop score <= 0, order by score desc and coordinates
+    prof.begin("report");
+    const int bsc = bits_for((uint64_t)maxL * (uint64_t)p->match + 1);
+    TRY(make_words({{A_Q, bq, 0}, {A_SCORE_DESC, bsc, (int32_t)(maxL * p->match)}, {A_SEQ, bs, 0},
+                    {A_QS, bl, 0}, {A_DS, bsl, 0}, {A_QE, bl, 0}, {A_DE, bsl, 0}, {A_BQS, bl, 0},
+                    {A_BDS, bsl, 0}, {A_BQE, bl, 0}, {A_BDE, bsl, 0}},
+                   words));
+    Align *al = as<Align>(ws->aligns);
+    TRY(sort_records(ws, nsel, words,
+                     [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
+                         launch_align_keys(al, nsel, w, nqw, out, pm, st);
+                     },
+                     &perm));
+    launch_gather_aligns(al, perm, nsel, as<Align>(ws->aligns2), st);
+    TRY(ensure(ws->rstart, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->rend, sizeof(uint32_t) * (nqw + 1)));
+    HIPCHK(hipMemsetAsync(ws->rstart.p, 0, sizeof(uint32_t) * nqw, st));
+    HIPCHK(hipMemsetAsync(ws->rend.p, 0, sizeof(uint32_t) * nqw, st));
+    launch_segments_align(as<Align>(ws->aligns2), nsel, nqw, as<uint32_t>(ws->rstart),
+                          as<uint32_t>(ws->rend), st);
+    prof.end(nsel);
+
+    // ---- copy back the ordered alignments and per-query ranges
+    std::vector<Align> res(nsel);
+    HIPCHK(hipMemcpyAsync(res.data(), ws->aligns2.p, sizeof(Align) * nsel, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_rs, ws->rstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_re, ws->rend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+    if (bo.stats) {
+        HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_cells, ws->cells_q.p, sizeof(unsigned long long) * nqw,
+                              hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int32_t ql = 0; ql < nqw; ++ql) {
+        const int32_t q = qa + ql;
+        const uint32_t n = h_re[ql] - h_rs[ql];
+        bo.n_out[q] = (int32_t)n;
+        if (n > (uint32_t)bo.cap) bo.truncated = true;
+        const uint32_t m = std::min<uint32_t>(n, (uint32_t)bo.cap);
+        gg_hit *dst = bo.out + (size_t)q * bo.cap;
+        for (uint32_t r = 0; r < m; ++r) {
+            const Align &a = res[h_rs[ql] + r];
+            dst[r] = gg_hit{a.seq_id,      a.score,       a.q_start,     a.q_end,
+                            a.d_start,     a.d_end,       a.box_q_start, a.box_q_end,
+                            a.box_d_start, a.box_d_end,   a.box_len};
+        }
+        if (bo.stats) {
+            gg_stats &s = bo.stats[q];
+            s.n_cands = h_cq[ql];
+            s.n_selected = h_sel_off[ql + 1] - h_sel_off[ql];
+            s.n_cells = (int64_t)h_cells[ql];
+            s.n_out = n;
+        }
+    }
+    return GG_OK;
+}
+
+gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const int64_t *qoff,
+                    int64_t nq, const gg_params *p, BatchOut &bo, uint64_t budget_bytes)
+{
+    hipStream_t st = ws->st;
+    if (nq == 0) return GG_OK;
+    std::vector<int64_t> qoff_h(nq + 1);
+    for (int64_t q = 0; q <= nq; ++q) qoff_h[q] = qoff[q] - qoff[0];
+    for (int64_t q = 0; q < nq; ++q)
+        if (qoff_h[q + 1] < qoff_h[q] || qoff_h[q + 1] - qoff_h[q] > (int64_t)INT32_MAX / 2)
+            return GG_EINVAL;
+    const int64_t T = qoff_h[nq];
+    if (T > (int64_t)INT32_MAX) return GG_EINVAL;
+    if (T > 0 && !qbuf) return GG_EINVAL;
+    Prof prof(ix, ws);
+
+    TRY(ensure(ws->ascii, T));
+    TRY(ensure(ws->qoff, sizeof(int64_t) * (nq + 1)));
+    TRY(ensure(ws->qcode, T));
+    TRY(ensure(ws->kcode, sizeof(uint32_t) * T));
+    TRY(ensure(ws->cnt, sizeof(uint32_t) * T));
+    TRY(ensure(ws->qid, sizeof(int32_t) * T));
+    TRY(ensure(ws->hoff, sizeof(uint64_t) * (T + 1)));
+    TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(T, nq + 1))));
+    TRY(ensure(ws->qtot, sizeof(uint64_t) * nq));
+    TRY(ensure(ws->err, sizeof(int32_t) * 4));
+    if (T > 0) HIPCHK(hipMemcpyAsync(ws->ascii.p, qbuf + qoff[0], T, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws->qoff.p, qoff_h.data(), sizeof(int64_t) * (nq + 1),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(ws->err.p, 0, sizeof(int32_t), st));
+
+    // ---- S1 encode + S2 count and scan
+    prof.begin("encode");
+    launch_encode_kmers(as<uint8_t>(ws->ascii), as<int64_t>(ws->qoff), (int32_t)nq, T, ix->k,
+                        ix->d_list_off, as<uint8_t>(ws->qcode), as<uint32_t>(ws->kcode),
+                        as<uint32_t>(ws->cnt), as<int32_t>(ws->qid), as<int32_t>(ws->err), st);
+    prof.end(T);
+    prof.begin("scan");
+    launch_scan_u32_to_u64(as<uint32_t>(ws->cnt), as<uint64_t>(ws->hoff), T,
+                           as<uint64_t>(ws->partials), st);
+    launch_query_totals(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), (int32_t)nq,
+                        as<uint64_t>(ws->qtot), st);
+    prof.end(T);
+    std::vector<uint64_t> qtot(nq);
+    int32_t err = 0;
+    HIPCHK(hipMemcpyAsync(qtot.data(), ws->qtot.p, sizeof(uint64_t) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&err, ws->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (err) return GG_EINVAL;
+
+    // ---- waves: consecutive queries whose hit keys fit the budget and the key bits
+    const uint64_t max_hits = std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
+    for (int64_t q = 0; q < nq; ++q)
+        if (qtot[q] > max_hits) return GG_EBUDGET;
+    const int bs = bits_for((uint64_t)ix->n_seqs);
+    int32_t qa = 0;
+    while (qa < nq) {
+        uint64_t h = 0;
+        int64_t maxL = 0;
+        int32_t qb = qa;
+        while (qb < nq) {
+            const uint64_t h2 = h + qtot[qb];
+            const int64_t L2 = std::max<int64_t>(maxL, qoff_h[qb + 1] - qoff_h[qb]);
+            const int bits = bits_for((uint64_t)L2) + bits_for((uint64_t)ix->max_seq_len + L2) + bs +
+                             bits_for((uint64_t)(qb - qa + 1)) ;
+            const int wbits = bits_for((uint64_t)(qb - qa + 2));  // record keys hold q up to nqw
+            if (qb > qa && (h2 > max_hits || bits > 64 || wbits > 31)) break;
+            if (bits > 64) return GG_EINVAL;
+            h = h2;
+            maxL = L2;
+            ++qb;
+        }
+        TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, qa, qb, bo));
+        prof.collect();
+        qa = qb;
+    }
+    prof.collect();
+    return GG_OK;
+}
+
+uint64_t budget_of(const gg_index *ix) { return ix->hit_budget ? ix->hit_budget : ix->default_budget; }
+
+}  // namespace
+
+namespace gg {
+
+uint64_t index_budget(const gg_index *ix) { return budget_of(ix); }
+
+gg_status search_batch_budget(const gg_index *ix, const char *qbuf, const int64_t *qoff,
+                              int64_t n_q, const gg_params *params, gg_hit *out, int32_t cap,
+                              int32_t *n_out, gg_stats *stats, uint64_t budget)
+{
+    if (!ix || n_q < 0 || n_q > (1 << 30) || cap < 0 || (n_q > 0 && (!qoff || !n_out)) ||
+        (cap > 0 && n_q > 0 && !out))
+        return GG_EINVAL;
+    TRY(check_params(params));
+    if (n_q == 0) return GG_OK;
+    if (hipSetDevice(ix->device) != hipSuccess) return GG_EDEVICE;
+    Workspace *ws = nullptr;
+    TRY(get_ws(ix, &ws));
+    BatchOut bo{out, cap, n_out, stats};
+    gg_status s = run_batch(ix, ws, qbuf, qoff, n_q, params, bo, budget);
+    if (s != GG_OK) {
+        (void)hipStreamSynchronize(ws->st);
+        (void)hipGetLastError();
+    }
+    put_ws(ix, ws);
+    if (s == GG_OK && bo.truncated) s = GG_ETRUNC;
+    return s;
+}
+
+}  // namespace gg
+
+// ==================================================================== C ABI
+
+extern "C" {
+
+const char *gg_strerror(gg_status s)
+{
+    switch (s) {
+    case GG_OK: return "ok";
+    case GG_EINVAL: return "invalid argument";
+    case GG_ENOMEM: return "out of memory";
+    case GG_EDEVICE: return "GPU error";
+    case GG_EAGAIN: return "not finished";
+    case GG_ETRUNC: return "output truncated";
+    case GG_ENOTFOUND: return "unknown ticket";
+    case GG_EBUDGET: return "query exceeds the hit-buffer budget";
+    default: return "unknown status";
+    }
+}
+
+void gg_index_free(gg_index *ix)
+{
+    if (!ix) return;
+    (void)hipSetDevice(ix->device);
+    for (Workspace *ws : ix->ws_free) delete ws;
+    ix->ws_free.clear();
+    if (ix->d_list_off) (void)hipFree(ix->d_list_off);
+    if (ix->d_post) (void)hipFree(ix->d_post);
+    if (ix->d_dbw) (void)hipFree(ix->d_dbw);
+    if (ix->d_seq_start) (void)hipFree(ix->d_seq_start);
+    delete ix;
+}
+
+// Formatting and index construction (Sections 2, 2.1).  The list heads are a
+// counting sort of the windows by code: count, exclusive prefix, then place the
+// windows in (sequence, position) order, which keeps each list sorted.
+gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
+                         int32_t device, gg_index **out)
+{
+    if (!out) return GG_EINVAL;
+    *out = nullptr;
+    if (k < 1 || k > 16 || n_seqs < 0 || n_seqs > INT32_MAX) return GG_EINVAL;
+    if (n_seqs > 0 && (!seq_off || !seqs)) return GG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GG_EDEVICE;
+    const int64_t base0 = n_seqs > 0 ? seq_off[0] : 0;
+    int64_t maxlen = 0;
+    for (int64_t s = 0; s < n_seqs; ++s) {
+        const int64_t n = seq_off[s + 1] - seq_off[s];
+        if (n < 0 || n > INT32_MAX) return GG_EINVAL;
+        maxlen = std::max(maxlen, n);
+    }
+    const int64_t total = n_seqs > 0 ? seq_off[n_seqs] - base0 : 0;
+    static const int8_t kCode[256] = {
+#define X -1
+        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
+        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
+        X, 0, X, 1, X, X, X, 2, X, X, X, X, X, X, X, X, X, X, X, X, 3, 3, X, X, X, X, X, X, X, X, X, X,
+        X, 0, X, 1, X, X, X, 2, X, X, X, X, X, X, X, X, X, X, X, X, 3, 3, X, X, X, X, X, X, X, X, X, X,
+        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
+        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
+        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
+        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
+#undef X
+    };
+    // 2-bit packing, 16 bases per 32-bit word, base g at bits 2 (g % 16)
+    const int64_t nwords = (total + 15) / 16 + 1;
+    std::vector<uint32_t> dbw;
+    std::vector<uint32_t> head;
+    std::vector<int2> post;
+    try {
+        dbw.assign((size_t)nwords, 0u);
+        head.assign(((size_t)1 << (2 * k)) + 1, 0u);
+    } catch (...) {
+        return GG_ENOMEM;
+    }
+    {
+        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::atomic<int> bad{0};
+        std::vector<std::thread> th;
+        const int64_t chunk = ((nwords + nt - 1) / nt);
+        for (unsigned t = 0; t < nt; ++t) {
+            th.emplace_back([&, t]() {
+                const int64_t w0 = t * chunk, w1 = std::min<int64_t>(nwords, w0 + chunk);
+                for (int64_t w = w0; w < w1; ++w) {
+                    uint32_t word = 0;
+                    for (int b = 0; b < 16; ++b) {
+                        const int64_t g = w * 16 + b;
+                        if (g >= total) break;
+                        const int8_t c = kCode[(uint8_t)seqs[base0 + g]];
+                        if (c < 0) {
+                            bad = 1;
+                            continue;
+                        }
+                        word |= (uint32_t)c << (2 * b);
+                    }
+                    dbw[(size_t)w] = word;
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+        if (bad) return GG_EINVAL;
+    }
+    auto base_at = [&](int64_t g) -> uint32_t { return (dbw[(size_t)(g >> 4)] >> ((g & 15) * 2)) & 3u; };
+    auto window_code = [&](int64_t g) -> uint32_t {
+        uint32_t c = 0;
+        for (int t = 0; t < k; ++t) c = (c << 2) | base_at(g + t);
+        return c;
+    };
+    uint64_t n_post = 0;
+    for (int64_t s = 0; s < n_seqs; ++s) n_post += (uint64_t)((seq_off[s + 1] - seq_off[s]) / k);
+    if (n_post >= 0xffffffffull) return GG_EINVAL;
+    for (int64_t s = 0; s < n_seqs; ++s) {
+        const int64_t g0 = seq_off[s] - base0, n = seq_off[s + 1] - seq_off[s];
+        for (int64_t w = 0; (w + 1) * k <= n; ++w) head[window_code(g0 + w * k) + 1] += 1;
+    }
+    for (size_t c = 1; c < head.size(); ++c) head[c] += head[c - 1];
+    try {
+        post.resize((size_t)std::max<uint64_t>(n_post, 1));
+    } catch (...) {
+        return GG_ENOMEM;
+    }
+    {
+        std::vector<uint32_t> cursor(head.begin(), head.end() - 1);
+        for (int64_t s = 0; s < n_seqs; ++s) {
+            const int64_t g0 = seq_off[s] - base0, n = seq_off[s + 1] - seq_off[s];
+            for (int64_t w = 0; (w + 1) * k <= n; ++w) {
+                const uint32_t c = window_code(g0 + w * k);
+                post[cursor[c]++] = int2{(int32_t)s, (int32_t)(w * k)};
+            }
+        }
+    }
+    std::vector<int64_t> seq_start((size_t)n_seqs + 1);
+    for (int64_t s = 0; s <= n_seqs; ++s) seq_start[(size_t)s] = n_seqs > 0 ? seq_off[s] - base0 : 0;
+
+    auto *ix = new (std::nothrow) gg_index();
+    if (!ix) return GG_ENOMEM;
+    ix->device = device;
+    ix->k = k;
+    ix->n_seqs = n_seqs;
+    ix->n_bases = total;
+    ix->n_post = n_post;
+    ix->max_seq_len = maxlen;
+    auto fail = [&](gg_status s) {
+        gg_index_free(ix);
+        return s;
+    };
+    if (hipSetDevice(device) != hipSuccess) return fail(GG_EDEVICE);
+    auto up = [&](void **dst, const void *src, size_t bytes) -> gg_status {
+        if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) {
+            (void)hipGetLastError();
+            *dst = nullptr;
+            return GG_ENOMEM;
+        }
+        if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return GG_EDEVICE;
+        return GG_OK;
+    };
+    gg_status s;
+    if ((s = up((void **)&ix->d_list_off, head.data(), head.size() * sizeof(uint32_t))) != GG_OK)
+        return fail(s);
+    if ((s = up((void **)&ix->d_post, post.data(), n_post * sizeof(int2))) != GG_OK) return fail(s);
+    if ((s = up((void **)&ix->d_dbw, dbw.data(), dbw.size() * sizeof(uint32_t))) != GG_OK)
+        return fail(s);
+    if ((s = up((void **)&ix->d_seq_start, seq_start.data(), seq_start.size() * sizeof(int64_t))) !=
+        GG_OK)
+        return fail(s);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(GG_EDEVICE);
+    ix->default_budget = std::min<uint64_t>((uint64_t)16 << 30, free_b / 4);
+    *out = ix;
+    return GG_OK;
+}
+
+gg_status gg_index_info(const gg_index *ix, int64_t *n_postings, int64_t *n_bases, int64_t *n_seqs,
+                        int32_t *k)
+{
+    if (!ix) return GG_EINVAL;
+    if (n_postings) *n_postings = (int64_t)ix->n_post;
+    if (n_bases) *n_bases = ix->n_bases;
+    if (n_seqs) *n_seqs = ix->n_seqs;
+    if (k) *k = ix->k;
+    return GG_OK;
+}
+
+gg_status gg_index_set_hit_budget(gg_index *ix, uint64_t bytes)
+{
+    if (!ix) return GG_EINVAL;
+    ix->hit_budget = bytes;
+    return GG_OK;
+}
+
+gg_status gg_search_batch(const gg_index *ix, const char *qbuf, const int64_t *qoff, int64_t n_q,
+                          const gg_params *params, gg_hit *out, int32_t cap, int32_t *n_out,
+                          gg_stats *stats)
+{
+    if (!ix) return GG_EINVAL;
+    return gg::search_batch_budget(ix, qbuf, qoff, n_q, params, out, cap, n_out, stats,
+                                   budget_of(ix));
+}
+
+gg_status gg_search(const gg_index *ix, const char *query, int64_t qlen, const gg_params *params,
+                    gg_hit *out, int32_t cap, int32_t *n_out)
+{
+    if (qlen < 0 || (qlen > 0 && !query) || !n_out) return GG_EINVAL;
+    const int64_t off[2] = {0, qlen};
+    return gg_search_batch(ix, query, off, 1, params, out, cap, n_out, nullptr);
+}
+
+gg_status gg_profile_enable(gg_index *ix, int32_t on)
+{
+    if (!ix) return GG_EINVAL;
+    std::lock_guard<std::mutex> g(ix->prof_mu);
+    ix->prof.clear();
+    ix->prof_on = on ? 1 : 0;
+    return GG_OK;
+}
+
+gg_status gg_profile_read(const gg_index *ix, const char *stage, double *ms, int64_t *launches,
+                          int64_t *units)
+{
+    if (!ix || !stage) return GG_EINVAL;
+    std::lock_guard<std::mutex> g(ix->prof_mu);
+    auto it = ix->prof.find(stage);
+    StageTime t;
+    if (it != ix->prof.end()) t = it->second;
+    if (ms) *ms = t.ms;
+    if (launches) *launches = t.launches;
+    if (units) *units = t.units;
+    return GG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+"""Python binding of libgg.so (include/gg.h): argument marshalling only.
+
+Every stage of a search runs in the library's HIP kernels.  There is no CPU
+fallback: if the compiled library is missing, importing this module works but
+any call raises ``RuntimeError``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgg.so")
+
+GG_OK, GG_EINVAL, GG_ENOMEM, GG_EDEVICE, GG_EAGAIN, GG_ETRUNC, GG_ENOTFOUND, GG_EBUDGET = range(8)
+STATUS = {0: "GG_OK", 1: "GG_EINVAL", 2: "GG_ENOMEM", 3: "GG_EDEVICE", 4: "GG_EAGAIN",
+          5: "GG_ETRUNC", 6: "GG_ENOTFOUND", 7: "GG_EBUDGET"}
+
+HIT_FIELDS = ("seq_id", "score", "q_start", "q_end", "d_start", "d_end",
+              "box_q_start", "box_q_end", "box_d_start", "box_d_end", "box_len")
+HIT_DTYPE = np.dtype([(f, np.int32) for f in HIT_FIELDS])
+STAT_FIELDS = ("n_kmers", "n_hits", "n_cands", "n_merged", "n_selected", "n_cells", "n_out")
+STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
+
+# Exported symbols of include/gg.h, in declaration order.
+SYMBOLS = ("gg_index_build", "gg_index_free", "gg_index_info", "gg_index_set_hit_budget",
+           "gg_search", "gg_search_batch", "gg_profile_enable", "gg_profile_read",
+           "gg_server_create", "gg_serve_submit", "gg_serve_poll", "gg_server_destroy",
+           "gg_strerror")
+
+
+class GGError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("match", "mismatch", "gap_open", "gap_extend", "band",
+                                         "xdrop", "max_gap", "min_hsp_len", "max_hits")]
+
+
+def params(max_hits: int = 20, match: int = 1, mismatch: int = 3, gap_open: int = 5,
+           gap_extend: int = 2, band: int = 32, xdrop: int = 20, max_gap: int = 22,
+           min_hsp_len: int = 22) -> Params:
+    """The workloads' scoring: +1/-3, gap 5 + 2 g, band 32, X-drop 20."""
+    return Params(match, mismatch, gap_open, gap_extend, band, xdrop, max_gap, min_hsp_len,
+                  max_hits)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1507_02987_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        L.gg_index_build.argtypes = [vp, vp, i64, i32, i32, C.POINTER(vp)]
+        L.gg_index_free.argtypes = [vp]
+        L.gg_index_free.restype = None
+        L.gg_index_info.argtypes = [vp, vp, vp, vp, vp]
+        L.gg_index_set_hit_budget.argtypes = [vp, u64]
+        L.gg_search.argtypes = [vp, vp, i64, C.POINTER(Params), vp, i32, vp]
+        L.gg_search_batch.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, i32, vp, vp]
+        L.gg_profile_enable.argtypes = [vp, i32]
+        L.gg_profile_read.argtypes = [vp, C.c_char_p, vp, vp, vp]
+        L.gg_server_create.argtypes = [vp, C.POINTER(Params), u64, i32, C.POINTER(vp)]
+        L.gg_serve_submit.argtypes = [vp, vp, i64, vp]
+        L.gg_serve_poll.argtypes = [vp, u64, vp, i32, vp, i32]
+        L.gg_server_destroy.argtypes = [vp]
+        L.gg_server_destroy.restype = None
+        L.gg_strerror.argtypes = [i32]
+        L.gg_strerror.restype = C.c_char_p
+        for name in SYMBOLS:
+            fn = getattr(L, name)
+            if fn.restype is C.c_int:
+                fn.restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _u8(x) -> np.ndarray:
+    if isinstance(x, np.ndarray):
+        return np.ascontiguousarray(x, dtype=np.uint8)
+    return np.frombuffer(bytes(x), dtype=np.uint8)
+
+
+class Index:
+    """gg_index_build / gg_index_free: device-resident data bank and inverted index."""
+
+    def __init__(self, seqs, seq_off, k: int, device: int = 0):
+        s = _u8(seqs)
+        off = np.ascontiguousarray(seq_off, dtype=np.int64)
+        h = C.c_void_p()
+        rc = lib().gg_index_build(_ptr(s) if len(s) else None, _ptr(off), len(off) - 1, k, device,
+                                  C.byref(h))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_build")
+        self._h = h
+        self.k = k
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().gg_index_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        k = C.c_int32()
+        rc = lib().gg_index_info(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(k))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_info")
+        return {"n_postings": a.value, "n_bases": b.value, "n_seqs": c.value, "k": k.value}
+
+    def set_hit_budget(self, nbytes: int):
+        rc = lib().gg_index_set_hit_budget(self._h, int(nbytes))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_set_hit_budget")
+
+    def search(self, query, prm: Params, cap: int = 1024):
+        """gg_search: returns (status, hits[:min(n, cap)], n)."""
+        q = _u8(query)
+        out = np.zeros(max(cap, 1), dtype=HIT_DTYPE)
+        n = C.c_int32()
+        rc = lib().gg_search(self._h, _ptr(q) if len(q) else None, len(q), C.byref(prm), _ptr(out),
+                             cap, C.byref(n))
+        if rc not in (GG_OK, GG_ETRUNC):
+            return rc, np.zeros(0, HIT_DTYPE), 0
+        return rc, out[: min(n.value, cap)].copy(), n.value
+
+    def search_batch(self, qbuf, qoff, prm: Params, cap: int = 1024, stats: bool = False):
+        """gg_search_batch: returns (status, list of hit arrays, counts, stats or None)."""
+        b = _u8(qbuf)
+        off = np.ascontiguousarray(qoff, dtype=np.int64)
+        nq = len(off) - 1
+        out = np.zeros(max(nq * cap, 1), dtype=HIT_DTYPE)
+        nout = np.zeros(max(nq, 1), dtype=np.int32)
+        st = np.zeros(max(nq, 1), dtype=STAT_DTYPE) if stats else None
+        rc = lib().gg_search_batch(self._h, _ptr(b) if len(b) else None, _ptr(off), nq,
+                                   C.byref(prm), _ptr(out), cap, _ptr(nout),
+                                   _ptr(st) if stats else None)
+        if rc not in (GG_OK, GG_ETRUNC):
+            return rc, [], nout[:nq], None
+        res = [out[i * cap: i * cap + min(int(nout[i]), cap)].copy() for i in range(nq)]
+        return rc, res, nout[:nq].copy(), (st[:nq] if stats else None)
+
+    # ---- per-stage GPU timing
+    def profile(self, on: bool = True):
+        rc = lib().gg_profile_enable(self._h, 1 if on else 0)
+        if rc != GG_OK:
+            raise GGError(rc, "gg_profile_enable")
+
+    def profile_read(self, stage: str) -> dict:
+        ms, la, un = C.c_double(), C.c_int64(), C.c_int64()
+        rc = lib().gg_profile_read(self._h, stage.encode(), C.byref(ms), C.byref(la), C.byref(un))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_profile_read")
+        return {"ms": ms.value, "launches": la.value, "units": un.value}
+
+
+class Server:
+    """gg_server_create / gg_serve_submit / gg_serve_poll / gg_server_destroy."""
+
+    def __init__(self, index: Index, prm: Params, hit_budget_bytes: int = 0, max_slots: int = 64):
+        h = C.c_void_p()
+        rc = lib().gg_server_create(index.handle, C.byref(prm), int(hit_budget_bytes), max_slots,
+                                    C.byref(h))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_server_create")
+        self._h = h
+        self._index = index  # keep the index alive while serving
+
+    def submit(self, query) -> int:
+        q = _u8(query)
+        t = C.c_uint64()
+        rc = lib().gg_serve_submit(self._h, _ptr(q) if len(q) else None, len(q), C.byref(t))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_serve_submit")
+        return t.value
+
+    def poll(self, ticket: int, cap: int = 1024, timeout_us: int = 0):
+        """Returns (status, hits, n); status GG_EAGAIN while pending."""
+        out = np.zeros(max(cap, 1), dtype=HIT_DTYPE)
+        n = C.c_int32()
+        rc = lib().gg_serve_poll(self._h, ticket, _ptr(out), cap, C.byref(n), timeout_us)
+        if rc in (GG_OK, GG_ETRUNC):
+            return rc, out[: min(n.value, cap)].copy(), n.value
+        return rc, np.zeros(0, HIT_DTYPE), 0
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().gg_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,179 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit-exact.
+
+Every integer field of every reported hit, the hit order and the per-query work
+counts must be identical.  Inputs are the seeded synthetic workloads; sizes span
+several gather / sort tiles with ragged tails, plus edge cases.
+"""
+import numpy as np
+import pytest
+
+from paper_1507_02987_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu():
+    from paper_1507_02987_amd import gg
+
+    gg.lib()  # fails loudly when the library is not built
+    return gg
+
+
+def as_rows(a):
+    return [tuple(int(x) for x in r) for r in a.tolist()]
+
+
+def oracle_all(ggo, oix, qs, prm_o, cap=100000):
+    res, stats = [], []
+    for i in range(qs.n):
+        rc, h, n, st = oix.search(qs.query(i), prm_o, cap=cap)
+        assert rc == 0
+        res.append(h)
+        stats.append(st)
+    return res, stats
+
+
+def check_batch(G, gix, qs, prm_g, want, want_stats, cap=100000):
+    rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm_g, cap=cap, stats=True)
+    assert rc == 0, G.STATUS[rc]
+    for i in range(qs.n):
+        assert as_rows(got[i]) == as_rows(want[i]), f"query {i}"
+        for f in ("n_kmers", "n_hits", "n_cands", "n_merged", "n_selected", "n_cells", "n_out"):
+            assert int(st[i][f]) == want_stats[i][f], (i, f)
+
+
+@pytest.fixture(scope="module")
+def c0(ggo):
+    G = gpu()
+    db = synth.config0_db()
+    qs = synth.config0_queries(db)
+    return G, db, qs, G.Index(db.seqs, db.off, 11), ggo.Index(db.seqs, db.off, 11)
+
+
+def test_config0_batch_and_single(ggo, c0):
+    G, db, qs, gix, oix = c0
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(20))
+    check_batch(G, gix, qs, G.params(20), want, wst)
+    for i in range(qs.n):
+        rc, h, n = gix.search(qs.query(i), G.params(20), cap=1000)
+        assert rc == 0 and as_rows(h) == as_rows(want[i])
+    info = gix.info()
+    assert info["n_postings"] == oix.n_post and info["k"] == 11
+
+
+@pytest.mark.parametrize("k,band,max_hits,seed", [
+    (4, 32, 20, 1), (6, 5, 0, 2), (8, 0, 3, 3), (11, 63, 50, 4), (12, 32, 1, 5), (7, 17, -1, 6)])
+def test_random_banks(ggo, k, band, max_hits, seed):
+    G = gpu()
+    db = synth.random_db(seed, n_seqs=300, lmin=0, lmax=3000)
+    qs = synth.random_queries(seed, db, n=40, lmin=0, lmax=1500, frac_homolog=0.7,
+                              ident_lo=0.8, ident_hi=1.0, indel_rate=0.02)
+    oix, gix = ggo.Index(db.seqs, db.off, k), G.Index(db.seqs, db.off, k)
+    kw = dict(band=band, max_gap=3 * k - 2 * (seed % 2), min_hsp_len=2 * k)
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(max_hits, **kw))
+    check_batch(G, gix, qs, G.params(max_hits, **kw), want, wst)
+
+
+def test_scoring_variants(ggo, c0):
+    G, db, qs, gix, oix = c0
+    for kw in (dict(match=2, mismatch=1, gap_open=1, gap_extend=1, xdrop=10),
+               dict(match=1, mismatch=1, gap_open=0, gap_extend=3, xdrop=5, max_gap=0,
+                    min_hsp_len=11),
+               dict(max_gap=100, min_hsp_len=0, band=1)):
+        want, wst = oracle_all(ggo, oix, qs, ggo.params(7, **kw))
+        check_batch(G, gix, qs, G.params(7, **kw), want, wst)
+
+
+def test_waves_under_small_budget(ggo):
+    """A tiny hit budget forces one query per wave; results must not change."""
+    G = gpu()
+    db = synth.config1_db(n_seqs=20_000)
+    qs = synth.config1_queries(db, n=60)
+    oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(50))
+    check_batch(G, gix, qs, G.params(50), want, wst)
+    hits = max(int(s["n_hits"]) for s in wst)
+    gix.set_hit_budget(16 * hits)
+    check_batch(G, gix, qs, G.params(50), want, wst)
+    gix.set_hit_budget(16 * (hits - 1))
+    rc, _, _, _ = gix.search_batch(qs.buf, qs.off, G.params(50))
+    assert rc == G.GG_EBUDGET
+
+
+def test_edge_cases(ggo, c0):
+    G, db, qs, gix, oix = c0
+    prm = G.params(20)
+    # empty batch, empty query, shorter than k, lowercase and U
+    rc, res, n, _ = gix.search_batch(b"", np.array([0]), prm)
+    assert rc == 0 and len(res) == 0
+    parts = [b"", b"ACGTACGTAC", bytes(qs.query(0)).lower().replace(b"t", b"u"), b"A" * 11,
+             bytes(qs.query(3))]
+    off = np.cumsum([0] + [len(p) for p in parts])
+    rc, res, n, _ = gix.search_batch(b"".join(parts), off, prm)
+    assert rc == 0
+    for i, p in enumerate(parts):
+        orc, oh, on, _ = oix.search(p, ggo.params(20))
+        assert as_rows(res[i]) == as_rows(oh)
+    # bad byte anywhere fails the call
+    rc, _, _ = gix.search(b"ACGTNACGTACGTACGTAC", prm)
+    assert rc == G.GG_EINVAL
+    # truncation: first cap hits, full count
+    rc, full, nfull = gix.search(qs.query(0), prm, cap=1000)
+    assert rc == 0 and nfull >= 2
+    rc, part, n = gix.search(qs.query(0), prm, cap=1)
+    assert rc == G.GG_ETRUNC and n == nfull and as_rows(part) == as_rows(full[:1])
+    # parameters outside the supported range
+    assert gix.search(qs.query(0), G.params(20, band=64))[0] == G.GG_EINVAL
+    assert gix.search(qs.query(0), G.params(20, match=0))[0] == G.GG_EINVAL
+
+
+def test_index_build_errors():
+    G = gpu()
+    with pytest.raises(G.GGError):
+        G.Index(b"ACGTN", np.array([0, 5]), 3)
+    with pytest.raises(G.GGError):
+        G.Index(b"ACGT", np.array([0, 4]), 17)
+    ix = G.Index(b"ACGTACGT" * 4, np.array([0, 0, 3, 32]), 3)  # empty and short sequences
+    assert ix.info()["n_postings"] == 10
+
+
+def test_deterministic_repeat(c0):
+    G, db, qs, gix, oix = c0
+    a = gix.search_batch(qs.buf, qs.off, G.params(20))[1]
+    b = gix.search_batch(qs.buf, qs.off, G.params(20))[1]
+    assert all(x.tobytes() == y.tobytes() for x, y in zip(a, b))
+
+
+def test_server_matches_plain(c0):
+    G, db, qs, gix, oix = c0
+    prm = G.params(20)
+    want = [gix.search(qs.query(i), prm, cap=1000)[1] for i in range(qs.n)]
+    sv = G.Server(gix, prm, max_slots=8)
+    try:
+        tickets = [sv.submit(qs.query(i)) for i in range(qs.n)]
+        for i, t in enumerate(tickets):
+            rc, h, n = sv.poll(t, cap=1000, timeout_us=-1)
+            assert rc == 0 and as_rows(h) == as_rows(want[i])
+        assert sv.poll(tickets[0], timeout_us=0)[0] == G.GG_ENOTFOUND
+    finally:
+        sv.close()
+
+
+@pytest.mark.slow
+def test_config1_full_bank_sampled(ggo):
+    """The full 200,000-sequence bank and all 1,000 queries in one batched call (the
+    benchmark's configuration); 60 sampled queries are checked against the oracle."""
+    G = gpu()
+    db = synth.config1_db()
+    qs = synth.config1_queries(db)
+    gix = G.Index(db.seqs, db.off, 11)
+    rc, got, n, st = gix.search_batch(qs.buf, qs.off, G.params(50), cap=200, stats=True)
+    assert rc == 0
+    oix = ggo.Index(db.seqs, db.off, 11)
+    rng = np.random.default_rng(0)
+    pick = np.concatenate([np.argsort(qs.lengths())[-10:], rng.choice(qs.n, 50, replace=False)])
+    for i in pick:
+        orc, oh, on, ost = oix.search(qs.query(int(i)), ggo.params(50), cap=200)
+        assert orc == 0
+        assert as_rows(got[i]) == as_rows(oh), int(i)
+        assert int(st[i]["n_hits"]) == ost["n_hits"] and int(st[i]["n_cells"]) == ost["n_cells"]
