@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the batched GPU search on the mid-size workload, one JSON line.
+
+Workload (the paper's mid-size plain method): a 200,000-sequence data bank
+(log-normal lengths, median 1,000 bp, about 275 Mbp, per-sequence GC 0.35-0.65)
+and 1,000 queries, log-uniform 80-10,000 bp, half planted homologs at 70-99%
+identity with 1% indels; k = 11, +1/-3, gap 5 + 2g, band 32, X-drop 20, top 50.
+
+A step is one gg_search_batch_device call over all 1,000 queries: every stage of
+the path, with the queries already resident in GPU memory and the hits written
+to GPU memory.  The call returns only when its results are complete.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1507_02987_amd import gg, synth  # noqa: E402
+
+METRIC = "queries/s and DB-Gbp·query-kbp/s at 1 GPU; p50/p99 latency under load"
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: int32 vector lane-operations per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+CAP = 64
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gg_kernels.hip", "gg_internal.h"):
+        with open(os.path.join(ROOT, "paper_1507_02987_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(db, qs, max_hits: int, min_seconds: float = 8.0):
+    """The oracle, untuned, over all queries on the host cores (index excluded)."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import ggo  # checker / baseline only
+    from concurrent.futures import ThreadPoolExecutor
+
+    ggo.build()
+    cores = min(16, len(os.sched_getaffinity(0)))
+    oix = ggo.Index(db.seqs, db.off, 11)
+    prm = ggo.params(max_hits)
+    queries = [bytes(qs.query(i)) for i in range(qs.n)]
+
+    def run(q):
+        return oix.search(q, prm, cap=CAP)[0]
+
+    done, t0 = 0, time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        while True:
+            rcs = list(ex.map(run, queries))
+            assert all(r in (0, 5) for r in rcs)
+            done += len(queries)
+            if time.perf_counter() - t0 >= min_seconds:
+                break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {qs.n} queries of the workload, {done // qs.n} passes, "
+                      f"{dt:.1f} s wall on {cores} threads (index build excluded)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--queries", type=int, default=1000)
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the one-query-at-a-time comparison (for kernel-trace runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the search shards by query or by data-bank range, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    gg.lib()  # the compiled HIP library, or a loud failure
+    t = time.perf_counter()
+    db = synth.config1_db()
+    qs = synth.config1_queries(db, n=args.queries)
+    log(f"workload: {db.n_seqs} seqs, {db.total_bp / 1e6:.1f} Mbp, {qs.n} queries, "
+        f"{qs.lengths().sum()} query bp ({time.perf_counter() - t:.1f} s)")
+    max_hits = synth.CONFIG_TOP_N[1]
+    prm = gg.params(max_hits)
+
+    t = time.perf_counter()
+    gix = gg.Index(db.seqs, db.off, 11, device=0)
+    build_s = time.perf_counter() - t
+    log(f"index built on GPU 0 in {build_s:.1f} s: {gix.info()}")
+
+    # inputs resident in HBM before the timed region
+    dq = gg.DeviceBuffer(max(len(qs.buf), 1))
+    dq.upload(qs.buf)
+    dout = gg.DeviceBuffer(qs.n * CAP * gg.HIT_DTYPE.itemsize)
+    dn = gg.DeviceBuffer(qs.n * 4)
+
+    def step():
+        rc, _ = gix.search_batch_device(dq, qs.off, prm, dout, dn, CAP)
+        if rc not in (gg.GG_OK, gg.GG_ETRUNC):
+            raise gg.GGError(rc, "gg_search_batch_device")
+
+    for _ in range(args.warmup):
+        step()
+    log(f"warmup {args.warmup} done")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    dt = time.perf_counter() - t0
+    qps = qs.n * args.steps / dt
+    gbp_kbp = (db.total_bp / 1e9) * (qs.lengths().sum() / 1e3) * args.steps / dt
+    log(f"timed {args.steps} steps: {dt * 1e3 / args.steps:.3f} ms/step, {qps:.0f} queries/s")
+
+    # device results equal the host-buffer form (PCIe-inclusive rate measured here too)
+    got_n = dn.download(np.zeros(qs.n, np.int32))
+    got = dout.download(np.zeros(qs.n * CAP, gg.HIT_DTYPE))
+    t1 = time.perf_counter()
+    rc, res, n_host, stats = gix.search_batch(qs.buf, qs.off, prm, cap=CAP, stats=True)
+    pcie_qps = qs.n / (time.perf_counter() - t1)
+    assert rc in (gg.GG_OK, gg.GG_ETRUNC)
+    assert np.array_equal(got_n, n_host)
+    for i in range(qs.n):
+        m = min(int(n_host[i]), CAP)
+        assert got[i * CAP: i * CAP + m].tobytes() == res[i].tobytes(), i
+
+    # per-kernel GPU time, HIP events on the library's stream, over profiled steps
+    gix.profile(True)
+    for _ in range(3):
+        step()
+    stages = {s: gix.profile_read(s) for s in (
+        "encode", "scan", "gather_prep", "gather", "sort_hist", "sort_scan", "sort_scatter",
+        "chain", "extend", "merge", "select", "align", "report")}
+    gix.profile(False)
+    step_ms = {s: v["ms"] / 3 for s, v in stages.items()}
+    # algorithmic bytes per unit: gather reads an 8 B posting and writes an 8 B key per
+    # hit; a radix scatter reads and writes an 8 B key; a histogram pass reads one
+    bytes_per_unit = {"gather": 16, "sort_scatter": 16, "sort_hist": 8}
+    cand = {s: stages[s] for s in bytes_per_unit if stages[s]["launches"]}
+    dom = max(cand, key=lambda s: cand[s]["ms"])
+    st = cand[dom]
+    per_launch_bytes = bytes_per_unit[dom] * st["units"] / st["launches"]
+    avg_s = st["ms"] / 1e3 / st["launches"]
+    achieved = per_launch_bytes / avg_s / 1e9
+    workload = "config1"
+    roofline = {"bound": "hbm", "kernel": {"gather": "k_gather", "sort_scatter": "k_rs_scatter",
+                                          "sort_hist": "k_rs_hist"}[dom],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for(dom, workload),
+                "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": int(per_launch_bytes)}
+    # the banded Smith-Waterman against the integer vector ALUs
+    al = stages["align"]
+    cells = int(stats["n_cells"].sum())
+    align_gcups = cells / (al["ms"] / 3 / 1e3) / 1e9 if al["ms"] > 0 else None
+
+    # the plain one-query-at-a-time loop on the same GPU, for comparison
+    plain_qps = None
+    if not args.no_plain:
+        n_plain = min(200, qs.n)
+        t1 = time.perf_counter()
+        for i in range(n_plain):
+            rc, _, _ = gix.search(qs.query(i), prm, cap=CAP)
+            assert rc in (gg.GG_OK, gg.GG_ETRUNC)
+        plain_qps = n_plain / (time.perf_counter() - t1)
+    log(f"plain per-query loop: {plain_qps} queries/s; PCIe-inclusive batch: {pcie_qps:.0f}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("oracle CPU baseline ...")
+        cpu = cpu_baseline(db, qs, max_hits)
+        log(f"oracle: {cpu['value']:.0f} queries/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "config1: 200,000-seq bank (~275 Mbp), 1,000 queries 80-10,000 bp, "
+                               "k=11, top 50, batched", "db_bp": db.total_bp,
+                   "queries": qs.n, "query_bp": int(qs.lengths().sum()), "k": 11,
+                   "max_hits": max_hits, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": {
+            "db_gbp_query_kbp_per_s": round(gbp_kbp, 2),
+            "plain_per_query_qps": round(plain_qps, 1) if plain_qps else None,
+            "pcie_inclusive_batch_qps": round(pcie_qps, 1),
+            "index_build_s": round(build_s, 2),
+            "stage_ms_per_step": {s: round(v, 4) for s, v in step_ms.items()},
+            "hits_per_step": int(stats["n_hits"].sum()),
+            "align_cells_per_step": cells,
+            "align_gcups": round(align_gcups, 2) if align_gcups else None,
+            "valu_peak_tops": round(VALU_PEAK_TOPS, 1),
+        },
+    }
+    print(json.dumps(line), flush=True)
+    for b in (dq, dout, dn):
+        b.close()
+    gix.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

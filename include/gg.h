@@ -136,12 +136,33 @@ gg_status gg_search_batch(const gg_index *index, const char *qbuf, const int64_t
                           int32_t *n_out, gg_stats *stats);
 
 /*
+ * Device-resident form of gg_search_batch, same results: the queries' bytes
+ * already sit in GPU memory of the index's device (d_qbuf, e.g. from
+ * gg_device_alloc) and the hits are written to GPU memory: d_out holds n_q * cap
+ * gg_hit records (query q's at d_out + q * cap) and d_n_out n_q counts.  qoff
+ * (n_q + 1 offsets into d_qbuf) and stats stay in host memory.  The call returns
+ * when the results are complete in device memory.  Errors as gg_search_batch.
+ */
+gg_status gg_search_batch_device(const gg_index *index, const char *d_qbuf, const int64_t *qoff,
+                                 int64_t n_q, const gg_params *params, gg_hit *d_out,
+                                 int32_t cap, int32_t *d_n_out, gg_stats *stats);
+
+/* Plain device-memory plumbing for the device-resident form (synchronous). */
+gg_status gg_device_alloc(int32_t device, uint64_t bytes, void **ptr);
+gg_status gg_device_free(int32_t device, void *ptr);
+gg_status gg_memcpy_to_device(void *dst, const void *src, uint64_t bytes);
+gg_status gg_memcpy_to_host(void *dst, const void *src, uint64_t bytes);
+
+/*
  * Per-stage GPU timing of batched searches on this index, for roofline reports.
  * Enabling records HIP events around each stage on the stream it runs on.
- * stage names: "encode", "scan", "gather", "sort", "chain", "extend", "merge",
- * "select", "align", "report".  ms is the summed kernel time, launches the number
- * of timed stage runs, units the stage's work units (hits for gather/chain, key
- * passes x keys for sort, cells for align, ...).
+ * Names: "encode", "scan", "gather_prep", "gather" (the posting-gather kernel
+ * alone), "sort_hist", "sort_scan", "sort_scatter" (one mark per radix pass of the
+ * hit sort), "chain", "extend", "merge", "select", "align" (the banded
+ * Smith-Waterman kernel alone), "report".  ms is the summed GPU time between the
+ * marks, launches the number of marks, units the work they covered (query bases
+ * for encode and scan, positions for gather_prep, hits for gather, the sort marks and chain, runs
+ * for extend/merge/select, boxes for align/report).
  */
 gg_status gg_profile_enable(gg_index *index, int32_t on);
 gg_status gg_profile_read(const gg_index *index, const char *stage, double *ms,

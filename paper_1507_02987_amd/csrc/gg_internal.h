@@ -85,6 +85,11 @@ void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                uint32_t n, int lo, int hi, uint32_t *hist, uint32_t *partials, hipStream_t st);
 size_t radix_hist_needed(uint32_t n);
+// The three kernels of one radix pass (digit histogram, its scan, stable scatter).
+void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st);
+void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st);
+void launch_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout,
+                       uint32_t n, int shift, const uint32_t *hist, hipStream_t st);
 void launch_chain(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k, int32_t max_gap,
                   int32_t min_len, Cand *out, uint32_t cap, uint32_t *count,
                   uint32_t *cand_per_q, hipStream_t st);
@@ -112,5 +117,9 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
                 unsigned long long *cells_per_q, hipStream_t st);
+// Results of queries [qa, qa + nq) as gg_hit records (11 int32) in device memory.
+void launch_write_out(const Align *sorted, const uint32_t *rstart, const uint32_t *rend,
+                      int32_t nq, int32_t qa, int32_t cap, int32_t *out, int32_t *n_out,
+                      hipStream_t st);
 
 }  // namespace gg

@@ -434,22 +434,39 @@ size_t radix_hist_needed(uint32_t n)
     return nb * kRadix + 1;
 }
 
+void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st)
+{
+    const uint32_t nb = (n + kTile - 1) / kTile;
+    k_rs_hist<<<nb, kBlock, 0, st>>>(keys, n, shift, hist, nb);
+}
+
+void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st)
+{
+    const uint32_t nb = (n + kTile - 1) / kTile;
+    scan_impl<uint32_t, uint32_t>(hist, hist, (int64_t)nb * kRadix, partials, st);
+}
+
+void launch_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout,
+                       uint32_t n, int shift, const uint32_t *hist, hipStream_t st)
+{
+    const uint32_t nb = (n + kTile - 1) / kTile;
+    if (vin)
+        k_rs_scatter<true><<<nb, kBlock, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nb);
+    else
+        k_rs_scatter<false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n, shift, hist, nb);
+}
+
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                uint32_t n, int lo, int hi, uint32_t *hist, uint32_t *partials, hipStream_t st)
 {
     int cur = 0;
     if (n <= 1 || hi <= lo) return 0;
-    const uint32_t nb = (n + kTile - 1) / kTile;
     for (int shift = lo; shift < hi; shift += kRadixBits) {
         uint64_t *kin = cur ? keys_alt : keys, *kout = cur ? keys : keys_alt;
         uint32_t *vin = cur ? vals_alt : vals, *vout = cur ? vals : vals_alt;
-        k_rs_hist<<<nb, kBlock, 0, st>>>(kin, n, shift, hist, nb);
-        scan_impl<uint32_t, uint32_t>(hist, hist, (int64_t)nb * kRadix, partials, st);
-        if (vals)
-            k_rs_scatter<true><<<nb, kBlock, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nb);
-        else
-            k_rs_scatter<false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n, shift, hist,
-                                                       nb);
+        launch_rs_hist(kin, n, shift, hist, st);
+        launch_rs_scan(hist, n, partials, st);
+        launch_rs_scatter(kin, vals ? vin : nullptr, kout, vout, n, shift, hist, st);
         cur ^= 1;
     }
     return cur;
@@ -920,6 +937,29 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
     k_bsw<<<(nsel_total + per - 1) / per, kBlock, 0, st>>>(
         sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw, seq_start, match, mismatch,
         gap_open + gap_extend, gap_extend, band, out, cells_per_q);
+}
+
+// ------------------------------------------------------------------ results to device memory
+// One block per query: its first min(cap, n) ordered alignments become gg_hit
+// records at out[q * cap], and its count goes to n_out[q].
+__global__ void k_write_out(const Align *__restrict__ sorted, const uint32_t *__restrict__ rstart,
+                            const uint32_t *__restrict__ rend, int32_t qa, int32_t cap,
+                            int32_t *__restrict__ out, int32_t *__restrict__ n_out)
+{
+    const int32_t ql = blockIdx.x;
+    const uint32_t a = rstart[ql], n = rend[ql] - a;
+    if (threadIdx.x == 0) n_out[qa + ql] = (int32_t)n;
+    const uint32_t m = min(n, (uint32_t)cap);
+    int32_t *dst = out + ((size_t)(qa + ql) * (size_t)cap) * 11;
+    const int32_t *src = reinterpret_cast<const int32_t *>(sorted + a);  // 12 int32 per record
+    for (uint32_t e = threadIdx.x; e < m * 11; e += blockDim.x) dst[e] = src[(e / 11) * 12 + 1 + e % 11];
+}
+
+void launch_write_out(const Align *sorted, const uint32_t *rstart, const uint32_t *rend,
+                      int32_t nq, int32_t qa, int32_t cap, int32_t *out, int32_t *n_out,
+                      hipStream_t st)
+{
+    if (nq > 0) k_write_out<<<nq, kBlock, 0, st>>>(sorted, rstart, rend, qa, cap, out, n_out);
 }
 
 }  // namespace gg

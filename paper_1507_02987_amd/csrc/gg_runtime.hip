@@ -325,10 +325,11 @@ gg_status check_params(const gg_params *p)
 }
 
 struct BatchOut {
-    gg_hit *out;
+    gg_hit *out;        // host results (host form) or device results (device form)
     int32_t cap;
-    int32_t *n_out;
-    gg_stats *stats;
+    int32_t *n_out;     // host counts (host form) or device counts (device form)
+    gg_stats *stats;    // host, or NULL
+    bool device = false;
     bool truncated = false;
 };
 
@@ -354,8 +355,9 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             s.n_kmers = L >= ix->k ? L - ix->k + 1 : 0;
             s.n_hits = (int64_t)qtot[q];
         }
-        bo.n_out[q] = 0;
+        if (!bo.device) bo.n_out[q] = 0;
     }
+    if (bo.device) HIPCHK(hipMemsetAsync(bo.n_out + qa, 0, sizeof(int32_t) * nqw, st));
     if (H64 == 0) return GG_OK;
     const uint32_t H = (uint32_t)H64;
 
@@ -377,23 +379,34 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     TRY(ensure(ws->keys_alt, sizeof(uint64_t) * H));
     TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(H)));
     TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(H))));
-    prof.begin("gather");
+    prof.begin("gather_prep");
     launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
                      as<int32_t>(ws->qid), ix->d_list_off, qa, g0, g1, lay, as<uint32_t>(ws->hrel),
                      as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), st);
+    prof.end(np);
+    prof.begin("gather");
     launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), np,
                   ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
     prof.end(H);
 
     // ---- S4 group: order hits by (q, s, diag); qpos order is kept by stability
-    prof.begin("sort");
     const int sort_lo = lay.bp, sort_hi = lay.bp + lay.bd + lay.bs + lay.bq;
-    const int where = radix_sort(as<uint64_t>(ws->keys), as<uint64_t>(ws->keys_alt), nullptr,
-                                 nullptr, H, sort_lo, sort_hi, as<uint32_t>(ws->hist),
-                                 as<uint32_t>(ws->rs_partials), st);
-    const uint64_t *sorted = where ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys);
-    const int passes = (sort_hi - sort_lo + kRadixBits - 1) / kRadixBits;
-    prof.end((int64_t)H * passes);
+    uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
+    if (H > 1) {
+        for (int shift = sort_lo; shift < sort_hi; shift += kRadixBits) {
+            prof.begin("sort_hist");
+            launch_rs_hist(kcur, H, shift, as<uint32_t>(ws->hist), st);
+            prof.end(H);
+            prof.begin("sort_scan");
+            launch_rs_scan(as<uint32_t>(ws->hist), H, as<uint32_t>(ws->rs_partials), st);
+            prof.end(H);
+            prof.begin("sort_scatter");
+            launch_rs_scatter(kcur, nullptr, knext, nullptr, H, shift, as<uint32_t>(ws->hist), st);
+            prof.end(H);
+            std::swap(kcur, knext);
+        }
+    }
+    const uint64_t *sorted = kcur;
 
     // ---- S5 chain + filter (runs past the buffer are counted, then the buffer grows)
     uint32_t ccap = (uint32_t)std::min<uint64_t>(H, std::max<uint64_t>(1u << 20, H / 8));
@@ -536,9 +549,16 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                           as<uint32_t>(ws->rend), st);
     prof.end(nsel);
 
-    // ---- copy back the ordered alignments and per-query ranges
-    std::vector<Align> res(nsel);
-    HIPCHK(hipMemcpyAsync(res.data(), ws->aligns2.p, sizeof(Align) * nsel, hipMemcpyDeviceToHost, st));
+    // ---- results: ordered alignments and per-query ranges
+    std::vector<Align> res;
+    if (bo.device) {
+        launch_write_out(as<Align>(ws->aligns2), as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend),
+                         nqw, qa, bo.cap, reinterpret_cast<int32_t *>(bo.out), bo.n_out, st);
+    } else {
+        res.resize(nsel);
+        HIPCHK(hipMemcpyAsync(res.data(), ws->aligns2.p, sizeof(Align) * nsel,
+                              hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipMemcpyAsync(h_rs, ws->rstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_re, ws->rend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
     if (bo.stats) {
@@ -550,15 +570,17 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     for (int32_t ql = 0; ql < nqw; ++ql) {
         const int32_t q = qa + ql;
         const uint32_t n = h_re[ql] - h_rs[ql];
-        bo.n_out[q] = (int32_t)n;
         if (n > (uint32_t)bo.cap) bo.truncated = true;
-        const uint32_t m = std::min<uint32_t>(n, (uint32_t)bo.cap);
-        gg_hit *dst = bo.out + (size_t)q * bo.cap;
-        for (uint32_t r = 0; r < m; ++r) {
-            const Align &a = res[h_rs[ql] + r];
-            dst[r] = gg_hit{a.seq_id,      a.score,       a.q_start,     a.q_end,
-                            a.d_start,     a.d_end,       a.box_q_start, a.box_q_end,
-                            a.box_d_start, a.box_d_end,   a.box_len};
+        if (!bo.device) {
+            bo.n_out[q] = (int32_t)n;
+            const uint32_t m = std::min<uint32_t>(n, (uint32_t)bo.cap);
+            gg_hit *dst = bo.out + (size_t)q * bo.cap;
+            for (uint32_t r = 0; r < m; ++r) {
+                const Align &a = res[h_rs[ql] + r];
+                dst[r] = gg_hit{a.seq_id,      a.score,     a.q_start,     a.q_end,
+                                a.d_start,     a.d_end,     a.box_q_start, a.box_q_end,
+                                a.box_d_start, a.box_d_end, a.box_len};
+            }
         }
         if (bo.stats) {
             gg_stats &s = bo.stats[q];
@@ -586,7 +608,13 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     if (T > 0 && !qbuf) return GG_EINVAL;
     Prof prof(ix, ws);
 
-    TRY(ensure(ws->ascii, T));
+    const uint8_t *ascii = nullptr;
+    if (bo.device) {
+        ascii = reinterpret_cast<const uint8_t *>(qbuf) + qoff[0];
+    } else {
+        TRY(ensure(ws->ascii, T));
+        ascii = as<uint8_t>(ws->ascii);
+    }
     TRY(ensure(ws->qoff, sizeof(int64_t) * (nq + 1)));
     TRY(ensure(ws->qcode, T));
     TRY(ensure(ws->kcode, sizeof(uint32_t) * T));
@@ -596,14 +624,15 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(T, nq + 1))));
     TRY(ensure(ws->qtot, sizeof(uint64_t) * nq));
     TRY(ensure(ws->err, sizeof(int32_t) * 4));
-    if (T > 0) HIPCHK(hipMemcpyAsync(ws->ascii.p, qbuf + qoff[0], T, hipMemcpyHostToDevice, st));
+    if (T > 0 && !bo.device)
+        HIPCHK(hipMemcpyAsync(ws->ascii.p, qbuf + qoff[0], T, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ws->qoff.p, qoff_h.data(), sizeof(int64_t) * (nq + 1),
                           hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(ws->err.p, 0, sizeof(int32_t), st));
 
     // ---- S1 encode + S2 count and scan
     prof.begin("encode");
-    launch_encode_kmers(as<uint8_t>(ws->ascii), as<int64_t>(ws->qoff), (int32_t)nq, T, ix->k,
+    launch_encode_kmers(ascii, as<int64_t>(ws->qoff), (int32_t)nq, T, ix->k,
                         ix->d_list_off, as<uint8_t>(ws->qcode), as<uint32_t>(ws->kcode),
                         as<uint32_t>(ws->cnt), as<int32_t>(ws->qid), as<int32_t>(ws->err), st);
     prof.end(T);
@@ -660,7 +689,7 @@ uint64_t index_budget(const gg_index *ix) { return budget_of(ix); }
 
 gg_status search_batch_budget(const gg_index *ix, const char *qbuf, const int64_t *qoff,
                               int64_t n_q, const gg_params *params, gg_hit *out, int32_t cap,
-                              int32_t *n_out, gg_stats *stats, uint64_t budget)
+                              int32_t *n_out, gg_stats *stats, uint64_t budget, bool device)
 {
     if (!ix || n_q < 0 || n_q > (1 << 30) || cap < 0 || (n_q > 0 && (!qoff || !n_out)) ||
         (cap > 0 && n_q > 0 && !out))
@@ -671,6 +700,7 @@ gg_status search_batch_budget(const gg_index *ix, const char *qbuf, const int64_
     Workspace *ws = nullptr;
     TRY(get_ws(ix, &ws));
     BatchOut bo{out, cap, n_out, stats};
+    bo.device = device;
     gg_status s = run_batch(ix, ws, qbuf, qoff, n_q, params, bo, budget);
     if (s != GG_OK) {
         (void)hipStreamSynchronize(ws->st);
@@ -880,7 +910,51 @@ gg_status gg_search_batch(const gg_index *ix, const char *qbuf, const int64_t *q
 {
     if (!ix) return GG_EINVAL;
     return gg::search_batch_budget(ix, qbuf, qoff, n_q, params, out, cap, n_out, stats,
-                                   budget_of(ix));
+                                   budget_of(ix), false);
+}
+
+gg_status gg_search_batch_device(const gg_index *ix, const char *d_qbuf, const int64_t *qoff,
+                                 int64_t n_q, const gg_params *params, gg_hit *d_out, int32_t cap,
+                                 int32_t *d_n_out, gg_stats *stats)
+{
+    if (!ix) return GG_EINVAL;
+    if (n_q > 0 && !d_n_out) return GG_EINVAL;
+    return gg::search_batch_budget(ix, d_qbuf, qoff, n_q, params, d_out, cap, d_n_out, stats,
+                                   budget_of(ix), true);
+}
+
+gg_status gg_device_alloc(int32_t device, uint64_t bytes, void **ptr)
+{
+    if (!ptr) return GG_EINVAL;
+    *ptr = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return GG_EDEVICE;
+    if (hipMalloc(ptr, std::max<uint64_t>(bytes, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return GG_ENOMEM;
+    }
+    return GG_OK;
+}
+
+gg_status gg_device_free(int32_t device, void *ptr)
+{
+    if (!ptr) return GG_OK;
+    if (hipSetDevice(device) != hipSuccess) return GG_EDEVICE;
+    return hipFree(ptr) == hipSuccess ? GG_OK : GG_EDEVICE;
+}
+
+gg_status gg_memcpy_to_device(void *dst, const void *src, uint64_t bytes)
+{
+    if (bytes == 0) return GG_OK;
+    if (!dst || !src) return GG_EINVAL;
+    return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess ? GG_OK : GG_EDEVICE;
+}
+
+gg_status gg_memcpy_to_host(void *dst, const void *src, uint64_t bytes)
+{
+    if (bytes == 0) return GG_OK;
+    if (!dst || !src) return GG_EINVAL;
+    return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) == hipSuccess ? GG_OK : GG_EDEVICE;
 }
 
 gg_status gg_search(const gg_index *ix, const char *query, int64_t qlen, const gg_params *params,

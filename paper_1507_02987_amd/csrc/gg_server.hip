@@ -23,7 +23,7 @@
 namespace gg {
 gg_status search_batch_budget(const gg_index *ix, const char *qbuf, const int64_t *qoff,
                               int64_t n_q, const gg_params *params, gg_hit *out, int32_t cap,
-                              int32_t *n_out, gg_stats *stats, uint64_t budget);
+                              int32_t *n_out, gg_stats *stats, uint64_t budget, bool device);
 uint64_t index_budget(const gg_index *ix);
 }  // namespace gg
 
@@ -92,7 +92,7 @@ void worker_loop(gg_server *sv)
         nout.assign(n, 0);
         gg_status st = gg::search_batch_budget(sv->ix, buf.data(), off.data(), (int64_t)n,
                                                &sv->params, out.data(), cap0, nout.data(), nullptr,
-                                               sv->budget);
+                                               sv->budget, false);
         std::vector<gg_status> each(n, st);
         if (st == GG_EBUDGET || st == GG_EINVAL) {
             // one bad or oversized query must not fail its batch-mates: run each alone
@@ -100,7 +100,7 @@ void worker_loop(gg_server *sv)
                 const int64_t o2[2] = {0, off[i + 1] - off[i]};
                 each[i] = gg::search_batch_budget(sv->ix, buf.data() + off[i], o2, 1, &sv->params,
                                                   out.data() + i * cap0, cap0, &nout[i], nullptr,
-                                                  sv->budget);
+                                                  sv->budget, false);
             }
         }
         for (size_t i = 0; i < n; ++i) {
@@ -113,7 +113,7 @@ void worker_loop(gg_server *sv)
                     const int64_t o2[2] = {0, off[i + 1] - off[i]};
                     r->status = gg::search_batch_budget(sv->ix, buf.data() + off[i], o2, 1,
                                                         &sv->params, big.data(), nout[i], &n2,
-                                                        nullptr, sv->budget);
+                                                        nullptr, sv->budget, false);
                     big.resize((size_t)std::min(n2, nout[i]));
                     r->hits.swap(big);
                 } else {
@@ -153,7 +153,7 @@ gg_status gg_server_create(const gg_index *ix, const gg_params *params, uint64_t
     int32_t dummy = 0;
     const int64_t off0[1] = {0};
     gg_status s = gg::search_batch_budget(ix, "", off0, 0, params, nullptr, 0, &dummy, nullptr,
-                                          sv->budget);
+                                          sv->budget, false);
     if (s != GG_OK) {
         delete sv;
         return s;

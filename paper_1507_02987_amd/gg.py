@@ -26,7 +26,9 @@ STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 
 # Exported symbols of include/gg.h, in declaration order.
 SYMBOLS = ("gg_index_build", "gg_index_free", "gg_index_info", "gg_index_set_hit_budget",
-           "gg_search", "gg_search_batch", "gg_profile_enable", "gg_profile_read",
+           "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
+           "gg_device_free", "gg_memcpy_to_device", "gg_memcpy_to_host",
+           "gg_profile_enable", "gg_profile_read",
            "gg_server_create", "gg_serve_submit", "gg_serve_poll", "gg_server_destroy",
            "gg_strerror")
 
@@ -67,6 +69,11 @@ def lib():
         L.gg_index_set_hit_budget.argtypes = [vp, u64]
         L.gg_search.argtypes = [vp, vp, i64, C.POINTER(Params), vp, i32, vp]
         L.gg_search_batch.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, i32, vp, vp]
+        L.gg_search_batch_device.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, i32, vp, vp]
+        L.gg_device_alloc.argtypes = [i32, u64, C.POINTER(vp)]
+        L.gg_device_free.argtypes = [i32, vp]
+        L.gg_memcpy_to_device.argtypes = [vp, vp, u64]
+        L.gg_memcpy_to_host.argtypes = [vp, vp, u64]
         L.gg_profile_enable.argtypes = [vp, i32]
         L.gg_profile_read.argtypes = [vp, C.c_char_p, vp, vp, vp]
         L.gg_server_create.argtypes = [vp, C.POINTER(Params), u64, i32, C.POINTER(vp)]
@@ -163,6 +170,16 @@ class Index:
         res = [out[i * cap: i * cap + min(int(nout[i]), cap)].copy() for i in range(nq)]
         return rc, res, nout[:nq].copy(), (st[:nq] if stats else None)
 
+    def search_batch_device(self, dq: "DeviceBuffer", qoff, prm: Params, dout: "DeviceBuffer",
+                            dn: "DeviceBuffer", cap: int, stats: bool = False):
+        """gg_search_batch_device on device-resident queries and result buffers."""
+        off = np.ascontiguousarray(qoff, dtype=np.int64)
+        nq = len(off) - 1
+        st = np.zeros(max(nq, 1), dtype=STAT_DTYPE) if stats else None
+        rc = lib().gg_search_batch_device(self._h, dq.ptr, _ptr(off), nq, C.byref(prm), dout.ptr,
+                                          cap, dn.ptr, _ptr(st) if stats else None)
+        return rc, (st[:nq] if stats else None)
+
     # ---- per-stage GPU timing
     def profile(self, on: bool = True):
         rc = lib().gg_profile_enable(self._h, 1 if on else 0)
@@ -175,6 +192,42 @@ class Index:
         if rc != GG_OK:
             raise GGError(rc, "gg_profile_read")
         return {"ms": ms.value, "launches": la.value, "units": un.value}
+
+
+class DeviceBuffer:
+    """gg_device_alloc / gg_device_free: raw GPU memory for the device-resident form."""
+
+    def __init__(self, nbytes: int, device: int = 0):
+        p = C.c_void_p()
+        rc = lib().gg_device_alloc(device, int(nbytes), C.byref(p))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_device_alloc")
+        self.ptr, self.nbytes, self.device = p, int(nbytes), device
+
+    def upload(self, a: np.ndarray):
+        a = np.ascontiguousarray(a)
+        assert a.nbytes <= self.nbytes
+        rc = lib().gg_memcpy_to_device(self.ptr, _ptr(a), a.nbytes)
+        if rc != GG_OK:
+            raise GGError(rc, "gg_memcpy_to_device")
+
+    def download(self, a: np.ndarray) -> np.ndarray:
+        assert a.flags.c_contiguous and a.nbytes <= self.nbytes
+        rc = lib().gg_memcpy_to_host(_ptr(a), self.ptr, a.nbytes)
+        if rc != GG_OK:
+            raise GGError(rc, "gg_memcpy_to_host")
+        return a
+
+    def close(self):
+        if getattr(self, "ptr", None) and self.ptr.value:
+            lib().gg_device_free(self.device, self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

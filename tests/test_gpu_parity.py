@@ -177,3 +177,25 @@ def test_config1_full_bank_sampled(ggo):
         assert orc == 0
         assert as_rows(got[i]) == as_rows(oh), int(i)
         assert int(st[i]["n_hits"]) == ost["n_hits"] and int(st[i]["n_cells"]) == ost["n_cells"]
+
+
+def test_device_resident_form(ggo, c0):
+    """gg_search_batch_device (queries and hits in GPU memory) equals the oracle."""
+    G, db, qs, gix, oix = c0
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(20))
+    cap = 8
+    dq = G.DeviceBuffer(len(qs.buf))
+    dq.upload(qs.buf)
+    dout = G.DeviceBuffer(qs.n * cap * G.HIT_DTYPE.itemsize)
+    dn = G.DeviceBuffer(qs.n * 4)
+    for rep in range(2):  # the second call reuses the workspace
+        rc, st = gix.search_batch_device(dq, qs.off, G.params(20), dout, dn, cap, stats=True)
+        assert rc in (G.GG_OK, G.GG_ETRUNC)
+        n = dn.download(np.zeros(qs.n, np.int32))
+        got = dout.download(np.zeros(qs.n * cap, G.HIT_DTYPE))
+        for i in range(qs.n):
+            assert int(n[i]) == len(want[i])
+            m = min(cap, len(want[i]))
+            assert as_rows(got[i * cap: i * cap + m]) == as_rows(want[i][:m])
+            assert int(st[i]["n_cells"]) == wst[i]["n_cells"]
+        assert (rc == G.GG_ETRUNC) == any(len(w) > cap for w in want)
