@@ -15,6 +15,8 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kGatherCap = 4096;         // positions of one gather tile kept in LDS
 constexpr int kMaxBand = 63;             // band half-width supported by one wave
+constexpr int kSegCap = 1024;            // records of one query sorted in LDS
+constexpr int kBswStage = 4096;          // box bases staged in LDS by the aligner
 
 // A chained run of hits: query (local to the wave), sequence, diagonal, [qs, qe).
 struct Cand {
@@ -90,9 +92,20 @@ void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist,
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st);
 void launch_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout,
                        uint32_t n, int shift, const uint32_t *hist, hipStream_t st);
-void launch_chain(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k, int32_t max_gap,
-                  int32_t min_len, Cand *out, uint32_t cap, uint32_t *count,
-                  uint32_t *cand_per_q, hipStream_t st);
+// Runs in hit-key order: per-tile counts, then (after a scan of them) the writes.
+uint32_t chain_tiles(uint32_t n);
+void launch_chain_count(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
+                        int32_t max_gap, int32_t min_len, uint32_t *counts, hipStream_t st);
+void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
+                        int32_t max_gap, int32_t min_len, const uint32_t *tile_off, Cand *out,
+                        uint32_t *cand_per_q, hipStream_t st);
+// Per-query LDS sorts (segments of at most kSegCap records; longer ones are skipped).
+// mode 0: merge order, mode 1: selection order.
+void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_off, int32_t nq,
+                         hipStream_t st);
+void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int32_t nq,
+                       uint32_t *rstart, uint32_t *rend, int32_t qa, int32_t cap, int32_t *dev_out,
+                       int32_t *dev_n, hipStream_t st);
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
                    int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
                    int32_t mismatch, int32_t xdrop, Box *out, hipStream_t st);

@@ -473,78 +473,172 @@ int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *val
 }
 
 // ------------------------------------------------------------------ S5: chain + filter
-// One thread per sorted hit.  A hit ends a run when the next hit is in another
-// (q, s, diag) group or further than G past this hit's window; the run's first
-// hit is found by walking back while the chaining rule holds.  Runs with
-// qe - qs >= M are appended (one atomic per wave).
-__global__ __launch_bounds__(kBlock) void k_chain(const uint64_t *__restrict__ keys, uint32_t n,
-                                                  HitKeyLayout lay, int32_t k, int32_t G,
-                                                  int32_t M, Cand *__restrict__ out,
-                                                  uint32_t cap, uint32_t *__restrict__ count,
-                                                  uint32_t *__restrict__ cand_per_q)
+// A sorted hit ends a run when the next hit is in another (q, s, diag) group or
+// more than G past this hit's window; the run's first hit is found by walking back
+// while the chaining rule holds.  Runs with qe - qs >= M are kept.  Two passes
+// over tiles of hits (count, then write after a scan of the tile counts) keep the
+// runs in hit-key order, so they come out grouped by query and sequence.
+__device__ __forceinline__ bool chain_end(const uint64_t *__restrict__ keys, uint32_t n,
+                                          uint32_t i, int bp, int32_t k, int32_t G, int32_t M,
+                                          int32_t *qs_out)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t pmask = low_mask(lay.bp);
-    bool emit = false;
-    Cand c{0, 0, 0, 0, 0};
-    if (i < n) {
-        const uint64_t key = keys[i];
-        const uint64_t grp = key >> lay.bp;
-        const int32_t qp = (int32_t)(key & pmask);
-        bool end = true;
-        if (i + 1 < n) {
-            const uint64_t nx = keys[i + 1];
-            end = ((nx >> lay.bp) != grp) || ((int32_t)(nx & pmask) - (qp + k) > G);
-        }
-        if (end) {
-            uint32_t j = i;
-            int32_t qj = qp;
-            while (j > 0) {
-                const uint64_t pv = keys[j - 1];
-                if ((pv >> lay.bp) != grp) break;
-                const int32_t qv = (int32_t)(pv & pmask);
-                if (qj - (qv + k) > G) break;
-                --j;
-                qj = qv;
-            }
-            if (qp + k - qj >= M) {
-                emit = true;
-                c.d = (int32_t)(grp & low_mask(lay.bd)) - lay.bias;
-                c.s = (int32_t)(shr64(grp, lay.bd) & low_mask(lay.bs));
-                c.q = (int32_t)shr64(grp, lay.bd + lay.bs);
-                c.qs = qj;
-                c.qe = qp + k;
-            }
-        }
+    const uint64_t pmask = low_mask(bp);
+    const uint64_t key = keys[i];
+    const uint64_t grp = key >> bp;
+    const int32_t qp = (int32_t)(key & pmask);
+    if (i + 1 < n) {
+        const uint64_t nx = keys[i + 1];
+        if ((nx >> bp) == grp && (int32_t)(nx & pmask) - (qp + k) <= G) return false;
     }
-    const uint64_t m = __ballot(emit);
-    if (m) {
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-        base = __shfl(base, leader, 64);
+    uint32_t j = i;
+    int32_t qj = qp;
+    while (j > 0) {
+        const uint64_t pv = keys[j - 1];
+        if ((pv >> bp) != grp) break;
+        const int32_t qv = (int32_t)(pv & pmask);
+        if (qj - (qv + k) > G) break;
+        --j;
+        qj = qv;
+    }
+    *qs_out = qj;
+    return qp + k - qj >= M;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chain_count(const uint64_t *__restrict__ keys,
+                                                        uint32_t n, int bp, int32_t k, int32_t G,
+                                                        int32_t M, uint32_t *__restrict__ counts)
+{
+    const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = base + r * kBlock + threadIdx.x;
+        int32_t qs;
+        if (i < n && chain_end(keys, n, i, bp, k, G, M, &qs)) ++c;
+    }
+    uint32_t tot;
+    block_excl_scan<uint32_t>(c, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restrict__ keys,
+                                                        uint32_t n, HitKeyLayout lay, int32_t k,
+                                                        int32_t G, int32_t M,
+                                                        const uint32_t *__restrict__ tile_off,
+                                                        Cand *__restrict__ out,
+                                                        uint32_t *__restrict__ cand_per_q)
+{
+    const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    uint32_t at = tile_off[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = base + r * kBlock + threadIdx.x;
+        int32_t qs = 0;
+        const bool emit = i < n && chain_end(keys, n, i, lay.bp, k, G, M, &qs);
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<uint32_t>(emit ? 1u : 0u, &tot);
         if (emit) {
-            const uint32_t at = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            if (at < cap) out[at] = c;  // past cap: only counted, the caller grows and reruns
+            const uint64_t key = keys[i];
+            const uint64_t grp = key >> lay.bp;
+            Cand c;
+            c.d = (int32_t)(grp & low_mask(lay.bd)) - lay.bias;
+            c.s = (int32_t)(shr64(grp, lay.bd) & low_mask(lay.bs));
+            c.q = (int32_t)shr64(grp, lay.bd + lay.bs);
+            c.qs = qs;
+            c.qe = (int32_t)(key & low_mask(lay.bp)) + k;
+            out[at + ex] = c;
             atomicAdd(&cand_per_q[c.q], 1u);
         }
+        at += tot;
     }
 }
 
-void launch_chain(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k, int32_t max_gap,
-                  int32_t min_len, Cand *out, uint32_t cap, uint32_t *count,
-                  uint32_t *cand_per_q, hipStream_t st)
+void launch_chain_count(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
+                        int32_t max_gap, int32_t min_len, uint32_t *counts, hipStream_t st)
 {
     if (n == 0) return;
-    k_chain<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(keys, n, lay, k, max_gap, min_len, out,
-                                                           cap, count, cand_per_q);
+    k_chain_count<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(keys, n, lay.bp, k, max_gap, min_len,
+                                                              counts);
 }
 
+void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
+                        int32_t max_gap, int32_t min_len, const uint32_t *tile_off, Cand *out,
+                        uint32_t *cand_per_q, hipStream_t st)
+{
+    if (n == 0) return;
+    k_chain_write<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(keys, n, lay, k, max_gap, min_len,
+                                                              tile_off, out, cand_per_q);
+}
+
+uint32_t chain_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
+
 // ------------------------------------------------------------------ S6: X-drop extension
-// One thread per run: ungapped walk right from qe and left from qs - 1 along the
-// run's diagonal; each side stops at a sequence end or when the running sum drops
-// more than X below its best, and extends to the first position of that best.
+// One wave per run and side.  The walk is taken 64 steps at a time: each lane
+// scores one step, a wave prefix sum gives the running sums, a prefix maximum the
+// best-so-far, and the first lane whose sum is more than X below that best ends
+// the walk.  The extension is the first step at the best sum (strictly above the
+// best of earlier steps), exactly as a step-by-step walk finds it.
+__device__ __forceinline__ int32_t wave_incl_sum(int32_t x, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int32_t wave_incl_max(int32_t x, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x = max(x, y);
+    }
+    return x;
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// Steps s = 0 .. T-1 score query base from + s (right) or from - 1 - s (left)
+// against data-bank base at the same query position + d.
+template <bool RIGHT>
+__device__ __forceinline__ int32_t xdrop_side(const uint8_t *__restrict__ q,
+                                              const uint32_t *__restrict__ dbw, int64_t s0,
+                                              int32_t from, int32_t d, int32_t T, int32_t match,
+                                              int32_t mismatch, int32_t X, int lane)
+{
+    int32_t run = 0, best = 0, bl = 0;
+    for (int32_t base = 0; base < T; base += 64) {
+        const int32_t step = base + lane;
+        const bool valid = step < T;
+        int32_t v = 0;
+        if (valid) {
+            const int32_t qi = RIGHT ? from + step : from - 1 - step;
+            v = ((int32_t)q[qi] == db_base(dbw, s0 + qi + d)) ? match : -mismatch;
+        }
+        const int32_t r = run + wave_incl_sum(v, lane);
+        const int32_t bt = max(best, wave_incl_max(r, lane));
+        const uint64_t sm = __ballot(valid && (bt - r > X));
+        const int32_t lim = sm ? (__ffsll((unsigned long long)sm) - 1) : min(63, T - 1 - base);
+        const bool in = lane <= lim;
+        const int32_t m = wave_max(in ? r : INT32_MIN);
+        if (m > best) {
+            const uint64_t am = __ballot(in && r == m);
+            best = m;
+            bl = base + __ffsll((unsigned long long)am);  // first step (1-based) at the best
+        }
+        run = __shfl(r, lim, 64);
+        if (sm) break;
+    }
+    return bl;
+}
+
 __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cands, uint32_t n,
                                                    const uint8_t *__restrict__ qcode,
                                                    const int64_t *__restrict__ qoff, int32_t qa,
@@ -553,8 +647,9 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
                                                    int32_t match, int32_t mismatch, int32_t X,
                                                    Box *__restrict__ out)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;  // whole wave
+    const int lane = threadIdx.x & 63;
     const Cand c = cands[i];
     const int64_t q0 = qoff[qa + c.q];
     const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
@@ -562,29 +657,14 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
     const int64_t s0 = seq_start[c.s];
     const int32_t ns = (int32_t)(seq_start[c.s + 1] - s0);
     const int32_t d = c.d;
-    int32_t run = 0, best = 0, bl = 0, t = 0;
-    while (c.qe + t < L && c.qe + d + t < ns) {
-        run += ((int32_t)q[c.qe + t] == db_base(dbw, s0 + c.qe + d + t)) ? match : -mismatch;
-        ++t;
-        if (run > best) {
-            best = run;
-            bl = t;
-        }
-        if (best - run > X) break;
+    const int32_t tr = min(L - c.qe, ns - (c.qe + d));
+    const int32_t tl = min(c.qs, c.qs + d);
+    const int32_t er = xdrop_side<true>(q, dbw, s0, c.qe, d, tr, match, mismatch, X, lane);
+    const int32_t el = xdrop_side<false>(q, dbw, s0, c.qs, d, tl, match, mismatch, X, lane);
+    if (lane == 0) {
+        const int32_t qs = c.qs - el, qe = c.qe + er;
+        out[i] = Box{c.q, c.s, qs, qe, qs + d, qe + d, d, d};
     }
-    const int32_t qe = c.qe + bl;
-    run = 0, best = 0, bl = 0, t = 0;
-    while (c.qs - 1 - t >= 0 && c.qs - 1 - t + d >= 0) {
-        run += ((int32_t)q[c.qs - 1 - t] == db_base(dbw, s0 + c.qs - 1 - t + d)) ? match : -mismatch;
-        ++t;
-        if (run > best) {
-            best = run;
-            bl = t;
-        }
-        if (best - run > X) break;
-    }
-    const int32_t qs = c.qs - bl;
-    out[i] = Box{c.q, c.s, qs, qe, qs + d, qe + d, d, d};
 }
 
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
@@ -592,8 +672,9 @@ void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_
                    int32_t mismatch, int32_t xdrop, Box *out, hipStream_t st)
 {
     if (n == 0) return;
-    k_extend<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start,
-                                                            match, mismatch, xdrop, out);
+    const uint32_t per = kBlock / 64;
+    k_extend<<<(n + per - 1) / per, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start, match,
+                                                      mismatch, xdrop, out);
 }
 
 // ------------------------------------------------------------------ record sort keys
@@ -700,6 +781,159 @@ void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Ali
     if (n) k_gather_rec<Align><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(in, perm, n, out);
 }
 
+// ------------------------------------------------------------------ per-query LDS sorts
+// The runs of one query are contiguous, so the record sorts of merging, selection
+// and reporting are segmented sorts: one block per query sorts its records in LDS
+// with a bitonic network on indices.  Ties between equal records fall back to the
+// input position, which makes the order total and the result deterministic.
+// Segments longer than kSegCap go through the global radix sort instead.
+template <typename Rec, typename Less>
+__device__ void lds_bitonic(const Rec *__restrict__ s_r, uint16_t *__restrict__ s_ix, uint32_t n,
+                            Less less)
+{
+    uint32_t n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) s_ix[i] = (uint16_t)i;
+    __syncthreads();
+    auto before = [&](uint32_t a, uint32_t b) -> bool {  // a strictly before b
+        if (a >= n) return false;
+        if (b >= n) return true;
+        if (less(s_r[a], s_r[b])) return true;
+        if (less(s_r[b], s_r[a])) return false;
+        return a < b;
+    };
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = s_ix[i], b = s_ix[l];
+                    const bool up = (i & k) == 0;
+                    if (up ? before(b, a) : before(a, b)) {
+                        s_ix[i] = (uint16_t)b;
+                        s_ix[l] = (uint16_t)a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// MODE 0: merge order (s, qs, ds, qe, de); MODE 1: selection order (kept boxes
+// first, then length descending, s, qs, ds, qe, de).  Length = min of the spans.
+template <int MODE>
+struct BoxLess {
+    __device__ bool operator()(const Box &x, const Box &y) const
+    {
+        if (MODE == 1) {
+            const bool vx = x.q >= 0, vy = y.q >= 0;
+            if (vx != vy) return vx;
+            if (!vx) return false;
+            const int32_t lx = min(x.qe - x.qs, x.de - x.ds), ly = min(y.qe - y.qs, y.de - y.ds);
+            if (lx != ly) return lx > ly;
+        }
+        if (x.s != y.s) return x.s < y.s;
+        if (x.qs != y.qs) return x.qs < y.qs;
+        if (x.ds != y.ds) return x.ds < y.ds;
+        if (x.qe != y.qe) return x.qe < y.qe;
+        return x.de < y.de;
+    }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_seg_sort_box(const Box *__restrict__ in,
+                                                         Box *__restrict__ out,
+                                                         const uint32_t *__restrict__ seg_off)
+{
+    __shared__ Box s_r[kSegCap];
+    __shared__ uint16_t s_ix[kSegCap];
+    const uint32_t a0 = seg_off[blockIdx.x], n = seg_off[blockIdx.x + 1] - a0;
+    if (n == 0 || n > (uint32_t)kSegCap) return;  // longer segments take the global sort
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_r[i] = in[a0 + i];
+    lds_bitonic(s_r, s_ix, n, BoxLess<MODE>());
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[a0 + i] = s_r[s_ix[i]];
+}
+
+void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_off, int32_t nq,
+                         hipStream_t st)
+{
+    if (nq <= 0) return;
+    if (mode == 0) k_seg_sort_box<0><<<nq, kBlock, 0, st>>>(in, out, seg_off);
+    else k_seg_sort_box<1><<<nq, kBlock, 0, st>>>(in, out, seg_off);
+}
+
+// Report order: alignments with score > 0 first, score descending, then seq,
+// q_start, d_start, q_end, d_end and the box.
+struct AlignLess {
+    __device__ bool operator()(const Align &x, const Align &y) const
+    {
+        const bool vx = x.score > 0, vy = y.score > 0;
+        if (vx != vy) return vx;
+        if (!vx) return false;
+        if (x.score != y.score) return x.score > y.score;
+        if (x.seq_id != y.seq_id) return x.seq_id < y.seq_id;
+        if (x.q_start != y.q_start) return x.q_start < y.q_start;
+        if (x.d_start != y.d_start) return x.d_start < y.d_start;
+        if (x.q_end != y.q_end) return x.q_end < y.q_end;
+        if (x.d_end != y.d_end) return x.d_end < y.d_end;
+        if (x.box_q_start != y.box_q_start) return x.box_q_start < y.box_q_start;
+        if (x.box_d_start != y.box_d_start) return x.box_d_start < y.box_d_start;
+        if (x.box_q_end != y.box_q_end) return x.box_q_end < y.box_q_end;
+        return x.box_d_end < y.box_d_end;
+    }
+};
+
+// One block per query: sort its aligned boxes, record the range of those with
+// score > 0, and (device form) write the first cap of them as gg_hit records.
+__global__ __launch_bounds__(kBlock) void k_report_seg(const Align *__restrict__ in,
+                                                       Align *__restrict__ out,
+                                                       const uint32_t *__restrict__ sel_off,
+                                                       uint32_t *__restrict__ rstart,
+                                                       uint32_t *__restrict__ rend, int32_t qa,
+                                                       int32_t cap, int32_t *__restrict__ dev_out,
+                                                       int32_t *__restrict__ dev_n)
+{
+    __shared__ Align s_r[kSegCap];
+    __shared__ uint16_t s_ix[kSegCap];
+    __shared__ uint32_t s_valid;
+    const int32_t ql = blockIdx.x;
+    const uint32_t a0 = sel_off[ql], n = sel_off[ql + 1] - a0;
+    if (n > (uint32_t)kSegCap) return;  // longer segments take the global sort
+    if (threadIdx.x == 0) s_valid = 0;
+    __syncthreads();
+    uint32_t v = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        s_r[i] = in[a0 + i];
+        v += s_r[i].score > 0 ? 1u : 0u;
+    }
+    if (v) atomicAdd(&s_valid, v);
+    lds_bitonic(s_r, s_ix, n, AlignLess());  // starts and ends with a barrier
+    const uint32_t nv = s_valid;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[a0 + i] = s_r[s_ix[i]];
+    if (threadIdx.x == 0) {
+        rstart[ql] = a0;
+        rend[ql] = a0 + nv;
+        if (dev_n) dev_n[qa + ql] = (int32_t)nv;
+    }
+    if (dev_out) {
+        const uint32_t m = min(nv, (uint32_t)cap);
+        int32_t *dst = dev_out + ((size_t)(qa + ql) * (size_t)cap) * 11;
+        for (uint32_t e = threadIdx.x; e < m * 11; e += blockDim.x) {
+            const int32_t *src = reinterpret_cast<const int32_t *>(&s_r[s_ix[e / 11]]);
+            dst[e] = src[1 + e % 11];
+        }
+    }
+}
+
+void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int32_t nq,
+                       uint32_t *rstart, uint32_t *rend, int32_t qa, int32_t cap, int32_t *dev_out,
+                       int32_t *dev_n, hipStream_t st)
+{
+    if (nq > 0)
+        k_report_seg<<<nq, kBlock, 0, st>>>(in, out, sel_off, rstart, rend, qa, cap, dev_out, dev_n);
+}
+
 // ------------------------------------------------------------------ S7: merge overlaps
 // Boxes sorted by (q, s, qs, ds, qe, de).  The thread at the start of each (q, s)
 // group sweeps it once, merging the next box into the open one when both their
@@ -798,11 +1032,160 @@ void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t 
 // ------------------------------------------------------------------ S9: banded Smith-Waterman
 // One wave per selected box.  Cells are swept by anti-diagonal a = i + j.  On
 // anti-diagonal a the band holds every other band diagonal t = j - i - c0 + W, all
-// of one parity p; lane u owns t = p + 2u, so at most W + 1 lanes are busy.  The
+// of one parity p; lane u owns t = p + 2u, so W + 1 lanes at most are busy.  The
 // left neighbour (t - 1) and the upper neighbour (t + 1) were on anti-diagonal
-// a - 1, in this lane or the next one over; the diagonal neighbour (same t) was
-// this lane's own cell on a - 2.  Starts are packed as i * 128 + t.
-__global__ __launch_bounds__(kBlock) void k_bsw(
+// a - 1 in this lane or the adjacent one, and arrive by a one-lane DPP shift; the
+// diagonal neighbour (same t) is this lane's own cell of a - 2.
+//
+// Each lane walks a staircase: after a step of parity 0 it moves one column
+// right, after parity 1 one row down.  The data-bank base a lane needs next is
+// the one its right neighbour holds, and the query base the one its left
+// neighbour holds, so bases also flow by lane shifts; only lane W (columns) and
+// lane 0 (rows) take new bases, from 64-base windows loaded one window ahead.
+// Starts and best cells are packed as i * 128 + t.
+// Lanes without a source (lane 0, resp. lane 63) read 0; the kernel never uses them.
+__device__ __forceinline__ int32_t from_lower_lane(int32_t v)  // lane u gets lane u - 1
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);  // wave_shr:1
+}
+__device__ __forceinline__ int32_t from_upper_lane(int32_t v)  // lane u gets lane u + 1
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);  // wave_shl:1
+}
+
+// In-band cells of an R x C box: band diagonals c = j - i in [clo, chi], each
+// holding min(R, C - c) - max(0, -c) cells.  Lane-parallel over c, wave sum.
+__device__ __forceinline__ unsigned long long band_cells(int32_t R, int32_t C, int32_t clo,
+                                                         int32_t chi, int32_t lane)
+{
+    unsigned long long n = 0;
+    for (int32_t c = clo + lane; c <= chi; c += 64) n += (uint32_t)(min(R, C - c) - max(0, -c));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+    return n;
+}
+
+// One cell of the affine recurrence with start tracking (see the oracle's O9):
+// E/F open from the left/upper cell when the open term is >= the extend term;
+// H > 0 takes its start from G (its diagonal predecessor's start, or itself if
+// that H <= 0), else from E, else from F.
+struct CellOut {
+    int32_t H, E, F, S, SE, SF;
+};
+
+__device__ __forceinline__ CellOut sw_cell(int32_t hl, int32_t el, int32_t sl, int32_t sel,
+                                           int32_t hu, int32_t fu, int32_t su, int32_t sfu,
+                                           int32_t hd, int32_t sd, bool same, int32_t here,
+                                           int32_t match, int32_t mismatch, int32_t o1,
+                                           int32_t ext)
+{
+    CellOut c;
+    const int32_t eo = hl - o1, ee = el - ext;
+    const bool eop = eo >= ee;
+    c.E = eop ? eo : ee;
+    c.SE = eop ? sl : sel;
+    const int32_t fo = hu - o1, fe = fu - ext;
+    const bool fop = fo >= fe;
+    c.F = fop ? fo : fe;
+    c.SF = fop ? su : sfu;
+    const int32_t g = hd + (same ? match : -mismatch);
+    c.H = max(max(g, 0), max(c.E, c.F));
+    const int32_t sg = hd > 0 ? sd : here;
+    c.S = (c.H > 0) ? ((g == c.H) ? sg : ((c.E == c.H) ? c.SE : c.SF)) : here;
+    return c;
+}
+
+// The sweep over anti-diagonals [a0, a1] in pairs: X = the lane's cell of even
+// parity (t = 2u) on a, Y = its cell of odd parity (t = 2u + 1) on a + 1, one
+// column to the right.  X's left neighbour is the lower lane's previous Y, its
+// upper neighbour this lane's previous Y, its diagonal this lane's previous X;
+// Y's left neighbour is this lane's X, its upper the upper lane's X, its diagonal
+// this lane's previous Y.
+template <bool STAGED>
+__device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
+                                          const uint8_t *__restrict__ sd,
+                                          const uint8_t *__restrict__ qp,
+                                          const uint32_t *__restrict__ dbw, int64_t dbase,
+                                          int32_t R, int32_t C, int32_t c0, int32_t W, int32_t a0,
+                                          int32_t a1, int32_t match, int32_t mismatch, int32_t o1,
+                                          int32_t ext, int32_t lane, int32_t &best,
+                                          int32_t &bcell, int32_t &bstart)
+{
+    const int32_t tX = 2 * lane, tY = tX + 1;
+    const bool laneX = tX <= 2 * W, laneY = tY <= 2 * W, topX = tX == 2 * W;
+    int32_t i = (a0 - (tX - W + c0)) >> 1;
+    int32_t j = a0 - i;
+    int32_t hereX = i * 128 + tX;
+    int32_t HX = kNegInf, EX = kNegInf, FX = kNegInf, SX = 0, SEX = 0, SFX = 0;
+    int32_t HY = kNegInf, EY = kNegInf, FY = kNegInf, SY = 0, SEY = 0, SFY = 0;
+    auto bases = [&](int32_t ii, int32_t jj, int32_t &qb, int32_t &dX, int32_t &dY) {
+        const int32_t ic = min(max(ii, 0), R - 1);
+        const int32_t jc = min(max(jj, 0), C - 1), jc1 = min(max(jj + 1, 0), C - 1);
+        if (STAGED) {
+            qb = sq[ic];
+            dX = sd[jc];
+            dY = sd[jc1];
+        } else {
+            qb = qp[ic];
+            dX = db_base(dbw, dbase + jc);
+            dY = db_base(dbw, dbase + jc1);
+        }
+    };
+    int32_t nqb, ndX, ndY;  // bases of the next pair, read one pair ahead
+    bases(i, j, nqb, ndX, ndY);
+    for (int32_t a = a0; a <= a1; a += 2, ++i, ++j, hereX += 128) {
+        const int32_t qb = nqb, dX = ndX, dY = ndY;
+        bases(i + 1, j + 1, nqb, ndX, ndY);
+        const bool rowok = (uint32_t)i < (uint32_t)R;
+        {  // X = (i, j)
+            int32_t hl = from_lower_lane(HY), el = from_lower_lane(EY);
+            const int32_t sl = from_lower_lane(SY), sel = from_lower_lane(SEY);
+            int32_t hu = HY, fu = FY;
+            if (j == 0) { hl = 0; el = kNegInf; }
+            else if (lane == 0) { hl = kNegInf; el = kNegInf; }
+            if (i == 0) { hu = 0; fu = kNegInf; }
+            else if (topX) { hu = kNegInf; fu = kNegInf; }
+            const int32_t hd = (i == 0 || j == 0) ? 0 : HX;
+            const CellOut c = sw_cell(hl, el, sl, sel, hu, fu, SY, SFY, hd, SX, qb == dX, hereX, match,
+                                      mismatch, o1, ext);
+            const bool v = laneX && rowok && (uint32_t)j < (uint32_t)C;
+            HX = v ? c.H : kNegInf;
+            EX = v ? c.E : kNegInf;
+            FX = v ? c.F : kNegInf;
+            SX = c.S; SEX = c.SE; SFX = c.SF;
+            if (v && c.H > best) {
+                best = c.H;
+                bcell = hereX;
+                bstart = c.S;
+            }
+        }
+        {  // Y = (i, j + 1)
+            const int32_t jy = j + 1;
+            int32_t hl = HX, el = EX;
+            int32_t hu = from_upper_lane(HX), fu = from_upper_lane(FX);
+            const int32_t su = from_upper_lane(SX), sfu = from_upper_lane(SFX);
+            if (jy == 0) { hl = 0; el = kNegInf; }
+            if (i == 0) { hu = 0; fu = kNegInf; }
+            const int32_t hd = (i == 0 || jy == 0) ? 0 : HY;
+            const CellOut c = sw_cell(hl, el, SX, SEX, hu, fu, su, sfu, hd, SY, qb == dY, hereX + 1,
+                                      match, mismatch, o1, ext);
+            const bool v = laneY && rowok && (uint32_t)jy < (uint32_t)C;
+            HY = v ? c.H : kNegInf;
+            EY = v ? c.E : kNegInf;
+            FY = v ? c.F : kNegInf;
+            SY = c.S; SEY = c.SE; SFY = c.SF;
+            if (v && c.H > best) {
+                best = c.H;
+                bcell = hereX + 1;
+                bstart = c.S;
+            }
+        }
+    }
+}
+
+// One wave (one block) per selected box; boxes whose bases fit kBswStage each
+// for query and data bank are first staged in LDS.
+__global__ __launch_bounds__(64) void k_bsw(
     const Box *__restrict__ sorted, const uint32_t *__restrict__ qstart,
     const uint32_t *__restrict__ sel_off, int32_t nq, uint32_t total,
     const uint8_t *__restrict__ qcode, const int64_t *__restrict__ qoff, int32_t qa,
@@ -810,9 +1193,11 @@ __global__ __launch_bounds__(kBlock) void k_bsw(
     int32_t mismatch, int32_t o1, int32_t ext, int32_t W, Align *__restrict__ out,
     unsigned long long *__restrict__ cells_q)
 {
-    const uint32_t b = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (b >= total) return;  // whole wave
-    const int32_t lane = threadIdx.x & 63;
+    __shared__ uint8_t s_q[kBswStage];
+    __shared__ uint8_t s_d[kBswStage];
+    const uint32_t b = blockIdx.x;
+    if (b >= total) return;
+    const int32_t lane = threadIdx.x;
     int32_t lo = 0, hi = nq - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
@@ -833,61 +1218,20 @@ __global__ __launch_bounds__(kBlock) void k_bsw(
         const int32_t a_lo = (clo <= 0 && chi >= 0) ? 0 : (clo > 0 ? clo : -chi);
         const int32_t cs = min(max(C - R, clo), chi);
         const int32_t a_hi = (cs <= C - R) ? 2 * (R - 1) + cs : 2 * (C - 1) - cs;
-        int32_t H1 = kNegInf, E1 = kNegInf, F1 = kNegInf, S1 = 0, SE1 = 0, SF1 = 0;
-        int32_t H2 = kNegInf, S2 = 0;
-        for (int32_t a = a_lo; a <= a_hi; ++a) {
-            const int32_t p = (a - c0 + W) & 1;
-            const int32_t t = p + 2 * lane;
-            const int32_t c = t - W + c0;
-            const int32_t i = (a - c) >> 1;
-            const int32_t j = a - i;
-            const bool valid = (t <= 2 * W) && i >= 0 && i < R && j >= 0 && j < C;
-            int32_t hl, el, sl, sel, hu, fu, su, sfu;
-            if (p == 0) {
-                hl = __shfl_up(H1, 1, 64);
-                el = __shfl_up(E1, 1, 64);
-                sl = __shfl_up(S1, 1, 64);
-                sel = __shfl_up(SE1, 1, 64);
-                hu = H1; fu = F1; su = S1; sfu = SF1;
-            } else {
-                hl = H1; el = E1; sl = S1; sel = SE1;
-                hu = __shfl_down(H1, 1, 64);
-                fu = __shfl_down(F1, 1, 64);
-                su = __shfl_down(S1, 1, 64);
-                sfu = __shfl_down(SF1, 1, 64);
-            }
-            int32_t H = kNegInf, E = kNegInf, F = kNegInf, S = 0, SE = 0, SF = 0;
-            if (valid) {
-                if (j == 0) { hl = 0; el = kNegInf; }
-                else if (t == 0) { hl = kNegInf; el = kNegInf; }
-                if (i == 0) { hu = 0; fu = kNegInf; }
-                else if (t == 2 * W) { hu = kNegInf; fu = kNegInf; }
-                const bool border = (i == 0 || j == 0);
-                const int32_t hd = border ? 0 : H2;
-                const int32_t sd = S2;
-                const int32_t eo = hl - o1, ee = el - ext;
-                if (eo >= ee) { E = eo; SE = sl; } else { E = ee; SE = sel; }
-                const int32_t fo = hu - o1, fe = fu - ext;
-                if (fo >= fe) { F = fo; SF = su; } else { F = fe; SF = sfu; }
-                const int32_t g = hd + (((int32_t)qp[i] == db_base(dbw, dbase + j)) ? match : -mismatch);
-                H = max(max(0, g), max(E, F));
-                const int32_t here = i * 128 + t;
-                if (H > 0) {
-                    if (g == H) S = (hd > 0) ? sd : here;
-                    else if (E == H) S = SE;
-                    else S = SF;
-                } else {
-                    S = here;
-                }
-                if (H > best) {
-                    best = H;
-                    bcell = here;
-                    bstart = S;
-                }
-                ++cells;
-            }
-            H2 = H1; S2 = S1;
-            H1 = H; E1 = E; F1 = F; S1 = S; SE1 = SE; SF1 = SF;
+        // pairs start on an even-parity and end on an odd-parity anti-diagonal; the
+        // extra anti-diagonals this may add hold no cell of the box
+        const int32_t a0 = a_lo - ((a_lo - c0 + W) & 1);
+        const int32_t a1 = a_hi + (((a_hi - c0 + W) & 1) ^ 1);
+        cells = band_cells(R, C, clo, chi, lane);
+        if (R <= kBswStage && C <= kBswStage) {
+            for (int32_t x = lane; x < R; x += 64) s_q[x] = qp[x];
+            for (int32_t x = lane; x < C; x += 64) s_d[x] = (uint8_t)db_base(dbw, dbase + x);
+            __syncthreads();
+            bsw_sweep<true>(s_q, s_d, qp, dbw, dbase, R, C, c0, W, a0, a1, match, mismatch, o1,
+                            ext, lane, best, bcell, bstart);
+        } else {
+            bsw_sweep<false>(s_q, s_d, qp, dbw, dbase, R, C, c0, W, a0, a1, match, mismatch, o1,
+                             ext, lane, best, bcell, bstart);
         }
     }
 #pragma unroll
@@ -895,7 +1239,6 @@ __global__ __launch_bounds__(kBlock) void k_bsw(
         const int32_t ob = __shfl_xor(best, off, 64);
         const int32_t oc = __shfl_xor(bcell, off, 64);
         const int32_t os = __shfl_xor(bstart, off, 64);
-        cells += __shfl_xor(cells, off, 64);
         if (ob > best || (ob == best && oc < bcell)) {
             best = ob;
             bcell = oc;
@@ -933,10 +1276,9 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 unsigned long long *cells_per_q, hipStream_t st)
 {
     if (nsel_total == 0) return;
-    const uint32_t per = kBlock / 64;
-    k_bsw<<<(nsel_total + per - 1) / per, kBlock, 0, st>>>(
-        sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw, seq_start, match, mismatch,
-        gap_open + gap_extend, gap_extend, band, out, cells_per_q);
+    k_bsw<<<nsel_total, 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
+                                      seq_start, match, mismatch, gap_open + gap_extend, gap_extend,
+                                      band, out, cells_per_q);
 }
 
 // ------------------------------------------------------------------ results to device memory

@@ -94,7 +94,7 @@ struct Workspace {
     hipStream_t st = nullptr;
     DevBuf ascii, qoff, qcode, kcode, cnt, qid, hoff, partials, qtot, err;
     DevBuf hrel, pbase, akey, keys, keys_alt, hist, rs_partials;
-    DevBuf cands, ccount, cand_q, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
+    DevBuf cands, ccount, cand_q, cand_off, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
@@ -112,7 +112,7 @@ struct Workspace {
         if (st) (void)hipSetDevice(device);
         DevBuf *all[] = {&ascii, &qoff, &qcode, &kcode, &cnt, &qid, &hoff, &partials, &qtot, &err,
                          &hrel, &pbase, &akey, &keys, &keys_alt, &hist, &rs_partials, &cands,
-                         &ccount, &cand_q, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
+                         &ccount, &cand_q, &cand_off, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
                          &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
                          &cells_q};
         for (DevBuf *b : all)
@@ -408,30 +408,51 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     }
     const uint64_t *sorted = kcur;
 
-    // ---- S5 chain + filter (runs past the buffer are counted, then the buffer grows)
-    uint32_t ccap = (uint32_t)std::min<uint64_t>(H, std::max<uint64_t>(1u << 20, H / 8));
-    TRY(ensure(ws->ccount, sizeof(uint32_t) * 4));
-    TRY(ensure(ws->cand_q, sizeof(uint32_t) * nqw));
+    // ---- S5 chain + filter: runs in hit-key order (grouped by query, then sequence)
+    const uint32_t ntile = chain_tiles(H);
+    TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
+    TRY(ensure(ws->cand_q, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->cand_off, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nqw) + 1)));
     void *pin;
-    TRY(pinned(ws, sizeof(uint32_t) * 4, &pin));
-    uint32_t nc = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        TRY(ensure(ws->cands, sizeof(Cand) * ccap));
-        HIPCHK(hipMemsetAsync(ws->ccount.p, 0, sizeof(uint32_t), st));
-        HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
-        prof.begin("chain");
-        launch_chain(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len, as<Cand>(ws->cands), ccap,
-                     as<uint32_t>(ws->ccount), as<uint32_t>(ws->cand_q), st);
-        prof.end(H);
-        HIPCHK(hipMemcpyAsync(pin, ws->ccount.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        nc = *reinterpret_cast<uint32_t *>(pin);
-        if (nc <= ccap) break;
-        ccap = nc;
+    const size_t n1 = (size_t)nqw + 1;
+    // pinned staging: run count | runs per query[nqw] | sel_off[nqw+1] | sel start[nqw] |
+    // sel end[nqw] | report start[nqw] | report end[nqw] | (8-aligned) cells per query[nqw]
+    const size_t u32s = 1 + (size_t)nqw + n1 + 4 * (size_t)nqw;
+    const size_t cells_at = ((u32s * 4 + 7) / 8) * 8;
+    TRY(pinned(ws, cells_at + 8 * (size_t)nqw + 64, &pin));
+    uint32_t *h_nc = reinterpret_cast<uint32_t *>(pin);
+    uint32_t *h_cq = h_nc + 1;
+    uint32_t *h_sel_off = h_cq + nqw;
+    uint32_t *h_ss = h_sel_off + n1, *h_se = h_ss + nqw, *h_rs = h_se + nqw, *h_re = h_rs + nqw;
+    unsigned long long *h_cells =
+        reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(pin) + cells_at);
+    HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
+    prof.begin("chain");
+    launch_chain_count(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len, as<uint32_t>(ws->ccount),
+                       st);
+    launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount), ntile,
+                    as<uint32_t>(ws->partials), st);
+    HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + ntile, sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint32_t nc = *h_nc;
+    if (nc > 0) {
+        TRY(ensure(ws->cands, sizeof(Cand) * nc));
+        launch_chain_write(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
+                           as<uint32_t>(ws->ccount), as<Cand>(ws->cands), as<uint32_t>(ws->cand_q),
+                           st);
+        launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nqw,
+                        as<uint32_t>(ws->partials), st);
     }
-    if (nc == 0) return GG_OK;
+    prof.end(H);
+    if (nc == 0) {
+        if (bo.stats) HIPCHK(hipStreamSynchronize(st));
+        return GG_OK;
+    }
+    HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
 
-    // ---- S6 extend
+    // ---- S6 extend (one wave per run)
     TRY(ensure(ws->boxes, sizeof(Box) * nc));
     TRY(ensure(ws->boxes2, sizeof(Box) * nc));
     TRY(ensure(ws->boxes3, sizeof(Box) * nc));
@@ -440,46 +461,57 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                   ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop, as<Box>(ws->boxes),
                   st);
     prof.end(nc);
+    HIPCHK(hipStreamSynchronize(st));  // h_cq ready
+    uint32_t max_seg = 0;
+    for (int32_t ql = 0; ql < nqw; ++ql) max_seg = std::max(max_seg, h_cq[ql]);
+    const bool seg_path = max_seg <= (uint32_t)kSegCap;
 
     const int bq = bits_for((uint64_t)nqw + 1);  // room for the "empty" query value nqw
     const int bs = lay.bs;
     const int bl = bits_for((uint64_t)maxL + 1);
     const int bsl = bits_for((uint64_t)ix->max_seq_len + 1);
-
-    // ---- S7 merge: sort by (q, s, qs, ds, qe, de), sweep each (q, s) group
-    prof.begin("merge");
     std::vector<KeyWord> words;
-    TRY(make_words({{F_Q, bq, 0}, {F_S, bs, 0}, {F_QS, bl, 0}, {F_DS, bsl, 0}, {F_QE, bl, 0},
-                    {F_DE, bsl, 0}},
-                   words));
     uint32_t *perm = nullptr;
+
+    // ---- S7 merge: order each query's boxes by (s, qs, ds, qe, de), sweep each (q, s)
+    prof.begin("merge");
     Box *boxes = as<Box>(ws->boxes);
-    TRY(sort_records(ws, nc, words,
-                     [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
-                         launch_box_keys(boxes, nc, w, nqw, out, pm, st);
-                     },
-                     &perm));
-    launch_gather_boxes(boxes, perm, nc, as<Box>(ws->boxes2), st);
+    if (seg_path) {
+        launch_seg_sort_box(0, boxes, as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nqw, st);
+    } else {
+        TRY(make_words({{F_Q, bq, 0}, {F_S, bs, 0}, {F_QS, bl, 0}, {F_DS, bsl, 0}, {F_QE, bl, 0},
+                        {F_DE, bsl, 0}},
+                       words));
+        TRY(sort_records(ws, nc, words,
+                         [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
+                             launch_box_keys(boxes, nc, w, nqw, out, pm, st);
+                         },
+                         &perm));
+        launch_gather_boxes(boxes, perm, nc, as<Box>(ws->boxes2), st);
+    }
     launch_merge_sweep(as<Box>(ws->boxes2), nc, as<Box>(ws->boxes3), st);
     prof.end(nc);
 
-    // ---- S8 select by length: sort by (q, len desc, s, qs, ds, qe, de), keep N per query
+    // ---- S8 select by length: (kept first, len desc, s, qs, ds, qe, de), first N per query
     prof.begin("select");
-    TRY(make_words({{F_Q, bq, 0}, {F_LEN_DESC, bl, (int32_t)maxL}, {F_S, bs, 0}, {F_QS, bl, 0},
-                    {F_DS, bsl, 0}, {F_QE, bl, 0}, {F_DE, bsl, 0}},
-                   words));
     Box *merged = as<Box>(ws->boxes3);
-    TRY(sort_records(ws, nc, words,
-                     [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
-                         launch_box_keys(merged, nc, w, nqw, out, pm, st);
-                     },
-                     &perm));
-    launch_gather_boxes(merged, perm, nc, as<Box>(ws->boxes2), st);
+    if (seg_path) {
+        launch_seg_sort_box(1, merged, as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nqw, st);
+    } else {
+        TRY(make_words({{F_Q, bq, 0}, {F_LEN_DESC, bl, (int32_t)maxL}, {F_S, bs, 0},
+                        {F_QS, bl, 0}, {F_DS, bsl, 0}, {F_QE, bl, 0}, {F_DE, bsl, 0}},
+                       words));
+        TRY(sort_records(ws, nc, words,
+                         [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
+                             launch_box_keys(merged, nc, w, nqw, out, pm, st);
+                         },
+                         &perm));
+        launch_gather_boxes(merged, perm, nc, as<Box>(ws->boxes2), st);
+    }
     TRY(ensure(ws->qstart, sizeof(uint32_t) * (nqw + 1)));
     TRY(ensure(ws->qend, sizeof(uint32_t) * (nqw + 1)));
     TRY(ensure(ws->nsel, sizeof(uint32_t) * (nqw + 1)));
     TRY(ensure(ws->sel_off, sizeof(uint32_t) * (nqw + 1)));
-    TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(nqw + 1)));
     HIPCHK(hipMemsetAsync(ws->qstart.p, 0, sizeof(uint32_t) * nqw, st));
     HIPCHK(hipMemsetAsync(ws->qend.p, 0, sizeof(uint32_t) * nqw, st));
     launch_segments_box(as<Box>(ws->boxes2), nc, nqw, as<uint32_t>(ws->qstart),
@@ -489,31 +521,19 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     launch_scan_u32(as<uint32_t>(ws->nsel), as<uint32_t>(ws->sel_off), nqw,
                     as<uint32_t>(ws->partials), st);
     prof.end(nc);
-    // pinned staging: sel_off[nqw+1] | sel start[nqw] | sel end[nqw] | report start[nqw] |
-    // report end[nqw] | runs per query[nqw] | (8-aligned) cells per query[nqw]
-    const size_t n1 = (size_t)nqw + 1;
-    const size_t u32s = n1 + 5 * (size_t)nqw;
-    TRY(pinned(ws, ((u32s * 4 + 7) / 8) * 8 + 8 * (size_t)nqw + 64, &pin));
-    uint32_t *h_sel_off = reinterpret_cast<uint32_t *>(pin);
-    uint32_t *h_ss = h_sel_off + n1, *h_se = h_ss + nqw, *h_rs = h_se + nqw, *h_re = h_rs + nqw;
-    uint32_t *h_cq = h_re + nqw;
-    unsigned long long *h_cells = reinterpret_cast<unsigned long long *>(
-        reinterpret_cast<char *>(pin) + ((u32s * 4 + 7) / 8) * 8);
     HIPCHK(hipMemcpyAsync(h_sel_off, ws->sel_off.p, sizeof(uint32_t) * n1, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_ss, ws->qstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_se, ws->qend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+    if (bo.stats) {
+        HIPCHK(hipMemcpyAsync(h_ss, ws->qstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_se, ws->qend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipStreamSynchronize(st));
     const uint32_t nsel = h_sel_off[nqw];
     if (bo.stats)
-        for (int32_t ql = 0; ql < nqw; ++ql) bo.stats[qa + ql].n_merged = h_se[ql] - h_ss[ql];
-    if (nsel == 0) {
-        if (bo.stats) {
-            HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            for (int32_t ql = 0; ql < nqw; ++ql) bo.stats[qa + ql].n_cands = h_cq[ql];
+        for (int32_t ql = 0; ql < nqw; ++ql) {
+            bo.stats[qa + ql].n_cands = h_cq[ql];
+            bo.stats[qa + ql].n_merged = h_se[ql] - h_ss[ql];
         }
-        return GG_OK;
-    }
+    if (nsel == 0) return GG_OK;
 
     // ---- S9 banded Smith-Waterman
     TRY(ensure(ws->aligns, sizeof(Align) * nsel));
@@ -527,33 +547,47 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                as<unsigned long long>(ws->cells_q), st);
     prof.end(nsel);
 
-    // ---- S10 report: drop score <= 0, order by score desc and coordinates
-    prof.begin("report");
-    const int bsc = bits_for((uint64_t)maxL * (uint64_t)p->match + 1);
-    TRY(make_words({{A_Q, bq, 0}, {A_SCORE_DESC, bsc, (int32_t)(maxL * p->match)}, {A_SEQ, bs, 0},
-                    {A_QS, bl, 0}, {A_DS, bsl, 0}, {A_QE, bl, 0}, {A_DE, bsl, 0}, {A_BQS, bl, 0},
-                    {A_BDS, bsl, 0}, {A_BQE, bl, 0}, {A_BDE, bsl, 0}},
-                   words));
-    Align *al = as<Align>(ws->aligns);
-    TRY(sort_records(ws, nsel, words,
-                     [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
-                         launch_align_keys(al, nsel, w, nqw, out, pm, st);
-                     },
-                     &perm));
-    launch_gather_aligns(al, perm, nsel, as<Align>(ws->aligns2), st);
+    // ---- S10 report: score > 0 first, score desc, coordinates; per-query ranges
+    uint32_t max_sel = 0;
+    for (int32_t ql = 0; ql < nqw; ++ql) max_sel = std::max(max_sel, h_sel_off[ql + 1] - h_sel_off[ql]);
     TRY(ensure(ws->rstart, sizeof(uint32_t) * (nqw + 1)));
     TRY(ensure(ws->rend, sizeof(uint32_t) * (nqw + 1)));
-    HIPCHK(hipMemsetAsync(ws->rstart.p, 0, sizeof(uint32_t) * nqw, st));
-    HIPCHK(hipMemsetAsync(ws->rend.p, 0, sizeof(uint32_t) * nqw, st));
-    launch_segments_align(as<Align>(ws->aligns2), nsel, nqw, as<uint32_t>(ws->rstart),
-                          as<uint32_t>(ws->rend), st);
+    prof.begin("report");
+    Align *al = as<Align>(ws->aligns);
+    bool written = false;
+    if (max_sel <= (uint32_t)kSegCap) {
+        launch_report_seg(al, as<Align>(ws->aligns2), as<uint32_t>(ws->sel_off), nqw,
+                          as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend), qa, bo.cap,
+                          bo.device ? reinterpret_cast<int32_t *>(bo.out) : nullptr,
+                          bo.device ? bo.n_out : nullptr, st);
+        written = bo.device;
+    } else {
+        const int bsc = bits_for((uint64_t)maxL * (uint64_t)p->match + 1);
+        TRY(make_words({{A_Q, bq, 0}, {A_SCORE_DESC, bsc, (int32_t)(maxL * p->match)},
+                        {A_SEQ, bs, 0}, {A_QS, bl, 0}, {A_DS, bsl, 0}, {A_QE, bl, 0},
+                        {A_DE, bsl, 0}, {A_BQS, bl, 0}, {A_BDS, bsl, 0}, {A_BQE, bl, 0},
+                        {A_BDE, bsl, 0}},
+                       words));
+        TRY(sort_records(ws, nsel, words,
+                         [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
+                             launch_align_keys(al, nsel, w, nqw, out, pm, st);
+                         },
+                         &perm));
+        launch_gather_aligns(al, perm, nsel, as<Align>(ws->aligns2), st);
+        HIPCHK(hipMemsetAsync(ws->rstart.p, 0, sizeof(uint32_t) * nqw, st));
+        HIPCHK(hipMemsetAsync(ws->rend.p, 0, sizeof(uint32_t) * nqw, st));
+        launch_segments_align(as<Align>(ws->aligns2), nsel, nqw, as<uint32_t>(ws->rstart),
+                              as<uint32_t>(ws->rend), st);
+    }
     prof.end(nsel);
 
     // ---- results: ordered alignments and per-query ranges
     std::vector<Align> res;
     if (bo.device) {
-        launch_write_out(as<Align>(ws->aligns2), as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend),
-                         nqw, qa, bo.cap, reinterpret_cast<int32_t *>(bo.out), bo.n_out, st);
+        if (!written)
+            launch_write_out(as<Align>(ws->aligns2), as<uint32_t>(ws->rstart),
+                             as<uint32_t>(ws->rend), nqw, qa, bo.cap,
+                             reinterpret_cast<int32_t *>(bo.out), bo.n_out, st);
     } else {
         res.resize(nsel);
         HIPCHK(hipMemcpyAsync(res.data(), ws->aligns2.p, sizeof(Align) * nsel,
@@ -561,11 +595,9 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     }
     HIPCHK(hipMemcpyAsync(h_rs, ws->rstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_re, ws->rend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
-    if (bo.stats) {
-        HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
+    if (bo.stats)
         HIPCHK(hipMemcpyAsync(h_cells, ws->cells_q.p, sizeof(unsigned long long) * nqw,
                               hipMemcpyDeviceToHost, st));
-    }
     HIPCHK(hipStreamSynchronize(st));
     for (int32_t ql = 0; ql < nqw; ++ql) {
         const int32_t q = qa + ql;
@@ -584,7 +616,6 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         }
         if (bo.stats) {
             gg_stats &s = bo.stats[q];
-            s.n_cands = h_cq[ql];
             s.n_selected = h_sel_off[ql + 1] - h_sel_off[ql];
             s.n_cells = (int64_t)h_cells[ql];
             s.n_out = n;

@@ -62,7 +62,8 @@ def test_config0_batch_and_single(ggo, c0):
 
 
 @pytest.mark.parametrize("k,band,max_hits,seed", [
-    (4, 32, 20, 1), (6, 5, 0, 2), (8, 0, 3, 3), (11, 63, 50, 4), (12, 32, 1, 5), (7, 17, -1, 6)])
+    (4, 32, 20, 1), (6, 5, 0, 2), (8, 0, 3, 3), (11, 63, 50, 4), (12, 32, 1, 5), (7, 17, -1, 6),
+    (4, 10, 0, 7)])
 def test_random_banks(ggo, k, band, max_hits, seed):
     G = gpu()
     db = synth.random_db(seed, n_seqs=300, lmin=0, lmax=3000)
@@ -72,6 +73,10 @@ def test_random_banks(ggo, k, band, max_hits, seed):
     kw = dict(band=band, max_gap=3 * k - 2 * (seed % 2), min_hsp_len=2 * k)
     want, wst = oracle_all(ggo, oix, qs, ggo.params(max_hits, **kw))
     check_batch(G, gix, qs, G.params(max_hits, **kw), want, wst)
+    if k == 4:  # more than one LDS segment of runs per query: the global-sort paths ran
+        assert max(s["n_cands"] for s in wst) > 1024
+        if max_hits <= 0:
+            assert max(s["n_selected"] for s in wst) > 1024
 
 
 def test_scoring_variants(ggo, c0):
