@@ -31,6 +31,10 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: int32 vector lane-operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 CAP = 64
+# int32 operations one banded Smith-Waterman cell needs: E and F (2 subtractions,
+# 1 max and 1 start select each), G (compare, select, add), H (3 max), the start
+# of H (2 compares, 2 selects) and the best-cell update (compare, 3 selects)
+ALIGN_OPS_PER_CELL = 22
 
 
 def log(msg: str) -> None:
@@ -155,30 +159,46 @@ def main() -> int:
     for _ in range(3):
         step()
     stages = {s: gix.profile_read(s) for s in (
-        "encode", "scan", "gather_prep", "gather", "sort_hist", "sort_scan", "sort_scatter",
-        "chain", "extend", "merge", "select", "align", "report")}
+        "encode", "scan", "gather_prep", "probe", "gather_count", "gather", "group", "sort_hist",
+        "sort_scan", "sort_scatter", "chain", "extend", "merge", "select", "align", "report")}
     gix.profile(False)
     step_ms = {s: v["ms"] / 3 for s, v in stages.items()}
-    # algorithmic bytes per unit: gather reads an 8 B posting and writes an 8 B key per
-    # hit; a radix scatter reads and writes an 8 B key; a histogram pass reads one
-    bytes_per_unit = {"gather": 16, "sort_scatter": 16, "sort_hist": 8}
-    cand = {s: stages[s] for s in bytes_per_unit if stages[s]["launches"]}
+    cells = int(stats["n_cells"].sum())
+    hits = int(stats["n_hits"].sum())
+    # Algorithmic work per launch of each modelled kernel:
+    #  probe   - HBM: the 8 B posting of every hit plus 16 B per query position
+    #            (hit offset, list head, query id, window code); neighbour-window
+    #            probes are cache traffic and not counted
+    #  gather  - HBM: 8 B posting read + 8 B key write per hit
+    #  sort_*  - HBM: 16 B per key per scatter pass, 8 B per histogram pass
+    #  align   - integer ALU: ALIGN_OPS_PER_CELL int32 operations per in-band cell
+    positions = int(qs.lengths().sum())
+    model = {
+        "probe": ("hbm", lambda st: 8 * st["units"] + 16 * positions * st["launches"]),
+        "gather": ("hbm", lambda st: 16 * st["units"]),
+        "sort_scatter": ("hbm", lambda st: 16 * st["units"]),
+        "sort_hist": ("hbm", lambda st: 8 * st["units"]),
+        "align": ("alu", lambda st: ALIGN_OPS_PER_CELL * cells / 3 * st["launches"]),
+    }
+    kernel_name = {"probe": "k_probe_chain", "gather": "k_gather", "sort_scatter": "k_rs_scatter",
+                   "sort_hist": "k_rs_hist", "align": "k_bsw"}
+    cand = {s: stages[s] for s in model if stages[s]["launches"]}
     dom = max(cand, key=lambda s: cand[s]["ms"])
     st = cand[dom]
-    per_launch_bytes = bytes_per_unit[dom] * st["units"] / st["launches"]
+    bound, work_fn = model[dom]
+    per_launch = work_fn(st) / st["launches"]
     avg_s = st["ms"] / 1e3 / st["launches"]
-    achieved = per_launch_bytes / avg_s / 1e9
     workload = "config1"
-    roofline = {"bound": "hbm", "kernel": {"gather": "k_gather", "sort_scatter": "k_rs_scatter",
-                                          "sort_hist": "k_rs_hist"}[dom],
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(dom, workload),
+    if bound == "hbm":
+        achieved, peak, unit = per_launch / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = per_launch / avg_s / 1e12, VALU_PEAK_TOPS, "TOP/s"
+    roofline = {"bound": bound, "kernel": kernel_name[dom], "achieved": round(achieved, 2),
+                "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
+                "traffic": traffic_for(dom, workload) if bound == "hbm" else None,
                 "avg_launch_us": round(avg_s * 1e6, 2),
-                "algorithmic_bytes_per_launch": int(per_launch_bytes)}
-    # the banded Smith-Waterman against the integer vector ALUs
+                "algorithmic_work_per_launch": int(per_launch)}
     al = stages["align"]
-    cells = int(stats["n_cells"].sum())
     align_gcups = cells / (al["ms"] / 3 / 1e3) / 1e9 if al["ms"] > 0 else None
 
     # the plain one-query-at-a-time loop on the same GPU, for comparison
@@ -215,7 +235,7 @@ def main() -> int:
             "pcie_inclusive_batch_qps": round(pcie_qps, 1),
             "index_build_s": round(build_s, 2),
             "stage_ms_per_step": {s: round(v, 4) for s, v in step_ms.items()},
-            "hits_per_step": int(stats["n_hits"].sum()),
+            "hits_per_step": hits,
             "align_cells_per_step": cells,
             "align_gcups": round(align_gcups, 2) if align_gcups else None,
             "valu_peak_tops": round(VALU_PEAK_TOPS, 1),

@@ -17,6 +17,16 @@ constexpr int kGatherCap = 4096;         // positions of one gather tile kept in
 constexpr int kMaxBand = 63;             // band half-width supported by one wave
 constexpr int kSegCap = 1024;            // records of one query sorted in LDS
 constexpr int kBswStage = 4096;          // box bases staged in LDS by the aligner
+constexpr int kBinCap = 1024;            // buckets one gather tile counts in LDS
+constexpr uint32_t kBucketCapMax = 512;  // most keys of one bucket (one wave sorts it in LDS)
+constexpr uint32_t kBucketBig = 16384;   // most keys of one bucket sorted by a block (128 KiB)
+constexpr int kMaxProbe = 4;             // neighbour windows probed per side (G / k + 1)
+constexpr int kBoundCap = 2048;          // run bounds of one query paired in LDS
+
+// First or last hit of a run of several hits: query (local), sequence, diagonal, qpos.
+struct Bound {
+    int32_t q, s, d, qpos;
+};
 
 // A chained run of hits: query (local to the wave), sequence, diagonal, [qs, qe).
 struct Cand {
@@ -82,6 +92,42 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
 void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                    int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
                    uint64_t *keys, hipStream_t st);
+// Runs found by probing the windows next to every hit (no stored hit): single-hit
+// runs and the bounds of longer runs; bounds are grouped by query, then sorted
+// and paired per query.  Runs in any order are finally grouped by query.
+void launch_probe(const uint32_t *hrel, const uint32_t *pbase, int64_t np, const int2 *post,
+                  uint32_t nhits, int64_t g0, const int32_t *qid, const int64_t *qoff, int32_t qa,
+                  const uint32_t *kcode, const uint32_t *dbw, const int64_t *seq_start, int32_t k,
+                  int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap, uint32_t *ccount,
+                  uint32_t *cand_per_q, Bound *bounds, uint32_t bcap, uint32_t *bcount,
+                  uint32_t *bound_per_q, hipStream_t st);
+void launch_bounds_by_query(const Bound *in, uint32_t n, const uint32_t *qoff_b, uint32_t *cur,
+                            Bound *out, hipStream_t st);
+void launch_pair_bounds(const Bound *b, const uint32_t *qoff_b, int32_t nq, int32_t k,
+                        int32_t min_len, Cand *cands, uint32_t ccap, uint32_t *ccount,
+                        uint32_t *cand_per_q, hipStream_t st);
+void launch_group_by_query(const Cand *in, uint32_t n, const uint32_t *qoff_c, uint32_t *cur,
+                           Cand *out, hipStream_t st);
+// Bucketed grouping (mode 1: count hits per bucket, mode 2: write keys into
+// buckets), then one block per bucket sorts and chains it in LDS.
+void launch_gather_bucket(int mode, const uint32_t *hrel, const uint32_t *pbase,
+                          const uint64_t *akey, int64_t npos, const int2 *post, uint32_t nhits,
+                          HitKeyLayout lay, const uint32_t *bb, const uint32_t *nbq,
+                          uint32_t *bcount, const uint32_t *boff, uint64_t *keys, hipStream_t st);
+void launch_bucket_sort_chain(const uint64_t *keys, const uint32_t *boff, uint32_t nbk,
+                              uint32_t max_bucket, HitKeyLayout lay, int32_t k, int32_t max_gap,
+                              int32_t min_len, Cand *tmp, uint32_t cap, uint32_t *cursor,
+                              uint32_t *btmp, uint32_t *bcands, uint32_t *cand_per_q,
+                              hipStream_t st);
+void launch_bucket_sort_chain_big(const uint64_t *keys, const uint32_t *boff,
+                                  const uint32_t *list, uint32_t nlist, uint32_t max_bucket,
+                                  HitKeyLayout lay, int32_t k, int32_t max_gap, int32_t min_len,
+                                  Cand *tmp, uint32_t cap, uint32_t *cursor, uint32_t *btmp,
+                                  uint32_t *bcands, uint32_t *cand_per_q, hipStream_t st);
+// One-time per-process kernel attributes (dynamic LDS above 64 KiB).
+hipError_t setup_kernels();
+void launch_compact_cands(const Cand *tmp, const uint32_t *btmp, const uint32_t *bcands,
+                          const uint32_t *coff, uint32_t nbk, Cand *out, hipStream_t st);
 // Stable LSD radix sort of n keys (and optional u32 values) on bits [lo, hi).
 // Returns which buffer holds the result: 0 = keys/vals, 1 = keys_alt/vals_alt.
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,

@@ -28,10 +28,21 @@ __device__ __forceinline__ uint64_t low_mask(int n) { return n >= 64 ? ~0ull : (
 
 __device__ __forceinline__ int32_t floor_half(int32_t x) { return x >> 1; }  // arithmetic shift
 
-// 2-bit packed data bank: base of global index g sits in word g / 16 at bit 2 (g % 16)
+// 2-bit packed data bank, first base most significant: base of global index g
+// sits in word g / 16 at bits 30 - 2 (g % 16); the array has one spare word.
 __device__ __forceinline__ int32_t db_base(const uint32_t *__restrict__ dbw, int64_t g)
 {
-    return (int32_t)((dbw[g >> 4] >> ((uint32_t)(g & 15) << 1)) & 3u);
+    return (int32_t)((dbw[g >> 4] >> (30u - ((uint32_t)(g & 15) << 1))) & 3u);
+}
+
+// Code of the k bases starting at global index g (first base most significant),
+// the same integer the query's window of those bases has.
+__device__ __forceinline__ uint32_t db_window(const uint32_t *__restrict__ dbw, int64_t g,
+                                              int32_t k)
+{
+    const int64_t w = g >> 4;
+    const uint64_t x = ((uint64_t)dbw[w] << 32) | (uint64_t)dbw[w + 1];
+    return (uint32_t)((x << ((uint32_t)(g & 15) << 1)) >> (64 - 2 * k));
 }
 
 // Exclusive scan over the 256 threads of a block; *total receives the block sum.
@@ -58,6 +69,40 @@ __device__ __forceinline__ T block_excl_scan(T v, T *total)
     __syncthreads();
     *total = tot;
     return before + x - v;
+}
+
+// Bitonic sort of n <= 65536 records in LDS, through an index array.
+template <typename Rec, typename Less>
+__device__ void lds_bitonic(const Rec *__restrict__ s_r, uint16_t *__restrict__ s_ix, uint32_t n,
+                            Less less)
+{
+    uint32_t n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) s_ix[i] = (uint16_t)i;
+    __syncthreads();
+    auto before = [&](uint32_t a, uint32_t b) -> bool {  // a strictly before b
+        if (a >= n) return false;
+        if (b >= n) return true;
+        if (less(s_r[a], s_r[b])) return true;
+        if (less(s_r[b], s_r[a])) return false;
+        return a < b;
+    };
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = s_ix[i], b = s_ix[l];
+                    const bool up = (i & k) == 0;
+                    if (up ? before(b, a) : before(a, b)) {
+                        s_ix[i] = (uint16_t)b;
+                        s_ix[l] = (uint16_t)a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // ------------------------------------------------------------------ S1/S2: encode + count
@@ -256,11 +301,402 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
 // Consecutive threads take consecutive hits, so reads of one posting run and the
 // key writes are coalesced.  The owning position of hit j is the last p with
 // hrel[p] <= j, searched in LDS when the tile spans few positions.
-__global__ __launch_bounds__(kBlock) void k_gather(const uint32_t *__restrict__ hrel,
-                                                   const uint32_t *__restrict__ pbase,
-                                                   const uint64_t *__restrict__ akey, int64_t np,
-                                                   const int2 *__restrict__ post, uint32_t nhits,
-                                                   int sh_s, int sh_d, uint64_t *__restrict__ keys)
+//
+// MODE 0 writes key j to keys[j].  MODE 1 and 2 serve the bucketed grouping: a
+// hit of query q on sequence s falls in bucket bb[q] + (s * nb[q]) >> bs, one of
+// nb[q] equal slices of the sequence-id range, so buckets in index order are in
+// (q, s) order.  MODE 1 counts hits per bucket; MODE 2 writes each key into its
+// bucket (in no particular order inside it), reserving space per tile and bucket.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather(
+    const uint32_t *__restrict__ hrel, const uint32_t *__restrict__ pbase,
+    const uint64_t *__restrict__ akey, int64_t np, const int2 *__restrict__ post, uint32_t nhits,
+    int sh_s, int sh_d, int sh_q, int bs, uint64_t *__restrict__ keys,
+    const uint32_t *__restrict__ bb, const uint32_t *__restrict__ nbq,
+    uint32_t *__restrict__ bcount, const uint32_t *__restrict__ boff)
+{
+    __shared__ uint32_t s_h[kGatherCap + 1];
+    __shared__ uint32_t s_bin[kBinCap];
+    __shared__ int64_t s_lo, s_hi;
+    __shared__ uint32_t s_b0, s_nbin;
+    const uint32_t t0 = blockIdx.x * (uint32_t)kTile;
+    const uint32_t t1 = min(t0 + (uint32_t)kTile, nhits);
+    if (threadIdx.x == 0) {
+        int64_t a = 0, b = np - 1;
+        while (a < b) {
+            const int64_t m = (a + b + 1) >> 1;
+            if (hrel[m] <= t0) a = m;
+            else b = m - 1;
+        }
+        s_lo = a;
+        b = np - 1;
+        while (a < b) {
+            const int64_t m = (a + b + 1) >> 1;
+            if (hrel[m] <= t1 - 1) a = m;
+            else b = m - 1;
+        }
+        s_hi = a;
+        if (MODE != 0) {
+            const uint32_t qf = (uint32_t)shr64(akey[s_lo], sh_q), ql = (uint32_t)shr64(akey[a], sh_q);
+            s_b0 = bb[qf];
+            s_nbin = bb[ql] + nbq[ql] - bb[qf];
+        }
+    }
+    __syncthreads();
+    const int64_t lo = s_lo, hi = s_hi;
+    const bool in_lds = (hi - lo + 2) <= (int64_t)(kGatherCap + 1);
+    if (in_lds)
+        for (int64_t p = lo + threadIdx.x; p <= hi + 1; p += blockDim.x) s_h[p - lo] = hrel[p];
+    const uint32_t b0 = MODE != 0 ? s_b0 : 0;
+    const bool bins = MODE != 0 && s_nbin <= (uint32_t)kBinCap;
+    if (bins)
+        for (uint32_t i = threadIdx.x; i < s_nbin; i += blockDim.x) s_bin[i] = 0;
+    __syncthreads();
+    uint64_t kk[kItems];
+    uint32_t bk[kItems], rk[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t j = t0 + r * kBlock + threadIdx.x;
+        bk[r] = 0xffffffffu;
+        if (j >= t1) continue;
+        int64_t p;
+        uint32_t first;
+        if (in_lds) {
+            int32_t a = 0, b = (int32_t)(hi - lo);
+            while (a < b) {
+                const int32_t m = (a + b + 1) >> 1;
+                if (s_h[m] <= j) a = m;
+                else b = m - 1;
+            }
+            p = lo + a;
+            first = s_h[a];
+        } else {
+            int64_t a = lo, b = hi;
+            while (a < b) {
+                const int64_t m = (a + b + 1) >> 1;
+                if (hrel[m] <= j) a = m;
+                else b = m - 1;
+            }
+            p = a;
+            first = hrel[a];
+        }
+        const int2 e = post[pbase[p] + (j - first)];
+        const uint64_t ak = akey[p];
+        const uint64_t key = ak + ((uint64_t)(uint32_t)e.x << sh_s) + ((uint64_t)(uint32_t)e.y << sh_d);
+        if (MODE == 0) {
+            keys[j] = key;
+            continue;
+        }
+        const uint32_t q = (uint32_t)shr64(ak, sh_q);
+        const uint32_t bkt = bb[q] + (uint32_t)(((uint64_t)(uint32_t)e.x * nbq[q]) >> bs);
+        bk[r] = bkt;
+        kk[r] = key;
+        if (bins) {
+            rk[r] = atomicAdd(&s_bin[bkt - b0], 1u);
+        } else if (MODE == 1) {
+            atomicAdd(&bcount[bkt], 1u);
+        } else {
+            keys[boff[bkt] + atomicAdd(&bcount[bkt], 1u)] = key;
+        }
+    }
+    if (MODE == 0 || !bins) return;  // uniform
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < s_nbin; i += blockDim.x) {
+        const uint32_t c = s_bin[i];
+        if (MODE == 1) {
+            if (c) atomicAdd(&bcount[b0 + i], c);
+        } else {
+            s_bin[i] = c ? atomicAdd(&bcount[b0 + i], c) : 0u;  // count -> reserved start
+        }
+    }
+    if (MODE == 1) return;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+        if (bk[r] != 0xffffffffu) keys[boff[bk[r]] + s_bin[bk[r] - b0] + rk[r]] = kk[r];
+}
+
+void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
+                   int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
+                   uint64_t *keys, hipStream_t st)
+{
+    if (nhits == 0) return;
+    const uint32_t nb = (nhits + kTile - 1) / kTile;
+    k_gather<0><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
+                                       lay.bp, 64, 0, keys, nullptr, nullptr, nullptr, nullptr);
+}
+
+void launch_gather_bucket(int mode, const uint32_t *hrel, const uint32_t *pbase,
+                          const uint64_t *akey, int64_t npos, const int2 *post, uint32_t nhits,
+                          HitKeyLayout lay, const uint32_t *bb, const uint32_t *nbq,
+                          uint32_t *bcount, const uint32_t *boff, uint64_t *keys, hipStream_t st)
+{
+    if (nhits == 0) return;
+    const uint32_t nb = (nhits + kTile - 1) / kTile;
+    const int sh_q = lay.bp + lay.bd + lay.bs;
+    if (mode == 1)
+        k_gather<1><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
+                                           lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff);
+    else
+        k_gather<2><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
+                                           lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff);
+}
+
+// ------------------------------------------------------------------ S4+S5 per bucket
+// One block per bucket: sort its keys in LDS (bitonic; keys are unique), then
+// chain them as k_chain_* does.  Each thread takes a contiguous slice of the
+// sorted bucket, so a scan of the per-thread run counts gives every run its rank
+// in key order; the bucket's runs go to a range reserved with one atomic.
+__device__ __forceinline__ bool chain_end_lds(const uint64_t *__restrict__ s_k, uint32_t n,
+                                              uint32_t i, int bp, int32_t k, int32_t G,
+                                              int32_t M, int32_t *qs_out)
+{
+    const uint64_t pmask = low_mask(bp);
+    const uint64_t key = s_k[i];
+    const uint64_t grp = key >> bp;
+    const int32_t qp = (int32_t)(key & pmask);
+    if (i + 1 < n) {
+        const uint64_t nx = s_k[i + 1];
+        if ((nx >> bp) == grp && (int32_t)(nx & pmask) - (qp + k) <= G) return false;
+    }
+    uint32_t j = i;
+    int32_t qj = qp;
+    while (j > 0) {
+        const uint64_t pv = s_k[j - 1];
+        if ((pv >> bp) != grp) break;
+        const int32_t qv = (int32_t)(pv & pmask);
+        if (qj - (qv + k) > G) break;
+        --j;
+        qj = qv;
+    }
+    *qs_out = qj;
+    return qp + k - qj >= M;
+}
+
+// One wave per bucket: the wave sorts the bucket's unique keys in its own LDS
+// slice (bitonic network, wave-scope ordering only, no block barrier), then
+// chains them; a ballot prefix gives every kept run its rank in key order, and
+// the bucket's runs go to a range reserved with one atomic.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(kBlock) void k_bucket_sort_chain(
+    const uint64_t *__restrict__ keys, const uint32_t *__restrict__ boff, uint32_t nbk,
+    HitKeyLayout lay, int32_t k, int32_t G, int32_t M, Cand *__restrict__ tmp, uint32_t cap,
+    uint32_t *__restrict__ cursor, uint32_t *__restrict__ btmp, uint32_t *__restrict__ bcands,
+    uint32_t *__restrict__ cand_per_q)
+{
+    __shared__ uint64_t s_all[kBlock / 64][kBucketCapMax];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t bkt = blockIdx.x * (kBlock / 64) + w;
+    if (bkt >= nbk) return;  // whole wave
+    uint64_t *__restrict__ s_k = s_all[w];
+    const uint32_t a0 = boff[bkt], n = boff[bkt + 1] - a0;
+    if (n == 0 || n > kBucketCapMax) {  // larger buckets never reach this kernel
+        if (lane == 0) bcands[bkt] = 0;
+        return;
+    }
+    uint32_t n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    for (uint32_t i = lane; i < n2; i += 64) s_k[i] = i < n ? keys[a0 + i] : ~0ull;
+    wave_lds_sync();
+    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = lane; i < n2; i += 64) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = s_k[i], y = s_k[l];
+                    if ((x > y) == ((i & kk) == 0)) {
+                        s_k[i] = y;
+                        s_k[l] = x;
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t tot = 0;
+    for (uint32_t base = 0; base < n; base += 64) {
+        int32_t qs;
+        const uint32_t i = base + lane;
+        const bool e = i < n && chain_end_lds(s_k, n, i, lay.bp, k, G, M, &qs);
+        tot += (uint32_t)__popcll(__ballot(e));
+    }
+    if (tot == 0) {
+        if (lane == 0) bcands[bkt] = 0;
+        return;
+    }
+    uint32_t at = 0;
+    if (lane == 0) {
+        at = atomicAdd(cursor, tot);
+        btmp[bkt] = at;
+        bcands[bkt] = tot;
+        const uint32_t q = (uint32_t)shr64(s_k[0] >> lay.bp, lay.bd + lay.bs);
+        atomicAdd(&cand_per_q[q], tot);
+    }
+    at = __shfl(at, 0, 64);
+    if (at + tot > cap) return;  // past cap: the caller grows the buffer and reruns
+    for (uint32_t base = 0; base < n; base += 64) {
+        int32_t qs = 0;
+        const uint32_t i = base + lane;
+        const bool e = i < n && chain_end_lds(s_k, n, i, lay.bp, k, G, M, &qs);
+        const uint64_t m = __ballot(e);
+        if (e) {
+            const uint64_t key = s_k[i];
+            const uint64_t grp = key >> lay.bp;
+            Cand cd;
+            cd.d = (int32_t)(grp & low_mask(lay.bd)) - lay.bias;
+            cd.s = (int32_t)(shr64(grp, lay.bd) & low_mask(lay.bs));
+            cd.q = (int32_t)shr64(grp, lay.bd + lay.bs);
+            cd.qs = qs;
+            cd.qe = (int32_t)(key & low_mask(lay.bp)) + k;
+            tmp[at + (uint32_t)__popcll(m & below)] = cd;
+        }
+        at += (uint32_t)__popcll(m);
+    }
+}
+
+// Buckets over kBucketCapMax keys (a long run puts all its hits on one diagonal):
+// one block per listed bucket, bitonic over the whole block in dynamic LDS, then
+// each thread chains a contiguous slice and a block scan orders the runs.
+__global__ __launch_bounds__(kBlock) void k_bucket_sort_chain_big(
+    const uint64_t *__restrict__ keys, const uint32_t *__restrict__ boff,
+    const uint32_t *__restrict__ list, HitKeyLayout lay, int32_t k, int32_t G, int32_t M,
+    Cand *__restrict__ tmp, uint32_t cap, uint32_t *__restrict__ cursor,
+    uint32_t *__restrict__ btmp, uint32_t *__restrict__ bcands, uint32_t *__restrict__ cand_per_q)
+{
+    extern __shared__ uint64_t s_k[];
+    __shared__ uint32_t s_at;
+    const uint32_t bkt = list[blockIdx.x];
+    const uint32_t a0 = boff[bkt], n = boff[bkt + 1] - a0;
+    uint32_t n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) s_k[i] = i < n ? keys[a0 + i] : ~0ull;
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = s_k[i], y = s_k[l];
+                    if ((x > y) == ((i & kk) == 0)) {
+                        s_k[i] = y;
+                        s_k[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+    uint32_t c = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        int32_t qs;
+        if (chain_end_lds(s_k, n, i, lay.bp, k, G, M, &qs)) ++c;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t>(c, &tot);
+    if (threadIdx.x == 0) {
+        const uint32_t at = tot ? atomicAdd(cursor, tot) : 0u;
+        s_at = at;
+        btmp[bkt] = at;
+        bcands[bkt] = tot;
+        if (tot) atomicAdd(&cand_per_q[(uint32_t)shr64(s_k[0] >> lay.bp, lay.bd + lay.bs)], tot);
+    }
+    __syncthreads();
+    const uint32_t base = s_at;
+    if (tot == 0 || base + tot > cap) return;  // past cap: the caller grows the buffer and reruns
+    uint32_t at = base + ex;
+    for (uint32_t i = lo; i < hi; ++i) {
+        int32_t qs;
+        if (chain_end_lds(s_k, n, i, lay.bp, k, G, M, &qs)) {
+            const uint64_t key = s_k[i];
+            const uint64_t grp = key >> lay.bp;
+            Cand cd;
+            cd.d = (int32_t)(grp & low_mask(lay.bd)) - lay.bias;
+            cd.s = (int32_t)(shr64(grp, lay.bd) & low_mask(lay.bs));
+            cd.q = (int32_t)shr64(grp, lay.bd + lay.bs);
+            cd.qs = qs;
+            cd.qe = (int32_t)(key & low_mask(lay.bp)) + k;
+            tmp[at++] = cd;
+        }
+    }
+}
+
+void launch_bucket_sort_chain_big(const uint64_t *keys, const uint32_t *boff,
+                                  const uint32_t *list, uint32_t nlist, uint32_t max_bucket,
+                                  HitKeyLayout lay, int32_t k, int32_t max_gap, int32_t min_len,
+                                  Cand *tmp, uint32_t cap, uint32_t *cursor, uint32_t *btmp,
+                                  uint32_t *bcands, uint32_t *cand_per_q, hipStream_t st)
+{
+    if (nlist == 0) return;
+    uint32_t n2 = 1;
+    while (n2 < max_bucket) n2 <<= 1;
+    k_bucket_sort_chain_big<<<nlist, kBlock, n2 * sizeof(uint64_t), st>>>(
+        keys, boff, list, lay, k, max_gap, min_len, tmp, cap, cursor, btmp, bcands, cand_per_q);
+}
+
+hipError_t setup_kernels()
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bucket_sort_chain_big),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kBucketBig * sizeof(uint64_t)));
+}
+
+void launch_bucket_sort_chain(const uint64_t *keys, const uint32_t *boff, uint32_t nbk,
+                              uint32_t max_bucket, HitKeyLayout lay, int32_t k, int32_t max_gap,
+                              int32_t min_len, Cand *tmp, uint32_t cap, uint32_t *cursor,
+                              uint32_t *btmp, uint32_t *bcands, uint32_t *cand_per_q,
+                              hipStream_t st)
+{
+    (void)max_bucket;
+    if (nbk == 0) return;
+    const uint32_t per = kBlock / 64;
+    k_bucket_sort_chain<<<(nbk + per - 1) / per, kBlock, 0, st>>>(
+        keys, boff, nbk, lay, k, max_gap, min_len, tmp, cap, cursor, btmp, bcands, cand_per_q);
+}
+
+// Runs of bucket b move from their reserved range to their rank in bucket order.
+__global__ void k_compact_cands(const Cand *__restrict__ tmp, const uint32_t *__restrict__ btmp,
+                                const uint32_t *__restrict__ bcands,
+                                const uint32_t *__restrict__ coff, Cand *__restrict__ out)
+{
+    const uint32_t b = blockIdx.x;
+    const uint32_t n = bcands[b], from = btmp[b], to = coff[b];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[to + i] = tmp[from + i];
+}
+
+void launch_compact_cands(const Cand *tmp, const uint32_t *btmp, const uint32_t *bcands,
+                          const uint32_t *coff, uint32_t nbk, Cand *out, hipStream_t st)
+{
+    if (nbk) k_compact_cands<<<nbk, 64, 0, st>>>(tmp, btmp, bcands, coff, out);
+}
+
+// ------------------------------------------------------------------ S3+S4+S5 by probing
+// Data-bank windows start at multiples of k, so the hits that can share a run
+// with hit (qpos, dpos) of query q on sequence s lie on the same diagonal at
+// (qpos +- m k, dpos +- m k); the closest one chains iff its gap (m - 1) k <= G,
+// i.e. m <= G / k + 1.  Such a hit exists exactly when the query window at
+// qpos + m k and the data-bank window at dpos + m k have the same code.  Each
+// hit probes both sides (all loads issued together) and is then a single-hit
+// run, the first hit of a longer run, its last hit, or inside it.  Single-hit
+// runs are final (kept when k >= M); first and last hits are stored as run
+// bounds and paired per query after sorting.  No other hit is ever stored, and
+// the runs are those of sorting all hits by (q, s, diag, qpos) and scanning them.
+__global__ __launch_bounds__(kBlock) void k_probe(
+    const uint32_t *__restrict__ hrel, const uint32_t *__restrict__ pbase, int64_t np,
+    const int2 *__restrict__ post, uint32_t nhits, int64_t g0, const int32_t *__restrict__ qid,
+    const int64_t *__restrict__ qoff, int32_t qa, const uint32_t *__restrict__ kcode,
+    const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t k,
+    int32_t mmax, int32_t M, Cand *__restrict__ cands, uint32_t ccap,
+    uint32_t *__restrict__ ccount, uint32_t *__restrict__ cand_per_q, Bound *__restrict__ bounds,
+    uint32_t bcap, uint32_t *__restrict__ bcount, uint32_t *__restrict__ bound_per_q)
 {
     __shared__ uint32_t s_h[kGatherCap + 1];
     __shared__ int64_t s_lo, s_hi;
@@ -288,41 +724,190 @@ __global__ __launch_bounds__(kBlock) void k_gather(const uint32_t *__restrict__ 
     if (in_lds)
         for (int64_t p = lo + threadIdx.x; p <= hi + 1; p += blockDim.x) s_h[p - lo] = hrel[p];
     __syncthreads();
-    for (uint32_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
-        int64_t p;
-        uint32_t first;
-        if (in_lds) {
-            int32_t a = 0, b = (int32_t)(hi - lo);
-            while (a < b) {
-                const int32_t m = (a + b + 1) >> 1;
-                if (s_h[m] <= j) a = m;
-                else b = m - 1;
+    const int lane = threadIdx.x & 63;
+#pragma unroll 2
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t j = t0 + r * kBlock + threadIdx.x;
+        int kind = 0;  // 0 none, 1 single-hit run kept, 2 run bound
+        int32_t q = 0, sq = 0, d = 0, qpos = 0;
+        if (j < t1) {
+            int64_t p;
+            uint32_t first;
+            if (in_lds) {
+                int32_t a = 0, b = (int32_t)(hi - lo);
+                while (a < b) {
+                    const int32_t m = (a + b + 1) >> 1;
+                    if (s_h[m] <= j) a = m;
+                    else b = m - 1;
+                }
+                p = lo + a;
+                first = s_h[a];
+            } else {
+                int64_t a = lo, b = hi;
+                while (a < b) {
+                    const int64_t m = (a + b + 1) >> 1;
+                    if (hrel[m] <= j) a = m;
+                    else b = m - 1;
+                }
+                p = a;
+                first = hrel[a];
             }
-            p = lo + a;
-            first = s_h[a];
-        } else {
-            int64_t a = lo, b = hi;
-            while (a < b) {
-                const int64_t m = (a + b + 1) >> 1;
-                if (hrel[m] <= j) a = m;
-                else b = m - 1;
+            const int2 e = post[pbase[p] + (j - first)];
+            const int64_t g = g0 + p;
+            q = qid[g];
+            const int64_t qb = qoff[q];
+            const int32_t L = (int32_t)(qoff[q + 1] - qb);
+            qpos = (int32_t)(g - qb);
+            const int64_t s0 = seq_start[e.x];
+            const int32_t ns = (int32_t)(seq_start[e.x + 1] - s0);
+            bool pred = false, succ = false;
+#pragma unroll
+            for (int32_t m = 1; m <= kMaxProbe; ++m) {
+                if (m > mmax) break;
+                const int32_t qp = qpos - m * k, dp = e.y - m * k;
+                if (qp >= 0 && dp >= 0)
+                    pred |= kcode[qb + qp] == db_window(dbw, s0 + dp, k);
+                const int32_t qn = qpos + m * k, dn = e.y + m * k;
+                if (qn + k <= L && dn + k <= ns)
+                    succ |= kcode[qb + qn] == db_window(dbw, s0 + dn, k);
             }
-            p = a;
-            first = hrel[a];
+            sq = e.x;
+            d = e.y - qpos;
+            if (!pred && !succ) kind = (k >= M) ? 1 : 0;
+            else if (pred != succ) kind = 2;
         }
-        const int2 e = post[pbase[p] + (j - first)];
-        keys[j] = akey[p] + ((uint64_t)(uint32_t)e.x << sh_s) + ((uint64_t)(uint32_t)e.y << sh_d);
+        const uint64_t m1 = __ballot(kind == 1);
+        if (m1) {
+            const int leader = __ffsll((unsigned long long)m1) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(ccount, (uint32_t)__popcll(m1));
+            base = __shfl(base, leader, 64);
+            if (kind == 1) {
+                const uint32_t at = base + (uint32_t)__popcll(m1 & ((1ull << lane) - 1ull));
+                if (at < ccap) cands[at] = Cand{q - qa, sq, d, qpos, qpos + k};
+                atomicAdd(&cand_per_q[q - qa], 1u);
+            }
+        }
+        const uint64_t m2 = __ballot(kind == 2);
+        if (m2) {
+            const int leader = __ffsll((unsigned long long)m2) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(bcount, (uint32_t)__popcll(m2));
+            base = __shfl(base, leader, 64);
+            if (kind == 2) {
+                const uint32_t at = base + (uint32_t)__popcll(m2 & ((1ull << lane) - 1ull));
+                if (at < bcap) bounds[at] = Bound{q - qa, sq, d, qpos};
+                atomicAdd(&bound_per_q[q - qa], 1u);
+            }
+        }
     }
 }
 
-void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
-                   int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
-                   uint64_t *keys, hipStream_t st)
+void launch_probe(const uint32_t *hrel, const uint32_t *pbase, int64_t np, const int2 *post,
+                  uint32_t nhits, int64_t g0, const int32_t *qid, const int64_t *qoff, int32_t qa,
+                  const uint32_t *kcode, const uint32_t *dbw, const int64_t *seq_start, int32_t k,
+                  int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap, uint32_t *ccount,
+                  uint32_t *cand_per_q, Bound *bounds, uint32_t bcap, uint32_t *bcount,
+                  uint32_t *bound_per_q, hipStream_t st)
 {
     if (nhits == 0) return;
     const uint32_t nb = (nhits + kTile - 1) / kTile;
-    k_gather<<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd, lay.bp,
-                                    keys);
+    k_probe<<<nb, kBlock, 0, st>>>(hrel, pbase, np, post, nhits, g0, qid, qoff, qa, kcode, dbw,
+                                   seq_start, k, max_gap / k + 1, min_len, cands, ccap, ccount,
+                                   cand_per_q, bounds, bcap, bcount, bound_per_q);
+}
+
+// Run bounds appended in any order go to their query's range (counting sort).
+__global__ void k_bounds_by_query(const Bound *__restrict__ in, uint32_t n,
+                                  const uint32_t *__restrict__ qoff_b, uint32_t *__restrict__ cur,
+                                  Bound *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Bound b = in[i];
+    out[qoff_b[b.q] + atomicAdd(&cur[b.q], 1u)] = b;
+}
+
+void launch_bounds_by_query(const Bound *in, uint32_t n, const uint32_t *qoff_b, uint32_t *cur,
+                            Bound *out, hipStream_t st)
+{
+    if (n) k_bounds_by_query<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(in, n, qoff_b, cur, out);
+}
+
+struct BoundLess {
+    __device__ bool operator()(const Bound &x, const Bound &y) const
+    {
+        if (x.s != y.s) return x.s < y.s;
+        if (x.d != y.d) return x.d < y.d;
+        return x.qpos < y.qpos;
+    }
+};
+
+// One block per query: sort its run bounds by (s, diag, qpos); they then
+// alternate first hit, last hit, so pair 2i and 2i + 1 spans one run.
+__global__ __launch_bounds__(kBlock) void k_pair_bounds(const Bound *__restrict__ b,
+                                                        const uint32_t *__restrict__ qoff_b,
+                                                        int32_t k, int32_t M,
+                                                        Cand *__restrict__ cands, uint32_t ccap,
+                                                        uint32_t *__restrict__ ccount,
+                                                        uint32_t *__restrict__ cand_per_q)
+{
+    __shared__ Bound s_r[kBoundCap];
+    __shared__ uint16_t s_ix[kBoundCap];
+    const int32_t ql = blockIdx.x;
+    const uint32_t a0 = qoff_b[ql], n = qoff_b[ql + 1] - a0;
+    if (n == 0 || n > (uint32_t)kBoundCap) return;  // longer lists take another grouping
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_r[i] = b[a0 + i];
+    lds_bitonic(s_r, s_ix, n, BoundLess());
+    const int lane = threadIdx.x & 63;
+    const uint32_t npairs = n / 2;
+    for (uint32_t base = 0; base < npairs; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        bool keep = false;
+        Cand c{0, 0, 0, 0, 0};
+        if (i < npairs) {
+            const Bound x = s_r[s_ix[2 * i]], y = s_r[s_ix[2 * i + 1]];
+            c = Cand{ql, x.s, x.d, x.qpos, y.qpos + k};
+            keep = c.qe - c.qs >= M;
+        }
+        const uint64_t mk = __ballot(keep);
+        if (mk) {
+            const int leader = __ffsll((unsigned long long)mk) - 1;
+            uint32_t at0 = 0;
+            if (lane == leader) at0 = atomicAdd(ccount, (uint32_t)__popcll(mk));
+            at0 = __shfl(at0, leader, 64);
+            if (keep) {
+                const uint32_t at = at0 + (uint32_t)__popcll(mk & ((1ull << lane) - 1ull));
+                if (at < ccap) cands[at] = c;
+                atomicAdd(&cand_per_q[ql], 1u);
+            }
+        }
+    }
+}
+
+void launch_pair_bounds(const Bound *b, const uint32_t *qoff_b, int32_t nq, int32_t k,
+                        int32_t min_len, Cand *cands, uint32_t ccap, uint32_t *ccount,
+                        uint32_t *cand_per_q, hipStream_t st)
+{
+    if (nq > 0)
+        k_pair_bounds<<<nq, kBlock, 0, st>>>(b, qoff_b, k, min_len, cands, ccap, ccount, cand_per_q);
+}
+
+// Runs appended in any order go to their query's range (a counting sort by query).
+__global__ void k_group_by_query(const Cand *__restrict__ in, uint32_t n,
+                                 const uint32_t *__restrict__ qoff_c, uint32_t *__restrict__ cur,
+                                 Cand *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Cand c = in[i];
+    out[qoff_c[c.q] + atomicAdd(&cur[c.q], 1u)] = c;
+}
+
+void launch_group_by_query(const Cand *in, uint32_t n, const uint32_t *qoff_c, uint32_t *cur,
+                           Cand *out, hipStream_t st)
+{
+    if (n) k_group_by_query<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(in, n, qoff_c, cur, out);
 }
 
 // ------------------------------------------------------------------ S4: radix sort
@@ -787,39 +1372,6 @@ void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Ali
 // with a bitonic network on indices.  Ties between equal records fall back to the
 // input position, which makes the order total and the result deterministic.
 // Segments longer than kSegCap go through the global radix sort instead.
-template <typename Rec, typename Less>
-__device__ void lds_bitonic(const Rec *__restrict__ s_r, uint16_t *__restrict__ s_ix, uint32_t n,
-                            Less less)
-{
-    uint32_t n2 = 1;
-    while (n2 < n) n2 <<= 1;
-    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) s_ix[i] = (uint16_t)i;
-    __syncthreads();
-    auto before = [&](uint32_t a, uint32_t b) -> bool {  // a strictly before b
-        if (a >= n) return false;
-        if (b >= n) return true;
-        if (less(s_r[a], s_r[b])) return true;
-        if (less(s_r[b], s_r[a])) return false;
-        return a < b;
-    };
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-                const uint32_t l = i ^ j;
-                if (l > i) {
-                    const uint32_t a = s_ix[i], b = s_ix[l];
-                    const bool up = (i & k) == 0;
-                    if (up ? before(b, a) : before(a, b)) {
-                        s_ix[i] = (uint16_t)b;
-                        s_ix[l] = (uint16_t)a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // MODE 0: merge order (s, qs, ds, qe, de); MODE 1: selection order (kept boxes
 // first, then length descending, s, qs, ds, qe, de).  Length = min of the spans.
 template <int MODE>

@@ -96,6 +96,8 @@ struct Workspace {
     DevBuf hrel, pbase, akey, keys, keys_alt, hist, rs_partials;
     DevBuf cands, ccount, cand_q, cand_off, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
+    DevBuf bplan, bcount, boff, bcands, btmp, bcoff, ctmp, cursor, qcur, bound_q, bound_off,
+        btmp_b, bounds, blist;
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
     std::vector<hipEvent_t> events;
@@ -114,7 +116,8 @@ struct Workspace {
                          &hrel, &pbase, &akey, &keys, &keys_alt, &hist, &rs_partials, &cands,
                          &ccount, &cand_q, &cand_off, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
                          &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
-                         &cells_q};
+                         &cells_q, &bplan, &bcount, &boff, &bcands, &btmp, &bcoff, &ctmp, &cursor, &qcur,
+                         &bound_q, &bound_off, &btmp_b, &bounds, &blist};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -137,6 +140,8 @@ struct gg_index {
     int64_t *d_seq_start = nullptr;
     uint64_t hit_budget = 0;
     uint64_t default_budget = 0;
+    uint32_t bucket_cap = 0;  // keys of one bucket one wave sorts in LDS
+    uint32_t bucket_big = 0;  // keys of one bucket one block sorts in LDS
     mutable std::mutex ws_mu;
     mutable std::vector<Workspace *> ws_free;
     std::atomic<int> prof_on{0};
@@ -334,9 +339,22 @@ struct BatchOut {
 };
 
 // Run every GPU stage for queries [qa, qb) of the batch (one wave).
+// How index hits become runs (Section 2.2 phase 2): kProbe tests the windows next
+// to each hit and stores no hit; kBucket and kSort store every hit as a 64-bit key
+// (q, s, diag, qpos) and sort them, by slices in LDS or by global radix passes.
+enum Grouping { kProbe = 0, kBucket = 1, kSort = 2 };
+
+Grouping grouping_from_env()
+{
+    const char *g = getenv("GG_GROUPING");
+    if (g && !strcmp(g, "probe")) return kProbe;
+    if (g && !strcmp(g, "bucket")) return kBucket;
+    return kSort;
+}
+
 gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
                    const std::vector<int64_t> &qoff_h, const std::vector<uint64_t> &qtot,
-                   int32_t qa, int32_t qb, BatchOut &bo)
+                   int32_t qa, int32_t qb, BatchOut &bo, Grouping grouping)
 {
     hipStream_t st = ws->st;
     const int32_t nqw = qb - qa;
@@ -367,7 +385,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     lay.bd = bits_for((uint64_t)ix->max_seq_len + (uint64_t)maxL);
     lay.bs = bits_for((uint64_t)ix->n_seqs);
     lay.bq = bits_for((uint64_t)nqw);
-    if (lay.bp + lay.bd + lay.bs + lay.bq > 64) return GG_EINVAL;
+    if (grouping != kProbe && lay.bp + lay.bd + lay.bs + lay.bq > 64) return GG_EINVAL;
     if ((uint64_t)maxL * (uint64_t)p->match >= (1ull << 30)) return GG_EINVAL;  // int32 scores
 
     // ---- S3 gather
@@ -375,81 +393,258 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     TRY(ensure(ws->hrel, sizeof(uint32_t) * (np + 1)));
     TRY(ensure(ws->pbase, sizeof(uint32_t) * (np + 1)));
     TRY(ensure(ws->akey, sizeof(uint64_t) * (np + 1)));
-    TRY(ensure(ws->keys, sizeof(uint64_t) * H));
-    TRY(ensure(ws->keys_alt, sizeof(uint64_t) * H));
-    TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(H)));
-    TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(H))));
     prof.begin("gather_prep");
     launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
                      as<int32_t>(ws->qid), ix->d_list_off, qa, g0, g1, lay, as<uint32_t>(ws->hrel),
                      as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), st);
     prof.end(np);
-    prof.begin("gather");
-    launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), np,
-                  ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
-    prof.end(H);
 
-    // ---- S4 group: order hits by (q, s, diag); qpos order is kept by stability
-    const int sort_lo = lay.bp, sort_hi = lay.bp + lay.bd + lay.bs + lay.bq;
-    uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
-    if (H > 1) {
-        for (int shift = sort_lo; shift < sort_hi; shift += kRadixBits) {
-            prof.begin("sort_hist");
-            launch_rs_hist(kcur, H, shift, as<uint32_t>(ws->hist), st);
-            prof.end(H);
-            prof.begin("sort_scan");
-            launch_rs_scan(as<uint32_t>(ws->hist), H, as<uint32_t>(ws->rs_partials), st);
-            prof.end(H);
-            prof.begin("sort_scatter");
-            launch_rs_scatter(kcur, nullptr, knext, nullptr, H, shift, as<uint32_t>(ws->hist), st);
-            prof.end(H);
-            std::swap(kcur, knext);
-        }
-    }
-    const uint64_t *sorted = kcur;
-
-    // ---- S5 chain + filter: runs in hit-key order (grouped by query, then sequence)
-    const uint32_t ntile = chain_tiles(H);
-    TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
-    TRY(ensure(ws->cand_q, sizeof(uint32_t) * (nqw + 1)));
-    TRY(ensure(ws->cand_off, sizeof(uint32_t) * (nqw + 1)));
-    TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nqw) + 1)));
+    // pinned staging: run and bound counts[2] | runs per query[nqw] | sel_off[nqw+1] | sel start[nqw] |
+    // sel end[nqw] | report start[nqw] | report end[nqw] | (8-aligned) cells per query[nqw]
     void *pin;
     const size_t n1 = (size_t)nqw + 1;
-    // pinned staging: run count | runs per query[nqw] | sel_off[nqw+1] | sel start[nqw] |
-    // sel end[nqw] | report start[nqw] | report end[nqw] | (8-aligned) cells per query[nqw]
-    const size_t u32s = 1 + (size_t)nqw + n1 + 4 * (size_t)nqw;
+    const size_t u32s = 2 + (size_t)nqw + n1 + 4 * (size_t)nqw;
     const size_t cells_at = ((u32s * 4 + 7) / 8) * 8;
     TRY(pinned(ws, cells_at + 8 * (size_t)nqw + 64, &pin));
     uint32_t *h_nc = reinterpret_cast<uint32_t *>(pin);
-    uint32_t *h_cq = h_nc + 1;
+    uint32_t *h_cq = h_nc + 2;
     uint32_t *h_sel_off = h_cq + nqw;
     uint32_t *h_ss = h_sel_off + n1, *h_se = h_ss + nqw, *h_rs = h_se + nqw, *h_re = h_rs + nqw;
     unsigned long long *h_cells =
         reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(pin) + cells_at);
+    TRY(ensure(ws->cand_q, sizeof(uint32_t) * (nqw + 1)));
+    TRY(ensure(ws->cand_off, sizeof(uint32_t) * (nqw + 1)));
     HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
-    prof.begin("chain");
-    launch_chain_count(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len, as<uint32_t>(ws->ccount),
-                       st);
-    launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount), ntile,
-                    as<uint32_t>(ws->partials), st);
-    HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + ntile, sizeof(uint32_t),
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const uint32_t nc = *h_nc;
-    if (nc > 0) {
-        TRY(ensure(ws->cands, sizeof(Cand) * nc));
-        launch_chain_write(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
-                           as<uint32_t>(ws->ccount), as<Cand>(ws->cands), as<uint32_t>(ws->cand_q),
-                           st);
-        launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nqw,
+    uint32_t nc = 0;
+
+    // ---- S3 + S4 + S5, bucketed: a query's hits are cut into slices of its
+    // sequence-id range of about bucket_cap / 4 hits; each slice is sorted and
+    // chained in LDS.  A slice over bucket_cap hits sends the wave to the global path.
+    const uint32_t target = std::max<uint32_t>(ix->bucket_cap / 4, 1);
+    std::vector<uint32_t> plan(2 * (size_t)nqw);  // bucket base | bucket count per query
+    uint64_t nbk64 = 0;
+    for (int32_t ql = 0; ql < nqw; ++ql) {
+        const uint64_t nb = std::max<uint64_t>(1, (qtot[qa + ql] + target - 1) / target);
+        plan[ql] = (uint32_t)nbk64;
+        plan[nqw + ql] = (uint32_t)nb;
+        nbk64 += nb;
+    }
+    if (grouping == kProbe && p->max_gap / ix->k + 1 > kMaxProbe) grouping = kBucket;
+    if (grouping == kProbe) {
+        // ---- S3 + S4 + S5 by probing: single-hit runs and run bounds, no stored hit
+        uint32_t ccap = (uint32_t)std::max<uint64_t>(1u << 16, H / 64);
+        uint32_t bcap = (uint32_t)std::max<uint64_t>(1u << 16, H / 32);
+        TRY(ensure(ws->cursor, sizeof(uint32_t) * 4));
+        TRY(ensure(ws->bound_q, sizeof(uint32_t) * (nqw + 1)));
+        TRY(ensure(ws->bound_off, sizeof(uint32_t) * (nqw + 1)));
+        TRY(ensure(ws->qcur, sizeof(uint32_t) * (nqw + 1)));
+        TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed((int64_t)nqw + 1)));
+        uint32_t *h_cur = h_nc;  // [0] runs, [1] bounds
+        uint32_t nb = 0;
+        std::vector<uint32_t> bq(nqw);
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            TRY(ensure(ws->ctmp, sizeof(Cand) * ccap));
+            TRY(ensure(ws->btmp_b, sizeof(Bound) * bcap));
+            HIPCHK(hipMemsetAsync(ws->cursor.p, 0, sizeof(uint32_t) * 2, st));
+            HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
+            HIPCHK(hipMemsetAsync(ws->bound_q.p, 0, sizeof(uint32_t) * nqw, st));
+            prof.begin("probe");
+            launch_probe(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), np, ix->d_post, H, g0,
+                         as<int32_t>(ws->qid), as<int64_t>(ws->qoff), qa, as<uint32_t>(ws->kcode),
+                         ix->d_dbw, ix->d_seq_start, ix->k, p->max_gap, p->min_hsp_len,
+                         as<Cand>(ws->ctmp), ccap, as<uint32_t>(ws->cursor),
+                         as<uint32_t>(ws->cand_q), as<Bound>(ws->btmp_b), bcap,
+                         as<uint32_t>(ws->cursor) + 1, as<uint32_t>(ws->bound_q), st);
+            prof.end(H);
+            HIPCHK(hipMemcpyAsync(h_cur, ws->cursor.p, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost,
+                                  st));
+            HIPCHK(hipMemcpyAsync(bq.data(), ws->bound_q.p, sizeof(uint32_t) * nqw,
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            nc = h_cur[0];
+            nb = h_cur[1];
+            if (nc <= ccap && nb <= bcap) break;
+            ccap = std::max(ccap, nc);
+            bcap = std::max(bcap, nb);
+        }
+        const uint32_t maxb = nqw ? *std::max_element(bq.begin(), bq.end()) : 0;
+        if (maxb > (uint32_t)kBoundCap) {
+            grouping = kBucket;  // a query with too many runs to pair in LDS
+            nc = 0;
+            HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
+        } else {
+            if (nb > 0) {
+                // room for every pair after the single-hit runs
+                const uint32_t need = nc + nb / 2;
+                if (need > ccap) {
+                    DevBuf bigger;
+                    TRY(ensure(bigger, sizeof(Cand) * need));
+                    HIPCHK(hipMemcpyAsync(bigger.p, ws->ctmp.p, sizeof(Cand) * nc,
+                                          hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    (void)hipFree(ws->ctmp.p);
+                    ws->ctmp = bigger;
+                    ccap = need;
+                }
+                TRY(ensure(ws->bounds, sizeof(Bound) * nb));
+                prof.begin("pair");
+                launch_scan_u32(as<uint32_t>(ws->bound_q), as<uint32_t>(ws->bound_off), nqw,
+                                as<uint32_t>(ws->partials), st);
+                HIPCHK(hipMemsetAsync(ws->qcur.p, 0, sizeof(uint32_t) * nqw, st));
+                launch_bounds_by_query(as<Bound>(ws->btmp_b), nb, as<uint32_t>(ws->bound_off),
+                                       as<uint32_t>(ws->qcur), as<Bound>(ws->bounds), st);
+                launch_pair_bounds(as<Bound>(ws->bounds), as<uint32_t>(ws->bound_off), nqw, ix->k,
+                                   p->min_hsp_len, as<Cand>(ws->ctmp), ccap,
+                                   as<uint32_t>(ws->cursor), as<uint32_t>(ws->cand_q), st);
+                prof.end(nb);
+                HIPCHK(hipMemcpyAsync(h_cur, ws->cursor.p, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                      st));
+                HIPCHK(hipStreamSynchronize(st));
+                nc = h_cur[0];
+            }
+            if (nc > 0) {
+                TRY(ensure(ws->cands, sizeof(Cand) * nc));
+                launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nqw,
+                                as<uint32_t>(ws->partials), st);
+                HIPCHK(hipMemsetAsync(ws->qcur.p, 0, sizeof(uint32_t) * nqw, st));
+                launch_group_by_query(as<Cand>(ws->ctmp), nc, as<uint32_t>(ws->cand_off),
+                                      as<uint32_t>(ws->qcur), as<Cand>(ws->cands), st);
+            }
+        }
+        if (grouping != kProbe && lay.bp + lay.bd + lay.bs + lay.bq > 64) return GG_EINVAL;
+    }
+    bool bucketed = grouping == kBucket && nbk64 < (1ull << 30);
+    if (grouping != kProbe) TRY(ensure(ws->keys, sizeof(uint64_t) * H));
+    if (bucketed) {
+        const uint32_t nbk = (uint32_t)nbk64;
+        TRY(ensure(ws->bplan, sizeof(uint32_t) * 2 * nqw));
+        TRY(ensure(ws->bcount, sizeof(uint32_t) * (nbk + 1)));
+        TRY(ensure(ws->boff, sizeof(uint32_t) * (nbk + 1)));
+        TRY(ensure(ws->bcands, sizeof(uint32_t) * (nbk + 1)));
+        TRY(ensure(ws->btmp, sizeof(uint32_t) * (nbk + 1)));
+        TRY(ensure(ws->bcoff, sizeof(uint32_t) * (nbk + 1)));
+        TRY(ensure(ws->cursor, sizeof(uint32_t) * 4));
+        TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed((int64_t)nbk + 1)));
+        const uint32_t *bb = as<uint32_t>(ws->bplan), *nbq = bb + nqw;
+        HIPCHK(hipMemcpyAsync(ws->bplan.p, plan.data(), sizeof(uint32_t) * 2 * nqw,
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(ws->bcount.p, 0, sizeof(uint32_t) * nbk, st));
+        prof.begin("gather_count");
+        launch_gather_bucket(1, as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase),
+                             as<uint64_t>(ws->akey), np, ix->d_post, H, lay, bb, nbq,
+                             as<uint32_t>(ws->bcount), nullptr, nullptr, st);
+        prof.end(H);
+        launch_scan_u32(as<uint32_t>(ws->bcount), as<uint32_t>(ws->boff), nbk,
                         as<uint32_t>(ws->partials), st);
+        std::vector<uint32_t> cnt(nbk);
+        HIPCHK(hipMemcpyAsync(cnt.data(), ws->bcount.p, sizeof(uint32_t) * nbk,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const uint32_t maxb = *std::max_element(cnt.begin(), cnt.end());
+        bucketed = maxb <= ix->bucket_big;
+        std::vector<uint32_t> big;  // buckets over one wave's LDS slice
+        for (uint32_t b = 0; bucketed && b < nbk; ++b)
+            if (cnt[b] > ix->bucket_cap) big.push_back(b);
+        if (bucketed) {
+            TRY(ensure(ws->blist, sizeof(uint32_t) * (big.size() + 1)));
+            if (!big.empty())
+                HIPCHK(hipMemcpyAsync(ws->blist.p, big.data(), sizeof(uint32_t) * big.size(),
+                                      hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemsetAsync(ws->bcount.p, 0, sizeof(uint32_t) * nbk, st));
+            prof.begin("gather");
+            launch_gather_bucket(2, as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase),
+                                 as<uint64_t>(ws->akey), np, ix->d_post, H, lay, bb, nbq,
+                                 as<uint32_t>(ws->bcount), as<uint32_t>(ws->boff),
+                                 as<uint64_t>(ws->keys), st);
+            prof.end(H);
+            uint32_t ccap = (uint32_t)std::max<uint64_t>(1u << 16, H / 16);
+            for (int attempt = 0; attempt < 2; ++attempt) {
+                TRY(ensure(ws->ctmp, sizeof(Cand) * ccap));
+                HIPCHK(hipMemsetAsync(ws->cursor.p, 0, sizeof(uint32_t), st));
+                if (attempt) HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
+                prof.begin("group");
+                launch_bucket_sort_chain(as<uint64_t>(ws->keys), as<uint32_t>(ws->boff), nbk, maxb,
+                                         lay, ix->k, p->max_gap, p->min_hsp_len,
+                                         as<Cand>(ws->ctmp), ccap, as<uint32_t>(ws->cursor),
+                                         as<uint32_t>(ws->btmp), as<uint32_t>(ws->bcands),
+                                         as<uint32_t>(ws->cand_q), st);
+                launch_bucket_sort_chain_big(as<uint64_t>(ws->keys), as<uint32_t>(ws->boff),
+                                             as<uint32_t>(ws->blist), (uint32_t)big.size(), maxb,
+                                             lay, ix->k, p->max_gap, p->min_hsp_len,
+                                             as<Cand>(ws->ctmp), ccap, as<uint32_t>(ws->cursor),
+                                             as<uint32_t>(ws->btmp), as<uint32_t>(ws->bcands),
+                                             as<uint32_t>(ws->cand_q), st);
+                prof.end(H);
+                HIPCHK(hipMemcpyAsync(h_nc, ws->cursor.p, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                      st));
+                HIPCHK(hipStreamSynchronize(st));
+                nc = *h_nc;
+                if (nc <= ccap) break;
+                ccap = nc;
+            }
+            if (nc > 0) {
+                TRY(ensure(ws->cands, sizeof(Cand) * nc));
+                launch_scan_u32(as<uint32_t>(ws->bcands), as<uint32_t>(ws->bcoff), nbk,
+                                as<uint32_t>(ws->partials), st);
+                launch_compact_cands(as<Cand>(ws->ctmp), as<uint32_t>(ws->btmp),
+                                     as<uint32_t>(ws->bcands), as<uint32_t>(ws->bcoff), nbk,
+                                     as<Cand>(ws->cands), st);
+                launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nqw,
+                                as<uint32_t>(ws->partials), st);
+            }
+        }
     }
-    prof.end(H);
-    if (nc == 0) {
-        if (bo.stats) HIPCHK(hipStreamSynchronize(st));
-        return GG_OK;
+    if (grouping != kProbe && !bucketed) {
+        // ---- global path: gather in place, stable LSD radix sort, chain
+        TRY(ensure(ws->keys_alt, sizeof(uint64_t) * H));
+        TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(H)));
+        TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(H))));
+        prof.begin("gather");
+        launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), np,
+                      ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
+        prof.end(H);
+        const int sort_lo = lay.bp, sort_hi = lay.bp + lay.bd + lay.bs + lay.bq;
+        uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
+        if (H > 1) {
+            for (int shift = sort_lo; shift < sort_hi; shift += kRadixBits) {
+                prof.begin("sort_hist");
+                launch_rs_hist(kcur, H, shift, as<uint32_t>(ws->hist), st);
+                prof.end(H);
+                prof.begin("sort_scan");
+                launch_rs_scan(as<uint32_t>(ws->hist), H, as<uint32_t>(ws->rs_partials), st);
+                prof.end(H);
+                prof.begin("sort_scatter");
+                launch_rs_scatter(kcur, nullptr, knext, nullptr, H, shift, as<uint32_t>(ws->hist),
+                                  st);
+                prof.end(H);
+                std::swap(kcur, knext);
+            }
+        }
+        const uint64_t *sorted = kcur;
+        const uint32_t ntile = chain_tiles(H);
+        TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
+        TRY(ensure(ws->partials,
+                   sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nqw) + 1)));
+        prof.begin("chain");
+        launch_chain_count(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
+                           as<uint32_t>(ws->ccount), st);
+        launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount), ntile,
+                        as<uint32_t>(ws->partials), st);
+        HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + ntile, sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        nc = *h_nc;
+        if (nc > 0) {
+            TRY(ensure(ws->cands, sizeof(Cand) * nc));
+            launch_chain_write(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
+                               as<uint32_t>(ws->ccount), as<Cand>(ws->cands),
+                               as<uint32_t>(ws->cand_q), st);
+            launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nqw,
+                            as<uint32_t>(ws->partials), st);
+        }
+        prof.end(H);
     }
+    if (nc == 0) return GG_OK;
     HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
 
     // ---- S6 extend (one wave per run)
@@ -680,8 +875,12 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     HIPCHK(hipStreamSynchronize(st));
     if (err) return GG_EINVAL;
 
-    // ---- waves: consecutive queries whose hit keys fit the budget and the key bits
-    const uint64_t max_hits = std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
+    // ---- waves: consecutive queries whose stored hit keys fit the budget and the key
+    // bits (probing stores no hit: its waves are bounded only by 32-bit hit counts)
+    const Grouping grouping = grouping_from_env();
+    const uint64_t max_hits = grouping == kProbe
+                                  ? (uint64_t)INT32_MAX
+                                  : std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
     for (int64_t q = 0; q < nq; ++q)
         if (qtot[q] > max_hits) return GG_EBUDGET;
     const int bs = bits_for((uint64_t)ix->n_seqs);
@@ -696,13 +895,14 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
             const int bits = bits_for((uint64_t)L2) + bits_for((uint64_t)ix->max_seq_len + L2) + bs +
                              bits_for((uint64_t)(qb - qa + 1)) ;
             const int wbits = bits_for((uint64_t)(qb - qa + 2));  // record keys hold q up to nqw
-            if (qb > qa && (h2 > max_hits || bits > 64 || wbits > 31)) break;
-            if (bits > 64) return GG_EINVAL;
+            const bool too_wide = grouping != kProbe && bits > 64;
+            if (qb > qa && (h2 > max_hits || too_wide || wbits > 31)) break;
+            if (too_wide) return GG_EINVAL;
             h = h2;
             maxL = L2;
             ++qb;
         }
-        TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, qa, qb, bo));
+        TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, qa, qb, bo, grouping));
         prof.collect();
         qa = qb;
     }
@@ -808,7 +1008,8 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
         X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
 #undef X
     };
-    // 2-bit packing, 16 bases per 32-bit word, base g at bits 2 (g % 16)
+    // 2-bit packing, 16 bases per 32-bit word, first base most significant:
+    // base g at bits 30 - 2 (g % 16) of word g / 16
     const int64_t nwords = (total + 15) / 16 + 1;
     std::vector<uint32_t> dbw;
     std::vector<uint32_t> head;
@@ -837,7 +1038,7 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
                             bad = 1;
                             continue;
                         }
-                        word |= (uint32_t)c << (2 * b);
+                        word |= (uint32_t)c << (30 - 2 * b);
                     }
                     dbw[(size_t)w] = word;
                 }
@@ -846,7 +1047,7 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
         for (auto &t : th) t.join();
         if (bad) return GG_EINVAL;
     }
-    auto base_at = [&](int64_t g) -> uint32_t { return (dbw[(size_t)(g >> 4)] >> ((g & 15) * 2)) & 3u; };
+    auto base_at = [&](int64_t g) -> uint32_t { return (dbw[(size_t)(g >> 4)] >> (30 - (g & 15) * 2)) & 3u; };
     auto window_code = [&](int64_t g) -> uint32_t {
         uint32_t c = 0;
         for (int t = 0; t < k; ++t) c = (c << 2) | base_at(g + t);
@@ -913,6 +1114,15 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(GG_EDEVICE);
     ix->default_budget = std::min<uint64_t>((uint64_t)16 << 30, free_b / 4);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        return fail(GG_EDEVICE);
+    if ((size_t)lds < (size_t)kBucketCapMax * 8 * (kBlock / 64) + 1024) return fail(GG_EDEVICE);
+    ix->bucket_cap = kBucketCapMax;
+    ix->bucket_big = (size_t)lds >= (size_t)kBucketBig * 8 + 1024 && setup_kernels() == hipSuccess
+                         ? kBucketBig
+                         : kBucketCapMax;
+    (void)hipGetLastError();
     *out = ix;
     return GG_OK;
 }

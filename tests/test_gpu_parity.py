@@ -89,9 +89,11 @@ def test_scoring_variants(ggo, c0):
         check_batch(G, gix, qs, G.params(7, **kw), want, wst)
 
 
-def test_waves_under_small_budget(ggo):
-    """A tiny hit budget forces one query per wave; results must not change."""
+def test_waves_under_small_budget(ggo, monkeypatch):
+    """With stored hits (radix-sort grouping), a tiny hit budget forces one query
+    per wave; results must not change."""
     G = gpu()
+    monkeypatch.setenv("GG_GROUPING", "sort")
     db = synth.config1_db(n_seqs=20_000)
     qs = synth.config1_queries(db, n=60)
     oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
@@ -204,3 +206,18 @@ def test_device_resident_form(ggo, c0):
             assert as_rows(got[i * cap: i * cap + m]) == as_rows(want[i][:m])
             assert int(st[i]["n_cells"]) == wst[i]["n_cells"]
         assert (rc == G.GG_ETRUNC) == any(len(w) > cap for w in want)
+
+
+@pytest.mark.parametrize("grouping", ["probe", "bucket", "sort"])
+def test_grouping_strategies_agree(ggo, monkeypatch, grouping):
+    """Runs found by probing neighbour windows (default), by sorting hits in LDS
+    slices, or by global radix sorting are the same runs."""
+    G = gpu()
+    db = synth.random_db(11, n_seqs=400, lmin=50, lmax=4000)
+    qs = synth.random_queries(11, db, n=30, lmin=100, lmax=3000, frac_homolog=0.8,
+                              ident_lo=0.85, ident_hi=1.0, indel_rate=0.01)
+    oix, gix = ggo.Index(db.seqs, db.off, 8), G.Index(db.seqs, db.off, 8)
+    for kw in (dict(), dict(max_gap=0, min_hsp_len=8), dict(max_gap=40, min_hsp_len=30)):
+        want, wst = oracle_all(ggo, oix, qs, ggo.params(10, **kw))
+        monkeypatch.setenv("GG_GROUPING", grouping)
+        check_batch(G, gix, qs, G.params(10, **kw), want, wst)
