@@ -91,6 +91,67 @@ def cpu_baseline(db, qs, max_hits: int, min_seconds: float = 8.0):
                       f"{dt:.1f} s wall on {cores} threads (index build excluded)"}
 
 
+def serve_leg(gix, db, prm, rate: float, n: int) -> dict:
+    """Open-loop Poisson arrivals at `rate` queries/s into the continuous-batching
+    server; latency = completion time - scheduled arrival time.  The first 32
+    served results are checked against the one-query form."""
+    import threading
+
+    qs = synth.config4_queries(db, n=n)
+    arr = synth.config4_arrivals(rate, n)
+    want = {}
+    for i in range(min(32, n)):
+        rc, h, _ = gix.search(qs.query(i), prm, cap=CAP)
+        want[i] = h.tobytes()
+    sv = gg.Server(gix, prm, hit_budget_bytes=0, max_slots=256)
+    tickets = [None] * n
+    done = [0.0] * n
+    submitted = [0]
+    lock = threading.Lock()
+    status = []
+
+    def collector():
+        pending = set()
+        nxt = 0
+        while nxt < n or pending:
+            with lock:
+                upto = submitted[0]
+            while nxt < upto:
+                pending.add(nxt)
+                nxt += 1
+            for i in list(pending):
+                rc, h, m = sv.poll(tickets[i], cap=CAP, timeout_us=0)
+                if rc != gg.GG_EAGAIN:
+                    done[i] = time.perf_counter()
+                    status.append(rc)
+                    pending.discard(i)
+                    if i in want:
+                        assert h.tobytes() == want[i], f"served query {i} differs"
+            time.sleep(0.0001)
+
+    th = threading.Thread(target=collector)
+    th.start()
+    t0 = time.perf_counter()
+    for i in range(n):
+        target = t0 + arr[i]
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            time.sleep(min(target - now, 0.0005))
+        tickets[i] = sv.submit(qs.query(i))
+        with lock:
+            submitted[0] = i + 1
+    th.join()
+    t_end = max(done)
+    sv.close()
+    assert all(r in (gg.GG_OK, gg.GG_ETRUNC) for r in status)
+    lat = np.array([done[i] - (t0 + arr[i]) for i in range(n)]) * 1e3
+    return {"rate_per_s": rate, "requests": n, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "achieved_qps": round(n / (t_end - t0), 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +159,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--queries", type=int, default=1000)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form latency leg")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the one-query-at-a-time comparison (for kernel-trace runs)")
     args = ap.parse_args()
@@ -212,6 +274,14 @@ def main() -> int:
         plain_qps = n_plain / (time.perf_counter() - t1)
     log(f"plain per-query loop: {plain_qps} queries/s; PCIe-inclusive batch: {pcie_qps:.0f}")
 
+    serve = []
+    if not args.no_serve:
+        # served form: queries shaped like the serving workload (log-uniform 50-20,000
+        # bp, 60% planted homologs) against the resident bank, Poisson arrivals
+        for rate, n in ((200.0, 400), (1000.0, 1000), (5000.0, 2000)):
+            serve.append(serve_leg(gix, db, prm, rate, n))
+            log(f"served at {rate:.0f}/s: {serve[-1]}")
+
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline ...")
@@ -239,6 +309,7 @@ def main() -> int:
             "align_cells_per_step": cells,
             "align_gcups": round(align_gcups, 2) if align_gcups else None,
             "valu_peak_tops": round(VALU_PEAK_TOPS, 1),
+            "served": serve,
         },
     }
     print(json.dumps(line), flush=True)
