@@ -49,17 +49,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def traffic_for(stage: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary for this
+    kernel, if the counters were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}.txt")
     if not os.path.exists(path):
         return None
+    fields = {}
     with open(path) as fh:
-        t = json.load(fh)
-    if t.get("kernel_source") != kernel_source_hash():
+        for line in fh:
+            if ":" in line:
+                key, val = line.split(":", 1)
+                fields[key.strip()] = val.strip()
+    if fields.get("kernel_source") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return int(fields["bytes_per_launch"]) if "bytes_per_launch" in fields else None
 
 
 def cpu_baseline(db, qs, max_hits: int, min_seconds: float = 8.0):
@@ -160,6 +164,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--queries", type=int, default=1000)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form latency leg")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES device-to-device three times (counter calibration)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the one-query-at-a-time comparison (for kernel-trace runs)")
     args = ap.parse_args()
@@ -169,6 +175,12 @@ def main() -> int:
         return 2
 
     gg.lib()  # the compiled HIP library, or a loud failure
+    if args.calibrate_copy:
+        a, b = gg.DeviceBuffer(args.calibrate_copy), gg.DeviceBuffer(args.calibrate_copy)
+        for _ in range(3):
+            b.copy_from(a, args.calibrate_copy)
+        log(f"copied {args.calibrate_copy} bytes device-to-device 3 times")
+        return 0
     t = time.perf_counter()
     db = synth.config1_db()
     qs = synth.config1_queries(db, n=args.queries)

@@ -152,6 +152,9 @@ gg_status gg_device_alloc(int32_t device, uint64_t bytes, void **ptr);
 gg_status gg_device_free(int32_t device, void *ptr);
 gg_status gg_memcpy_to_device(void *dst, const void *src, uint64_t bytes);
 gg_status gg_memcpy_to_host(void *dst, const void *src, uint64_t bytes);
+/* Device-to-device copy of `bytes` (the runtime's copy kernel); a transfer of known
+ * size against which memory-traffic counters are calibrated. */
+gg_status gg_device_copy(void *dst, const void *src, uint64_t bytes);
 
 /*
  * Per-stage GPU timing of batched searches on this index, for roofline reports.

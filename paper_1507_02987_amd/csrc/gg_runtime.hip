@@ -1191,6 +1191,14 @@ gg_status gg_memcpy_to_device(void *dst, const void *src, uint64_t bytes)
     return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess ? GG_OK : GG_EDEVICE;
 }
 
+gg_status gg_device_copy(void *dst, const void *src, uint64_t bytes)
+{
+    if (bytes == 0) return GG_OK;
+    if (!dst || !src) return GG_EINVAL;
+    if (hipMemcpy(dst, src, bytes, hipMemcpyDeviceToDevice) != hipSuccess) return GG_EDEVICE;
+    return hipDeviceSynchronize() == hipSuccess ? GG_OK : GG_EDEVICE;
+}
+
 gg_status gg_memcpy_to_host(void *dst, const void *src, uint64_t bytes)
 {
     if (bytes == 0) return GG_OK;

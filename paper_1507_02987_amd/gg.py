@@ -27,7 +27,7 @@ STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 # Exported symbols of include/gg.h, in declaration order.
 SYMBOLS = ("gg_index_build", "gg_index_free", "gg_index_info", "gg_index_set_hit_budget",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
-           "gg_device_free", "gg_memcpy_to_device", "gg_memcpy_to_host",
+           "gg_device_free", "gg_memcpy_to_device", "gg_memcpy_to_host", "gg_device_copy",
            "gg_profile_enable", "gg_profile_read",
            "gg_server_create", "gg_serve_submit", "gg_serve_poll", "gg_server_destroy",
            "gg_strerror")
@@ -74,6 +74,7 @@ def lib():
         L.gg_device_free.argtypes = [i32, vp]
         L.gg_memcpy_to_device.argtypes = [vp, vp, u64]
         L.gg_memcpy_to_host.argtypes = [vp, vp, u64]
+        L.gg_device_copy.argtypes = [vp, vp, u64]
         L.gg_profile_enable.argtypes = [vp, i32]
         L.gg_profile_read.argtypes = [vp, C.c_char_p, vp, vp, vp]
         L.gg_server_create.argtypes = [vp, C.POINTER(Params), u64, i32, C.POINTER(vp)]
@@ -217,6 +218,11 @@ class DeviceBuffer:
         if rc != GG_OK:
             raise GGError(rc, "gg_memcpy_to_host")
         return a
+
+    def copy_from(self, other: "DeviceBuffer", nbytes: int):
+        rc = lib().gg_device_copy(self.ptr, other.ptr, int(nbytes))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_device_copy")
 
     def close(self):
         if getattr(self, "ptr", None) and self.ptr.value:
