@@ -210,8 +210,8 @@ def test_device_resident_form(ggo, c0):
 
 @pytest.mark.parametrize("grouping", ["probe", "bucket", "sort"])
 def test_grouping_strategies_agree(ggo, monkeypatch, grouping):
-    """Runs found by probing neighbour windows (default), by sorting hits in LDS
-    slices, or by global radix sorting are the same runs."""
+    """Runs found by probing neighbour windows, by sorting hits in LDS slices, or
+    by global radix sorting (the default) are the same runs."""
     G = gpu()
     db = synth.random_db(11, n_seqs=400, lmin=50, lmax=4000)
     qs = synth.random_queries(11, db, n=30, lmin=100, lmax=3000, frac_homolog=0.8,
