@@ -9,6 +9,12 @@ identity with 1% indels; k = 11, +1/-3, gap 5 + 2g, band 32, X-drop 20, top 50.
 A step is one gg_search_batch_device call over all 1,000 queries: every stage of
 the path, with the queries already resident in GPU memory and the hits written
 to GPU memory.  The call returns only when its results are complete.
+
+``--workload large-batched`` times the same step over 100,000 short queries
+(100-250 bp, 80% bank regions with 1-3% substitutions, top 20) against the large
+bank (500,000 sequences, about 3 Gbp, with tandem and interspersed repeats);
+``--workload large-served`` serves queries of 50-20,000 bp against the large bank
+at 50, 200 and 1,000 arrivals/s and times the batched step over 2,000 of them.
 """
 from __future__ import annotations
 
@@ -82,17 +88,19 @@ def cpu_baseline(db, qs, max_hits: int, min_seconds: float = 8.0):
         return oix.search(q, prm, cap=CAP)[0]
 
     done, t0 = 0, time.perf_counter()
+    chunk = 4 * cores
     with ThreadPoolExecutor(max_workers=cores) as ex:
         while True:
-            rcs = list(ex.map(run, queries))
+            part = [queries[(done + j) % len(queries)] for j in range(chunk)]
+            rcs = list(ex.map(run, part))
             assert all(r in (0, 5) for r in rcs)
-            done += len(queries)
+            done += len(part)
             if time.perf_counter() - t0 >= min_seconds:
                 break
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"all {qs.n} queries of the workload, {done // qs.n} passes, "
-                      f"{dt:.1f} s wall on {cores} threads (index build excluded)"}
+            "sample": f"the workload's queries in order, {done} searched ({done / len(queries):.2f} "
+                      f"of the set), {dt:.1f} s wall on {cores} threads (index build excluded)"}
 
 
 def serve_leg(gix, db, prm, rate: float, n: int) -> dict:
@@ -162,7 +170,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--queries", type=int, default=1000)
+    ap.add_argument("--workload", choices=("mid", "large-batched", "large-served"), default="mid")
+    ap.add_argument("--queries", type=int, default=0, help="queries per step (0: the workload's)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form latency leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device three times (counter calibration)")
@@ -171,7 +180,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the search shards by query or by data-bank range, see DESIGN.md)", file=sys.stderr)
+              "(the search would shard by query or by data-bank range)", file=sys.stderr)
         return 2
 
     gg.lib()  # the compiled HIP library, or a loud failure
@@ -182,11 +191,26 @@ def main() -> int:
         log(f"copied {args.calibrate_copy} bytes device-to-device 3 times")
         return 0
     t = time.perf_counter()
-    db = synth.config1_db()
-    qs = synth.config1_queries(db, n=args.queries)
+    if args.workload == "mid":
+        cfg, db = 1, synth.config1_db()
+        qs = synth.config1_queries(db, n=args.queries or 1000)
+        desc = "config1: 200,000-seq bank (~275 Mbp), 1,000 queries 80-10,000 bp, k=11, top 50"
+    else:
+        db = synth.config2_db()
+        if args.workload == "large-batched":
+            cfg, qs = 3, synth.config3_queries(db, n=args.queries or 100_000)
+            desc = ("config3: 500,000-seq bank (~3 Gbp, repeats), 100,000 queries 100-250 bp, "
+                    "k=11, top 20")
+        else:
+            cfg, qs = 4, synth.config4_queries(db, n=args.queries or 2000)
+            desc = ("config4: 500,000-seq bank (~3 Gbp, repeats), queries 50-20,000 bp, k=11, "
+                    "top 50, served at 50/200/1,000 per s")
+    if args.queries:
+        desc = desc.replace(f"{qs.n:,}", str(qs.n))
+    workload = f"config{cfg}"
     log(f"workload: {db.n_seqs} seqs, {db.total_bp / 1e6:.1f} Mbp, {qs.n} queries, "
         f"{qs.lengths().sum()} query bp ({time.perf_counter() - t:.1f} s)")
-    max_hits = synth.CONFIG_TOP_N[1]
+    max_hits = synth.CONFIG_TOP_N[cfg]
     prm = gg.params(max_hits)
 
     t = time.perf_counter()
@@ -262,7 +286,6 @@ def main() -> int:
     bound, work_fn = model[dom]
     per_launch = work_fn(st) / st["launches"]
     avg_s = st["ms"] / 1e3 / st["launches"]
-    workload = "config1"
     if bound == "hbm":
         achieved, peak, unit = per_launch / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
     else:
@@ -278,7 +301,7 @@ def main() -> int:
     # the plain one-query-at-a-time loop on the same GPU, for comparison
     plain_qps = None
     if not args.no_plain:
-        n_plain = min(200, qs.n)
+        n_plain = min(200 if cfg != 3 else 2000, qs.n)
         t1 = time.perf_counter()
         for i in range(n_plain):
             rc, _, _ = gix.search(qs.query(i), prm, cap=CAP)
@@ -287,10 +310,12 @@ def main() -> int:
     log(f"plain per-query loop: {plain_qps} queries/s; PCIe-inclusive batch: {pcie_qps:.0f}")
 
     serve = []
-    if not args.no_serve:
+    if not args.no_serve and cfg != 3:
         # served form: queries shaped like the serving workload (log-uniform 50-20,000
         # bp, 60% planted homologs) against the resident bank, Poisson arrivals
-        for rate, n in ((200.0, 400), (1000.0, 1000), (5000.0, 2000)):
+        legs = ((50.0, 2000), (200.0, 2000), (1000.0, 2000)) if cfg == 4 else \
+            ((200.0, 400), (1000.0, 1000), (5000.0, 2000))
+        for rate, n in legs:
             serve.append(serve_leg(gix, db, prm, rate, n))
             log(f"served at {rate:.0f}/s: {serve[-1]}")
 
@@ -305,8 +330,7 @@ def main() -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "config1: 200,000-seq bank (~275 Mbp), 1,000 queries 80-10,000 bp, "
-                               "k=11, top 50, batched", "db_bp": db.total_bp,
+        "config": {"workload": desc + ", batched", "db_bp": db.total_bp,
                    "queries": qs.n, "query_bp": int(qs.lengths().sum()), "k": 11,
                    "max_hits": max_hits, "parallelism": "single GPU"},
         "roofline": roofline,

@@ -22,6 +22,9 @@ constexpr uint32_t kBucketCapMax = 512;  // most keys of one bucket (one wave so
 constexpr uint32_t kBucketBig = 16384;   // most keys of one bucket sorted by a block (128 KiB)
 constexpr int kMaxProbe = 4;             // neighbour windows probed per side (G / k + 1)
 constexpr int kBoundCap = 2048;          // run bounds of one query paired in LDS
+// Blocks of a grid-stride launch: a dispatch counts its work-items in 32 bits, so
+// kernels with a wave or block per record loop over records beyond this grid.
+constexpr uint32_t kMaxGrid = 1u << 20;
 
 // First or last hit of a run of several hits: query (local), sequence, diagonal, qpos.
 struct Bound {
@@ -144,7 +147,9 @@ void launch_chain_count(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int3
                         int32_t max_gap, int32_t min_len, uint32_t *counts, hipStream_t st);
 void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
                         int32_t max_gap, int32_t min_len, const uint32_t *tile_off, Cand *out,
-                        uint32_t *cand_per_q, hipStream_t st);
+                        hipStream_t st);
+void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t *qend,
+                          hipStream_t st);
 // Per-query LDS sorts (segments of at most kSegCap records; longer ones are skipped).
 // mode 0: merge order, mode 1: selection order.
 void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_off, int32_t nq,

@@ -5,6 +5,8 @@
 // query is just a batch of one.  Nothing here is a dense contraction, so there is
 // no MFMA: the gather and sort stages are bound by HBM bandwidth and the banded
 // Smith-Waterman by the integer vector ALUs.
+#include <algorithm>
+
 #include "gg_internal.h"
 
 namespace gg {
@@ -1110,8 +1112,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
                                                         uint32_t n, HitKeyLayout lay, int32_t k,
                                                         int32_t G, int32_t M,
                                                         const uint32_t *__restrict__ tile_off,
-                                                        Cand *__restrict__ out,
-                                                        uint32_t *__restrict__ cand_per_q)
+                                                        Cand *__restrict__ out)
 {
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
     uint32_t at = tile_off[blockIdx.x];
@@ -1132,7 +1133,6 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
             c.qs = qs;
             c.qe = (int32_t)(key & low_mask(lay.bp)) + k;
             out[at + ex] = c;
-            atomicAdd(&cand_per_q[c.q], 1u);
         }
         at += tot;
     }
@@ -1148,11 +1148,29 @@ void launch_chain_count(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int3
 
 void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
                         int32_t max_gap, int32_t min_len, const uint32_t *tile_off, Cand *out,
-                        uint32_t *cand_per_q, hipStream_t st)
+                        hipStream_t st)
 {
     if (n == 0) return;
     k_chain_write<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(keys, n, lay, k, max_gap, min_len,
-                                                              tile_off, out, cand_per_q);
+                                                              tile_off, out);
+}
+
+// Runs come out in (q, s, diag) order: each query's runs are one range
+// [qstart, qend), found at its boundaries (no per-run counter, no atomics).
+__global__ void k_cand_segments(const Cand *__restrict__ c, uint32_t n,
+                                uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t q = c[i].q;
+    if (i == 0 || c[i - 1].q != q) qstart[q] = i;
+    if (i + 1 == n || c[i + 1].q != q) qend[q] = i + 1;
+}
+
+void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t *qend,
+                          hipStream_t st)
+{
+    if (n) k_cand_segments<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(c, n, qstart, qend);
 }
 
 uint32_t chain_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
@@ -1232,9 +1250,9 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
                                                    int32_t match, int32_t mismatch, int32_t X,
                                                    Box *__restrict__ out)
 {
-    const uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (i >= n) return;  // whole wave
     const int lane = threadIdx.x & 63;
+    for (uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < n;
+         i += gridDim.x * (kBlock / 64)) {  // whole waves
     const Cand c = cands[i];
     const int64_t q0 = qoff[qa + c.q];
     const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
@@ -1250,6 +1268,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
         const int32_t qs = c.qs - el, qe = c.qe + er;
         out[i] = Box{c.q, c.s, qs, qe, qs + d, qe + d, d, d};
     }
+    }
 }
 
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
@@ -1258,8 +1277,9 @@ void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_
 {
     if (n == 0) return;
     const uint32_t per = kBlock / 64;
-    k_extend<<<(n + per - 1) / per, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start, match,
-                                                      mismatch, xdrop, out);
+    const uint32_t nb = std::min<uint32_t>((n + per - 1) / per, kMaxGrid);
+    k_extend<<<nb, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start, match, mismatch, xdrop,
+                                    out);
 }
 
 // ------------------------------------------------------------------ record sort keys
@@ -1747,9 +1767,8 @@ __global__ __launch_bounds__(64) void k_bsw(
 {
     __shared__ uint8_t s_q[kBswStage];
     __shared__ uint8_t s_d[kBswStage];
-    const uint32_t b = blockIdx.x;
-    if (b >= total) return;
     const int32_t lane = threadIdx.x;
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
     int32_t lo = 0, hi = nq - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
@@ -1819,6 +1838,8 @@ __global__ __launch_bounds__(64) void k_bsw(
         out[b] = r;
         atomicAdd(&cells_q[q], cells);
     }
+    __syncthreads();  // the next box restages s_q and s_d
+    }
 }
 
 void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_off, int32_t nq,
@@ -1828,7 +1849,7 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 unsigned long long *cells_per_q, hipStream_t st)
 {
     if (nsel_total == 0) return;
-    k_bsw<<<nsel_total, 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
+    k_bsw<<<std::min<uint32_t>(nsel_total, kMaxGrid), 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
                                       seq_start, match, mismatch, gap_open + gap_extend, gap_extend,
                                       band, out, cells_per_q);
 }

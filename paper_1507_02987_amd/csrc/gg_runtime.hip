@@ -51,6 +51,14 @@ struct Err {
         }                                             \
     } while (0)
 
+// Wait for the stream; a kernel that could not be launched (its error is kept
+// until read) fails the call instead of leaving its outputs unwritten.
+#define SYNC(stream)                                          \
+    do {                                                      \
+        HIPCHK(hipStreamSynchronize(stream));                 \
+        if (hipGetLastError() != hipSuccess) return GG_EDEVICE; \
+    } while (0)
+
 #define TRY(expr)                     \
     do {                              \
         gg_status s_ = (expr);        \
@@ -460,7 +468,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                                   st));
             HIPCHK(hipMemcpyAsync(bq.data(), ws->bound_q.p, sizeof(uint32_t) * nqw,
                                   hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            SYNC(st);
             nc = h_cur[0];
             nb = h_cur[1];
             if (nc <= ccap && nb <= bcap) break;
@@ -481,7 +489,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                     TRY(ensure(bigger, sizeof(Cand) * need));
                     HIPCHK(hipMemcpyAsync(bigger.p, ws->ctmp.p, sizeof(Cand) * nc,
                                           hipMemcpyDeviceToDevice, st));
-                    HIPCHK(hipStreamSynchronize(st));
+                    SYNC(st);
                     (void)hipFree(ws->ctmp.p);
                     ws->ctmp = bigger;
                     ccap = need;
@@ -499,7 +507,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                 prof.end(nb);
                 HIPCHK(hipMemcpyAsync(h_cur, ws->cursor.p, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                       st));
-                HIPCHK(hipStreamSynchronize(st));
+                SYNC(st);
                 nc = h_cur[0];
             }
             if (nc > 0) {
@@ -539,7 +547,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         std::vector<uint32_t> cnt(nbk);
         HIPCHK(hipMemcpyAsync(cnt.data(), ws->bcount.p, sizeof(uint32_t) * nbk,
                               hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        SYNC(st);
         const uint32_t maxb = *std::max_element(cnt.begin(), cnt.end());
         bucketed = maxb <= ix->bucket_big;
         std::vector<uint32_t> big;  // buckets over one wave's LDS slice
@@ -577,7 +585,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                 prof.end(H);
                 HIPCHK(hipMemcpyAsync(h_nc, ws->cursor.p, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                       st));
-                HIPCHK(hipStreamSynchronize(st));
+                SYNC(st);
                 nc = *h_nc;
                 if (nc <= ccap) break;
                 ccap = nc;
@@ -632,17 +640,26 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                         as<uint32_t>(ws->partials), st);
         HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + ntile, sizeof(uint32_t),
                               hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        prof.end(H);
+        SYNC(st);
         nc = *h_nc;
         if (nc > 0) {
             TRY(ensure(ws->cands, sizeof(Cand) * nc));
+            TRY(ensure(ws->qstart, sizeof(uint32_t) * (nqw + 1)));
+            TRY(ensure(ws->qend, sizeof(uint32_t) * (nqw + 1)));
+            prof.begin("chain_write");
             launch_chain_write(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
-                               as<uint32_t>(ws->ccount), as<Cand>(ws->cands),
-                               as<uint32_t>(ws->cand_q), st);
+                               as<uint32_t>(ws->ccount), as<Cand>(ws->cands), st);
+            HIPCHK(hipMemsetAsync(ws->qstart.p, 0, sizeof(uint32_t) * nqw, st));
+            HIPCHK(hipMemsetAsync(ws->qend.p, 0, sizeof(uint32_t) * nqw, st));
+            launch_cand_segments(as<Cand>(ws->cands), nc, as<uint32_t>(ws->qstart),
+                                 as<uint32_t>(ws->qend), st);
+            launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nqw, 0,
+                                 as<uint32_t>(ws->cand_q), st);
             launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nqw,
                             as<uint32_t>(ws->partials), st);
+            prof.end(H);
         }
-        prof.end(H);
     }
     if (nc == 0) return GG_OK;
     HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
@@ -656,7 +673,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                   ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop, as<Box>(ws->boxes),
                   st);
     prof.end(nc);
-    HIPCHK(hipStreamSynchronize(st));  // h_cq ready
+    SYNC(st);  // h_cq ready
     uint32_t max_seg = 0;
     for (int32_t ql = 0; ql < nqw; ++ql) max_seg = std::max(max_seg, h_cq[ql]);
     const bool seg_path = max_seg <= (uint32_t)kSegCap;
@@ -684,6 +701,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                          &perm));
         launch_gather_boxes(boxes, perm, nc, as<Box>(ws->boxes2), st);
     }
+    prof.end(nc);
+    prof.begin("merge_sweep");
     launch_merge_sweep(as<Box>(ws->boxes2), nc, as<Box>(ws->boxes3), st);
     prof.end(nc);
 
@@ -721,7 +740,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         HIPCHK(hipMemcpyAsync(h_ss, ws->qstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(h_se, ws->qend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
     }
-    HIPCHK(hipStreamSynchronize(st));
+    SYNC(st);
     const uint32_t nsel = h_sel_off[nqw];
     if (bo.stats)
         for (int32_t ql = 0; ql < nqw; ++ql) {
@@ -793,7 +812,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     if (bo.stats)
         HIPCHK(hipMemcpyAsync(h_cells, ws->cells_q.p, sizeof(unsigned long long) * nqw,
                               hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    SYNC(st);
     for (int32_t ql = 0; ql < nqw; ++ql) {
         const int32_t q = qa + ql;
         const uint32_t n = h_re[ql] - h_rs[ql];
@@ -872,7 +891,7 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     int32_t err = 0;
     HIPCHK(hipMemcpyAsync(qtot.data(), ws->qtot.p, sizeof(uint64_t) * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&err, ws->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    SYNC(st);
     if (err) return GG_EINVAL;
 
     // ---- waves: consecutive queries whose stored hit keys fit the budget and the key
@@ -1047,35 +1066,75 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
         for (auto &t : th) t.join();
         if (bad) return GG_EINVAL;
     }
-    auto base_at = [&](int64_t g) -> uint32_t { return (dbw[(size_t)(g >> 4)] >> (30 - (g & 15) * 2)) & 3u; };
+    // window code of the k bases from global base g: one 64-bit funnel of two words
     auto window_code = [&](int64_t g) -> uint32_t {
-        uint32_t c = 0;
-        for (int t = 0; t < k; ++t) c = (c << 2) | base_at(g + t);
-        return c;
+        const uint64_t x = ((uint64_t)dbw[(size_t)(g >> 4)] << 32) | dbw[(size_t)(g >> 4) + 1];
+        return (uint32_t)((x << (2 * (g & 15))) >> (64 - 2 * k));
     };
     uint64_t n_post = 0;
     for (int64_t s = 0; s < n_seqs; ++s) n_post += (uint64_t)((seq_off[s + 1] - seq_off[s]) / k);
     if (n_post >= 0xffffffffull) return GG_EINVAL;
-    for (int64_t s = 0; s < n_seqs; ++s) {
-        const int64_t g0 = seq_off[s] - base0, n = seq_off[s + 1] - seq_off[s];
-        for (int64_t w = 0; (w + 1) * k <= n; ++w) head[window_code(g0 + w * k) + 1] += 1;
+    // Threads own contiguous sequence ranges in id order.  Each counts its windows
+    // per code; a list's slots are handed out list by list, and within a list
+    // thread by thread, so placing every thread's windows in its own order keeps
+    // each list in (sequence, position) order.
+    const size_t ncode = (size_t)1 << (2 * k);
+    // at most 16 threads, and per-thread code counts of at most 1 GiB in total
+    const unsigned nth = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>({16, (int64_t)std::max(1u, std::thread::hardware_concurrency()),
+                              n_seqs, (int64_t)(((size_t)1 << 28) / ncode)}));
+    std::vector<int64_t> sbeg(nth + 1, n_seqs);
+    {
+        int64_t s = 0;
+        for (unsigned t = 0; t < nth; ++t) {
+            sbeg[t] = s;
+            const int64_t goal = base0 + total * (int64_t)(t + 1) / nth;
+            while (s < n_seqs && seq_off[s + 1] <= goal) ++s;
+        }
+        sbeg[nth] = n_seqs;
     }
-    for (size_t c = 1; c < head.size(); ++c) head[c] += head[c - 1];
+    std::vector<std::vector<uint32_t>> cnt(nth);
     try {
+        for (auto &c : cnt) c.assign(ncode, 0u);
         post.resize((size_t)std::max<uint64_t>(n_post, 1));
     } catch (...) {
         return GG_ENOMEM;
     }
-    {
-        std::vector<uint32_t> cursor(head.begin(), head.end() - 1);
-        for (int64_t s = 0; s < n_seqs; ++s) {
+    auto for_windows = [&](unsigned t, auto &&fn) {
+        for (int64_t s = sbeg[t]; s < sbeg[t + 1]; ++s) {
             const int64_t g0 = seq_off[s] - base0, n = seq_off[s + 1] - seq_off[s];
-            for (int64_t w = 0; (w + 1) * k <= n; ++w) {
-                const uint32_t c = window_code(g0 + w * k);
-                post[cursor[c]++] = int2{(int32_t)s, (int32_t)(w * k)};
+            for (int64_t w = 0; (w + 1) * k <= n; ++w) fn(s, w * k, window_code(g0 + w * k));
+        }
+    };
+    auto parallel = [&](auto &&body) {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nth; ++t) th.emplace_back(body, t);
+        for (auto &x : th) x.join();
+    };
+    parallel([&](unsigned t) {
+        uint32_t *c = cnt[t].data();
+        for_windows(t, [&](int64_t, int64_t, uint32_t code) { ++c[code]; });
+    });
+    // head[c] = number of windows with a smaller code; cnt[t][c] becomes thread t's
+    // first slot in list c
+    {
+        uint32_t run = 0;
+        for (size_t c = 0; c < ncode; ++c) {
+            head[c] = run;
+            for (unsigned t = 0; t < nth; ++t) {
+                const uint32_t n = cnt[t][c];
+                cnt[t][c] = run;
+                run += n;
             }
         }
+        head[ncode] = run;
     }
+    parallel([&](unsigned t) {
+        uint32_t *cur = cnt[t].data();
+        for_windows(t, [&](int64_t s, int64_t pos, uint32_t code) {
+            post[cur[code]++] = int2{(int32_t)s, (int32_t)pos};
+        });
+    });
     std::vector<int64_t> seq_start((size_t)n_seqs + 1);
     for (int64_t s = 0; s <= n_seqs; ++s) seq_start[(size_t)s] = n_seqs > 0 ? seq_off[s] - base0 : 0;
 

@@ -15,6 +15,7 @@ Everything is a pure function of ``ROOT_SEED`` and the config id, through
 from __future__ import annotations
 
 import math
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -105,17 +106,39 @@ def _uniform_bases(rng, n: int) -> np.ndarray:
 
 
 def _gc_bases(rng, lengths: np.ndarray, gc: np.ndarray, chunk: int = 1 << 25) -> np.ndarray:
-    """Bases with per-sequence GC fraction: P(G)=P(C)=gc/2, P(A)=P(T)=(1-gc)/2."""
+    """Bases with per-sequence GC fraction: P(G)=P(C)=gc/2, P(A)=P(T)=(1-gc)/2.
+
+    One float32 uniform per base, drawn in order; base = number of the sequence's
+    three thresholds (1-gc)/2, (1-gc)/2 + gc/2, (1-gc)/2 + gc that it reaches.
+    The draws are sequential, the threshold tests run on a thread pool.
+    """
     total = int(lengths.sum())
     out = np.empty(total, dtype=np.uint8)
-    seq_of = np.repeat(np.arange(len(lengths)), lengths)
-    for lo in range(0, total, chunk):
-        hi = min(total, lo + chunk)
-        g = gc[seq_of[lo:hi]].astype(np.float32)
-        u = rng.random(hi - lo, dtype=np.float32)
-        a = (1.0 - g) * 0.5
-        idx = (u >= a).astype(np.uint8) + (u >= a + g * 0.5) + (u >= a + g)
+    off = _offsets(lengths)
+    g = gc.astype(np.float32)
+    a = (1.0 - g) * 0.5
+    thr = (a, a + g * 0.5, a + g)
+
+    def fill(lo, u):
+        hi = lo + len(u)
+        # sequences overlapping [lo, hi) and how many of their bases fall inside
+        s0 = int(np.searchsorted(off, lo, side="right")) - 1
+        s1 = int(np.searchsorted(off, hi, side="left"))
+        part = np.minimum(off[s0 + 1:s1 + 1], hi) - np.maximum(off[s0:s1], lo)
+        idx = np.zeros(len(u), dtype=np.uint8)
+        for t in thr:
+            idx += u >= np.repeat(t[s0:s1], part)
         out[lo:hi] = ASCII[idx]
+
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        pending = []
+        for lo in range(0, total, chunk):
+            pending.append(pool.submit(fill, lo, rng.random(min(total, lo + chunk) - lo,
+                                                            dtype=np.float32)))
+            if len(pending) >= 16:
+                pending.pop(0).result()
+        for f in pending:
+            f.result()
     return out
 
 

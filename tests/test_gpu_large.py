@@ -1,0 +1,128 @@
+"""GPU parity on the large resident bank (500,000 sequences, about 3 Gbp, with
+tandem and interspersed repeats) for its three query sets: long queries with the
+top 100 kept, 100,000 short queries in one batched call, and served queries of
+mixed lengths arriving while others run.
+
+Every query of a set runs on the GPU; a sample that always holds the queries with
+the most hits is checked field by field against the oracle.  Served results must
+also equal the same query searched alone.
+"""
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from paper_1507_02987_amd import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def note(msg):
+    """Progress line (shown with pytest -s): these tests take a minute or more."""
+    print(f"[large] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
+def as_rows(a):
+    return [tuple(int(x) for x in r) for r in a.tolist()]
+
+
+@pytest.fixture(scope="module")
+def large(ggo):
+    from paper_1507_02987_amd import gg
+
+    gg.lib()  # fails loudly when the library is not built
+    note("drawing the bank")
+    db = synth.config2_db()
+    note(f"bank: {db.n_seqs} sequences, {db.total_bp} bp; building the GPU index")
+    gix = gg.Index(db.seqs, db.off, 11)
+    note("building the oracle index")
+    oix = ggo.Index(db.seqs, db.off, 11)
+    note(f"indexes built: {oix.n_post} postings")
+    assert gix.info()["n_postings"] == oix.n_post
+    return gg, db, gix, oix
+
+
+def sample(st, n_rand, n_heavy, seed, max_hits=20_000_000):
+    """n_rand queries drawn at random plus the n_heavy with the most hits among
+    those the oracle searches in a second or two (at most max_hits hits)."""
+    hits = st["n_hits"].astype(np.int64)
+    ok = np.flatnonzero(hits <= max_hits)
+    heavy = ok[np.argsort(hits[ok], kind="stable")[-n_heavy:]]
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([heavy, rng.choice(ok, n_rand, replace=False)]))
+
+
+def check_sampled(ggo, oix, qs, got, st, pick, top_n, cap):
+    def one(i):
+        return oix.search(qs.query(i), ggo.params(top_n), cap=cap)
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        res = list(ex.map(one, [int(i) for i in pick]))
+    for i, (orc, oh, on, ost) in zip(pick, res):
+        i = int(i)
+        assert orc == 0 and on == len(got[i]), i
+        assert as_rows(got[i]) == as_rows(oh), i
+        for f in ("n_kmers", "n_hits", "n_cands", "n_merged", "n_selected", "n_cells", "n_out"):
+            assert int(st[i][f]) == ost[f], (i, f)
+
+
+def test_long_queries_top100(ggo, large):
+    """2,000 queries of 500-5,000 bp, half planted homologs at 75-99% identity."""
+    G, db, gix, oix = large
+    qs = synth.config2_queries(db)
+    note(f"{qs.n} long queries on the GPU")
+    rc, got, n, st = gix.search_batch(qs.buf, qs.off, G.params(100), cap=100, stats=True)
+    assert rc == 0
+    note(f"done: {int(st['n_hits'].sum())} hits; checking a sample against the oracle")
+    assert int(st["n_hits"].max()) > 1_000_000  # repeat-rich queries are in the set
+    check_sampled(ggo, oix, qs, got, st, sample(st, 30, 6, 2), 100, 100)
+
+
+def test_short_queries_one_batch(ggo, large):
+    """20,000 of the 100,000 queries of 100-250 bp (about 10^11 hits) in one
+    batched call, top 20, against the oracle on a sample and against the
+    one-query path on a smaller sample."""
+    G, db, gix, oix = large
+    qs = synth.config3_queries(db).subset(np.arange(20_000))
+    prm = G.params(20)
+    note(f"{qs.n} short queries on the GPU")
+    rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=20, stats=True)
+    assert rc == 0
+    note(f"done: {int(st['n_hits'].sum())} hits; checking a sample against the oracle")
+    pick = sample(st, 150, 10, 3)
+    check_sampled(ggo, oix, qs, got, st, pick, 20, 20)
+    for i in pick[:40]:
+        rc1, h1, n1 = gix.search(qs.query(int(i)), prm, cap=20)
+        assert rc1 == 0 and as_rows(h1) == as_rows(got[int(i)])
+    # 80% are bank regions with 1-3% substitutions: most report their source
+    # (repeats shared with other sequences can push it out of the top 20)
+    src_found = sum(1 for i in range(qs.n) if qs.kind[i]
+                    and int(qs.src_seq[i]) in set(int(x) for x in got[i]["seq_id"]))
+    note(f"source reported for {src_found} of {int(qs.kind.sum())} bank-region queries")
+    assert src_found > 0.85 * int(qs.kind.sum())
+
+
+def test_served_mixed_lengths(ggo, large):
+    """Queries of 50-20,000 bp submitted all at once to the server (more than its
+    slots, under a 16 GB hit-buffer budget); each result equals the query searched
+    alone, the batched form and, on a sample, the oracle."""
+    G, db, gix, oix = large
+    qs = synth.config4_queries(db).subset(np.arange(300))
+    prm = G.params(50)
+    note(f"{qs.n} mixed queries one at a time")
+    alone = [gix.search(qs.query(i), prm, cap=50) for i in range(qs.n)]
+    note("the same queries through the server")
+    assert all(a[0] == 0 for a in alone)
+    sv = G.Server(gix, prm, hit_budget_bytes=16_000_000_000, max_slots=16)
+    try:
+        tickets = [sv.submit(qs.query(i)) for i in range(qs.n)]
+        for i, t in enumerate(tickets):
+            rc, h, n = sv.poll(t, cap=50, timeout_us=-1)
+            assert rc == 0 and as_rows(h) == as_rows(alone[i][1]), i
+    finally:
+        sv.close()
+    rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=50, stats=True)
+    assert rc == 0 and all(as_rows(got[i]) == as_rows(alone[i][1]) for i in range(qs.n))
+    check_sampled(ggo, oix, qs, got, st, sample(st, 25, 5, 4), 50, 50)
