@@ -37,7 +37,7 @@ typedef enum {
     GG_EAGAIN = 4,    /* served query not finished yet */
     GG_ETRUNC = 5,    /* more hits than `cap`: the first `cap` are written, *n_out is the count */
     GG_ENOTFOUND = 6, /* unknown or already collected ticket */
-    GG_EBUDGET = 7    /* one query's hits do not fit the hit-buffer budget */
+    GG_EBUDGET = 7    /* one query's hits on one sequence do not fit the hit budget */
 } gg_status;
 
 typedef struct gg_index gg_index;   /* device-resident data bank and inverted index */
@@ -105,8 +105,11 @@ gg_status gg_index_info(const gg_index *index, int64_t *n_postings, int64_t *n_b
 
 /*
  * Device bytes the batched search may use for index hits at once (two 8-byte
- * keys per hit).  Queries are processed in waves that fit it; a single query
- * whose hits exceed it fails with GG_EBUDGET.  0 restores the default.
+ * keys per hit).  Queries are processed in waves that fit it.  A query whose
+ * hits exceed it alone is searched in pieces over ranges of data-bank sequence
+ * ids (every phase up to the alignment is per sequence, so the result is the
+ * same); it fails with GG_EBUDGET only if one sequence's hits exceed the budget.
+ * 0 restores the default, min(16 GiB, a quarter of free device memory).
  */
 gg_status gg_index_set_hit_budget(gg_index *index, uint64_t bytes);
 

@@ -92,6 +92,15 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
                       const int32_t *qid, const uint32_t *list_off, int32_t qa, int64_t g0,
                       int64_t g1, HitKeyLayout lay, uint32_t *hrel, uint32_t *pbase, uint64_t *akey,
                       hipStream_t st);
+// A query searched by pieces over ranges of sequence ids: below[y] += its hits on
+// sequences < bounds[y]; per-position sub-lists of the range [s_lo, s_hi).
+void launch_range_counts(const uint32_t *kcode, const uint32_t *cnt, int64_t np,
+                         const uint32_t *list_off, const int2 *post, const int32_t *bounds,
+                         int32_t nbounds, unsigned long long *below, hipStream_t st);
+void launch_piece_prep(const uint32_t *kcode, const uint32_t *cnt, int64_t np,
+                       const uint32_t *list_off, const int2 *post, int32_t s_lo, int32_t s_hi,
+                       HitKeyLayout lay, uint32_t *pcnt, uint32_t *pbase, uint64_t *akey,
+                       hipStream_t st);
 void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                    int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
                    uint64_t *keys, hipStream_t st);
@@ -180,7 +189,8 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 uint32_t nsel_total, const uint8_t *qcode, const int64_t *qoff, int32_t qa,
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
-                unsigned long long *cells_per_q, hipStream_t st);
+                unsigned long long *cells_per_q, unsigned long long *cells_per_box,
+                hipStream_t st);
 // Results of queries [qa, qa + nq) as gg_hit records (11 int32) in device memory.
 void launch_write_out(const Align *sorted, const uint32_t *rstart, const uint32_t *rend,
                       int32_t nq, int32_t qa, int32_t cap, int32_t *out, int32_t *n_out,

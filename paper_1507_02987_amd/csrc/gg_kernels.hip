@@ -299,6 +299,90 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
                                                              g0, np, lay, hrel, pbase, akey);
 }
 
+// ------------------------------------------------------------------ S3 by sequence range
+// A query whose hits overflow the per-call budget is searched in pieces, each over
+// a contiguous range of data-bank sequence ids.  Lists are in (seq, pos) order, so
+// the postings of sequences below s are a prefix of each list, found by binary
+// search.
+__device__ __forceinline__ uint32_t seq_lower_bound(const int2 *__restrict__ post, uint32_t lo,
+                                                    uint32_t hi, int32_t s)
+{
+    while (lo < hi) {
+        const uint32_t m = lo + ((hi - lo) >> 1);
+        if (post[m].x < s) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+// below[y] += hits of the query's positions [0, np) on sequences < bounds[y]
+// (block row y of the grid; cnt[p] is the full list length of position p).
+__global__ __launch_bounds__(kBlock) void k_range_counts(const uint32_t *__restrict__ kcode,
+                                                         const uint32_t *__restrict__ cnt,
+                                                         int64_t np,
+                                                         const uint32_t *__restrict__ list_off,
+                                                         const int2 *__restrict__ post,
+                                                         const int32_t *__restrict__ bounds,
+                                                         unsigned long long *__restrict__ below)
+{
+    const int32_t s = bounds[blockIdx.y];
+    unsigned long long c = 0;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * kBlock) {
+        const uint32_t n = cnt[p];
+        if (n == 0) continue;
+        const uint32_t lo = list_off[kcode[p]];
+        c += seq_lower_bound(post, lo, lo + n, s) - lo;
+    }
+    unsigned long long tot;
+    block_excl_scan<unsigned long long>(c, &tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(&below[blockIdx.y], tot);
+}
+
+void launch_range_counts(const uint32_t *kcode, const uint32_t *cnt, int64_t np,
+                         const uint32_t *list_off, const int2 *post, const int32_t *bounds,
+                         int32_t nbounds, unsigned long long *below, hipStream_t st)
+{
+    if (np <= 0 || nbounds <= 0) return;
+    const uint32_t gx = (uint32_t)std::min<int64_t>((np + kBlock - 1) / kBlock, 64);
+    k_range_counts<<<dim3(gx, (uint32_t)nbounds), kBlock, 0, st>>>(kcode, cnt, np, list_off, post,
+                                                                    bounds, below);
+}
+
+// Positions of one query restricted to sequences [s_lo, s_hi): per position the
+// start and length of its sub-list, and the constant part of its hit keys (the
+// query's index in the wave is 0).
+__global__ void k_piece_prep(const uint32_t *__restrict__ kcode, const uint32_t *__restrict__ cnt,
+                             int64_t np, const uint32_t *__restrict__ list_off,
+                             const int2 *__restrict__ post, int32_t s_lo, int32_t s_hi,
+                             HitKeyLayout lay, uint32_t *__restrict__ pcnt,
+                             uint32_t *__restrict__ pbase, uint64_t *__restrict__ akey)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const uint32_t n = cnt[p];
+    uint32_t a = 0, b = 0;
+    if (n) {
+        const uint32_t lo = list_off[kcode[p]];
+        a = seq_lower_bound(post, lo, lo + n, s_lo);
+        b = seq_lower_bound(post, a, lo + n, s_hi);
+    }
+    pbase[p] = a;
+    pcnt[p] = b - a;
+    const int32_t qpos = (int32_t)p;
+    akey[p] = ((uint64_t)(uint32_t)(lay.bias - qpos) << lay.bp) + (uint64_t)(uint32_t)qpos;
+}
+
+void launch_piece_prep(const uint32_t *kcode, const uint32_t *cnt, int64_t np,
+                       const uint32_t *list_off, const int2 *post, int32_t s_lo, int32_t s_hi,
+                       HitKeyLayout lay, uint32_t *pcnt, uint32_t *pbase, uint64_t *akey,
+                       hipStream_t st)
+{
+    if (np <= 0) return;
+    k_piece_prep<<<(uint32_t)((np + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        kcode, cnt, np, list_off, post, s_lo, s_hi, lay, pcnt, pbase, akey);
+}
+
 // Load-balanced over hits: block b owns hits [b*kTile, (b+1)*kTile) of the wave.
 // Consecutive threads take consecutive hits, so reads of one posting run and the
 // key writes are coalesced.  The owning position of hit j is the last p with
@@ -1763,7 +1847,7 @@ __global__ __launch_bounds__(64) void k_bsw(
     const uint8_t *__restrict__ qcode, const int64_t *__restrict__ qoff, int32_t qa,
     const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t match,
     int32_t mismatch, int32_t o1, int32_t ext, int32_t W, Align *__restrict__ out,
-    unsigned long long *__restrict__ cells_q)
+    unsigned long long *__restrict__ cells_q, unsigned long long *__restrict__ cells_box)
 {
     __shared__ uint8_t s_q[kBswStage];
     __shared__ uint8_t s_d[kBswStage];
@@ -1837,6 +1921,7 @@ __global__ __launch_bounds__(64) void k_bsw(
         r.box_len = min(R, C);
         out[b] = r;
         atomicAdd(&cells_q[q], cells);
+        if (cells_box) cells_box[b] = cells;
     }
     __syncthreads();  // the next box restages s_q and s_d
     }
@@ -1846,12 +1931,12 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 uint32_t nsel_total, const uint8_t *qcode, const int64_t *qoff, int32_t qa,
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
-                unsigned long long *cells_per_q, hipStream_t st)
+                unsigned long long *cells_per_q, unsigned long long *cells_per_box, hipStream_t st)
 {
     if (nsel_total == 0) return;
     k_bsw<<<std::min<uint32_t>(nsel_total, kMaxGrid), 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
                                       seq_start, match, mismatch, gap_open + gap_extend, gap_extend,
-                                      band, out, cells_per_q);
+                                      band, out, cells_per_q, cells_per_box);
 }
 
 // ------------------------------------------------------------------ results to device memory

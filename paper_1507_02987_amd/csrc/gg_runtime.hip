@@ -14,6 +14,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -105,7 +106,7 @@ struct Workspace {
     DevBuf cands, ccount, cand_q, cand_off, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
     DevBuf bplan, bcount, boff, bcands, btmp, bcoff, ctmp, cursor, qcur, bound_q, bound_off,
-        btmp_b, bounds, blist;
+        btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow;
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
     std::vector<hipEvent_t> events;
@@ -125,7 +126,8 @@ struct Workspace {
                          &ccount, &cand_q, &cand_off, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
                          &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
                          &cells_q, &bplan, &bcount, &boff, &bcands, &btmp, &bcoff, &ctmp, &cursor, &qcur,
-                         &bound_q, &bound_off, &btmp_b, &bounds, &blist};
+                         &bound_q, &bound_off, &btmp_b, &bounds, &blist, &pcnt, &cells_box,
+                         &rbounds, &rbelow};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -346,6 +348,17 @@ struct BatchOut {
     bool truncated = false;
 };
 
+// One query's search restricted to data-bank sequences [s_lo, s_hi) (used when
+// the query's hits overflow the per-call budget).  run_wave leaves the piece's
+// selected boxes, aligned and in selection order, with their in-band cell counts.
+struct Piece {
+    int32_t s_lo = 0, s_hi = 0;
+    uint64_t hits = 0;
+    uint32_t n_cands = 0, n_merged = 0;
+    std::vector<Align> sel;
+    std::vector<unsigned long long> cells;
+};
+
 // Run every GPU stage for queries [qa, qb) of the batch (one wave).
 // How index hits become runs (Section 2.2 phase 2): kProbe tests the windows next
 // to each hit and stores no hit; kBucket and kSort store every hit as a 64-bit key
@@ -362,7 +375,8 @@ Grouping grouping_from_env()
 
 gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
                    const std::vector<int64_t> &qoff_h, const std::vector<uint64_t> &qtot,
-                   int32_t qa, int32_t qb, BatchOut &bo, Grouping grouping)
+                   int32_t qa, int32_t qb, BatchOut &bo, Grouping grouping,
+                   Piece *piece = nullptr)
 {
     hipStream_t st = ws->st;
     const int32_t nqw = qb - qa;
@@ -373,7 +387,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         H64 += qtot[q];
         maxL = std::max<int64_t>(maxL, qoff_h[q + 1] - qoff_h[q]);
     }
-    for (int32_t q = qa; q < qb; ++q) {
+    if (piece) H64 = piece->hits;  // a piece is one query (qb == qa + 1)
+    for (int32_t q = qa; q < qb && !piece; ++q) {
         const int64_t L = qoff_h[q + 1] - qoff_h[q];
         if (bo.stats) {
             gg_stats &s = bo.stats[q];
@@ -383,7 +398,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         }
         if (!bo.device) bo.n_out[q] = 0;
     }
-    if (bo.device) HIPCHK(hipMemsetAsync(bo.n_out + qa, 0, sizeof(int32_t) * nqw, st));
+    if (bo.device && !piece) HIPCHK(hipMemsetAsync(bo.n_out + qa, 0, sizeof(int32_t) * nqw, st));
     if (H64 == 0) return GG_OK;
     const uint32_t H = (uint32_t)H64;
 
@@ -402,9 +417,20 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     TRY(ensure(ws->pbase, sizeof(uint32_t) * (np + 1)));
     TRY(ensure(ws->akey, sizeof(uint64_t) * (np + 1)));
     prof.begin("gather_prep");
-    launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
-                     as<int32_t>(ws->qid), ix->d_list_off, qa, g0, g1, lay, as<uint32_t>(ws->hrel),
-                     as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), st);
+    if (piece) {
+        TRY(ensure(ws->pcnt, sizeof(uint32_t) * (np + 1)));
+        launch_piece_prep(as<uint32_t>(ws->kcode) + g0, as<uint32_t>(ws->cnt) + g0, np,
+                          ix->d_list_off, ix->d_post, piece->s_lo, piece->s_hi, lay,
+                          as<uint32_t>(ws->pcnt), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
+                          st);
+        launch_scan_u32(as<uint32_t>(ws->pcnt), as<uint32_t>(ws->hrel), np,
+                        as<uint32_t>(ws->partials), st);
+    } else {
+        launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
+                         as<int32_t>(ws->qid), ix->d_list_off, qa, g0, g1, lay,
+                         as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
+                         st);
+    }
     prof.end(np);
 
     // pinned staging: run and bound counts[2] | runs per query[nqw] | sel_off[nqw+1] | sel start[nqw] |
@@ -736,17 +762,21 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                     as<uint32_t>(ws->partials), st);
     prof.end(nc);
     HIPCHK(hipMemcpyAsync(h_sel_off, ws->sel_off.p, sizeof(uint32_t) * n1, hipMemcpyDeviceToHost, st));
-    if (bo.stats) {
+    if (bo.stats || piece) {
         HIPCHK(hipMemcpyAsync(h_ss, ws->qstart.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(h_se, ws->qend.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
     }
     SYNC(st);
     const uint32_t nsel = h_sel_off[nqw];
-    if (bo.stats)
+    if (piece) {
+        piece->n_cands = h_cq[0];
+        piece->n_merged = h_se[0] - h_ss[0];
+    } else if (bo.stats) {
         for (int32_t ql = 0; ql < nqw; ++ql) {
             bo.stats[qa + ql].n_cands = h_cq[ql];
             bo.stats[qa + ql].n_merged = h_se[ql] - h_ss[ql];
         }
+    }
     if (nsel == 0) return GG_OK;
 
     // ---- S9 banded Smith-Waterman
@@ -754,12 +784,24 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     TRY(ensure(ws->aligns2, sizeof(Align) * nsel));
     TRY(ensure(ws->cells_q, sizeof(unsigned long long) * nqw));
     HIPCHK(hipMemsetAsync(ws->cells_q.p, 0, sizeof(unsigned long long) * nqw, st));
+    if (piece) TRY(ensure(ws->cells_box, sizeof(unsigned long long) * nsel));
     prof.begin("align");
     launch_bsw(as<Box>(ws->boxes2), as<uint32_t>(ws->qstart), as<uint32_t>(ws->sel_off), nqw, nsel,
                as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), qa, ix->d_dbw, ix->d_seq_start,
                p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, as<Align>(ws->aligns),
-               as<unsigned long long>(ws->cells_q), st);
+               as<unsigned long long>(ws->cells_q),
+               piece ? as<unsigned long long>(ws->cells_box) : nullptr, st);
     prof.end(nsel);
+    if (piece) {  // the piece's selection, in selection order, is its whole result
+        piece->sel.resize(nsel);
+        piece->cells.resize(nsel);
+        HIPCHK(hipMemcpyAsync(piece->sel.data(), ws->aligns.p, sizeof(Align) * nsel,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(piece->cells.data(), ws->cells_box.p,
+                              sizeof(unsigned long long) * nsel, hipMemcpyDeviceToHost, st));
+        SYNC(st);
+        return GG_OK;
+    }
 
     // ---- S10 report: score > 0 first, score desc, coordinates; per-query ranges
     uint32_t max_sel = 0;
@@ -838,6 +880,129 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     return GG_OK;
 }
 
+// Cut sequence ids [s_lo, s_hi) into ranges whose hits for query positions
+// [g0, g0 + np) stay within max_hits: hits below 256 evenly spaced ids are
+// counted on the GPU, ranges are grown greedily, and a span that is too big on
+// its own is cut again.  A single sequence over the budget cannot be cut.
+gg_status plan_pieces(const gg_index *ix, Workspace *ws, int64_t g0, int64_t np, int32_t s_lo,
+                      int32_t s_hi, uint64_t max_hits, std::vector<Piece> &out)
+{
+    constexpr int kBounds = 256;
+    hipStream_t st = ws->st;
+    std::vector<int32_t> b;
+    for (int i = 0; i <= kBounds; ++i) {
+        const int32_t v = s_lo + (int32_t)((int64_t)(s_hi - s_lo) * i / kBounds);
+        if (b.empty() || v != b.back()) b.push_back(v);
+    }
+    const int32_t nb = (int32_t)b.size();
+    TRY(ensure(ws->rbounds, sizeof(int32_t) * nb));
+    TRY(ensure(ws->rbelow, sizeof(unsigned long long) * nb));
+    std::vector<unsigned long long> below(nb);
+    HIPCHK(hipMemcpyAsync(ws->rbounds.p, b.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(ws->rbelow.p, 0, sizeof(unsigned long long) * nb, st));
+    launch_range_counts(as<uint32_t>(ws->kcode) + g0, as<uint32_t>(ws->cnt) + g0, np,
+                        ix->d_list_off, ix->d_post, as<int32_t>(ws->rbounds), nb,
+                        as<unsigned long long>(ws->rbelow), st);
+    HIPCHK(hipMemcpyAsync(below.data(), ws->rbelow.p, sizeof(unsigned long long) * nb,
+                          hipMemcpyDeviceToHost, st));
+    SYNC(st);
+    auto emit = [&](int32_t lo, int32_t hi, uint64_t h) {
+        if (h == 0) return;
+        Piece pc;
+        pc.s_lo = lo;
+        pc.s_hi = hi;
+        pc.hits = h;
+        out.push_back(std::move(pc));
+    };
+    int32_t a = 0;  // the open range starts at b[a]
+    for (int32_t i = 1; i < nb; ++i) {
+        if (below[i] - below[a] <= max_hits) continue;
+        if (i - 1 > a) {  // close the range before b[i] and test b[i] again
+            emit(b[a], b[i - 1], below[i - 1] - below[a]);
+            a = i - 1;
+            --i;
+            continue;
+        }
+        if (b[i] - b[a] == 1) return GG_EBUDGET;
+        TRY(plan_pieces(ix, ws, g0, np, b[a], b[i], max_hits, out));
+        a = i;
+    }
+    if (a < nb - 1) emit(b[a], b[nb - 1], below[nb - 1] - below[a]);
+    return GG_OK;
+}
+
+// Query q searched piece by piece.  Section 2.2's selection keeps the longest N
+// boxes of the query; the N longest overall are among the N longest of each
+// piece, so the pieces' selections are merged by the selection order, cut to N,
+// and then ordered for the report like any other query's alignments.
+gg_status search_pieces(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
+                        const std::vector<int64_t> &qoff_h, const std::vector<uint64_t> &qtot,
+                        int32_t q, uint64_t max_hits, BatchOut &bo, Grouping grouping)
+{
+    const int64_t g0 = qoff_h[q], L = qoff_h[q + 1] - g0;
+    std::vector<Piece> pieces;
+    TRY(plan_pieces(ix, ws, g0, L, 0, (int32_t)ix->n_seqs, max_hits, pieces));
+    std::vector<std::pair<Align, unsigned long long>> all;
+    int64_t n_cands = 0, n_merged = 0;
+    for (Piece &pc : pieces) {
+        TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, q, q + 1, bo, grouping, &pc));
+        prof.collect();
+        n_cands += pc.n_cands;
+        n_merged += pc.n_merged;
+        for (size_t i = 0; i < pc.sel.size(); ++i) all.emplace_back(pc.sel[i], pc.cells[i]);
+    }
+    auto sel_key = [](const Align &a) {
+        return std::make_tuple(-a.box_len, a.seq_id, a.box_q_start, a.box_d_start, a.box_q_end,
+                               a.box_d_end);
+    };
+    std::sort(all.begin(), all.end(),
+              [&](const auto &x, const auto &y) { return sel_key(x.first) < sel_key(y.first); });
+    if (p->max_hits > 0 && all.size() > (size_t)p->max_hits) all.resize((size_t)p->max_hits);
+    unsigned long long cells = 0;
+    std::vector<Align> rep;
+    for (const auto &x : all) {
+        cells += x.second;
+        if (x.first.score > 0) rep.push_back(x.first);
+    }
+    auto rep_key = [](const Align &a) {
+        return std::make_tuple(-a.score, a.seq_id, a.q_start, a.d_start, a.q_end, a.d_end,
+                               a.box_q_start, a.box_d_start, a.box_q_end, a.box_d_end);
+    };
+    std::sort(rep.begin(), rep.end(),
+              [&](const Align &x, const Align &y) { return rep_key(x) < rep_key(y); });
+    const int32_t n = (int32_t)rep.size();
+    const int32_t m = std::min(n, bo.cap);
+    if (n > bo.cap) bo.truncated = true;
+    std::vector<gg_hit> hits((size_t)std::max(m, 1));
+    for (int32_t r = 0; r < m; ++r) {
+        const Align &a = rep[(size_t)r];
+        hits[(size_t)r] = gg_hit{a.seq_id,      a.score,     a.q_start,     a.q_end,
+                                 a.d_start,     a.d_end,     a.box_q_start, a.box_q_end,
+                                 a.box_d_start, a.box_d_end, a.box_len};
+    }
+    if (bo.device) {
+        if (m > 0)
+            HIPCHK(hipMemcpyAsync(bo.out + (size_t)q * bo.cap, hits.data(), sizeof(gg_hit) * m,
+                                  hipMemcpyHostToDevice, ws->st));
+        HIPCHK(hipMemcpyAsync(bo.n_out + q, &n, sizeof(int32_t), hipMemcpyHostToDevice, ws->st));
+        SYNC(ws->st);
+    } else {
+        std::copy(hits.begin(), hits.begin() + m, bo.out + (size_t)q * bo.cap);
+        bo.n_out[q] = n;
+    }
+    if (bo.stats) {
+        gg_stats &s = bo.stats[q];
+        s.n_kmers = L >= ix->k ? L - ix->k + 1 : 0;
+        s.n_hits = (int64_t)qtot[q];
+        s.n_cands = n_cands;
+        s.n_merged = n_merged;
+        s.n_selected = (int64_t)all.size();
+        s.n_cells = (int64_t)cells;
+        s.n_out = n;
+    }
+    return GG_OK;
+}
+
 gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const int64_t *qoff,
                     int64_t nq, const gg_params *p, BatchOut &bo, uint64_t budget_bytes)
 {
@@ -900,15 +1065,18 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     const uint64_t max_hits = grouping == kProbe
                                   ? (uint64_t)INT32_MAX
                                   : std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
-    for (int64_t q = 0; q < nq; ++q)
-        if (qtot[q] > max_hits) return GG_EBUDGET;
     const int bs = bits_for((uint64_t)ix->n_seqs);
     int32_t qa = 0;
     while (qa < nq) {
+        if (qtot[qa] > max_hits) {  // searched alone, by ranges of sequences
+            TRY(search_pieces(ix, ws, prof, p, qoff_h, qtot, qa, max_hits, bo, grouping));
+            ++qa;
+            continue;
+        }
         uint64_t h = 0;
         int64_t maxL = 0;
         int32_t qb = qa;
-        while (qb < nq) {
+        while (qb < nq && qtot[qb] <= max_hits) {
             const uint64_t h2 = h + qtot[qb];
             const int64_t L2 = std::max<int64_t>(maxL, qoff_h[qb + 1] - qoff_h[qb]);
             const int bits = bits_for((uint64_t)L2) + bits_for((uint64_t)ix->max_seq_len + L2) + bs +

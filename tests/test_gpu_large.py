@@ -126,3 +126,26 @@ def test_served_mixed_lengths(ggo, large):
     rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=50, stats=True)
     assert rc == 0 and all(as_rows(got[i]) == as_rows(alone[i][1]) for i in range(qs.n))
     check_sampled(ggo, oix, qs, got, st, sample(st, 25, 5, 4), 50, 50)
+
+
+def test_served_set_over_budget_query(large):
+    """All 2,000 served-workload queries in one batched call under a 16 GB
+    hit-buffer budget: the largest (about 1.1 billion hits, over the budget) is
+    searched by ranges of sequences and equals the same query run in one piece
+    under a budget big enough for it."""
+    G, db, gix, oix = large
+    qs = synth.config4_queries(db)
+    prm = G.params(50)
+    gix.set_hit_budget(16_000_000_000)
+    try:
+        note(f"{qs.n} served-workload queries in one batched call")
+        rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=50, stats=True)
+        assert rc == 0
+        big = int(np.argmax(st["n_hits"]))
+        note(f"done; largest query {big}: {int(st['n_hits'][big])} hits")
+        assert int(st["n_hits"][big]) * 16 > 16_000_000_000
+        gix.set_hit_budget(40 << 30)
+        rc1, h1, n1 = gix.search(qs.query(big), prm, cap=50)
+        assert rc1 == 0 and as_rows(h1) == as_rows(got[big])
+    finally:
+        gix.set_hit_budget(0)

@@ -90,8 +90,9 @@ def test_scoring_variants(ggo, c0):
 
 
 def test_waves_under_small_budget(ggo, monkeypatch):
-    """With stored hits (radix-sort grouping), a tiny hit budget forces one query
-    per wave; results must not change."""
+    """With stored hits (radix-sort grouping), a small hit budget forces one query
+    per wave, then cuts the largest queries into ranges of sequences; results
+    must not change.  Only a single sequence over the budget is refused."""
     G = gpu()
     monkeypatch.setenv("GG_GROUPING", "sort")
     db = synth.config1_db(n_seqs=20_000)
@@ -102,9 +103,42 @@ def test_waves_under_small_budget(ggo, monkeypatch):
     hits = max(int(s["n_hits"]) for s in wst)
     gix.set_hit_budget(16 * hits)
     check_batch(G, gix, qs, G.params(50), want, wst)
-    gix.set_hit_budget(16 * (hits - 1))
+    gix.set_hit_budget(16 * (hits // 7))
+    check_batch(G, gix, qs, G.params(50), want, wst)
+    gix.set_hit_budget(16)
     rc, _, _, _ = gix.search_batch(qs.buf, qs.off, G.params(50))
     assert rc == G.GG_EBUDGET
+
+
+@pytest.mark.parametrize("grouping", ["probe", "bucket", "sort"])
+def test_pieces_by_sequence_range(ggo, monkeypatch, grouping):
+    """Queries over the hit budget are searched in ranges of sequence ids (with
+    every grouping strategy, all boxes kept or the top 3, host and device
+    results); the merged selection equals the unsplit oracle."""
+    G = gpu()
+    monkeypatch.setenv("GG_GROUPING", grouping)
+    db = synth.random_db(12, n_seqs=500, lmin=50, lmax=3000)
+    qs = synth.random_queries(12, db, n=24, lmin=100, lmax=2500, frac_homolog=0.8,
+                              ident_lo=0.85, ident_hi=1.0, indel_rate=0.01)
+    oix, gix = ggo.Index(db.seqs, db.off, 6), G.Index(db.seqs, db.off, 6)
+    for top in (3, 0):
+        want, wst = oracle_all(ggo, oix, qs, ggo.params(top))
+        hits = max(int(s["n_hits"]) for s in wst)
+        gix.set_hit_budget(16 * (hits // 9))
+        check_batch(G, gix, qs, G.params(top), want, wst)
+    cap = 4
+    dq = G.DeviceBuffer(len(qs.buf))
+    dq.upload(qs.buf)
+    dout = G.DeviceBuffer(qs.n * cap * G.HIT_DTYPE.itemsize)
+    dn = G.DeviceBuffer(qs.n * 4)
+    rc, st = gix.search_batch_device(dq, qs.off, G.params(0), dout, dn, cap, stats=True)
+    assert rc in (G.GG_OK, G.GG_ETRUNC)
+    n = dn.download(np.zeros(qs.n, np.int32))
+    got = dout.download(np.zeros(qs.n * cap, G.HIT_DTYPE))
+    for i in range(qs.n):
+        assert int(n[i]) == len(want[i])
+        m = min(cap, len(want[i]))
+        assert as_rows(got[i * cap: i * cap + m]) == as_rows(want[i][:m])
 
 
 def test_edge_cases(ggo, c0):
