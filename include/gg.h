@@ -114,6 +114,38 @@ gg_status gg_index_info(const gg_index *index, int64_t *n_postings, int64_t *n_b
 gg_status gg_index_set_hit_budget(gg_index *index, uint64_t bytes);
 
 /*
+ * Launch choices of an index; none changes a result, only the time to get it.
+ * grouping   : how index hits become runs (Section 2.2 phase 2):
+ *              0 probe the windows next to each hit (no hit stored),
+ *              1 sort hits in LDS slices of each query's sequence range,
+ *              2 radix-sort all hits of a wave (the default).
+ * lane_steps : X-drop steps (Section 2.2 phase 3) one lane takes before a whole
+ *              wave resumes the walk; 0..4096 (0: every walk by a wave), default 64.
+ * ms         : gg_index_autotune only: wall time of the sample batch with this
+ *              choice (best of its runs).
+ * The environment variable GG_GROUPING (probe, bucket, sort) overrides grouping.
+ */
+typedef struct {
+    int32_t grouping;
+    int32_t lane_steps;
+    double ms;
+} gg_tuning;
+
+gg_status gg_index_get_tuning(const gg_index *index, gg_tuning *out);
+gg_status gg_index_set_tuning(gg_index *index, const gg_tuning *tuning);
+
+/*
+ * Autotuner: search the sample batch (same layout as gg_search_batch) under every
+ * candidate choice (3 groupings x lane steps 0, 16, 64, 256), twice each, check that
+ * all choices return identical hits, and keep the fastest on the index.
+ * chosen (may be NULL) receives it.  Use queries shaped like the real workload;
+ * a few hundred are enough.  Errors: those of gg_search_batch, and GG_EDEVICE if
+ * two choices disagree (the previous choice is then kept).
+ */
+gg_status gg_index_autotune(gg_index *index, const char *queries, const int64_t *query_off,
+                            int64_t n_queries, const gg_params *params, gg_tuning *chosen);
+
+/*
  * Search one ASCII query (Section 2.2, all seven phases; forward strand only).
  * out/cap  : room for `cap` hits; *n_out receives the number found.  Hits are in
  *            descending score, then ascending (seq_id, q_start, d_start, q_end,

@@ -9,8 +9,10 @@ namespace gg {
 
 constexpr int32_t kNegInf = -(1 << 30);  // minus infinity of the alignment DP
 constexpr int kBlock = 256;              // threads per block for the stream kernels
-constexpr int kItems = 8;                // keys per thread in the radix passes
-constexpr int kTile = kBlock * kItems;   // keys per radix tile
+constexpr int kItems = 8;                // hits per thread in the gather and chain passes
+constexpr int kTile = kBlock * kItems;   // hits per gather / chain tile
+constexpr int kSortItems = 8;            // keys per thread in the radix passes
+constexpr int kSortTile = kBlock * kSortItems;  // keys per radix tile
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kGatherCap = 4096;         // positions of one gather tile kept in LDS
@@ -145,6 +147,18 @@ void launch_compact_cands(const Cand *tmp, const uint32_t *btmp, const uint32_t 
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                uint32_t n, int lo, int hi, uint32_t *hist, uint32_t *partials, hipStream_t st);
 size_t radix_hist_needed(uint32_t n);
+// One-sweep LSD sort of keys on bits [lo, hi), 8-bit digits: onesweep_prepare
+// counts the digits of every pass in one read, then onesweep_pass(p) scatters
+// pass p with look-back tile offsets (ping-pong buffers, like the passes above).
+// scratch holds onesweep_scratch_bytes(n); the failure flag (device u32) is
+// non-zero if a look-back wait ran out, and the result must then be discarded.
+size_t onesweep_scratch_bytes(uint32_t n);
+void onesweep_prepare(const uint64_t *keys, uint32_t n, int lo, int hi, void *scratch,
+                      hipStream_t st);
+void onesweep_pass(const uint64_t *kin, uint64_t *kout, uint32_t n, int lo, int pass,
+                   void *scratch, hipStream_t st);
+const uint32_t *onesweep_fail_flag(const void *scratch);
+void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 // The three kernels of one radix pass (digit histogram, its scan, stable scatter).
 void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st);
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st);
@@ -166,9 +180,12 @@ void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_
 void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int32_t nq,
                        uint32_t *rstart, uint32_t *rend, int32_t qa, int32_t cap, int32_t *dev_out,
                        int32_t *dev_n, hipStream_t st);
+// queue_mem: extend_queue_bytes(n) bytes of device scratch.
+size_t extend_queue_bytes(uint32_t n);
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
                    int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
-                   int32_t mismatch, int32_t xdrop, Box *out, hipStream_t st);
+                   int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
+                   int32_t lane_steps, hipStream_t st);
 void launch_box_keys(const Box *b, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
                      const uint32_t *perm, hipStream_t st);
 void launch_align_keys(const Align *a, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,

@@ -1009,9 +1009,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
     __shared__ uint32_t h[kRadix];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint32_t i = base + r * kBlock + threadIdx.x;
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
     }
@@ -1019,29 +1019,94 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
     hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-template <bool VALS>
+// One-sweep passes (no per-pass histogram kernel): a tile learns how many keys of
+// each digit the tiles before it hold by decoupled look-back over per-tile
+// descriptors [tag | flag | count] (tag = pass + 1, flag 1 = this tile's count,
+// 2 = count of every tile up to this one).  Tiles are numbered in start order by
+// a counter, so every tile waited on has started and publishes its own count
+// before it waits; each wait is still bounded, and running out sets *fail (the
+// pass's output is then invalid and the caller sorts again without look-back).
+struct Lookback {
+    unsigned long long *desc;  // [tiles][kRadix]
+    const uint32_t *base;      // [kRadix] keys of smaller digits in the whole input
+    uint32_t *counter;         // next tile number of this pass
+    uint32_t *fail;
+    uint32_t tag;
+};
+
+constexpr int kDescFlagShift = 58;
+constexpr int kDescTagShift = 60;
+constexpr unsigned long long kDescCount = (1ull << kDescFlagShift) - 1;
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ void desc_store(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long desc_load(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Keys of digit d in tiles before `tile` (thread d of the block; cnt = this tile's).
+__device__ uint32_t look_back(const Lookback &lb, uint32_t tile, uint32_t d, uint32_t cnt)
+{
+    unsigned long long *me = lb.desc + (size_t)tile * kRadix + d;
+    const unsigned long long tag = (unsigned long long)lb.tag << kDescTagShift;
+    if (tile == 0) {
+        desc_store(me, tag | (2ull << kDescFlagShift) | cnt);
+        return 0;
+    }
+    desc_store(me, tag | (1ull << kDescFlagShift) | cnt);
+    unsigned long long excl = 0;
+    int64_t j = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        const unsigned long long w = desc_load(lb.desc + (size_t)j * kRadix + d);
+        const uint32_t flag = (uint32_t)(w >> kDescFlagShift) & 3u;
+        if ((uint32_t)(w >> kDescTagShift) != lb.tag || flag == 0) {
+            if (++spins > kSpinLimit) {
+                atomicOr(lb.fail, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        excl += w & kDescCount;
+        if (flag == 2) break;
+        --j;
+    }
+    desc_store(me, tag | (2ull << kDescFlagShift) | (excl + cnt));
+    return (uint32_t)excl;
+}
+
+template <bool VALS, bool LB>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restrict__ kin,
                                                        const uint32_t *__restrict__ vin,
                                                        uint64_t *__restrict__ kout,
                                                        uint32_t *__restrict__ vout, uint32_t n,
                                                        int shift, const uint32_t *__restrict__ hist,
-                                                       uint32_t nb)
+                                                       uint32_t nb, Lookback lb)
 {
-    __shared__ uint64_t s_k[kTile];
-    __shared__ uint32_t s_v[VALS ? kTile : 1];
+    __shared__ uint64_t s_k[kSortTile];
+    __shared__ uint32_t s_v[VALS ? kSortTile : 1];
     __shared__ uint32_t s_wc[kBlock / 64][kRadix];
     __shared__ uint32_t s_start[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_tile;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < kBlock / 64; ++i) s_wc[i][threadIdx.x] = 0;
+    if (LB && threadIdx.x == 0) s_tile = atomicAdd(lb.counter, 1u);
     __syncthreads();
-    const uint32_t sub = blockIdx.x * (uint32_t)kTile + w * 64 * kItems;
+    const uint32_t tile = LB ? s_tile : blockIdx.x;
+    const uint32_t sub = tile * (uint32_t)kSortTile + w * 64 * kSortItems;
     const uint64_t below = (1ull << lane) - 1ull;
-    uint64_t k[kItems];
-    uint32_t v[kItems], rank[kItems];
+    uint64_t k[kSortItems];
+    uint32_t v[kSortItems], rank[kSortItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = sub + r * 64 + lane;
         const bool ok = idx < n;
         k[r] = ok ? kin[idx] : 0ull;
@@ -1071,11 +1136,14 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
         }
         uint32_t tot;
         s_start[d] = block_excl_scan<uint32_t>(run, &tot);
-        s_gbase[d] = hist[(size_t)d * nb + blockIdx.x];
+        if (LB)
+            s_gbase[d] = lb.base[d] + look_back(lb, tile, d, run);
+        else
+            s_gbase[d] = hist[(size_t)d * nb + tile];
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = sub + r * 64 + lane;
         if (idx < n) {
             const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
@@ -1085,9 +1153,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
         }
     }
     __syncthreads();
-    const uint32_t tn = min((uint32_t)kTile, n - blockIdx.x * (uint32_t)kTile);
+    const uint32_t tn = min((uint32_t)kSortTile, n - tile * (uint32_t)kSortTile);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint32_t i = r * kBlock + threadIdx.x;
         if (i < tn) {
             const uint64_t key = s_k[i];
@@ -1099,32 +1167,121 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
     }
 }
 
+// Digit counts of every pass in one read of the keys: hist[p][d] = keys whose
+// digit p (bits lo + 8p .. lo + 8p + 7) is d.
+__global__ __launch_bounds__(kBlock) void k_os_hist(const uint64_t *__restrict__ keys, uint32_t n,
+                                                    int lo, int passes,
+                                                    uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[8][kRadix];
+    for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const uint64_t key = keys[i];
+        for (int p = 0; p < passes; ++p)
+            atomicAdd(&h[p][(uint32_t)(key >> (lo + 8 * p)) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t c = h[p][threadIdx.x];
+        if (c) atomicAdd(&hist[p * kRadix + threadIdx.x], c);
+    }
+}
+
+// hist[p][d] -> keys of digits below d in pass p (one block).
+__global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t *__restrict__ hist, int passes)
+{
+    for (int p = 0; p < passes; ++p) {
+        uint32_t tot;
+        const uint32_t e = block_excl_scan<uint32_t>(hist[p * kRadix + threadIdx.x], &tot);
+        hist[p * kRadix + threadIdx.x] = e;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st)
+{
+    if (n == 0) return;
+    const size_t nb = std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+    k_fill_u32<<<(uint32_t)nb, kBlock, 0, st>>>(p, n, v);
+}
+
+// Scratch of a one-sweep sort of n keys: digit counts (8 passes x 256), tile
+// counters and the failure flag, then the descriptors.
+constexpr size_t kOsHead = (8 * kRadix + 64) * sizeof(uint32_t);
+
+size_t onesweep_scratch_bytes(uint32_t n)
+{
+    const size_t nt = (n + kSortTile - 1) / kSortTile;
+    return kOsHead + nt * kRadix * sizeof(unsigned long long);
+}
+
+void onesweep_prepare(const uint64_t *keys, uint32_t n, int lo, int hi, void *scratch,
+                      hipStream_t st)
+{
+    if (n == 0 || hi <= lo) return;
+    const int passes = (hi - lo + kRadixBits - 1) / kRadixBits;
+    uint32_t *hist = static_cast<uint32_t *>(scratch);
+    launch_fill_u32(hist, onesweep_scratch_bytes(n) / 4, 0u, st);
+    const uint32_t hb = std::min<uint32_t>((n + kBlock * 8 - 1) / (kBlock * 8), 4096);
+    k_os_hist<<<hb, kBlock, 0, st>>>(keys, n, lo, passes, hist);
+    k_os_scan<<<1, kBlock, 0, st>>>(hist, passes);
+}
+
+void onesweep_pass(const uint64_t *kin, uint64_t *kout, uint32_t n, int lo, int pass,
+                   void *scratch, hipStream_t st)
+{
+    if (n == 0) return;
+    uint32_t *hist = static_cast<uint32_t *>(scratch);
+    uint32_t *counters = hist + 8 * kRadix;  // [8], then the failure flag at [8]
+    auto *desc = reinterpret_cast<unsigned long long *>(static_cast<char *>(scratch) + kOsHead);
+    const uint32_t nt = (n + kSortTile - 1) / kSortTile;
+    const Lookback lb{desc, hist + pass * kRadix, counters + pass, counters + 8,
+                      (uint32_t)pass + 1};
+    k_rs_scatter<false, true><<<nt, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n,
+                                                     lo + kRadixBits * pass, nullptr, nt, lb);
+}
+
+const uint32_t *onesweep_fail_flag(const void *scratch)
+{
+    return static_cast<const uint32_t *>(scratch) + 8 * kRadix + 8;
+}
+
 size_t radix_hist_needed(uint32_t n)
 {
-    const size_t nb = (n + kTile - 1) / kTile;
+    const size_t nb = (n + kSortTile - 1) / kSortTile;
     return nb * kRadix + 1;
 }
 
 void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st)
 {
-    const uint32_t nb = (n + kTile - 1) / kTile;
+    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
     k_rs_hist<<<nb, kBlock, 0, st>>>(keys, n, shift, hist, nb);
 }
 
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st)
 {
-    const uint32_t nb = (n + kTile - 1) / kTile;
+    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
     scan_impl<uint32_t, uint32_t>(hist, hist, (int64_t)nb * kRadix, partials, st);
 }
 
 void launch_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout,
                        uint32_t n, int shift, const uint32_t *hist, hipStream_t st)
 {
-    const uint32_t nb = (n + kTile - 1) / kTile;
+    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+    const Lookback none{};
     if (vin)
-        k_rs_scatter<true><<<nb, kBlock, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nb);
+        k_rs_scatter<true, false><<<nb, kBlock, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nb,
+                                                         none);
     else
-        k_rs_scatter<false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n, shift, hist, nb);
+        k_rs_scatter<false, false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n, shift,
+                                                          hist, nb, none);
 }
 
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
@@ -1293,15 +1450,17 @@ __device__ __forceinline__ int32_t wave_max(int32_t x)
 }
 
 // Steps s = 0 .. T-1 score query base from + s (right) or from - 1 - s (left)
-// against data-bank base at the same query position + d.
+// against data-bank base at the same query position + d.  The walk may resume at
+// step t0 with its running sum, best sum and best step so far.
 template <bool RIGHT>
 __device__ __forceinline__ int32_t xdrop_side(const uint8_t *__restrict__ q,
                                               const uint32_t *__restrict__ dbw, int64_t s0,
                                               int32_t from, int32_t d, int32_t T, int32_t match,
-                                              int32_t mismatch, int32_t X, int lane)
+                                              int32_t mismatch, int32_t X, int lane,
+                                              int32_t t0 = 0, int32_t run = 0, int32_t best = 0,
+                                              int32_t bl = 0)
 {
-    int32_t run = 0, best = 0, bl = 0;
-    for (int32_t base = 0; base < T; base += 64) {
+    for (int32_t base = t0; base < T; base += 64) {
         const int32_t step = base + lane;
         const bool valid = step < T;
         int32_t v = 0;
@@ -1326,44 +1485,202 @@ __device__ __forceinline__ int32_t xdrop_side(const uint8_t *__restrict__ q,
     return bl;
 }
 
+// The same walk one step at a time in one lane, for at most `cap` steps (bases
+// read four steps ahead; the data-bank word is kept while the walk stays in it).
+// Returns true when the walk ended (drop over X, or the sequence or query end);
+// otherwise (t, run, best, bl) hold the state after `cap` steps.
+template <bool RIGHT>
+__device__ __forceinline__ bool xdrop_lane(const uint8_t *__restrict__ q,
+                                           const uint32_t *__restrict__ dbw, int64_t s0,
+                                           int32_t from, int32_t d, int32_t T, int32_t match,
+                                           int32_t mismatch, int32_t X, int32_t cap, int32_t &t,
+                                           int32_t &run, int32_t &best, int32_t &bl)
+{
+    t = 0;
+    run = 0;
+    best = 0;
+    bl = 0;
+    const int32_t end = min(T, cap);
+    int64_t wi = -1;
+    uint32_t word = 0;
+    while (t < end) {
+        int32_t qb[4], db[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            qb[u] = -1;
+            db[u] = -2;
+            if (t + u < end) {
+                const int32_t qi = RIGHT ? from + t + u : from - 1 - (t + u);
+                const int64_t g = s0 + qi + d;
+                if ((g >> 4) != wi) {
+                    wi = g >> 4;
+                    word = dbw[wi];
+                }
+                qb[u] = q[qi];
+                db[u] = (int32_t)((word >> (30u - ((uint32_t)(g & 15) << 1))) & 3u);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (t >= end) break;
+            run += qb[u] == db[u] ? match : -mismatch;
+            ++t;
+            if (run > best) {
+                best = run;
+                bl = t;
+            }
+            if (best - run > X) return true;
+        }
+    }
+    return t >= T;
+}
+
+// Extension in two kernels.  k_extend walks both sides of every run in one lane
+// for up to lane_steps steps (0: none), which ends most walks in random sequence;
+// the state of a walk still going is queued, and k_extend_long resumes each
+// queued walk with a whole wave, 64 steps at a time.  A full queue makes the lane
+// finish its own walk.
+struct XWalk {
+    uint32_t run_ix;  // index of the run; bit 31 set for the left side
+    int32_t t, run, best, bl;
+};
+
+// Queue slot of this lane's walk if `need` (one atomic per wave: the lanes that
+// need a slot take consecutive ones).
+__device__ __forceinline__ uint32_t queue_slot(bool need, uint32_t *__restrict__ qcount, int lane)
+{
+    const uint64_t m = __ballot(need);
+    if (m == 0) return 0;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(qcount, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cands, uint32_t n,
                                                    const uint8_t *__restrict__ qcode,
                                                    const int64_t *__restrict__ qoff, int32_t qa,
                                                    const uint32_t *__restrict__ dbw,
                                                    const int64_t *__restrict__ seq_start,
                                                    int32_t match, int32_t mismatch, int32_t X,
-                                                   Box *__restrict__ out)
+                                                   Box *__restrict__ out, XWalk *__restrict__ queue,
+                                                   uint32_t qcap, uint32_t *__restrict__ qcount,
+                                                   int32_t lane_steps)
 {
     const int lane = threadIdx.x & 63;
-    for (uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < n;
-         i += gridDim.x * (kBlock / 64)) {  // whole waves
-    const Cand c = cands[i];
-    const int64_t q0 = qoff[qa + c.q];
-    const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
-    const uint8_t *__restrict__ q = qcode + q0;
-    const int64_t s0 = seq_start[c.s];
-    const int32_t ns = (int32_t)(seq_start[c.s + 1] - s0);
-    const int32_t d = c.d;
-    const int32_t tr = min(L - c.qe, ns - (c.qe + d));
-    const int32_t tl = min(c.qs, c.qs + d);
-    const int32_t er = xdrop_side<true>(q, dbw, s0, c.qe, d, tr, match, mismatch, X, lane);
-    const int32_t el = xdrop_side<false>(q, dbw, s0, c.qs, d, tl, match, mismatch, X, lane);
-    if (lane == 0) {
-        const int32_t qs = c.qs - el, qe = c.qe + er;
-        out[i] = Box{c.q, c.s, qs, qe, qs + d, qe + d, d, d};
+    const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint32_t nwave = gridDim.x * (kBlock / 64);
+    // whole waves step through the runs together (the queue slots are per wave)
+    for (uint32_t i0 = wave * 64; i0 < n; i0 += nwave * 64) {
+        const uint32_t i = i0 + lane;
+        const bool valid = i < n;
+        Cand c{0, 0, 0, 0, 0};
+        if (valid) c = cands[i];
+        const int64_t q0 = qoff[qa + c.q];
+        const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
+        const uint8_t *__restrict__ q = qcode + q0;
+        const int64_t s0 = seq_start[c.s];
+        const int32_t ns = (int32_t)(seq_start[c.s + 1] - s0);
+        const int32_t d = c.d;
+        const int32_t tr = valid ? min(L - c.qe, ns - (c.qe + d)) : 0;
+        const int32_t tl = valid ? min(c.qs, c.qs + d) : 0;
+        int32_t t, run, best, bl;
+        bool done = xdrop_lane<true>(q, dbw, s0, c.qe, d, tr, match, mismatch, X, lane_steps, t,
+                                     run, best, bl);
+        uint32_t slot = queue_slot(!done, qcount, lane);
+        if (!done) {
+            if (slot < qcap) queue[slot] = XWalk{i, t, run, best, bl};
+            else xdrop_lane<true>(q, dbw, s0, c.qe, d, tr, match, mismatch, X, INT32_MAX, t, run,
+                                  best, bl);
+        }
+        const int32_t er = bl;
+        done = xdrop_lane<false>(q, dbw, s0, c.qs, d, tl, match, mismatch, X, lane_steps, t, run,
+                                 best, bl);
+        slot = queue_slot(!done, qcount, lane);
+        if (!done) {
+            if (slot < qcap) queue[slot] = XWalk{i | 0x80000000u, t, run, best, bl};
+            else xdrop_lane<false>(q, dbw, s0, c.qs, d, tl, match, mismatch, X, INT32_MAX, t, run,
+                                   best, bl);
+        }
+        const int32_t el = bl;
+        // a queued side is rewritten by k_extend_long (it owns qs/ds or qe/de)
+        if (valid) {
+            const int32_t qs = c.qs - el, qe = c.qe + er;
+            out[i] = Box{c.q, c.s, qs, qe, qs + d, qe + d, d, d};
+        }
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_extend_long(const Cand *__restrict__ cands,
+                                                        const uint8_t *__restrict__ qcode,
+                                                        const int64_t *__restrict__ qoff,
+                                                        int32_t qa,
+                                                        const uint32_t *__restrict__ dbw,
+                                                        const int64_t *__restrict__ seq_start,
+                                                        int32_t match, int32_t mismatch, int32_t X,
+                                                        Box *__restrict__ out,
+                                                        const XWalk *__restrict__ queue,
+                                                        uint32_t qcap,
+                                                        const uint32_t *__restrict__ qcount)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t nw = min(*qcount, qcap);
+    for (uint32_t e = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); e < nw;
+         e += gridDim.x * (kBlock / 64)) {  // whole waves
+        const XWalk w = queue[e];
+        const bool left = (w.run_ix >> 31) != 0;
+        const uint32_t i = w.run_ix & 0x7fffffffu;
+        const Cand c = cands[i];
+        const int64_t q0 = qoff[qa + c.q];
+        const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
+        const uint8_t *__restrict__ q = qcode + q0;
+        const int64_t s0 = seq_start[c.s];
+        const int32_t ns = (int32_t)(seq_start[c.s + 1] - s0);
+        const int32_t d = c.d;
+        if (left) {
+            const int32_t tl = min(c.qs, c.qs + d);
+            const int32_t el = xdrop_side<false>(q, dbw, s0, c.qs, d, tl, match, mismatch, X, lane,
+                                                 w.t, w.run, w.best, w.bl);
+            if (lane == 0) {
+                out[i].qs = c.qs - el;
+                out[i].ds = c.qs - el + d;
+            }
+        } else {
+            const int32_t tr = min(L - c.qe, ns - (c.qe + d));
+            const int32_t er = xdrop_side<true>(q, dbw, s0, c.qe, d, tr, match, mismatch, X, lane,
+                                                w.t, w.run, w.best, w.bl);
+            if (lane == 0) {
+                out[i].qe = c.qe + er;
+                out[i].de = c.qe + er + d;
+            }
+        }
     }
+}
+
+size_t extend_queue_bytes(uint32_t n)
+{
+    return sizeof(XWalk) * (size_t)std::min<uint32_t>(std::max<uint32_t>(n, 1u), 1u << 22) +
+           256;
 }
 
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
                    int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
-                   int32_t mismatch, int32_t xdrop, Box *out, hipStream_t st)
+                   int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
+                   int32_t lane_steps, hipStream_t st)
 {
     if (n == 0) return;
-    const uint32_t per = kBlock / 64;
-    const uint32_t nb = std::min<uint32_t>((n + per - 1) / per, kMaxGrid);
+    uint32_t *qcount = static_cast<uint32_t *>(queue_mem);
+    XWalk *queue = reinterpret_cast<XWalk *>(static_cast<char *>(queue_mem) + 256);
+    const uint32_t qcap = (uint32_t)((extend_queue_bytes(n) - 256) / sizeof(XWalk));
+    launch_fill_u32(qcount, 1, 0u, st);
+    const uint32_t nb = std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid);
     k_extend<<<nb, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start, match, mismatch, xdrop,
-                                    out);
+                                    out, queue, qcap, qcount, std::max(lane_steps, 0));
+    const uint64_t most = std::min<uint64_t>(2ull * n, qcap);  // queued walks at most
+    const uint32_t lb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((most + 3) / 4, 1u << 16));
+    k_extend_long<<<lb, kBlock, 0, st>>>(c, qcode, qoff, qa, dbw, seq_start, match, mismatch,
+                                         xdrop, out, queue, qcap, qcount);
 }
 
 // ------------------------------------------------------------------ record sort keys

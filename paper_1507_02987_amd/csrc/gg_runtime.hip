@@ -106,7 +106,7 @@ struct Workspace {
     DevBuf cands, ccount, cand_q, cand_off, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
     DevBuf bplan, bcount, boff, bcands, btmp, bcoff, ctmp, cursor, qcur, bound_q, bound_off,
-        btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow;
+        btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue;
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
     std::vector<hipEvent_t> events;
@@ -127,7 +127,7 @@ struct Workspace {
                          &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
                          &cells_q, &bplan, &bcount, &boff, &bcands, &btmp, &bcoff, &ctmp, &cursor, &qcur,
                          &bound_q, &bound_off, &btmp_b, &bounds, &blist, &pcnt, &cells_box,
-                         &rbounds, &rbelow};
+                         &rbounds, &rbelow, &os_scratch, &xqueue};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -155,6 +155,9 @@ struct gg_index {
     mutable std::mutex ws_mu;
     mutable std::vector<Workspace *> ws_free;
     std::atomic<int> prof_on{0};
+    // tuned launch choices (gg_index_autotune / gg_index_set_tuning)
+    std::atomic<int32_t> tune_grouping{2};
+    std::atomic<int32_t> tune_lane_steps{64};
     mutable std::mutex prof_mu;
     mutable std::map<std::string, StageTime> prof;
 };
@@ -365,12 +368,29 @@ struct Piece {
 // (q, s, diag, qpos) and sort them, by slices in LDS or by global radix passes.
 enum Grouping { kProbe = 0, kBucket = 1, kSort = 2 };
 
-Grouping grouping_from_env()
+// How the stored hit keys are sorted: a digit histogram and scan per pass
+// (default), or one-sweep passes with look-back tile offsets (GG_SORT=onesweep).
+// Look-back reads go to device-coherent memory across the chip's separate L2
+// caches, so a tile's walk over still-running predecessors is slow here: on
+// 13 M keys a one-sweep pass takes about 2.5x the time of the three kernels.
+enum SortKind { kClassic = 0, kOneSweep = 1 };
+
+SortKind sort_kind_from_env()
+{
+    const char *g = getenv("GG_SORT");
+    return (g && !strcmp(g, "onesweep")) ? kOneSweep : kClassic;
+}
+
+// GG_GROUPING (probe, bucket or sort) pins the strategy; otherwise the index's
+// tuned choice is used (sort until tuned).
+Grouping grouping_for(const gg_index *ix)
 {
     const char *g = getenv("GG_GROUPING");
     if (g && !strcmp(g, "probe")) return kProbe;
     if (g && !strcmp(g, "bucket")) return kBucket;
-    return kSort;
+    if (g && !strcmp(g, "sort")) return kSort;
+    const int32_t t = ix->tune_grouping.load();
+    return t == 0 ? kProbe : t == 1 ? kBucket : kSort;
 }
 
 gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
@@ -633,41 +653,64 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         TRY(ensure(ws->keys_alt, sizeof(uint64_t) * H));
         TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(H)));
         TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(H))));
-        prof.begin("gather");
-        launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), np,
-                      ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
-        prof.end(H);
         const int sort_lo = lay.bp, sort_hi = lay.bp + lay.bd + lay.bs + lay.bq;
-        uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
-        if (H > 1) {
-            for (int shift = sort_lo; shift < sort_hi; shift += kRadixBits) {
-                prof.begin("sort_hist");
-                launch_rs_hist(kcur, H, shift, as<uint32_t>(ws->hist), st);
-                prof.end(H);
-                prof.begin("sort_scan");
-                launch_rs_scan(as<uint32_t>(ws->hist), H, as<uint32_t>(ws->rs_partials), st);
-                prof.end(H);
-                prof.begin("sort_scatter");
-                launch_rs_scatter(kcur, nullptr, knext, nullptr, H, shift, as<uint32_t>(ws->hist),
-                                  st);
-                prof.end(H);
-                std::swap(kcur, knext);
-            }
-        }
-        const uint64_t *sorted = kcur;
+        const uint64_t *sorted = nullptr;
         const uint32_t ntile = chain_tiles(H);
         TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
         TRY(ensure(ws->partials,
                    sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nqw) + 1)));
-        prof.begin("chain");
-        launch_chain_count(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
-                           as<uint32_t>(ws->ccount), st);
-        launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount), ntile,
-                        as<uint32_t>(ws->partials), st);
-        HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + ntile, sizeof(uint32_t),
-                              hipMemcpyDeviceToHost, st));
-        prof.end(H);
-        SYNC(st);
+        const bool lookback = sort_kind_from_env() == kOneSweep;
+        if (lookback) TRY(ensure(ws->os_scratch, onesweep_scratch_bytes(H)));
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            // with one-sweep passes, a look-back wait that ran out sends the wave
+            // back to the gather and the per-pass histogram sort
+            const bool os = lookback && attempt == 0;
+            prof.begin("gather");
+            launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
+                          np, ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
+            prof.end(H);
+            uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
+            if (H > 1 && os) {
+                prof.begin("sort_hist");
+                onesweep_prepare(kcur, H, sort_lo, sort_hi, ws->os_scratch.p, st);
+                prof.end(H);
+                for (int pass = 0; sort_lo + kRadixBits * pass < sort_hi; ++pass) {
+                    prof.begin("sort_scatter");
+                    onesweep_pass(kcur, knext, H, sort_lo, pass, ws->os_scratch.p, st);
+                    prof.end(H);
+                    std::swap(kcur, knext);
+                }
+            } else if (H > 1) {
+                for (int shift = sort_lo; shift < sort_hi; shift += kRadixBits) {
+                    prof.begin("sort_hist");
+                    launch_rs_hist(kcur, H, shift, as<uint32_t>(ws->hist), st);
+                    prof.end(H);
+                    prof.begin("sort_scan");
+                    launch_rs_scan(as<uint32_t>(ws->hist), H, as<uint32_t>(ws->rs_partials), st);
+                    prof.end(H);
+                    prof.begin("sort_scatter");
+                    launch_rs_scatter(kcur, nullptr, knext, nullptr, H, shift,
+                                      as<uint32_t>(ws->hist), st);
+                    prof.end(H);
+                    std::swap(kcur, knext);
+                }
+            }
+            sorted = kcur;
+            prof.begin("chain");
+            launch_chain_count(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
+                               as<uint32_t>(ws->ccount), st);
+            launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount), ntile,
+                            as<uint32_t>(ws->partials), st);
+            HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + ntile, sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, st));
+            h_nc[1] = 0;
+            if (os && H > 1)
+                HIPCHK(hipMemcpyAsync(h_nc + 1, onesweep_fail_flag(ws->os_scratch.p),
+                                      sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            prof.end(H);
+            SYNC(st);
+            if (!(os && h_nc[1])) break;
+        }
         nc = *h_nc;
         if (nc > 0) {
             TRY(ensure(ws->cands, sizeof(Cand) * nc));
@@ -690,14 +733,15 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     if (nc == 0) return GG_OK;
     HIPCHK(hipMemcpyAsync(h_cq, ws->cand_q.p, sizeof(uint32_t) * nqw, hipMemcpyDeviceToHost, st));
 
-    // ---- S6 extend (one wave per run)
+    // ---- S6 extend (one lane per run, long walks resumed by a wave)
     TRY(ensure(ws->boxes, sizeof(Box) * nc));
     TRY(ensure(ws->boxes2, sizeof(Box) * nc));
     TRY(ensure(ws->boxes3, sizeof(Box) * nc));
+    TRY(ensure(ws->xqueue, extend_queue_bytes(nc)));
     prof.begin("extend");
     launch_extend(as<Cand>(ws->cands), nc, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), qa,
                   ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop, as<Box>(ws->boxes),
-                  st);
+                  ws->xqueue.p, ix->tune_lane_steps.load(), st);
     prof.end(nc);
     SYNC(st);  // h_cq ready
     uint32_t max_seg = 0;
@@ -1061,7 +1105,7 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
 
     // ---- waves: consecutive queries whose stored hit keys fit the budget and the key
     // bits (probing stores no hit: its waves are bounded only by 32-bit hit counts)
-    const Grouping grouping = grouping_from_env();
+    const Grouping grouping = grouping_for(ix);
     const uint64_t max_hits = grouping == kProbe
                                   ? (uint64_t)INT32_MAX
                                   : std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
@@ -1369,6 +1413,71 @@ gg_status gg_index_set_hit_budget(gg_index *ix, uint64_t bytes)
 {
     if (!ix) return GG_EINVAL;
     ix->hit_budget = bytes;
+    return GG_OK;
+}
+
+gg_status gg_index_get_tuning(const gg_index *ix, gg_tuning *out)
+{
+    if (!ix || !out) return GG_EINVAL;
+    out->grouping = ix->tune_grouping.load();
+    out->lane_steps = ix->tune_lane_steps.load();
+    out->ms = 0.0;
+    return GG_OK;
+}
+
+gg_status gg_index_set_tuning(gg_index *ix, const gg_tuning *t)
+{
+    if (!ix || !t || t->grouping < 0 || t->grouping > 2 || t->lane_steps < 0 ||
+        t->lane_steps > 4096)
+        return GG_EINVAL;
+    ix->tune_grouping = t->grouping;
+    ix->tune_lane_steps = t->lane_steps;
+    return GG_OK;
+}
+
+gg_status gg_index_autotune(gg_index *ix, const char *qbuf, const int64_t *qoff, int64_t n_q,
+                            const gg_params *params, gg_tuning *chosen)
+{
+    if (!ix || n_q < 1 || !qoff || !params) return GG_EINVAL;
+    const int32_t cap = params->max_hits > 0 ? params->max_hits : 256;
+    gg_tuning keep;
+    TRY(gg_index_get_tuning(ix, &keep));
+    std::vector<gg_hit> ref, out((size_t)n_q * cap);
+    std::vector<int32_t> ref_n, n_out((size_t)n_q);
+    gg_tuning best = keep;
+    best.ms = -1.0;
+    for (int32_t grouping = 0; grouping <= 2; ++grouping) {
+        for (int32_t steps : {0, 16, 64, 256}) {
+            const gg_tuning t{grouping, steps, 0.0};
+            TRY(gg_index_set_tuning(ix, &t));
+            double ms = -1.0;
+            for (int rep = 0; rep < 2; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                gg_status s = gg::search_batch_budget(ix, qbuf, qoff, n_q, params, out.data(), cap,
+                                                      n_out.data(), nullptr, gg::index_budget(ix),
+                                                      false);
+                const double dt = std::chrono::duration<double, std::milli>(
+                                      std::chrono::steady_clock::now() - t0)
+                                      .count();
+                if (s != GG_OK && s != GG_ETRUNC) {
+                    (void)gg_index_set_tuning(ix, &keep);
+                    return s;
+                }
+                ms = ms < 0 ? dt : std::min(ms, dt);
+            }
+            if (ref.empty()) {
+                ref = out;
+                ref_n = n_out;
+            } else if (ref_n != n_out ||
+                       memcmp(ref.data(), out.data(), sizeof(gg_hit) * out.size()) != 0) {
+                (void)gg_index_set_tuning(ix, &keep);
+                return GG_EDEVICE;
+            }
+            if (best.ms < 0 || ms < best.ms) best = gg_tuning{grouping, steps, ms};
+        }
+    }
+    TRY(gg_index_set_tuning(ix, &best));
+    if (chosen) *chosen = best;
     return GG_OK;
 }
 

@@ -26,6 +26,7 @@ STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 
 # Exported symbols of include/gg.h, in declaration order.
 SYMBOLS = ("gg_index_build", "gg_index_free", "gg_index_info", "gg_index_set_hit_budget",
+           "gg_index_get_tuning", "gg_index_set_tuning", "gg_index_autotune",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
            "gg_device_free", "gg_memcpy_to_device", "gg_memcpy_to_host", "gg_device_copy",
            "gg_profile_enable", "gg_profile_read",
@@ -42,6 +43,13 @@ class GGError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("match", "mismatch", "gap_open", "gap_extend", "band",
                                          "xdrop", "max_gap", "min_hsp_len", "max_hits")]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("grouping", C.c_int32), ("lane_steps", C.c_int32), ("ms", C.c_double)]
+
+
+GROUPINGS = ("probe", "bucket", "sort")
 
 
 def params(max_hits: int = 20, match: int = 1, mismatch: int = 3, gap_open: int = 5,
@@ -67,6 +75,9 @@ def lib():
         L.gg_index_free.restype = None
         L.gg_index_info.argtypes = [vp, vp, vp, vp, vp]
         L.gg_index_set_hit_budget.argtypes = [vp, u64]
+        L.gg_index_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.gg_index_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.gg_index_autotune.argtypes = [vp, vp, vp, i64, C.POINTER(Params), C.POINTER(Tuning)]
         L.gg_search.argtypes = [vp, vp, i64, C.POINTER(Params), vp, i32, vp]
         L.gg_search_batch.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, i32, vp, vp]
         L.gg_search_batch_device.argtypes = [vp, vp, vp, i64, C.POINTER(Params), vp, i32, vp, vp]
@@ -143,6 +154,31 @@ class Index:
         rc = lib().gg_index_set_hit_budget(self._h, int(nbytes))
         if rc != GG_OK:
             raise GGError(rc, "gg_index_set_hit_budget")
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        rc = lib().gg_index_get_tuning(self._h, C.byref(t))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_get_tuning")
+        return {"grouping": GROUPINGS[t.grouping], "lane_steps": t.lane_steps}
+
+    def set_tuning(self, grouping: str = "sort", lane_steps: int = 32):
+        t = Tuning(GROUPINGS.index(grouping), lane_steps, 0.0)
+        rc = lib().gg_index_set_tuning(self._h, C.byref(t))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_set_tuning")
+
+    def autotune(self, qbuf, qoff, prm: Params) -> dict:
+        """gg_index_autotune on a sample batch; returns the kept choice."""
+        q = _u8(qbuf)
+        off = np.ascontiguousarray(qoff, dtype=np.int64)
+        t = Tuning()
+        rc = lib().gg_index_autotune(self._h, _ptr(q) if len(q) else None, _ptr(off),
+                                     len(off) - 1, C.byref(prm), C.byref(t))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_autotune")
+        return {"grouping": GROUPINGS[t.grouping], "lane_steps": t.lane_steps,
+                "sample_ms": round(t.ms, 3)}
 
     def search(self, query, prm: Params, cap: int = 1024):
         """gg_search: returns (status, hits[:min(n, cap)], n)."""

@@ -242,10 +242,11 @@ def test_device_resident_form(ggo, c0):
         assert (rc == G.GG_ETRUNC) == any(len(w) > cap for w in want)
 
 
-@pytest.mark.parametrize("grouping", ["probe", "bucket", "sort"])
+@pytest.mark.parametrize("grouping", ["probe", "bucket", "sort", "sort-onesweep"])
 def test_grouping_strategies_agree(ggo, monkeypatch, grouping):
     """Runs found by probing neighbour windows, by sorting hits in LDS slices, or
-    by global radix sorting (the default) are the same runs."""
+    by global radix sorting (the default; per-pass histograms or one-sweep
+    look-back) are the same runs."""
     G = gpu()
     db = synth.random_db(11, n_seqs=400, lmin=50, lmax=4000)
     qs = synth.random_queries(11, db, n=30, lmin=100, lmax=3000, frac_homolog=0.8,
@@ -253,5 +254,31 @@ def test_grouping_strategies_agree(ggo, monkeypatch, grouping):
     oix, gix = ggo.Index(db.seqs, db.off, 8), G.Index(db.seqs, db.off, 8)
     for kw in (dict(), dict(max_gap=0, min_hsp_len=8), dict(max_gap=40, min_hsp_len=30)):
         want, wst = oracle_all(ggo, oix, qs, ggo.params(10, **kw))
-        monkeypatch.setenv("GG_GROUPING", grouping)
+        monkeypatch.setenv("GG_GROUPING", grouping.split("-")[0])
+        monkeypatch.setenv("GG_SORT", "onesweep" if grouping.endswith("onesweep") else "classic")
         check_batch(G, gix, qs, G.params(10, **kw), want, wst)
+
+
+def test_autotune_and_lane_steps(ggo, monkeypatch):
+    """The autotuner keeps one of its candidates, every candidate returned the same
+    hits (it checks), and the kept choice, like the extreme lane-step settings
+    (a wave resumes almost every walk / lanes finish every walk), equals the
+    oracle."""
+    G = gpu()
+    monkeypatch.delenv("GG_GROUPING", raising=False)
+    db = synth.config1_db(n_seqs=20_000)
+    qs = synth.config1_queries(db, n=80)
+    oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(50))
+    assert gix.tuning() == {"grouping": "sort", "lane_steps": 64}
+    got = gix.autotune(qs.buf, qs.off, G.params(50))
+    assert got["grouping"] in G.GROUPINGS and got["lane_steps"] in (0, 16, 64, 256)
+    assert got["sample_ms"] > 0
+    assert {k: gix.tuning()[k] for k in ("grouping", "lane_steps")} == {
+        k: got[k] for k in ("grouping", "lane_steps")}
+    check_batch(G, gix, qs, G.params(50), want, wst)
+    for steps in (0, 1, 4096):
+        gix.set_tuning("sort", steps)
+        check_batch(G, gix, qs, G.params(50), want, wst)
+    with pytest.raises(G.GGError):
+        gix.set_tuning("sort", -1)
