@@ -8,7 +8,8 @@ identity with 1% indels; k = 11, +1/-3, gap 5 + 2g, band 32, X-drop 20, top 50.
 
 A step is one gg_search_batch_device call over all 1,000 queries: every stage of
 the path, with the queries already resident in GPU memory and the hits written
-to GPU memory.  The call returns only when its results are complete.
+to GPU memory, its waves replayed from the library's captured HIP graph.  The
+call returns only when its results are complete.
 
 ``--workload large-batched`` times the same step over 100,000 short queries
 (100-250 bp, 80% bank regions with 1-3% substitutions, top 20) against the large
@@ -218,9 +219,11 @@ def main() -> int:
     build_s = time.perf_counter() - t
     log(f"index built on GPU 0 in {build_s:.1f} s: {gix.info()}")
 
-    # launch choices picked by the library's autotuner on a sample of the workload
+    # launch choices picked by the library's autotuner on the workload's batch (on
+    # its first 48 queries for the large workloads, whose batches take seconds)
     t = time.perf_counter()
-    sample = qs.subset(np.arange(min(200, qs.n)))
+    sample = qs if cfg == 1 else qs.subset(np.arange(min(48, qs.n)))
+    log(f"autotuning on {sample.n} queries ...")
     tuning = gix.autotune(sample.buf, sample.off, prm)
     log(f"autotuned on {sample.n} queries in {time.perf_counter() - t:.1f} s: {tuning}")
 
@@ -245,28 +248,50 @@ def main() -> int:
     qps = qs.n * args.steps / dt
     gbp_kbp = (db.total_bp / 1e9) * (qs.lengths().sum() / 1e3) * args.steps / dt
     log(f"timed {args.steps} steps: {dt * 1e3 / args.steps:.3f} ms/step, {qps:.0f} queries/s")
+    # the same steps with every wave launched kernel by kernel (no captured graph);
+    # the large workloads' queries exceed a graph wave, so they never use it
+    nograph_ms, graph_waves = None, 0
+    if args.workload == "mid":
+        os.environ["GG_GRAPH"] = "0"
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        nograph_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        del os.environ["GG_GRAPH"]
+        gix.profile(True)
+        step()
+        graph_waves = gix.profile_read("graph")["units"]
+        gix.profile(False)
+        log(f"without the wave graph: {nograph_ms:.3f} ms/step; graph waves per step: "
+            f"{graph_waves}")
 
-    # device results equal the host-buffer form (PCIe-inclusive rate measured here too)
-    got_n = dn.download(np.zeros(qs.n, np.int32))
-    got = dout.download(np.zeros(qs.n * CAP, gg.HIT_DTYPE))
-    t1 = time.perf_counter()
-    rc, res, n_host, stats = gix.search_batch(qs.buf, qs.off, prm, cap=CAP, stats=True)
-    pcie_qps = qs.n / (time.perf_counter() - t1)
-    assert rc in (gg.GG_OK, gg.GG_ETRUNC)
-    assert np.array_equal(got_n, n_host)
-    for i in range(qs.n):
-        m = min(int(n_host[i]), CAP)
-        assert got[i * CAP: i * CAP + m].tobytes() == res[i].tobytes(), i
+    # device results equal the host-buffer form (PCIe-inclusive rate measured here
+    # too); the large workloads skip this second full pass
+    pcie_qps = None
+    if args.workload == "mid":
+        got_n = dn.download(np.zeros(qs.n, np.int32))
+        got = dout.download(np.zeros(qs.n * CAP, gg.HIT_DTYPE))
+        t1 = time.perf_counter()
+        rc, res, n_host, _ = gix.search_batch(qs.buf, qs.off, prm, cap=CAP, stats=True)
+        pcie_qps = qs.n / (time.perf_counter() - t1)
+        assert rc in (gg.GG_OK, gg.GG_ETRUNC)
+        assert np.array_equal(got_n, n_host)
+        for i in range(qs.n):
+            m = min(int(n_host[i]), CAP)
+            assert got[i * CAP: i * CAP + m].tobytes() == res[i].tobytes(), i
 
     # per-kernel GPU time, HIP events on the library's stream, over profiled steps
+    nprof = 3 if args.workload == "mid" else 1
     gix.profile(True)
-    for _ in range(3):
-        step()
+    for _ in range(nprof):
+        rc, stats = gix.search_batch_device(dq, qs.off, prm, dout, dn, CAP, stats=True)
+        assert rc in (gg.GG_OK, gg.GG_ETRUNC)
     stages = {s: gix.profile_read(s) for s in (
         "encode", "scan", "gather_prep", "probe", "gather_count", "gather", "group", "sort_hist",
-        "sort_scan", "sort_scatter", "chain", "extend", "merge", "select", "align", "report")}
+        "sort_scan", "sort_scatter", "chain", "chain_write", "extend", "merge", "merge_sweep",
+        "select", "align", "report")}
     gix.profile(False)
-    step_ms = {s: v["ms"] / 3 for s, v in stages.items()}
+    step_ms = {s: v["ms"] / nprof for s, v in stages.items()}
     cells = int(stats["n_cells"].sum())
     hits = int(stats["n_hits"].sum())
     # Algorithmic work per launch of each modelled kernel:
@@ -282,7 +307,7 @@ def main() -> int:
         "gather": ("hbm", lambda st: 16 * st["units"]),
         "sort_scatter": ("hbm", lambda st: 16 * st["units"]),
         "sort_hist": ("hbm", lambda st: 8 * st["units"]),
-        "align": ("alu", lambda st: ALIGN_OPS_PER_CELL * cells / 3 * st["launches"]),
+        "align": ("alu", lambda st: ALIGN_OPS_PER_CELL * cells * nprof),
     }
     kernel_name = {"probe": "k_probe_chain", "gather": "k_gather", "sort_scatter": "k_rs_scatter",
                    "sort_hist": "k_rs_hist", "align": "k_bsw"}
@@ -302,7 +327,7 @@ def main() -> int:
                 "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_work_per_launch": int(per_launch)}
     al = stages["align"]
-    align_gcups = cells / (al["ms"] / 3 / 1e3) / 1e9 if al["ms"] > 0 else None
+    align_gcups = cells / (al["ms"] / nprof / 1e3) / 1e9 if al["ms"] > 0 else None
 
     # the plain one-query-at-a-time loop on the same GPU, for comparison
     plain_qps = None
@@ -313,7 +338,7 @@ def main() -> int:
             rc, _, _ = gix.search(qs.query(i), prm, cap=CAP)
             assert rc in (gg.GG_OK, gg.GG_ETRUNC)
         plain_qps = n_plain / (time.perf_counter() - t1)
-    log(f"plain per-query loop: {plain_qps} queries/s; PCIe-inclusive batch: {pcie_qps:.0f}")
+    log(f"plain per-query loop: {plain_qps} queries/s; PCIe-inclusive batch: {pcie_qps}")
 
     serve = []
     if not args.no_serve and cfg != 3:
@@ -344,9 +369,11 @@ def main() -> int:
         "extra": {
             "db_gbp_query_kbp_per_s": round(gbp_kbp, 2),
             "plain_per_query_qps": round(plain_qps, 1) if plain_qps else None,
-            "pcie_inclusive_batch_qps": round(pcie_qps, 1),
+            "pcie_inclusive_batch_qps": round(pcie_qps, 1) if pcie_qps else None,
             "index_build_s": round(build_s, 2),
             "tuning": tuning,
+            "graph_waves_per_step": graph_waves,
+            "ms_per_step_without_graph": round(nograph_ms, 4) if nograph_ms else None,
             "stage_ms_per_step": {s: round(v, 4) for s, v in step_ms.items()},
             "hits_per_step": hits,
             "align_cells_per_step": cells,

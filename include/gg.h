@@ -136,7 +136,9 @@ gg_status gg_index_set_tuning(gg_index *index, const gg_tuning *tuning);
 
 /*
  * Autotuner: search the sample batch (same layout as gg_search_batch) under every
- * candidate choice (3 groupings x lane steps 0, 16, 64, 256), twice each, check that
+ * candidate choice (3 groupings x lane steps 0, 16, 64, 256) after one untimed
+ * run, twice each (once if the first timed run takes over twice the best time so
+ * far), check that
  * all choices return identical hits, and keep the fastest on the index.
  * chosen (may be NULL) receives it.  Use queries shaped like the real workload;
  * a few hundred are enough.  Errors: those of gg_search_batch, and GG_EDEVICE if
@@ -193,14 +195,22 @@ gg_status gg_device_copy(void *dst, const void *src, uint64_t bytes);
 
 /*
  * Per-stage GPU timing of batched searches on this index, for roofline reports.
- * Enabling records HIP events around each stage on the stream it runs on.
- * Names: "encode", "scan", "gather_prep", "gather" (the posting-gather kernel
- * alone), "sort_hist", "sort_scan", "sort_scatter" (one mark per radix pass of the
- * hit sort), "chain", "extend", "merge", "select", "align" (the banded
- * Smith-Waterman kernel alone), "report".  ms is the summed GPU time between the
- * marks, launches the number of marks, units the work they covered (query bases
- * for encode and scan, positions for gather_prep, hits for gather, the sort marks and chain, runs
- * for extend/merge/select, boxes for align/report).
+ * Enabling (on or off) clears the totals; when on, HIP events are recorded around
+ * each stage on the stream it runs on.  Names: "encode", "scan", "gather_prep",
+ * "gather" (the posting-gather kernel alone), "sort_hist", "sort_scan",
+ * "sort_scatter" (one mark per radix pass of the hit sort), "chain" (run counts),
+ * "chain_write", "extend", "merge" (ordering for the sweep), "merge_sweep",
+ * "select", "align" (the banded Smith-Waterman kernel alone), "report", and
+ * "graph" (all replays of a batch's captured wave graph, whose kernels are not
+ * timed one by one: units = waves).  ms is the summed GPU time between the marks,
+ * launches the number of marks, units the work they covered (query bases for
+ * encode and scan, positions for gather_prep, hits for gather, the sort marks and
+ * the chain marks, runs for extend/merge/select, boxes for align/report).
+ *
+ * Batched calls without statistics, with the radix-sort grouping and 1 <= max_hits
+ * <= 1024, run each wave as a replay of one captured HIP graph (all waves after a
+ * single synchronisation; the graph is kept for later calls of the same shape).
+ * GG_GRAPH=0 in the environment turns this off.
  */
 gg_status gg_profile_enable(gg_index *index, int32_t on);
 gg_status gg_profile_read(const gg_index *index, const char *stage, double *ms,

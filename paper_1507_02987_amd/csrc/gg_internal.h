@@ -27,6 +27,7 @@ constexpr int kBoundCap = 2048;          // run bounds of one query paired in LD
 // Blocks of a grid-stride launch: a dispatch counts its work-items in 32 bits, so
 // kernels with a wave or block per record loop over records beyond this grid.
 constexpr uint32_t kMaxGrid = 1u << 20;
+constexpr uint32_t kStrideGrid = 2048;  // blocks of a graph's grid-stride kernels
 
 // First or last hit of a run of several hits: query (local), sequence, diagonal, qpos.
 struct Bound {
@@ -56,6 +57,21 @@ struct Align {
 struct HitKeyLayout {
     int bq, bs, bd, bp;  // field widths
     int32_t bias;        // added to the diagonal so that it is >= 0
+};
+
+// One wave of a graph-replayed batch, in device memory.  The host plans the waves
+// (qa .. bq, and the hit-key layout); k_wave_begin copies the next plan entry
+// here, and the kernels that produce the run and selection counts store them.
+// Kernels given a WaveCtl read their sizes from it instead of their arguments,
+// so one captured graph serves every wave.
+struct WaveCtl {
+    int32_t qa, nqw;  // first query of the wave, queries in it
+    int64_t g0, np;   // first base of the wave in the batch, bases
+    uint32_t H;       // hits
+    uint32_t nc;      // runs kept (written on the device)
+    HitKeyLayout lay;
+    uint32_t overflow;  // a query's runs or selections exceeded the per-query LDS sorts
+    uint32_t pad;
 };
 
 // Which box field feeds a sort-key field.
@@ -159,6 +175,25 @@ void onesweep_pass(const uint64_t *kin, uint64_t *kout, uint32_t n, int lo, int 
                    void *scratch, hipStream_t st);
 const uint32_t *onesweep_fail_flag(const void *scratch);
 void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
+
+// ---- graph-replayed waves: the kernels below read the wave's sizes from ctl;
+// grids are sized for the largest wave of the batch (hits_cap, np_cap, nq_cap).
+void launch_wave_begin(const WaveCtl *plan, uint32_t *cursor, WaveCtl *ctl, hipStream_t st);
+void launch_wave_end(const WaveCtl *ctl, const uint32_t *cursor, uint32_t *oflags, hipStream_t st);
+void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
+                          const int32_t *qid, const uint32_t *list_off, int64_t np_cap,
+                          uint32_t *hrel, uint32_t *pbase, uint64_t *akey, const WaveCtl *ctl,
+                          hipStream_t st);
+void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
+                       const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
+                       hipStream_t st);
+void launch_rs_pass_ctl(const uint64_t *kin, uint64_t *kout, uint32_t hits_cap, int pass,
+                        uint32_t *hist, uint32_t *partials, const WaveCtl *ctl, hipStream_t st);
+void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_t max_gap,
+                      int32_t min_len, uint32_t *counts, uint32_t *partials, Cand *out,
+                      WaveCtl *ctl, hipStream_t st);
+void launch_cand_segments_ctl(const Cand *c, uint32_t *qstart, uint32_t *qend, const WaveCtl *ctl,
+                              hipStream_t st);
 // The three kernels of one radix pass (digit histogram, its scan, stable scatter).
 void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st);
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st);
@@ -176,16 +211,17 @@ void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t 
 // Per-query LDS sorts (segments of at most kSegCap records; longer ones are skipped).
 // mode 0: merge order, mode 1: selection order.
 void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_off, int32_t nq,
-                         hipStream_t st);
+                         hipStream_t st, WaveCtl *ctl = nullptr);
 void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int32_t nq,
                        uint32_t *rstart, uint32_t *rend, int32_t qa, int32_t cap, int32_t *dev_out,
-                       int32_t *dev_n, hipStream_t st);
+                       int32_t *dev_n, hipStream_t st, WaveCtl *ctl = nullptr);
 // queue_mem: extend_queue_bytes(n) bytes of device scratch.
 size_t extend_queue_bytes(uint32_t n);
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
                    int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
                    int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
-                   int32_t lane_steps, hipStream_t st);
+                   int32_t lane_steps, hipStream_t st, const WaveCtl *ctl = nullptr,
+                   uint32_t n_cap = 0);
 void launch_box_keys(const Box *b, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
                      const uint32_t *perm, hipStream_t st);
 void launch_align_keys(const Align *a, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
@@ -195,19 +231,21 @@ void launch_gather_boxes(const Box *in, const uint32_t *perm, uint32_t n, Box *o
                          hipStream_t st);
 void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Align *out,
                           hipStream_t st);
-void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st);
+void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st,
+                        const WaveCtl *ctl = nullptr);
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
-                         uint32_t *qend, hipStream_t st);
+                         uint32_t *qend, hipStream_t st, const WaveCtl *ctl = nullptr);
 void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
                            uint32_t *qend, hipStream_t st);
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
-                          int32_t max_hits, uint32_t *nsel, hipStream_t st);
+                          int32_t max_hits, uint32_t *nsel, hipStream_t st,
+                          const WaveCtl *ctl = nullptr);
 void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_off, int32_t nq,
                 uint32_t nsel_total, const uint8_t *qcode, const int64_t *qoff, int32_t qa,
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
                 unsigned long long *cells_per_q, unsigned long long *cells_per_box,
-                hipStream_t st);
+                hipStream_t st, const WaveCtl *ctl = nullptr);
 // Results of queries [qa, qa + nq) as gg_hit records (11 int32) in device memory.
 void launch_write_out(const Align *sorted, const uint32_t *rstart, const uint32_t *rend,
                       int32_t nq, int32_t qa, int32_t cap, int32_t *out, int32_t *n_out,

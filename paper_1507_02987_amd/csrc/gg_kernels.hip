@@ -272,8 +272,15 @@ __global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__
                             const uint32_t *__restrict__ kcode, const int32_t *__restrict__ qid,
                             const uint32_t *__restrict__ list_off, int32_t qa, int64_t g0,
                             int64_t np, HitKeyLayout lay, uint32_t *__restrict__ hrel,
-                            uint32_t *__restrict__ pbase, uint64_t *__restrict__ akey)
+                            uint32_t *__restrict__ pbase, uint64_t *__restrict__ akey,
+                            const WaveCtl *__restrict__ ctl)
 {
+    if (ctl) {
+        qa = ctl->qa;
+        g0 = ctl->g0;
+        np = ctl->np;
+        lay = ctl->lay;
+    }
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p > np) return;
     const uint64_t hb = hoff[g0];
@@ -296,7 +303,19 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
     const int64_t np = g1 - g0;
     const int64_t nb = (np + 1 + kBlock - 1) / kBlock;
     k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, kcode, qid, list_off, qa,
-                                                             g0, np, lay, hrel, pbase, akey);
+                                                             g0, np, lay, hrel, pbase, akey,
+                                                             nullptr);
+}
+
+void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
+                          const int32_t *qid, const uint32_t *list_off, int64_t np_cap,
+                          uint32_t *hrel, uint32_t *pbase, uint64_t *akey, const WaveCtl *ctl,
+                          hipStream_t st)
+{
+    const int64_t nb = (np_cap + 1 + kBlock - 1) / kBlock;
+    k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, kcode, qid, list_off, 0, 0,
+                                                             0, HitKeyLayout{}, hrel, pbase, akey,
+                                                             ctl);
 }
 
 // ------------------------------------------------------------------ S3 by sequence range
@@ -399,13 +418,21 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     const uint64_t *__restrict__ akey, int64_t np, const int2 *__restrict__ post, uint32_t nhits,
     int sh_s, int sh_d, int sh_q, int bs, uint64_t *__restrict__ keys,
     const uint32_t *__restrict__ bb, const uint32_t *__restrict__ nbq,
-    uint32_t *__restrict__ bcount, const uint32_t *__restrict__ boff)
+    uint32_t *__restrict__ bcount, const uint32_t *__restrict__ boff,
+    const WaveCtl *__restrict__ ctl)
 {
     __shared__ uint32_t s_h[kGatherCap + 1];
     __shared__ uint32_t s_bin[kBinCap];
     __shared__ int64_t s_lo, s_hi;
     __shared__ uint32_t s_b0, s_nbin;
+    if (MODE == 0 && ctl) {
+        np = ctl->np;
+        nhits = ctl->H;
+        sh_s = ctl->lay.bp + ctl->lay.bd;
+        sh_d = ctl->lay.bp;
+    }
     const uint32_t t0 = blockIdx.x * (uint32_t)kTile;
+    if (t0 >= nhits) return;  // a graph's grid covers the largest wave
     const uint32_t t1 = min(t0 + (uint32_t)kTile, nhits);
     if (threadIdx.x == 0) {
         int64_t a = 0, b = np - 1;
@@ -509,7 +536,17 @@ void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *
     if (nhits == 0) return;
     const uint32_t nb = (nhits + kTile - 1) / kTile;
     k_gather<0><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
-                                       lay.bp, 64, 0, keys, nullptr, nullptr, nullptr, nullptr);
+                                       lay.bp, 64, 0, keys, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr);
+}
+
+void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
+                       const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
+                       hipStream_t st)
+{
+    const uint32_t nb = std::max<uint32_t>(1, (hits_cap + kTile - 1) / kTile);
+    k_gather<0><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, 0, post, 0, 0, 0, 64, 0, keys, nullptr,
+                                       nullptr, nullptr, nullptr, ctl);
 }
 
 void launch_gather_bucket(int mode, const uint32_t *hrel, const uint32_t *pbase,
@@ -522,10 +559,12 @@ void launch_gather_bucket(int mode, const uint32_t *hrel, const uint32_t *pbase,
     const int sh_q = lay.bp + lay.bd + lay.bs;
     if (mode == 1)
         k_gather<1><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
-                                           lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff);
+                                           lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff,
+                                           nullptr);
     else
         k_gather<2><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
-                                           lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff);
+                                           lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff,
+                                           nullptr);
 }
 
 // ------------------------------------------------------------------ S4+S5 per bucket
@@ -1004,9 +1043,13 @@ void launch_group_by_query(const Cand *in, uint32_t n, const uint32_t *qoff_c, u
 // global writes of each digit run are contiguous.
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys, uint32_t n,
                                                     int shift, uint32_t *__restrict__ hist,
-                                                    uint32_t nb)
+                                                    uint32_t nb, const WaveCtl *__restrict__ ctl)
 {
     __shared__ uint32_t h[kRadix];
+    if (ctl) {  // shift holds the pass number; tiles past the wave's keys count zeros
+        n = ctl->H;
+        shift = ctl->lay.bp + kRadixBits * shift;
+    }
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
@@ -1087,8 +1130,14 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
                                                        uint64_t *__restrict__ kout,
                                                        uint32_t *__restrict__ vout, uint32_t n,
                                                        int shift, const uint32_t *__restrict__ hist,
-                                                       uint32_t nb, Lookback lb)
+                                                       uint32_t nb, Lookback lb,
+                                                       const WaveCtl *__restrict__ ctl)
 {
+    if (ctl) {  // shift holds the pass number
+        n = ctl->H;
+        shift = ctl->lay.bp + kRadixBits * shift;
+        if (blockIdx.x * (uint32_t)kSortTile >= n) return;  // the grid covers the largest wave
+    }
     __shared__ uint64_t s_k[kSortTile];
     __shared__ uint32_t s_v[VALS ? kSortTile : 1];
     __shared__ uint32_t s_wc[kBlock / 64][kRadix];
@@ -1198,6 +1247,37 @@ __global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t *__restrict__ hist,
     }
 }
 
+// First and last node of a replayed wave graph: take the next planned wave, and
+// record whether it overflowed the per-query LDS sorts.
+__global__ void k_wave_begin(const WaveCtl *__restrict__ plan, uint32_t *__restrict__ cursor,
+                             WaveCtl *__restrict__ ctl)
+{
+    const uint32_t w = *cursor;
+    *ctl = plan[w];
+    *cursor = w + 1;
+}
+
+__global__ void k_wave_end(const WaveCtl *__restrict__ ctl, const uint32_t *__restrict__ cursor,
+                           uint32_t *__restrict__ oflags)
+{
+    oflags[*cursor - 1] = ctl->overflow;
+}
+
+void launch_wave_begin(const WaveCtl *plan, uint32_t *cursor, WaveCtl *ctl, hipStream_t st)
+{
+    k_wave_begin<<<1, 1, 0, st>>>(plan, cursor, ctl);
+}
+
+void launch_wave_end(const WaveCtl *ctl, const uint32_t *cursor, uint32_t *oflags, hipStream_t st)
+{
+    k_wave_end<<<1, 1, 0, st>>>(ctl, cursor, oflags);
+}
+
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst)
+{
+    *dst = *src;
+}
+
 __global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1245,7 +1325,8 @@ void onesweep_pass(const uint64_t *kin, uint64_t *kout, uint32_t n, int lo, int 
     const Lookback lb{desc, hist + pass * kRadix, counters + pass, counters + 8,
                       (uint32_t)pass + 1};
     k_rs_scatter<false, true><<<nt, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n,
-                                                     lo + kRadixBits * pass, nullptr, nt, lb);
+                                                     lo + kRadixBits * pass, nullptr, nt, lb,
+                                                     nullptr);
 }
 
 const uint32_t *onesweep_fail_flag(const void *scratch)
@@ -1262,7 +1343,7 @@ size_t radix_hist_needed(uint32_t n)
 void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st)
 {
     const uint32_t nb = (n + kSortTile - 1) / kSortTile;
-    k_rs_hist<<<nb, kBlock, 0, st>>>(keys, n, shift, hist, nb);
+    k_rs_hist<<<nb, kBlock, 0, st>>>(keys, n, shift, hist, nb, nullptr);
 }
 
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st)
@@ -1278,10 +1359,24 @@ void launch_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
     const Lookback none{};
     if (vin)
         k_rs_scatter<true, false><<<nb, kBlock, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nb,
-                                                         none);
+                                                         none, nullptr);
     else
         k_rs_scatter<false, false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n, shift,
-                                                          hist, nb, none);
+                                                          hist, nb, none, nullptr);
+}
+
+// One radix pass of a graph-replayed wave: n and the shift come from the wave
+// (digit `pass` above the qpos bits); the tiles and histogram layout are those of
+// hits_cap keys.
+void launch_rs_pass_ctl(const uint64_t *kin, uint64_t *kout, uint32_t hits_cap, int pass,
+                        uint32_t *hist, uint32_t *partials, const WaveCtl *ctl, hipStream_t st)
+{
+    const uint32_t nb = std::max<uint32_t>(1, (hits_cap + kSortTile - 1) / kSortTile);
+    k_rs_hist<<<nb, kBlock, 0, st>>>(kin, 0, pass, hist, nb, ctl);
+    launch_rs_scan(hist, hits_cap, partials, st);
+    const Lookback none{};
+    k_rs_scatter<false, false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, 0, pass, hist,
+                                                      nb, none, ctl);
 }
 
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
@@ -1334,8 +1429,13 @@ __device__ __forceinline__ bool chain_end(const uint64_t *__restrict__ keys, uin
 
 __global__ __launch_bounds__(kBlock) void k_chain_count(const uint64_t *__restrict__ keys,
                                                         uint32_t n, int bp, int32_t k, int32_t G,
-                                                        int32_t M, uint32_t *__restrict__ counts)
+                                                        int32_t M, uint32_t *__restrict__ counts,
+                                                        const WaveCtl *__restrict__ ctl)
 {
+    if (ctl) {  // tiles past the wave's hits count zero runs
+        n = ctl->H;
+        bp = ctl->lay.bp;
+    }
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
     uint32_t c = 0;
 #pragma unroll
@@ -1353,9 +1453,15 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
                                                         uint32_t n, HitKeyLayout lay, int32_t k,
                                                         int32_t G, int32_t M,
                                                         const uint32_t *__restrict__ tile_off,
-                                                        Cand *__restrict__ out)
+                                                        Cand *__restrict__ out,
+                                                        const WaveCtl *__restrict__ ctl)
 {
+    if (ctl) {
+        n = ctl->H;
+        lay = ctl->lay;
+    }
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    if (ctl && base >= n) return;
     uint32_t at = tile_off[blockIdx.x];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -1384,7 +1490,7 @@ void launch_chain_count(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int3
 {
     if (n == 0) return;
     k_chain_count<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(keys, n, lay.bp, k, max_gap, min_len,
-                                                              counts);
+                                                              counts, nullptr);
 }
 
 void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
@@ -1393,25 +1499,49 @@ void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int3
 {
     if (n == 0) return;
     k_chain_write<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(keys, n, lay, k, max_gap, min_len,
-                                                              tile_off, out);
+                                                              tile_off, out, nullptr);
+}
+
+// Chaining of a graph-replayed wave over tiles of hits_cap hits: run counts per
+// tile, their scan (total at counts[tiles], copied to ctl->nc), then the runs.
+void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_t max_gap,
+                      int32_t min_len, uint32_t *counts, uint32_t *partials, Cand *out,
+                      WaveCtl *ctl, hipStream_t st)
+{
+    const uint32_t nt = std::max<uint32_t>(1, (hits_cap + kTile - 1) / kTile);
+    k_chain_count<<<nt, kBlock, 0, st>>>(keys, 0, 0, k, max_gap, min_len, counts, ctl);
+    launch_scan_u32(counts, counts, nt, partials, st);
+    k_copy_u32<<<1, 1, 0, st>>>(counts + nt, &ctl->nc);
+    k_chain_write<<<nt, kBlock, 0, st>>>(keys, 0, HitKeyLayout{}, k, max_gap, min_len, counts, out,
+                                         ctl);
 }
 
 // Runs come out in (q, s, diag) order: each query's runs are one range
 // [qstart, qend), found at its boundaries (no per-run counter, no atomics).
 __global__ void k_cand_segments(const Cand *__restrict__ c, uint32_t n,
-                                uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
+                                uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
+                                const WaveCtl *__restrict__ ctl)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t q = c[i].q;
-    if (i == 0 || c[i - 1].q != q) qstart[q] = i;
-    if (i + 1 == n || c[i + 1].q != q) qend[q] = i + 1;
+    if (ctl) n = ctl->nc;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int32_t q = c[i].q;
+        if (i == 0 || c[i - 1].q != q) qstart[q] = i;
+        if (i + 1 == n || c[i + 1].q != q) qend[q] = i + 1;
+    }
 }
 
 void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t *qend,
                           hipStream_t st)
 {
-    if (n) k_cand_segments<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(c, n, qstart, qend);
+    if (n)
+        k_cand_segments<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
+            c, n, qstart, qend, nullptr);
+}
+
+void launch_cand_segments_ctl(const Cand *c, uint32_t *qstart, uint32_t *qend, const WaveCtl *ctl,
+                              hipStream_t st)
+{
+    k_cand_segments<<<kStrideGrid, kBlock, 0, st>>>(c, 0, qstart, qend, ctl);
 }
 
 uint32_t chain_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
@@ -1566,8 +1696,12 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
                                                    int32_t match, int32_t mismatch, int32_t X,
                                                    Box *__restrict__ out, XWalk *__restrict__ queue,
                                                    uint32_t qcap, uint32_t *__restrict__ qcount,
-                                                   int32_t lane_steps)
+                                                   int32_t lane_steps, const WaveCtl *__restrict__ ctl)
 {
+    if (ctl) {
+        n = ctl->nc;
+        qa = ctl->qa;
+    }
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const uint32_t nwave = gridDim.x * (kBlock / 64);
@@ -1622,8 +1756,10 @@ __global__ __launch_bounds__(kBlock) void k_extend_long(const Cand *__restrict__
                                                         Box *__restrict__ out,
                                                         const XWalk *__restrict__ queue,
                                                         uint32_t qcap,
-                                                        const uint32_t *__restrict__ qcount)
+                                                        const uint32_t *__restrict__ qcount,
+                                                        const WaveCtl *__restrict__ ctl)
 {
+    if (ctl) qa = ctl->qa;
     const int lane = threadIdx.x & 63;
     const uint32_t nw = min(*qcount, qcap);
     for (uint32_t e = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); e < nw;
@@ -1667,20 +1803,22 @@ size_t extend_queue_bytes(uint32_t n)
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
                    int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
                    int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
-                   int32_t lane_steps, hipStream_t st)
+                   int32_t lane_steps, hipStream_t st, const WaveCtl *ctl, uint32_t n_cap)
 {
-    if (n == 0) return;
+    // graph form: n comes from ctl, grids are sized for n_cap runs
+    const uint32_t nmax = ctl ? n_cap : n;
+    if (nmax == 0) return;
     uint32_t *qcount = static_cast<uint32_t *>(queue_mem);
     XWalk *queue = reinterpret_cast<XWalk *>(static_cast<char *>(queue_mem) + 256);
-    const uint32_t qcap = (uint32_t)((extend_queue_bytes(n) - 256) / sizeof(XWalk));
+    const uint32_t qcap = (uint32_t)((extend_queue_bytes(nmax) - 256) / sizeof(XWalk));
     launch_fill_u32(qcount, 1, 0u, st);
-    const uint32_t nb = std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid);
+    const uint32_t nb = ctl ? kStrideGrid : std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid);
     k_extend<<<nb, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start, match, mismatch, xdrop,
-                                    out, queue, qcap, qcount, std::max(lane_steps, 0));
-    const uint64_t most = std::min<uint64_t>(2ull * n, qcap);  // queued walks at most
+                                    out, queue, qcap, qcount, std::max(lane_steps, 0), ctl);
+    const uint64_t most = std::min<uint64_t>(2ull * nmax, qcap);  // queued walks at most
     const uint32_t lb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((most + 3) / 4, 1u << 16));
     k_extend_long<<<lb, kBlock, 0, st>>>(c, qcode, qoff, qa, dbw, seq_start, match, mismatch,
-                                         xdrop, out, queue, qcap, qcount);
+                                         xdrop, out, queue, qcap, qcount, ctl);
 }
 
 // ------------------------------------------------------------------ record sort keys
@@ -1817,11 +1955,14 @@ struct BoxLess {
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_seg_sort_box(const Box *__restrict__ in,
                                                          Box *__restrict__ out,
-                                                         const uint32_t *__restrict__ seg_off)
+                                                         const uint32_t *__restrict__ seg_off,
+                                                         WaveCtl *__restrict__ ctl)
 {
     __shared__ Box s_r[kSegCap];
     __shared__ uint16_t s_ix[kSegCap];
+    if (ctl && ((int32_t)blockIdx.x >= ctl->nqw || (MODE == 1 && ctl->overflow))) return;
     const uint32_t a0 = seg_off[blockIdx.x], n = seg_off[blockIdx.x + 1] - a0;
+    if (ctl && n > (uint32_t)kSegCap && threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
     if (n == 0 || n > (uint32_t)kSegCap) return;  // longer segments take the global sort
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_r[i] = in[a0 + i];
     lds_bitonic(s_r, s_ix, n, BoxLess<MODE>());
@@ -1829,11 +1970,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_sort_box(const Box *__restrict__
 }
 
 void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_off, int32_t nq,
-                         hipStream_t st)
+                         hipStream_t st, WaveCtl *ctl)
 {
     if (nq <= 0) return;
-    if (mode == 0) k_seg_sort_box<0><<<nq, kBlock, 0, st>>>(in, out, seg_off);
-    else k_seg_sort_box<1><<<nq, kBlock, 0, st>>>(in, out, seg_off);
+    if (mode == 0) k_seg_sort_box<0><<<nq, kBlock, 0, st>>>(in, out, seg_off, ctl);
+    else k_seg_sort_box<1><<<nq, kBlock, 0, st>>>(in, out, seg_off, ctl);
 }
 
 // Report order: alignments with score > 0 first, score descending, then seq,
@@ -1865,13 +2006,19 @@ __global__ __launch_bounds__(kBlock) void k_report_seg(const Align *__restrict__
                                                        uint32_t *__restrict__ rstart,
                                                        uint32_t *__restrict__ rend, int32_t qa,
                                                        int32_t cap, int32_t *__restrict__ dev_out,
-                                                       int32_t *__restrict__ dev_n)
+                                                       int32_t *__restrict__ dev_n,
+                                                       WaveCtl *__restrict__ ctl)
 {
     __shared__ Align s_r[kSegCap];
     __shared__ uint16_t s_ix[kSegCap];
     __shared__ uint32_t s_valid;
     const int32_t ql = blockIdx.x;
+    if (ctl) {
+        if (ql >= ctl->nqw) return;
+        qa = ctl->qa;
+    }
     const uint32_t a0 = sel_off[ql], n = sel_off[ql + 1] - a0;
+    if (ctl && n > (uint32_t)kSegCap && threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
     if (n > (uint32_t)kSegCap) return;  // longer segments take the global sort
     if (threadIdx.x == 0) s_valid = 0;
     __syncthreads();
@@ -1901,10 +2048,11 @@ __global__ __launch_bounds__(kBlock) void k_report_seg(const Align *__restrict__
 
 void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int32_t nq,
                        uint32_t *rstart, uint32_t *rend, int32_t qa, int32_t cap, int32_t *dev_out,
-                       int32_t *dev_n, hipStream_t st)
+                       int32_t *dev_n, hipStream_t st, WaveCtl *ctl)
 {
     if (nq > 0)
-        k_report_seg<<<nq, kBlock, 0, st>>>(in, out, sel_off, rstart, rend, qa, cap, dev_out, dev_n);
+        k_report_seg<<<nq, kBlock, 0, st>>>(in, out, sel_off, rstart, rend, qa, cap, dev_out, dev_n,
+                                            ctl);
 }
 
 // ------------------------------------------------------------------ S7: merge overlaps
@@ -1912,14 +2060,16 @@ void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int
 // group sweeps it once, merging the next box into the open one when both their
 // query and data-bank intervals intersect; the merged boxes are written from the
 // group's start and its remaining slots are marked empty (q = -1).
-__global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__restrict__ out)
+__global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__restrict__ out,
+                              const WaveCtl *__restrict__ ctl)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (ctl) n = ctl->overflow ? 0 : ctl->nc;  // an overflowed wave is run again later
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x) {
     const Box first = s[i];
     if (i > 0) {
         const Box p = s[i - 1];
-        if (p.q == first.q && p.s == first.s) return;
+        if (p.q == first.q && p.s == first.s) continue;
     }
     Box cur = first;
     uint32_t w = i, j = i + 1;
@@ -1940,30 +2090,46 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
     }
     out[w++] = cur;
     for (; w < j; ++w) out[w].q = -1;
+    }
 }
 
-void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st)
+void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st,
+                        const WaveCtl *ctl)
 {
-    if (n) k_merge_sweep<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(sorted, n, out);
+    if (ctl)
+        k_merge_sweep<<<kStrideGrid, kBlock, 0, st>>>(sorted, 0, out, ctl);
+    else if (n)
+        k_merge_sweep<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
+            sorted, n, out, nullptr);
 }
 
 // ------------------------------------------------------------------ S8: select
 // Records sorted by query first (empty ones last): each query's run [qstart, qend).
 __global__ void k_segments_box(const Box *__restrict__ s, uint32_t n, int32_t nq,
-                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
+                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
+                               const WaveCtl *__restrict__ ctl)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t q = s[i].q;
-    if (q < 0 || q >= nq) return;
-    if (i == 0 || s[i - 1].q != q) qstart[q] = i;
-    if (i + 1 == n || s[i + 1].q != q) qend[q] = i + 1;
+    if (ctl) {
+        n = ctl->overflow ? 0 : ctl->nc;
+        nq = ctl->nqw;
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x) {
+        const int32_t q = s[i].q;
+        if (q < 0 || q >= nq) continue;
+        if (i == 0 || s[i - 1].q != q) qstart[q] = i;
+        if (i + 1 == n || s[i + 1].q != q) qend[q] = i + 1;
+    }
 }
 
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
-                         uint32_t *qend, hipStream_t st)
+                         uint32_t *qend, hipStream_t st, const WaveCtl *ctl)
 {
-    if (n) k_segments_box<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(sorted, n, nq, qstart, qend);
+    if (ctl)
+        k_segments_box<<<kStrideGrid, kBlock, 0, st>>>(sorted, 0, 0, qstart, qend, ctl);
+    else if (n)
+        k_segments_box<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
+            sorted, n, nq, qstart, qend, nullptr);
 }
 
 __global__ void k_segments_align(const Align *__restrict__ s, uint32_t n, int32_t nq,
@@ -1986,20 +2152,21 @@ void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t
 
 __global__ void k_select_counts(const uint32_t *__restrict__ qstart,
                                 const uint32_t *__restrict__ qend, int32_t nq, int32_t N,
-                                uint32_t *__restrict__ nsel)
+                                uint32_t *__restrict__ nsel, const WaveCtl *__restrict__ ctl)
 {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
+    if (ctl && (q >= ctl->nqw || ctl->overflow) && q < nq) nsel[q] = 0;  // nothing to select
+    if (q >= (ctl ? (ctl->overflow ? 0 : min(nq, ctl->nqw)) : nq)) return;
     const uint32_t c = qend[q] - qstart[q];
     nsel[q] = (N > 0 && c > (uint32_t)N) ? (uint32_t)N : c;
 }
 
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
-                          int32_t max_hits, uint32_t *nsel, hipStream_t st)
+                          int32_t max_hits, uint32_t *nsel, hipStream_t st, const WaveCtl *ctl)
 {
     if (nq > 0)
         k_select_counts<<<(nq + kBlock - 1) / kBlock, kBlock, 0, st>>>(qstart, qend, nq, max_hits,
-                                                                        nsel);
+                                                                        nsel, ctl);
 }
 
 // ------------------------------------------------------------------ S9: banded Smith-Waterman
@@ -2164,11 +2331,17 @@ __global__ __launch_bounds__(64) void k_bsw(
     const uint8_t *__restrict__ qcode, const int64_t *__restrict__ qoff, int32_t qa,
     const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t match,
     int32_t mismatch, int32_t o1, int32_t ext, int32_t W, Align *__restrict__ out,
-    unsigned long long *__restrict__ cells_q, unsigned long long *__restrict__ cells_box)
+    unsigned long long *__restrict__ cells_q, unsigned long long *__restrict__ cells_box,
+    const WaveCtl *__restrict__ ctl)
 {
     __shared__ uint8_t s_q[kBswStage];
     __shared__ uint8_t s_d[kBswStage];
     const int32_t lane = threadIdx.x;
+    if (ctl) {
+        nq = ctl->nqw;
+        qa = ctl->qa;
+        total = nq > 0 ? sel_off[nq] : 0;
+    }
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
     int32_t lo = 0, hi = nq - 1;
     while (lo < hi) {
@@ -2237,7 +2410,7 @@ __global__ __launch_bounds__(64) void k_bsw(
         r.box_d_end = bx.de;
         r.box_len = min(R, C);
         out[b] = r;
-        atomicAdd(&cells_q[q], cells);
+        if (cells_q) atomicAdd(&cells_q[q], cells);
         if (cells_box) cells_box[b] = cells;
     }
     __syncthreads();  // the next box restages s_q and s_d
@@ -2248,12 +2421,15 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 uint32_t nsel_total, const uint8_t *qcode, const int64_t *qoff, int32_t qa,
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
-                unsigned long long *cells_per_q, unsigned long long *cells_per_box, hipStream_t st)
+                unsigned long long *cells_per_q, unsigned long long *cells_per_box, hipStream_t st,
+                const WaveCtl *ctl)
 {
-    if (nsel_total == 0) return;
-    k_bsw<<<std::min<uint32_t>(nsel_total, kMaxGrid), 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
-                                      seq_start, match, mismatch, gap_open + gap_extend, gap_extend,
-                                      band, out, cells_per_q, cells_per_box);
+    // graph form: the wave's selection count is read on the device
+    const uint32_t grid = ctl ? 8 * kStrideGrid : std::min<uint32_t>(nsel_total, kMaxGrid);
+    if (grid == 0) return;
+    k_bsw<<<grid, 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
+                               seq_start, match, mismatch, gap_open + gap_extend, gap_extend, band,
+                               out, cells_per_q, cells_per_box, ctl);
 }
 
 // ------------------------------------------------------------------ results to device memory

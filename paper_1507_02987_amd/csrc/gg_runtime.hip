@@ -106,9 +106,14 @@ struct Workspace {
     DevBuf cands, ccount, cand_q, cand_off, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
     DevBuf bplan, bcount, boff, bcands, btmp, bcoff, ctmp, cursor, qcur, bound_q, bound_off,
-        btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue;
+        btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue, gout, gn,
+        gctl, gplan, gcursor, goflags;
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
+    // the captured wave graph and what it was captured for (every argument baked
+    // into its nodes: capacities, parameters, buffer addresses)
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uint64_t> gkey;
     std::vector<hipEvent_t> events;
     size_t ev_used = 0;
     struct Mark {
@@ -121,13 +126,15 @@ struct Workspace {
     ~Workspace()
     {
         if (st) (void)hipSetDevice(device);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         DevBuf *all[] = {&ascii, &qoff, &qcode, &kcode, &cnt, &qid, &hoff, &partials, &qtot, &err,
                          &hrel, &pbase, &akey, &keys, &keys_alt, &hist, &rs_partials, &cands,
                          &ccount, &cand_q, &cand_off, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
                          &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
                          &cells_q, &bplan, &bcount, &boff, &bcands, &btmp, &bcoff, &ctmp, &cursor, &qcur,
                          &bound_q, &bound_off, &btmp_b, &bounds, &blist, &pcnt, &cells_box,
-                         &rbounds, &rbelow, &os_scratch, &xqueue};
+                         &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
+                         &gcursor, &goflags};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -1047,6 +1054,237 @@ gg_status search_pieces(const gg_index *ix, Workspace *ws, Prof &prof, const gg_
     return GG_OK;
 }
 
+// ---- graph-replayed batches
+// Waves of a batch are replayed from one captured HIP graph: every kernel reads
+// the wave's sizes from a device WaveCtl (see k_wave_begin), so after the single
+// synchronisation that gives the per-query hit counts, all waves run without
+// further host round trips, and the graph is reused by later calls of the same
+// shape.  It covers the radix-sort grouping with per-query LDS sorts: a wave in
+// which some query has more than kSegCap runs or selections is flagged and run
+// again by run_wave.  GG_GRAPH=0 turns the form off.
+constexpr uint64_t kGraphHits = 1ull << 25;  // hits of one graph wave at most
+
+uint64_t pow2_at_least(uint64_t v)
+{
+    uint64_t r = 1;
+    while (r < v) r <<= 1;
+    return r;
+}
+
+bool graph_enabled()
+{
+    const char *g = getenv("GG_GRAPH");
+    return !(g && !strcmp(g, "0"));
+}
+
+gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
+                          const std::vector<int64_t> &qoff_h, const std::vector<uint64_t> &qtot,
+                          int64_t nq, BatchOut &bo, uint64_t budget_bytes, bool *used)
+{
+    *used = false;
+    hipStream_t st = ws->st;
+    const uint64_t wave_hits = std::min<uint64_t>(kGraphHits, budget_bytes / 16);
+    int64_t maxL = 0;
+    for (int64_t q = 0; q < nq; ++q) {
+        if (qtot[q] > wave_hits) return GG_OK;  // needs pieces: the regular path
+        maxL = std::max<int64_t>(maxL, qoff_h[q + 1] - qoff_h[q]);
+    }
+    // waves by hits; one key layout for all of them
+    std::vector<WaveCtl> plan;
+    uint64_t hmax = 0;
+    int64_t npmax = 0;
+    int32_t nqmax = 0;
+    for (int64_t qa = 0; qa < nq;) {
+        uint64_t h = 0;
+        int64_t qb = qa;
+        while (qb < nq && (qb == qa || h + qtot[qb] <= wave_hits) && qb - qa < (1 << 20)) h += qtot[qb++];
+        WaveCtl w{};
+        w.qa = (int32_t)qa;
+        w.nqw = (int32_t)(qb - qa);
+        w.g0 = qoff_h[qa];
+        w.np = qoff_h[qb] - qoff_h[qa];
+        w.H = (uint32_t)h;
+        plan.push_back(w);
+        hmax = std::max(hmax, h);
+        npmax = std::max(npmax, w.np);
+        nqmax = std::max(nqmax, w.nqw);
+        qa = qb;
+    }
+    const uint32_t hits_cap = (uint32_t)pow2_at_least(std::max<uint64_t>(hmax, kTile));
+    const int64_t np_cap = (int64_t)pow2_at_least((uint64_t)std::max<int64_t>(npmax, 1));
+    const int32_t nq_cap = (int32_t)pow2_at_least((uint64_t)nqmax);
+    HitKeyLayout lay;
+    lay.bp = bits_for((uint64_t)maxL);
+    lay.bias = (int32_t)maxL;
+    lay.bd = bits_for((uint64_t)ix->max_seq_len + (uint64_t)maxL);
+    lay.bs = bits_for((uint64_t)ix->n_seqs);
+    lay.bq = bits_for((uint64_t)nq_cap);
+    if (lay.bp + lay.bd + lay.bs + lay.bq > 64) return GG_OK;
+    if ((uint64_t)maxL * (uint64_t)p->match >= (1ull << 30)) return GG_EINVAL;
+    for (WaveCtl &w : plan) w.lay = lay;
+    const int passes = (lay.bd + lay.bs + lay.bq + kRadixBits - 1) / kRadixBits;
+    const int32_t N = p->max_hits, cap = bo.cap;
+    const uint32_t sel_cap = (uint32_t)N * (uint32_t)nq_cap;
+    const uint32_t ntile = (hits_cap + kTile - 1) / kTile;
+    const size_t nq_out = (size_t)pow2_at_least((uint64_t)nq);
+    const size_t nwave_cap = (size_t)pow2_at_least(std::max<uint64_t>(plan.size(), 64));
+
+    // buffers for the largest wave (they only grow, so a cached graph stays valid
+    // while its key matches)
+    TRY(ensure(ws->hrel, sizeof(uint32_t) * (np_cap + 1)));
+    TRY(ensure(ws->pbase, sizeof(uint32_t) * (np_cap + 1)));
+    TRY(ensure(ws->akey, sizeof(uint64_t) * (np_cap + 1)));
+    TRY(ensure(ws->keys, sizeof(uint64_t) * hits_cap));
+    TRY(ensure(ws->keys_alt, sizeof(uint64_t) * hits_cap));
+    TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(hits_cap)));
+    TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(hits_cap))));
+    TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
+    TRY(ensure(ws->partials,
+               sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nq_cap) + 1)));
+    TRY(ensure(ws->cands, sizeof(Cand) * hits_cap));
+    TRY(ensure(ws->boxes, sizeof(Box) * hits_cap));
+    TRY(ensure(ws->boxes2, sizeof(Box) * hits_cap));
+    TRY(ensure(ws->boxes3, sizeof(Box) * hits_cap));
+    TRY(ensure(ws->xqueue, extend_queue_bytes(hits_cap)));
+    for (DevBuf *b : {&ws->qstart, &ws->qend, &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off,
+                      &ws->rstart, &ws->rend})
+        TRY(ensure(*b, sizeof(uint32_t) * (nq_cap + 1)));
+    TRY(ensure(ws->aligns, sizeof(Align) * std::max<uint32_t>(sel_cap, 1)));
+    TRY(ensure(ws->aligns2, sizeof(Align) * std::max<uint32_t>(sel_cap, 1)));
+    TRY(ensure(ws->gout, sizeof(gg_hit) * nq_out * std::max(cap, 1)));
+    TRY(ensure(ws->gn, sizeof(int32_t) * nq_out));
+    TRY(ensure(ws->gctl, sizeof(WaveCtl)));
+    TRY(ensure(ws->gplan, sizeof(WaveCtl) * nwave_cap));
+    TRY(ensure(ws->gcursor, sizeof(uint32_t) * 4));
+    TRY(ensure(ws->goflags, sizeof(uint32_t) * nwave_cap));
+
+    WaveCtl *ctl = as<WaveCtl>(ws->gctl);
+    uint32_t *cursor = as<uint32_t>(ws->gcursor);
+    const uint64_t *sorted = (passes & 1) ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys);
+    const int32_t steps = ix->tune_lane_steps.load();
+    std::vector<uint64_t> key = {hits_cap, (uint64_t)np_cap, (uint64_t)nq_cap, (uint64_t)passes,
+                                 (uint64_t)lay.bp, (uint64_t)lay.bd, (uint64_t)lay.bs,
+                                 (uint64_t)lay.bq, (uint64_t)(uint32_t)lay.bias, (uint64_t)cap,
+                                 (uint64_t)(uint32_t)steps, (uint64_t)ix->k,
+                                 (uint64_t)(uintptr_t)ix->d_post};
+    for (int32_t v : {p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, p->xdrop,
+                      p->max_gap, p->min_hsp_len, p->max_hits})
+        key.push_back((uint64_t)(uint32_t)v);
+    for (const DevBuf *b : {&ws->hoff, &ws->qoff, &ws->kcode, &ws->qid, &ws->qcode, &ws->hrel,
+                            &ws->pbase, &ws->akey, &ws->keys, &ws->keys_alt, &ws->hist,
+                            &ws->rs_partials, &ws->ccount, &ws->partials, &ws->cands, &ws->boxes,
+                            &ws->boxes2, &ws->boxes3, &ws->xqueue, &ws->qstart, &ws->qend,
+                            &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
+                            &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
+                            &ws->gplan, &ws->gcursor, &ws->goflags})
+        key.push_back((uint64_t)(uintptr_t)b->p);
+
+    if (!ws->gexec || ws->gkey != key) {
+        if (ws->gexec) {
+            (void)hipGraphExecDestroy(ws->gexec);
+            ws->gexec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        launch_wave_begin(as<WaveCtl>(ws->gplan), cursor, ctl, st);
+        launch_wave_prep_ctl(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
+                             as<int32_t>(ws->qid), ix->d_list_off, np_cap, as<uint32_t>(ws->hrel),
+                             as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), ctl, st);
+        launch_gather_ctl(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
+                          ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl, st);
+        for (int pass = 0; pass < passes; ++pass) {
+            const bool odd = pass & 1;
+            launch_rs_pass_ctl(odd ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys),
+                               odd ? as<uint64_t>(ws->keys) : as<uint64_t>(ws->keys_alt), hits_cap,
+                               pass, as<uint32_t>(ws->hist), as<uint32_t>(ws->rs_partials), ctl, st);
+        }
+        launch_chain_ctl(sorted, hits_cap, ix->k, p->max_gap, p->min_hsp_len,
+                         as<uint32_t>(ws->ccount), as<uint32_t>(ws->partials), as<Cand>(ws->cands),
+                         ctl, st);
+        launch_fill_u32(as<uint32_t>(ws->qstart), nq_cap, 0u, st);
+        launch_fill_u32(as<uint32_t>(ws->qend), nq_cap, 0u, st);
+        launch_cand_segments_ctl(as<Cand>(ws->cands), as<uint32_t>(ws->qstart),
+                                 as<uint32_t>(ws->qend), ctl, st);
+        launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nq_cap, 0,
+                             as<uint32_t>(ws->cand_q), st, ctl);
+        launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nq_cap,
+                        as<uint32_t>(ws->partials), st);
+        launch_extend(as<Cand>(ws->cands), 0, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0,
+                      ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop,
+                      as<Box>(ws->boxes), ws->xqueue.p, steps, st, ctl, hits_cap);
+        launch_seg_sort_box(0, as<Box>(ws->boxes), as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off),
+                            nq_cap, st, ctl);
+        launch_merge_sweep(as<Box>(ws->boxes2), 0, as<Box>(ws->boxes3), st, ctl);
+        launch_seg_sort_box(1, as<Box>(ws->boxes3), as<Box>(ws->boxes2),
+                            as<uint32_t>(ws->cand_off), nq_cap, st, ctl);
+        launch_fill_u32(as<uint32_t>(ws->qstart), nq_cap, 0u, st);
+        launch_fill_u32(as<uint32_t>(ws->qend), nq_cap, 0u, st);
+        launch_segments_box(as<Box>(ws->boxes2), 0, 0, as<uint32_t>(ws->qstart),
+                            as<uint32_t>(ws->qend), st, ctl);
+        launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nq_cap, N,
+                             as<uint32_t>(ws->nsel), st, ctl);
+        launch_scan_u32(as<uint32_t>(ws->nsel), as<uint32_t>(ws->sel_off), nq_cap,
+                        as<uint32_t>(ws->partials), st);
+        launch_bsw(as<Box>(ws->boxes2), as<uint32_t>(ws->qstart), as<uint32_t>(ws->sel_off), 0, 0,
+                   as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0, ix->d_dbw, ix->d_seq_start,
+                   p->match, p->mismatch, p->gap_open, p->gap_extend, p->band,
+                   as<Align>(ws->aligns), nullptr, nullptr, st, ctl);
+        launch_report_seg(as<Align>(ws->aligns), as<Align>(ws->aligns2), as<uint32_t>(ws->sel_off),
+                          nq_cap, as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend), 0, cap,
+                          as<int32_t>(ws->gout), as<int32_t>(ws->gn), st, ctl);
+        launch_wave_end(ctl, cursor, as<uint32_t>(ws->goflags), st);
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        if (ec != hipSuccess) {
+            (void)hipGetLastError();
+            return GG_EDEVICE;
+        }
+        const hipError_t ei = hipGraphInstantiate(&ws->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            ws->gexec = nullptr;
+            (void)hipGetLastError();
+            return GG_EDEVICE;
+        }
+        ws->gkey = key;
+    }
+
+    // replay it once per wave
+    const size_t W = plan.size();
+    HIPCHK(hipMemcpyAsync(ws->gplan.p, plan.data(), sizeof(WaveCtl) * W, hipMemcpyHostToDevice, st));
+    launch_fill_u32(cursor, 1, 0u, st);
+    launch_fill_u32(as<uint32_t>(ws->gn), (size_t)nq, 0u, st);
+    prof.begin("graph");
+    for (size_t w = 0; w < W; ++w) HIPCHK(hipGraphLaunch(ws->gexec, st));
+    prof.end((int64_t)W);
+    std::vector<uint32_t> oflags(W);
+    std::vector<int32_t> nout((size_t)nq);
+    HIPCHK(hipMemcpyAsync(oflags.data(), ws->goflags.p, sizeof(uint32_t) * W,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(nout.data(), ws->gn.p, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+    if (cap > 0) {
+        const size_t bytes = sizeof(gg_hit) * (size_t)nq * cap;
+        HIPCHK(hipMemcpyAsync(bo.out, ws->gout.p, bytes,
+                              bo.device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    }
+    if (bo.device)
+        HIPCHK(hipMemcpyAsync(bo.n_out, ws->gn.p, sizeof(int32_t) * nq, hipMemcpyDeviceToDevice,
+                              st));
+    SYNC(st);
+    prof.collect();
+    *used = true;
+    if (!bo.device) std::copy(nout.begin(), nout.end(), bo.n_out);
+    for (int64_t q = 0; q < nq; ++q)
+        if (nout[(size_t)q] > cap) bo.truncated = true;
+    // waves the per-query LDS sorts could not hold run again on the regular path
+    for (size_t w = 0; w < W; ++w) {
+        if (!oflags[w]) continue;
+        const int32_t qa = plan[w].qa, qb = plan[w].qa + plan[w].nqw;
+        TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, qa, qb, bo, kSort));
+        prof.collect();
+    }
+    return GG_OK;
+}
+
 gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const int64_t *qoff,
                     int64_t nq, const gg_params *p, BatchOut &bo, uint64_t budget_bytes)
 {
@@ -1106,6 +1344,12 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     // ---- waves: consecutive queries whose stored hit keys fit the budget and the key
     // bits (probing stores no hit: its waves are bounded only by 32-bit hit counts)
     const Grouping grouping = grouping_for(ix);
+    if (graph_enabled() && grouping == kSort && !bo.stats && p->max_hits >= 1 &&
+        p->max_hits <= kSegCap) {
+        bool used = false;
+        TRY(run_graph_waves(ix, ws, prof, p, qoff_h, qtot, nq, bo, budget_bytes, &used));
+        if (used) return GG_OK;
+    }
     const uint64_t max_hits = grouping == kProbe
                                   ? (uint64_t)INT32_MAX
                                   : std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
@@ -1451,7 +1695,7 @@ gg_status gg_index_autotune(gg_index *ix, const char *qbuf, const int64_t *qoff,
             const gg_tuning t{grouping, steps, 0.0};
             TRY(gg_index_set_tuning(ix, &t));
             double ms = -1.0;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = -1; rep < 2; ++rep) {  // rep -1 warms up (graph capture, buffers)
                 const auto t0 = std::chrono::steady_clock::now();
                 gg_status s = gg::search_batch_budget(ix, qbuf, qoff, n_q, params, out.data(), cap,
                                                       n_out.data(), nullptr, gg::index_budget(ix),
@@ -1463,7 +1707,9 @@ gg_status gg_index_autotune(gg_index *ix, const char *qbuf, const int64_t *qoff,
                     (void)gg_index_set_tuning(ix, &keep);
                     return s;
                 }
+                if (rep < 0) continue;
                 ms = ms < 0 ? dt : std::min(ms, dt);
+                if (best.ms >= 0 && ms > 2.0 * best.ms) break;  // clearly slower: one run is enough
             }
             if (ref.empty()) {
                 ref = out;

@@ -282,3 +282,60 @@ def test_autotune_and_lane_steps(ggo, monkeypatch):
         check_batch(G, gix, qs, G.params(50), want, wst)
     with pytest.raises(G.GGError):
         gix.set_tuning("sort", -1)
+
+
+def graph_waves(gix):
+    return gix.profile_read("graph")["units"]
+
+
+@pytest.mark.parametrize("k,band,max_hits,seed", [(11, 32, 20, 21), (8, 17, 5, 22), (4, 32, 3, 23)])
+def test_graph_replayed_batches(ggo, monkeypatch, k, band, max_hits, seed):
+    """Batches without per-query statistics run as replays of one captured graph
+    (one replay per wave, sizes read on the device).  With one wave, with many
+    waves (small hit budget), host and device results, a reused graph and a
+    recaptured one all equal the oracle; k = 4 gives queries with more runs than
+    the per-query LDS sorts hold, whose waves are run again without the graph."""
+    G = gpu()
+    monkeypatch.setenv("GG_GROUPING", "sort")
+    monkeypatch.delenv("GG_GRAPH", raising=False)
+    db = synth.random_db(seed, n_seqs=300, lmin=0, lmax=3000)
+    qs = synth.random_queries(seed, db, n=40, lmin=0, lmax=1500, frac_homolog=0.7,
+                              ident_lo=0.8, ident_hi=1.0, indel_rate=0.02)
+    oix, gix = ggo.Index(db.seqs, db.off, k), G.Index(db.seqs, db.off, k)
+    kw = dict(band=band, max_gap=3 * k, min_hsp_len=2 * k)
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(max_hits, **kw))
+    prm = G.params(max_hits, **kw)
+
+    def check(tag):
+        rc, got, n, _ = gix.search_batch(qs.buf, qs.off, prm, cap=1000)
+        assert rc == 0, tag
+        for i in range(qs.n):
+            assert as_rows(got[i]) == as_rows(want[i]), (tag, i)
+
+    gix.profile(True)
+    check("one wave")
+    assert graph_waves(gix) >= 1
+    check("graph reused")
+    hits = max(int(s["n_hits"]) for s in wst)
+    gix.set_hit_budget(16 * max(hits, 1))  # about one query per wave
+    before = graph_waves(gix)
+    check("many waves")
+    assert graph_waves(gix) - before > 2
+    gix.set_hit_budget(0)
+    check("recaptured")
+    cap = 3
+    dq = G.DeviceBuffer(len(qs.buf))
+    dq.upload(qs.buf)
+    dout = G.DeviceBuffer(qs.n * cap * G.HIT_DTYPE.itemsize)
+    dn = G.DeviceBuffer(qs.n * 4)
+    rc, _ = gix.search_batch_device(dq, qs.off, prm, dout, dn, cap)
+    assert rc == (G.GG_ETRUNC if any(len(w) > cap for w in want) else G.GG_OK)
+    n = dn.download(np.zeros(qs.n, np.int32))
+    got = dout.download(np.zeros(qs.n * cap, G.HIT_DTYPE))
+    for i in range(qs.n):
+        assert int(n[i]) == len(want[i])
+        m = min(cap, len(want[i]))
+        assert as_rows(got[i * cap: i * cap + m]) == as_rows(want[i][:m])
+    gix.profile(False)
+    if k == 4:
+        assert max(s["n_cands"] for s in wst) > 1024
