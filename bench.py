@@ -176,6 +176,8 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form latency leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device three times (counter calibration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default launch choices (for profiler runs)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the one-query-at-a-time comparison (for kernel-trace runs)")
     args = ap.parse_args()
@@ -222,10 +224,13 @@ def main() -> int:
     # launch choices picked by the library's autotuner on the workload's batch (on
     # its first 48 queries for the large workloads, whose batches take seconds)
     t = time.perf_counter()
-    sample = qs if cfg == 1 else qs.subset(np.arange(min(48, qs.n)))
-    log(f"autotuning on {sample.n} queries ...")
-    tuning = gix.autotune(sample.buf, sample.off, prm)
-    log(f"autotuned on {sample.n} queries in {time.perf_counter() - t:.1f} s: {tuning}")
+    if args.no_tune:
+        tuning = gix.tuning()
+    else:
+        sample = qs if cfg == 1 else qs.subset(np.arange(min(48, qs.n)))
+        log(f"autotuning on {sample.n} queries ...")
+        tuning = gix.autotune(sample.buf, sample.off, prm)
+        log(f"autotuned on {sample.n} queries in {time.perf_counter() - t:.1f} s: {tuning}")
 
     # inputs resident in HBM before the timed region
     dq = gg.DeviceBuffer(max(len(qs.buf), 1))
