@@ -110,6 +110,16 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
                       const int32_t *qid, const uint32_t *list_off, int32_t qa, int64_t g0,
                       int64_t g1, HitKeyLayout lay, uint32_t *hrel, uint32_t *pbase, uint64_t *akey,
                       hipStream_t st);
+// Index build (Sections 2, 2.1): pack the bank 2 bits per base; code every
+// non-overlapping window (keys = code, vals = window number, counts per code);
+// after a stable sort by code, window numbers become (sequence, position) postings.
+void launch_pack_bases(const uint8_t *ascii, int64_t total, uint32_t *dbw, int64_t nwords,
+                       int32_t *err, hipStream_t st);
+void launch_window_keys(const uint32_t *dbw, const int64_t *seq_start, const uint32_t *woff,
+                        int32_t n_seqs, uint32_t n_win, int32_t k, uint64_t *keys, uint32_t *vals,
+                        uint32_t *counts, hipStream_t st);
+void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff, int32_t n_seqs,
+                     int32_t k, int2 *post, hipStream_t st);
 // A query searched by pieces over ranges of sequence ids: below[y] += its hits on
 // sequences < bounds[y]; per-position sub-lists of the range [s_lo, s_hi).
 void launch_range_counts(const uint32_t *kcode, const uint32_t *cnt, int64_t np,

@@ -107,6 +107,98 @@ __device__ void lds_bitonic(const Rec *__restrict__ s_r, uint16_t *__restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ S0: index build
+// Formatting (Section 2): the bank's bases packed 2 bits each, 16 to a word, first
+// base most significant; a byte outside the alphabet sets *err.
+__global__ void k_pack_bases(const uint8_t *__restrict__ ascii, int64_t total,
+                             uint32_t *__restrict__ dbw, int64_t nwords, int32_t *__restrict__ err)
+{
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t word = 0;
+        bool bad = false;
+        for (int b = 0; b < 16; ++b) {
+            const int64_t g = w * 16 + b;
+            if (g >= total) break;
+            const int32_t c = base_code(ascii[g]);
+            bad |= c < 0;
+            word |= (uint32_t)(c < 0 ? 0 : c) << (30 - 2 * b);
+        }
+        dbw[w] = word;
+        if (bad) atomicOr(err, 1);
+    }
+}
+
+// Sequence of window w: the last s with woff[s] <= w (woff: windows before s).
+__device__ __forceinline__ int32_t window_seq(const uint32_t *__restrict__ woff, int32_t n_seqs,
+                                              uint32_t w)
+{
+    int32_t lo = 0, hi = n_seqs - 1;
+    while (lo < hi) {
+        const int32_t m = (lo + hi + 1) >> 1;
+        if (woff[m] <= w) lo = m;
+        else hi = m - 1;
+    }
+    return lo;
+}
+
+// Index (Section 2.1): every non-overlapping window of every sequence, in (seq,
+// pos) order: its code (the sort key), its number (the value) and a count per code.
+__global__ void k_window_keys(const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start,
+                              const uint32_t *__restrict__ woff, int32_t n_seqs, uint32_t n_win,
+                              int32_t k, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                              uint32_t *__restrict__ counts)
+{
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < n_win;
+         w += gridDim.x * blockDim.x) {
+        const int32_t s = window_seq(woff, n_seqs, w);
+        const int64_t g = seq_start[s] + (int64_t)(w - woff[s]) * k;
+        const uint32_t code = db_window(dbw, g, k);
+        keys[w] = code;
+        vals[w] = w;
+        atomicAdd(&counts[code], 1u);
+    }
+}
+
+// Postings in list order: window number -> (sequence, position).
+__global__ void k_postings(const uint32_t *__restrict__ vals, uint32_t n_win,
+                           const uint32_t *__restrict__ woff, int32_t n_seqs, int32_t k,
+                           int2 *__restrict__ post)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_win;
+         i += gridDim.x * blockDim.x) {
+        const uint32_t w = vals[i];
+        const int32_t s = window_seq(woff, n_seqs, w);
+        post[i] = int2{s, (int32_t)((w - woff[s]) * (uint32_t)k)};
+    }
+}
+
+void launch_pack_bases(const uint8_t *ascii, int64_t total, uint32_t *dbw, int64_t nwords,
+                       int32_t *err, hipStream_t st)
+{
+    if (nwords <= 0) return;
+    const int64_t nb = std::min<int64_t>((nwords + kBlock - 1) / kBlock, kMaxGrid);
+    k_pack_bases<<<(uint32_t)nb, kBlock, 0, st>>>(ascii, total, dbw, nwords, err);
+}
+
+void launch_window_keys(const uint32_t *dbw, const int64_t *seq_start, const uint32_t *woff,
+                        int32_t n_seqs, uint32_t n_win, int32_t k, uint64_t *keys, uint32_t *vals,
+                        uint32_t *counts, hipStream_t st)
+{
+    if (n_win == 0) return;
+    const uint32_t nb = std::min<uint32_t>((n_win + kBlock - 1) / kBlock, kMaxGrid);
+    k_window_keys<<<nb, kBlock, 0, st>>>(dbw, seq_start, woff, n_seqs, n_win, k, keys, vals,
+                                         counts);
+}
+
+void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff, int32_t n_seqs,
+                     int32_t k, int2 *post, hipStream_t st)
+{
+    if (n_win == 0) return;
+    const uint32_t nb = std::min<uint32_t>((n_win + kBlock - 1) / kBlock, kMaxGrid);
+    k_postings<<<nb, kBlock, 0, st>>>(vals, n_win, woff, n_seqs, k, post);
+}
+
 // ------------------------------------------------------------------ S1/S2: encode + count
 // One thread per query base g of the batch: code the base (flagging bytes outside
 // the alphabet), find its query, and if a whole window of k bases starts here,

@@ -16,7 +16,6 @@
 #include <mutex>
 #include <tuple>
 #include <string>
-#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -1451,9 +1450,9 @@ void gg_index_free(gg_index *ix)
     delete ix;
 }
 
-// Formatting and index construction (Sections 2, 2.1).  The list heads are a
-// counting sort of the windows by code: count, exclusive prefix, then place the
-// windows in (sequence, position) order, which keeps each list sorted.
+// Formatting and index construction (Sections 2, 2.1), on the GPU: the bases are
+// uploaded once, packed and windowed by kernels; the lists are a stable sort of
+// the windows by code, so each list keeps (sequence, position) order.
 gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
                          int32_t device, gg_index **out)
 {
@@ -1471,128 +1470,20 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
         maxlen = std::max(maxlen, n);
     }
     const int64_t total = n_seqs > 0 ? seq_off[n_seqs] - base0 : 0;
-    static const int8_t kCode[256] = {
-#define X -1
-        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
-        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
-        X, 0, X, 1, X, X, X, 2, X, X, X, X, X, X, X, X, X, X, X, X, 3, 3, X, X, X, X, X, X, X, X, X, X,
-        X, 0, X, 1, X, X, X, 2, X, X, X, X, X, X, X, X, X, X, X, X, 3, 3, X, X, X, X, X, X, X, X, X, X,
-        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
-        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
-        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
-        X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X, X,
-#undef X
-    };
-    // 2-bit packing, 16 bases per 32-bit word, first base most significant:
-    // base g at bits 30 - 2 (g % 16) of word g / 16
-    const int64_t nwords = (total + 15) / 16 + 1;
-    std::vector<uint32_t> dbw;
-    std::vector<uint32_t> head;
-    std::vector<int2> post;
-    try {
-        dbw.assign((size_t)nwords, 0u);
-        head.assign(((size_t)1 << (2 * k)) + 1, 0u);
-    } catch (...) {
-        return GG_ENOMEM;
-    }
-    {
-        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        std::atomic<int> bad{0};
-        std::vector<std::thread> th;
-        const int64_t chunk = ((nwords + nt - 1) / nt);
-        for (unsigned t = 0; t < nt; ++t) {
-            th.emplace_back([&, t]() {
-                const int64_t w0 = t * chunk, w1 = std::min<int64_t>(nwords, w0 + chunk);
-                for (int64_t w = w0; w < w1; ++w) {
-                    uint32_t word = 0;
-                    for (int b = 0; b < 16; ++b) {
-                        const int64_t g = w * 16 + b;
-                        if (g >= total) break;
-                        const int8_t c = kCode[(uint8_t)seqs[base0 + g]];
-                        if (c < 0) {
-                            bad = 1;
-                            continue;
-                        }
-                        word |= (uint32_t)c << (30 - 2 * b);
-                    }
-                    dbw[(size_t)w] = word;
-                }
-            });
-        }
-        for (auto &t : th) t.join();
-        if (bad) return GG_EINVAL;
-    }
-    // window code of the k bases from global base g: one 64-bit funnel of two words
-    auto window_code = [&](int64_t g) -> uint32_t {
-        const uint64_t x = ((uint64_t)dbw[(size_t)(g >> 4)] << 32) | dbw[(size_t)(g >> 4) + 1];
-        return (uint32_t)((x << (2 * (g & 15))) >> (64 - 2 * k));
-    };
+    // windows before each sequence (sequence lengths only; the bases go to the GPU)
+    std::vector<uint32_t> woff((size_t)n_seqs + 1, 0u);
+    std::vector<int64_t> seq_start((size_t)n_seqs + 1, 0);
     uint64_t n_post = 0;
-    for (int64_t s = 0; s < n_seqs; ++s) n_post += (uint64_t)((seq_off[s + 1] - seq_off[s]) / k);
+    for (int64_t s = 0; s < n_seqs; ++s) {
+        woff[(size_t)s] = (uint32_t)std::min<uint64_t>(n_post, 0xffffffffull);
+        n_post += (uint64_t)((seq_off[s + 1] - seq_off[s]) / k);
+        seq_start[(size_t)s] = seq_off[s] - base0;
+    }
     if (n_post >= 0xffffffffull) return GG_EINVAL;
-    // Threads own contiguous sequence ranges in id order.  Each counts its windows
-    // per code; a list's slots are handed out list by list, and within a list
-    // thread by thread, so placing every thread's windows in its own order keeps
-    // each list in (sequence, position) order.
-    const size_t ncode = (size_t)1 << (2 * k);
-    // at most 16 threads, and per-thread code counts of at most 1 GiB in total
-    const unsigned nth = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>({16, (int64_t)std::max(1u, std::thread::hardware_concurrency()),
-                              n_seqs, (int64_t)(((size_t)1 << 28) / ncode)}));
-    std::vector<int64_t> sbeg(nth + 1, n_seqs);
-    {
-        int64_t s = 0;
-        for (unsigned t = 0; t < nth; ++t) {
-            sbeg[t] = s;
-            const int64_t goal = base0 + total * (int64_t)(t + 1) / nth;
-            while (s < n_seqs && seq_off[s + 1] <= goal) ++s;
-        }
-        sbeg[nth] = n_seqs;
-    }
-    std::vector<std::vector<uint32_t>> cnt(nth);
-    try {
-        for (auto &c : cnt) c.assign(ncode, 0u);
-        post.resize((size_t)std::max<uint64_t>(n_post, 1));
-    } catch (...) {
-        return GG_ENOMEM;
-    }
-    auto for_windows = [&](unsigned t, auto &&fn) {
-        for (int64_t s = sbeg[t]; s < sbeg[t + 1]; ++s) {
-            const int64_t g0 = seq_off[s] - base0, n = seq_off[s + 1] - seq_off[s];
-            for (int64_t w = 0; (w + 1) * k <= n; ++w) fn(s, w * k, window_code(g0 + w * k));
-        }
-    };
-    auto parallel = [&](auto &&body) {
-        std::vector<std::thread> th;
-        for (unsigned t = 0; t < nth; ++t) th.emplace_back(body, t);
-        for (auto &x : th) x.join();
-    };
-    parallel([&](unsigned t) {
-        uint32_t *c = cnt[t].data();
-        for_windows(t, [&](int64_t, int64_t, uint32_t code) { ++c[code]; });
-    });
-    // head[c] = number of windows with a smaller code; cnt[t][c] becomes thread t's
-    // first slot in list c
-    {
-        uint32_t run = 0;
-        for (size_t c = 0; c < ncode; ++c) {
-            head[c] = run;
-            for (unsigned t = 0; t < nth; ++t) {
-                const uint32_t n = cnt[t][c];
-                cnt[t][c] = run;
-                run += n;
-            }
-        }
-        head[ncode] = run;
-    }
-    parallel([&](unsigned t) {
-        uint32_t *cur = cnt[t].data();
-        for_windows(t, [&](int64_t s, int64_t pos, uint32_t code) {
-            post[cur[code]++] = int2{(int32_t)s, (int32_t)pos};
-        });
-    });
-    std::vector<int64_t> seq_start((size_t)n_seqs + 1);
-    for (int64_t s = 0; s <= n_seqs; ++s) seq_start[(size_t)s] = n_seqs > 0 ? seq_off[s] - base0 : 0;
+    woff[(size_t)n_seqs] = (uint32_t)n_post;
+    seq_start[(size_t)n_seqs] = total;
+    const int64_t nwords = (total + 15) / 16 + 1;  // one spare word for window reads
+    const uint64_t ncode = (uint64_t)1 << (2 * k);
 
     auto *ix = new (std::nothrow) gg_index();
     if (!ix) return GG_ENOMEM;
@@ -1607,25 +1498,87 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
         return s;
     };
     if (hipSetDevice(device) != hipSuccess) return fail(GG_EDEVICE);
-    auto up = [&](void **dst, const void *src, size_t bytes) -> gg_status {
+    auto alloc = [](void **dst, size_t bytes) -> gg_status {
         if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) {
             (void)hipGetLastError();
             *dst = nullptr;
             return GG_ENOMEM;
         }
-        if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
-            return GG_EDEVICE;
         return GG_OK;
     };
     gg_status s;
-    if ((s = up((void **)&ix->d_list_off, head.data(), head.size() * sizeof(uint32_t))) != GG_OK)
+    if ((s = alloc((void **)&ix->d_list_off, sizeof(uint32_t) * (ncode + 1))) != GG_OK ||
+        (s = alloc((void **)&ix->d_post, sizeof(int2) * n_post)) != GG_OK ||
+        (s = alloc((void **)&ix->d_dbw, sizeof(uint32_t) * nwords)) != GG_OK ||
+        (s = alloc((void **)&ix->d_seq_start, sizeof(int64_t) * (n_seqs + 1))) != GG_OK)
         return fail(s);
-    if ((s = up((void **)&ix->d_post, post.data(), n_post * sizeof(int2))) != GG_OK) return fail(s);
-    if ((s = up((void **)&ix->d_dbw, dbw.data(), dbw.size() * sizeof(uint32_t))) != GG_OK)
-        return fail(s);
-    if ((s = up((void **)&ix->d_seq_start, seq_start.data(), seq_start.size() * sizeof(int64_t))) !=
-        GG_OK)
-        return fail(s);
+
+    // Sections 2, 2.1 on the GPU: pack the bases, code every window, sort the
+    // windows stably by code (they start in (seq, pos) order, so every list stays
+    // in that order), list heads = exclusive scan of the per-code counts.
+    {
+        struct Tmp {
+            std::vector<void *> p;
+            ~Tmp()
+            {
+                for (void *x : p) (void)hipFree(x);
+            }
+            void *get(size_t bytes)
+            {
+                void *x = nullptr;
+                if (hipMalloc(&x, std::max<size_t>(bytes, 16)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return nullptr;
+                }
+                p.push_back(x);
+                return x;
+            }
+        } tmp;
+        hipStream_t bst = nullptr;
+        if (hipStreamCreateWithFlags(&bst, hipStreamNonBlocking) != hipSuccess) return fail(GG_EDEVICE);
+        struct StreamGuard {
+            hipStream_t s;
+            ~StreamGuard() { (void)hipStreamDestroy(s); }
+        } sg{bst};
+        const uint32_t nw = (uint32_t)n_post;
+        auto *d_ascii = static_cast<uint8_t *>(tmp.get((size_t)total));
+        auto *d_woff = static_cast<uint32_t *>(tmp.get(sizeof(uint32_t) * (n_seqs + 1)));
+        auto *d_err = static_cast<int32_t *>(tmp.get(sizeof(int32_t) * 4));
+        auto *d_keys = static_cast<uint64_t *>(tmp.get(sizeof(uint64_t) * nw));
+        auto *d_keys2 = static_cast<uint64_t *>(tmp.get(sizeof(uint64_t) * nw));
+        auto *d_vals = static_cast<uint32_t *>(tmp.get(sizeof(uint32_t) * nw));
+        auto *d_vals2 = static_cast<uint32_t *>(tmp.get(sizeof(uint32_t) * nw));
+        auto *d_hist = static_cast<uint32_t *>(tmp.get(sizeof(uint32_t) * radix_hist_needed(nw)));
+        const size_t parts = std::max<size_t>(scan_partials_needed(radix_hist_needed(nw)),
+                                              scan_partials_needed((int64_t)ncode + 1));
+        auto *d_parts = static_cast<uint32_t *>(tmp.get(sizeof(uint32_t) * parts));
+        if (!d_ascii || !d_woff || !d_err || !d_keys || !d_keys2 || !d_vals || !d_vals2 ||
+            !d_hist || !d_parts)
+            return fail(GG_ENOMEM);
+        int32_t err = 0;
+        if (total > 0 && hipMemcpyAsync(d_ascii, seqs + base0, (size_t)total,
+                                        hipMemcpyHostToDevice, bst) != hipSuccess)
+            return fail(GG_EDEVICE);
+        if (hipMemcpyAsync(d_woff, woff.data(), sizeof(uint32_t) * (n_seqs + 1),
+                           hipMemcpyHostToDevice, bst) != hipSuccess ||
+            hipMemcpyAsync(ix->d_seq_start, seq_start.data(), sizeof(int64_t) * (n_seqs + 1),
+                           hipMemcpyHostToDevice, bst) != hipSuccess ||
+            hipMemsetAsync(d_err, 0, sizeof(int32_t), bst) != hipSuccess ||
+            hipMemsetAsync(ix->d_list_off, 0, sizeof(uint32_t) * (ncode + 1), bst) != hipSuccess)
+            return fail(GG_EDEVICE);
+        launch_pack_bases(d_ascii, total, ix->d_dbw, nwords, d_err, bst);
+        launch_window_keys(ix->d_dbw, ix->d_seq_start, d_woff, (int32_t)n_seqs, nw, k, d_keys,
+                           d_vals, ix->d_list_off, bst);
+        launch_scan_u32(ix->d_list_off, ix->d_list_off, (int64_t)ncode, d_parts, bst);
+        const int cur = radix_sort(d_keys, d_keys2, d_vals, d_vals2, nw, 0, 2 * k, d_hist, d_parts,
+                                   bst);
+        launch_postings(cur ? d_vals2 : d_vals, nw, d_woff, (int32_t)n_seqs, k, ix->d_post, bst);
+        if (hipMemcpyAsync(&err, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, bst) != hipSuccess ||
+            hipStreamSynchronize(bst) != hipSuccess || hipGetLastError() != hipSuccess)
+            return fail(GG_EDEVICE);
+        if (err) return fail(GG_EINVAL);
+    }
+
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(GG_EDEVICE);
     ix->default_budget = std::min<uint64_t>((uint64_t)16 << 30, free_b / 4);
