@@ -135,11 +135,11 @@ gg_status gg_index_get_tuning(const gg_index *index, gg_tuning *out);
 gg_status gg_index_set_tuning(gg_index *index, const gg_tuning *tuning);
 
 /*
- * Autotuner: search the sample batch (same layout as gg_search_batch) under every
- * candidate choice (3 groupings x lane steps 0, 16, 64, 256) after one untimed
- * run, twice each (once if the first timed run takes over twice the best time so
- * far), check that
- * all choices return identical hits, and keep the fastest on the index.
+ * Autotuner: search the sample batch (same layout as gg_search_batch; copied once
+ * to GPU memory and searched in the device-resident form) under every candidate
+ * choice (3 groupings x lane steps 0, 16, 64, 256) after one untimed run, three
+ * times each (once if the first timed run takes over twice the best time so far),
+ * check that all choices return identical hits, and keep the fastest on the index.
  * chosen (may be NULL) receives it.  Use queries shaped like the real workload;
  * a few hundred are enough.  Errors: those of gg_search_batch, and GG_EDEVICE if
  * two choices disagree (the previous choice is then kept).

@@ -1636,9 +1636,33 @@ gg_status gg_index_autotune(gg_index *ix, const char *qbuf, const int64_t *qoff,
                             const gg_params *params, gg_tuning *chosen)
 {
     if (!ix || n_q < 1 || !qoff || !params) return GG_EINVAL;
+    const int64_t T = qoff[n_q] - qoff[0];
+    if (T < 0 || (T > 0 && !qbuf)) return GG_EINVAL;
     const int32_t cap = params->max_hits > 0 ? params->max_hits : 256;
     gg_tuning keep;
     TRY(gg_index_get_tuning(ix, &keep));
+    if (hipSetDevice(ix->device) != hipSuccess) return GG_EDEVICE;
+    // the sample is timed in the device-resident form (queries and hits in GPU
+    // memory), so transfers do not blur the comparison
+    struct Dev {
+        void *q = nullptr, *out = nullptr, *n = nullptr;
+        ~Dev()
+        {
+            for (void *x : {q, out, n})
+                if (x) (void)hipFree(x);
+        }
+    } dev;
+    const size_t out_bytes = sizeof(gg_hit) * (size_t)n_q * cap;
+    if (hipMalloc(&dev.q, (size_t)std::max<int64_t>(T, 1)) != hipSuccess ||
+        hipMalloc(&dev.out, out_bytes) != hipSuccess ||
+        hipMalloc(&dev.n, sizeof(int32_t) * n_q) != hipSuccess) {
+        (void)hipGetLastError();
+        return GG_ENOMEM;
+    }
+    if (T > 0 && hipMemcpy(dev.q, qbuf + qoff[0], (size_t)T, hipMemcpyHostToDevice) != hipSuccess)
+        return GG_EDEVICE;
+    std::vector<int64_t> off((size_t)n_q + 1);
+    for (int64_t q = 0; q <= n_q; ++q) off[(size_t)q] = qoff[q] - qoff[0];
     std::vector<gg_hit> ref, out((size_t)n_q * cap);
     std::vector<int32_t> ref_n, n_out((size_t)n_q);
     gg_tuning best = keep;
@@ -1648,11 +1672,12 @@ gg_status gg_index_autotune(gg_index *ix, const char *qbuf, const int64_t *qoff,
             const gg_tuning t{grouping, steps, 0.0};
             TRY(gg_index_set_tuning(ix, &t));
             double ms = -1.0;
-            for (int rep = -1; rep < 2; ++rep) {  // rep -1 warms up (graph capture, buffers)
+            for (int rep = -1; rep < 3; ++rep) {  // rep -1 warms up (graph capture, buffers)
                 const auto t0 = std::chrono::steady_clock::now();
-                gg_status s = gg::search_batch_budget(ix, qbuf, qoff, n_q, params, out.data(), cap,
-                                                      n_out.data(), nullptr, gg::index_budget(ix),
-                                                      false);
+                gg_status s = gg::search_batch_budget(
+                    ix, static_cast<const char *>(dev.q), off.data(), n_q, params,
+                    static_cast<gg_hit *>(dev.out), cap, static_cast<int32_t *>(dev.n), nullptr,
+                    gg::index_budget(ix), true);
                 const double dt = std::chrono::duration<double, std::milli>(
                                       std::chrono::steady_clock::now() - t0)
                                       .count();
@@ -1664,13 +1689,26 @@ gg_status gg_index_autotune(gg_index *ix, const char *qbuf, const int64_t *qoff,
                 ms = ms < 0 ? dt : std::min(ms, dt);
                 if (best.ms >= 0 && ms > 2.0 * best.ms) break;  // clearly slower: one run is enough
             }
+            if (hipMemcpy(out.data(), dev.out, out_bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(n_out.data(), dev.n, sizeof(int32_t) * n_q, hipMemcpyDeviceToHost) !=
+                    hipSuccess) {
+                (void)gg_index_set_tuning(ix, &keep);
+                return GG_EDEVICE;
+            }
             if (ref.empty()) {
                 ref = out;
                 ref_n = n_out;
-            } else if (ref_n != n_out ||
-                       memcmp(ref.data(), out.data(), sizeof(gg_hit) * out.size()) != 0) {
-                (void)gg_index_set_tuning(ix, &keep);
-                return GG_EDEVICE;
+            } else {
+                bool same = ref_n == n_out;
+                for (int64_t q = 0; same && q < n_q; ++q) {
+                    const size_t m = (size_t)std::min(n_out[(size_t)q], cap);
+                    same = memcmp(&ref[(size_t)q * cap], &out[(size_t)q * cap],
+                                  sizeof(gg_hit) * m) == 0;
+                }
+                if (!same) {
+                    (void)gg_index_set_tuning(ix, &keep);
+                    return GG_EDEVICE;
+                }
             }
             if (best.ms < 0 || ms < best.ms) best = gg_tuning{grouping, steps, ms};
         }
