@@ -71,7 +71,16 @@ struct WaveCtl {
     uint32_t nc;      // runs kept (written on the device)
     HitKeyLayout lay;
     uint32_t overflow;  // a query's runs or selections exceeded the per-query LDS sorts
-    uint32_t pad;
+    uint32_t tile0, ntile;  // the wave's radix tiles in the batch's tile table
+};
+
+// A radix tile of a sort done within query segments: keys [start, start + count)
+// all belong to one query, whose nt tiles (this is its tq-th) keep their digit
+// counts at hist[hbase + digit * nt + tq], after all earlier queries' counts.  One
+// exclusive scan over such counts then places every key inside its query's own
+// range, so the passes need not sort on the query bits.
+struct SortTile {
+    uint32_t start, count, hbase, nt, tq;
 };
 
 // Which box field feeds a sort-key field.
@@ -197,8 +206,16 @@ void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint3
 void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                        const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
                        hipStream_t st);
-void launch_rs_pass_ctl(const uint64_t *kin, uint64_t *kout, uint32_t hits_cap, int pass,
-                        uint32_t *hist, uint32_t *partials, const WaveCtl *ctl, hipStream_t st);
+void launch_rs_pass_ctl(const uint64_t *kin, uint64_t *kout, uint32_t ntile_cap, int pass,
+                        const SortTile *tiles, uint32_t *hist, uint32_t *partials,
+                        const WaveCtl *ctl, hipStream_t st);
+// One pass within query segments (tiles from the host's table, ntile of them):
+// counts, scan, scatter.
+void launch_rs_hist_seg(const uint64_t *kin, uint32_t ntile, int shift, const SortTile *tiles,
+                        uint32_t *hist, hipStream_t st);
+void launch_rs_scan_seg(uint32_t *hist, uint32_t ntile, uint32_t *partials, hipStream_t st);
+void launch_rs_scatter_seg(const uint64_t *kin, uint64_t *kout, uint32_t ntile, int shift,
+                           const SortTile *tiles, const uint32_t *hist, hipStream_t st);
 void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_t max_gap,
                       int32_t min_len, uint32_t *counts, uint32_t *partials, Cand *out,
                       WaveCtl *ctl, hipStream_t st);

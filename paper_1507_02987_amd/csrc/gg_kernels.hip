@@ -1133,25 +1133,59 @@ void launch_group_by_query(const Cand *in, uint32_t n, const uint32_t *qoff_c, u
 // ranks its keys with ballot-built peer masks (lanes holding the same digit) and
 // per-wave digit counters in LDS; the tile is then reordered in LDS so that the
 // global writes of each digit run are contiguous.
+// The keys and count slots of one radix tile: its key range [base, base + cnt) and
+// count index hidx + digit * stride.  Plain tiles split [0, n) evenly and keep
+// digit-major counts over nb tiles; segmented tiles come from a table (tiles of
+// a graph's capacity past the wave count zero keys after every real tile).
+struct TileView {
+    uint32_t base, cnt, hidx, stride;
+};
+
+__device__ __forceinline__ TileView tile_view(uint32_t tile, uint32_t n, uint32_t nb,
+                                              const SortTile *__restrict__ tiles, uint32_t ntile)
+{
+    TileView v;
+    if (tiles) {
+        if (tile < ntile) {
+            const SortTile t = tiles[tile];
+            v = TileView{t.start, t.count, t.hbase + t.tq, t.nt};
+        } else {
+            v = TileView{0, 0, tile * (uint32_t)kRadix, 1};
+        }
+    } else {
+        v.base = tile * (uint32_t)kSortTile;
+        v.cnt = v.base < n ? min((uint32_t)kSortTile, n - v.base) : 0u;
+        v.hidx = tile;
+        v.stride = nb;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys, uint32_t n,
                                                     int shift, uint32_t *__restrict__ hist,
-                                                    uint32_t nb, const WaveCtl *__restrict__ ctl)
+                                                    uint32_t nb, const WaveCtl *__restrict__ ctl,
+                                                    const SortTile *__restrict__ tiles)
 {
     __shared__ uint32_t h[kRadix];
+    uint32_t ntile = nb;
     if (ctl) {  // shift holds the pass number; tiles past the wave's keys count zeros
         n = ctl->H;
         shift = ctl->lay.bp + kRadixBits * shift;
+        if (tiles) {
+            tiles += ctl->tile0;
+            ntile = ctl->ntile;
+        }
     }
+    const TileView tv = tile_view(blockIdx.x, n, nb, tiles, ntile);
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t i = base + r * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+        const uint32_t i = r * kBlock + threadIdx.x;
+        if (i < tv.cnt) atomicAdd(&h[(uint32_t)(keys[tv.base + i] >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    hist[(size_t)tv.hidx + (size_t)threadIdx.x * tv.stride] = h[threadIdx.x];
 }
 
 // One-sweep passes (no per-pass histogram kernel): a tile learns how many keys of
@@ -1223,12 +1257,17 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
                                                        uint32_t *__restrict__ vout, uint32_t n,
                                                        int shift, const uint32_t *__restrict__ hist,
                                                        uint32_t nb, Lookback lb,
-                                                       const WaveCtl *__restrict__ ctl)
+                                                       const WaveCtl *__restrict__ ctl,
+                                                       const SortTile *__restrict__ tiles)
 {
+    uint32_t ntile = nb;
     if (ctl) {  // shift holds the pass number
         n = ctl->H;
         shift = ctl->lay.bp + kRadixBits * shift;
-        if (blockIdx.x * (uint32_t)kSortTile >= n) return;  // the grid covers the largest wave
+        if (tiles) {
+            tiles += ctl->tile0;
+            ntile = ctl->ntile;
+        }
     }
     __shared__ uint64_t s_k[kSortTile];
     __shared__ uint32_t s_v[VALS ? kSortTile : 1];
@@ -1242,16 +1281,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
     if (LB && threadIdx.x == 0) s_tile = atomicAdd(lb.counter, 1u);
     __syncthreads();
     const uint32_t tile = LB ? s_tile : blockIdx.x;
-    const uint32_t sub = tile * (uint32_t)kSortTile + w * 64 * kSortItems;
+    const TileView tv = tile_view(tile, n, nb, tiles, ntile);
+    if (tv.cnt == 0) return;  // whole block: only capacity tiles of a graph are empty
+    const uint32_t sub = w * 64 * kSortItems;  // this wave's first key in the tile
     const uint64_t below = (1ull << lane) - 1ull;
     uint64_t k[kSortItems];
     uint32_t v[kSortItems], rank[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = sub + r * 64 + lane;
-        const bool ok = idx < n;
-        k[r] = ok ? kin[idx] : 0ull;
-        if (VALS) v[r] = ok ? vin[idx] : 0u;
+        const bool ok = idx < tv.cnt;
+        k[r] = ok ? kin[tv.base + idx] : 0ull;
+        if (VALS) v[r] = ok ? vin[tv.base + idx] : 0u;
         const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
         uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -1280,13 +1321,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
         if (LB)
             s_gbase[d] = lb.base[d] + look_back(lb, tile, d, run);
         else
-            s_gbase[d] = hist[(size_t)d * nb + tile];
+            s_gbase[d] = hist[(size_t)tv.hidx + (size_t)d * tv.stride];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = sub + r * 64 + lane;
-        if (idx < n) {
+        if (idx < tv.cnt) {
             const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
             const uint32_t pos = s_start[d] + s_wc[w][d] + rank[r];
             s_k[pos] = k[r];
@@ -1294,7 +1335,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
         }
     }
     __syncthreads();
-    const uint32_t tn = min((uint32_t)kSortTile, n - tile * (uint32_t)kSortTile);
+    const uint32_t tn = tv.cnt;
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t i = r * kBlock + threadIdx.x;
@@ -1418,7 +1459,7 @@ void onesweep_pass(const uint64_t *kin, uint64_t *kout, uint32_t n, int lo, int 
                       (uint32_t)pass + 1};
     k_rs_scatter<false, true><<<nt, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n,
                                                      lo + kRadixBits * pass, nullptr, nt, lb,
-                                                     nullptr);
+                                                     nullptr, nullptr);
 }
 
 const uint32_t *onesweep_fail_flag(const void *scratch)
@@ -1435,7 +1476,7 @@ size_t radix_hist_needed(uint32_t n)
 void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st)
 {
     const uint32_t nb = (n + kSortTile - 1) / kSortTile;
-    k_rs_hist<<<nb, kBlock, 0, st>>>(keys, n, shift, hist, nb, nullptr);
+    k_rs_hist<<<nb, kBlock, 0, st>>>(keys, n, shift, hist, nb, nullptr, nullptr);
 }
 
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st)
@@ -1451,24 +1492,48 @@ void launch_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
     const Lookback none{};
     if (vin)
         k_rs_scatter<true, false><<<nb, kBlock, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nb,
-                                                         none, nullptr);
+                                                         none, nullptr, nullptr);
     else
         k_rs_scatter<false, false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, n, shift,
-                                                          hist, nb, none, nullptr);
+                                                          hist, nb, none, nullptr, nullptr);
 }
 
-// One radix pass of a graph-replayed wave: n and the shift come from the wave
-// (digit `pass` above the qpos bits); the tiles and histogram layout are those of
-// hits_cap keys.
-void launch_rs_pass_ctl(const uint64_t *kin, uint64_t *kout, uint32_t hits_cap, int pass,
-                        uint32_t *hist, uint32_t *partials, const WaveCtl *ctl, hipStream_t st)
+// One radix pass within query segments, in three launches: digit counts per tile
+// of the table (in its segmented layout), their exclusive scan (ntile * 256
+// counts), the stable scatter.
+void launch_rs_hist_seg(const uint64_t *kin, uint32_t ntile, int shift, const SortTile *tiles,
+                        uint32_t *hist, hipStream_t st)
 {
-    const uint32_t nb = std::max<uint32_t>(1, (hits_cap + kSortTile - 1) / kSortTile);
-    k_rs_hist<<<nb, kBlock, 0, st>>>(kin, 0, pass, hist, nb, ctl);
-    launch_rs_scan(hist, hits_cap, partials, st);
+    if (ntile) k_rs_hist<<<ntile, kBlock, 0, st>>>(kin, 0, shift, hist, ntile, nullptr, tiles);
+}
+
+void launch_rs_scan_seg(uint32_t *hist, uint32_t ntile, uint32_t *partials, hipStream_t st)
+{
+    if (ntile) scan_impl<uint32_t, uint32_t>(hist, hist, (int64_t)ntile * kRadix, partials, st);
+}
+
+void launch_rs_scatter_seg(const uint64_t *kin, uint64_t *kout, uint32_t ntile, int shift,
+                           const SortTile *tiles, const uint32_t *hist, hipStream_t st)
+{
+    const Lookback none{};
+    if (ntile)
+        k_rs_scatter<false, false><<<ntile, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, 0, shift,
+                                                             hist, ntile, none, nullptr, tiles);
+}
+
+// The same pass for a graph-replayed wave: the wave's tiles (ctl->tile0,
+// ctl->ntile) and shift (digit `pass` above the qpos bits) are read on the device;
+// the grid and count layout cover ntile_cap tiles.
+void launch_rs_pass_ctl(const uint64_t *kin, uint64_t *kout, uint32_t ntile_cap, int pass,
+                        const SortTile *tiles, uint32_t *hist, uint32_t *partials,
+                        const WaveCtl *ctl, hipStream_t st)
+{
+    const uint32_t nb = std::max<uint32_t>(1, ntile_cap);
+    k_rs_hist<<<nb, kBlock, 0, st>>>(kin, 0, pass, hist, nb, ctl, tiles);
+    scan_impl<uint32_t, uint32_t>(hist, hist, (int64_t)nb * kRadix, partials, st);
     const Lookback none{};
     k_rs_scatter<false, false><<<nb, kBlock, 0, st>>>(kin, nullptr, kout, nullptr, 0, pass, hist,
-                                                      nb, none, ctl);
+                                                      nb, none, ctl, tiles);
 }
 
 int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,

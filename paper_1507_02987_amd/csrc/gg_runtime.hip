@@ -106,7 +106,7 @@ struct Workspace {
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
     DevBuf bplan, bcount, boff, bcands, btmp, bcoff, ctmp, cursor, qcur, bound_q, bound_off,
         btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue, gout, gn,
-        gctl, gplan, gcursor, goflags;
+        gctl, gplan, gcursor, goflags, stiles, gtiles;
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
     // the captured wave graph and what it was captured for (every argument baked
@@ -133,7 +133,7 @@ struct Workspace {
                          &cells_q, &bplan, &bcount, &boff, &bcands, &btmp, &bcoff, &ctmp, &cursor, &qcur,
                          &bound_q, &bound_off, &btmp_b, &bounds, &blist, &pcnt, &cells_box,
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
-                         &gcursor, &goflags};
+                         &gcursor, &goflags, &stiles, &gtiles};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -356,6 +356,23 @@ struct BatchOut {
     bool device = false;
     bool truncated = false;
 };
+
+// Radix tiles of hits sorted within query segments: the hits of the wave's query
+// ql are the next counts[ql] keys in gather order; each query gets whole tiles.
+void seg_tiles(const uint64_t *counts, int32_t nq, std::vector<SortTile> &out)
+{
+    out.clear();
+    uint64_t start = 0;
+    for (int32_t q = 0; q < nq; ++q) {
+        const uint32_t c = (uint32_t)counts[q];
+        const uint32_t nt = (c + kSortTile - 1) / kSortTile;
+        const uint32_t hbase = (uint32_t)out.size() * kRadix;
+        for (uint32_t t = 0; t < nt; ++t)
+            out.push_back(SortTile{(uint32_t)start + t * kSortTile,
+                                   std::min<uint32_t>(kSortTile, c - t * kSortTile), hbase, nt, t});
+        start += c;
+    }
+}
 
 // One query's search restricted to data-bank sequences [s_lo, s_hi) (used when
 // the query's hits overflow the per-call budget).  run_wave leaves the piece's
@@ -657,9 +674,21 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     if (grouping != kProbe && !bucketed) {
         // ---- global path: gather in place, stable LSD radix sort, chain
         TRY(ensure(ws->keys_alt, sizeof(uint64_t) * H));
-        TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(H)));
-        TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(H))));
+        // tiles within query segments: the passes skip the query bits of the keys
+        std::vector<uint64_t> qcounts((size_t)nqw);
+        for (int32_t ql = 0; ql < nqw; ++ql) qcounts[(size_t)ql] = piece ? piece->hits : qtot[qa + ql];
+        std::vector<SortTile> tiles;
+        seg_tiles(qcounts.data(), nqw, tiles);
+        const uint32_t nst = (uint32_t)tiles.size();
+        TRY(ensure(ws->stiles, sizeof(SortTile) * std::max<uint32_t>(nst, 1)));
+        if (nst)
+            HIPCHK(hipMemcpyAsync(ws->stiles.p, tiles.data(), sizeof(SortTile) * nst,
+                                  hipMemcpyHostToDevice, st));
+        const size_t nhist = std::max<size_t>(radix_hist_needed(H), (size_t)nst * kRadix + 1);
+        TRY(ensure(ws->hist, sizeof(uint32_t) * nhist));
+        TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed((int64_t)nhist)));
         const int sort_lo = lay.bp, sort_hi = lay.bp + lay.bd + lay.bs + lay.bq;
+        const int seg_hi = lay.bp + lay.bd + lay.bs;
         const uint64_t *sorted = nullptr;
         const uint32_t ntile = chain_tiles(H);
         TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
@@ -687,16 +716,18 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                     std::swap(kcur, knext);
                 }
             } else if (H > 1) {
-                for (int shift = sort_lo; shift < sort_hi; shift += kRadixBits) {
+                for (int shift = sort_lo; shift < seg_hi; shift += kRadixBits) {
                     prof.begin("sort_hist");
-                    launch_rs_hist(kcur, H, shift, as<uint32_t>(ws->hist), st);
+                    launch_rs_hist_seg(kcur, nst, shift, as<SortTile>(ws->stiles),
+                                       as<uint32_t>(ws->hist), st);
                     prof.end(H);
                     prof.begin("sort_scan");
-                    launch_rs_scan(as<uint32_t>(ws->hist), H, as<uint32_t>(ws->rs_partials), st);
+                    launch_rs_scan_seg(as<uint32_t>(ws->hist), nst, as<uint32_t>(ws->rs_partials),
+                                       st);
                     prof.end(H);
                     prof.begin("sort_scatter");
-                    launch_rs_scatter(kcur, nullptr, knext, nullptr, H, shift,
-                                      as<uint32_t>(ws->hist), st);
+                    launch_rs_scatter_seg(kcur, knext, nst, shift, as<SortTile>(ws->stiles),
+                                          as<uint32_t>(ws->hist), st);
                     prof.end(H);
                     std::swap(kcur, knext);
                 }
@@ -1120,8 +1151,22 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     lay.bq = bits_for((uint64_t)nq_cap);
     if (lay.bp + lay.bd + lay.bs + lay.bq > 64) return GG_OK;
     if ((uint64_t)maxL * (uint64_t)p->match >= (1ull << 30)) return GG_EINVAL;
-    for (WaveCtl &w : plan) w.lay = lay;
-    const int passes = (lay.bd + lay.bs + lay.bq + kRadixBits - 1) / kRadixBits;
+    // radix tiles within query segments, all waves in one table
+    std::vector<SortTile> tiles, wt;
+    std::vector<uint64_t> qc;
+    uint32_t ntile_max = 1;
+    for (WaveCtl &w : plan) {
+        w.lay = lay;
+        qc.assign(qtot.begin() + w.qa, qtot.begin() + w.qa + w.nqw);
+        seg_tiles(qc.data(), w.nqw, wt);
+        w.tile0 = (uint32_t)tiles.size();
+        w.ntile = (uint32_t)wt.size();
+        ntile_max = std::max(ntile_max, w.ntile);
+        tiles.insert(tiles.end(), wt.begin(), wt.end());
+    }
+    const uint32_t ntile_cap = (uint32_t)pow2_at_least(ntile_max);
+    const size_t tiles_cap = (size_t)pow2_at_least(std::max<uint64_t>(tiles.size(), 1));
+    const int passes = (lay.bd + lay.bs + kRadixBits - 1) / kRadixBits;
     const int32_t N = p->max_hits, cap = bo.cap;
     const uint32_t sel_cap = (uint32_t)N * (uint32_t)nq_cap;
     const uint32_t ntile = (hits_cap + kTile - 1) / kTile;
@@ -1135,8 +1180,10 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     TRY(ensure(ws->akey, sizeof(uint64_t) * (np_cap + 1)));
     TRY(ensure(ws->keys, sizeof(uint64_t) * hits_cap));
     TRY(ensure(ws->keys_alt, sizeof(uint64_t) * hits_cap));
-    TRY(ensure(ws->hist, sizeof(uint32_t) * radix_hist_needed(hits_cap)));
-    TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed(radix_hist_needed(hits_cap))));
+    TRY(ensure(ws->hist, sizeof(uint32_t) * ((size_t)ntile_cap * kRadix + 1)));
+    TRY(ensure(ws->rs_partials,
+               sizeof(uint32_t) * scan_partials_needed((int64_t)ntile_cap * kRadix + 1)));
+    TRY(ensure(ws->gtiles, sizeof(SortTile) * tiles_cap));
     TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
     TRY(ensure(ws->partials,
                sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nq_cap) + 1)));
@@ -1162,6 +1209,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     const uint64_t *sorted = (passes & 1) ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys);
     const int32_t steps = ix->tune_lane_steps.load();
     std::vector<uint64_t> key = {hits_cap, (uint64_t)np_cap, (uint64_t)nq_cap, (uint64_t)passes,
+                                 (uint64_t)ntile_cap,
                                  (uint64_t)lay.bp, (uint64_t)lay.bd, (uint64_t)lay.bs,
                                  (uint64_t)lay.bq, (uint64_t)(uint32_t)lay.bias, (uint64_t)cap,
                                  (uint64_t)(uint32_t)steps, (uint64_t)ix->k,
@@ -1175,7 +1223,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                             &ws->boxes2, &ws->boxes3, &ws->xqueue, &ws->qstart, &ws->qend,
                             &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
                             &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
-                            &ws->gplan, &ws->gcursor, &ws->goflags})
+                            &ws->gplan, &ws->gcursor, &ws->goflags, &ws->gtiles})
         key.push_back((uint64_t)(uintptr_t)b->p);
 
     if (!ws->gexec || ws->gkey != key) {
@@ -1194,8 +1242,9 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         for (int pass = 0; pass < passes; ++pass) {
             const bool odd = pass & 1;
             launch_rs_pass_ctl(odd ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys),
-                               odd ? as<uint64_t>(ws->keys) : as<uint64_t>(ws->keys_alt), hits_cap,
-                               pass, as<uint32_t>(ws->hist), as<uint32_t>(ws->rs_partials), ctl, st);
+                               odd ? as<uint64_t>(ws->keys) : as<uint64_t>(ws->keys_alt), ntile_cap,
+                               pass, as<SortTile>(ws->gtiles), as<uint32_t>(ws->hist),
+                               as<uint32_t>(ws->rs_partials), ctl, st);
         }
         launch_chain_ctl(sorted, hits_cap, ix->k, p->max_gap, p->min_hsp_len,
                          as<uint32_t>(ws->ccount), as<uint32_t>(ws->partials), as<Cand>(ws->cands),
@@ -1250,6 +1299,9 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     // replay it once per wave
     const size_t W = plan.size();
     HIPCHK(hipMemcpyAsync(ws->gplan.p, plan.data(), sizeof(WaveCtl) * W, hipMemcpyHostToDevice, st));
+    if (!tiles.empty())
+        HIPCHK(hipMemcpyAsync(ws->gtiles.p, tiles.data(), sizeof(SortTile) * tiles.size(),
+                              hipMemcpyHostToDevice, st));
     launch_fill_u32(cursor, 1, 0u, st);
     launch_fill_u32(as<uint32_t>(ws->gn), (size_t)nq, 0u, st);
     prof.begin("graph");
