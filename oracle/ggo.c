@@ -56,6 +56,16 @@ uint32_t ggo_kmer_code(const uint8_t *b, int32_t k)
     return c;
 }
 
+/* Section 2.1: a mask marks which bases of a window are kept ('1') or removed
+ * ('0'); the kept bases, in window order, form the code (first most significant). */
+uint32_t ggo_masked_code(const uint8_t *b, int32_t span, uint32_t mask)
+{
+    uint32_t c = 0;
+    for (int32_t t = 0; t < span; t++)
+        if ((mask >> t) & 1u) c = c * 4u + (uint32_t)b[t];
+    return c;
+}
+
 /* ------------------------------------------------------------------ O1: index
  * Section 2: the data bank is cut into NON-overlapping windows of k bases; a tail
  * shorter than k is not indexed [R].  Section 2.1: the main vector has 4^k
@@ -65,11 +75,43 @@ uint32_t ggo_kmer_code(const uint8_t *b, int32_t k)
  * windows, taken in (sequence, position) order, on their code (a counting sort),
  * so each list is in ascending (sequence, position) order, as the sort-based
  * inversion the paper cites produces. */
+static int32_t index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                           int32_t span, uint32_t mask, int32_t k, ggo_index **out);
+
 int32_t ggo_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
                         ggo_index **out)
 {
-    if (!out || k < 1 || k > 16 || n_seqs < 0 || (n_seqs > 0 && (!seqs || !seq_off)))
-        return GGO_EINVAL;
+    if (k < 1 || k > 16) return GGO_EINVAL;
+    return index_build(seqs, seq_off, n_seqs, k, (1u << k) - 1u, k, out);
+}
+
+/* Section 2.1 with a mask: the bank is cut into non-overlapping windows of the
+ * mask's length m; each window's code keeps the bases under the mask's '1's, so
+ * the main vector has 4^s entries for a mask of weight s.  A tail shorter than m
+ * is not indexed [R]. */
+int32_t ggo_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                               const char *mask, ggo_index **out)
+{
+    if (!mask) return GGO_EINVAL;
+    int32_t span = 0, weight = 0;
+    uint32_t bits = 0;
+    for (; mask[span]; span++) {
+        if (span >= 32) return GGO_EINVAL;
+        if (mask[span] == '1') {
+            bits |= 1u << span;
+            weight++;
+        } else if (mask[span] != '0') {
+            return GGO_EINVAL;
+        }
+    }
+    if (weight < 1 || weight > 16) return GGO_EINVAL;
+    return index_build(seqs, seq_off, n_seqs, span, bits, weight, out);
+}
+
+static int32_t index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                           int32_t span, uint32_t mask, int32_t k, ggo_index **out)
+{
+    if (!out || n_seqs < 0 || (n_seqs > 0 && (!seqs || !seq_off))) return GGO_EINVAL;
     *out = NULL;
     for (int64_t s = 0; s < n_seqs; s++)
         if (seq_off[s + 1] < seq_off[s] || seq_off[s + 1] - seq_off[s] > INT32_MAX)
@@ -79,6 +121,8 @@ int32_t ggo_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs
     ggo_index *ix = (ggo_index *)calloc(1, sizeof(ggo_index));
     if (!ix) return GGO_ENOMEM;
     ix->k = k;
+    ix->span = span;
+    ix->mask = mask;
     ix->n_seqs = n_seqs;
     ix->n_lists = (int64_t)1 << (2 * k);
     ix->seq_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_seqs + 1));
@@ -97,8 +141,8 @@ int32_t ggo_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs
     for (int64_t s = 0; s < n_seqs; s++) {
         const uint8_t *b = ix->base + ix->seq_off[s];
         int64_t n_s = ix->seq_off[s + 1] - ix->seq_off[s];
-        for (int64_t w = 0; (w + 1) * k <= n_s; w++)
-            ix->list_off[ggo_kmer_code(b + w * k, k) + 1] += 1;
+        for (int64_t w = 0; (w + 1) * span <= n_s; w++)
+            ix->list_off[ggo_masked_code(b + w * span, span, mask) + 1] += 1;
     }
     for (int64_t c = 0; c < ix->n_lists; c++) ix->list_off[c + 1] += ix->list_off[c];
     ix->n_post = ix->list_off[ix->n_lists];
@@ -111,11 +155,11 @@ int32_t ggo_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs
     for (int64_t s = 0; s < n_seqs; s++) {
         const uint8_t *b = ix->base + ix->seq_off[s];
         int64_t n_s = ix->seq_off[s + 1] - ix->seq_off[s];
-        for (int64_t w = 0; (w + 1) * k <= n_s; w++) {
-            uint32_t c = ggo_kmer_code(b + w * k, k);
+        for (int64_t w = 0; (w + 1) * span <= n_s; w++) {
+            uint32_t c = ggo_masked_code(b + w * span, span, mask);
             int64_t j = ix->list_off[c]++;
             ix->post_seq[j] = (int32_t)s;
-            ix->post_pos[j] = (int32_t)(w * k);
+            ix->post_pos[j] = (int32_t)(w * span);
         }
     }
     for (int64_t c = ix->n_lists; c > 0; c--) ix->list_off[c] = ix->list_off[c - 1];
@@ -137,34 +181,35 @@ void ggo_index_free(ggo_index *ix)
 
 /* ------------------------------------------------------------------ O2 + O3
  * Section 2 and 2.2: the query is read with OVERLAPPING windows, one at every
- * offset qpos in [0, L-k]; each code is its own slot in the main vector, and every
- * occurrence (s, dpos) stored there is retrieved.  Repeated query sub-sequences
- * are not deduplicated [R].  A hit is kept as (s, diag = dpos - qpos, qpos). */
+ * offset qpos in [0, L-m] (m = k, or the mask's length, the window read masked);
+ * each code is its own slot in the main vector, and every occurrence (s, dpos)
+ * stored there is retrieved.  Repeated query sub-sequences are not deduplicated
+ * [R].  A hit is kept as (s, diag = dpos - qpos, qpos). */
 int32_t ggo_hits(const ggo_index *ix, const uint8_t *q, int32_t L, ggo_hitrec **out, int64_t *n)
 {
-    const int32_t k = ix->k;
+    const int32_t m = ix->span;  /* with a mask, the window is read masked too */
     *out = NULL;
     *n = 0;
-    if (L < k) return GGO_OK;
+    if (L < m) return GGO_OK;
     int64_t count = 0;
-    for (int32_t qpos = 0; qpos + k <= L; qpos++) {
-        uint32_t c = ggo_kmer_code(q + qpos, k);
+    for (int32_t qpos = 0; qpos + m <= L; qpos++) {
+        uint32_t c = ggo_masked_code(q + qpos, m, ix->mask);
         count += ix->list_off[c + 1] - ix->list_off[c];
     }
     ggo_hitrec *h = (ggo_hitrec *)malloc(sizeof(ggo_hitrec) * (size_t)(count > 0 ? count : 1));
     if (!h) return GGO_ENOMEM;
-    int64_t m = 0;
-    for (int32_t qpos = 0; qpos + k <= L; qpos++) {
-        uint32_t c = ggo_kmer_code(q + qpos, k);
+    int64_t nh = 0;
+    for (int32_t qpos = 0; qpos + m <= L; qpos++) {
+        uint32_t c = ggo_masked_code(q + qpos, m, ix->mask);
         for (int64_t j = ix->list_off[c]; j < ix->list_off[c + 1]; j++) {
-            h[m].seq = ix->post_seq[j];
-            h[m].diag = ix->post_pos[j] - qpos;
-            h[m].qpos = qpos;
-            m++;
+            h[nh].seq = ix->post_seq[j];
+            h[nh].diag = ix->post_pos[j] - qpos;
+            h[nh].qpos = qpos;
+            nh++;
         }
     }
     *out = h;
-    *n = m;
+    *n = nh;
     return GGO_OK;
 }
 
@@ -496,8 +541,8 @@ int32_t ggo_search(const ggo_index *ix, const char *query, int64_t qlen, const g
     uint8_t *q = (uint8_t *)malloc((size_t)(L > 0 ? L : 1));
     if (!q) return GGO_ENOMEM;
     if (ggo_encode(query, L, q) != GGO_OK) { free(q); return GGO_EINVAL; }
-    if (L < ix->k) { free(q); return GGO_OK; }
-    st->n_kmers = L - ix->k + 1;
+    if (L < ix->span) { free(q); return GGO_OK; }
+    st->n_kmers = L - ix->span + 1;
 
     int32_t rc = GGO_OK;
     ggo_hitrec *hits = NULL;
@@ -509,7 +554,8 @@ int32_t ggo_search(const ggo_index *ix, const char *query, int64_t qlen, const g
     if ((rc = ggo_hits(ix, q, L, &hits, &nh)) != GGO_OK) goto done;
     st->n_hits = nh;
     ggo_group(hits, nh);
-    if ((rc = ggo_chain(hits, nh, ix->k, p->max_gap, p->min_hsp_len, &cands, &nc)) != GGO_OK)
+    /* a hit covers its window's whole span: runs and gaps are measured with it [R] */
+    if ((rc = ggo_chain(hits, nh, ix->span, p->max_gap, p->min_hsp_len, &cands, &nc)) != GGO_OK)
         goto done;
     st->n_cands = nc;
     boxes = (ggo_box *)malloc(sizeof(ggo_box) * (size_t)(nc > 0 ? nc : 1));

@@ -39,6 +39,8 @@ typedef struct {
     int32_t *post_seq;  /* sequence id of each occurrence */
     int32_t *post_pos;  /* position of the window inside that sequence */
     int64_t n_post;
+    int32_t span;       /* bases a window covers (the mask's length; k without a mask) */
+    uint32_t mask;      /* bit t set: the window's base t is part of its code */
 } ggo_index;
 
 typedef struct {
@@ -68,10 +70,17 @@ int32_t ggo_base_code(int32_t ch);
 int32_t ggo_encode(const char *s, int64_t n, uint8_t *out);
 /* O0/O2: integer of k coded bases, first base most significant [R]. */
 uint32_t ggo_kmer_code(const uint8_t *b, int32_t k);
+/* O0/O2 with a mask (Section 2.1): the code of the bases of a span-base window
+ * whose mask bit is set, in window order, first base most significant. */
+uint32_t ggo_masked_code(const uint8_t *b, int32_t span, uint32_t mask);
 
 /* O1: format the data bank and build the inverted index (Section 2.1). */
 int32_t ggo_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
                         ggo_index **out);
+/* O1 with a mask of '1' (kept) and '0' (removed) characters (Section 2.1): windows
+ * of the mask's length, codes of its weight (1..16); length at most 32. */
+int32_t ggo_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                               const char *mask, ggo_index **out);
 void ggo_index_free(ggo_index *ix);
 
 /* O2+O3: every (seq, diag, qpos) hit of the coded query, in generation order. */

@@ -51,7 +51,8 @@ class _Index(C.Structure):
     _fields_ = [("k", C.c_int32), ("n_seqs", C.c_int64), ("seq_off", C.POINTER(C.c_int64)),
                 ("base", C.POINTER(C.c_uint8)), ("n_lists", C.c_int64),
                 ("list_off", C.POINTER(C.c_int64)), ("post_seq", C.POINTER(C.c_int32)),
-                ("post_pos", C.POINTER(C.c_int32)), ("n_post", C.c_int64)]
+                ("post_pos", C.POINTER(C.c_int32)), ("n_post", C.c_int64),
+                ("span", C.c_int32), ("mask", C.c_uint32)]
 
 
 class _Stats(C.Structure):
@@ -77,6 +78,11 @@ def lib():
         L.ggo_kmer_code.restype = C.c_uint32
         L.ggo_index_build.argtypes = [vp, vp, i64, i32, C.POINTER(C.POINTER(_Index))]
         L.ggo_index_build.restype = i32
+        L.ggo_index_build_masked.argtypes = [vp, vp, i64, C.c_char_p,
+                                             C.POINTER(C.POINTER(_Index))]
+        L.ggo_index_build_masked.restype = i32
+        L.ggo_masked_code.argtypes = [vp, i32, C.c_uint32]
+        L.ggo_masked_code.restype = C.c_uint32
         L.ggo_index_free.argtypes = [C.POINTER(_Index)]
         L.ggo_hits.argtypes = [C.POINTER(_Index), vp, i32, C.POINTER(vp), P64]
         L.ggo_hits.restype = i32
@@ -131,19 +137,37 @@ def kmer_code(codes: np.ndarray, k: int) -> int:
     return int(lib().ggo_kmer_code(_ptr(codes), k))
 
 
-class Index:
-    """O1: the formatted data bank and its inverted index, owned by the C side."""
+def mask_bits(mask: str) -> int:
+    """Bit t set when the mask keeps the window's base t."""
+    return sum(1 << t for t, ch in enumerate(mask) if ch == "1")
 
-    def __init__(self, seqs: np.ndarray, off: np.ndarray, k: int):
+
+def masked_code(codes: np.ndarray, mask: str) -> int:
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    assert len(codes) >= len(mask)
+    return int(lib().ggo_masked_code(_ptr(codes), len(mask), mask_bits(mask)))
+
+
+class Index:
+    """O1: the formatted data bank and its inverted index, owned by the C side.
+    k windows, or windows of a mask's length coded on its '1' positions."""
+
+    def __init__(self, seqs: np.ndarray, off: np.ndarray, k: int = 0, mask: str | None = None):
         self._seqs = np.ascontiguousarray(seqs, dtype=np.uint8)
         self._off = np.ascontiguousarray(off, dtype=np.int64)
         p = C.POINTER(_Index)()
-        rc = lib().ggo_index_build(_ptr(self._seqs), _ptr(self._off), len(self._off) - 1, k,
-                                   C.byref(p))
+        if mask is not None:
+            rc = lib().ggo_index_build_masked(_ptr(self._seqs), _ptr(self._off),
+                                              len(self._off) - 1, mask.encode(), C.byref(p))
+        else:
+            rc = lib().ggo_index_build(_ptr(self._seqs), _ptr(self._off), len(self._off) - 1, k,
+                                       C.byref(p))
         if rc != 0:
             raise ValueError(f"ggo_index_build failed with status {rc}")
         self._p = p
-        self.k = k
+        self.k = int(p.contents.k)
+        self.span = int(p.contents.span)
+        self.mask = mask
 
     def __del__(self):
         if getattr(self, "_p", None):
