@@ -97,6 +97,18 @@ typedef struct {
  */
 gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
                          int32_t device, gg_index **out);
+/*
+ * The same index with a spaced-seed mask (Section 2.1): mask is a NUL-terminated
+ * string of '1' (base kept) and '0' (base removed), of length m <= 32 and weight s
+ * (number of '1's) 1..16.  The bank is cut into non-overlapping windows of m
+ * bases, coded on their s kept bases (4^s lists); queries are read with an
+ * overlapping window of m bases at every offset, coded the same way.  A hit
+ * covers its window's m bases: runs, gaps (G) and lengths (M) are measured with
+ * m.  A mask of k '1's gives exactly gg_index_build(k).  Errors as
+ * gg_index_build, and GG_EINVAL for a malformed mask.
+ */
+gg_status gg_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                                const char *mask, int32_t device, gg_index **out);
 void gg_index_free(gg_index *index);
 
 /* Sizes of a built index: windows indexed, bases, sequences, k. */

@@ -104,8 +104,9 @@ struct KeyWord {
 // Every launcher only enqueues work on `st`; sizes are checked by the caller.
 
 void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
-                         int32_t k, const uint32_t *list_off, uint8_t *qcode, uint32_t *kcode,
-                         uint32_t *cnt, int32_t *qid, int32_t *err, hipStream_t st);
+                         int32_t span, uint32_t mask, const uint32_t *list_off, uint8_t *qcode,
+                         uint32_t *kcode, uint32_t *cnt, int32_t *qid, int32_t *err,
+                         hipStream_t st);
 // out[i] = sum of in[0..i) for i in [0, n]; in is u32, out u64.
 void launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *partials,
                             hipStream_t st);
@@ -125,10 +126,10 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
 void launch_pack_bases(const uint8_t *ascii, int64_t total, uint32_t *dbw, int64_t nwords,
                        int32_t *err, hipStream_t st);
 void launch_window_keys(const uint32_t *dbw, const int64_t *seq_start, const uint32_t *woff,
-                        int32_t n_seqs, uint32_t n_win, int32_t k, uint64_t *keys, uint32_t *vals,
-                        uint32_t *counts, hipStream_t st);
+                        int32_t n_seqs, uint32_t n_win, int32_t span, uint32_t mask,
+                        uint64_t *keys, uint32_t *vals, uint32_t *counts, hipStream_t st);
 void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff, int32_t n_seqs,
-                     int32_t k, int2 *post, hipStream_t st);
+                     int32_t span, int2 *post, hipStream_t st);
 // A query searched by pieces over ranges of sequence ids: below[y] += its hits on
 // sequences < bounds[y]; per-position sub-lists of the range [s_lo, s_hi).
 void launch_range_counts(const uint32_t *kcode, const uint32_t *cnt, int64_t np,
@@ -147,9 +148,9 @@ void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *
 void launch_probe(const uint32_t *hrel, const uint32_t *pbase, int64_t np, const int2 *post,
                   uint32_t nhits, int64_t g0, const int32_t *qid, const int64_t *qoff, int32_t qa,
                   const uint32_t *kcode, const uint32_t *dbw, const int64_t *seq_start, int32_t k,
-                  int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap, uint32_t *ccount,
-                  uint32_t *cand_per_q, Bound *bounds, uint32_t bcap, uint32_t *bcount,
-                  uint32_t *bound_per_q, hipStream_t st);
+                  uint32_t mask, int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap,
+                  uint32_t *ccount, uint32_t *cand_per_q, Bound *bounds, uint32_t bcap,
+                  uint32_t *bcount, uint32_t *bound_per_q, hipStream_t st);
 void launch_bounds_by_query(const Bound *in, uint32_t n, const uint32_t *qoff_b, uint32_t *cur,
                             Bound *out, hipStream_t st);
 void launch_pair_bounds(const Bound *b, const uint32_t *qoff_b, int32_t nq, int32_t k,

@@ -47,6 +47,18 @@ __device__ __forceinline__ uint32_t db_window(const uint32_t *__restrict__ dbw, 
     return (uint32_t)((x << ((uint32_t)(g & 15) << 1)) >> (64 - 2 * k));
 }
 
+// Code of the window of `span` bases at global index g under a spaced-seed mask
+// (bit t set: base t kept; Section 2.1).  A mask of all ones is the plain window.
+__device__ __forceinline__ uint32_t db_code(const uint32_t *__restrict__ dbw, int64_t g,
+                                            int32_t span, uint32_t mask)
+{
+    if (span <= 16 && mask == (1u << span) - 1u) return db_window(dbw, g, span);
+    uint32_t c = 0;
+    for (int32_t t = 0; t < span; ++t)
+        if ((mask >> t) & 1u) c = c * 4u + (uint32_t)db_base(dbw, g + t);
+    return c;
+}
+
 // Exclusive scan over the 256 threads of a block; *total receives the block sum.
 template <typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T *total)
@@ -146,14 +158,14 @@ __device__ __forceinline__ int32_t window_seq(const uint32_t *__restrict__ woff,
 // pos) order: its code (the sort key), its number (the value) and a count per code.
 __global__ void k_window_keys(const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start,
                               const uint32_t *__restrict__ woff, int32_t n_seqs, uint32_t n_win,
-                              int32_t k, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                              uint32_t *__restrict__ counts)
+                              int32_t span, uint32_t mask, uint64_t *__restrict__ keys,
+                              uint32_t *__restrict__ vals, uint32_t *__restrict__ counts)
 {
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < n_win;
          w += gridDim.x * blockDim.x) {
         const int32_t s = window_seq(woff, n_seqs, w);
-        const int64_t g = seq_start[s] + (int64_t)(w - woff[s]) * k;
-        const uint32_t code = db_window(dbw, g, k);
+        const int64_t g = seq_start[s] + (int64_t)(w - woff[s]) * span;
+        const uint32_t code = db_code(dbw, g, span, mask);
         keys[w] = code;
         vals[w] = w;
         atomicAdd(&counts[code], 1u);
@@ -162,14 +174,14 @@ __global__ void k_window_keys(const uint32_t *__restrict__ dbw, const int64_t *_
 
 // Postings in list order: window number -> (sequence, position).
 __global__ void k_postings(const uint32_t *__restrict__ vals, uint32_t n_win,
-                           const uint32_t *__restrict__ woff, int32_t n_seqs, int32_t k,
+                           const uint32_t *__restrict__ woff, int32_t n_seqs, int32_t span,
                            int2 *__restrict__ post)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_win;
          i += gridDim.x * blockDim.x) {
         const uint32_t w = vals[i];
         const int32_t s = window_seq(woff, n_seqs, w);
-        post[i] = int2{s, (int32_t)((w - woff[s]) * (uint32_t)k)};
+        post[i] = int2{s, (int32_t)((w - woff[s]) * (uint32_t)span)};
     }
 }
 
@@ -182,21 +194,21 @@ void launch_pack_bases(const uint8_t *ascii, int64_t total, uint32_t *dbw, int64
 }
 
 void launch_window_keys(const uint32_t *dbw, const int64_t *seq_start, const uint32_t *woff,
-                        int32_t n_seqs, uint32_t n_win, int32_t k, uint64_t *keys, uint32_t *vals,
-                        uint32_t *counts, hipStream_t st)
+                        int32_t n_seqs, uint32_t n_win, int32_t span, uint32_t mask,
+                        uint64_t *keys, uint32_t *vals, uint32_t *counts, hipStream_t st)
 {
     if (n_win == 0) return;
     const uint32_t nb = std::min<uint32_t>((n_win + kBlock - 1) / kBlock, kMaxGrid);
-    k_window_keys<<<nb, kBlock, 0, st>>>(dbw, seq_start, woff, n_seqs, n_win, k, keys, vals,
-                                         counts);
+    k_window_keys<<<nb, kBlock, 0, st>>>(dbw, seq_start, woff, n_seqs, n_win, span, mask, keys,
+                                         vals, counts);
 }
 
 void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff, int32_t n_seqs,
-                     int32_t k, int2 *post, hipStream_t st)
+                     int32_t span, int2 *post, hipStream_t st)
 {
     if (n_win == 0) return;
     const uint32_t nb = std::min<uint32_t>((n_win + kBlock - 1) / kBlock, kMaxGrid);
-    k_postings<<<nb, kBlock, 0, st>>>(vals, n_win, woff, n_seqs, k, post);
+    k_postings<<<nb, kBlock, 0, st>>>(vals, n_win, woff, n_seqs, span, post);
 }
 
 // ------------------------------------------------------------------ S1/S2: encode + count
@@ -205,7 +217,7 @@ void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff,
 // code the window (first base most significant) and count its postings.
 __global__ __launch_bounds__(kBlock) void k_encode_kmers(
     const uint8_t *__restrict__ ascii, const int64_t *__restrict__ qoff, int32_t nq, int64_t T,
-    int32_t k, const uint32_t *__restrict__ list_off, uint8_t *__restrict__ qcode,
+    int32_t span, uint32_t mask, const uint32_t *__restrict__ list_off, uint8_t *__restrict__ qcode,
     uint32_t *__restrict__ kcode, uint32_t *__restrict__ cnt, int32_t *__restrict__ qid,
     int32_t *__restrict__ err)
 {
@@ -225,8 +237,9 @@ __global__ __launch_bounds__(kBlock) void k_encode_kmers(
     }
     qid[g] = lo;
     uint32_t code = 0, n = 0;
-    if (g + k <= qoff[lo + 1]) {
-        for (int32_t t = 0; t < k; ++t) {
+    if (g + span <= qoff[lo + 1]) {
+        for (int32_t t = 0; t < span; ++t) {
+            if (!((mask >> t) & 1u)) continue;  // a base the mask removes
             const int32_t b = base_code(ascii[g + t]);
             code = code * 4u + (uint32_t)(b < 0 ? 0 : b);
         }
@@ -237,13 +250,15 @@ __global__ __launch_bounds__(kBlock) void k_encode_kmers(
 }
 
 void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
-                         int32_t k, const uint32_t *list_off, uint8_t *qcode, uint32_t *kcode,
-                         uint32_t *cnt, int32_t *qid, int32_t *err, hipStream_t st)
+                         int32_t span, uint32_t mask, const uint32_t *list_off, uint8_t *qcode,
+                         uint32_t *kcode, uint32_t *cnt, int32_t *qid, int32_t *err,
+                         hipStream_t st)
 {
     if (T <= 0) return;
     const int64_t nb = (T + kBlock - 1) / kBlock;
-    k_encode_kmers<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(ascii, qoff, nq, T, k, list_off,
-                                                                qcode, kcode, cnt, qid, err);
+    k_encode_kmers<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(ascii, qoff, nq, T, span, mask,
+                                                                list_off, qcode, kcode, cnt, qid,
+                                                                err);
 }
 
 // ------------------------------------------------------------------ scans
@@ -911,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(
     const int2 *__restrict__ post, uint32_t nhits, int64_t g0, const int32_t *__restrict__ qid,
     const int64_t *__restrict__ qoff, int32_t qa, const uint32_t *__restrict__ kcode,
     const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t k,
-    int32_t mmax, int32_t M, Cand *__restrict__ cands, uint32_t ccap,
+    uint32_t mask, int32_t mmax, int32_t M, Cand *__restrict__ cands, uint32_t ccap,
     uint32_t *__restrict__ ccount, uint32_t *__restrict__ cand_per_q, Bound *__restrict__ bounds,
     uint32_t bcap, uint32_t *__restrict__ bcount, uint32_t *__restrict__ bound_per_q)
 {
@@ -983,10 +998,10 @@ __global__ __launch_bounds__(kBlock) void k_probe(
                 if (m > mmax) break;
                 const int32_t qp = qpos - m * k, dp = e.y - m * k;
                 if (qp >= 0 && dp >= 0)
-                    pred |= kcode[qb + qp] == db_window(dbw, s0 + dp, k);
+                    pred |= kcode[qb + qp] == db_code(dbw, s0 + dp, k, mask);
                 const int32_t qn = qpos + m * k, dn = e.y + m * k;
                 if (qn + k <= L && dn + k <= ns)
-                    succ |= kcode[qb + qn] == db_window(dbw, s0 + dn, k);
+                    succ |= kcode[qb + qn] == db_code(dbw, s0 + dn, k, mask);
             }
             sq = e.x;
             d = e.y - qpos;
@@ -1023,15 +1038,16 @@ __global__ __launch_bounds__(kBlock) void k_probe(
 void launch_probe(const uint32_t *hrel, const uint32_t *pbase, int64_t np, const int2 *post,
                   uint32_t nhits, int64_t g0, const int32_t *qid, const int64_t *qoff, int32_t qa,
                   const uint32_t *kcode, const uint32_t *dbw, const int64_t *seq_start, int32_t k,
-                  int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap, uint32_t *ccount,
-                  uint32_t *cand_per_q, Bound *bounds, uint32_t bcap, uint32_t *bcount,
-                  uint32_t *bound_per_q, hipStream_t st)
+                  uint32_t mask, int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap,
+                  uint32_t *ccount, uint32_t *cand_per_q, Bound *bounds, uint32_t bcap,
+                  uint32_t *bcount, uint32_t *bound_per_q, hipStream_t st)
 {
+    // k is the window span here; mask picks its coded bases
     if (nhits == 0) return;
     const uint32_t nb = (nhits + kTile - 1) / kTile;
     k_probe<<<nb, kBlock, 0, st>>>(hrel, pbase, np, post, nhits, g0, qid, qoff, qa, kcode, dbw,
-                                   seq_start, k, max_gap / k + 1, min_len, cands, ccap, ccount,
-                                   cand_per_q, bounds, bcap, bcount, bound_per_q);
+                                   seq_start, k, mask, max_gap / k + 1, min_len, cands, ccap,
+                                   ccount, cand_per_q, bounds, bcap, bcount, bound_per_q);
 }
 
 // Run bounds appended in any order go to their query's range (counting sort).

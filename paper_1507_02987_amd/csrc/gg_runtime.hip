@@ -146,7 +146,9 @@ struct Workspace {
 
 struct gg_index {
     int device = 0;
-    int32_t k = 0;
+    int32_t k = 0;       // bases in a window's code (the mask's weight)
+    int32_t span = 0;    // bases a window covers (the mask's length; k without a mask)
+    uint32_t mask = 0;   // bit t set: base t of a window is coded
     int64_t n_seqs = 0, n_bases = 0;
     uint64_t n_post = 0;
     int64_t max_seq_len = 0;
@@ -436,7 +438,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         if (bo.stats) {
             gg_stats &s = bo.stats[q];
             s = gg_stats{};
-            s.n_kmers = L >= ix->k ? L - ix->k + 1 : 0;
+            s.n_kmers = L >= ix->span ? L - ix->span + 1 : 0;
             s.n_hits = (int64_t)qtot[q];
         }
         if (!bo.device) bo.n_out[q] = 0;
@@ -506,7 +508,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         plan[nqw + ql] = (uint32_t)nb;
         nbk64 += nb;
     }
-    if (grouping == kProbe && p->max_gap / ix->k + 1 > kMaxProbe) grouping = kBucket;
+    if (grouping == kProbe && p->max_gap / ix->span + 1 > kMaxProbe) grouping = kBucket;
     if (grouping == kProbe) {
         // ---- S3 + S4 + S5 by probing: single-hit runs and run bounds, no stored hit
         uint32_t ccap = (uint32_t)std::max<uint64_t>(1u << 16, H / 64);
@@ -528,7 +530,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             prof.begin("probe");
             launch_probe(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), np, ix->d_post, H, g0,
                          as<int32_t>(ws->qid), as<int64_t>(ws->qoff), qa, as<uint32_t>(ws->kcode),
-                         ix->d_dbw, ix->d_seq_start, ix->k, p->max_gap, p->min_hsp_len,
+                         ix->d_dbw, ix->d_seq_start, ix->span, ix->mask, p->max_gap,
+                         p->min_hsp_len,
                          as<Cand>(ws->ctmp), ccap, as<uint32_t>(ws->cursor),
                          as<uint32_t>(ws->cand_q), as<Bound>(ws->btmp_b), bcap,
                          as<uint32_t>(ws->cursor) + 1, as<uint32_t>(ws->bound_q), st);
@@ -570,7 +573,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                 HIPCHK(hipMemsetAsync(ws->qcur.p, 0, sizeof(uint32_t) * nqw, st));
                 launch_bounds_by_query(as<Bound>(ws->btmp_b), nb, as<uint32_t>(ws->bound_off),
                                        as<uint32_t>(ws->qcur), as<Bound>(ws->bounds), st);
-                launch_pair_bounds(as<Bound>(ws->bounds), as<uint32_t>(ws->bound_off), nqw, ix->k,
+                launch_pair_bounds(as<Bound>(ws->bounds), as<uint32_t>(ws->bound_off), nqw, ix->span,
                                    p->min_hsp_len, as<Cand>(ws->ctmp), ccap,
                                    as<uint32_t>(ws->cursor), as<uint32_t>(ws->cand_q), st);
                 prof.end(nb);
@@ -641,13 +644,13 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                 if (attempt) HIPCHK(hipMemsetAsync(ws->cand_q.p, 0, sizeof(uint32_t) * nqw, st));
                 prof.begin("group");
                 launch_bucket_sort_chain(as<uint64_t>(ws->keys), as<uint32_t>(ws->boff), nbk, maxb,
-                                         lay, ix->k, p->max_gap, p->min_hsp_len,
+                                         lay, ix->span, p->max_gap, p->min_hsp_len,
                                          as<Cand>(ws->ctmp), ccap, as<uint32_t>(ws->cursor),
                                          as<uint32_t>(ws->btmp), as<uint32_t>(ws->bcands),
                                          as<uint32_t>(ws->cand_q), st);
                 launch_bucket_sort_chain_big(as<uint64_t>(ws->keys), as<uint32_t>(ws->boff),
                                              as<uint32_t>(ws->blist), (uint32_t)big.size(), maxb,
-                                             lay, ix->k, p->max_gap, p->min_hsp_len,
+                                             lay, ix->span, p->max_gap, p->min_hsp_len,
                                              as<Cand>(ws->ctmp), ccap, as<uint32_t>(ws->cursor),
                                              as<uint32_t>(ws->btmp), as<uint32_t>(ws->bcands),
                                              as<uint32_t>(ws->cand_q), st);
@@ -734,7 +737,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             }
             sorted = kcur;
             prof.begin("chain");
-            launch_chain_count(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
+            launch_chain_count(sorted, H, lay, ix->span, p->max_gap, p->min_hsp_len,
                                as<uint32_t>(ws->ccount), st);
             launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount), ntile,
                             as<uint32_t>(ws->partials), st);
@@ -754,7 +757,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             TRY(ensure(ws->qstart, sizeof(uint32_t) * (nqw + 1)));
             TRY(ensure(ws->qend, sizeof(uint32_t) * (nqw + 1)));
             prof.begin("chain_write");
-            launch_chain_write(sorted, H, lay, ix->k, p->max_gap, p->min_hsp_len,
+            launch_chain_write(sorted, H, lay, ix->span, p->max_gap, p->min_hsp_len,
                                as<uint32_t>(ws->ccount), as<Cand>(ws->cands), st);
             HIPCHK(hipMemsetAsync(ws->qstart.p, 0, sizeof(uint32_t) * nqw, st));
             HIPCHK(hipMemsetAsync(ws->qend.p, 0, sizeof(uint32_t) * nqw, st));
@@ -1073,7 +1076,7 @@ gg_status search_pieces(const gg_index *ix, Workspace *ws, Prof &prof, const gg_
     }
     if (bo.stats) {
         gg_stats &s = bo.stats[q];
-        s.n_kmers = L >= ix->k ? L - ix->k + 1 : 0;
+        s.n_kmers = L >= ix->span ? L - ix->span + 1 : 0;
         s.n_hits = (int64_t)qtot[q];
         s.n_cands = n_cands;
         s.n_merged = n_merged;
@@ -1212,7 +1215,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                                  (uint64_t)ntile_cap,
                                  (uint64_t)lay.bp, (uint64_t)lay.bd, (uint64_t)lay.bs,
                                  (uint64_t)lay.bq, (uint64_t)(uint32_t)lay.bias, (uint64_t)cap,
-                                 (uint64_t)(uint32_t)steps, (uint64_t)ix->k,
+                                 (uint64_t)(uint32_t)steps, (uint64_t)ix->span,
+                                 (uint64_t)ix->mask,
                                  (uint64_t)(uintptr_t)ix->d_post};
     for (int32_t v : {p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, p->xdrop,
                       p->max_gap, p->min_hsp_len, p->max_hits})
@@ -1246,7 +1250,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                                pass, as<SortTile>(ws->gtiles), as<uint32_t>(ws->hist),
                                as<uint32_t>(ws->rs_partials), ctl, st);
         }
-        launch_chain_ctl(sorted, hits_cap, ix->k, p->max_gap, p->min_hsp_len,
+        launch_chain_ctl(sorted, hits_cap, ix->span, p->max_gap, p->min_hsp_len,
                          as<uint32_t>(ws->ccount), as<uint32_t>(ws->partials), as<Cand>(ws->cands),
                          ctl, st);
         launch_fill_u32(as<uint32_t>(ws->qstart), nq_cap, 0u, st);
@@ -1375,7 +1379,7 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
 
     // ---- S1 encode + S2 count and scan
     prof.begin("encode");
-    launch_encode_kmers(ascii, as<int64_t>(ws->qoff), (int32_t)nq, T, ix->k,
+    launch_encode_kmers(ascii, as<int64_t>(ws->qoff), (int32_t)nq, T, ix->span, ix->mask,
                         ix->d_list_off, as<uint8_t>(ws->qcode), as<uint32_t>(ws->kcode),
                         as<uint32_t>(ws->cnt), as<int32_t>(ws->qid), as<int32_t>(ws->err), st);
     prof.end(T);
@@ -1505,12 +1509,17 @@ void gg_index_free(gg_index *ix)
 // Formatting and index construction (Sections 2, 2.1), on the GPU: the bases are
 // uploaded once, packed and windowed by kernels; the lists are a stable sort of
 // the windows by code, so each list keeps (sequence, position) order.
-gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
-                         int32_t device, gg_index **out)
+namespace {
+
+// Windows of `span` bases coded on the bases of `mask` (k of them); the plain
+// index is span = k with every base coded.
+gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t span,
+                      uint32_t mask, int32_t k, int32_t device, gg_index **out)
 {
     if (!out) return GG_EINVAL;
     *out = nullptr;
-    if (k < 1 || k > 16 || n_seqs < 0 || n_seqs > INT32_MAX) return GG_EINVAL;
+    if (k < 1 || k > 16 || span < k || span > 32 || n_seqs < 0 || n_seqs > INT32_MAX)
+        return GG_EINVAL;
     if (n_seqs > 0 && (!seq_off || !seqs)) return GG_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GG_EDEVICE;
@@ -1528,7 +1537,7 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
     uint64_t n_post = 0;
     for (int64_t s = 0; s < n_seqs; ++s) {
         woff[(size_t)s] = (uint32_t)std::min<uint64_t>(n_post, 0xffffffffull);
-        n_post += (uint64_t)((seq_off[s + 1] - seq_off[s]) / k);
+        n_post += (uint64_t)((seq_off[s + 1] - seq_off[s]) / span);
         seq_start[(size_t)s] = seq_off[s] - base0;
     }
     if (n_post >= 0xffffffffull) return GG_EINVAL;
@@ -1541,6 +1550,8 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
     if (!ix) return GG_ENOMEM;
     ix->device = device;
     ix->k = k;
+    ix->span = span;
+    ix->mask = mask;
     ix->n_seqs = n_seqs;
     ix->n_bases = total;
     ix->n_post = n_post;
@@ -1619,12 +1630,12 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
             hipMemsetAsync(ix->d_list_off, 0, sizeof(uint32_t) * (ncode + 1), bst) != hipSuccess)
             return fail(GG_EDEVICE);
         launch_pack_bases(d_ascii, total, ix->d_dbw, nwords, d_err, bst);
-        launch_window_keys(ix->d_dbw, ix->d_seq_start, d_woff, (int32_t)n_seqs, nw, k, d_keys,
-                           d_vals, ix->d_list_off, bst);
+        launch_window_keys(ix->d_dbw, ix->d_seq_start, d_woff, (int32_t)n_seqs, nw, span, mask,
+                           d_keys, d_vals, ix->d_list_off, bst);
         launch_scan_u32(ix->d_list_off, ix->d_list_off, (int64_t)ncode, d_parts, bst);
         const int cur = radix_sort(d_keys, d_keys2, d_vals, d_vals2, nw, 0, 2 * k, d_hist, d_parts,
                                    bst);
-        launch_postings(cur ? d_vals2 : d_vals, nw, d_woff, (int32_t)n_seqs, k, ix->d_post, bst);
+        launch_postings(cur ? d_vals2 : d_vals, nw, d_woff, (int32_t)n_seqs, span, ix->d_post, bst);
         if (hipMemcpyAsync(&err, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, bst) != hipSuccess ||
             hipStreamSynchronize(bst) != hipSuccess || hipGetLastError() != hipSuccess)
             return fail(GG_EDEVICE);
@@ -1645,6 +1656,38 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
     (void)hipGetLastError();
     *out = ix;
     return GG_OK;
+}
+
+}  // namespace
+
+gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t k,
+                         int32_t device, gg_index **out)
+{
+    if (k < 1 || k > 16) {
+        if (out) *out = nullptr;
+        return GG_EINVAL;
+    }
+    return index_build(seqs, seq_off, n_seqs, k, (1u << k) - 1u, k, device, out);
+}
+
+gg_status gg_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                                const char *mask, int32_t device, gg_index **out)
+{
+    if (out) *out = nullptr;
+    if (!mask) return GG_EINVAL;
+    int32_t span = 0, weight = 0;
+    uint32_t bits = 0;
+    for (; mask[span]; ++span) {
+        if (span >= 32) return GG_EINVAL;
+        if (mask[span] == '1') {
+            bits |= 1u << span;
+            ++weight;
+        } else if (mask[span] != '0') {
+            return GG_EINVAL;
+        }
+    }
+    if (weight < 1 || weight > 16) return GG_EINVAL;
+    return index_build(seqs, seq_off, n_seqs, span, bits, weight, device, out);
 }
 
 gg_status gg_index_info(const gg_index *ix, int64_t *n_postings, int64_t *n_bases, int64_t *n_seqs,

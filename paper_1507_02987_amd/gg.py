@@ -25,7 +25,8 @@ STAT_FIELDS = ("n_kmers", "n_hits", "n_cands", "n_merged", "n_selected", "n_cell
 STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 
 # Exported symbols of include/gg.h, in declaration order.
-SYMBOLS = ("gg_index_build", "gg_index_free", "gg_index_info", "gg_index_set_hit_budget",
+SYMBOLS = ("gg_index_build", "gg_index_build_masked", "gg_index_free", "gg_index_info",
+           "gg_index_set_hit_budget",
            "gg_index_get_tuning", "gg_index_set_tuning", "gg_index_autotune",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
            "gg_device_free", "gg_memcpy_to_device", "gg_memcpy_to_host", "gg_device_copy",
@@ -71,6 +72,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
         L.gg_index_build.argtypes = [vp, vp, i64, i32, i32, C.POINTER(vp)]
+        L.gg_index_build_masked.argtypes = [vp, vp, i64, C.c_char_p, i32, C.POINTER(vp)]
         L.gg_index_free.argtypes = [vp]
         L.gg_index_free.restype = None
         L.gg_index_info.argtypes = [vp, vp, vp, vp, vp]
@@ -116,16 +118,27 @@ def _u8(x) -> np.ndarray:
 class Index:
     """gg_index_build / gg_index_free: device-resident data bank and inverted index."""
 
-    def __init__(self, seqs, seq_off, k: int, device: int = 0):
+    def __init__(self, seqs, seq_off, k: int = 0, device: int = 0, mask: str | None = None):
+        """k: contiguous windows of k bases; mask: a '0'/'1' spaced-seed mask instead
+        (gg_index_build_masked), whose weight is then the index's k."""
         s = _u8(seqs)
         off = np.ascontiguousarray(seq_off, dtype=np.int64)
         h = C.c_void_p()
-        rc = lib().gg_index_build(_ptr(s) if len(s) else None, _ptr(off), len(off) - 1, k, device,
-                                  C.byref(h))
+        if mask is not None:
+            rc = lib().gg_index_build_masked(_ptr(s) if len(s) else None, _ptr(off), len(off) - 1,
+                                             mask.encode(), device, C.byref(h))
+            name = "gg_index_build_masked"
+            k = mask.count("1")
+        else:
+            rc = lib().gg_index_build(_ptr(s) if len(s) else None, _ptr(off), len(off) - 1, k,
+                                      device, C.byref(h))
+            name = "gg_index_build"
         if rc != GG_OK:
-            raise GGError(rc, "gg_index_build")
+            raise GGError(rc, name)
         self._h = h
         self.k = k
+        self.mask = mask
+        self.span = len(mask) if mask is not None else k
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
