@@ -108,6 +108,102 @@ int32_t ggo_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t
     return index_build(seqs, seq_off, n_seqs, span, bits, weight, out);
 }
 
+/* Both strands [R]: the paper indexes one strand only.  The option adds, after the
+ * n given sequences, the reverse complement of each (sequence n + s is sequence s
+ * read backwards with every base replaced by its pair: A-T, C-G; U pairs with A),
+ * and indexes all 2n in the same way, so a query is compared with both strands of
+ * every bank sequence and its hits on the reverse strand are reported on the
+ * reverse complement's own coordinates.  A byte that is not a base is copied as
+ * it is, so the coding step rejects it on either strand.
+ *
+ * Repeat cutoff [R]: the paper keeps every occurrence.  With max_posting > 0 a
+ * list holding more than max_posting occurrences is dropped whole, so its
+ * windows give no hits; the other lists are unchanged. */
+static char complement_base(char ch)
+{
+    switch (ch) {
+    case 'A': case 'a': return 'T';
+    case 'C': case 'c': return 'G';
+    case 'G': case 'g': return 'C';
+    case 'T': case 't': case 'U': case 'u': return 'A';
+    default: return ch;
+    }
+}
+
+static int32_t drop_long_lists(ggo_index *ix, int64_t max_posting)
+{
+    int64_t *keep_off = (int64_t *)calloc((size_t)(ix->n_lists + 1), sizeof(int64_t));
+    if (!keep_off) return GGO_ENOMEM;
+    for (int64_t c = 0; c < ix->n_lists; c++) {
+        int64_t len = ix->list_off[c + 1] - ix->list_off[c];
+        keep_off[c + 1] = keep_off[c] + (len > max_posting ? 0 : len);
+    }
+    /* move each kept list down to its new start (never past its old start) */
+    for (int64_t c = 0; c < ix->n_lists; c++) {
+        if (keep_off[c + 1] == keep_off[c]) continue;
+        for (int64_t j = 0; j < keep_off[c + 1] - keep_off[c]; j++) {
+            ix->post_seq[keep_off[c] + j] = ix->post_seq[ix->list_off[c] + j];
+            ix->post_pos[keep_off[c] + j] = ix->post_pos[ix->list_off[c] + j];
+        }
+    }
+    free(ix->list_off);
+    ix->list_off = keep_off;
+    ix->n_post = keep_off[ix->n_lists];
+    return GGO_OK;
+}
+
+int32_t ggo_index_build_opts(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                             int32_t k, const char *mask, int32_t strands, int64_t max_posting,
+                             ggo_index **out)
+{
+    if (!out) return GGO_EINVAL;
+    *out = NULL;
+    if ((strands != 1 && strands != 2) || max_posting < 0 || n_seqs < 0 ||
+        (n_seqs > 0 && (!seqs || !seq_off)))
+        return GGO_EINVAL;
+    int32_t rc;
+    if (strands == 1) {
+        rc = mask ? ggo_index_build_masked(seqs, seq_off, n_seqs, mask, out)
+                  : ggo_index_build(seqs, seq_off, n_seqs, k, out);
+    } else {
+        int64_t base0 = n_seqs > 0 ? seq_off[0] : 0;
+        int64_t total = n_seqs > 0 ? seq_off[n_seqs] - base0 : 0;
+        for (int64_t s = 0; s < n_seqs; s++)
+            if (seq_off[s + 1] < seq_off[s]) return GGO_EINVAL;
+        char *both = (char *)malloc((size_t)(2 * total + 1));
+        int64_t *both_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * n_seqs + 1));
+        if (!both || !both_off) {
+            free(both);
+            free(both_off);
+            return GGO_ENOMEM;
+        }
+        if (total > 0) memcpy(both, seqs + base0, (size_t)total);
+        both_off[0] = 0;
+        for (int64_t s = 0; s < n_seqs; s++) both_off[s + 1] = seq_off[s + 1] - base0;
+        for (int64_t s = 0; s < n_seqs; s++) {
+            int64_t lo = seq_off[s] - base0, n_s = seq_off[s + 1] - seq_off[s];
+            int64_t at = both_off[n_seqs + s];
+            for (int64_t i = 0; i < n_s; i++)
+                both[at + i] = complement_base(seqs[base0 + lo + n_s - 1 - i]);
+            both_off[n_seqs + s + 1] = at + n_s;
+        }
+        rc = mask ? ggo_index_build_masked(both, both_off, 2 * n_seqs, mask, out)
+                  : ggo_index_build(both, both_off, 2 * n_seqs, k, out);
+        free(both);
+        free(both_off);
+    }
+    if (rc != GGO_OK) return rc;
+    (*out)->strands = strands;
+    if (max_posting > 0) {
+        rc = drop_long_lists(*out, max_posting);
+        if (rc != GGO_OK) {
+            ggo_index_free(*out);
+            *out = NULL;
+        }
+    }
+    return rc;
+}
+
 static int32_t index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
                            int32_t span, uint32_t mask, int32_t k, ggo_index **out)
 {
@@ -123,6 +219,7 @@ static int32_t index_build(const char *seqs, const int64_t *seq_off, int64_t n_s
     ix->k = k;
     ix->span = span;
     ix->mask = mask;
+    ix->strands = 1;
     ix->n_seqs = n_seqs;
     ix->n_lists = (int64_t)1 << (2 * k);
     ix->seq_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_seqs + 1));

@@ -41,6 +41,7 @@ typedef struct {
     int64_t n_post;
     int32_t span;       /* bases a window covers (the mask's length; k without a mask) */
     uint32_t mask;      /* bit t set: the window's base t is part of its code */
+    int32_t strands;    /* 2: sequences n_seqs/2 .. are the reverse complements of the first half */
 } ggo_index;
 
 typedef struct {
@@ -81,6 +82,12 @@ int32_t ggo_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs
  * of the mask's length, codes of its weight (1..16); length at most 32. */
 int32_t ggo_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
                                const char *mask, ggo_index **out);
+/* O1 with options [R]: k windows, or a mask (non-NULL) as above; strands 2 also
+ * indexes the reverse complement of every sequence, as sequence n_seqs + s;
+ * max_posting > 0 drops every list longer than it (0 keeps all). */
+int32_t ggo_index_build_opts(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                             int32_t k, const char *mask, int32_t strands, int64_t max_posting,
+                             ggo_index **out);
 void ggo_index_free(ggo_index *ix);
 
 /* O2+O3: every (seq, diag, qpos) hit of the coded query, in generation order. */

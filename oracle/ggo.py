@@ -52,7 +52,7 @@ class _Index(C.Structure):
                 ("base", C.POINTER(C.c_uint8)), ("n_lists", C.c_int64),
                 ("list_off", C.POINTER(C.c_int64)), ("post_seq", C.POINTER(C.c_int32)),
                 ("post_pos", C.POINTER(C.c_int32)), ("n_post", C.c_int64),
-                ("span", C.c_int32), ("mask", C.c_uint32)]
+                ("span", C.c_int32), ("mask", C.c_uint32), ("strands", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -81,6 +81,9 @@ def lib():
         L.ggo_index_build_masked.argtypes = [vp, vp, i64, C.c_char_p,
                                              C.POINTER(C.POINTER(_Index))]
         L.ggo_index_build_masked.restype = i32
+        L.ggo_index_build_opts.argtypes = [vp, vp, i64, i32, C.c_char_p, i32, i64,
+                                           C.POINTER(C.POINTER(_Index))]
+        L.ggo_index_build_opts.restype = i32
         L.ggo_masked_code.argtypes = [vp, i32, C.c_uint32]
         L.ggo_masked_code.restype = C.c_uint32
         L.ggo_index_free.argtypes = [C.POINTER(_Index)]
@@ -150,13 +153,20 @@ def masked_code(codes: np.ndarray, mask: str) -> int:
 
 class Index:
     """O1: the formatted data bank and its inverted index, owned by the C side.
-    k windows, or windows of a mask's length coded on its '1' positions."""
+    k windows, or windows of a mask's length coded on its '1' positions; strands=2
+    adds every sequence's reverse complement (as sequence n + s); max_posting > 0
+    drops the lists longer than it."""
 
-    def __init__(self, seqs: np.ndarray, off: np.ndarray, k: int = 0, mask: str | None = None):
+    def __init__(self, seqs: np.ndarray, off: np.ndarray, k: int = 0, mask: str | None = None,
+                 strands: int = 1, max_posting: int = 0):
         self._seqs = np.ascontiguousarray(seqs, dtype=np.uint8)
         self._off = np.ascontiguousarray(off, dtype=np.int64)
         p = C.POINTER(_Index)()
-        if mask is not None:
+        if strands != 1 or max_posting != 0:
+            rc = lib().ggo_index_build_opts(_ptr(self._seqs), _ptr(self._off), len(self._off) - 1,
+                                            k, mask.encode() if mask is not None else None,
+                                            strands, max_posting, C.byref(p))
+        elif mask is not None:
             rc = lib().ggo_index_build_masked(_ptr(self._seqs), _ptr(self._off),
                                               len(self._off) - 1, mask.encode(), C.byref(p))
         else:
@@ -168,6 +178,8 @@ class Index:
         self.k = int(p.contents.k)
         self.span = int(p.contents.span)
         self.mask = mask
+        self.strands = int(p.contents.strands)
+        self.n_seqs = int(p.contents.n_seqs)
 
     def __del__(self):
         if getattr(self, "_p", None):

@@ -393,6 +393,25 @@ def random_db(seed: int, n_seqs: int, lmin: int, lmax: int) -> Database:
     return Database(_uniform_bases(rng, int(lengths.sum())), _offsets(lengths), f"random{seed}")
 
 
+def repeat_db(seed: int, n_seqs: int, lmin: int, lmax: int, frac_repeat: float = 0.3) -> Database:
+    """A tiny uniform data bank where about frac_repeat of the sequences carry one
+    tandem repeat (unit of 1-4 bases, 30-400 bases long) at a uniform offset, so a
+    few posting lists grow long, as low-complexity regions make them."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([ROOT_SEED, 9, seed])))
+    lengths = rng.integers(lmin, lmax + 1, size=n_seqs).astype(np.int64)
+    seqs = _uniform_bases(rng, int(lengths.sum()))
+    off = _offsets(lengths)
+    for s in range(n_seqs):
+        n = int(lengths[s])
+        if n < 30 or rng.random() >= frac_repeat:
+            continue
+        unit = _uniform_bases(rng, int(rng.integers(1, 5)))
+        rl = int(rng.integers(30, min(400, n) + 1))
+        at = int(off[s]) + int(rng.integers(0, n - rl + 1))
+        seqs[at:at + rl] = np.resize(unit, rl)
+    return Database(seqs, off, f"repeat{seed}")
+
+
 def random_queries(seed: int, db: Database, n: int, lmin: int, lmax: int, frac_homolog: float,
                    ident_lo: float, ident_hi: float, indel_rate: float) -> QuerySet:
     """Tiny mixed query sets for unit and parity tests."""
