@@ -109,7 +109,49 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
  */
 gg_status gg_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
                                 const char *mask, int32_t device, gg_index **out);
+/*
+ * The general builder: a k-base window (mask NULL) or a spaced-seed mask as above,
+ * and two options the paper does not have.
+ *
+ * strands = 2 indexes both strands of the bank: after the n given sequences, the
+ * index holds the reverse complement of each, as sequence n + s (sequence s read
+ * from its end, A<->T, C<->G, U pairing with A), indexed like any other.  A search
+ * therefore compares the query with both strands of every sequence, in one
+ * selection of the N longest boxes; a hit with seq_id >= n lies on the reverse
+ * strand of sequence seq_id - n, and its d_ coordinates count on that reverse
+ * complement (forward position = length - 1 - reverse position).  gg_index_info
+ * then reports 2n sequences and twice the bases.  strands = 1 is the paper's
+ * single-strand index.
+ *
+ * max_posting > 0 is a repeat cutoff: every list holding more than max_posting
+ * occurrences is dropped whole (its query windows give no hits), which bounds the
+ * hits that low-complexity regions create; 0 keeps every occurrence, as the paper
+ * does.  Other lists are unchanged.
+ *
+ * Errors as gg_index_build; GG_EINVAL for strands outside {1, 2}, a negative
+ * max_posting, a malformed mask, or 2n above 2^31 - 1 sequences.
+ */
+typedef struct {
+    int32_t k;            /* window length 1..16, used when mask is NULL */
+    const char *mask;     /* spaced-seed mask ('1' kept, '0' removed), or NULL */
+    int32_t strands;      /* 1 or 2 */
+    int64_t max_posting;  /* > 0: drop lists longer than this; 0: keep all */
+} gg_index_options;
+gg_status gg_index_build_ex(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                            const gg_index_options *opt, int32_t device, gg_index **out);
 void gg_index_free(gg_index *index);
+
+/*
+ * Copy a built index to host memory (Section 2.1's main vector and lists):
+ * list_off receives the 4^k + 1 list heads (list c holds postings
+ * [list_off[c], list_off[c + 1])), postings the n_postings (sequence id, position)
+ * pairs as 2 x int32 each, lists in code order and each list in (sequence,
+ * position) order.  Either pointer may be NULL to skip it.  The caller owns both
+ * buffers; cap_postings is the pairs postings can hold: GG_ETRUNC (nothing
+ * copied) when it is below n_postings.  GG_EDEVICE on a copy failure.
+ */
+gg_status gg_index_export(const gg_index *index, uint32_t *list_off, int32_t *postings,
+                          int64_t cap_postings);
 
 /* Sizes of a built index: windows indexed, bases, sequences, k. */
 gg_status gg_index_info(const gg_index *index, int64_t *n_postings, int64_t *n_bases,

@@ -130,6 +130,17 @@ void launch_window_keys(const uint32_t *dbw, const int64_t *seq_start, const uin
                         uint64_t *keys, uint32_t *vals, uint32_t *counts, hipStream_t st);
 void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff, int32_t n_seqs,
                      int32_t span, int2 *post, hipStream_t st);
+// Both strands: dst holds each sequence's reverse complement at the sequence's own
+// start (start: n_seqs + 1 forward starts).
+void launch_reverse_strand(const uint8_t *src, const int64_t *start, int32_t n_seqs, uint8_t *dst,
+                           hipStream_t st);
+// Repeat cutoff: kept list lengths (0 for a list longer than max_posting), and the
+// postings of kept lists placed at their kept heads.
+void launch_cut_counts(const uint32_t *off, uint32_t ncode, uint32_t max_posting, uint32_t *kept,
+                       hipStream_t st);
+void launch_postings_cut(const uint32_t *vals, const uint64_t *keys, uint32_t n_win,
+                         const uint32_t *woff, int32_t n_seqs, int32_t span, const uint32_t *off,
+                         const uint32_t *kept_off, uint32_t max_posting, int2 *post, hipStream_t st);
 // A query searched by pieces over ranges of sequence ids: below[y] += its hits on
 // sequences < bounds[y]; per-position sub-lists of the range [s_lo, s_hi).
 void launch_range_counts(const uint32_t *kcode, const uint32_t *cnt, int64_t np,
@@ -147,7 +158,8 @@ void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *
 // and paired per query.  Runs in any order are finally grouped by query.
 void launch_probe(const uint32_t *hrel, const uint32_t *pbase, int64_t np, const int2 *post,
                   uint32_t nhits, int64_t g0, const int32_t *qid, const int64_t *qoff, int32_t qa,
-                  const uint32_t *kcode, const uint32_t *dbw, const int64_t *seq_start, int32_t k,
+                  const uint32_t *kcode, const uint32_t *kcnt, const uint32_t *dbw,
+                  const int64_t *seq_start, int32_t k,
                   uint32_t mask, int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap,
                   uint32_t *ccount, uint32_t *cand_per_q, Bound *bounds, uint32_t bcap,
                   uint32_t *bcount, uint32_t *bound_per_q, hipStream_t st);

@@ -185,6 +185,88 @@ __global__ void k_postings(const uint32_t *__restrict__ vals, uint32_t n_win,
     }
 }
 
+// The paired base of an ASCII base on the other strand (A-T, C-G; U pairs with
+// A); any other byte is returned unchanged, so packing still rejects it.
+__device__ __forceinline__ uint8_t paired_base(uint8_t ch)
+{
+    switch (ch) {
+    case 'A': case 'a': return 'T';
+    case 'C': case 'c': return 'G';
+    case 'G': case 'g': return 'C';
+    case 'T': case 't': case 'U': case 'u': return 'A';
+    default: return ch;
+    }
+}
+
+// Reverse strand of every sequence: dst[start[s] + i] = pair of src[start[s] + n_s - 1 - i],
+// with start and n_s from the forward sequence starts.  One block per sequence
+// (grid-stride over sequences), its threads striding through the bases.
+__global__ void k_reverse_strand(const uint8_t *__restrict__ src, const int64_t *__restrict__ start,
+                                 int32_t n_seqs, uint8_t *__restrict__ dst)
+{
+    for (int32_t s = blockIdx.x; s < n_seqs; s += gridDim.x) {
+        const int64_t lo = start[s], n = start[s + 1] - lo;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+            dst[lo + i] = paired_base(src[lo + n - 1 - i]);
+    }
+}
+
+// Repeat cutoff: kept[c] = length of list c (heads in off) if it is at most
+// max_posting, else 0.
+__global__ void k_cut_counts(const uint32_t *__restrict__ off, uint32_t ncode, uint32_t max_posting,
+                             uint32_t *__restrict__ kept)
+{
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncode;
+         c += gridDim.x * blockDim.x) {
+        const uint32_t len = off[c + 1] - off[c];
+        kept[c] = len > max_posting ? 0u : len;
+    }
+}
+
+// Postings of the kept lists only: window i of the code-sorted order (code keys[i])
+// moves from its place in list c of the full heads (off) to the same place in
+// list c of the kept heads (kept_off); windows of dropped lists are skipped.
+__global__ void k_postings_cut(const uint32_t *__restrict__ vals, const uint64_t *__restrict__ keys,
+                               uint32_t n_win, const uint32_t *__restrict__ woff, int32_t n_seqs,
+                               int32_t span, const uint32_t *__restrict__ off,
+                               const uint32_t *__restrict__ kept_off, uint32_t max_posting,
+                               int2 *__restrict__ post)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_win;
+         i += gridDim.x * blockDim.x) {
+        const uint32_t c = (uint32_t)keys[i];
+        if (off[c + 1] - off[c] > max_posting) continue;
+        const uint32_t w = vals[i];
+        const int32_t s = window_seq(woff, n_seqs, w);
+        post[kept_off[c] + (i - off[c])] = int2{s, (int32_t)((w - woff[s]) * (uint32_t)span)};
+    }
+}
+
+void launch_reverse_strand(const uint8_t *src, const int64_t *start, int32_t n_seqs, uint8_t *dst,
+                           hipStream_t st)
+{
+    if (n_seqs <= 0) return;
+    const uint32_t nb = std::min<uint32_t>((uint32_t)n_seqs, kMaxGrid);
+    k_reverse_strand<<<nb, kBlock, 0, st>>>(src, start, n_seqs, dst);
+}
+
+void launch_cut_counts(const uint32_t *off, uint32_t ncode, uint32_t max_posting, uint32_t *kept,
+                       hipStream_t st)
+{
+    const uint32_t nb = std::min<uint32_t>((ncode + kBlock - 1) / kBlock, kMaxGrid);
+    k_cut_counts<<<nb, kBlock, 0, st>>>(off, ncode, max_posting, kept);
+}
+
+void launch_postings_cut(const uint32_t *vals, const uint64_t *keys, uint32_t n_win,
+                         const uint32_t *woff, int32_t n_seqs, int32_t span, const uint32_t *off,
+                         const uint32_t *kept_off, uint32_t max_posting, int2 *post, hipStream_t st)
+{
+    if (n_win == 0) return;
+    const uint32_t nb = std::min<uint32_t>((n_win + kBlock - 1) / kBlock, kMaxGrid);
+    k_postings_cut<<<nb, kBlock, 0, st>>>(vals, keys, n_win, woff, n_seqs, span, off, kept_off,
+                                          max_posting, post);
+}
+
 void launch_pack_bases(const uint8_t *ascii, int64_t total, uint32_t *dbw, int64_t nwords,
                        int32_t *err, hipStream_t st)
 {
@@ -925,7 +1007,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(
     const uint32_t *__restrict__ hrel, const uint32_t *__restrict__ pbase, int64_t np,
     const int2 *__restrict__ post, uint32_t nhits, int64_t g0, const int32_t *__restrict__ qid,
     const int64_t *__restrict__ qoff, int32_t qa, const uint32_t *__restrict__ kcode,
-    const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t k,
+    const uint32_t *__restrict__ kcnt, const uint32_t *__restrict__ dbw,
+    const int64_t *__restrict__ seq_start, int32_t k,
     uint32_t mask, int32_t mmax, int32_t M, Cand *__restrict__ cands, uint32_t ccap,
     uint32_t *__restrict__ ccount, uint32_t *__restrict__ cand_per_q, Bound *__restrict__ bounds,
     uint32_t bcap, uint32_t *__restrict__ bcount, uint32_t *__restrict__ bound_per_q)
@@ -992,15 +1075,18 @@ __global__ __launch_bounds__(kBlock) void k_probe(
             qpos = (int32_t)(g - qb);
             const int64_t s0 = seq_start[e.x];
             const int32_t ns = (int32_t)(seq_start[e.x + 1] - s0);
+            // a neighbour window is a hit when its code equals the query window's
+            // and that code's list is indexed (a repeat cutoff may have dropped it;
+            // a kept list holds every window of its code, so it is not empty)
             bool pred = false, succ = false;
 #pragma unroll
             for (int32_t m = 1; m <= kMaxProbe; ++m) {
                 if (m > mmax) break;
                 const int32_t qp = qpos - m * k, dp = e.y - m * k;
-                if (qp >= 0 && dp >= 0)
+                if (qp >= 0 && dp >= 0 && kcnt[qb + qp] > 0u)
                     pred |= kcode[qb + qp] == db_code(dbw, s0 + dp, k, mask);
                 const int32_t qn = qpos + m * k, dn = e.y + m * k;
-                if (qn + k <= L && dn + k <= ns)
+                if (qn + k <= L && dn + k <= ns && kcnt[qb + qn] > 0u)
                     succ |= kcode[qb + qn] == db_code(dbw, s0 + dn, k, mask);
             }
             sq = e.x;
@@ -1037,7 +1123,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(
 
 void launch_probe(const uint32_t *hrel, const uint32_t *pbase, int64_t np, const int2 *post,
                   uint32_t nhits, int64_t g0, const int32_t *qid, const int64_t *qoff, int32_t qa,
-                  const uint32_t *kcode, const uint32_t *dbw, const int64_t *seq_start, int32_t k,
+                  const uint32_t *kcode, const uint32_t *kcnt, const uint32_t *dbw,
+                  const int64_t *seq_start, int32_t k,
                   uint32_t mask, int32_t max_gap, int32_t min_len, Cand *cands, uint32_t ccap,
                   uint32_t *ccount, uint32_t *cand_per_q, Bound *bounds, uint32_t bcap,
                   uint32_t *bcount, uint32_t *bound_per_q, hipStream_t st)
@@ -1045,7 +1132,7 @@ void launch_probe(const uint32_t *hrel, const uint32_t *pbase, int64_t np, const
     // k is the window span here; mask picks its coded bases
     if (nhits == 0) return;
     const uint32_t nb = (nhits + kTile - 1) / kTile;
-    k_probe<<<nb, kBlock, 0, st>>>(hrel, pbase, np, post, nhits, g0, qid, qoff, qa, kcode, dbw,
+    k_probe<<<nb, kBlock, 0, st>>>(hrel, pbase, np, post, nhits, g0, qid, qoff, qa, kcode, kcnt, dbw,
                                    seq_start, k, mask, max_gap / k + 1, min_len, cands, ccap,
                                    ccount, cand_per_q, bounds, bcap, bcount, bound_per_q);
 }

@@ -149,6 +149,7 @@ struct gg_index {
     int32_t k = 0;       // bases in a window's code (the mask's weight)
     int32_t span = 0;    // bases a window covers (the mask's length; k without a mask)
     uint32_t mask = 0;   // bit t set: base t of a window is coded
+    int32_t strands = 1; // 2: sequences n/2 .. n-1 are the reverse complements of the first half
     int64_t n_seqs = 0, n_bases = 0;
     uint64_t n_post = 0;
     int64_t max_seq_len = 0;
@@ -530,7 +531,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             prof.begin("probe");
             launch_probe(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), np, ix->d_post, H, g0,
                          as<int32_t>(ws->qid), as<int64_t>(ws->qoff), qa, as<uint32_t>(ws->kcode),
-                         ix->d_dbw, ix->d_seq_start, ix->span, ix->mask, p->max_gap,
+                         as<uint32_t>(ws->cnt), ix->d_dbw, ix->d_seq_start, ix->span, ix->mask,
+                         p->max_gap,
                          p->min_hsp_len,
                          as<Cand>(ws->ctmp), ccap, as<uint32_t>(ws->cursor),
                          as<uint32_t>(ws->cand_q), as<Bound>(ws->btmp_b), bcap,
@@ -1513,32 +1515,38 @@ namespace {
 
 // Windows of `span` bases coded on the bases of `mask` (k of them); the plain
 // index is span = k with every base coded.
-gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, int32_t span,
-                      uint32_t mask, int32_t k, int32_t device, gg_index **out)
+gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_in, int32_t span,
+                      uint32_t mask, int32_t k, int32_t strands, int64_t max_posting,
+                      int32_t device, gg_index **out)
 {
     if (!out) return GG_EINVAL;
     *out = nullptr;
-    if (k < 1 || k > 16 || span < k || span > 32 || n_seqs < 0 || n_seqs > INT32_MAX)
+    if (k < 1 || k > 16 || span < k || span > 32 || n_in < 0 || (strands != 1 && strands != 2) ||
+        max_posting < 0 || n_in * strands > INT32_MAX)
         return GG_EINVAL;
-    if (n_seqs > 0 && (!seq_off || !seqs)) return GG_EINVAL;
+    // with both strands, sequence n_in + s is the reverse complement of sequence s
+    const int64_t n_seqs = n_in * strands;
+    if (n_in > 0 && (!seq_off || !seqs)) return GG_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GG_EDEVICE;
-    const int64_t base0 = n_seqs > 0 ? seq_off[0] : 0;
+    const int64_t base0 = n_in > 0 ? seq_off[0] : 0;
     int64_t maxlen = 0;
-    for (int64_t s = 0; s < n_seqs; ++s) {
+    for (int64_t s = 0; s < n_in; ++s) {
         const int64_t n = seq_off[s + 1] - seq_off[s];
         if (n < 0 || n > INT32_MAX) return GG_EINVAL;
         maxlen = std::max(maxlen, n);
     }
-    const int64_t total = n_seqs > 0 ? seq_off[n_seqs] - base0 : 0;
+    const int64_t total_in = n_in > 0 ? seq_off[n_in] - base0 : 0;
+    const int64_t total = total_in * strands;
     // windows before each sequence (sequence lengths only; the bases go to the GPU)
     std::vector<uint32_t> woff((size_t)n_seqs + 1, 0u);
     std::vector<int64_t> seq_start((size_t)n_seqs + 1, 0);
     uint64_t n_post = 0;
     for (int64_t s = 0; s < n_seqs; ++s) {
+        const int64_t f = s % (n_in > 0 ? n_in : 1);  // the forward sequence of s
         woff[(size_t)s] = (uint32_t)std::min<uint64_t>(n_post, 0xffffffffull);
-        n_post += (uint64_t)((seq_off[s + 1] - seq_off[s]) / span);
-        seq_start[(size_t)s] = seq_off[s] - base0;
+        n_post += (uint64_t)((seq_off[f + 1] - seq_off[f]) / span);
+        seq_start[(size_t)s] = seq_off[f] - base0 + (s >= n_in ? total_in : 0);
     }
     if (n_post >= 0xffffffffull) return GG_EINVAL;
     woff[(size_t)n_seqs] = (uint32_t)n_post;
@@ -1552,6 +1560,7 @@ gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, 
     ix->k = k;
     ix->span = span;
     ix->mask = mask;
+    ix->strands = strands;
     ix->n_seqs = n_seqs;
     ix->n_bases = total;
     ix->n_post = n_post;
@@ -1570,8 +1579,10 @@ gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, 
         return GG_OK;
     };
     gg_status s;
+    // with a repeat cutoff the postings are allocated once the kept count is known
+    const bool cut = max_posting > 0 && (uint64_t)max_posting < n_post;
     if ((s = alloc((void **)&ix->d_list_off, sizeof(uint32_t) * (ncode + 1))) != GG_OK ||
-        (s = alloc((void **)&ix->d_post, sizeof(int2) * n_post)) != GG_OK ||
+        (!cut && (s = alloc((void **)&ix->d_post, sizeof(int2) * n_post)) != GG_OK) ||
         (s = alloc((void **)&ix->d_dbw, sizeof(uint32_t) * nwords)) != GG_OK ||
         (s = alloc((void **)&ix->d_seq_start, sizeof(int64_t) * (n_seqs + 1))) != GG_OK)
         return fail(s);
@@ -1615,12 +1626,14 @@ gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, 
         const size_t parts = std::max<size_t>(scan_partials_needed(radix_hist_needed(nw)),
                                               scan_partials_needed((int64_t)ncode + 1));
         auto *d_parts = static_cast<uint32_t *>(tmp.get(sizeof(uint32_t) * parts));
+        auto *d_kept = cut ? static_cast<uint32_t *>(tmp.get(sizeof(uint32_t) * (ncode + 1)))
+                           : nullptr;
         if (!d_ascii || !d_woff || !d_err || !d_keys || !d_keys2 || !d_vals || !d_vals2 ||
-            !d_hist || !d_parts)
+            !d_hist || !d_parts || (cut && !d_kept))
             return fail(GG_ENOMEM);
         int32_t err = 0;
-        if (total > 0 && hipMemcpyAsync(d_ascii, seqs + base0, (size_t)total,
-                                        hipMemcpyHostToDevice, bst) != hipSuccess)
+        if (total_in > 0 && hipMemcpyAsync(d_ascii, seqs + base0, (size_t)total_in,
+                                           hipMemcpyHostToDevice, bst) != hipSuccess)
             return fail(GG_EDEVICE);
         if (hipMemcpyAsync(d_woff, woff.data(), sizeof(uint32_t) * (n_seqs + 1),
                            hipMemcpyHostToDevice, bst) != hipSuccess ||
@@ -1629,13 +1642,34 @@ gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_seqs, 
             hipMemsetAsync(d_err, 0, sizeof(int32_t), bst) != hipSuccess ||
             hipMemsetAsync(ix->d_list_off, 0, sizeof(uint32_t) * (ncode + 1), bst) != hipSuccess)
             return fail(GG_EDEVICE);
+        if (strands == 2)  // the first n_in + 1 starts are the forward sequences'
+            launch_reverse_strand(d_ascii, ix->d_seq_start, (int32_t)n_in, d_ascii + total_in, bst);
         launch_pack_bases(d_ascii, total, ix->d_dbw, nwords, d_err, bst);
         launch_window_keys(ix->d_dbw, ix->d_seq_start, d_woff, (int32_t)n_seqs, nw, span, mask,
                            d_keys, d_vals, ix->d_list_off, bst);
         launch_scan_u32(ix->d_list_off, ix->d_list_off, (int64_t)ncode, d_parts, bst);
         const int cur = radix_sort(d_keys, d_keys2, d_vals, d_vals2, nw, 0, 2 * k, d_hist, d_parts,
                                    bst);
-        launch_postings(cur ? d_vals2 : d_vals, nw, d_woff, (int32_t)n_seqs, span, ix->d_post, bst);
+        if (!cut) {
+            launch_postings(cur ? d_vals2 : d_vals, nw, d_woff, (int32_t)n_seqs, span, ix->d_post,
+                            bst);
+        } else {  // drop the lists longer than max_posting, then place the others
+            const uint32_t mp = (uint32_t)max_posting;
+            uint32_t kept = 0;
+            launch_cut_counts(ix->d_list_off, (uint32_t)ncode, mp, d_kept, bst);
+            launch_scan_u32(d_kept, d_kept, (int64_t)ncode, d_parts, bst);
+            if (hipMemcpyAsync(&kept, d_kept + ncode, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               bst) != hipSuccess ||
+                hipStreamSynchronize(bst) != hipSuccess)
+                return fail(GG_EDEVICE);
+            if ((s = alloc((void **)&ix->d_post, sizeof(int2) * kept)) != GG_OK) return fail(s);
+            ix->n_post = kept;
+            launch_postings_cut(cur ? d_vals2 : d_vals, cur ? d_keys2 : d_keys, nw, d_woff,
+                                (int32_t)n_seqs, span, ix->d_list_off, d_kept, mp, ix->d_post, bst);
+            if (hipMemcpyAsync(ix->d_list_off, d_kept, sizeof(uint32_t) * (ncode + 1),
+                               hipMemcpyDeviceToDevice, bst) != hipSuccess)
+                return fail(GG_EDEVICE);
+        }
         if (hipMemcpyAsync(&err, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, bst) != hipSuccess ||
             hipStreamSynchronize(bst) != hipSuccess || hipGetLastError() != hipSuccess)
             return fail(GG_EDEVICE);
@@ -1667,14 +1701,27 @@ gg_status gg_index_build(const char *seqs, const int64_t *seq_off, int64_t n_seq
         if (out) *out = nullptr;
         return GG_EINVAL;
     }
-    return index_build(seqs, seq_off, n_seqs, k, (1u << k) - 1u, k, device, out);
+    return index_build(seqs, seq_off, n_seqs, k, (1u << k) - 1u, k, 1, 0, device, out);
 }
 
 gg_status gg_index_build_masked(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
                                 const char *mask, int32_t device, gg_index **out)
 {
+    gg_index_options opt{0, mask, 1, 0};
+    return gg_index_build_ex(seqs, seq_off, n_seqs, &opt, device, out);
+}
+
+gg_status gg_index_build_ex(const char *seqs, const int64_t *seq_off, int64_t n_seqs,
+                            const gg_index_options *opt, int32_t device, gg_index **out)
+{
     if (out) *out = nullptr;
-    if (!mask) return GG_EINVAL;
+    if (!opt) return GG_EINVAL;
+    if (!opt->mask) {
+        if (opt->k < 1 || opt->k > 16) return GG_EINVAL;
+        return index_build(seqs, seq_off, n_seqs, opt->k, (1u << opt->k) - 1u, opt->k,
+                           opt->strands, opt->max_posting, device, out);
+    }
+    const char *mask = opt->mask;
     int32_t span = 0, weight = 0;
     uint32_t bits = 0;
     for (; mask[span]; ++span) {
@@ -1687,7 +1734,8 @@ gg_status gg_index_build_masked(const char *seqs, const int64_t *seq_off, int64_
         }
     }
     if (weight < 1 || weight > 16) return GG_EINVAL;
-    return index_build(seqs, seq_off, n_seqs, span, bits, weight, device, out);
+    return index_build(seqs, seq_off, n_seqs, span, bits, weight, opt->strands, opt->max_posting,
+                       device, out);
 }
 
 gg_status gg_index_info(const gg_index *ix, int64_t *n_postings, int64_t *n_bases, int64_t *n_seqs,
@@ -1698,6 +1746,23 @@ gg_status gg_index_info(const gg_index *ix, int64_t *n_postings, int64_t *n_base
     if (n_bases) *n_bases = ix->n_bases;
     if (n_seqs) *n_seqs = ix->n_seqs;
     if (k) *k = ix->k;
+    return GG_OK;
+}
+
+gg_status gg_index_export(const gg_index *ix, uint32_t *list_off, int32_t *postings,
+                          int64_t cap_postings)
+{
+    if (!ix) return GG_EINVAL;
+    if (postings && cap_postings < (int64_t)ix->n_post) return GG_ETRUNC;
+    if (hipSetDevice(ix->device) != hipSuccess) return GG_EDEVICE;
+    const size_t nheads = ((size_t)1 << (2 * ix->k)) + 1;
+    if (list_off && hipMemcpy(list_off, ix->d_list_off, sizeof(uint32_t) * nheads,
+                              hipMemcpyDeviceToHost) != hipSuccess)
+        return GG_EDEVICE;
+    if (postings && ix->n_post > 0 &&
+        hipMemcpy(postings, ix->d_post, sizeof(int2) * ix->n_post, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return GG_EDEVICE;
     return GG_OK;
 }
 

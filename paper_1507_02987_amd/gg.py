@@ -25,7 +25,8 @@ STAT_FIELDS = ("n_kmers", "n_hits", "n_cands", "n_merged", "n_selected", "n_cell
 STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 
 # Exported symbols of include/gg.h, in declaration order.
-SYMBOLS = ("gg_index_build", "gg_index_build_masked", "gg_index_free", "gg_index_info",
+SYMBOLS = ("gg_index_build", "gg_index_build_masked", "gg_index_build_ex", "gg_index_free",
+           "gg_index_info", "gg_index_export",
            "gg_index_set_hit_budget",
            "gg_index_get_tuning", "gg_index_set_tuning", "gg_index_autotune",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
@@ -44,6 +45,11 @@ class GGError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("match", "mismatch", "gap_open", "gap_extend", "band",
                                          "xdrop", "max_gap", "min_hsp_len", "max_hits")]
+
+
+class IndexOptions(C.Structure):
+    _fields_ = [("k", C.c_int32), ("mask", C.c_char_p), ("strands", C.c_int32),
+                ("max_posting", C.c_int64)]
 
 
 class Tuning(C.Structure):
@@ -73,6 +79,8 @@ def lib():
         vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
         L.gg_index_build.argtypes = [vp, vp, i64, i32, i32, C.POINTER(vp)]
         L.gg_index_build_masked.argtypes = [vp, vp, i64, C.c_char_p, i32, C.POINTER(vp)]
+        L.gg_index_build_ex.argtypes = [vp, vp, i64, C.POINTER(IndexOptions), i32, C.POINTER(vp)]
+        L.gg_index_export.argtypes = [vp, vp, vp, i64]
         L.gg_index_free.argtypes = [vp]
         L.gg_index_free.restype = None
         L.gg_index_info.argtypes = [vp, vp, vp, vp, vp]
@@ -118,13 +126,23 @@ def _u8(x) -> np.ndarray:
 class Index:
     """gg_index_build / gg_index_free: device-resident data bank and inverted index."""
 
-    def __init__(self, seqs, seq_off, k: int = 0, device: int = 0, mask: str | None = None):
+    def __init__(self, seqs, seq_off, k: int = 0, device: int = 0, mask: str | None = None,
+                 strands: int = 1, max_posting: int = 0):
         """k: contiguous windows of k bases; mask: a '0'/'1' spaced-seed mask instead
-        (gg_index_build_masked), whose weight is then the index's k."""
+        (gg_index_build_masked), whose weight is then the index's k; strands=2 and
+        max_posting > 0 go through gg_index_build_ex."""
         s = _u8(seqs)
         off = np.ascontiguousarray(seq_off, dtype=np.int64)
         h = C.c_void_p()
-        if mask is not None:
+        if strands != 1 or max_posting != 0:
+            opt = IndexOptions(k, mask.encode() if mask is not None else None, strands,
+                               max_posting)
+            rc = lib().gg_index_build_ex(_ptr(s) if len(s) else None, _ptr(off), len(off) - 1,
+                                         C.byref(opt), device, C.byref(h))
+            name = "gg_index_build_ex"
+            if mask is not None:
+                k = mask.count("1")
+        elif mask is not None:
             rc = lib().gg_index_build_masked(_ptr(s) if len(s) else None, _ptr(off), len(off) - 1,
                                              mask.encode(), device, C.byref(h))
             name = "gg_index_build_masked"
@@ -139,6 +157,8 @@ class Index:
         self.k = k
         self.mask = mask
         self.span = len(mask) if mask is not None else k
+        self.strands = strands
+        self.max_posting = max_posting
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -162,6 +182,16 @@ class Index:
         if rc != GG_OK:
             raise GGError(rc, "gg_index_info")
         return {"n_postings": a.value, "n_bases": b.value, "n_seqs": c.value, "k": k.value}
+
+    def export(self):
+        """gg_index_export: (list heads u32[4^k + 1], postings int32[n, 2] of (seq, pos))."""
+        n = self.info()["n_postings"]
+        heads = np.zeros((1 << (2 * self.k)) + 1, np.uint32)
+        post = np.zeros((max(n, 1), 2), np.int32)
+        rc = lib().gg_index_export(self._h, _ptr(heads), _ptr(post), n)
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_export")
+        return heads, post[:n]
 
     def set_hit_budget(self, nbytes: int):
         rc = lib().gg_index_set_hit_budget(self._h, int(nbytes))
