@@ -37,7 +37,8 @@ typedef enum {
     GG_EAGAIN = 4,    /* served query not finished yet */
     GG_ETRUNC = 5,    /* more hits than `cap`: the first `cap` are written, *n_out is the count */
     GG_ENOTFOUND = 6, /* unknown or already collected ticket */
-    GG_EBUDGET = 7    /* one query's hits on one sequence do not fit the hit budget */
+    GG_EBUDGET = 7,   /* one query's hits on one sequence do not fit the hit budget */
+    GG_EIO = 8        /* an index file cannot be opened, read or written, or is not one */
 } gg_status;
 
 typedef struct gg_index gg_index;   /* device-resident data bank and inverted index */
@@ -152,6 +153,29 @@ void gg_index_free(gg_index *index);
  */
 gg_status gg_index_export(const gg_index *index, uint32_t *list_off, int32_t *postings,
                           int64_t cap_postings);
+
+/*
+ * Persistence (Section 2.1: the index and the formatted bank are kept on disk and
+ * the whole index is read into memory at start).  gg_index_save writes the index
+ * and its 2-bit bank to `path` (created or replaced); gg_index_load reads such a
+ * file onto `device`, where it serves exactly as the index it was saved from
+ * (same lists, postings, bank, window span and mask, strands).  Tuning and the hit
+ * budget are not saved.
+ *
+ * File layout, little-endian: "GGINDEX1"; u32 version (1); i32 k, span, strands;
+ * u32 mask; u32 0; i64 n_seqs, n_bases, n_postings, max_seq_len, n_words;
+ * i64 seq_start[n_seqs + 1]; u32 list_off[4^k + 1]; i32 postings[2 n_postings]
+ * ((sequence, position) pairs); u32 bank[n_words] (16 bases per word, first base
+ * in the top bits); u64 check, a hash of every preceding byte after the magic.
+ *
+ * gg_index_load checks the header, the file size, the hash, and that heads and
+ * sequence starts are monotone and every posting is a whole window inside its
+ * sequence, so a damaged file is refused before anything reaches the GPU.
+ * Errors: GG_EIO (cannot open / read / write, wrong magic, size or hash), GG_EINVAL
+ * (null argument, inconsistent contents), GG_ENOMEM, GG_EDEVICE.
+ */
+gg_status gg_index_save(const gg_index *index, const char *path);
+gg_status gg_index_load(const char *path, int32_t device, gg_index **out);
 
 /* Sizes of a built index: windows indexed, bases, sequences, k. */
 gg_status gg_index_info(const gg_index *index, int64_t *n_postings, int64_t *n_bases,

@@ -1491,6 +1491,7 @@ const char *gg_strerror(gg_status s)
     case GG_ETRUNC: return "output truncated";
     case GG_ENOTFOUND: return "unknown ticket";
     case GG_EBUDGET: return "query exceeds the hit-buffer budget";
+    case GG_EIO: return "index file cannot be read or written, or is damaged";
     default: return "unknown status";
     }
 }
@@ -1512,6 +1513,26 @@ void gg_index_free(gg_index *ix)
 // uploaded once, packed and windowed by kernels; the lists are a stable sort of
 // the windows by code, so each list keeps (sequence, position) order.
 namespace {
+
+// Device-dependent settings of a built or loaded index: the default hit budget
+// and the LDS bucket sizes.
+gg_status index_finish(gg_index *ix)
+{
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return GG_EDEVICE;
+    ix->default_budget = std::min<uint64_t>((uint64_t)16 << 30, free_b / 4);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) !=
+        hipSuccess)
+        return GG_EDEVICE;
+    if ((size_t)lds < (size_t)kBucketCapMax * 8 * (kBlock / 64) + 1024) return GG_EDEVICE;
+    ix->bucket_cap = kBucketCapMax;
+    ix->bucket_big = (size_t)lds >= (size_t)kBucketBig * 8 + 1024 && setup_kernels() == hipSuccess
+                         ? kBucketBig
+                         : kBucketCapMax;
+    (void)hipGetLastError();
+    return GG_OK;
+}
 
 // Windows of `span` bases coded on the bases of `mask` (k of them); the plain
 // index is span = k with every base coded.
@@ -1676,18 +1697,7 @@ gg_status index_build(const char *seqs, const int64_t *seq_off, int64_t n_in, in
         if (err) return fail(GG_EINVAL);
     }
 
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(GG_EDEVICE);
-    ix->default_budget = std::min<uint64_t>((uint64_t)16 << 30, free_b / 4);
-    int lds = 0;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
-        return fail(GG_EDEVICE);
-    if ((size_t)lds < (size_t)kBucketCapMax * 8 * (kBlock / 64) + 1024) return fail(GG_EDEVICE);
-    ix->bucket_cap = kBucketCapMax;
-    ix->bucket_big = (size_t)lds >= (size_t)kBucketBig * 8 + 1024 && setup_kernels() == hipSuccess
-                         ? kBucketBig
-                         : kBucketCapMax;
-    (void)hipGetLastError();
+    if ((s = index_finish(ix)) != GG_OK) return fail(s);
     *out = ix;
     return GG_OK;
 }
@@ -1763,6 +1773,228 @@ gg_status gg_index_export(const gg_index *ix, uint32_t *list_off, int32_t *posti
         hipMemcpy(postings, ix->d_post, sizeof(int2) * ix->n_post, hipMemcpyDeviceToHost) !=
             hipSuccess)
         return GG_EDEVICE;
+    return GG_OK;
+}
+
+namespace {
+
+// Hash of an index file's bytes after the magic: 64-bit words (the last one
+// zero-padded), each xored in and mixed by a multiply and a shift.
+struct FileHash {
+    uint64_t h = 0x9e3779b97f4a7c15ull;
+    uint8_t part[8];
+    size_t np = 0;
+    void word(uint64_t w)
+    {
+        h ^= w;
+        h *= 0xff51afd7ed558ccdull;
+        h ^= h >> 33;
+    }
+    void add(const void *data, size_t n)
+    {
+        const uint8_t *b = static_cast<const uint8_t *>(data);
+        while (n && np) {
+            part[np++] = *b++;
+            --n;
+            if (np == 8) {
+                uint64_t w;
+                memcpy(&w, part, 8);
+                word(w);
+                np = 0;
+            }
+        }
+        for (; n >= 8; n -= 8, b += 8) {
+            uint64_t w;
+            memcpy(&w, b, 8);
+            word(w);
+        }
+        while (n--) part[np++] = *b++;
+    }
+    uint64_t done()
+    {
+        if (np) {
+            memset(part + np, 0, 8 - np);
+            uint64_t w;
+            memcpy(&w, part, 8);
+            word(w);
+            np = 0;
+        }
+        return h;
+    }
+};
+
+struct FileHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t k, span, strands;
+    uint32_t mask, zero;
+    int64_t n_seqs, n_bases, n_post, max_seq_len, n_words;
+};
+static_assert(sizeof(FileHeader) == 72, "index file header layout");
+constexpr char kFileMagic[8] = {'G', 'G', 'I', 'N', 'D', 'E', 'X', '1'};
+
+struct File {
+    FILE *f = nullptr;
+    ~File()
+    {
+        if (f) fclose(f);
+    }
+};
+
+bool write_all(FILE *f, FileHash &hash, const void *data, size_t n)
+{
+    hash.add(data, n);
+    return n == 0 || fwrite(data, 1, n, f) == n;
+}
+
+bool read_all(FILE *f, FileHash &hash, void *data, size_t n)
+{
+    if (n && fread(data, 1, n, f) != n) return false;
+    hash.add(data, n);
+    return true;
+}
+
+}  // namespace
+
+gg_status gg_index_save(const gg_index *ix, const char *path)
+{
+    if (!ix || !path) return GG_EINVAL;
+    if (hipSetDevice(ix->device) != hipSuccess) return GG_EDEVICE;
+    const size_t nheads = ((size_t)1 << (2 * ix->k)) + 1;
+    const int64_t nwords = (ix->n_bases + 15) / 16 + 1;
+    std::vector<int64_t> seq_start((size_t)ix->n_seqs + 1);
+    std::vector<uint32_t> heads(nheads);
+    std::vector<int2> post((size_t)ix->n_post);
+    std::vector<uint32_t> bank((size_t)nwords);
+    if (hipMemcpy(seq_start.data(), ix->d_seq_start, sizeof(int64_t) * seq_start.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(heads.data(), ix->d_list_off, sizeof(uint32_t) * nheads,
+                  hipMemcpyDeviceToHost) != hipSuccess ||
+        (ix->n_post && hipMemcpy(post.data(), ix->d_post, sizeof(int2) * post.size(),
+                                 hipMemcpyDeviceToHost) != hipSuccess) ||
+        hipMemcpy(bank.data(), ix->d_dbw, sizeof(uint32_t) * bank.size(), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return GG_EDEVICE;
+    FileHeader hd{};
+    memcpy(hd.magic, kFileMagic, 8);
+    hd.version = 1;
+    hd.k = ix->k;
+    hd.span = ix->span;
+    hd.strands = ix->strands;
+    hd.mask = ix->mask;
+    hd.n_seqs = ix->n_seqs;
+    hd.n_bases = ix->n_bases;
+    hd.n_post = (int64_t)ix->n_post;
+    hd.max_seq_len = ix->max_seq_len;
+    hd.n_words = nwords;
+    File fl;
+    fl.f = fopen(path, "wb");
+    if (!fl.f) return GG_EIO;
+    FileHash hash;
+    if (fwrite(hd.magic, 1, 8, fl.f) != 8 ||
+        !write_all(fl.f, hash, reinterpret_cast<const char *>(&hd) + 8, sizeof(hd) - 8) ||
+        !write_all(fl.f, hash, seq_start.data(), sizeof(int64_t) * seq_start.size()) ||
+        !write_all(fl.f, hash, heads.data(), sizeof(uint32_t) * heads.size()) ||
+        !write_all(fl.f, hash, post.data(), sizeof(int2) * post.size()) ||
+        !write_all(fl.f, hash, bank.data(), sizeof(uint32_t) * bank.size()))
+        return GG_EIO;
+    const uint64_t check = hash.done();
+    if (fwrite(&check, 1, 8, fl.f) != 8) return GG_EIO;
+    const int rc = fclose(fl.f);
+    fl.f = nullptr;
+    return rc == 0 ? GG_OK : GG_EIO;
+}
+
+gg_status gg_index_load(const char *path, int32_t device, gg_index **out)
+{
+    if (!out || !path) return GG_EINVAL;
+    *out = nullptr;
+    File fl;
+    fl.f = fopen(path, "rb");
+    if (!fl.f) return GG_EIO;
+    FileHeader hd{};
+    FileHash hash;
+    if (fread(hd.magic, 1, 8, fl.f) != 8 || memcmp(hd.magic, kFileMagic, 8) != 0 ||
+        !read_all(fl.f, hash, reinterpret_cast<char *>(&hd) + 8, sizeof(hd) - 8) || hd.version != 1)
+        return GG_EIO;
+    // header consistency (before any size is trusted)
+    if (hd.k < 1 || hd.k > 16 || hd.span < hd.k || hd.span > 32 || (hd.strands != 1 && hd.strands != 2) ||
+        hd.zero != 0 || __builtin_popcount(hd.mask) != hd.k ||
+        (hd.span < 32 && (hd.mask >> hd.span) != 0) || hd.n_seqs < 0 || hd.n_seqs > INT32_MAX ||
+        hd.n_bases < 0 || hd.n_post < 0 || hd.n_post >= (int64_t)0xffffffffll ||
+        hd.max_seq_len < 0 || hd.max_seq_len > INT32_MAX || hd.n_words != (hd.n_bases + 15) / 16 + 1)
+        return GG_EINVAL;
+    const uint64_t nheads = ((uint64_t)1 << (2 * hd.k)) + 1;
+    const uint64_t want = 8 + sizeof(FileHeader) - 8 + 8 * ((uint64_t)hd.n_seqs + 1) + 4 * nheads +
+                          8 * (uint64_t)hd.n_post + 4 * (uint64_t)hd.n_words + 8;
+    if (fseeko(fl.f, 0, SEEK_END) != 0 || (uint64_t)ftello(fl.f) != want ||
+        fseeko(fl.f, (off_t)sizeof(FileHeader), SEEK_SET) != 0)
+        return GG_EIO;
+    std::vector<int64_t> seq_start((size_t)hd.n_seqs + 1);
+    std::vector<uint32_t> heads((size_t)nheads);
+    std::vector<int2> post((size_t)hd.n_post);
+    std::vector<uint32_t> bank((size_t)hd.n_words);
+    uint64_t check = 0;
+    if (!read_all(fl.f, hash, seq_start.data(), sizeof(int64_t) * seq_start.size()) ||
+        !read_all(fl.f, hash, heads.data(), sizeof(uint32_t) * heads.size()) ||
+        !read_all(fl.f, hash, post.data(), sizeof(int2) * post.size()) ||
+        !read_all(fl.f, hash, bank.data(), sizeof(uint32_t) * bank.size()) ||
+        fread(&check, 1, 8, fl.f) != 8 || check != hash.done())
+        return GG_EIO;
+    // contents: every later kernel indexes through these, so each is checked
+    int64_t maxlen = 0;
+    if (seq_start[0] != 0 || seq_start[(size_t)hd.n_seqs] != hd.n_bases) return GG_EINVAL;
+    for (int64_t s = 0; s < hd.n_seqs; ++s) {
+        const int64_t n = seq_start[(size_t)s + 1] - seq_start[(size_t)s];
+        if (n < 0 || n > INT32_MAX) return GG_EINVAL;
+        maxlen = std::max(maxlen, n);
+    }
+    if (maxlen != hd.max_seq_len || heads[0] != 0 || heads[(size_t)nheads - 1] != (uint64_t)hd.n_post)
+        return GG_EINVAL;
+    for (uint64_t c = 0; c + 1 < nheads; ++c)
+        if (heads[c + 1] < heads[c]) return GG_EINVAL;
+    for (const int2 &e : post) {
+        if (e.x < 0 || e.x >= hd.n_seqs || e.y < 0 || e.y % hd.span != 0) return GG_EINVAL;
+        if ((int64_t)e.y + hd.span > seq_start[(size_t)e.x + 1] - seq_start[(size_t)e.x])
+            return GG_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GG_EDEVICE;
+    auto *ix = new (std::nothrow) gg_index();
+    if (!ix) return GG_ENOMEM;
+    ix->device = device;
+    ix->k = hd.k;
+    ix->span = hd.span;
+    ix->mask = hd.mask;
+    ix->strands = hd.strands;
+    ix->n_seqs = hd.n_seqs;
+    ix->n_bases = hd.n_bases;
+    ix->n_post = (uint64_t)hd.n_post;
+    ix->max_seq_len = hd.max_seq_len;
+    auto fail = [&](gg_status st) {
+        gg_index_free(ix);
+        return st;
+    };
+    if (hipSetDevice(device) != hipSuccess) return fail(GG_EDEVICE);
+    auto up = [](void **dst, const void *src, size_t bytes) -> gg_status {
+        if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) {
+            (void)hipGetLastError();
+            *dst = nullptr;
+            return GG_ENOMEM;
+        }
+        if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return GG_EDEVICE;
+        return GG_OK;
+    };
+    gg_status st;
+    if ((st = up((void **)&ix->d_seq_start, seq_start.data(), sizeof(int64_t) * seq_start.size())) !=
+            GG_OK ||
+        (st = up((void **)&ix->d_list_off, heads.data(), sizeof(uint32_t) * heads.size())) != GG_OK ||
+        (st = up((void **)&ix->d_post, post.data(), sizeof(int2) * post.size())) != GG_OK ||
+        (st = up((void **)&ix->d_dbw, bank.data(), sizeof(uint32_t) * bank.size())) != GG_OK)
+        return fail(st);
+    if ((st = index_finish(ix)) != GG_OK) return fail(st);
+    *out = ix;
     return GG_OK;
 }
 

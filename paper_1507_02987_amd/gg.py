@@ -14,9 +14,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgg.so")
 
-GG_OK, GG_EINVAL, GG_ENOMEM, GG_EDEVICE, GG_EAGAIN, GG_ETRUNC, GG_ENOTFOUND, GG_EBUDGET = range(8)
+GG_OK, GG_EINVAL, GG_ENOMEM, GG_EDEVICE, GG_EAGAIN, GG_ETRUNC, GG_ENOTFOUND, GG_EBUDGET, GG_EIO = \
+    range(9)
 STATUS = {0: "GG_OK", 1: "GG_EINVAL", 2: "GG_ENOMEM", 3: "GG_EDEVICE", 4: "GG_EAGAIN",
-          5: "GG_ETRUNC", 6: "GG_ENOTFOUND", 7: "GG_EBUDGET"}
+          5: "GG_ETRUNC", 6: "GG_ENOTFOUND", 7: "GG_EBUDGET", 8: "GG_EIO"}
 
 HIT_FIELDS = ("seq_id", "score", "q_start", "q_end", "d_start", "d_end",
               "box_q_start", "box_q_end", "box_d_start", "box_d_end", "box_len")
@@ -26,7 +27,7 @@ STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 
 # Exported symbols of include/gg.h, in declaration order.
 SYMBOLS = ("gg_index_build", "gg_index_build_masked", "gg_index_build_ex", "gg_index_free",
-           "gg_index_info", "gg_index_export",
+           "gg_index_info", "gg_index_export", "gg_index_save", "gg_index_load",
            "gg_index_set_hit_budget",
            "gg_index_get_tuning", "gg_index_set_tuning", "gg_index_autotune",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
@@ -81,6 +82,8 @@ def lib():
         L.gg_index_build_masked.argtypes = [vp, vp, i64, C.c_char_p, i32, C.POINTER(vp)]
         L.gg_index_build_ex.argtypes = [vp, vp, i64, C.POINTER(IndexOptions), i32, C.POINTER(vp)]
         L.gg_index_export.argtypes = [vp, vp, vp, i64]
+        L.gg_index_save.argtypes = [vp, C.c_char_p]
+        L.gg_index_load.argtypes = [C.c_char_p, i32, C.POINTER(vp)]
         L.gg_index_free.argtypes = [vp]
         L.gg_index_free.restype = None
         L.gg_index_info.argtypes = [vp, vp, vp, vp, vp]
@@ -182,6 +185,26 @@ class Index:
         if rc != GG_OK:
             raise GGError(rc, "gg_index_info")
         return {"n_postings": a.value, "n_bases": b.value, "n_seqs": c.value, "k": k.value}
+
+    def save(self, path: str):
+        """gg_index_save: the index and its 2-bit bank to a file."""
+        rc = lib().gg_index_save(self._h, os.fsencode(path))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_save")
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "Index":
+        """gg_index_load: an index saved by save(), on `device`."""
+        h = C.c_void_p()
+        rc = lib().gg_index_load(os.fsencode(path), device, C.byref(h))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_index_load")
+        self = cls.__new__(cls)
+        self._h = h
+        self.k = self.info()["k"]
+        self.mask = self.span = None  # not reported by the library
+        self.strands = self.max_posting = None
+        return self
 
     def export(self):
         """gg_index_export: (list heads u32[4^k + 1], postings int32[n, 2] of (seq, pos))."""
