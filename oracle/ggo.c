@@ -9,6 +9,7 @@
  */
 #include "ggo.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -687,4 +688,69 @@ done:
     free(sel);
     free(res);
     return rc;
+}
+
+
+/* ------------------------------------------------------------------ significance
+ * Section 2.2 returns an e-value and a normalized score with each alignment but
+ * does not say how they are computed.  Reading [R]: Karlin-Altschul statistics of
+ * ungapped local alignment (Karlin and Altschul 1990) for the scoring scheme on
+ * uniform, independent bases, so one aligned pair scores +match with probability
+ * 1/4 and -mismatch with probability 3/4.
+ *   lambda: the positive root of E[exp(lambda X)] = 1;
+ *   H = lambda E[X exp(lambda X)] (relative entropy of the target pairs);
+ *   K, lattice case with span d = gcd(match, mismatch):
+ *     K = exp(-2 sigma) lambda d / (H (1 - exp(-lambda d))),
+ *     sigma = sum over k >= 1 of (1/k) (E[exp(lambda S_k); S_k < 0] + P(S_k >= 0)),
+ *   S_k the sum of k independent pair scores: with j matches out of k,
+ *   S_k = j match - (k - j) mismatch and j is binomial(k, 1/4). */
+static int32_t gcd32(int32_t a, int32_t b)
+{
+    while (b) {
+        int32_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+int32_t ggo_karlin_altschul(int32_t match, int32_t mismatch, double *lambda, double *K, double *H)
+{
+    if (match <= 0 || mismatch <= 0 || !lambda || !K || !H) return GGO_EINVAL;
+    const double p = 0.25, q = 0.75;
+    /* E[exp(l X)] - 1 is negative just above 0 (negative drift) and grows without
+     * bound: bisect on it */
+    double lo = 0.0, hi = 1.0;
+    while (p * exp(hi * match) + q * exp(-hi * mismatch) - 1.0 < 0.0) hi *= 2.0;
+    for (int it = 0; it < 200; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (p * exp(mid * match) + q * exp(-mid * mismatch) - 1.0 > 0.0) hi = mid;
+        else lo = mid;
+    }
+    const double l = 0.5 * (lo + hi);
+    const double h = l * (p * match * exp(l * match) - q * mismatch * exp(-l * mismatch));
+    double sigma = 0.0;
+    for (int32_t k = 1; k <= 5000; k++) {
+        double term = 0.0;
+        for (int32_t j = 0; j <= k; j++) {
+            double logpr = lgamma(k + 1.0) - lgamma(j + 1.0) - lgamma(k - j + 1.0) + j * log(p) +
+                           (k - j) * log(q);
+            double s = (double)j * match - (double)(k - j) * mismatch;
+            term += s < 0 ? exp(logpr + l * s) : exp(logpr);
+        }
+        sigma += term / k;
+        if (term / k < 1e-18) break;
+    }
+    const double d = (double)gcd32(match, mismatch);
+    *lambda = l;
+    *H = h;
+    *K = exp(-2.0 * sigma) * l * d / (h * (1.0 - exp(-l * d)));
+    return GGO_OK;
+}
+
+void ggo_significance(int32_t score, int64_t m, int64_t n, double lambda, double K, double *bits,
+                      double *evalue)
+{
+    *bits = (lambda * score - log(K)) / log(2.0);
+    *evalue = K * (double)m * (double)n * exp(-lambda * score);
 }

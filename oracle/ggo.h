@@ -115,6 +115,15 @@ int64_t ggo_report(ggo_hit *h, int64_t n);
 int32_t ggo_search(const ggo_index *ix, const char *query, int64_t qlen, const ggo_params *p,
                    ggo_hit *out, int32_t cap, int32_t *n_out, ggo_stats *st);
 
+/* Significance of a reported score (Section 2.2: the e-value and the normalized
+ * score returned with each alignment) by Karlin-Altschul statistics [R]: lambda,
+ * K and H of ungapped scoring with +match / -mismatch on uniform, independent bases,
+ * then bits = (lambda S - ln K) / ln 2 and E = K m n exp(-lambda S) for a query of
+ * m bases against n bank bases.  Returns GGO_EINVAL for non-positive scores. */
+int32_t ggo_karlin_altschul(int32_t match, int32_t mismatch, double *lambda, double *K, double *H);
+void ggo_significance(int32_t score, int64_t m, int64_t n, double lambda, double K, double *bits,
+                      double *evalue);
+
 void ggo_free(void *ptr);
 
 #ifdef __cplusplus

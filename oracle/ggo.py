@@ -30,7 +30,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-                               SRC, "-o", tmp])
+                               SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -84,6 +84,12 @@ def lib():
         L.ggo_index_build_opts.argtypes = [vp, vp, i64, i32, C.c_char_p, i32, i64,
                                            C.POINTER(C.POINTER(_Index))]
         L.ggo_index_build_opts.restype = i32
+        L.ggo_karlin_altschul.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
+        L.ggo_karlin_altschul.restype = i32
+        L.ggo_significance.argtypes = [i32, i64, i64, C.c_double, C.c_double,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ggo_significance.restype = None
         L.ggo_masked_code.argtypes = [vp, i32, C.c_uint32]
         L.ggo_masked_code.restype = C.c_uint32
         L.ggo_index_free.argtypes = [C.POINTER(_Index)]
@@ -138,6 +144,21 @@ def kmer_code(codes: np.ndarray, k: int) -> int:
     codes = np.ascontiguousarray(codes, dtype=np.uint8)
     assert len(codes) >= k
     return int(lib().ggo_kmer_code(_ptr(codes), k))
+
+
+def karlin_altschul(match: int = 1, mismatch: int = 3) -> tuple[float, float, float]:
+    """(lambda, K, H) of ungapped +match / -mismatch scoring on uniform bases."""
+    lam, K, H = C.c_double(), C.c_double(), C.c_double()
+    if lib().ggo_karlin_altschul(match, mismatch, C.byref(lam), C.byref(K), C.byref(H)) != 0:
+        raise ValueError("scores must be positive")
+    return lam.value, K.value, H.value
+
+
+def significance(score: int, m: int, n: int, lam: float, K: float) -> tuple[float, float]:
+    """(bit score, e-value) of a score for a query of m bases against n bank bases."""
+    bits, ev = C.c_double(), C.c_double()
+    lib().ggo_significance(score, m, n, lam, K, C.byref(bits), C.byref(ev))
+    return bits.value, ev.value
 
 
 def mask_bits(mask: str) -> int:
