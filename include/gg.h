@@ -67,6 +67,8 @@ typedef struct {
 typedef struct {
     int32_t seq_id, score, q_start, q_end, d_start, d_end;
     int32_t box_q_start, box_q_end, box_d_start, box_d_end, box_len;
+    int32_t band_d0;  /* diagonal (d - q) the alignment band was centred on: floor of the
+                         mean of the merged runs' extreme diagonals (gg_traceback uses it) */
 } gg_hit;
 
 /* Per-query work counts of one search. */

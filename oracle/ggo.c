@@ -589,6 +589,7 @@ int64_t ggo_bsw(const uint8_t *q, const uint8_t *s, const ggo_box *b, const ggo_
     out->box_d_start = b->ds;
     out->box_d_end = b->de;
     out->box_len = box_len(b);
+    out->band_d0 = d0;
     return cells;
 }
 
@@ -610,6 +611,7 @@ static int cmp_report(const void *a, const void *b)
     if (x->box_d_start != y->box_d_start) return x->box_d_start < y->box_d_start ? -1 : 1;
     if (x->box_q_end != y->box_q_end) return x->box_q_end < y->box_q_end ? -1 : 1;
     if (x->box_d_end != y->box_d_end) return x->box_d_end < y->box_d_end ? -1 : 1;
+    if (x->band_d0 != y->band_d0) return x->band_d0 < y->band_d0 ? -1 : 1;
     return 0;
 }
 

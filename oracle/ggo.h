@@ -59,6 +59,7 @@ typedef struct { int32_t seq, qs, qe, ds, de, dmin, dmax; } ggo_box; /* HSP regi
 typedef struct {
     int32_t seq_id, score, q_start, q_end, d_start, d_end;
     int32_t box_q_start, box_q_end, box_d_start, box_d_end, box_len;
+    int32_t band_d0; /* the diagonal the band was centred on */
 } ggo_hit;
 
 typedef struct {

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libggo.so")
 SRC = os.path.join(HERE, "ggo.c")
 
 HIT_FIELDS = ["seq_id", "score", "q_start", "q_end", "d_start", "d_end",
-              "box_q_start", "box_q_end", "box_d_start", "box_d_end", "box_len"]
+              "box_q_start", "box_q_end", "box_d_start", "box_d_end", "box_len",
+              "band_d0"]
 HIT_DTYPE = np.dtype([(f, np.int32) for f in HIT_FIELDS])
 HITREC_DTYPE = np.dtype([("seq", np.int32), ("diag", np.int32), ("qpos", np.int32)])
 CAND_DTYPE = np.dtype([("seq", np.int32), ("diag", np.int32), ("qs", np.int32), ("qe", np.int32)])

@@ -50,7 +50,10 @@ struct Align {
     int32_t q;
     int32_t seq_id, score, q_start, q_end, d_start, d_end;
     int32_t box_q_start, box_q_end, box_d_start, box_d_end, box_len;
+    int32_t band_d0;
 };
+constexpr int kAlignInts = 13;  // int32 fields of an Align
+constexpr int kHitInts = 12;    // int32 fields of a gg_hit (an Align without q)
 
 // Bit layout of the 64-bit hit key: [q | s | diag + bias | qpos], most
 // significant first.  Sorting the keys orders hits by (q, s, diag, qpos).
@@ -88,7 +91,8 @@ enum BoxField : int32_t {
     F_Q = 0, F_S, F_QS, F_QE, F_DS, F_DE, F_LEN_DESC
 };
 enum AlignField : int32_t {
-    A_Q = 0, A_SCORE_DESC, A_SEQ, A_QS, A_QE, A_DS, A_DE, A_BQS, A_BQE, A_BDS, A_BDE
+    A_Q = 0, A_SCORE_DESC, A_SEQ, A_QS, A_QE, A_DS, A_DE, A_BQS, A_BQE, A_BDS, A_BDE,
+    A_D0  // band centre plus the bias held in desc_max
 };
 
 // Up to 8 fields packed into one 64-bit key word.

@@ -2127,6 +2127,7 @@ __device__ __forceinline__ uint64_t align_field(const Align &a, int32_t f, int32
     case A_BQS: return (uint32_t)a.box_q_start;
     case A_BQE: return (uint32_t)a.box_q_end;
     case A_BDS: return (uint32_t)a.box_d_start;
+    case A_D0: return (uint32_t)(a.band_d0 + desc_max);
     default: return (uint32_t)a.box_d_end;
     }
 }
@@ -2254,7 +2255,8 @@ struct AlignLess {
         if (x.box_q_start != y.box_q_start) return x.box_q_start < y.box_q_start;
         if (x.box_d_start != y.box_d_start) return x.box_d_start < y.box_d_start;
         if (x.box_q_end != y.box_q_end) return x.box_q_end < y.box_q_end;
-        return x.box_d_end < y.box_d_end;
+        if (x.box_d_end != y.box_d_end) return x.box_d_end < y.box_d_end;
+        return x.band_d0 < y.band_d0;
     }
 };
 
@@ -2298,10 +2300,10 @@ __global__ __launch_bounds__(kBlock) void k_report_seg(const Align *__restrict__
     }
     if (dev_out) {
         const uint32_t m = min(nv, (uint32_t)cap);
-        int32_t *dst = dev_out + ((size_t)(qa + ql) * (size_t)cap) * 11;
-        for (uint32_t e = threadIdx.x; e < m * 11; e += blockDim.x) {
-            const int32_t *src = reinterpret_cast<const int32_t *>(&s_r[s_ix[e / 11]]);
-            dst[e] = src[1 + e % 11];
+        int32_t *dst = dev_out + ((size_t)(qa + ql) * (size_t)cap) * kHitInts;
+        for (uint32_t e = threadIdx.x; e < m * kHitInts; e += blockDim.x) {
+            const int32_t *src = reinterpret_cast<const int32_t *>(&s_r[s_ix[e / kHitInts]]);
+            dst[e] = src[1 + e % kHitInts];
         }
     }
 }
@@ -2669,6 +2671,7 @@ __global__ __launch_bounds__(64) void k_bsw(
         r.box_d_start = bx.ds;
         r.box_d_end = bx.de;
         r.box_len = min(R, C);
+        r.band_d0 = d0;
         out[b] = r;
         if (cells_q) atomicAdd(&cells_q[q], cells);
         if (cells_box) cells_box[b] = cells;
@@ -2703,9 +2706,10 @@ __global__ void k_write_out(const Align *__restrict__ sorted, const uint32_t *__
     const uint32_t a = rstart[ql], n = rend[ql] - a;
     if (threadIdx.x == 0) n_out[qa + ql] = (int32_t)n;
     const uint32_t m = min(n, (uint32_t)cap);
-    int32_t *dst = out + ((size_t)(qa + ql) * (size_t)cap) * 11;
-    const int32_t *src = reinterpret_cast<const int32_t *>(sorted + a);  // 12 int32 per record
-    for (uint32_t e = threadIdx.x; e < m * 11; e += blockDim.x) dst[e] = src[(e / 11) * 12 + 1 + e % 11];
+    int32_t *dst = out + ((size_t)(qa + ql) * (size_t)cap) * kHitInts;
+    const int32_t *src = reinterpret_cast<const int32_t *>(sorted + a);
+    for (uint32_t e = threadIdx.x; e < m * kHitInts; e += blockDim.x)
+        dst[e] = src[(e / kHitInts) * kAlignInts + 1 + e % kHitInts];
 }
 
 void launch_write_out(const Align *sorted, const uint32_t *rstart, const uint32_t *rend,

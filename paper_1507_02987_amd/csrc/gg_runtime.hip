@@ -908,7 +908,9 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         TRY(make_words({{A_Q, bq, 0}, {A_SCORE_DESC, bsc, (int32_t)(maxL * p->match)},
                         {A_SEQ, bs, 0}, {A_QS, bl, 0}, {A_DS, bsl, 0}, {A_QE, bl, 0},
                         {A_DE, bsl, 0}, {A_BQS, bl, 0}, {A_BDS, bsl, 0}, {A_BQE, bl, 0},
-                        {A_BDE, bsl, 0}},
+                        {A_BDE, bsl, 0},
+                        {A_D0, bits_for((uint64_t)ix->max_seq_len + (uint64_t)maxL + 1),
+                         (int32_t)maxL}},
                        words));
         TRY(sort_records(ws, nsel, words,
                          [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
@@ -953,7 +955,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                 const Align &a = res[h_rs[ql] + r];
                 dst[r] = gg_hit{a.seq_id,      a.score,     a.q_start,     a.q_end,
                                 a.d_start,     a.d_end,     a.box_q_start, a.box_q_end,
-                                a.box_d_start, a.box_d_end, a.box_len};
+                                a.box_d_start, a.box_d_end, a.box_len,     a.band_d0};
             }
         }
         if (bo.stats) {
@@ -1052,7 +1054,8 @@ gg_status search_pieces(const gg_index *ix, Workspace *ws, Prof &prof, const gg_
     }
     auto rep_key = [](const Align &a) {
         return std::make_tuple(-a.score, a.seq_id, a.q_start, a.d_start, a.q_end, a.d_end,
-                               a.box_q_start, a.box_d_start, a.box_q_end, a.box_d_end);
+                               a.box_q_start, a.box_d_start, a.box_q_end, a.box_d_end,
+                               a.band_d0);
     };
     std::sort(rep.begin(), rep.end(),
               [&](const Align &x, const Align &y) { return rep_key(x) < rep_key(y); });
@@ -1064,7 +1067,7 @@ gg_status search_pieces(const gg_index *ix, Workspace *ws, Prof &prof, const gg_
         const Align &a = rep[(size_t)r];
         hits[(size_t)r] = gg_hit{a.seq_id,      a.score,     a.q_start,     a.q_end,
                                  a.d_start,     a.d_end,     a.box_q_start, a.box_q_end,
-                                 a.box_d_start, a.box_d_end, a.box_len};
+                                 a.box_d_start, a.box_d_end, a.box_len,     a.band_d0};
     }
     if (bo.device) {
         if (m > 0)

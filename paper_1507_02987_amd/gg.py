@@ -20,7 +20,8 @@ STATUS = {0: "GG_OK", 1: "GG_EINVAL", 2: "GG_ENOMEM", 3: "GG_EDEVICE", 4: "GG_EA
           5: "GG_ETRUNC", 6: "GG_ENOTFOUND", 7: "GG_EBUDGET", 8: "GG_EIO"}
 
 HIT_FIELDS = ("seq_id", "score", "q_start", "q_end", "d_start", "d_end",
-              "box_q_start", "box_q_end", "box_d_start", "box_d_end", "box_len")
+              "box_q_start", "box_q_end", "box_d_start", "box_d_end", "box_len",
+              "band_d0")
 HIT_DTYPE = np.dtype([(f, np.int32) for f in HIT_FIELDS])
 STAT_FIELDS = ("n_kmers", "n_hits", "n_cands", "n_merged", "n_selected", "n_cells", "n_out")
 STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])

@@ -92,6 +92,7 @@ def test_masked_exact_copy_found_whole(ggo):
     assert (int(top["seq_id"]), int(top["score"])) == (src, 600)
     assert (int(top["q_start"]), int(top["q_end"]), int(top["d_start"]), int(top["d_end"])) == \
         (0, 600, 100, 700)
+    assert int(top["band_d0"]) == 100  # every run of the copy lies on diagonal 100
 
 
 def test_bad_masks(ggo):

@@ -197,12 +197,14 @@ def test_select_case(ggo):
 def test_report_order_and_drop(ggo):
     dt = np.dtype([(f, np.int32) for f in ggo.HIT_FIELDS])
     rows = [
-        (5, 10, 0, 10, 0, 10, 0, 10, 0, 10, 10),
-        (2, 30, 4, 40, 4, 40, 0, 50, 0, 50, 50),
-        (1, 30, 4, 40, 4, 40, 0, 50, 0, 50, 50),
-        (1, 30, 2, 40, 9, 47, 0, 50, 0, 50, 50),
-        (1, 0, -1, -1, -1, -1, 0, 5, 0, 5, 5),
-        (1, 30, 2, 40, 9, 47, 1, 50, 0, 50, 49),
+        (5, 10, 0, 10, 0, 10, 0, 10, 0, 10, 10, 0),
+        (2, 30, 4, 40, 4, 40, 0, 50, 0, 50, 50, 0),
+        (1, 30, 4, 40, 4, 40, 0, 50, 0, 50, 50, 0),
+        (1, 30, 2, 40, 9, 47, 0, 50, 0, 50, 50, 7),
+        (1, 0, -1, -1, -1, -1, 0, 5, 0, 5, 5, 0),
+        (1, 30, 2, 40, 9, 47, 1, 50, 0, 50, 49, 7),
+        (1, 30, 4, 40, 4, 40, 0, 50, 0, 50, 50, -3),  # ties rows[2] but for the band centre
     ]
     got = ggo.report(np.array(rows, dtype=dt))
-    assert [tuple(r) for r in got.tolist()] == [rows[3], rows[5], rows[2], rows[1], rows[0]]
+    assert [tuple(r) for r in got.tolist()] == [rows[3], rows[5], rows[6], rows[2], rows[1],
+                                                rows[0]]
