@@ -756,3 +756,111 @@ void ggo_significance(int32_t score, int64_t m, int64_t n, double lambda, double
     *bits = (lambda * score - log(K)) / log(2.0);
     *evalue = K * (double)m * (double)n * exp(-lambda * score);
 }
+
+
+/* ------------------------------------------------------------------ traceback
+ * Section 2.2 returns each alignment to the user; its path is read back from the
+ * banded DP [R].  The path of a reported alignment lies in the rectangle
+ * [q_start, q_end) x [d_start, d_end) and in the band of its box (|d - q - band_d0|
+ * <= W), so the DP is recomputed over that rectangle alone, with the recurrences of
+ * O9 and the rectangle's edges as borders.  Along the path every value equals the
+ * box DP's, and no competing value is larger, so the same choices are made: from
+ * the end cell back, a cell continues diagonally if G = H (the path starts there
+ * when its diagonal predecessor is not positive), else through its horizontal gap
+ * if E = H, else through its vertical gap; inside a gap, opening is taken when it
+ * ties extending.  Operations, first to last: '=' and 'X' a matched and a
+ * mismatched pair, 'I' a query base against a gap (vertical), 'D' a bank base
+ * against a gap (horizontal). */
+int32_t ggo_traceback(const ggo_index *ix, const char *query, int64_t qlen, const ggo_params *p,
+                      const ggo_hit *h, char *ops, int64_t cap, int64_t *len)
+{
+    if (!ix || !p || !h || !len || qlen < 0 || qlen > INT32_MAX || (qlen > 0 && !query))
+        return GGO_EINVAL;
+    *len = 0;
+    if (h->seq_id < 0 || h->seq_id >= ix->n_seqs || h->score <= 0) return GGO_EINVAL;
+    const int64_t n_s = ix->seq_off[h->seq_id + 1] - ix->seq_off[h->seq_id];
+    if (h->q_start < 0 || h->q_end <= h->q_start || h->q_end > qlen || h->d_start < 0 ||
+        h->d_end <= h->d_start || h->d_end > n_s)
+        return GGO_EINVAL;
+    const int32_t R = h->q_end - h->q_start, C = h->d_end - h->d_start, W = p->band;
+    const int32_t open1 = p->gap_open + p->gap_extend, ext = p->gap_extend;
+    uint8_t *q = (uint8_t *)malloc((size_t)qlen + 1);
+    int32_t *H = (int32_t *)malloc(sizeof(int32_t) * (size_t)R * (size_t)C);
+    int32_t *E = (int32_t *)malloc(sizeof(int32_t) * (size_t)R * (size_t)C);
+    int32_t *F = (int32_t *)malloc(sizeof(int32_t) * (size_t)R * (size_t)C);
+    char *rev = (char *)malloc((size_t)R + (size_t)C);
+    int32_t rc = GGO_OK;
+    if (!q || !H || !E || !F || !rev) { rc = GGO_ENOMEM; goto done; }
+    if (ggo_encode(query, qlen, q) != GGO_OK) { rc = GGO_EINVAL; goto done; }
+    {
+        const uint8_t *qs = q + h->q_start;
+        const uint8_t *ds = ix->base + ix->seq_off[h->seq_id] + h->d_start;
+#define AT(M, i, j) M[(size_t)(i) * (size_t)C + (size_t)(j)]
+        for (int32_t i = 0; i < R; i++) {
+            for (int32_t j = 0; j < C; j++) {
+                const int32_t diag = (h->d_start + j) - (h->q_start + i) - h->band_d0;
+                if (diag < -W || diag > W) {
+                    AT(H, i, j) = AT(E, i, j) = AT(F, i, j) = NEG_INF;
+                    continue;
+                }
+                const int32_t hd = (i == 0 || j == 0) ? 0 : AT(H, i - 1, j - 1);
+                const int32_t hl = (j == 0) ? 0 : AT(H, i, j - 1);
+                const int32_t el = (j == 0) ? NEG_INF : AT(E, i, j - 1);
+                const int32_t hu = (i == 0) ? 0 : AT(H, i - 1, j);
+                const int32_t fu = (i == 0) ? NEG_INF : AT(F, i - 1, j);
+                const int32_t e = imax(hl - open1, el - ext);
+                const int32_t f = imax(hu - open1, fu - ext);
+                const int32_t g = hd + (qs[i] == ds[j] ? p->match : -p->mismatch);
+                AT(E, i, j) = e;
+                AT(F, i, j) = f;
+                AT(H, i, j) = imax(imax(0, g), imax(e, f));
+            }
+        }
+        if (AT(H, R - 1, C - 1) != h->score) { rc = GGO_EINVAL; goto done; }
+        int32_t i = R - 1, j = C - 1, state = 0; /* 0: H, 1: E (horizontal), 2: F (vertical) */
+        int64_t n = 0;
+        for (;;) {
+            if (i < 0 || j < 0 || n >= (int64_t)R + C) { rc = GGO_EINVAL; goto done; }
+            if (state == 0) {
+                const int32_t hd = (i == 0 || j == 0) ? 0 : AT(H, i - 1, j - 1);
+                const int32_t g = hd + (qs[i] == ds[j] ? p->match : -p->mismatch);
+                if (AT(H, i, j) == g) {
+                    rev[n++] = qs[i] == ds[j] ? '=' : 'X';
+                    if (hd <= 0) {
+                        if (i != 0 || j != 0) { rc = GGO_EINVAL; goto done; }
+                        break;
+                    }
+                    i--;
+                    j--;
+                } else if (AT(H, i, j) == AT(E, i, j)) {
+                    state = 1;
+                } else {
+                    state = 2;
+                }
+            } else if (state == 1) {
+                const int32_t hl = (j == 0) ? 0 : AT(H, i, j - 1);
+                const int32_t el = (j == 0) ? NEG_INF : AT(E, i, j - 1);
+                rev[n++] = 'D';
+                state = (hl - open1 >= el - ext) ? 0 : 1;
+                j--;
+            } else {
+                const int32_t hu = (i == 0) ? 0 : AT(H, i - 1, j);
+                const int32_t fu = (i == 0) ? NEG_INF : AT(F, i - 1, j);
+                rev[n++] = 'I';
+                state = (hu - open1 >= fu - ext) ? 0 : 2;
+                i--;
+            }
+        }
+#undef AT
+        *len = n;
+        if (n > cap || (n > 0 && !ops)) { rc = GGO_ETRUNC; goto done; }
+        for (int64_t t = 0; t < n; t++) ops[t] = rev[n - 1 - t];
+    }
+done:
+    free(q);
+    free(H);
+    free(E);
+    free(F);
+    free(rev);
+    return rc;
+}

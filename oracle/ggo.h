@@ -125,6 +125,15 @@ int32_t ggo_karlin_altschul(int32_t match, int32_t mismatch, double *lambda, dou
 void ggo_significance(int32_t score, int64_t m, int64_t n, double lambda, double K, double *bits,
                       double *evalue);
 
+/* Path of one reported alignment (Section 2.2 returns each alignment) [R]: the O9
+ * DP recomputed over [q_start, q_end) x [d_start, d_end) inside the band centred
+ * on band_d0, walked back from the end cell.  ops receives '=' 'X' 'I' 'D' (pair,
+ * mismatch, query base vs gap, bank base vs gap), first to last; *len its length.
+ * GGO_EINVAL if the hit is not an alignment of this query and bank under p;
+ * GGO_ETRUNC if *len > cap. */
+int32_t ggo_traceback(const ggo_index *ix, const char *query, int64_t qlen, const ggo_params *p,
+                      const ggo_hit *h, char *ops, int64_t cap, int64_t *len);
+
 void ggo_free(void *ptr);
 
 #ifdef __cplusplus

@@ -91,6 +91,9 @@ def lib():
         L.ggo_significance.argtypes = [i32, i64, i64, C.c_double, C.c_double,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ggo_significance.restype = None
+        L.ggo_traceback.argtypes = [C.POINTER(_Index), vp, i64, C.POINTER(Params), vp, vp, i64,
+                                    C.POINTER(i64)]
+        L.ggo_traceback.restype = i32
         L.ggo_masked_code.argtypes = [vp, i32, C.c_uint32]
         L.ggo_masked_code.restype = C.c_uint32
         L.ggo_index_free.argtypes = [C.POINTER(_Index)]
@@ -241,6 +244,20 @@ class Index:
         if not p.value:
             return np.zeros(0, HITREC_DTYPE)
         return _take(p, n.value, HITREC_DTYPE)
+
+    def traceback(self, query: bytes | np.ndarray, prm: Params, hit) -> str:
+        """The path of one reported hit as '=' 'X' 'I' 'D' operations, first to last."""
+        q = np.frombuffer(bytes(query), np.uint8) if not isinstance(query, np.ndarray) else query
+        q = np.ascontiguousarray(q, dtype=np.uint8)
+        h = np.ascontiguousarray(np.array(hit, dtype=HIT_DTYPE).reshape(1))
+        cap = int(h["q_end"][0] - h["q_start"][0] + h["d_end"][0] - h["d_start"][0]) + 1
+        buf = C.create_string_buffer(max(cap, 1))
+        n = C.c_int64()
+        rc = lib().ggo_traceback(self._p, _ptr(q), len(q), C.byref(prm), _ptr(h), buf, cap,
+                                 C.byref(n))
+        if rc != 0:
+            raise ValueError(f"ggo_traceback failed with status {rc}")
+        return buf.raw[:n.value].decode()
 
     def search(self, query: bytes | np.ndarray, prm: Params, cap: int = 1 << 16):
         q = np.frombuffer(bytes(query), np.uint8) if not isinstance(query, np.ndarray) else query
