@@ -179,6 +179,45 @@ gg_status gg_index_export(const gg_index *index, uint32_t *list_off, int32_t *po
 gg_status gg_index_save(const gg_index *index, const char *path);
 gg_status gg_index_load(const char *path, int32_t device, gg_index **out);
 
+/*
+ * Report fields of Section 2.2: with each alignment the search returns its score,
+ * positions, e-value, normalized score and the alignment itself.
+ *
+ * gg_karlin_altschul: lambda, K and H (relative entropy, nats per pair) of ungapped
+ * local alignment scored +match / -mismatch on uniform, independent bases
+ * (Karlin-Altschul statistics; the paper does not say how its e-values are made,
+ * and gapped constants would need simulation).  GG_EINVAL for a non-positive score.
+ *
+ * gg_hit_significance: for n hits of one query of query_len bases searched
+ * against bank_bases bases (gg_index_info's n_bases: both strands when indexed),
+ * bit_score[i] = (lambda S - ln K) / ln 2 and evalue[i] = K m n exp(-lambda S),
+ * S = hits[i].score, in double precision on the host.  Arrays of n, caller-owned.
+ *
+ * gg_traceback: the path of each of n reported hits of one query (hits as the
+ * search returned them for this query, index and params).  The banded DP is
+ * recomputed on the GPU over the hit's rectangle [q_start, q_end) x
+ * [d_start, d_end), in the band of half-width params->band centred on band_d0,
+ * and walked back from the end cell with the search's own choices (diagonal first,
+ * then a gap in the query, then a gap in the bank; a gap opened rather than
+ * extended on ties), so it ends exactly on (q_start, d_start).  Operations, first
+ * to last, one byte each: '=' a matched pair, 'X' a mismatched pair, 'I' a query
+ * base against a gap, 'D' a bank base against a gap.  Hit h's operations are
+ * written at ops + ops_off[h], ops_len[h] of them; ops_off (n + 1 entries) gives
+ * every hit a slot of (q_end - q_start) + (d_end - d_start) bytes and is always
+ * filled first.  GG_ETRUNC (nothing else written) when ops is NULL or ops_cap <
+ * ops_off[n]; GG_EINVAL for bad parameters, a hit outside the query or bank, or a
+ * hit that is not an alignment of this query and bank under params (its ops_len
+ * is 0; the other hits are still written).  All buffers are caller-owned host
+ * memory.
+ */
+gg_status gg_karlin_altschul(int32_t match, int32_t mismatch, double *lambda, double *K,
+                             double *H);
+gg_status gg_hit_significance(const gg_hit *hits, int64_t n, int64_t query_len, int64_t bank_bases,
+                              double lambda, double K, double *bit_score, double *evalue);
+gg_status gg_traceback(const gg_index *index, const char *query, int64_t qlen,
+                       const gg_params *params, const gg_hit *hits, int32_t n, char *ops,
+                       int64_t ops_cap, int64_t *ops_off, int32_t *ops_len);
+
 /* Sizes of a built index: windows indexed, bases, sequences, k. */
 gg_status gg_index_info(const gg_index *index, int64_t *n_postings, int64_t *n_bases,
                         int64_t *n_seqs, int32_t *k);

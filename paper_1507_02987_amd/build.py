@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgg.so")
-SOURCES = ["gg_kernels.hip", "gg_runtime.hip", "gg_server.hip"]
+SOURCES = ["gg_kernels.hip", "gg_runtime.hip", "gg_server.hip", "gg_stats.hip"]
 ARCH = os.environ.get("GG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -134,6 +134,15 @@ void launch_window_keys(const uint32_t *dbw, const int64_t *seq_start, const uin
                         uint64_t *keys, uint32_t *vals, uint32_t *counts, hipStream_t st);
 void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff, int32_t n_seqs,
                      int32_t span, int2 *post, hipStream_t st);
+// Traceback of n reported alignments (gg_hit records, kHitInts int32 each) of one
+// query (ASCII): per-hit direction rows of 64 bytes at dirs + dir_off[h], the
+// operations right-aligned in ops[ops_off[h] .. ops_off[h] + (q span + d span)),
+// their count in ops_len[h] and status[h] (0 ok, 1 not an alignment).
+void launch_traceback(const int32_t *hits, int32_t n, const uint8_t *qascii, int64_t qlen,
+                      const uint32_t *dbw, const int64_t *seq_start, int32_t n_seqs, int32_t match,
+                      int32_t mismatch, int32_t gap_open, int32_t gap_extend, int32_t band,
+                      const int64_t *dir_off, uint8_t *dirs, const int64_t *ops_off, char *ops,
+                      int32_t *ops_len, int32_t *status, hipStream_t st);
 // Both strands: dst holds each sequence's reverse complement at the sequence's own
 // start (start: n_seqs + 1 forward starts).
 void launch_reverse_strand(const uint8_t *src, const int64_t *start, int32_t n_seqs, uint8_t *dst,

@@ -2695,6 +2695,228 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                                out, cells_per_q, cells_per_box, ctl);
 }
 
+// ------------------------------------------------------------------ traceback
+// The path of each reported alignment (one wave per hit, grid-stride): the banded
+// DP recomputed over the hit's rectangle [q_start, q_end) x [d_start, d_end) in the
+// band |j - i - cc| <= W around the hit's band centre, row by row.  Row i's band
+// slot t is column j = i + cc - W + t; a lane holds slots lane and lane + 64.  The
+// horizontal gap of a row is a prefix maximum over its slots: E(t) = max over
+// t' < t of H'(t') - o1 - ext (t - 1 - t'), with H' = max(0, G, F) (a gap opened
+// after a gap never beats extending it when gap_open >= 0), then H = max(H', E).
+// Each cell stores 4 bits: how H was reached (0 diagonal, 1 horizontal gap, 2
+// vertical gap, 3 diagonal from a non-positive predecessor or H <= 0) and whether
+// each gap was opened here (ties open).  Lane 0 then walks back from the end cell
+// with the same priorities, rescoring as it goes, and writes the operations
+// right-aligned in the hit's slot.  status[h] = 0 when the walk ends on the
+// rectangle's first cell with the hit's score, 1 otherwise (not an alignment of
+// this query, bank and scoring).
+__global__ __launch_bounds__(64) void k_traceback(
+    const int32_t *__restrict__ hits, int32_t n, const uint8_t *__restrict__ qascii, int64_t qlen,
+    const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t n_seqs,
+    int32_t match, int32_t mismatch, int32_t o1, int32_t ext, int32_t W,
+    const int64_t *__restrict__ dir_off, uint8_t *__restrict__ dirs,
+    const int64_t *__restrict__ ops_off, char *__restrict__ ops, int32_t *__restrict__ ops_len,
+    int32_t *__restrict__ status)
+{
+    constexpr int32_t NEG = kNegInf;
+    constexpr int32_t LOW = -(1 << 30) - (1 << 28);  // below every score a scan can see
+    const int32_t lane = threadIdx.x;
+    __shared__ int32_t s_hend, s_bad;
+    for (int32_t h = blockIdx.x; h < n; h += gridDim.x) {
+        const int32_t *hr = hits + (size_t)h * kHitInts;
+        const int32_t s = hr[0], score = hr[1], qs = hr[2], qe = hr[3], ds = hr[4], de = hr[5];
+        const int32_t d0 = hr[11];
+        const int32_t R = qe - qs, C = de - ds, cc = d0 - (ds - qs);
+        if (lane == 0) {
+            s_hend = NEG;
+            s_bad = 0;
+        }
+        __syncthreads();
+        // the host checked the query span and the sequence id; the bank span is
+        // checked here, before any base is read
+        const bool shape_ok = s >= 0 && s < n_seqs && qs >= 0 && R > 0 && (int64_t)qe <= qlen &&
+                              ds >= 0 && C > 0 &&
+                              (int64_t)de <= seq_start[s + 1] - seq_start[s] && score > 0 &&
+                              (C - 1) - (R - 1) - cc <= W && (C - 1) - (R - 1) - cc >= -W;
+        if (!shape_ok) {
+            if (lane == 0) {
+                ops_len[h] = 0;
+                status[h] = 1;
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint8_t *qp = qascii + qs;
+        const int64_t dbase = seq_start[s] + ds;
+        uint8_t *drow = dirs + dir_off[h];
+        int32_t hp1 = NEG, hp2 = NEG, fp1 = NEG, fp2 = NEG;  // previous row, slots lane, lane + 64
+        int32_t bad = 0;
+        for (int32_t i = 0; i < R; ++i) {
+            const int32_t jb = i + cc - W;  // column of slot 0
+            const int32_t qb = base_code(qp[i]);
+            bad |= qb < 0;
+            // up neighbours: slot t + 1 of the previous row
+            const int32_t up1h = __shfl_down(hp1, 1, 64), up1f = __shfl_down(fp1, 1, 64);
+            const int32_t up2h = __shfl_down(hp2, 1, 64), up2f = __shfl_down(fp2, 1, 64);
+            const int32_t wrap_h = __shfl(hp2, 0, 64), wrap_f = __shfl(fp2, 0, 64);
+            int32_t hv[2], ev[2], fv[2], gv[2], dg[2], fo[2], tt[2], jj[2];
+            bool ok[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int32_t t = lane + 64 * x;
+                const int32_t j = jb + t;
+                tt[x] = t;
+                jj[x] = j;
+                ok[x] = t <= 2 * W && j >= 0 && j < C;
+                const int32_t hprev = x ? hp2 : hp1;
+                int32_t uh = x ? (lane == 63 ? NEG : up2h) : (lane == 63 ? wrap_h : up1h);
+                int32_t uf = x ? (lane == 63 ? NEG : up2f) : (lane == 63 ? wrap_f : up1f);
+                if (i == 0) {
+                    uh = 0;
+                    uf = NEG;
+                }
+                const int32_t dh = (i == 0 || j == 0) ? 0 : hprev;
+                int32_t g = NEG, f = NEG, hpr = NEG;
+                fo[x] = 0;
+                if (ok[x]) {
+                    const int32_t db = db_base(dbw, dbase + j);
+                    g = dh + (qb == db ? match : -mismatch);
+                    f = max(uh - o1, uf - ext);
+                    fo[x] = (uh - o1 >= uf - ext) ? 1 : 0;
+                    hpr = max(max(0, g), f);
+                }
+                gv[x] = g;
+                dg[x] = dh;
+                fv[x] = f;
+                hv[x] = hpr;
+            }
+            // horizontal gaps: exclusive prefix maximum of H'(t) + ext t over the slots
+            int32_t a1 = ok[0] ? hv[0] + ext * tt[0] : LOW;
+            int32_t a2 = ok[1] ? hv[1] + ext * tt[1] : LOW;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int32_t b1 = __shfl_up(a1, off, 64), b2 = __shfl_up(a2, off, 64);
+                if (lane >= off) {
+                    a1 = max(a1, b1);
+                    a2 = max(a2, b2);
+                }
+            }
+            const int32_t tot1 = __shfl(a1, 63, 64);
+            int32_t pm1 = __shfl_up(a1, 1, 64), pm2 = __shfl_up(a2, 1, 64);
+            if (lane == 0) {
+                pm1 = LOW;
+                pm2 = LOW;
+            }
+            pm2 = max(pm2, tot1);
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int32_t pm = x ? pm2 : pm1;
+                ev[x] = (ok[x] && pm > LOW) ? max(pm - o1 - ext * (tt[x] - 1), NEG - ext) : NEG;
+                if (ok[x]) hv[x] = max(hv[x], ev[x]);
+            }
+            // left neighbours: slot t - 1 of this row
+            int32_t l1h = __shfl_up(hv[0], 1, 64), l1e = __shfl_up(ev[0], 1, 64);
+            int32_t l2h = __shfl_up(hv[1], 1, 64), l2e = __shfl_up(ev[1], 1, 64);
+            const int32_t w2h = __shfl(hv[0], 63, 64), w2e = __shfl(ev[0], 63, 64);
+            if (lane == 0) {
+                l1h = NEG;
+                l1e = NEG;
+                l2h = w2h;
+                l2e = w2e;
+            }
+            uint8_t byte = 0;
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                int32_t lh = x ? l2h : l1h, le = x ? l2e : l1e;
+                if (jj[x] == 0) {
+                    lh = 0;
+                    le = NEG;
+                }
+                const int32_t eo = (lh - o1 >= le - ext) ? 1 : 0;
+                int32_t src = 3;
+                if (ok[x] && hv[x] > 0) {
+                    if (gv[x] == hv[x]) src = dg[x] > 0 ? 0 : 3;
+                    else if (ev[x] == hv[x]) src = 1;
+                    else src = 2;
+                }
+                const uint8_t nib = (uint8_t)(src | (eo << 2) | (fo[x] << 3));
+                byte |= (uint8_t)(nib << (4 * x));
+                if (ok[x] && i == R - 1 && jj[x] == C - 1) s_hend = hv[x];
+            }
+            drow[(size_t)i * 64 + lane] = byte;
+            hp1 = ok[0] ? hv[0] : NEG;
+            hp2 = ok[1] ? hv[1] : NEG;
+            fp1 = ok[0] ? fv[0] : NEG;
+            fp2 = ok[1] ? fv[1] : NEG;
+        }
+        if (bad) s_bad = 1;
+        __threadfence_block();
+        __syncthreads();
+        if (lane == 0) {
+            bool good = s_hend == score && !s_bad;
+            const volatile uint8_t *vd = drow;
+            char *o = ops + ops_off[h];
+            const int64_t cap = (int64_t)R + C;
+            int32_t i = R - 1, j = C - 1, state = 0;
+            int64_t k = 0;
+            int64_t sum = 0;
+            while (good) {
+                const int32_t t = j - (i + cc - W);
+                if (i < 0 || j < 0 || k >= cap || t < 0 || t > 2 * W) {
+                    good = false;
+                    break;
+                }
+                const uint8_t nib = (uint8_t)(vd[(size_t)i * 64 + (t & 63)] >> (4 * (t >> 6))) & 15u;
+                if (state == 0) {
+                    const int32_t src = nib & 3;
+                    if (src == 0 || src == 3) {
+                        const bool eq = base_code(qp[i]) == db_base(dbw, dbase + j);
+                        o[cap - 1 - k++] = eq ? '=' : 'X';
+                        sum += eq ? match : -mismatch;
+                        if (src == 3) {
+                            good = i == 0 && j == 0;
+                            break;
+                        }
+                        --i;
+                        --j;
+                    } else {
+                        state = src;
+                    }
+                } else if (state == 1) {
+                    o[cap - 1 - k++] = 'D';
+                    const bool opened = (nib >> 2) & 1u;
+                    sum -= opened ? o1 : ext;
+                    state = opened ? 0 : 1;
+                    --j;
+                } else {
+                    o[cap - 1 - k++] = 'I';
+                    const bool opened = (nib >> 3) & 1u;
+                    sum -= opened ? o1 : ext;
+                    state = opened ? 0 : 2;
+                    --i;
+                }
+            }
+            good = good && sum == score;
+            ops_len[h] = good ? (int32_t)k : 0;
+            status[h] = good ? 0 : 1;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_traceback(const int32_t *hits, int32_t n, const uint8_t *qascii, int64_t qlen,
+                      const uint32_t *dbw, const int64_t *seq_start, int32_t n_seqs, int32_t match,
+                      int32_t mismatch, int32_t gap_open, int32_t gap_extend, int32_t band,
+                      const int64_t *dir_off, uint8_t *dirs, const int64_t *ops_off, char *ops,
+                      int32_t *ops_len, int32_t *status, hipStream_t st)
+{
+    if (n <= 0) return;
+    const uint32_t grid = std::min<uint32_t>((uint32_t)n, kMaxGrid);
+    k_traceback<<<grid, 64, 0, st>>>(hits, n, qascii, qlen, dbw, seq_start, n_seqs, match,
+                                     mismatch, gap_open + gap_extend, gap_extend, band, dir_off,
+                                     dirs, ops_off, ops, ops_len, status);
+}
+
 // ------------------------------------------------------------------ results to device memory
 // One block per query: its first min(cap, n) ordered alignments become gg_hit
 // records at out[q * cap], and its count goes to n_out[q].

@@ -107,6 +107,7 @@ struct Workspace {
     DevBuf bplan, bcount, boff, bcands, btmp, bcoff, ctmp, cursor, qcur, bound_q, bound_off,
         btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue, gout, gn,
         gctl, gplan, gcursor, goflags, stiles, gtiles;
+    DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
     // the captured wave graph and what it was captured for (every argument baked
@@ -133,7 +134,8 @@ struct Workspace {
                          &cells_q, &bplan, &bcount, &boff, &bcands, &btmp, &bcoff, &ctmp, &cursor, &qcur,
                          &bound_q, &bound_off, &btmp_b, &bounds, &blist, &pcnt, &cells_box,
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
-                         &gcursor, &goflags, &stiles, &gtiles};
+                         &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
+                         &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -2180,6 +2182,84 @@ gg_status gg_search(const gg_index *ix, const char *query, int64_t qlen, const g
     if (qlen < 0 || (qlen > 0 && !query) || !n_out) return GG_EINVAL;
     const int64_t off[2] = {0, qlen};
     return gg_search_batch(ix, query, off, 1, params, out, cap, n_out, nullptr);
+}
+
+gg_status gg_traceback(const gg_index *ix, const char *query, int64_t qlen, const gg_params *params,
+                       const gg_hit *hits, int32_t n, char *ops, int64_t ops_cap, int64_t *ops_off,
+                       int32_t *ops_len)
+{
+    if (!ix || qlen < 0 || qlen > INT32_MAX || (qlen > 0 && !query) || n < 0 ||
+        (n > 0 && (!hits || !ops_off || !ops_len)))
+        return GG_EINVAL;
+    TRY(check_params(params));
+    // slots: each hit's operations fit in (query span + bank span) bytes
+    std::vector<int64_t> dir_off((size_t)n + 1, 0);
+    ops_off[0] = 0;
+    for (int32_t h = 0; h < n; ++h) {
+        const gg_hit &x = hits[h];
+        if (x.seq_id < 0 || x.seq_id >= ix->n_seqs || x.q_start < 0 || x.q_end <= x.q_start ||
+            x.q_end > qlen || x.d_start < 0 || x.d_end <= x.d_start || x.score <= 0)
+            return GG_EINVAL;
+        const int64_t R = x.q_end - x.q_start, C = x.d_end - x.d_start;
+        ops_off[h + 1] = ops_off[h] + R + C;
+        dir_off[(size_t)h + 1] = dir_off[(size_t)h] + 64 * R;
+    }
+    if (n == 0) return GG_OK;
+    if (ops_cap < ops_off[n] || !ops) return GG_ETRUNC;
+    if (hipSetDevice(ix->device) != hipSuccess) return GG_EDEVICE;
+    Workspace *ws = nullptr;
+    TRY(get_ws(ix, &ws));
+    std::vector<char> slots((size_t)ops_off[n]);
+    std::vector<int32_t> len((size_t)n), status((size_t)n);
+    auto run = [&]() -> gg_status {
+        hipStream_t st = ws->st;
+        TRY(ensure(ws->tb_hits, sizeof(gg_hit) * (size_t)n));
+        TRY(ensure(ws->tb_q, (size_t)qlen));
+        TRY(ensure(ws->tb_dir, (size_t)dir_off[(size_t)n]));
+        TRY(ensure(ws->tb_dir_off, sizeof(int64_t) * (size_t)(n + 1)));
+        TRY(ensure(ws->tb_ops_off, sizeof(int64_t) * (size_t)(n + 1)));
+        TRY(ensure(ws->tb_ops, (size_t)ops_off[n]));
+        TRY(ensure(ws->tb_len, sizeof(int32_t) * (size_t)n));
+        TRY(ensure(ws->tb_status, sizeof(int32_t) * (size_t)n));
+        HIPCHK(hipMemcpyAsync(ws->tb_hits.p, hits, sizeof(gg_hit) * (size_t)n,
+                              hipMemcpyHostToDevice, st));
+        if (qlen > 0)
+            HIPCHK(hipMemcpyAsync(ws->tb_q.p, query, (size_t)qlen, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ws->tb_dir_off.p, dir_off.data(), sizeof(int64_t) * (size_t)(n + 1),
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ws->tb_ops_off.p, ops_off, sizeof(int64_t) * (size_t)(n + 1),
+                              hipMemcpyHostToDevice, st));
+        launch_traceback(as<int32_t>(ws->tb_hits), n, as<uint8_t>(ws->tb_q), qlen, ix->d_dbw,
+                         ix->d_seq_start, (int32_t)ix->n_seqs, params->match, params->mismatch,
+                         params->gap_open, params->gap_extend, params->band,
+                         as<int64_t>(ws->tb_dir_off), as<uint8_t>(ws->tb_dir),
+                         as<int64_t>(ws->tb_ops_off), as<char>(ws->tb_ops), as<int32_t>(ws->tb_len),
+                         as<int32_t>(ws->tb_status), st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(slots.data(), ws->tb_ops.p, slots.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(len.data(), ws->tb_len.p, sizeof(int32_t) * (size_t)n,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(status.data(), ws->tb_status.p, sizeof(int32_t) * (size_t)n,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return GG_OK;
+    };
+    gg_status s = run();
+    if (s != GG_OK) {
+        (void)hipStreamSynchronize(ws->st);
+        (void)hipGetLastError();
+    }
+    put_ws(ix, ws);
+    if (s != GG_OK) return s;
+    // the kernel wrote each path right-aligned in its slot; hand it over left-aligned
+    bool all_ok = true;
+    for (int32_t h = 0; h < n; ++h) {
+        const int64_t slot = ops_off[h + 1] - ops_off[h];
+        ops_len[h] = status[(size_t)h] == 0 ? len[(size_t)h] : 0;
+        all_ok = all_ok && status[(size_t)h] == 0;
+        memcpy(ops + ops_off[h], slots.data() + ops_off[h] + slot - ops_len[h], (size_t)ops_len[h]);
+    }
+    return all_ok ? GG_OK : GG_EINVAL;
 }
 
 gg_status gg_profile_enable(gg_index *ix, int32_t on)

@@ -29,6 +29,7 @@ STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 # Exported symbols of include/gg.h, in declaration order.
 SYMBOLS = ("gg_index_build", "gg_index_build_masked", "gg_index_build_ex", "gg_index_free",
            "gg_index_info", "gg_index_export", "gg_index_save", "gg_index_load",
+           "gg_karlin_altschul", "gg_hit_significance", "gg_traceback",
            "gg_index_set_hit_budget",
            "gg_index_get_tuning", "gg_index_set_tuning", "gg_index_autotune",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
@@ -61,6 +62,27 @@ class Tuning(C.Structure):
 GROUPINGS = ("probe", "bucket", "sort")
 
 
+def karlin_altschul(match: int = 1, mismatch: int = 3) -> tuple[float, float, float]:
+    """gg_karlin_altschul: (lambda, K, H) of ungapped scoring on uniform bases."""
+    lam, K, H = C.c_double(), C.c_double(), C.c_double()
+    rc = lib().gg_karlin_altschul(match, mismatch, C.byref(lam), C.byref(K), C.byref(H))
+    if rc != GG_OK:
+        raise GGError(rc, "gg_karlin_altschul")
+    return lam.value, K.value, H.value
+
+
+def significance(hits: np.ndarray, query_len: int, bank_bases: int, lam: float, K: float):
+    """gg_hit_significance: (bit scores, e-values) of one query's hits."""
+    h = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    bits = np.zeros(max(len(h), 1))
+    ev = np.zeros(max(len(h), 1))
+    rc = lib().gg_hit_significance(_ptr(h) if len(h) else None, len(h), query_len, bank_bases,
+                                   lam, K, _ptr(bits), _ptr(ev))
+    if rc != GG_OK:
+        raise GGError(rc, "gg_hit_significance")
+    return bits[:len(h)], ev[:len(h)]
+
+
 def params(max_hits: int = 20, match: int = 1, mismatch: int = 3, gap_open: int = 5,
            gap_extend: int = 2, band: int = 32, xdrop: int = 20, max_gap: int = 22,
            min_hsp_len: int = 22) -> Params:
@@ -84,6 +106,10 @@ def lib():
         L.gg_index_build_ex.argtypes = [vp, vp, i64, C.POINTER(IndexOptions), i32, C.POINTER(vp)]
         L.gg_index_export.argtypes = [vp, vp, vp, i64]
         L.gg_index_save.argtypes = [vp, C.c_char_p]
+        dp = C.POINTER(C.c_double)
+        L.gg_karlin_altschul.argtypes = [i32, i32, dp, dp, dp]
+        L.gg_hit_significance.argtypes = [vp, i64, i64, i64, C.c_double, C.c_double, vp, vp]
+        L.gg_traceback.argtypes = [vp, vp, i64, C.POINTER(Params), vp, i32, vp, i64, vp, vp]
         L.gg_index_load.argtypes = [C.c_char_p, i32, C.POINTER(vp)]
         L.gg_index_free.argtypes = [vp]
         L.gg_index_free.restype = None
@@ -216,6 +242,22 @@ class Index:
         if rc != GG_OK:
             raise GGError(rc, "gg_index_export")
         return heads, post[:n]
+
+    def traceback(self, query, prm: Params, hits: np.ndarray):
+        """gg_traceback: (status, list of operation strings, one per hit)."""
+        q = _u8(query)
+        h = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+        n = len(h)
+        off = np.zeros(n + 1, np.int64)
+        ln = np.zeros(max(n, 1), np.int32)
+        spans = (h["q_end"].astype(np.int64) - h["q_start"]) + (h["d_end"] - h["d_start"])
+        cap = int(spans.clip(min=0).sum()) if n else 0
+        buf = np.zeros(max(cap, 1), np.uint8)
+        rc = lib().gg_traceback(self._h, _ptr(q) if len(q) else None, len(q), C.byref(prm),
+                                _ptr(h) if n else None, n, _ptr(buf), cap, _ptr(off), _ptr(ln))
+        if rc not in (GG_OK, GG_EINVAL) or (rc == GG_EINVAL and n and off[n] == 0):
+            return rc, []
+        return rc, [buf[off[i]:off[i] + ln[i]].tobytes().decode() for i in range(n)]
 
     def set_hit_budget(self, nbytes: int):
         rc = lib().gg_index_set_hit_budget(self._h, int(nbytes))
