@@ -1264,6 +1264,19 @@ __device__ __forceinline__ TileView tile_view(uint32_t tile, uint32_t n, uint32_
     return v;
 }
 
+// Blocks are handed to the 8 XCDs in turn (block b to XCD b % 8), and each XCD
+// has its own L2.  Consecutive tiles write neighbouring runs of each digit, which
+// share cache lines at their ends; giving every XCD one contiguous chunk of the
+// active tiles (in block order within the chunk) keeps those shared lines in one
+// L2, where the partial writes merge instead of each L2 reading the line back from
+// HBM.  A bijection on [0, active); blocks past it keep their own number.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t active)
+{
+    if (b >= active) return b;
+    const uint32_t x = b & 7u, slot = b >> 3, q = active >> 3, r = active & 7u;
+    return x * q + min(x, r) + slot;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys, uint32_t n,
                                                     int shift, uint32_t *__restrict__ hist,
                                                     uint32_t nb, const WaveCtl *__restrict__ ctl,
@@ -1279,7 +1292,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
             ntile = ctl->ntile;
         }
     }
-    const TileView tv = tile_view(blockIdx.x, n, nb, tiles, ntile);
+    const uint32_t active = tiles ? ntile : (n + kSortTile - 1) / kSortTile;
+    const TileView tv = tile_view(xcd_tile(blockIdx.x, active), n, nb, tiles, ntile);
     h[threadIdx.x] = 0;
     __syncthreads();
 #pragma unroll
@@ -1383,7 +1397,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
     for (int i = 0; i < kBlock / 64; ++i) s_wc[i][threadIdx.x] = 0;
     if (LB && threadIdx.x == 0) s_tile = atomicAdd(lb.counter, 1u);
     __syncthreads();
-    const uint32_t tile = LB ? s_tile : blockIdx.x;
+    const uint32_t tile =
+        LB ? s_tile : xcd_tile(blockIdx.x, tiles ? ntile : (n + kSortTile - 1) / kSortTile);
     const TileView tv = tile_view(tile, n, nb, tiles, ntile);
     if (tv.cnt == 0) return;  // whole block: only capacity tiles of a graph are empty
     const uint32_t sub = w * 64 * kSortItems;  // this wave's first key in the tile
