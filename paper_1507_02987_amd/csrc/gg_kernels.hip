@@ -344,7 +344,10 @@ void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, 
 }
 
 // ------------------------------------------------------------------ scans
-// Three passes: per-tile sums, one block scanning the tile sums, per-tile scan.
+// Per-tile sums, then a per-tile scan whose offset is the sum of the earlier tiles'
+// sums.  Up to kScanFuse tiles, each tile adds the earlier sums up itself (they are
+// few and cached); beyond that one block first scans the tile sums.
+constexpr int64_t kScanFuse = 2048;
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI *__restrict__ in, int64_t n,
                                                         TO *__restrict__ partials)
@@ -376,12 +379,23 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(TO *__restrict__ parti
     if (threadIdx.x == 0) partials[nb] = carry;
 }
 
-template <typename TI, typename TO>
+template <typename TI, typename TO, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in, int64_t n,
                                                       const TO *__restrict__ partials,
                                                       TO *__restrict__ out, int64_t nb)
 {
     __shared__ TO s_v[kTile];
+    // FUSED: partials holds each tile's sum; this tile's offset is their sum below it
+    TO pre = 0, all = 0;
+    if (FUSED) {
+        TO p = 0;
+        for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) p += partials[b];
+        block_excl_scan<TO>(p, &pre);
+        if (blockIdx.x == nb - 1) all = pre + partials[blockIdx.x];
+    } else {
+        pre = partials[blockIdx.x];
+        all = partials[nb];
+    }
     const int64_t base = (int64_t)blockIdx.x * kTile;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -397,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in,
         s += v[r];
     }
     TO tot;
-    TO run = block_excl_scan<TO>(s, &tot) + partials[blockIdx.x];
+    TO run = block_excl_scan<TO>(s, &tot) + pre;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         s_v[threadIdx.x * kItems + r] = run;
@@ -409,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in,
         const int64_t i = base + r * kBlock + threadIdx.x;
         if (i < n) out[i] = s_v[r * kBlock + threadIdx.x];
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = partials[nb];
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = all;
 }
 
 size_t scan_partials_needed(int64_t n) { return (size_t)((n + kTile - 1) / kTile + 1); }
@@ -423,8 +437,14 @@ static void scan_impl(const TI *in, TO *out, int64_t n, TO *partials, hipStream_
     }
     const int64_t nb = (n + kTile - 1) / kTile;
     k_scan_reduce<TI, TO><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials);
-    k_scan_partials<TO><<<1, kBlock, 0, st>>>(partials, nb);
-    k_scan_down<TI, TO><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials, out, nb);
+    if (nb <= kScanFuse) {
+        k_scan_down<TI, TO, true><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials,
+                                                                               out, nb);
+    } else {
+        k_scan_partials<TO><<<1, kBlock, 0, st>>>(partials, nb);
+        k_scan_down<TI, TO, false><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials,
+                                                                                out, nb);
+    }
 }
 
 void launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *partials,
