@@ -1387,15 +1387,13 @@ __device__ uint32_t look_back(const Lookback &lb, uint32_t tile, uint32_t d, uin
     return (uint32_t)excl;
 }
 
+// Key-only passes: eight waves per SIMD (64 VGPRs) and under 20 KiB of LDS let
+// eight tiles share a CU, so more loads and stores are in flight while tiles rank.
 template <bool VALS, bool LB>
-__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restrict__ kin,
-                                                       const uint32_t *__restrict__ vin,
-                                                       uint64_t *__restrict__ kout,
-                                                       uint32_t *__restrict__ vout, uint32_t n,
-                                                       int shift, const uint32_t *__restrict__ hist,
-                                                       uint32_t nb, Lookback lb,
-                                                       const WaveCtl *__restrict__ ctl,
-                                                       const SortTile *__restrict__ tiles)
+__global__ __launch_bounds__(kBlock, (VALS || LB) ? 4 : 8) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, uint32_t n, int shift, const uint32_t *__restrict__ hist,
+    uint32_t nb, Lookback lb, const WaveCtl *__restrict__ ctl, const SortTile *__restrict__ tiles)
 {
     uint32_t ntile = nb;
     if (ctl) {  // shift holds the pass number
@@ -1408,9 +1406,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
     }
     __shared__ uint64_t s_k[kSortTile];
     __shared__ uint32_t s_v[VALS ? kSortTile : 1];
-    __shared__ uint32_t s_wc[kBlock / 64][kRadix];
-    __shared__ uint32_t s_start[kRadix];
-    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint16_t s_wc[kBlock / 64][kRadix];  // per-wave digit counts, then positions
+    __shared__ uint32_t s_off[kRadix];  // output position of digit d's keys minus their tile position
     __shared__ uint32_t s_tile;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -1441,25 +1438,25 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
         const uint32_t before = s_wc[w][d];
         rank[r] = before + (uint32_t)__popcll(peers & below);
         __builtin_amdgcn_wave_barrier();
-        if (ok && (peers & below) == 0) s_wc[w][d] = before + (uint32_t)__popcll(peers);
+        if (ok && (peers & below) == 0) s_wc[w][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     {
         const uint32_t d = threadIdx.x;
-        uint32_t run = 0;
+        uint32_t run = 0, wc[kBlock / 64];
 #pragma unroll
         for (int i = 0; i < kBlock / 64; ++i) {
-            const uint32_t c = s_wc[i][d];
-            s_wc[i][d] = run;
-            run += c;
+            wc[i] = run;
+            run += s_wc[i][d];
         }
         uint32_t tot;
-        s_start[d] = block_excl_scan<uint32_t>(run, &tot);
-        if (LB)
-            s_gbase[d] = lb.base[d] + look_back(lb, tile, d, run);
-        else
-            s_gbase[d] = hist[(size_t)tv.hidx + (size_t)d * tv.stride];
+        const uint32_t start = block_excl_scan<uint32_t>(run, &tot);  // digit d's first key in the tile
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) s_wc[i][d] = (uint16_t)(start + wc[i]);
+        const uint32_t gbase = LB ? lb.base[d] + look_back(lb, tile, d, run)
+                                  : hist[(size_t)tv.hidx + (size_t)d * tv.stride];
+        s_off[d] = gbase - start;
     }
     __syncthreads();
 #pragma unroll
@@ -1467,7 +1464,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
         const uint32_t idx = sub + r * 64 + lane;
         if (idx < tv.cnt) {
             const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
-            const uint32_t pos = s_start[d] + s_wc[w][d] + rank[r];
+            const uint32_t pos = (uint32_t)s_wc[w][d] + rank[r];
             s_k[pos] = k[r];
             if (VALS) s_v[pos] = v[r];
         }
@@ -1480,7 +1477,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint64_t *__restric
         if (i < tn) {
             const uint64_t key = s_k[i];
             const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
-            const uint32_t o = s_gbase[d] + (i - s_start[d]);
+            const uint32_t o = s_off[d] + i;
             kout[o] = key;
             if (VALS) vout[o] = s_v[i];
         }
