@@ -1690,25 +1690,31 @@ int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *val
 // ------------------------------------------------------------------ S5: chain + filter
 // A sorted hit ends a run when the next hit is in another (q, s, diag) group or
 // more than G past this hit's window; the run's first hit is found by walking back
-// while the chaining rule holds.  Runs with qe - qs >= M are kept.  Two passes
-// over tiles of hits (count, then write after a scan of the tile counts) keep the
-// runs in hit-key order, so they come out grouped by query and sequence.
-__device__ __forceinline__ bool chain_end(const uint64_t *__restrict__ keys, uint32_t n,
-                                          uint32_t i, int bp, int32_t k, int32_t G, int32_t M,
-                                          int32_t *qs_out)
+// while the chaining rule holds (in the tile's LDS copy, then in global memory).
+// Runs with qe - qs >= M are kept.  Two passes over tiles of hits (count, then
+// write after a scan of the tile counts) keep the runs in hit-key order, so they
+// come out grouped by query and sequence.
+//
+// The test on a tile of keys staged in LDS: s_k[1 + l] is key base + l for
+// l < cnt, s_k[cnt + 1] the key after the tile (when i + 1 < n); a walk back that
+// leaves the tile continues in global memory.
+__device__ __forceinline__ bool chain_end_tile(const uint64_t *__restrict__ s_k,
+                                               const uint64_t *__restrict__ keys, uint32_t n,
+                                               uint32_t base, uint32_t l, int bp, int32_t k,
+                                               int32_t G, int32_t M, int32_t *qs_out)
 {
     const uint64_t pmask = low_mask(bp);
-    const uint64_t key = keys[i];
+    const uint64_t key = s_k[1 + l];
     const uint64_t grp = key >> bp;
     const int32_t qp = (int32_t)(key & pmask);
-    if (i + 1 < n) {
-        const uint64_t nx = keys[i + 1];
+    if (base + l + 1 < n) {
+        const uint64_t nx = s_k[2 + l];
         if ((nx >> bp) == grp && (int32_t)(nx & pmask) - (qp + k) <= G) return false;
     }
-    uint32_t j = i;
+    uint32_t j = base + l;
     int32_t qj = qp;
     while (j > 0) {
-        const uint64_t pv = keys[j - 1];
+        const uint64_t pv = j > base ? s_k[j - base] : keys[j - 1];
         if ((pv >> bp) != grp) break;
         const int32_t qv = (int32_t)(pv & pmask);
         if (qj - (qv + k) > G) break;
@@ -1719,22 +1725,39 @@ __device__ __forceinline__ bool chain_end(const uint64_t *__restrict__ keys, uin
     return qp + k - qj >= M;
 }
 
+// Stage keys [base, base + cnt] (the tile and the key after it) in LDS.
+__device__ __forceinline__ uint32_t stage_chain_tile(const uint64_t *__restrict__ keys, uint32_t n,
+                                                     uint32_t base, uint64_t *__restrict__ s_k)
+{
+    const uint32_t cnt = base < n ? min((uint32_t)kTile, n - base) : 0u;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t l = r * kBlock + threadIdx.x;
+        if (l < cnt) s_k[1 + l] = keys[base + l];
+    }
+    if (threadIdx.x == 0 && base + cnt < n) s_k[cnt + 1] = keys[base + cnt];
+    __syncthreads();
+    return cnt;
+}
+
 __global__ __launch_bounds__(kBlock) void k_chain_count(const uint64_t *__restrict__ keys,
                                                         uint32_t n, int bp, int32_t k, int32_t G,
                                                         int32_t M, uint32_t *__restrict__ counts,
                                                         const WaveCtl *__restrict__ ctl)
 {
+    __shared__ uint64_t s_k[kTile + 2];
     if (ctl) {  // tiles past the wave's hits count zero runs
         n = ctl->H;
         bp = ctl->lay.bp;
     }
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
     uint32_t c = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const uint32_t i = base + r * kBlock + threadIdx.x;
+        const uint32_t l = r * kBlock + threadIdx.x;
         int32_t qs;
-        if (i < n && chain_end(keys, n, i, bp, k, G, M, &qs)) ++c;
+        if (l < cnt && chain_end_tile(s_k, keys, n, base, l, bp, k, G, M, &qs)) ++c;
     }
     uint32_t tot;
     block_excl_scan<uint32_t>(c, &tot);
@@ -1754,16 +1777,18 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
     }
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
     if (ctl && base >= n) return;
+    __shared__ uint64_t s_k[kTile + 2];
+    const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
     uint32_t at = tile_off[blockIdx.x];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const uint32_t i = base + r * kBlock + threadIdx.x;
+        const uint32_t l = r * kBlock + threadIdx.x;
         int32_t qs = 0;
-        const bool emit = i < n && chain_end(keys, n, i, lay.bp, k, G, M, &qs);
+        const bool emit = l < cnt && chain_end_tile(s_k, keys, n, base, l, lay.bp, k, G, M, &qs);
         uint32_t tot;
         const uint32_t ex = block_excl_scan<uint32_t>(emit ? 1u : 0u, &tot);
         if (emit) {
-            const uint64_t key = keys[i];
+            const uint64_t key = s_k[1 + l];
             const uint64_t grp = key >> lay.bp;
             Cand c;
             c.d = (int32_t)(grp & low_mask(lay.bd)) - lay.bias;
