@@ -109,8 +109,8 @@ struct KeyWord {
 
 void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
                          int32_t span, uint32_t mask, const uint32_t *list_off, uint8_t *qcode,
-                         uint32_t *kcode, uint32_t *cnt, int32_t *qid, int32_t *err,
-                         hipStream_t st);
+                         uint32_t *kcode, uint32_t *cnt, uint32_t *lhead, int32_t *qid,
+                         int32_t *err, hipStream_t st);
 // out[i] = sum of in[0..i) for i in [0, n]; in is u32, out u64.
 void launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *partials,
                             hipStream_t st);
@@ -120,10 +120,9 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *par
 size_t scan_partials_needed(int64_t n);
 void launch_query_totals(const uint64_t *hoff, const int64_t *qoff, int32_t nq, uint64_t *qtot,
                          hipStream_t st);
-void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
-                      const int32_t *qid, const uint32_t *list_off, int32_t qa, int64_t g0,
-                      int64_t g1, HitKeyLayout lay, uint32_t *hrel, uint32_t *pbase, uint64_t *akey,
-                      hipStream_t st);
+void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
+                      const int32_t *qid, int32_t qa, int64_t g0, int64_t g1, HitKeyLayout lay,
+                      uint32_t *hrel, uint32_t *pbase, uint64_t *akey, hipStream_t st);
 // Index build (Sections 2, 2.1): pack the bank 2 bits per base; code every
 // non-overlapping window (keys = code, vals = window number, counts per code);
 // after a stable sort by code, window numbers become (sequence, position) postings.
@@ -225,10 +224,9 @@ void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 // grids are sized for the largest wave of the batch (hits_cap, np_cap, nq_cap).
 void launch_wave_begin(const WaveCtl *plan, uint32_t *cursor, WaveCtl *ctl, hipStream_t st);
 void launch_wave_end(const WaveCtl *ctl, const uint32_t *cursor, uint32_t *oflags, hipStream_t st);
-void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
-                          const int32_t *qid, const uint32_t *list_off, int64_t np_cap,
-                          uint32_t *hrel, uint32_t *pbase, uint64_t *akey, const WaveCtl *ctl,
-                          hipStream_t st);
+void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
+                          const int32_t *qid, int64_t np_cap, uint32_t *hrel, uint32_t *pbase,
+                          uint64_t *akey, const WaveCtl *ctl, hipStream_t st);
 void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                        const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
                        hipStream_t st);

@@ -300,47 +300,66 @@ void launch_postings(const uint32_t *vals, uint32_t n_win, const uint32_t *woff,
 __global__ __launch_bounds__(kBlock) void k_encode_kmers(
     const uint8_t *__restrict__ ascii, const int64_t *__restrict__ qoff, int32_t nq, int64_t T,
     int32_t span, uint32_t mask, const uint32_t *__restrict__ list_off, uint8_t *__restrict__ qcode,
-    uint32_t *__restrict__ kcode, uint32_t *__restrict__ cnt, int32_t *__restrict__ qid,
-    int32_t *__restrict__ err)
+    uint32_t *__restrict__ kcode, uint32_t *__restrict__ cnt, uint32_t *__restrict__ lhead,
+    int32_t *__restrict__ qid, int32_t *__restrict__ err)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= T) return;
-    int32_t c = base_code(ascii[g]);
-    if (c < 0) {
-        atomicOr(err, 1);
-        c = 0;
+    // the block's bases and the span after them, coded once in LDS; the block's
+    // first and last queries found once
+    __shared__ uint8_t s_c[kBlock + 32];
+    __shared__ int32_t s_q[2];
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    if (threadIdx.x < 2) {
+        const int64_t x = min(g0 + (int64_t)(threadIdx.x ? kBlock - 1 : 0), T - 1);
+        int32_t lo = 0, hi = nq - 1;  // last query whose first base is <= x
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (qoff[mid] <= x) lo = mid;
+            else hi = mid - 1;
+        }
+        s_q[threadIdx.x] = lo;
     }
-    qcode[g] = (uint8_t)c;
-    int32_t lo = 0, hi = nq - 1;  // last query whose first base is <= g
+    for (int32_t x = threadIdx.x; x < kBlock + 32; x += kBlock) {
+        const int64_t gx = g0 + x;
+        int32_t c = gx < T ? base_code(ascii[gx]) : 0;
+        if (c < 0) {
+            if (x < kBlock) atomicOr(err, 1);  // flagged by the base's own block
+            c = 0;
+        }
+        s_c[x] = (uint8_t)c;
+    }
+    __syncthreads();
+    const int64_t g = g0 + threadIdx.x;
+    if (g >= T) return;
+    qcode[g] = s_c[threadIdx.x];
+    int32_t lo = s_q[0], hi = s_q[1];
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
         if (qoff[mid] <= g) lo = mid;
         else hi = mid - 1;
     }
     qid[g] = lo;
-    uint32_t code = 0, n = 0;
+    uint32_t code = 0, n = 0, head = 0;
     if (g + span <= qoff[lo + 1]) {
-        for (int32_t t = 0; t < span; ++t) {
-            if (!((mask >> t) & 1u)) continue;  // a base the mask removes
-            const int32_t b = base_code(ascii[g + t]);
-            code = code * 4u + (uint32_t)(b < 0 ? 0 : b);
-        }
-        n = list_off[code + 1] - list_off[code];
+        for (int32_t t = 0; t < span; ++t)
+            if ((mask >> t) & 1u) code = code * 4u + s_c[threadIdx.x + t];  // kept bases only
+        head = list_off[code];
+        n = list_off[code + 1] - head;
     }
     kcode[g] = code;
     cnt[g] = n;
+    lhead[g] = head;
 }
 
 void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
                          int32_t span, uint32_t mask, const uint32_t *list_off, uint8_t *qcode,
-                         uint32_t *kcode, uint32_t *cnt, int32_t *qid, int32_t *err,
-                         hipStream_t st)
+                         uint32_t *kcode, uint32_t *cnt, uint32_t *lhead, int32_t *qid,
+                         int32_t *err, hipStream_t st)
 {
     if (T <= 0) return;
     const int64_t nb = (T + kBlock - 1) / kBlock;
     k_encode_kmers<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(ascii, qoff, nq, T, span, mask,
-                                                                list_off, qcode, kcode, cnt, qid,
-                                                                err);
+                                                                list_off, qcode, kcode, cnt, lhead,
+                                                                qid, err);
 }
 
 // ------------------------------------------------------------------ scans
@@ -478,8 +497,8 @@ void launch_query_totals(const uint64_t *hoff, const int64_t *qoff, int32_t nq, 
 // posting list's head, and the constant part of its hits' keys
 // (q << sh_q) + ((bias - qpos) << sh_d) + qpos.
 __global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__restrict__ qoff,
-                            const uint32_t *__restrict__ kcode, const int32_t *__restrict__ qid,
-                            const uint32_t *__restrict__ list_off, int32_t qa, int64_t g0,
+                            const uint32_t *__restrict__ lhead, const int32_t *__restrict__ qid,
+                            int32_t qa, int64_t g0,
                             int64_t np, HitKeyLayout lay, uint32_t *__restrict__ hrel,
                             uint32_t *__restrict__ pbase, uint64_t *__restrict__ akey,
                             const WaveCtl *__restrict__ ctl)
@@ -498,32 +517,29 @@ __global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__
     const int64_t g = g0 + p;
     const int32_t q = qid[g];
     const int32_t qpos = (int32_t)(g - qoff[q]);
-    pbase[p] = list_off[kcode[g]];
+    pbase[p] = lhead[g];
     const int sh_d = lay.bp, sh_q = lay.bp + lay.bd + lay.bs;
     const uint64_t qpart = sh_q >= 64 ? 0ull : ((uint64_t)(uint32_t)(q - qa) << sh_q);
     akey[p] = qpart + ((uint64_t)(uint32_t)(lay.bias - qpos) << sh_d) + (uint64_t)(uint32_t)qpos;
 }
 
-void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
-                      const int32_t *qid, const uint32_t *list_off, int32_t qa, int64_t g0,
-                      int64_t g1, HitKeyLayout lay, uint32_t *hrel, uint32_t *pbase, uint64_t *akey,
-                      hipStream_t st)
+void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
+                      const int32_t *qid, int32_t qa, int64_t g0, int64_t g1, HitKeyLayout lay,
+                      uint32_t *hrel, uint32_t *pbase, uint64_t *akey, hipStream_t st)
 {
     const int64_t np = g1 - g0;
     const int64_t nb = (np + 1 + kBlock - 1) / kBlock;
-    k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, kcode, qid, list_off, qa,
-                                                             g0, np, lay, hrel, pbase, akey,
-                                                             nullptr);
+    k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, lhead, qid, qa, g0, np,
+                                                             lay, hrel, pbase, akey, nullptr);
 }
 
-void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *kcode,
-                          const int32_t *qid, const uint32_t *list_off, int64_t np_cap,
-                          uint32_t *hrel, uint32_t *pbase, uint64_t *akey, const WaveCtl *ctl,
-                          hipStream_t st)
+void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
+                          const int32_t *qid, int64_t np_cap, uint32_t *hrel, uint32_t *pbase,
+                          uint64_t *akey, const WaveCtl *ctl, hipStream_t st)
 {
     const int64_t nb = (np_cap + 1 + kBlock - 1) / kBlock;
-    k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, kcode, qid, list_off, 0, 0,
-                                                             0, HitKeyLayout{}, hrel, pbase, akey,
+    k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, lhead, qid, 0, 0, 0,
+                                                             HitKeyLayout{}, hrel, pbase, akey,
                                                              ctl);
 }
 

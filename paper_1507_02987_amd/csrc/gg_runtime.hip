@@ -100,7 +100,7 @@ struct StageTime {
 struct Workspace {
     int device = 0;
     hipStream_t st = nullptr;
-    DevBuf ascii, qoff, qcode, kcode, cnt, qid, hoff, partials, qtot, err;
+    DevBuf ascii, qoff, qcode, kcode, cnt, lhead, qid, hoff, partials, qtot, err;
     DevBuf hrel, pbase, akey, keys, keys_alt, hist, rs_partials;
     DevBuf cands, ccount, cand_q, cand_off, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
@@ -127,7 +127,7 @@ struct Workspace {
     {
         if (st) (void)hipSetDevice(device);
         if (gexec) (void)hipGraphExecDestroy(gexec);
-        DevBuf *all[] = {&ascii, &qoff, &qcode, &kcode, &cnt, &qid, &hoff, &partials, &qtot, &err,
+        DevBuf *all[] = {&ascii, &qoff, &qcode, &kcode, &cnt, &lhead, &qid, &hoff, &partials, &qtot, &err,
                          &hrel, &pbase, &akey, &keys, &keys_alt, &hist, &rs_partials, &cands,
                          &ccount, &cand_q, &cand_off, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
                          &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
@@ -474,10 +474,9 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         launch_scan_u32(as<uint32_t>(ws->pcnt), as<uint32_t>(ws->hrel), np,
                         as<uint32_t>(ws->partials), st);
     } else {
-        launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
-                         as<int32_t>(ws->qid), ix->d_list_off, qa, g0, g1, lay,
-                         as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
-                         st);
+        launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->lhead),
+                         as<int32_t>(ws->qid), qa, g0, g1, lay, as<uint32_t>(ws->hrel),
+                         as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), st);
     }
     prof.end(np);
 
@@ -1245,8 +1244,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         launch_wave_begin(as<WaveCtl>(ws->gplan), cursor, ctl, st);
-        launch_wave_prep_ctl(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->kcode),
-                             as<int32_t>(ws->qid), ix->d_list_off, np_cap, as<uint32_t>(ws->hrel),
+        launch_wave_prep_ctl(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->lhead),
+                             as<int32_t>(ws->qid), np_cap, as<uint32_t>(ws->hrel),
                              as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), ctl, st);
         launch_gather_ctl(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
                           ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl, st);
@@ -1373,6 +1372,7 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     TRY(ensure(ws->qcode, T));
     TRY(ensure(ws->kcode, sizeof(uint32_t) * T));
     TRY(ensure(ws->cnt, sizeof(uint32_t) * T));
+    TRY(ensure(ws->lhead, sizeof(uint32_t) * T));
     TRY(ensure(ws->qid, sizeof(int32_t) * T));
     TRY(ensure(ws->hoff, sizeof(uint64_t) * (T + 1)));
     TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(T, nq + 1))));
@@ -1388,7 +1388,8 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     prof.begin("encode");
     launch_encode_kmers(ascii, as<int64_t>(ws->qoff), (int32_t)nq, T, ix->span, ix->mask,
                         ix->d_list_off, as<uint8_t>(ws->qcode), as<uint32_t>(ws->kcode),
-                        as<uint32_t>(ws->cnt), as<int32_t>(ws->qid), as<int32_t>(ws->err), st);
+                        as<uint32_t>(ws->cnt), as<uint32_t>(ws->lhead), as<int32_t>(ws->qid),
+                        as<int32_t>(ws->err), st);
     prof.end(T);
     prof.begin("scan");
     launch_scan_u32_to_u64(as<uint32_t>(ws->cnt), as<uint64_t>(ws->hoff), T,
