@@ -1576,6 +1576,24 @@ void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st)
     k_fill_u32<<<(uint32_t)nb, kBlock, 0, st>>>(p, n, v);
 }
 
+// Two arrays set to v in one launch (a graph node less than two fills).
+__global__ void k_fill2_u32(uint32_t *__restrict__ a, size_t na, uint32_t *__restrict__ b,
+                            size_t nb, uint32_t v)
+{
+    const size_t step = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += step) {
+        if (i < na) a[i] = v;
+        else b[i - na] = v;
+    }
+}
+
+void launch_fill2_u32(uint32_t *a, size_t na, uint32_t *b, size_t nb, uint32_t v, hipStream_t st)
+{
+    if (na + nb == 0) return;
+    const size_t blocks = std::min<size_t>((na + nb + kBlock - 1) / kBlock, 4096);
+    k_fill2_u32<<<(uint32_t)blocks, kBlock, 0, st>>>(a, na, b, nb, v);
+}
+
 // Scratch of a one-sweep sort of n keys: digit counts (8 passes x 256), tile
 // counters and the failure flag, then the descriptors.
 constexpr size_t kOsHead = (8 * kRadix + 64) * sizeof(uint32_t);

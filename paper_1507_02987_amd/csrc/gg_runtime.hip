@@ -1259,8 +1259,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_chain_ctl(sorted, hits_cap, ix->span, p->max_gap, p->min_hsp_len,
                          as<uint32_t>(ws->ccount), as<uint32_t>(ws->partials), as<Cand>(ws->cands),
                          ctl, st);
-        launch_fill_u32(as<uint32_t>(ws->qstart), nq_cap, 0u, st);
-        launch_fill_u32(as<uint32_t>(ws->qend), nq_cap, 0u, st);
+        launch_fill2_u32(as<uint32_t>(ws->qstart), nq_cap, as<uint32_t>(ws->qend), nq_cap, 0u, st);
         launch_cand_segments_ctl(as<Cand>(ws->cands), as<uint32_t>(ws->qstart),
                                  as<uint32_t>(ws->qend), ctl, st);
         launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nq_cap, 0,
@@ -1275,8 +1274,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_merge_sweep(as<Box>(ws->boxes2), 0, as<Box>(ws->boxes3), st, ctl);
         launch_seg_sort_box(1, as<Box>(ws->boxes3), as<Box>(ws->boxes2),
                             as<uint32_t>(ws->cand_off), nq_cap, st, ctl);
-        launch_fill_u32(as<uint32_t>(ws->qstart), nq_cap, 0u, st);
-        launch_fill_u32(as<uint32_t>(ws->qend), nq_cap, 0u, st);
+        launch_fill2_u32(as<uint32_t>(ws->qstart), nq_cap, as<uint32_t>(ws->qend), nq_cap, 0u, st);
         launch_segments_box(as<Box>(ws->boxes2), 0, 0, as<uint32_t>(ws->qstart),
                             as<uint32_t>(ws->qend), st, ctl);
         launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nq_cap, N,
@@ -1312,8 +1310,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     if (!tiles.empty())
         HIPCHK(hipMemcpyAsync(ws->gtiles.p, tiles.data(), sizeof(SortTile) * tiles.size(),
                               hipMemcpyHostToDevice, st));
-    launch_fill_u32(cursor, 1, 0u, st);
-    launch_fill_u32(as<uint32_t>(ws->gn), (size_t)nq, 0u, st);
+    launch_fill2_u32(cursor, 1, as<uint32_t>(ws->gn), (size_t)nq, 0u, st);
     prof.begin("graph");
     for (size_t w = 0; w < W; ++w) HIPCHK(hipGraphLaunch(ws->gexec, st));
     prof.end((int64_t)W);
