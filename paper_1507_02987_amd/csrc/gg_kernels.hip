@@ -2605,12 +2605,16 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
                                           int32_t &bcell, int32_t &bstart)
 {
     const int32_t tX = 2 * lane, tY = tX + 1;
-    const bool laneX = tX <= 2 * W, laneY = tY <= 2 * W, topX = tX == 2 * W;
+    const bool laneX = tX <= 2 * W, laneY = tY <= 2 * W;
     int32_t i = (a0 - (tX - W + c0)) >> 1;
     int32_t j = a0 - i;
     int32_t hereX = i * 128 + tX;
-    int32_t HX = kNegInf, EX = kNegInf, FX = kNegInf, SX = 0, SEX = 0, SFX = 0;
-    int32_t HY = kNegInf, EY = kNegInf, FY = kNegInf, SY = 0, SEY = 0, SFY = 0;
+    // the pair before the first, (i - 1, j - 1) and (i - 1, j), by the rule below: no
+    // in-box cell of the band lies on its anti-diagonals, so it is border or -inf
+    int32_t HX = (i < 1 || j < 1) ? 0 : kNegInf, EX = kNegInf, FX = kNegInf, SX = 0, SEX = 0,
+            SFX = 0;
+    int32_t HY = (i < 1 || j < 0) ? 0 : kNegInf, EY = kNegInf, FY = kNegInf, SY = 0, SEY = 0,
+            SFY = 0;
     auto bases = [&](int32_t ii, int32_t jj, int32_t &qb, int32_t &dX, int32_t &dY) {
         const int32_t ic = min(max(ii, 0), R - 1);
         const int32_t jc = min(max(jj, 0), C - 1), jc1 = min(max(jj + 1, 0), C - 1);
@@ -2626,48 +2630,49 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
     };
     int32_t nqb, ndX, ndY;  // bases of the next pair, read one pair ahead
     bases(i, j, nqb, ndX, ndY);
+    // Every cell a lane computes follows one rule: a cell before the box (row or
+    // column < 0) is the border (H = 0, E = F = -inf), a slot outside the band is
+    // -inf, any other cell takes the recurrence.  In-box cells read only cells at or
+    // before them, so this gives them exactly the box's borders and band; cells past
+    // the box are never read and only kept out of the best cell.  The one neighbour
+    // no lane holds, left of slot 0, is the border in column 0 and -inf elsewhere.
     for (int32_t a = a0; a <= a1; a += 2, ++i, ++j, hereX += 128) {
         const int32_t qb = nqb, dX = ndX, dY = ndY;
         bases(i + 1, j + 1, nqb, ndX, ndY);
-        const bool rowok = (uint32_t)i < (uint32_t)R;
-        {  // X = (i, j)
+        const bool before_row = i < 0;
+        const bool rowin = (uint32_t)i < (uint32_t)R;
+        {  // X = (i, j): left = the lower lane's previous Y, up = this lane's previous Y
             int32_t hl = from_lower_lane(HY), el = from_lower_lane(EY);
             const int32_t sl = from_lower_lane(SY), sel = from_lower_lane(SEY);
-            int32_t hu = HY, fu = FY;
-            if (j == 0) { hl = 0; el = kNegInf; }
-            else if (lane == 0) { hl = kNegInf; el = kNegInf; }
-            if (i == 0) { hu = 0; fu = kNegInf; }
-            else if (topX) { hu = kNegInf; fu = kNegInf; }
-            const int32_t hd = (i == 0 || j == 0) ? 0 : HX;
-            const CellOut c = sw_cell(hl, el, sl, sel, hu, fu, SY, SFY, hd, SX, qb == dX, hereX, match,
-                                      mismatch, o1, ext);
-            const bool v = laneX && rowok && (uint32_t)j < (uint32_t)C;
-            HX = v ? c.H : kNegInf;
-            EX = v ? c.E : kNegInf;
-            FX = v ? c.F : kNegInf;
+            if (lane == 0) {
+                hl = j == 0 ? 0 : kNegInf;
+                el = kNegInf;
+            }
+            const CellOut c = sw_cell(hl, el, sl, sel, HY, FY, SY, SFY, HX, SX, qb == dX, hereX,
+                                      match, mismatch, o1, ext);
+            const bool border = before_row || j < 0;
+            HX = border ? 0 : (laneX ? c.H : kNegInf);
+            EX = (border || !laneX) ? kNegInf : c.E;
+            FX = (border || !laneX) ? kNegInf : c.F;
             SX = c.S; SEX = c.SE; SFX = c.SF;
-            if (v && c.H > best) {
+            if (laneX && rowin && (uint32_t)j < (uint32_t)C && c.H > best) {
                 best = c.H;
                 bcell = hereX;
                 bstart = c.S;
             }
         }
-        {  // Y = (i, j + 1)
+        {  // Y = (i, j + 1): left = this lane's X, up = the upper lane's X
             const int32_t jy = j + 1;
-            int32_t hl = HX, el = EX;
-            int32_t hu = from_upper_lane(HX), fu = from_upper_lane(FX);
+            const int32_t hu = from_upper_lane(HX), fu = from_upper_lane(FX);
             const int32_t su = from_upper_lane(SX), sfu = from_upper_lane(SFX);
-            if (jy == 0) { hl = 0; el = kNegInf; }
-            if (i == 0) { hu = 0; fu = kNegInf; }
-            const int32_t hd = (i == 0 || jy == 0) ? 0 : HY;
-            const CellOut c = sw_cell(hl, el, SX, SEX, hu, fu, su, sfu, hd, SY, qb == dY, hereX + 1,
+            const CellOut c = sw_cell(HX, EX, SX, SEX, hu, fu, su, sfu, HY, SY, qb == dY, hereX + 1,
                                       match, mismatch, o1, ext);
-            const bool v = laneY && rowok && (uint32_t)jy < (uint32_t)C;
-            HY = v ? c.H : kNegInf;
-            EY = v ? c.E : kNegInf;
-            FY = v ? c.F : kNegInf;
+            const bool border = before_row || jy < 0;
+            HY = border ? 0 : (laneY ? c.H : kNegInf);
+            EY = (border || !laneY) ? kNegInf : c.E;
+            FY = (border || !laneY) ? kNegInf : c.F;
             SY = c.S; SEY = c.SE; SFY = c.SF;
-            if (v && c.H > best) {
+            if (laneY && rowin && (uint32_t)jy < (uint32_t)C && c.H > best) {
                 best = c.H;
                 bcell = hereX + 1;
                 bstart = c.S;
