@@ -24,6 +24,7 @@ constexpr uint32_t kBucketCapMax = 512;  // most keys of one bucket (one wave so
 constexpr uint32_t kBucketBig = 16384;   // most keys of one bucket sorted by a block (128 KiB)
 constexpr int kMaxProbe = 4;             // neighbour windows probed per side (G / k + 1)
 constexpr int kBoundCap = 2048;          // run bounds of one query paired in LDS
+constexpr int kLenBins = 1024;           // box-length bins of the selection prefilter
 // Blocks of a grid-stride launch: a dispatch counts its work-items in 32 bits, so
 // kernels with a wave or block per record loop over records beyond this grid.
 constexpr uint32_t kMaxGrid = 1u << 20;
@@ -142,6 +143,15 @@ void launch_traceback(const int32_t *hits, int32_t n, const uint8_t *qascii, int
                       int32_t mismatch, int32_t gap_open, int32_t gap_extend, int32_t band,
                       const int64_t *dir_off, uint8_t *dirs, const int64_t *ops_off, char *ops,
                       int32_t *ops_len, int32_t *status, hipStream_t st);
+// Selection prefilter over n boxes in query order: per-query length histograms
+// (hist: nq * kLenBins, cleared here), the threshold bin thr[q] and box count
+// nvalid[q], and per-tile kept counts scanned in place (kept total at
+// tile_counts[tiles]); then the kept boxes, in order, to out.
+void launch_len_prefilter(const Box *b, uint32_t n, int32_t nq, int32_t N, int shift,
+                          uint32_t *hist, uint32_t *thr, uint32_t *nvalid, uint32_t *tile_counts,
+                          uint32_t *partials, hipStream_t st);
+void launch_len_compact(const Box *b, uint32_t n, int shift, const uint32_t *thr,
+                        const uint32_t *tile_off, Box *out, hipStream_t st);
 // Both strands: dst holds each sequence's reverse complement at the sequence's own
 // start (start: n_seqs + 1 forward starts).
 void launch_reverse_strand(const uint8_t *src, const int64_t *start, int32_t n_seqs, uint8_t *dst,

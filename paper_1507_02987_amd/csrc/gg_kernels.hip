@@ -2475,6 +2475,160 @@ __global__ void k_segments_box(const Box *__restrict__ s, uint32_t n, int32_t nq
     }
 }
 
+// ------------------------------------------------------------------ S8 prefilter
+// Selecting the N longest boxes of a query needs only the boxes at least as long
+// as its N-th longest.  A histogram of each query's box lengths (bins of 2^shift,
+// kLenBins of them) gives the highest bin whose boxes and the longer ones number
+// at least N; every box in or above that bin is kept (a superset of the N longest,
+// ties included) and the full order is applied to those alone.  Boxes are in
+// query order; empty slots (q < 0) are dropped.
+__device__ __forceinline__ uint32_t len_bin(const Box &b, int shift)
+{
+    return min((uint32_t)min(b.qe - b.qs, b.de - b.ds) >> shift, (uint32_t)(kLenBins - 1));
+}
+
+// Tile of kTile boxes: counts into hist[q * kLenBins + bin]; a tile whose boxes
+// all belong to one query adds its LDS counts (one global atomic per bin in use),
+// a mixed tile counts every box in global memory.
+__global__ __launch_bounds__(kBlock) void k_len_hist(const Box *__restrict__ b, uint32_t n,
+                                                     int shift, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[kLenBins];
+    __shared__ int32_t s_lo, s_hi;
+    const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    if (threadIdx.x == 0) {
+        s_lo = INT32_MAX;
+        s_hi = -1;
+    }
+    for (int i = threadIdx.x; i < kLenBins; i += kBlock) h[i] = 0;
+    __syncthreads();
+    int32_t qv[kItems];
+    uint32_t bin[kItems];
+    int32_t lo = INT32_MAX, hi = -1;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = base + r * kBlock + threadIdx.x;
+        qv[r] = -1;
+        bin[r] = 0;
+        if (i < n) {
+            const Box x = b[i];
+            qv[r] = x.q;
+            if (x.q >= 0) {
+                bin[r] = len_bin(x, shift);
+                lo = min(lo, x.q);
+                hi = max(hi, x.q);
+            }
+        }
+    }
+    if (hi >= 0) {
+        atomicMin(&s_lo, lo);
+        atomicMax(&s_hi, hi);
+    }
+    __syncthreads();
+    const bool one = s_lo == s_hi;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (qv[r] < 0) continue;
+        if (one) atomicAdd(&h[bin[r]], 1u);
+        else atomicAdd(&hist[(size_t)qv[r] * kLenBins + bin[r]], 1u);
+    }
+    __syncthreads();
+    if (one)
+        for (int i = threadIdx.x; i < kLenBins; i += kBlock)
+            if (h[i]) atomicAdd(&hist[(size_t)s_lo * kLenBins + i], h[i]);
+}
+
+// One block per query: its box count (all bins) and the highest bin whose boxes
+// and the longer ones number at least N (bin 0 when the query has fewer).
+__global__ __launch_bounds__(kBlock) void k_len_threshold(const uint32_t *__restrict__ hist,
+                                                          int32_t nq, int32_t N,
+                                                          uint32_t *__restrict__ thr,
+                                                          uint32_t *__restrict__ nvalid)
+{
+    constexpr int kPer = kLenBins / kBlock;  // bins per thread, highest bins to thread 0
+    for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const uint32_t *h = hist + (size_t)q * kLenBins;
+        uint32_t c[kPer], sum = 0;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {  // thread t holds bins from the top: t * kPer + r
+            c[r] = h[kLenBins - 1 - (threadIdx.x * kPer + r)];
+            sum += c[r];
+        }
+        uint32_t tot;
+        uint32_t above = block_excl_scan<uint32_t>(sum, &tot);  // boxes in higher bins
+        uint32_t best = 0;  // a thread that crosses N names the bin; crossing is unique
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const uint32_t before = above;
+            above += c[r];
+            if (before < (uint32_t)N && above >= (uint32_t)N)
+                best = (uint32_t)(kLenBins - 1 - (threadIdx.x * kPer + r)) + 1;  // bin + 1
+        }
+        uint32_t pick;
+        block_excl_scan<uint32_t>(best, &pick);  // sum: at most one thread is non-zero
+        if (threadIdx.x == 0) {
+            thr[q] = pick ? pick - 1 : 0u;
+            nvalid[q] = tot;
+        }
+    }
+}
+
+// Stable compaction of the kept boxes, in two passes over tiles (count; write at
+// the scanned tile offsets), so the kept boxes stay in query order.
+__global__ __launch_bounds__(kBlock) void k_len_keep(const Box *__restrict__ b, uint32_t n,
+                                                     int shift, const uint32_t *__restrict__ thr,
+                                                     const uint32_t *__restrict__ tile_off,
+                                                     uint32_t *__restrict__ counts,
+                                                     Box *__restrict__ out)
+{
+    const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    uint32_t at = tile_off ? tile_off[blockIdx.x] : 0u, c = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = base + r * kBlock + threadIdx.x;
+        Box x{};
+        bool keep = false;
+        if (i < n) {
+            x = b[i];
+            keep = x.q >= 0 && len_bin(x, shift) >= thr[x.q];
+        }
+        if (tile_off) {
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<uint32_t>(keep ? 1u : 0u, &tot);
+            if (keep) out[at + ex] = x;
+            at += tot;
+        } else {
+            c += keep ? 1u : 0u;
+        }
+    }
+    if (!tile_off) {
+        uint32_t tot;
+        block_excl_scan<uint32_t>(c, &tot);
+        if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+    }
+}
+
+void launch_len_prefilter(const Box *b, uint32_t n, int32_t nq, int32_t N, int shift,
+                          uint32_t *hist, uint32_t *thr, uint32_t *nvalid, uint32_t *tile_counts,
+                          uint32_t *partials, hipStream_t st)
+{
+    if (n == 0 || nq <= 0) return;
+    const uint32_t tiles = (n + kTile - 1) / kTile;
+    launch_fill_u32(hist, (size_t)nq * kLenBins, 0u, st);
+    k_len_hist<<<tiles, kBlock, 0, st>>>(b, n, shift, hist);
+    k_len_threshold<<<std::min<uint32_t>((uint32_t)nq, kMaxGrid), kBlock, 0, st>>>(hist, nq, N, thr,
+                                                                                   nvalid);
+    k_len_keep<<<tiles, kBlock, 0, st>>>(b, n, shift, thr, nullptr, tile_counts, nullptr);
+    launch_scan_u32(tile_counts, tile_counts, tiles, partials, st);  // kept total at [tiles]
+}
+
+void launch_len_compact(const Box *b, uint32_t n, int shift, const uint32_t *thr,
+                        const uint32_t *tile_off, Box *out, hipStream_t st)
+{
+    if (n == 0) return;
+    k_len_keep<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(b, n, shift, thr, tile_off, nullptr, out);
+}
+
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
                          uint32_t *qend, hipStream_t st, const WaveCtl *ctl)
 {

@@ -108,6 +108,7 @@ struct Workspace {
         btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue, gout, gn,
         gctl, gplan, gcursor, goflags, stiles, gtiles;
     DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
+    DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
     // the captured wave graph and what it was captured for (every argument baked
@@ -135,7 +136,8 @@ struct Workspace {
                          &bound_q, &bound_off, &btmp_b, &bounds, &blist, &pcnt, &cells_box,
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
-                         &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status};
+                         &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
+                         &lvalid, &ltile};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -822,18 +824,42 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     // ---- S8 select by length: (kept first, len desc, s, qs, ds, qe, de), first N per query
     prof.begin("select");
     Box *merged = as<Box>(ws->boxes3);
+    uint32_t nbox = nc;                // boxes in the selection order
+    std::vector<uint32_t> nvalid_h;    // merged boxes per query, when prefiltered
     if (seg_path) {
         launch_seg_sort_box(1, merged, as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nqw, st);
     } else {
+        if (p->max_hits > 0) {
+            // only boxes at least as long as a query's N-th longest can be selected
+            const int shift = std::max(0, bits_for((uint64_t)maxL + 1) - 10);
+            const uint32_t tiles = (nc + kTile - 1) / kTile;
+            TRY(ensure(ws->lhist, sizeof(uint32_t) * (size_t)nqw * kLenBins));
+            TRY(ensure(ws->lthr, sizeof(uint32_t) * nqw));
+            TRY(ensure(ws->lvalid, sizeof(uint32_t) * nqw));
+            TRY(ensure(ws->ltile, sizeof(uint32_t) * (tiles + 1)));
+            TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(tiles + 1)));
+            launch_len_prefilter(merged, nc, nqw, p->max_hits, shift, as<uint32_t>(ws->lhist),
+                                 as<uint32_t>(ws->lthr), as<uint32_t>(ws->lvalid),
+                                 as<uint32_t>(ws->ltile), as<uint32_t>(ws->partials), st);
+            launch_len_compact(merged, nc, shift, as<uint32_t>(ws->lthr), as<uint32_t>(ws->ltile),
+                               as<Box>(ws->boxes), st);
+            nvalid_h.resize((size_t)nqw);
+            HIPCHK(hipMemcpyAsync(&nbox, as<uint32_t>(ws->ltile) + tiles, sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(nvalid_h.data(), ws->lvalid.p, sizeof(uint32_t) * nqw,
+                                  hipMemcpyDeviceToHost, st));
+            SYNC(st);
+            merged = as<Box>(ws->boxes);
+        }
         TRY(make_words({{F_Q, bq, 0}, {F_LEN_DESC, bl, (int32_t)maxL}, {F_S, bs, 0},
                         {F_QS, bl, 0}, {F_DS, bsl, 0}, {F_QE, bl, 0}, {F_DE, bsl, 0}},
                        words));
-        TRY(sort_records(ws, nc, words,
+        TRY(sort_records(ws, nbox, words,
                          [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
-                             launch_box_keys(merged, nc, w, nqw, out, pm, st);
+                             launch_box_keys(merged, nbox, w, nqw, out, pm, st);
                          },
                          &perm));
-        launch_gather_boxes(merged, perm, nc, as<Box>(ws->boxes2), st);
+        launch_gather_boxes(merged, perm, nbox, as<Box>(ws->boxes2), st);
     }
     TRY(ensure(ws->qstart, sizeof(uint32_t) * (nqw + 1)));
     TRY(ensure(ws->qend, sizeof(uint32_t) * (nqw + 1)));
@@ -841,7 +867,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     TRY(ensure(ws->sel_off, sizeof(uint32_t) * (nqw + 1)));
     HIPCHK(hipMemsetAsync(ws->qstart.p, 0, sizeof(uint32_t) * nqw, st));
     HIPCHK(hipMemsetAsync(ws->qend.p, 0, sizeof(uint32_t) * nqw, st));
-    launch_segments_box(as<Box>(ws->boxes2), nc, nqw, as<uint32_t>(ws->qstart),
+    launch_segments_box(as<Box>(ws->boxes2), nbox, nqw, as<uint32_t>(ws->qstart),
                         as<uint32_t>(ws->qend), st);
     launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nqw, p->max_hits,
                          as<uint32_t>(ws->nsel), st);
@@ -855,13 +881,16 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     }
     SYNC(st);
     const uint32_t nsel = h_sel_off[nqw];
+    auto merged_of = [&](int32_t ql) -> int64_t {
+        return nvalid_h.empty() ? (int64_t)(h_se[ql] - h_ss[ql]) : (int64_t)nvalid_h[(size_t)ql];
+    };
     if (piece) {
         piece->n_cands = h_cq[0];
-        piece->n_merged = h_se[0] - h_ss[0];
+        piece->n_merged = merged_of(0);
     } else if (bo.stats) {
         for (int32_t ql = 0; ql < nqw; ++ql) {
             bo.stats[qa + ql].n_cands = h_cq[ql];
-            bo.stats[qa + ql].n_merged = h_se[ql] - h_ss[ql];
+            bo.stats[qa + ql].n_merged = merged_of(ql);
         }
     }
     if (nsel == 0) return GG_OK;
