@@ -2426,19 +2426,33 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
     }
     Box cur = first;
     uint32_t w = i, j = i + 1;
-    for (; j < n; ++j) {
-        const Box h = s[j];
-        if (h.q != first.q || h.s != first.s) break;
-        if (h.qs < cur.qe && h.ds < cur.de && cur.ds < h.de) {
-            cur.qs = min(cur.qs, h.qs);
-            cur.qe = max(cur.qe, h.qe);
-            cur.ds = min(cur.ds, h.ds);
-            cur.de = max(cur.de, h.de);
-            cur.dmin = min(cur.dmin, h.dmin);
-            cur.dmax = max(cur.dmax, h.dmax);
-        } else {
-            out[w++] = cur;
-            cur = h;
+    bool open = true;
+    while (open && j < n) {
+        // four boxes loaded together, so a long group's walk waits on one load in four
+        constexpr uint32_t kAhead = 4;
+        Box h[kAhead];
+#pragma unroll
+        for (uint32_t x = 0; x < kAhead; ++x)
+            if (j + x < n) h[x] = s[j + x];
+#pragma unroll
+        for (uint32_t x = 0; x < kAhead; ++x) {
+            if (!open || j >= n) break;
+            if (h[x].q != first.q || h[x].s != first.s) {
+                open = false;
+                break;
+            }
+            if (h[x].qs < cur.qe && h[x].ds < cur.de && cur.ds < h[x].de) {
+                cur.qs = min(cur.qs, h[x].qs);
+                cur.qe = max(cur.qe, h[x].qe);
+                cur.ds = min(cur.ds, h[x].ds);
+                cur.de = max(cur.de, h[x].de);
+                cur.dmin = min(cur.dmin, h[x].dmin);
+                cur.dmax = max(cur.dmax, h[x].dmax);
+            } else {
+                out[w++] = cur;
+                cur = h[x];
+            }
+            ++j;
         }
     }
     out[w++] = cur;

@@ -339,3 +339,28 @@ def test_graph_replayed_batches(ggo, monkeypatch, k, band, max_hits, seed):
     gix.profile(False)
     if k == 4:
         assert max(s["n_cands"] for s in wst) > 1024
+
+
+def test_long_merge_groups(ggo):
+    """A tandem repeat gives one (query, sequence) pair thousands of runs, more than
+    one thread merges alone; the long groups are merged by whole waves and must
+    equal the oracle, with the selection prefilter active (N > 0) and not (N = 0)."""
+    G = gpu()
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([150702987, 90])))
+    unit = rng.choice(list(b"ACGT"), 7).astype(np.uint8)
+    rep = np.resize(unit, 20_000)
+    flank = rng.choice(list(b"ACGT"), 3_000).astype(np.uint8)
+    other = rng.choice(list(b"ACGT"), 5_000).astype(np.uint8)
+    seqs = np.concatenate([flank, rep, flank[::-1], other])
+    off = np.array([0, len(flank) + len(rep) + len(flank), len(seqs)], np.int64)
+    parts = [np.resize(np.roll(unit, 3), 2_000), np.concatenate([flank[500:1500], rep[:900]]),
+             other[1_000:3_000]]
+    qoff = np.zeros(len(parts) + 1, np.int64)
+    np.cumsum([len(p) for p in parts], out=qoff[1:])
+    qs = synth.QuerySet(np.concatenate(parts), qoff, np.zeros(len(parts), np.int8),
+                        np.full(len(parts), -1), np.zeros(len(parts)), np.zeros(len(parts)))
+    oix, gix = ggo.Index(seqs, off, 11), G.Index(seqs, off, 11)
+    for n in (20, 0):
+        want, wst = oracle_all(ggo, oix, qs, ggo.params(n))
+        assert max(s["n_cands"] for s in wst) > 2_000
+        check_batch(G, gix, qs, G.params(n), want, wst)
