@@ -292,9 +292,9 @@ def main() -> int:
         rc, stats = gix.search_batch_device(dq, qs.off, prm, dout, dn, CAP, stats=True)
         assert rc in (gg.GG_OK, gg.GG_ETRUNC)
     stages = {s: gix.profile_read(s) for s in (
-        "encode", "scan", "gather_prep", "probe", "gather_count", "gather", "group", "sort_hist",
-        "sort_scan", "sort_scatter", "chain", "chain_write", "extend", "merge", "merge_sweep",
-        "select", "align", "report")}
+        "encode", "scan", "gather_prep", "probe", "gather_count", "gather", "group", "filter",
+        "filter_compact", "sort_hist", "sort_scan", "sort_scatter", "chain", "chain_write",
+        "extend", "merge", "merge_sweep", "select", "align", "report")}
     gix.profile(False)
     step_ms = {s: v["ms"] / nprof for s, v in stages.items()}
     cells = int(stats["n_cells"].sum())
@@ -304,17 +304,20 @@ def main() -> int:
     #            (hit offset, list head, query id, window code); neighbour-window
     #            probes are cache traffic and not counted
     #  gather  - HBM: 8 B posting read + 8 B key write per hit
+    #  filter  - HBM: 8 B key read per hit (the kept few are written back)
     #  sort_*  - HBM: 16 B per key per scatter pass, 8 B per histogram pass
     #  align   - integer ALU: ALIGN_OPS_PER_CELL int32 operations per in-band cell
     positions = int(qs.lengths().sum())
     model = {
         "probe": ("hbm", lambda st: 8 * st["units"] + 16 * positions * st["launches"]),
         "gather": ("hbm", lambda st: 16 * st["units"]),
+        "filter": ("hbm", lambda st: 8 * st["units"]),
         "sort_scatter": ("hbm", lambda st: 16 * st["units"]),
         "sort_hist": ("hbm", lambda st: 8 * st["units"]),
         "align": ("alu", lambda st: ALIGN_OPS_PER_CELL * cells * nprof),
     }
-    kernel_name = {"probe": "k_probe_chain", "gather": "k_gather", "sort_scatter": "k_rs_scatter",
+    kernel_name = {"probe": "k_probe_chain", "gather": "k_gather", "filter": "k_hit_filter",
+                   "sort_scatter": "k_rs_scatter",
                    "sort_hist": "k_rs_hist", "align": "k_bsw"}
     cand = {s: stages[s] for s in model if stages[s]["launches"]}
     dom = max(cand, key=lambda s: cand[s]["ms"])

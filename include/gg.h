@@ -316,15 +316,19 @@ gg_status gg_device_copy(void *dst, const void *src, uint64_t bytes);
  * Per-stage GPU timing of batched searches on this index, for roofline reports.
  * Enabling (on or off) clears the totals; when on, HIP events are recorded around
  * each stage on the stream it runs on.  Names: "encode", "scan", "gather_prep",
- * "gather" (the posting-gather kernel alone), "sort_hist", "sort_scan",
- * "sort_scatter" (one mark per radix pass of the hit sort), "chain" (run counts),
+ * "gather" (the posting-gather kernel alone), "filter" (the kernel dropping hits
+ * alone on their (sequence, diagonal) when M exceeds the seed span and sorting the
+ * rest of each query), "filter_compact" (the kept hits' move into one array),
+ * "sort_hist", "sort_scan", "sort_scatter" (one mark per radix pass of the hit
+ * sort, when it runs), "chain" (run counts),
  * "chain_write", "extend", "merge" (ordering for the sweep), "merge_sweep",
  * "select", "align" (the banded Smith-Waterman kernel alone), "report", and
  * "graph" (all replays of a batch's captured wave graph, whose kernels are not
  * timed one by one: units = waves).  ms is the summed GPU time between the marks,
  * launches the number of marks, units the work they covered (query bases for
- * encode and scan, positions for gather_prep, hits for gather, the sort marks and
- * the chain marks, runs for extend/merge/select, boxes for align/report).
+ * encode and scan, positions for gather_prep, hits for gather, filter and the sort
+ * marks, hits left after the filter for the chain marks, runs for
+ * extend/merge/select, boxes for align/report).
  *
  * Batched calls without statistics, with the radix-sort grouping and 1 <= max_hits
  * <= 1024, run each wave as a replay of one captured HIP graph (all waves after a

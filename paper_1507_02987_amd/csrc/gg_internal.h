@@ -241,6 +241,18 @@ void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint3
 void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                        const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
                        hipStream_t st);
+// Per-query filter of hits alone on their (s, diag) group and LDS sort of the
+// kept keys, in place (kept counts per query in kept[]; queries too large for the
+// LDS sort set *flag, or ctl->overflow for a replayed wave, whose grid covers
+// nq_cap queries).  Then the kept keys' compaction in query order into `out`
+// (koff[] = exclusive scan of kept[]; a replayed wave's ctl->H becomes the total).
+void launch_hit_filter(uint64_t *keys, const uint32_t *hrel, const int64_t *qoff, int32_t qa,
+                       int64_t g0, int32_t nqw, int bp, uint32_t *kept, uint32_t *flag,
+                       hipStream_t st, WaveCtl *ctl = nullptr, int32_t nq_cap = 0);
+void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_t *qoff,
+                        int32_t qa, int64_t g0, int32_t nqw, const uint32_t *kept, uint32_t *koff,
+                        uint32_t *partials, uint64_t *out, hipStream_t st, WaveCtl *ctl = nullptr,
+                        int32_t nq_cap = 0);
 void launch_rs_pass_ctl(const uint64_t *kin, uint64_t *kout, uint32_t ntile_cap, int pass,
                         const SortTile *tiles, uint32_t *hist, uint32_t *partials,
                         const WaveCtl *ctl, hipStream_t st);

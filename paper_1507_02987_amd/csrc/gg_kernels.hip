@@ -1721,6 +1721,216 @@ int radix_sort(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *val
     return cur;
 }
 
+// ------------------------------------------------------------------ S4: drop lone diagonals
+// A run of one hit covers [qpos, qpos + span), so when M > span (Section 2.2's
+// minimum HSP length above the seed span) only hits whose (q, s, diag) group holds
+// another hit can end up in a kept run.  At the bank's scale nearly every hit is
+// alone on its diagonal, so each query's hits are filtered before grouping: one
+// block per query counts the groups in two bit tables (seen once, seen again) in
+// LDS, indexed by a hash of (s, diag), and keeps only hits whose slot was seen
+// again.  Every member of a real group shares its slot, so no group loses a hit;
+// a lone hit whose slot it shares with another group is kept too and forms a run
+// too short to keep.  Further rounds with another hash run over what is left
+// while they still drop keys.  The kept keys, in qpos order, are then sorted by the
+// whole key in LDS (keys are distinct: a query window meets a posting once), the
+// order the stable radix sort on (s, diag) gives.  Queries whose kept hits exceed
+// the LDS sort are left in qpos order and flagged.
+constexpr int kFiltBits = 18;                          // slots per bit table: 2^18
+constexpr uint32_t kFiltWords = 1u << (kFiltBits - 5);  // 32-bit words per table
+constexpr uint32_t kFiltCap = 2 * kFiltWords * 4 / 8;  // keys the tables' LDS holds (8192)
+constexpr uint32_t kFiltSmall = 512;                   // fewer keys are sorted unfiltered
+constexpr uint32_t kFiltMax = 2u << kFiltBits;         // more keys would fill the tables
+constexpr uint32_t kFiltRounds = 6;
+
+// Slot of a (q, s, diag) group in round r: the 64-bit finalizer of SplitMix64
+// (Steele, Lea and Flood, OOPSLA 2014) over the group bits and the round.
+__device__ __forceinline__ uint32_t diag_slot(uint64_t grp, uint32_t round)
+{
+    uint64_t x = grp + 0x9E3779B97F4A7C15ull * (uint64_t)(round + 1);
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (uint32_t)(x >> (64 - kFiltBits));
+}
+
+constexpr int kFiltBlock = 1024;  // threads of a filter block
+constexpr int kFiltItems = 8;     // keys per thread and batch, kFiltBlock apart
+constexpr uint32_t kFiltBatch = kFiltBlock * kFiltItems;
+constexpr int kFiltWaves = kFiltBlock / 64;
+
+// Hits of wave query ql: [hrel[qoff[qa + ql] - g0], hrel[qoff[qa + ql + 1] - g0]).
+// A batch is kFiltItems coalesced slabs of kFiltBlock keys whose loads are all in
+// flight together; kept keys are placed in input order by ballots per slab and
+// wave and one scan of those counts per batch.
+__global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict__ keys,
+                                                           const uint32_t *__restrict__ hrel,
+                                                           const int64_t *__restrict__ qoff,
+                                                           int32_t qa, int64_t g0, int32_t nqw,
+                                                           int bp, uint32_t *__restrict__ kept,
+                                                           uint32_t *__restrict__ flag,
+                                                           WaveCtl *__restrict__ ctl)
+{
+    __shared__ uint64_t s_buf[kFiltCap];  // the two bit tables, then the kept keys
+    __shared__ uint32_t s_cnt[kFiltItems * kFiltWaves];  // kept keys per slab and wave
+    __shared__ uint32_t s_pre[kFiltItems * kFiltWaves];  // their exclusive scan
+    __shared__ uint32_t s_tot;
+    if (ctl) {
+        qa = ctl->qa;
+        g0 = ctl->g0;
+        nqw = ctl->nqw;
+        bp = ctl->lay.bp;
+    }
+    const int32_t ql = (int32_t)blockIdx.x;
+    if (ql >= nqw) {
+        if (threadIdx.x == 0) kept[ql] = 0;
+        return;
+    }
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t a = hrel[qoff[qa + ql] - g0];
+    uint32_t m = hrel[qoff[qa + ql + 1] - g0] - a;
+    uint64_t *k = keys + a;
+    uint32_t *seen = reinterpret_cast<uint32_t *>(s_buf), *again = seen + kFiltWords;
+    for (uint32_t round = 0; round < kFiltRounds && m >= kFiltSmall && m <= kFiltMax; ++round) {
+        for (uint32_t i = threadIdx.x; i < 2 * kFiltWords; i += kFiltBlock) seen[i] = 0u;
+        __syncthreads();
+        for (uint32_t base = 0; base < m; base += kFiltBatch) {
+            uint64_t v[kFiltItems];
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j) {
+                const uint32_t i = base + j * kFiltBlock + threadIdx.x;
+                v[j] = i < m ? k[i] : 0ull;
+            }
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j) {
+                if (base + j * kFiltBlock + threadIdx.x < m) {
+                    const uint32_t h = diag_slot(v[j] >> bp, round), bit = 1u << (h & 31u);
+                    if (atomicOr(&seen[h >> 5], bit) & bit) atomicOr(&again[h >> 5], bit);
+                }
+            }
+        }
+        __syncthreads();
+        // stable compaction in place: a batch is read before any of its keys move,
+        // and keys only move down
+        uint32_t out = 0;
+        for (uint32_t base = 0; base < m; base += kFiltBatch) {
+            uint64_t v[kFiltItems], mask[kFiltItems];
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j) {
+                const uint32_t i = base + j * kFiltBlock + threadIdx.x;
+                v[j] = i < m ? k[i] : 0ull;
+            }
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j) {
+                bool keep = false;
+                if (base + j * kFiltBlock + threadIdx.x < m) {
+                    const uint32_t h = diag_slot(v[j] >> bp, round);
+                    keep = (again[h >> 5] >> (h & 31u)) & 1u;
+                }
+                mask[j] = __ballot(keep);
+                if (lane == 0) s_cnt[j * kFiltWaves + w] = (uint32_t)__popcll(mask[j]);
+            }
+            __syncthreads();
+            if (w == 0) {  // slab-major, wave-minor exclusive scan of the counts
+                static_assert(kFiltItems * kFiltWaves == 128, "two counts per lane");
+                const uint32_t c0 = s_cnt[2 * lane], c1 = s_cnt[2 * lane + 1];
+                uint32_t x = c0 + c1;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(x, o, 64);
+                    if ((int)lane >= o) x += y;
+                }
+                const uint32_t ex = x - c0 - c1;
+                s_pre[2 * lane] = ex;
+                s_pre[2 * lane + 1] = ex + c0;
+                if (lane == 63) s_tot = x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j)
+                if ((mask[j] >> lane) & 1ull)
+                    k[out + s_pre[j * kFiltWaves + w] + (uint32_t)__popcll(mask[j] & below)] = v[j];
+            out += s_tot;
+        }
+        __syncthreads();
+        const uint32_t before = m;
+        m = out;
+        if ((before - m) * 8u < before) break;  // the rest are (nearly all) real groups
+    }
+    if (threadIdx.x == 0) kept[ql] = m;
+    if (m > kFiltCap) {
+        if (threadIdx.x == 0) atomicOr(ctl ? &ctl->overflow : flag, 1u);
+        return;
+    }
+    uint32_t n2 = 1;
+    while (n2 < m) n2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < n2; i += kFiltBlock) s_buf[i] = i < m ? k[i] : ~0ull;
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += kFiltBlock) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = s_buf[i], y = s_buf[l];
+                    if ((i & kk) == 0 ? y < x : x < y) {
+                        s_buf[i] = y;
+                        s_buf[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < m; i += kFiltBlock) k[i] = s_buf[i];
+}
+
+// Each query's kept keys to koff[ql] of `out`, after the scan of the kept counts;
+// a replayed wave learns its sorted count here (none when a query overflowed: the
+// wave is run again by the host).
+__global__ __launch_bounds__(kBlock) void k_hit_compact(const uint64_t *__restrict__ keys,
+                                                        const uint32_t *__restrict__ hrel,
+                                                        const int64_t *__restrict__ qoff,
+                                                        int32_t qa, int64_t g0, int32_t nqw,
+                                                        const uint32_t *__restrict__ kept,
+                                                        const uint32_t *__restrict__ koff,
+                                                        uint64_t *__restrict__ out,
+                                                        WaveCtl *__restrict__ ctl)
+{
+    if (ctl) {
+        qa = ctl->qa;
+        g0 = ctl->g0;
+        nqw = ctl->nqw;
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->H = ctl->overflow ? 0u : koff[nqw];
+    }
+    const int32_t ql = (int32_t)blockIdx.x;
+    if (ql >= nqw) return;
+    const uint64_t *src = keys + hrel[qoff[qa + ql] - g0];
+    uint64_t *dst = out + koff[ql];
+    const uint32_t n = kept[ql];
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
+}
+
+void launch_hit_filter(uint64_t *keys, const uint32_t *hrel, const int64_t *qoff, int32_t qa,
+                       int64_t g0, int32_t nqw, int bp, uint32_t *kept, uint32_t *flag,
+                       hipStream_t st, WaveCtl *ctl, int32_t nq_cap)
+{
+    const int32_t nb = ctl ? nq_cap : nqw;
+    if (nb > 0)
+        k_hit_filter<<<nb, kFiltBlock, 0, st>>>(keys, hrel, qoff, qa, g0, nqw, bp, kept, flag,
+                                                ctl);
+}
+
+void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_t *qoff,
+                        int32_t qa, int64_t g0, int32_t nqw, const uint32_t *kept, uint32_t *koff,
+                        uint32_t *partials, uint64_t *out, hipStream_t st, WaveCtl *ctl,
+                        int32_t nq_cap)
+{
+    const int32_t nb = ctl ? nq_cap : nqw;
+    if (nb <= 0) return;
+    launch_scan_u32(kept, koff, nb, partials, st);
+    k_hit_compact<<<nb, kBlock, 0, st>>>(keys, hrel, qoff, qa, g0, nqw, kept, koff, out, ctl);
+}
+
 // ------------------------------------------------------------------ S5: chain + filter
 // A sorted hit ends a run when the next hit is in another (q, s, diag) group or
 // more than G past this hit's window; the run's first hit is found by walking back

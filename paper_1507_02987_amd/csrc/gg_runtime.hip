@@ -109,6 +109,7 @@ struct Workspace {
         gctl, gplan, gcursor, goflags, stiles, gtiles;
     DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
     DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
+    DevBuf fkept, fkoff, fflag;         // lone-diagonal filter
     void *pinned = nullptr;  // small pinned staging for counts
     size_t pinned_cap = 0;
     // the captured wave graph and what it was captured for (every argument baked
@@ -137,7 +138,7 @@ struct Workspace {
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
-                         &lvalid, &ltile};
+                         &lvalid, &ltile, &fkept, &fkoff, &fflag};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -411,6 +412,19 @@ SortKind sort_kind_from_env()
     return (g && !strcmp(g, "onesweep")) ? kOneSweep : kClassic;
 }
 
+// Hits alone on their (s, diag) group are dropped before grouping when no run of
+// one hit can be kept (M > span) and the wave's queries average at most
+// kFiltMean hits, the load at which the per-query LDS tables still drop most lone
+// hits; GG_FILTER=0 turns the filter off.
+constexpr uint64_t kFiltMean = 1u << 17;
+
+bool filter_for(const gg_index *ix, const gg_params *p, uint64_t hits, int64_t nq)
+{
+    const char *g = getenv("GG_FILTER");
+    if (g && !strcmp(g, "0")) return false;
+    return p->min_hsp_len > ix->span && hits <= (uint64_t)std::max<int64_t>(nq, 0) * kFiltMean;
+}
+
 // GG_GROUPING (probe, bucket or sort) pins the strategy; otherwise the index's
 // tuned choice is used (sort until tuned).
 Grouping grouping_for(const gg_index *ix)
@@ -680,30 +694,61 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         }
     }
     if (grouping != kProbe && !bucketed) {
-        // ---- global path: gather in place, stable LSD radix sort, chain
+        // ---- global path: gather in place, lone-diagonal filter with per-query LDS
+        // sorts, or a stable LSD radix sort within query segments; chain
         TRY(ensure(ws->keys_alt, sizeof(uint64_t) * H));
-        // tiles within query segments: the passes skip the query bits of the keys
-        std::vector<uint64_t> qcounts((size_t)nqw);
-        for (int32_t ql = 0; ql < nqw; ++ql) qcounts[(size_t)ql] = piece ? piece->hits : qtot[qa + ql];
-        std::vector<SortTile> tiles;
-        seg_tiles(qcounts.data(), nqw, tiles);
-        const uint32_t nst = (uint32_t)tiles.size();
-        TRY(ensure(ws->stiles, sizeof(SortTile) * std::max<uint32_t>(nst, 1)));
-        if (nst)
-            HIPCHK(hipMemcpyAsync(ws->stiles.p, tiles.data(), sizeof(SortTile) * nst,
-                                  hipMemcpyHostToDevice, st));
-        const size_t nhist = std::max<size_t>(radix_hist_needed(H), (size_t)nst * kRadix + 1);
-        TRY(ensure(ws->hist, sizeof(uint32_t) * nhist));
-        TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed((int64_t)nhist)));
         const int sort_lo = lay.bp, sort_hi = lay.bp + lay.bd + lay.bs + lay.bq;
         const int seg_hi = lay.bp + lay.bd + lay.bs;
         const uint64_t *sorted = nullptr;
+        uint32_t Hs = H;  // keys left to chain
         const uint32_t ntile = chain_tiles(H);
         TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
         TRY(ensure(ws->partials,
                    sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nqw) + 1)));
         const bool lookback = sort_kind_from_env() == kOneSweep;
+        const bool filt = !lookback && !piece && filter_for(ix, p, H, nqw);
         if (lookback) TRY(ensure(ws->os_scratch, onesweep_scratch_bytes(H)));
+        if (filt) {
+            TRY(ensure(ws->fkept, sizeof(uint32_t) * (nqw + 1)));
+            TRY(ensure(ws->fkoff, sizeof(uint32_t) * (nqw + 1)));
+            TRY(ensure(ws->fflag, sizeof(uint32_t)));
+        }
+        // segmented radix passes over n keys in kin, counts[ql] keys per query in
+        // query order; returns the buffer holding the sorted keys
+        auto radix_passes = [&](uint64_t *kin, uint64_t *kout, const std::vector<uint64_t> &counts,
+                                uint32_t n) -> gg_status {
+            // tiles within query segments: the passes skip the query bits of the keys
+            std::vector<SortTile> tiles;
+            seg_tiles(counts.data(), nqw, tiles);
+            const uint32_t nst = (uint32_t)tiles.size();
+            TRY(ensure(ws->stiles, sizeof(SortTile) * std::max<uint32_t>(nst, 1)));
+            if (nst)
+                HIPCHK(hipMemcpyAsync(ws->stiles.p, tiles.data(), sizeof(SortTile) * nst,
+                                      hipMemcpyHostToDevice, st));
+            const size_t nhist = std::max<size_t>(radix_hist_needed(n), (size_t)nst * kRadix + 1);
+            TRY(ensure(ws->hist, sizeof(uint32_t) * nhist));
+            TRY(ensure(ws->rs_partials, sizeof(uint32_t) * scan_partials_needed((int64_t)nhist)));
+            sorted = kin;
+            if (n <= 1) return GG_OK;
+            for (int shift = sort_lo; shift < seg_hi; shift += kRadixBits) {
+                prof.begin("sort_hist");
+                launch_rs_hist_seg(kin, nst, shift, as<SortTile>(ws->stiles),
+                                   as<uint32_t>(ws->hist), st);
+                prof.end(n);
+                prof.begin("sort_scan");
+                launch_rs_scan_seg(as<uint32_t>(ws->hist), nst, as<uint32_t>(ws->rs_partials), st);
+                prof.end(n);
+                prof.begin("sort_scatter");
+                launch_rs_scatter_seg(kin, kout, nst, shift, as<SortTile>(ws->stiles),
+                                      as<uint32_t>(ws->hist), st);
+                prof.end(n);
+                std::swap(kin, kout);
+            }
+            sorted = kin;
+            return GG_OK;
+        };
+        std::vector<uint64_t> qcounts((size_t)nqw);
+        for (int32_t ql = 0; ql < nqw; ++ql) qcounts[(size_t)ql] = piece ? piece->hits : qtot[qa + ql];
         for (int attempt = 0; attempt < 2; ++attempt) {
             // with one-sweep passes, a look-back wait that ran out sends the wave
             // back to the gather and the per-pass histogram sort
@@ -713,7 +758,35 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                           np, ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
             prof.end(H);
             uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
-            if (H > 1 && os) {
+            if (filt) {
+                HIPCHK(hipMemsetAsync(ws->fflag.p, 0, sizeof(uint32_t), st));
+                prof.begin("filter");
+                launch_hit_filter(kcur, as<uint32_t>(ws->hrel), as<int64_t>(ws->qoff), qa, g0, nqw,
+                                  lay.bp, as<uint32_t>(ws->fkept), as<uint32_t>(ws->fflag), st);
+                prof.end(H);
+                prof.begin("filter_compact");
+                launch_hit_compact(kcur, as<uint32_t>(ws->hrel), as<int64_t>(ws->qoff), qa, g0,
+                                   nqw, as<uint32_t>(ws->fkept), as<uint32_t>(ws->fkoff),
+                                   as<uint32_t>(ws->partials), knext, st);
+                prof.end(H);
+                HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->fkoff) + nqw, sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(h_nc + 1, ws->fflag.p, sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, st));
+                SYNC(st);
+                Hs = h_nc[0];
+                sorted = knext;
+                if (h_nc[1]) {
+                    // a query kept more hits than its LDS sort holds: radix passes
+                    // over the compacted keys, each query in qpos order
+                    std::vector<uint32_t> kept((size_t)nqw);
+                    HIPCHK(hipMemcpyAsync(kept.data(), ws->fkept.p, sizeof(uint32_t) * nqw,
+                                          hipMemcpyDeviceToHost, st));
+                    SYNC(st);
+                    for (int32_t ql = 0; ql < nqw; ++ql) qcounts[(size_t)ql] = kept[(size_t)ql];
+                    TRY(radix_passes(knext, kcur, qcounts, Hs));
+                }
+            } else if (H > 1 && os) {
                 prof.begin("sort_hist");
                 onesweep_prepare(kcur, H, sort_lo, sort_hi, ws->os_scratch.p, st);
                 prof.end(H);
@@ -723,36 +796,24 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                     prof.end(H);
                     std::swap(kcur, knext);
                 }
-            } else if (H > 1) {
-                for (int shift = sort_lo; shift < seg_hi; shift += kRadixBits) {
-                    prof.begin("sort_hist");
-                    launch_rs_hist_seg(kcur, nst, shift, as<SortTile>(ws->stiles),
-                                       as<uint32_t>(ws->hist), st);
-                    prof.end(H);
-                    prof.begin("sort_scan");
-                    launch_rs_scan_seg(as<uint32_t>(ws->hist), nst, as<uint32_t>(ws->rs_partials),
-                                       st);
-                    prof.end(H);
-                    prof.begin("sort_scatter");
-                    launch_rs_scatter_seg(kcur, knext, nst, shift, as<SortTile>(ws->stiles),
-                                          as<uint32_t>(ws->hist), st);
-                    prof.end(H);
-                    std::swap(kcur, knext);
-                }
+                sorted = kcur;
+            } else {
+                TRY(radix_passes(kcur, knext, qcounts, H));
             }
-            sorted = kcur;
+            h_nc[0] = h_nc[1] = 0;
             prof.begin("chain");
-            launch_chain_count(sorted, H, lay, ix->span, p->max_gap, p->min_hsp_len,
-                               as<uint32_t>(ws->ccount), st);
-            launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount), ntile,
-                            as<uint32_t>(ws->partials), st);
-            HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + ntile, sizeof(uint32_t),
-                                  hipMemcpyDeviceToHost, st));
-            h_nc[1] = 0;
+            if (Hs > 0) {
+                launch_chain_count(sorted, Hs, lay, ix->span, p->max_gap, p->min_hsp_len,
+                                   as<uint32_t>(ws->ccount), st);
+                launch_scan_u32(as<uint32_t>(ws->ccount), as<uint32_t>(ws->ccount),
+                                chain_tiles(Hs), as<uint32_t>(ws->partials), st);
+                HIPCHK(hipMemcpyAsync(h_nc, as<uint32_t>(ws->ccount) + chain_tiles(Hs),
+                                      sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            }
             if (os && H > 1)
                 HIPCHK(hipMemcpyAsync(h_nc + 1, onesweep_fail_flag(ws->os_scratch.p),
                                       sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-            prof.end(H);
+            prof.end(Hs);
             SYNC(st);
             if (!(os && h_nc[1])) break;
         }
@@ -762,7 +823,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             TRY(ensure(ws->qstart, sizeof(uint32_t) * (nqw + 1)));
             TRY(ensure(ws->qend, sizeof(uint32_t) * (nqw + 1)));
             prof.begin("chain_write");
-            launch_chain_write(sorted, H, lay, ix->span, p->max_gap, p->min_hsp_len,
+            launch_chain_write(sorted, Hs, lay, ix->span, p->max_gap, p->min_hsp_len,
                                as<uint32_t>(ws->ccount), as<Cand>(ws->cands), st);
             HIPCHK(hipMemsetAsync(ws->qstart.p, 0, sizeof(uint32_t) * nqw, st));
             HIPCHK(hipMemsetAsync(ws->qend.p, 0, sizeof(uint32_t) * nqw, st));
@@ -1244,7 +1305,15 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
 
     WaveCtl *ctl = as<WaveCtl>(ws->gctl);
     uint32_t *cursor = as<uint32_t>(ws->gcursor);
-    const uint64_t *sorted = (passes & 1) ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys);
+    uint64_t hsum = 0;
+    for (const WaveCtl &w : plan) hsum += w.H;
+    const bool filt = filter_for(ix, p, hsum, nq);
+    if (filt) {
+        TRY(ensure(ws->fkept, sizeof(uint32_t) * (nq_cap + 1)));
+        TRY(ensure(ws->fkoff, sizeof(uint32_t) * (nq_cap + 1)));
+    }
+    const uint64_t *sorted = (filt || (passes & 1)) ? as<uint64_t>(ws->keys_alt)
+                                                    : as<uint64_t>(ws->keys);
     const int32_t steps = ix->tune_lane_steps.load();
     std::vector<uint64_t> key = {hits_cap, (uint64_t)np_cap, (uint64_t)nq_cap, (uint64_t)passes,
                                  (uint64_t)ntile_cap,
@@ -1252,7 +1321,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                                  (uint64_t)lay.bq, (uint64_t)(uint32_t)lay.bias, (uint64_t)cap,
                                  (uint64_t)(uint32_t)steps, (uint64_t)ix->span,
                                  (uint64_t)ix->mask,
-                                 (uint64_t)(uintptr_t)ix->d_post};
+                                 (uint64_t)(uintptr_t)ix->d_post, (uint64_t)filt};
     for (int32_t v : {p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, p->xdrop,
                       p->max_gap, p->min_hsp_len, p->max_hits})
         key.push_back((uint64_t)(uint32_t)v);
@@ -1262,7 +1331,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                             &ws->boxes2, &ws->boxes3, &ws->xqueue, &ws->qstart, &ws->qend,
                             &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
                             &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
-                            &ws->gplan, &ws->gcursor, &ws->goflags, &ws->gtiles})
+                            &ws->gplan, &ws->gcursor, &ws->goflags, &ws->gtiles, &ws->fkept,
+                            &ws->fkoff})
         key.push_back((uint64_t)(uintptr_t)b->p);
 
     if (!ws->gexec || ws->gkey != key) {
@@ -1278,7 +1348,16 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                              as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), ctl, st);
         launch_gather_ctl(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
                           ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl, st);
-        for (int pass = 0; pass < passes; ++pass) {
+        if (filt) {
+            launch_hit_filter(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
+                              as<int64_t>(ws->qoff), 0, 0, 0, 0, as<uint32_t>(ws->fkept), nullptr,
+                              st, ctl, nq_cap);
+            launch_hit_compact(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
+                               as<int64_t>(ws->qoff), 0, 0, 0, as<uint32_t>(ws->fkept),
+                               as<uint32_t>(ws->fkoff), as<uint32_t>(ws->partials),
+                               as<uint64_t>(ws->keys_alt), st, ctl, nq_cap);
+        }
+        for (int pass = 0; pass < passes && !filt; ++pass) {
             const bool odd = pass & 1;
             launch_rs_pass_ctl(odd ? as<uint64_t>(ws->keys_alt) : as<uint64_t>(ws->keys),
                                odd ? as<uint64_t>(ws->keys) : as<uint64_t>(ws->keys_alt), ntile_cap,
