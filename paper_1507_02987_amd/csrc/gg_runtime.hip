@@ -110,8 +110,10 @@ struct Workspace {
     DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
     DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
     DevBuf fkept, fkoff, fflag;         // lone-diagonal filter
-    void *pinned = nullptr;  // small pinned staging for counts
-    size_t pinned_cap = 0;
+    // small pinned staging: [0] a wave's counts, [1] a batch's query offsets and hit
+    // totals, [2] the replayed waves' plan, overflow flags and result counts
+    void *pinned[3] = {nullptr, nullptr, nullptr};
+    size_t pinned_cap[3] = {0, 0, 0};
     // the captured wave graph and what it was captured for (every argument baked
     // into its nodes: capacities, parameters, buffer addresses)
     hipGraphExec_t gexec = nullptr;
@@ -142,7 +144,8 @@ struct Workspace {
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
-        if (pinned) (void)hipHostFree(pinned);
+        for (void *pn : pinned)
+            if (pn) (void)hipHostFree(pn);
         if (st) (void)hipStreamDestroy(st);
     }
 };
@@ -205,17 +208,17 @@ void put_ws(const gg_index *ix, Workspace *ws)
     ix->ws_free.push_back(ws);
 }
 
-gg_status pinned(Workspace *ws, size_t bytes, void **p)
+gg_status pinned(Workspace *ws, size_t bytes, void **p, int slot = 0)
 {
-    if (bytes > ws->pinned_cap) {
-        if (ws->pinned) (void)hipHostFree(ws->pinned);
-        ws->pinned = nullptr;
-        ws->pinned_cap = 0;
+    if (bytes > ws->pinned_cap[slot]) {
+        if (ws->pinned[slot]) (void)hipHostFree(ws->pinned[slot]);
+        ws->pinned[slot] = nullptr;
+        ws->pinned_cap[slot] = 0;
         size_t want = std::max<size_t>(bytes, 1 << 16);
-        HIPCHK(hipHostMalloc(&ws->pinned, want, hipHostMallocDefault));
-        ws->pinned_cap = want;
+        HIPCHK(hipHostMalloc(&ws->pinned[slot], want, hipHostMallocDefault));
+        ws->pinned_cap[slot] = want;
     }
-    *p = ws->pinned;
+    *p = ws->pinned[slot];
     return GG_OK;
 }
 
@@ -1325,6 +1328,12 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     for (int32_t v : {p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, p->xdrop,
                       p->max_gap, p->min_hsp_len, p->max_hits})
         key.push_back((uint64_t)(uint32_t)v);
+    // device-form results go straight to the caller's buffers
+    const bool direct = bo.device && cap > 0;
+    int32_t *gout = direct ? reinterpret_cast<int32_t *>(bo.out) : as<int32_t>(ws->gout);
+    int32_t *gn = bo.device ? bo.n_out : as<int32_t>(ws->gn);
+    key.push_back((uint64_t)(uintptr_t)gout);
+    key.push_back((uint64_t)(uintptr_t)gn);
     for (const DevBuf *b : {&ws->hoff, &ws->qoff, &ws->kcode, &ws->qid, &ws->qcode, &ws->hrel,
                             &ws->pbase, &ws->akey, &ws->keys, &ws->keys_alt, &ws->hist,
                             &ws->rs_partials, &ws->ccount, &ws->partials, &ws->cands, &ws->boxes,
@@ -1395,7 +1404,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                    as<Align>(ws->aligns), nullptr, nullptr, st, ctl);
         launch_report_seg(as<Align>(ws->aligns), as<Align>(ws->aligns2), as<uint32_t>(ws->sel_off),
                           nq_cap, as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend), 0, cap,
-                          as<int32_t>(ws->gout), as<int32_t>(ws->gn), st, ctl);
+                          gout, gn, st, ctl);
         launch_wave_end(ctl, cursor, as<uint32_t>(ws->goflags), st);
         const hipError_t ec = hipStreamEndCapture(st, &g);
         if (ec != hipSuccess) {
@@ -1414,31 +1423,31 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
 
     // replay it once per wave
     const size_t W = plan.size();
-    HIPCHK(hipMemcpyAsync(ws->gplan.p, plan.data(), sizeof(WaveCtl) * W, hipMemcpyHostToDevice, st));
-    if (!tiles.empty())
+    // staging: plan [W] | overflow flags [W] | result counts [nq]
+    void *pin;
+    TRY(pinned(ws, sizeof(WaveCtl) * W + sizeof(uint32_t) * W + sizeof(int32_t) * nq + 64, &pin,
+               2));
+    WaveCtl *h_plan = static_cast<WaveCtl *>(pin);
+    uint32_t *oflags = reinterpret_cast<uint32_t *>(h_plan + W);
+    int32_t *nout = reinterpret_cast<int32_t *>(oflags + W);
+    std::copy(plan.begin(), plan.end(), h_plan);
+    HIPCHK(hipMemcpyAsync(ws->gplan.p, h_plan, sizeof(WaveCtl) * W, hipMemcpyHostToDevice, st));
+    if (!tiles.empty() && !filt)
         HIPCHK(hipMemcpyAsync(ws->gtiles.p, tiles.data(), sizeof(SortTile) * tiles.size(),
                               hipMemcpyHostToDevice, st));
-    launch_fill2_u32(cursor, 1, as<uint32_t>(ws->gn), (size_t)nq, 0u, st);
+    launch_fill2_u32(cursor, 1, reinterpret_cast<uint32_t *>(gn), (size_t)nq, 0u, st);
     prof.begin("graph");
     for (size_t w = 0; w < W; ++w) HIPCHK(hipGraphLaunch(ws->gexec, st));
     prof.end((int64_t)W);
-    std::vector<uint32_t> oflags(W);
-    std::vector<int32_t> nout((size_t)nq);
-    HIPCHK(hipMemcpyAsync(oflags.data(), ws->goflags.p, sizeof(uint32_t) * W,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(nout.data(), ws->gn.p, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
-    if (cap > 0) {
-        const size_t bytes = sizeof(gg_hit) * (size_t)nq * cap;
-        HIPCHK(hipMemcpyAsync(bo.out, ws->gout.p, bytes,
-                              bo.device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-    }
-    if (bo.device)
-        HIPCHK(hipMemcpyAsync(bo.n_out, ws->gn.p, sizeof(int32_t) * nq, hipMemcpyDeviceToDevice,
-                              st));
+    HIPCHK(hipMemcpyAsync(oflags, ws->goflags.p, sizeof(uint32_t) * W, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(nout, gn, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+    if (cap > 0 && !direct)
+        HIPCHK(hipMemcpyAsync(bo.out, ws->gout.p, sizeof(gg_hit) * (size_t)nq * cap,
+                              hipMemcpyDeviceToHost, st));
     SYNC(st);
     prof.collect();
     *used = true;
-    if (!bo.device) std::copy(nout.begin(), nout.end(), bo.n_out);
+    if (!bo.device) std::copy(nout, nout + nq, bo.n_out);
     for (int64_t q = 0; q < nq; ++q)
         if (nout[(size_t)q] > cap) bo.truncated = true;
     // waves the per-query LDS sorts could not hold run again on the regular path
@@ -1485,8 +1494,15 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     TRY(ensure(ws->err, sizeof(int32_t) * 4));
     if (T > 0 && !bo.device)
         HIPCHK(hipMemcpyAsync(ws->ascii.p, qbuf + qoff[0], T, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ws->qoff.p, qoff_h.data(), sizeof(int64_t) * (nq + 1),
-                          hipMemcpyHostToDevice, st));
+    // staging: query offsets [nq + 1] | hit totals [nq] | error flag
+    void *pin;
+    TRY(pinned(ws, sizeof(int64_t) * (2 * (size_t)nq + 2), &pin, 1));
+    int64_t *h_qoff = static_cast<int64_t *>(pin);
+    uint64_t *h_qtot = reinterpret_cast<uint64_t *>(h_qoff + nq + 1);
+    int32_t *h_err = reinterpret_cast<int32_t *>(h_qtot + nq);
+    std::copy(qoff_h.begin(), qoff_h.end(), h_qoff);
+    HIPCHK(hipMemcpyAsync(ws->qoff.p, h_qoff, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice,
+                          st));
     HIPCHK(hipMemsetAsync(ws->err.p, 0, sizeof(int32_t), st));
 
     // ---- S1 encode + S2 count and scan
@@ -1502,12 +1518,11 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     launch_query_totals(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), (int32_t)nq,
                         as<uint64_t>(ws->qtot), st);
     prof.end(T);
-    std::vector<uint64_t> qtot(nq);
-    int32_t err = 0;
-    HIPCHK(hipMemcpyAsync(qtot.data(), ws->qtot.p, sizeof(uint64_t) * nq, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&err, ws->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_qtot, ws->qtot.p, sizeof(uint64_t) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_err, ws->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SYNC(st);
-    if (err) return GG_EINVAL;
+    if (*h_err) return GG_EINVAL;
+    const std::vector<uint64_t> qtot(h_qtot, h_qtot + nq);
 
     // ---- waves: consecutive queries whose stored hit keys fit the budget and the key
     // bits (probing stores no hit: its waves are bounded only by 32-bit hit counts)
