@@ -244,11 +244,15 @@ void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64
 // Per-query filter of hits alone on their (s, diag) group and LDS sort of the
 // kept keys, in place (kept counts per query in kept[]; queries too large for the
 // LDS sort set *flag, or ctl->overflow for a replayed wave, whose grid covers
-// nq_cap queries).  Then the kept keys' compaction in query order into `out`
-// (koff[] = exclusive scan of kept[]; a replayed wave's ctl->H becomes the total).
+// nq_cap queries).  The order array, when given, names the wave-local query that
+// block r filters (largest first): order[qa + r] for a replayed wave (one array for
+// the batch), order[r] otherwise.  Then the kept keys' compaction in query order into
+// `out` (koff[] = exclusive scan of kept[]; a replayed wave's ctl->H becomes the
+// total).
 void launch_hit_filter(uint64_t *keys, const uint32_t *hrel, const int64_t *qoff, int32_t qa,
-                       int64_t g0, int32_t nqw, int bp, uint32_t *kept, uint32_t *flag,
-                       hipStream_t st, WaveCtl *ctl = nullptr, int32_t nq_cap = 0);
+                       int64_t g0, int32_t nqw, int bp, const int32_t *order, uint32_t *kept,
+                       uint32_t *flag, hipStream_t st, WaveCtl *ctl = nullptr,
+                       int32_t nq_cap = 0);
 void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_t *qoff,
                         int32_t qa, int64_t g0, int32_t nqw, const uint32_t *kept, uint32_t *koff,
                         uint32_t *partials, uint64_t *out, hipStream_t st, WaveCtl *ctl = nullptr,
@@ -266,8 +270,6 @@ void launch_rs_scatter_seg(const uint64_t *kin, uint64_t *kout, uint32_t ntile, 
 void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_t max_gap,
                       int32_t min_len, uint32_t *counts, uint32_t *partials, Cand *out,
                       WaveCtl *ctl, hipStream_t st);
-void launch_cand_segments_ctl(const Cand *c, uint32_t *qstart, uint32_t *qend, const WaveCtl *ctl,
-                              hipStream_t st);
 // The three kernels of one radix pass (digit histogram, its scan, stable scatter).
 void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st);
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st);
@@ -311,6 +313,14 @@ void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qs
                          uint32_t *qend, hipStream_t st, const WaveCtl *ctl = nullptr);
 void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
                            uint32_t *qend, hipStream_t st);
+// A replayed wave's per-query run ranges and counts (runs in query order), and its
+// per-query selected-box ranges and counts capped at N (each query's boxes in its
+// own segment, selected ones first); grids of nq_cap threads.
+void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uint32_t *qend,
+                            uint32_t *counts, const WaveCtl *ctl, hipStream_t st);
+void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
+                           uint32_t *qstart, uint32_t *qend, uint32_t *counts, const WaveCtl *ctl,
+                           hipStream_t st);
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
                           int32_t max_hits, uint32_t *nsel, hipStream_t st,
                           const WaveCtl *ctl = nullptr);

@@ -401,16 +401,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(TO *__restrict__ parti
 template <typename TI, typename TO, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in, int64_t n,
                                                       const TO *__restrict__ partials,
-                                                      TO *__restrict__ out, int64_t nb)
+                                                      TO *__restrict__ out, int64_t nb,
+                                                      TO *__restrict__ total_copy)
 {
     __shared__ TO s_v[kTile];
-    // FUSED: partials holds each tile's sum; this tile's offset is their sum below it
+    // FUSED: partials holds each earlier tile's sum; this tile's offset is their sum
+    // (a single tile reads none)
     TO pre = 0, all = 0;
     if (FUSED) {
         TO p = 0;
         for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) p += partials[b];
         block_excl_scan<TO>(p, &pre);
-        if (blockIdx.x == nb - 1) all = pre + partials[blockIdx.x];
     } else {
         pre = partials[blockIdx.x];
         all = partials[nb];
@@ -431,6 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in,
     }
     TO tot;
     TO run = block_excl_scan<TO>(s, &tot) + pre;
+    if (FUSED) all = pre + tot;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         s_v[threadIdx.x * kItems + r] = run;
@@ -442,27 +444,34 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in,
         const int64_t i = base + r * kBlock + threadIdx.x;
         if (i < n) out[i] = s_v[r * kBlock + threadIdx.x];
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = all;
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
+        out[n] = all;
+        if (total_copy) *total_copy = all;
+    }
 }
 
 size_t scan_partials_needed(int64_t n) { return (size_t)((n + kTile - 1) / kTile + 1); }
 
+// out[0..n] = exclusive scan of in[0..n) and the total; the total also goes to
+// *total_copy when given.  A single tile is one launch.
 template <typename TI, typename TO>
-static void scan_impl(const TI *in, TO *out, int64_t n, TO *partials, hipStream_t st)
+static void scan_impl(const TI *in, TO *out, int64_t n, TO *partials, hipStream_t st,
+                      TO *total_copy = nullptr)
 {
     if (n <= 0) {
         (void)hipMemsetAsync(out, 0, sizeof(TO), st);
+        if (total_copy) (void)hipMemsetAsync(total_copy, 0, sizeof(TO), st);
         return;
     }
     const int64_t nb = (n + kTile - 1) / kTile;
-    k_scan_reduce<TI, TO><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials);
+    if (nb > 1) k_scan_reduce<TI, TO><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials);
     if (nb <= kScanFuse) {
         k_scan_down<TI, TO, true><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials,
-                                                                               out, nb);
+                                                                               out, nb, total_copy);
     } else {
         k_scan_partials<TO><<<1, kBlock, 0, st>>>(partials, nb);
-        k_scan_down<TI, TO, false><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials,
-                                                                                out, nb);
+        k_scan_down<TI, TO, false><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(
+            in, n, partials, out, nb, total_copy);
     }
 }
 
@@ -1742,15 +1751,18 @@ constexpr uint32_t kFiltSmall = 512;                   // fewer keys are sorted 
 constexpr uint32_t kFiltMax = 2u << kFiltBits;         // more keys would fill the tables
 constexpr uint32_t kFiltRounds = 6;
 
-// Slot of a (q, s, diag) group in round r: the 64-bit finalizer of SplitMix64
-// (Steele, Lea and Flood, OOPSLA 2014) over the group bits and the round.
+// Slot of a (q, s, diag) group in round r: the group bits folded to 32 and mixed
+// with the 32-bit finalizer of MurmurHash3 (Appleby), seeded by the round.  Groups
+// that fold alike share a slot in every round; that only keeps a few lone hits.
 __device__ __forceinline__ uint32_t diag_slot(uint64_t grp, uint32_t round)
 {
-    uint64_t x = grp + 0x9E3779B97F4A7C15ull * (uint64_t)(round + 1);
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    x ^= x >> 31;
-    return (uint32_t)(x >> (64 - kFiltBits));
+    uint32_t x = (uint32_t)grp ^ ((uint32_t)(grp >> 32) * 0x85EBCA6Bu) ^ (round * 0x9E3779B9u);
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x >> (32 - kFiltBits);
 }
 
 constexpr int kFiltBlock = 1024;  // threads of a filter block
@@ -1766,7 +1778,9 @@ __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict_
                                                            const uint32_t *__restrict__ hrel,
                                                            const int64_t *__restrict__ qoff,
                                                            int32_t qa, int64_t g0, int32_t nqw,
-                                                           int bp, uint32_t *__restrict__ kept,
+                                                           int bp,
+                                                           const int32_t *__restrict__ order,
+                                                           uint32_t *__restrict__ kept,
                                                            uint32_t *__restrict__ flag,
                                                            WaveCtl *__restrict__ ctl)
 {
@@ -1780,11 +1794,14 @@ __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict_
         nqw = ctl->nqw;
         bp = ctl->lay.bp;
     }
-    const int32_t ql = (int32_t)blockIdx.x;
-    if (ql >= nqw) {
-        if (threadIdx.x == 0) kept[ql] = 0;
+    if ((int32_t)blockIdx.x >= nqw) {
+        if (threadIdx.x == 0) kept[blockIdx.x] = 0;
         return;
     }
+    // blocks take the wave's queries largest first, so the longest filters start early
+    // (a replayed wave's order array covers the batch; a host-run wave's, the wave)
+    const int32_t ql = !order ? (int32_t)blockIdx.x
+                              : order[(ctl ? qa : 0) + (int32_t)blockIdx.x];
     const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t a = hrel[qoff[qa + ql] - g0];
@@ -1911,13 +1928,13 @@ __global__ __launch_bounds__(kBlock) void k_hit_compact(const uint64_t *__restri
 }
 
 void launch_hit_filter(uint64_t *keys, const uint32_t *hrel, const int64_t *qoff, int32_t qa,
-                       int64_t g0, int32_t nqw, int bp, uint32_t *kept, uint32_t *flag,
-                       hipStream_t st, WaveCtl *ctl, int32_t nq_cap)
+                       int64_t g0, int32_t nqw, int bp, const int32_t *order, uint32_t *kept,
+                       uint32_t *flag, hipStream_t st, WaveCtl *ctl, int32_t nq_cap)
 {
     const int32_t nb = ctl ? nq_cap : nqw;
     if (nb > 0)
-        k_hit_filter<<<nb, kFiltBlock, 0, st>>>(keys, hrel, qoff, qa, g0, nqw, bp, kept, flag,
-                                                ctl);
+        k_hit_filter<<<nb, kFiltBlock, 0, st>>>(keys, hrel, qoff, qa, g0, nqw, bp, order, kept,
+                                                flag, ctl);
 }
 
 void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_t *qoff,
@@ -2071,8 +2088,7 @@ void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_
 {
     const uint32_t nt = std::max<uint32_t>(1, (hits_cap + kTile - 1) / kTile);
     k_chain_count<<<nt, kBlock, 0, st>>>(keys, 0, 0, k, max_gap, min_len, counts, ctl);
-    launch_scan_u32(counts, counts, nt, partials, st);
-    k_copy_u32<<<1, 1, 0, st>>>(counts + nt, &ctl->nc);
+    scan_impl<uint32_t, uint32_t>(counts, counts, nt, partials, st, &ctl->nc);
     k_chain_write<<<nt, kBlock, 0, st>>>(keys, 0, HitKeyLayout{}, k, max_gap, min_len, counts, out,
                                          ctl);
 }
@@ -2097,12 +2113,6 @@ void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t 
     if (n)
         k_cand_segments<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
             c, n, qstart, qend, nullptr);
-}
-
-void launch_cand_segments_ctl(const Cand *c, uint32_t *qstart, uint32_t *qend, const WaveCtl *ctl,
-                              hipStream_t st)
-{
-    k_cand_segments<<<kStrideGrid, kBlock, 0, st>>>(c, 0, qstart, qend, ctl);
 }
 
 uint32_t chain_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
@@ -2890,6 +2900,81 @@ __global__ void k_select_counts(const uint32_t *__restrict__ qstart,
     if (q >= (ctl ? (ctl->overflow ? 0 : min(nq, ctl->nqw)) : nq)) return;
     const uint32_t c = qend[q] - qstart[q];
     nsel[q] = (N > 0 && c > (uint32_t)N) ? (uint32_t)N : c;
+}
+
+// A replayed wave's per-query ranges and counts in one launch (no zero-fill, no
+// per-record pass), thread ql for query ql of the nq_cap grid.  Runs are in query
+// order, so a binary search finds each query's range; a query's selected boxes
+// lead its own segment [seg_off[ql], seg_off[ql + 1]) (valid boxes sort first), so
+// a binary search in the segment finds where they end.  counts[ql] is the range's
+// length, capped at N when N > 0; queries past the wave, and every query of an
+// overflowed wave, get empty ranges.
+__global__ void k_cand_ranges(const Cand *__restrict__ c, int32_t nq_cap,
+                              uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
+                              uint32_t *__restrict__ counts, const WaveCtl *__restrict__ ctl)
+{
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq_cap) return;
+    const uint32_t n = ctl->overflow ? 0u : ctl->nc;
+    uint32_t a = 0, b = 0;
+    if (q < ctl->nqw && n > 0) {
+        uint32_t lo = 0, hi = n;  // first run of query >= q
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (c[mid].q < q) lo = mid + 1;
+            else hi = mid;
+        }
+        a = lo;
+        hi = n;  // first run of query > q
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (c[mid].q <= q) lo = mid + 1;
+            else hi = mid;
+        }
+        b = lo;
+    }
+    qstart[q] = a;
+    qend[q] = b;
+    counts[q] = b - a;
+}
+
+__global__ void k_box_ranges(const Box *__restrict__ s, const uint32_t *__restrict__ seg_off,
+                             int32_t nq_cap, int32_t N, uint32_t *__restrict__ qstart,
+                             uint32_t *__restrict__ qend, uint32_t *__restrict__ counts,
+                             const WaveCtl *__restrict__ ctl)
+{
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq_cap) return;
+    uint32_t a = 0, b = 0;
+    if (q < ctl->nqw && !ctl->overflow) {
+        a = seg_off[q];
+        uint32_t lo = a, hi = seg_off[q + 1];  // first empty slot of the segment
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s[mid].q >= 0) lo = mid + 1;
+            else hi = mid;
+        }
+        b = lo;
+    }
+    qstart[q] = a;
+    qend[q] = b;
+    const uint32_t cnt = b - a;
+    counts[q] = (N > 0 && cnt > (uint32_t)N) ? (uint32_t)N : cnt;
+}
+
+void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uint32_t *qend,
+                            uint32_t *counts, const WaveCtl *ctl, hipStream_t st)
+{
+    k_cand_ranges<<<(nq_cap + kBlock - 1) / kBlock, kBlock, 0, st>>>(c, nq_cap, qstart, qend,
+                                                                       counts, ctl);
+}
+
+void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
+                           uint32_t *qstart, uint32_t *qend, uint32_t *counts, const WaveCtl *ctl,
+                           hipStream_t st)
+{
+    k_box_ranges<<<(nq_cap + kBlock - 1) / kBlock, kBlock, 0, st>>>(s, seg_off, nq_cap, N, qstart,
+                                                                      qend, counts, ctl);
 }
 
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,

@@ -109,7 +109,7 @@ struct Workspace {
         gctl, gplan, gcursor, goflags, stiles, gtiles;
     DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
     DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
-    DevBuf fkept, fkoff, fflag;         // lone-diagonal filter
+    DevBuf fkept, fkoff, fflag, ford;   // lone-diagonal filter (ford: largest query first)
     // small pinned staging: [0] a wave's counts, [1] a batch's query offsets and hit
     // totals, [2] the replayed waves' plan, overflow flags and result counts
     void *pinned[3] = {nullptr, nullptr, nullptr};
@@ -140,7 +140,7 @@ struct Workspace {
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
-                         &lvalid, &ltile, &fkept, &fkoff, &fflag};
+                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -505,7 +505,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     const size_t n1 = (size_t)nqw + 1;
     const size_t u32s = 2 + (size_t)nqw + n1 + 4 * (size_t)nqw;
     const size_t cells_at = ((u32s * 4 + 7) / 8) * 8;
-    TRY(pinned(ws, cells_at + 8 * (size_t)nqw + 64, &pin));
+    TRY(pinned(ws, cells_at + 12 * (size_t)nqw + 64, &pin));  // + the filter's order [nqw]
     uint32_t *h_nc = reinterpret_cast<uint32_t *>(pin);
     uint32_t *h_cq = h_nc + 2;
     uint32_t *h_sel_off = h_cq + nqw;
@@ -715,6 +715,15 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             TRY(ensure(ws->fkept, sizeof(uint32_t) * (nqw + 1)));
             TRY(ensure(ws->fkoff, sizeof(uint32_t) * (nqw + 1)));
             TRY(ensure(ws->fflag, sizeof(uint32_t)));
+            TRY(ensure(ws->ford, sizeof(int32_t) * nqw));
+            int32_t *h_ord = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(h_cells) +
+                                                         8 * (size_t)nqw);
+            for (int32_t ql = 0; ql < nqw; ++ql) h_ord[ql] = ql;
+            std::stable_sort(h_ord, h_ord + nqw, [&](int32_t x, int32_t y) {
+                return qtot[qa + x] > qtot[qa + y];
+            });
+            HIPCHK(hipMemcpyAsync(ws->ford.p, h_ord, sizeof(int32_t) * nqw, hipMemcpyHostToDevice,
+                                  st));
         }
         // segmented radix passes over n keys in kin, counts[ql] keys per query in
         // query order; returns the buffer holding the sorted keys
@@ -765,7 +774,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                 HIPCHK(hipMemsetAsync(ws->fflag.p, 0, sizeof(uint32_t), st));
                 prof.begin("filter");
                 launch_hit_filter(kcur, as<uint32_t>(ws->hrel), as<int64_t>(ws->qoff), qa, g0, nqw,
-                                  lay.bp, as<uint32_t>(ws->fkept), as<uint32_t>(ws->fflag), st);
+                                  lay.bp, as<int32_t>(ws->ford), as<uint32_t>(ws->fkept),
+                                  as<uint32_t>(ws->fflag), st);
                 prof.end(H);
                 prof.begin("filter_compact");
                 launch_hit_compact(kcur, as<uint32_t>(ws->hrel), as<int64_t>(ws->qoff), qa, g0,
@@ -1314,6 +1324,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     if (filt) {
         TRY(ensure(ws->fkept, sizeof(uint32_t) * (nq_cap + 1)));
         TRY(ensure(ws->fkoff, sizeof(uint32_t) * (nq_cap + 1)));
+        TRY(ensure(ws->ford, sizeof(int32_t) * nq_out));
     }
     const uint64_t *sorted = (filt || (passes & 1)) ? as<uint64_t>(ws->keys_alt)
                                                     : as<uint64_t>(ws->keys);
@@ -1341,7 +1352,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                             &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
                             &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
                             &ws->gplan, &ws->gcursor, &ws->goflags, &ws->gtiles, &ws->fkept,
-                            &ws->fkoff})
+                            &ws->fkoff, &ws->ford})
         key.push_back((uint64_t)(uintptr_t)b->p);
 
     if (!ws->gexec || ws->gkey != key) {
@@ -1359,8 +1370,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                           ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl, st);
         if (filt) {
             launch_hit_filter(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
-                              as<int64_t>(ws->qoff), 0, 0, 0, 0, as<uint32_t>(ws->fkept), nullptr,
-                              st, ctl, nq_cap);
+                              as<int64_t>(ws->qoff), 0, 0, 0, 0, as<int32_t>(ws->ford),
+                              as<uint32_t>(ws->fkept), nullptr, st, ctl, nq_cap);
             launch_hit_compact(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
                                as<int64_t>(ws->qoff), 0, 0, 0, as<uint32_t>(ws->fkept),
                                as<uint32_t>(ws->fkoff), as<uint32_t>(ws->partials),
@@ -1376,11 +1387,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_chain_ctl(sorted, hits_cap, ix->span, p->max_gap, p->min_hsp_len,
                          as<uint32_t>(ws->ccount), as<uint32_t>(ws->partials), as<Cand>(ws->cands),
                          ctl, st);
-        launch_fill2_u32(as<uint32_t>(ws->qstart), nq_cap, as<uint32_t>(ws->qend), nq_cap, 0u, st);
-        launch_cand_segments_ctl(as<Cand>(ws->cands), as<uint32_t>(ws->qstart),
-                                 as<uint32_t>(ws->qend), ctl, st);
-        launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nq_cap, 0,
-                             as<uint32_t>(ws->cand_q), st, ctl);
+        launch_cand_ranges_ctl(as<Cand>(ws->cands), nq_cap, as<uint32_t>(ws->qstart),
+                               as<uint32_t>(ws->qend), as<uint32_t>(ws->cand_q), ctl, st);
         launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nq_cap,
                         as<uint32_t>(ws->partials), st);
         launch_extend(as<Cand>(ws->cands), 0, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0,
@@ -1391,11 +1399,9 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_merge_sweep(as<Box>(ws->boxes2), 0, as<Box>(ws->boxes3), st, ctl);
         launch_seg_sort_box(1, as<Box>(ws->boxes3), as<Box>(ws->boxes2),
                             as<uint32_t>(ws->cand_off), nq_cap, st, ctl);
-        launch_fill2_u32(as<uint32_t>(ws->qstart), nq_cap, as<uint32_t>(ws->qend), nq_cap, 0u, st);
-        launch_segments_box(as<Box>(ws->boxes2), 0, 0, as<uint32_t>(ws->qstart),
-                            as<uint32_t>(ws->qend), st, ctl);
-        launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nq_cap, N,
-                             as<uint32_t>(ws->nsel), st, ctl);
+        launch_box_ranges_ctl(as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nq_cap, N,
+                              as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend),
+                              as<uint32_t>(ws->nsel), ctl, st);
         launch_scan_u32(as<uint32_t>(ws->nsel), as<uint32_t>(ws->sel_off), nq_cap,
                         as<uint32_t>(ws->partials), st);
         launch_bsw(as<Box>(ws->boxes2), as<uint32_t>(ws->qstart), as<uint32_t>(ws->sel_off), 0, 0,
@@ -1423,15 +1429,26 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
 
     // replay it once per wave
     const size_t W = plan.size();
-    // staging: plan [W] | overflow flags [W] | result counts [nq]
+    // staging: plan [W] | overflow flags [W] | result counts [nq] | filter order [nq]
     void *pin;
-    TRY(pinned(ws, sizeof(WaveCtl) * W + sizeof(uint32_t) * W + sizeof(int32_t) * nq + 64, &pin,
-               2));
+    TRY(pinned(ws, sizeof(WaveCtl) * W + sizeof(uint32_t) * W + 2 * sizeof(int32_t) * nq + 64,
+               &pin, 2));
     WaveCtl *h_plan = static_cast<WaveCtl *>(pin);
     uint32_t *oflags = reinterpret_cast<uint32_t *>(h_plan + W);
     int32_t *nout = reinterpret_cast<int32_t *>(oflags + W);
     std::copy(plan.begin(), plan.end(), h_plan);
     HIPCHK(hipMemcpyAsync(ws->gplan.p, h_plan, sizeof(WaveCtl) * W, hipMemcpyHostToDevice, st));
+    if (filt) {  // each wave's queries, largest first, at the wave's own positions
+        int32_t *h_ord = nout + nq;
+        for (const WaveCtl &w : plan) {
+            int32_t *o = h_ord + w.qa;
+            for (int32_t r = 0; r < w.nqw; ++r) o[r] = r;
+            std::stable_sort(o, o + w.nqw, [&](int32_t x, int32_t y) {
+                return qtot[w.qa + x] > qtot[w.qa + y];
+            });
+        }
+        HIPCHK(hipMemcpyAsync(ws->ford.p, h_ord, sizeof(int32_t) * nq, hipMemcpyHostToDevice, st));
+    }
     if (!tiles.empty() && !filt)
         HIPCHK(hipMemcpyAsync(ws->gtiles.p, tiles.data(), sizeof(SortTile) * tiles.size(),
                               hipMemcpyHostToDevice, st));
