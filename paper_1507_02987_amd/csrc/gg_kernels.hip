@@ -3099,10 +3099,19 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
     // before them, so this gives them exactly the box's borders and band; cells past
     // the box are never read and only kept out of the best cell.  The one neighbour
     // no lane holds, left of slot 0, is the border in column 0 and -inf elsewhere.
-    for (int32_t a = a0; a <= a1; a += 2, ++i, ++j, hereX += 128) {
+    // The first pairs hold cells before the box (row or column < 0); once every
+    // band lane has reached row and column 0 (after `edge` pairs) no cell is, and
+    // the rest of the sweep drops the border tests.  There only the one lane whose
+    // Y slot lies past the band (t = 2W + 1) is still forced to -inf, since its X
+    // reads it; other slots past the band are read by no in-band cell.
+    int32_t edge = (lane <= W) ? max(0, max(-i, -j)) : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) edge = max(edge, __shfl_xor(edge, off, 64));
+    auto pair = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
         const int32_t qb = nqb, dX = ndX, dY = ndY;
         bases(i + 1, j + 1, nqb, ndX, ndY);
-        const bool before_row = i < 0;
+        const bool before_row = EDGE && i < 0;
         const bool rowin = (uint32_t)i < (uint32_t)R;
         {  // X = (i, j): left = the lower lane's previous Y, up = this lane's previous Y
             int32_t hl = from_lower_lane(HY), el = from_lower_lane(EY);
@@ -3113,10 +3122,16 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
             }
             const CellOut c = sw_cell(hl, el, sl, sel, HY, FY, SY, SFY, HX, SX, qb == dX, hereX,
                                       match, mismatch, o1, ext);
-            const bool border = before_row || j < 0;
-            HX = border ? 0 : (laneX ? c.H : kNegInf);
-            EX = (border || !laneX) ? kNegInf : c.E;
-            FX = (border || !laneX) ? kNegInf : c.F;
+            if (EDGE) {
+                const bool border = before_row || j < 0;
+                HX = border ? 0 : (laneX ? c.H : kNegInf);
+                EX = (border || !laneX) ? kNegInf : c.E;
+                FX = (border || !laneX) ? kNegInf : c.F;
+            } else {
+                HX = c.H;
+                EX = c.E;
+                FX = c.F;
+            }
             SX = c.S; SEX = c.SE; SFX = c.SF;
             if (laneX && rowin && (uint32_t)j < (uint32_t)C && c.H > best) {
                 best = c.H;
@@ -3130,10 +3145,16 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
             const int32_t su = from_upper_lane(SX), sfu = from_upper_lane(SFX);
             const CellOut c = sw_cell(HX, EX, SX, SEX, hu, fu, su, sfu, HY, SY, qb == dY, hereX + 1,
                                       match, mismatch, o1, ext);
-            const bool border = before_row || jy < 0;
-            HY = border ? 0 : (laneY ? c.H : kNegInf);
-            EY = (border || !laneY) ? kNegInf : c.E;
-            FY = (border || !laneY) ? kNegInf : c.F;
+            if (EDGE) {
+                const bool border = before_row || jy < 0;
+                HY = border ? 0 : (laneY ? c.H : kNegInf);
+                EY = (border || !laneY) ? kNegInf : c.E;
+                FY = (border || !laneY) ? kNegInf : c.F;
+            } else {
+                HY = laneY ? c.H : kNegInf;
+                EY = c.E;
+                FY = laneY ? c.F : kNegInf;
+            }
             SY = c.S; SEY = c.SE; SFY = c.SF;
             if (laneY && rowin && (uint32_t)jy < (uint32_t)C && c.H > best) {
                 best = c.H;
@@ -3141,7 +3162,11 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
                 bstart = c.S;
             }
         }
-    }
+    };
+    int32_t a = a0;
+    for (const int32_t a_edge = a0 + 2 * edge; a <= a1 && a < a_edge; a += 2, ++i, ++j, hereX += 128)
+        pair(std::true_type{});
+    for (; a <= a1; a += 2, ++i, ++j, hereX += 128) pair(std::false_type{});
 }
 
 // One wave (one block) per selected box; boxes whose bases fit kBswStage each
@@ -3189,6 +3214,12 @@ __global__ __launch_bounds__(64) void k_bsw(
         const int32_t a0 = a_lo - ((a_lo - c0 + W) & 1);
         const int32_t a1 = a_hi + (((a_hi - c0 + W) & 1) ^ 1);
         cells = band_cells(R, C, clo, chi, lane);
+        // a box's sweep is one serial chain of anti-diagonals, so the longest boxes
+        // set the kernel's time: their waves take issue priority over short ones
+        const int32_t span = a1 - a0;
+        if (span > 1024) __builtin_amdgcn_s_setprio(3);
+        else if (span > 512) __builtin_amdgcn_s_setprio(2);
+        else if (span > 256) __builtin_amdgcn_s_setprio(1);
         if (R <= kBswStage && C <= kBswStage) {
             for (int32_t x = lane; x < R; x += 64) s_q[x] = qp[x];
             for (int32_t x = lane; x < C; x += 64) s_d[x] = (uint8_t)db_base(dbw, dbase + x);
@@ -3200,6 +3231,7 @@ __global__ __launch_bounds__(64) void k_bsw(
                              ext, lane, best, bcell, bstart);
         }
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const int32_t ob = __shfl_xor(best, off, 64);
