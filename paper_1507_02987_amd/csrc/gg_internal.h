@@ -269,7 +269,7 @@ void launch_rs_scatter_seg(const uint64_t *kin, uint64_t *kout, uint32_t ntile, 
                            const SortTile *tiles, const uint32_t *hist, hipStream_t st);
 void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_t max_gap,
                       int32_t min_len, uint32_t *counts, uint32_t *partials, Cand *out,
-                      WaveCtl *ctl, hipStream_t st);
+                      WaveCtl *ctl, hipStream_t st, bool few = false);
 // The three kernels of one radix pass (digit histogram, its scan, stable scatter).
 void launch_rs_hist(const uint64_t *keys, uint32_t n, int shift, uint32_t *hist, hipStream_t st);
 void launch_rs_scan(uint32_t *hist, uint32_t n, uint32_t *partials, hipStream_t st);
@@ -313,14 +313,19 @@ void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qs
                          uint32_t *qend, hipStream_t st, const WaveCtl *ctl = nullptr);
 void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
                            uint32_t *qend, hipStream_t st);
-// A replayed wave's per-query run ranges and counts (runs in query order), and its
-// per-query selected-box ranges and counts capped at N (each query's boxes in its
-// own segment, selected ones first); grids of nq_cap threads.
+// A replayed wave's per-query run ranges, counts and offsets (off[0..nq_cap]: runs
+// are in query order, so offsets are the ranges' starts), and its per-query
+// selected-box ranges and counts capped at N (each query's boxes in its own
+// segment, selected ones first); grids of nq_cap threads.  The _scan form also
+// writes the counts' exclusive scan (sel_off[0..nq_cap]) from one block.
 void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uint32_t *qend,
-                            uint32_t *counts, const WaveCtl *ctl, hipStream_t st);
+                            uint32_t *counts, uint32_t *off, const WaveCtl *ctl, hipStream_t st);
 void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
                            uint32_t *qstart, uint32_t *qend, uint32_t *counts, const WaveCtl *ctl,
                            hipStream_t st);
+void launch_box_ranges_scan_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
+                                uint32_t *qstart, uint32_t *qend, uint32_t *sel_off,
+                                const WaveCtl *ctl, hipStream_t st);
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
                           int32_t max_hits, uint32_t *nsel, hipStream_t st,
                           const WaveCtl *ctl = nullptr);

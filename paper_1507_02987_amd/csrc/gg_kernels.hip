@@ -1901,6 +1901,16 @@ __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict_
     for (uint32_t i = threadIdx.x; i < m; i += kFiltBlock) k[i] = s_buf[i];
 }
 
+// Sum of v[0..n) over the block (kBlock threads); every thread gets it.
+__device__ __forceinline__ uint32_t block_sum(const uint32_t *__restrict__ v, uint32_t n)
+{
+    uint32_t x = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) x += v[i];
+    uint32_t tot;
+    block_excl_scan<uint32_t>(x, &tot);
+    return tot;
+}
+
 // Each query's kept keys to koff[ql] of `out`, after the scan of the kept counts;
 // a replayed wave learns its sorted count here (none when a query overflowed: the
 // wave is run again by the host).
@@ -1913,16 +1923,20 @@ __global__ __launch_bounds__(kBlock) void k_hit_compact(const uint64_t *__restri
                                                         uint64_t *__restrict__ out,
                                                         WaveCtl *__restrict__ ctl)
 {
+    // koff null: each block adds up the kept counts before its own (few queries)
     if (ctl) {
         qa = ctl->qa;
         g0 = ctl->g0;
         nqw = ctl->nqw;
-        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->H = ctl->overflow ? 0u : koff[nqw];
+        if (blockIdx.x == 0) {
+            const uint32_t total = koff ? koff[nqw] : block_sum(kept, (uint32_t)nqw);
+            if (threadIdx.x == 0) ctl->H = ctl->overflow ? 0u : total;
+        }
     }
     const int32_t ql = (int32_t)blockIdx.x;
     if (ql >= nqw) return;
     const uint64_t *src = keys + hrel[qoff[qa + ql] - g0];
-    uint64_t *dst = out + koff[ql];
+    uint64_t *dst = out + (koff ? koff[ql] : block_sum(kept, (uint32_t)ql));
     const uint32_t n = kept[ql];
     for (uint32_t i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
 }
@@ -1944,8 +1958,12 @@ void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_
 {
     const int32_t nb = ctl ? nq_cap : nqw;
     if (nb <= 0) return;
-    launch_scan_u32(kept, koff, nb, partials, st);
-    k_hit_compact<<<nb, kBlock, 0, st>>>(keys, hrel, qoff, qa, g0, nqw, kept, koff, out, ctl);
+    // a replayed wave of a few thousand queries skips the scan: blocks add up
+    // the counts before them
+    const bool self = ctl && nq_cap <= 4096;
+    if (!self) launch_scan_u32(kept, koff, nb, partials, st);
+    k_hit_compact<<<nb, kBlock, 0, st>>>(keys, hrel, qoff, qa, g0, nqw, kept, self ? nullptr : koff,
+                                         out, ctl);
 }
 
 // ------------------------------------------------------------------ S5: chain + filter
@@ -2025,22 +2043,26 @@ __global__ __launch_bounds__(kBlock) void k_chain_count(const uint64_t *__restri
     if (threadIdx.x == 0) counts[blockIdx.x] = tot;
 }
 
+// SELF (replayed waves with few hits): no scan of the tile counts; each tile with
+// hits adds up the counts before it, and the last one stores the total in ctl->nc.
+template <bool SELF>
 __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restrict__ keys,
                                                         uint32_t n, HitKeyLayout lay, int32_t k,
                                                         int32_t G, int32_t M,
                                                         const uint32_t *__restrict__ tile_off,
                                                         Cand *__restrict__ out,
-                                                        const WaveCtl *__restrict__ ctl)
+                                                        WaveCtl *__restrict__ ctl)
 {
     if (ctl) {
         n = ctl->H;
         lay = ctl->lay;
     }
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    if (SELF && n == 0 && blockIdx.x == 0 && threadIdx.x == 0) ctl->nc = 0;
     if (ctl && base >= n) return;
     __shared__ uint64_t s_k[kTile + 2];
     const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
-    uint32_t at = tile_off[blockIdx.x];
+    uint32_t at = SELF ? block_sum(tile_off, blockIdx.x) : tile_off[blockIdx.x];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const uint32_t l = r * kBlock + threadIdx.x;
@@ -2061,6 +2083,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
         }
         at += tot;
     }
+    if (SELF && base + kTile >= n && threadIdx.x == 0) ctl->nc = at;  // the last tile
 }
 
 void launch_chain_count(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
@@ -2076,21 +2099,28 @@ void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int3
                         hipStream_t st)
 {
     if (n == 0) return;
-    k_chain_write<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(keys, n, lay, k, max_gap, min_len,
+    k_chain_write<false><<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(keys, n, lay, k, max_gap, min_len,
                                                               tile_off, out, nullptr);
 }
 
 // Chaining of a graph-replayed wave over tiles of hits_cap hits: run counts per
 // tile, their scan (total at counts[tiles], copied to ctl->nc), then the runs.
+// With few hits (the lone-diagonal filter ran) the write kernel adds up the
+// counts of the tiles before it instead.
 void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_t max_gap,
                       int32_t min_len, uint32_t *counts, uint32_t *partials, Cand *out,
-                      WaveCtl *ctl, hipStream_t st)
+                      WaveCtl *ctl, hipStream_t st, bool few)
 {
     const uint32_t nt = std::max<uint32_t>(1, (hits_cap + kTile - 1) / kTile);
     k_chain_count<<<nt, kBlock, 0, st>>>(keys, 0, 0, k, max_gap, min_len, counts, ctl);
+    if (few) {
+        k_chain_write<true><<<nt, kBlock, 0, st>>>(keys, 0, HitKeyLayout{}, k, max_gap, min_len,
+                                                   counts, out, ctl);
+        return;
+    }
     scan_impl<uint32_t, uint32_t>(counts, counts, nt, partials, st, &ctl->nc);
-    k_chain_write<<<nt, kBlock, 0, st>>>(keys, 0, HitKeyLayout{}, k, max_gap, min_len, counts, out,
-                                         ctl);
+    k_chain_write<false><<<nt, kBlock, 0, st>>>(keys, 0, HitKeyLayout{}, k, max_gap, min_len,
+                                                counts, out, ctl);
 }
 
 // Runs come out in (q, s, diag) order: each query's runs are one range
@@ -2911,12 +2941,17 @@ __global__ void k_select_counts(const uint32_t *__restrict__ qstart,
 // overflowed wave, get empty ranges.
 __global__ void k_cand_ranges(const Cand *__restrict__ c, int32_t nq_cap,
                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
-                              uint32_t *__restrict__ counts, const WaveCtl *__restrict__ ctl)
+                              uint32_t *__restrict__ counts, uint32_t *__restrict__ off,
+                              const WaveCtl *__restrict__ ctl)
 {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq_cap) return;
+    if (q > nq_cap) return;
     const uint32_t n = ctl->overflow ? 0u : ctl->nc;
-    uint32_t a = 0, b = 0;
+    if (q == nq_cap) {
+        off[q] = n;
+        return;
+    }
+    uint32_t a = n, b = n;  // queries past the wave: empty ranges at the end
     if (q < ctl->nqw && n > 0) {
         uint32_t lo = 0, hi = n;  // first run of query >= q
         while (lo < hi) {
@@ -2936,6 +2971,7 @@ __global__ void k_cand_ranges(const Cand *__restrict__ c, int32_t nq_cap,
     qstart[q] = a;
     qend[q] = b;
     counts[q] = b - a;
+    off[q] = a;  // runs are in query order: a query's first run is its offset
 }
 
 __global__ void k_box_ranges(const Box *__restrict__ s, const uint32_t *__restrict__ seg_off,
@@ -2963,10 +2999,47 @@ __global__ void k_box_ranges(const Box *__restrict__ s, const uint32_t *__restri
 }
 
 void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uint32_t *qend,
-                            uint32_t *counts, const WaveCtl *ctl, hipStream_t st)
+                            uint32_t *counts, uint32_t *off, const WaveCtl *ctl, hipStream_t st)
 {
-    k_cand_ranges<<<(nq_cap + kBlock - 1) / kBlock, kBlock, 0, st>>>(c, nq_cap, qstart, qend,
-                                                                       counts, ctl);
+    k_cand_ranges<<<(nq_cap + kBlock) / kBlock, kBlock, 0, st>>>(c, nq_cap, qstart, qend, counts,
+                                                                   off, ctl);
+}
+
+// The same ranges, with the exclusive scan of the capped counts (sel_off[0..nq_cap],
+// total last) in the same launch: one block walks the queries kBlock at a time.
+__global__ __launch_bounds__(kBlock) void k_box_ranges_scan(const Box *__restrict__ s,
+                                                            const uint32_t *__restrict__ seg_off,
+                                                            int32_t nq_cap, int32_t N,
+                                                            uint32_t *__restrict__ qstart,
+                                                            uint32_t *__restrict__ qend,
+                                                            uint32_t *__restrict__ sel_off,
+                                                            const WaveCtl *__restrict__ ctl)
+{
+    uint32_t carry = 0;
+    for (int32_t q0 = 0; q0 < nq_cap; q0 += kBlock) {
+        const int32_t q = q0 + (int32_t)threadIdx.x;
+        uint32_t a = 0, b = 0;
+        if (q < nq_cap && q < ctl->nqw && !ctl->overflow) {
+            a = seg_off[q];
+            uint32_t lo = a, hi = seg_off[q + 1];  // first empty slot of the segment
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s[mid].q >= 0) lo = mid + 1;
+                else hi = mid;
+            }
+            b = lo;
+        }
+        const uint32_t cnt = (N > 0 && b - a > (uint32_t)N) ? (uint32_t)N : b - a;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<uint32_t>(cnt, &tot);
+        if (q < nq_cap) {
+            qstart[q] = a;
+            qend[q] = b;
+            sel_off[q] = carry + ex;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) sel_off[nq_cap] = carry;
 }
 
 void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
@@ -2975,6 +3048,13 @@ void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap
 {
     k_box_ranges<<<(nq_cap + kBlock - 1) / kBlock, kBlock, 0, st>>>(s, seg_off, nq_cap, N, qstart,
                                                                       qend, counts, ctl);
+}
+
+void launch_box_ranges_scan_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
+                                uint32_t *qstart, uint32_t *qend, uint32_t *sel_off,
+                                const WaveCtl *ctl, hipStream_t st)
+{
+    k_box_ranges_scan<<<1, kBlock, 0, st>>>(s, seg_off, nq_cap, N, qstart, qend, sel_off, ctl);
 }
 
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,

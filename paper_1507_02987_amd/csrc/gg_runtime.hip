@@ -1386,11 +1386,10 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         }
         launch_chain_ctl(sorted, hits_cap, ix->span, p->max_gap, p->min_hsp_len,
                          as<uint32_t>(ws->ccount), as<uint32_t>(ws->partials), as<Cand>(ws->cands),
-                         ctl, st);
+                         ctl, st, filt);
         launch_cand_ranges_ctl(as<Cand>(ws->cands), nq_cap, as<uint32_t>(ws->qstart),
-                               as<uint32_t>(ws->qend), as<uint32_t>(ws->cand_q), ctl, st);
-        launch_scan_u32(as<uint32_t>(ws->cand_q), as<uint32_t>(ws->cand_off), nq_cap,
-                        as<uint32_t>(ws->partials), st);
+                               as<uint32_t>(ws->qend), as<uint32_t>(ws->cand_q),
+                               as<uint32_t>(ws->cand_off), ctl, st);
         launch_extend(as<Cand>(ws->cands), 0, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0,
                       ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop,
                       as<Box>(ws->boxes), ws->xqueue.p, steps, st, ctl, hits_cap);
@@ -1399,11 +1398,17 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_merge_sweep(as<Box>(ws->boxes2), 0, as<Box>(ws->boxes3), st, ctl);
         launch_seg_sort_box(1, as<Box>(ws->boxes3), as<Box>(ws->boxes2),
                             as<uint32_t>(ws->cand_off), nq_cap, st, ctl);
-        launch_box_ranges_ctl(as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nq_cap, N,
-                              as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend),
-                              as<uint32_t>(ws->nsel), ctl, st);
-        launch_scan_u32(as<uint32_t>(ws->nsel), as<uint32_t>(ws->sel_off), nq_cap,
-                        as<uint32_t>(ws->partials), st);
+        if (nq_cap <= 4096) {  // ranges and their scan in one launch
+            launch_box_ranges_scan_ctl(as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nq_cap, N,
+                                       as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend),
+                                       as<uint32_t>(ws->sel_off), ctl, st);
+        } else {
+            launch_box_ranges_ctl(as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nq_cap, N,
+                                  as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend),
+                                  as<uint32_t>(ws->nsel), ctl, st);
+            launch_scan_u32(as<uint32_t>(ws->nsel), as<uint32_t>(ws->sel_off), nq_cap,
+                            as<uint32_t>(ws->partials), st);
+        }
         launch_bsw(as<Box>(ws->boxes2), as<uint32_t>(ws->qstart), as<uint32_t>(ws->sel_off), 0, 0,
                    as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0, ix->d_dbw, ix->d_seq_start,
                    p->match, p->mismatch, p->gap_open, p->gap_extend, p->band,
