@@ -233,11 +233,13 @@ void launch_fill2_u32(uint32_t *a, size_t na, uint32_t *b, size_t nb, uint32_t v
 
 // ---- graph-replayed waves: the kernels below read the wave's sizes from ctl;
 // grids are sized for the largest wave of the batch (hits_cap, np_cap, nq_cap).
-void launch_wave_begin(const WaveCtl *plan, uint32_t *cursor, WaveCtl *ctl, hipStream_t st);
-void launch_wave_end(const WaveCtl *ctl, const uint32_t *cursor, uint32_t *oflags, hipStream_t st);
+// The first node takes the wave's plan entry plan[*cursor] into ctl; the last
+// records the overflow flag at oflags[*cursor] and advances the cursor.
+void launch_wave_end(const WaveCtl *ctl, uint32_t *cursor, uint32_t *oflags, hipStream_t st);
 void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
                           const int32_t *qid, int64_t np_cap, uint32_t *hrel, uint32_t *pbase,
-                          uint64_t *akey, const WaveCtl *ctl, hipStream_t st);
+                          uint64_t *akey, const WaveCtl *plan, const uint32_t *cursor,
+                          WaveCtl *ctl, hipStream_t st);
 void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                        const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
                        hipStream_t st);
@@ -297,7 +299,7 @@ void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_
                    int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
                    int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
                    int32_t lane_steps, hipStream_t st, const WaveCtl *ctl = nullptr,
-                   uint32_t n_cap = 0);
+                   uint32_t n_cap = 0, bool count_cleared = false);
 void launch_box_keys(const Box *b, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
                      const uint32_t *perm, hipStream_t st);
 void launch_align_keys(const Align *a, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
@@ -316,10 +318,12 @@ void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t
 // A replayed wave's per-query run ranges, counts and offsets (off[0..nq_cap]: runs
 // are in query order, so offsets are the ranges' starts), and its per-query
 // selected-box ranges and counts capped at N (each query's boxes in its own
-// segment, selected ones first); grids of nq_cap threads.  The _scan form also
+// segment, selected ones first); grids of nq_cap threads (the first also zeroes
+// *clear, the extension's queue count, when given).  The _scan form also
 // writes the counts' exclusive scan (sel_off[0..nq_cap]) from one block.
 void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uint32_t *qend,
-                            uint32_t *counts, uint32_t *off, const WaveCtl *ctl, hipStream_t st);
+                            uint32_t *counts, uint32_t *off, uint32_t *clear, const WaveCtl *ctl,
+                            hipStream_t st);
 void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
                            uint32_t *qstart, uint32_t *qend, uint32_t *counts, const WaveCtl *ctl,
                            hipStream_t st);

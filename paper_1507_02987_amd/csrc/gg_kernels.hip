@@ -505,18 +505,24 @@ void launch_query_totals(const uint64_t *hoff, const int64_t *qoff, int32_t nq, 
 // Per position of the wave: its first hit (relative to the wave), the index of its
 // posting list's head, and the constant part of its hits' keys
 // (q << sh_q) + ((bias - qpos) << sh_d) + qpos.
+// A replayed wave (ctl given) takes its plan entry plan[*cursor] here, and block 0
+// publishes it in ctl for the wave's later kernels (the cursor moves on at the
+// wave's end).
 __global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__restrict__ qoff,
                             const uint32_t *__restrict__ lhead, const int32_t *__restrict__ qid,
                             int32_t qa, int64_t g0,
                             int64_t np, HitKeyLayout lay, uint32_t *__restrict__ hrel,
                             uint32_t *__restrict__ pbase, uint64_t *__restrict__ akey,
-                            const WaveCtl *__restrict__ ctl)
+                            const WaveCtl *__restrict__ plan, const uint32_t *__restrict__ cursor,
+                            WaveCtl *__restrict__ ctl)
 {
     if (ctl) {
-        qa = ctl->qa;
-        g0 = ctl->g0;
-        np = ctl->np;
-        lay = ctl->lay;
+        const WaveCtl w = plan[*cursor];
+        if (blockIdx.x == 0 && threadIdx.x == 0) *ctl = w;
+        qa = w.qa;
+        g0 = w.g0;
+        np = w.np;
+        lay = w.lay;
     }
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p > np) return;
@@ -539,17 +545,19 @@ void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t 
     const int64_t np = g1 - g0;
     const int64_t nb = (np + 1 + kBlock - 1) / kBlock;
     k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, lhead, qid, qa, g0, np,
-                                                             lay, hrel, pbase, akey, nullptr);
+                                                             lay, hrel, pbase, akey, nullptr,
+                                                             nullptr, nullptr);
 }
 
 void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
                           const int32_t *qid, int64_t np_cap, uint32_t *hrel, uint32_t *pbase,
-                          uint64_t *akey, const WaveCtl *ctl, hipStream_t st)
+                          uint64_t *akey, const WaveCtl *plan, const uint32_t *cursor,
+                          WaveCtl *ctl, hipStream_t st)
 {
     const int64_t nb = (np_cap + 1 + kBlock - 1) / kBlock;
     k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, lhead, qid, 0, 0, 0,
                                                              HitKeyLayout{}, hrel, pbase, akey,
-                                                             ctl);
+                                                             plan, cursor, ctl);
 }
 
 // ------------------------------------------------------------------ S3 by sequence range
@@ -1540,28 +1548,18 @@ __global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t *__restrict__ hist,
     }
 }
 
-// First and last node of a replayed wave graph: take the next planned wave, and
-// record whether it overflowed the per-query LDS sorts.
-__global__ void k_wave_begin(const WaveCtl *__restrict__ plan, uint32_t *__restrict__ cursor,
-                             WaveCtl *__restrict__ ctl)
+// Last node of a replayed wave graph: record whether the wave overflowed the
+// per-query LDS sorts, and move the cursor to the next planned wave (the first
+// node, the wave preparation, takes the plan entry at the cursor).
+__global__ void k_wave_end(const WaveCtl *__restrict__ ctl, uint32_t *__restrict__ cursor,
+                           uint32_t *__restrict__ oflags)
 {
     const uint32_t w = *cursor;
-    *ctl = plan[w];
+    oflags[w] = ctl->overflow;
     *cursor = w + 1;
 }
 
-__global__ void k_wave_end(const WaveCtl *__restrict__ ctl, const uint32_t *__restrict__ cursor,
-                           uint32_t *__restrict__ oflags)
-{
-    oflags[*cursor - 1] = ctl->overflow;
-}
-
-void launch_wave_begin(const WaveCtl *plan, uint32_t *cursor, WaveCtl *ctl, hipStream_t st)
-{
-    k_wave_begin<<<1, 1, 0, st>>>(plan, cursor, ctl);
-}
-
-void launch_wave_end(const WaveCtl *ctl, const uint32_t *cursor, uint32_t *oflags, hipStream_t st)
+void launch_wave_end(const WaveCtl *ctl, uint32_t *cursor, uint32_t *oflags, hipStream_t st)
 {
     k_wave_end<<<1, 1, 0, st>>>(ctl, cursor, oflags);
 }
@@ -2404,7 +2402,8 @@ size_t extend_queue_bytes(uint32_t n)
 void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
                    int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
                    int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
-                   int32_t lane_steps, hipStream_t st, const WaveCtl *ctl, uint32_t n_cap)
+                   int32_t lane_steps, hipStream_t st, const WaveCtl *ctl, uint32_t n_cap,
+                   bool count_cleared)
 {
     // graph form: n comes from ctl, grids are sized for n_cap runs
     const uint32_t nmax = ctl ? n_cap : n;
@@ -2412,7 +2411,7 @@ void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_
     uint32_t *qcount = static_cast<uint32_t *>(queue_mem);
     XWalk *queue = reinterpret_cast<XWalk *>(static_cast<char *>(queue_mem) + 256);
     const uint32_t qcap = (uint32_t)((extend_queue_bytes(nmax) - 256) / sizeof(XWalk));
-    launch_fill_u32(qcount, 1, 0u, st);
+    if (!count_cleared) launch_fill_u32(qcount, 1, 0u, st);
     const uint32_t nb = ctl ? kStrideGrid : std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid);
     k_extend<<<nb, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start, match, mismatch, xdrop,
                                     out, queue, qcap, qcount, std::max(lane_steps, 0), ctl);
@@ -2942,13 +2941,14 @@ __global__ void k_select_counts(const uint32_t *__restrict__ qstart,
 __global__ void k_cand_ranges(const Cand *__restrict__ c, int32_t nq_cap,
                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
                               uint32_t *__restrict__ counts, uint32_t *__restrict__ off,
-                              const WaveCtl *__restrict__ ctl)
+                              uint32_t *__restrict__ clear, const WaveCtl *__restrict__ ctl)
 {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q > nq_cap) return;
     const uint32_t n = ctl->overflow ? 0u : ctl->nc;
     if (q == nq_cap) {
         off[q] = n;
+        if (clear) *clear = 0u;
         return;
     }
     uint32_t a = n, b = n;  // queries past the wave: empty ranges at the end
@@ -2999,10 +2999,11 @@ __global__ void k_box_ranges(const Box *__restrict__ s, const uint32_t *__restri
 }
 
 void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uint32_t *qend,
-                            uint32_t *counts, uint32_t *off, const WaveCtl *ctl, hipStream_t st)
+                            uint32_t *counts, uint32_t *off, uint32_t *clear, const WaveCtl *ctl,
+                            hipStream_t st)
 {
     k_cand_ranges<<<(nq_cap + kBlock) / kBlock, kBlock, 0, st>>>(c, nq_cap, qstart, qend, counts,
-                                                                   off, ctl);
+                                                                   off, clear, ctl);
 }
 
 // The same ranges, with the exclusive scan of the capped counts (sel_off[0..nq_cap],

@@ -1362,10 +1362,10 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         }
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        launch_wave_begin(as<WaveCtl>(ws->gplan), cursor, ctl, st);
         launch_wave_prep_ctl(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->lhead),
                              as<int32_t>(ws->qid), np_cap, as<uint32_t>(ws->hrel),
-                             as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), ctl, st);
+                             as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
+                             as<WaveCtl>(ws->gplan), cursor, ctl, st);
         launch_gather_ctl(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
                           ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl, st);
         if (filt) {
@@ -1389,10 +1389,12 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                          ctl, st, filt);
         launch_cand_ranges_ctl(as<Cand>(ws->cands), nq_cap, as<uint32_t>(ws->qstart),
                                as<uint32_t>(ws->qend), as<uint32_t>(ws->cand_q),
-                               as<uint32_t>(ws->cand_off), ctl, st);
+                               as<uint32_t>(ws->cand_off), static_cast<uint32_t *>(ws->xqueue.p),
+                               ctl, st);
         launch_extend(as<Cand>(ws->cands), 0, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0,
                       ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop,
-                      as<Box>(ws->boxes), ws->xqueue.p, steps, st, ctl, hits_cap);
+                      as<Box>(ws->boxes), ws->xqueue.p, steps, st, ctl, hits_cap,
+                      /*count_cleared=*/true);
         launch_seg_sort_box(0, as<Box>(ws->boxes), as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off),
                             nq_cap, st, ctl);
         launch_merge_sweep(as<Box>(ws->boxes2), 0, as<Box>(ws->boxes3), st, ctl);
