@@ -123,7 +123,8 @@ void launch_query_totals(const uint64_t *hoff, const int64_t *qoff, int32_t nq, 
                          hipStream_t st);
 void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
                       const int32_t *qid, int32_t qa, int64_t g0, int64_t g1, HitKeyLayout lay,
-                      uint32_t *hrel, uint32_t *pbase, uint64_t *akey, hipStream_t st);
+                      uint32_t *hrel, uint32_t *pbase, uint64_t *akey, uint32_t *tile_pos,
+                      hipStream_t st);
 // Index build (Sections 2, 2.1): pack the bank 2 bits per base; code every
 // non-overlapping window (keys = code, vals = window number, counts per code);
 // after a stable sort by code, window numbers become (sequence, position) postings.
@@ -174,7 +175,7 @@ void launch_piece_prep(const uint32_t *kcode, const uint32_t *cnt, int64_t np,
                        hipStream_t st);
 void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                    int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
-                   uint64_t *keys, hipStream_t st);
+                   uint64_t *keys, const uint32_t *tile_pos, hipStream_t st);
 // Runs found by probing the windows next to every hit (no stored hit): single-hit
 // runs and the bounds of longer runs; bounds are grouped by query, then sorted
 // and paired per query.  Runs in any order are finally grouped by query.
@@ -239,10 +240,10 @@ void launch_wave_end(const WaveCtl *ctl, uint32_t *cursor, uint32_t *oflags, hip
 void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
                           const int32_t *qid, int64_t np_cap, uint32_t *hrel, uint32_t *pbase,
                           uint64_t *akey, const WaveCtl *plan, const uint32_t *cursor,
-                          WaveCtl *ctl, hipStream_t st);
+                          WaveCtl *ctl, uint32_t *tile_pos, hipStream_t st);
 void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                        const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
-                       hipStream_t st);
+                       const uint32_t *tile_pos, hipStream_t st);
 // Per-query filter of hits alone on their (s, diag) group and LDS sort of the
 // kept keys, in place (kept counts per query in kept[]; queries too large for the
 // LDS sort set *flag, or ctl->overflow for a replayed wave, whose grid covers

@@ -514,7 +514,7 @@ __global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__
                             int64_t np, HitKeyLayout lay, uint32_t *__restrict__ hrel,
                             uint32_t *__restrict__ pbase, uint64_t *__restrict__ akey,
                             const WaveCtl *__restrict__ plan, const uint32_t *__restrict__ cursor,
-                            WaveCtl *__restrict__ ctl)
+                            WaveCtl *__restrict__ ctl, uint32_t *__restrict__ tile_pos)
 {
     if (ctl) {
         const WaveCtl w = plan[*cursor];
@@ -527,8 +527,13 @@ __global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p > np) return;
     const uint64_t hb = hoff[g0];
-    hrel[p] = (uint32_t)(hoff[g0 + p] - hb);
+    const uint64_t r0 = hoff[g0 + p] - hb;
+    hrel[p] = (uint32_t)r0;
     if (p == np) return;
+    if (tile_pos) {  // the position holding each gather tile's first hit
+        const uint64_t r1 = hoff[g0 + p + 1] - hb;
+        for (uint64_t t = (r0 + kTile - 1) / kTile; t * kTile < r1; ++t) tile_pos[t] = (uint32_t)p;
+    }
     const int64_t g = g0 + p;
     const int32_t q = qid[g];
     const int32_t qpos = (int32_t)(g - qoff[q]);
@@ -540,24 +545,25 @@ __global__ void k_wave_prep(const uint64_t *__restrict__ hoff, const int64_t *__
 
 void launch_wave_prep(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
                       const int32_t *qid, int32_t qa, int64_t g0, int64_t g1, HitKeyLayout lay,
-                      uint32_t *hrel, uint32_t *pbase, uint64_t *akey, hipStream_t st)
+                      uint32_t *hrel, uint32_t *pbase, uint64_t *akey, uint32_t *tile_pos,
+                      hipStream_t st)
 {
     const int64_t np = g1 - g0;
     const int64_t nb = (np + 1 + kBlock - 1) / kBlock;
     k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, lhead, qid, qa, g0, np,
                                                              lay, hrel, pbase, akey, nullptr,
-                                                             nullptr, nullptr);
+                                                             nullptr, nullptr, tile_pos);
 }
 
 void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
                           const int32_t *qid, int64_t np_cap, uint32_t *hrel, uint32_t *pbase,
                           uint64_t *akey, const WaveCtl *plan, const uint32_t *cursor,
-                          WaveCtl *ctl, hipStream_t st)
+                          WaveCtl *ctl, uint32_t *tile_pos, hipStream_t st)
 {
     const int64_t nb = (np_cap + 1 + kBlock - 1) / kBlock;
     k_wave_prep<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(hoff, qoff, lhead, qid, 0, 0, 0,
                                                              HitKeyLayout{}, hrel, pbase, akey,
-                                                             plan, cursor, ctl);
+                                                             plan, cursor, ctl, tile_pos);
 }
 
 // ------------------------------------------------------------------ S3 by sequence range
@@ -661,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     int sh_s, int sh_d, int sh_q, int bs, uint64_t *__restrict__ keys,
     const uint32_t *__restrict__ bb, const uint32_t *__restrict__ nbq,
     uint32_t *__restrict__ bcount, const uint32_t *__restrict__ boff,
-    const WaveCtl *__restrict__ ctl)
+    const WaveCtl *__restrict__ ctl, const uint32_t *__restrict__ tile_pos)
 {
     __shared__ uint32_t s_h[kGatherCap + 1];
     __shared__ uint32_t s_bin[kBinCap];
@@ -676,7 +682,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     const uint32_t t0 = blockIdx.x * (uint32_t)kTile;
     if (t0 >= nhits) return;  // a graph's grid covers the largest wave
     const uint32_t t1 = min(t0 + (uint32_t)kTile, nhits);
-    if (threadIdx.x == 0) {
+    if (MODE == 0 && tile_pos) {
+        // the preparation recorded where each tile starts: this tile's positions
+        // run from there to where the next tile starts (a bound on the last one's)
+        if (threadIdx.x == 0) {
+            s_lo = tile_pos[t0 / kTile];
+            s_hi = t1 < nhits ? (int64_t)tile_pos[t1 / kTile] : np - 1;
+        }
+    } else if (threadIdx.x == 0) {
         int64_t a = 0, b = np - 1;
         while (a < b) {
             const int64_t m = (a + b + 1) >> 1;
@@ -773,22 +786,22 @@ __global__ __launch_bounds__(kBlock) void k_gather(
 
 void launch_gather(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                    int64_t npos, const int2 *post, uint32_t nhits, HitKeyLayout lay,
-                   uint64_t *keys, hipStream_t st)
+                   uint64_t *keys, const uint32_t *tile_pos, hipStream_t st)
 {
     if (nhits == 0) return;
     const uint32_t nb = (nhits + kTile - 1) / kTile;
     k_gather<0><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
                                        lay.bp, 64, 0, keys, nullptr, nullptr, nullptr, nullptr,
-                                       nullptr);
+                                       nullptr, tile_pos);
 }
 
 void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64_t *akey,
                        const int2 *post, uint32_t hits_cap, uint64_t *keys, const WaveCtl *ctl,
-                       hipStream_t st)
+                       const uint32_t *tile_pos, hipStream_t st)
 {
     const uint32_t nb = std::max<uint32_t>(1, (hits_cap + kTile - 1) / kTile);
     k_gather<0><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, 0, post, 0, 0, 0, 64, 0, keys, nullptr,
-                                       nullptr, nullptr, nullptr, ctl);
+                                       nullptr, nullptr, nullptr, ctl, tile_pos);
 }
 
 void launch_gather_bucket(int mode, const uint32_t *hrel, const uint32_t *pbase,
@@ -802,11 +815,11 @@ void launch_gather_bucket(int mode, const uint32_t *hrel, const uint32_t *pbase,
     if (mode == 1)
         k_gather<1><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
                                            lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff,
-                                           nullptr);
+                                           nullptr, nullptr);
     else
         k_gather<2><<<nb, kBlock, 0, st>>>(hrel, pbase, akey, npos, post, nhits, lay.bp + lay.bd,
                                            lay.bp, sh_q, lay.bs, keys, bb, nbq, bcount, boff,
-                                           nullptr);
+                                           nullptr, nullptr);
 }
 
 // ------------------------------------------------------------------ S4+S5 per bucket

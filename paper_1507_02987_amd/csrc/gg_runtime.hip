@@ -110,6 +110,7 @@ struct Workspace {
     DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
     DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
     DevBuf fkept, fkoff, fflag, ford;   // lone-diagonal filter (ford: largest query first)
+    DevBuf tpos;                        // the position where each gather tile starts
     // small pinned staging: [0] a wave's counts, [1] a batch's query offsets and hit
     // totals, [2] the replayed waves' plan, overflow flags and result counts
     void *pinned[3] = {nullptr, nullptr, nullptr};
@@ -140,7 +141,7 @@ struct Workspace {
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
-                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford};
+                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -493,9 +494,11 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         launch_scan_u32(as<uint32_t>(ws->pcnt), as<uint32_t>(ws->hrel), np,
                         as<uint32_t>(ws->partials), st);
     } else {
+        TRY(ensure(ws->tpos, sizeof(uint32_t) * ((size_t)H / kTile + 2)));
         launch_wave_prep(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->lhead),
                          as<int32_t>(ws->qid), qa, g0, g1, lay, as<uint32_t>(ws->hrel),
-                         as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), st);
+                         as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey), as<uint32_t>(ws->tpos),
+                         st);
     }
     prof.end(np);
 
@@ -767,7 +770,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             const bool os = lookback && attempt == 0;
             prof.begin("gather");
             launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
-                          np, ix->d_post, H, lay, as<uint64_t>(ws->keys), st);
+                          np, ix->d_post, H, lay, as<uint64_t>(ws->keys),
+                          piece ? nullptr : as<uint32_t>(ws->tpos), st);
             prof.end(H);
             uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
             if (filt) {
@@ -1296,6 +1300,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     TRY(ensure(ws->rs_partials,
                sizeof(uint32_t) * scan_partials_needed((int64_t)ntile_cap * kRadix + 1)));
     TRY(ensure(ws->gtiles, sizeof(SortTile) * tiles_cap));
+    TRY(ensure(ws->tpos, sizeof(uint32_t) * ((size_t)hits_cap / kTile + 2)));
     TRY(ensure(ws->ccount, sizeof(uint32_t) * (ntile + 1)));
     TRY(ensure(ws->partials,
                sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nq_cap) + 1)));
@@ -1352,7 +1357,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                             &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
                             &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
                             &ws->gplan, &ws->gcursor, &ws->goflags, &ws->gtiles, &ws->fkept,
-                            &ws->fkoff, &ws->ford})
+                            &ws->fkoff, &ws->ford, &ws->tpos})
         key.push_back((uint64_t)(uintptr_t)b->p);
 
     if (!ws->gexec || ws->gkey != key) {
@@ -1365,9 +1370,10 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_wave_prep_ctl(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), as<uint32_t>(ws->lhead),
                              as<int32_t>(ws->qid), np_cap, as<uint32_t>(ws->hrel),
                              as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
-                             as<WaveCtl>(ws->gplan), cursor, ctl, st);
+                             as<WaveCtl>(ws->gplan), cursor, ctl, as<uint32_t>(ws->tpos), st);
         launch_gather_ctl(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
-                          ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl, st);
+                          ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl,
+                          as<uint32_t>(ws->tpos), st);
         if (filt) {
             launch_hit_filter(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
                               as<int64_t>(ws->qoff), 0, 0, 0, 0, as<int32_t>(ws->ford),
