@@ -321,7 +321,9 @@ void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t
 // selected-box ranges and counts capped at N (each query's boxes in its own
 // segment, selected ones first); grids of nq_cap threads (the first also zeroes
 // *clear, the extension's queue count, when given).  The _scan form also
-// writes the counts' exclusive scan (sel_off[0..nq_cap]) from one block.
+// writes the counts' exclusive scan (sel_off[0..nq_cap]) and, for the aligner,
+// the box index of every selection (sel_box[sel_off[q] + r] = qstart[q] + r),
+// from one block.
 void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uint32_t *qend,
                             uint32_t *counts, uint32_t *off, uint32_t *clear, const WaveCtl *ctl,
                             hipStream_t st);
@@ -330,7 +332,7 @@ void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap
                            hipStream_t st);
 void launch_box_ranges_scan_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
                                 uint32_t *qstart, uint32_t *qend, uint32_t *sel_off,
-                                const WaveCtl *ctl, hipStream_t st);
+                                uint32_t *sel_box, const WaveCtl *ctl, hipStream_t st);
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
                           int32_t max_hits, uint32_t *nsel, hipStream_t st,
                           const WaveCtl *ctl = nullptr);
@@ -339,7 +341,7 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
                 unsigned long long *cells_per_q, unsigned long long *cells_per_box,
-                hipStream_t st, const WaveCtl *ctl = nullptr);
+                hipStream_t st, const WaveCtl *ctl = nullptr, const uint32_t *sel_box = nullptr);
 // Results of queries [qa, qa + nq) as gg_hit records (11 int32) in device memory.
 void launch_write_out(const Align *sorted, const uint32_t *rstart, const uint32_t *rend,
                       int32_t nq, int32_t qa, int32_t cap, int32_t *out, int32_t *n_out,

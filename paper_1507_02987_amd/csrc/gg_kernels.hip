@@ -3027,6 +3027,7 @@ __global__ __launch_bounds__(kBlock) void k_box_ranges_scan(const Box *__restric
                                                             uint32_t *__restrict__ qstart,
                                                             uint32_t *__restrict__ qend,
                                                             uint32_t *__restrict__ sel_off,
+                                                            uint32_t *__restrict__ sel_box,
                                                             const WaveCtl *__restrict__ ctl)
 {
     uint32_t carry = 0;
@@ -3050,6 +3051,8 @@ __global__ __launch_bounds__(kBlock) void k_box_ranges_scan(const Box *__restric
             qstart[q] = a;
             qend[q] = b;
             sel_off[q] = carry + ex;
+            // the aligner's boxes, in selection order: the r-th is box a + r
+            for (uint32_t r = 0; r < cnt; ++r) sel_box[carry + ex + r] = a + r;
         }
         carry += tot;
     }
@@ -3066,9 +3069,10 @@ void launch_box_ranges_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap
 
 void launch_box_ranges_scan_ctl(const Box *s, const uint32_t *seg_off, int32_t nq_cap, int32_t N,
                                 uint32_t *qstart, uint32_t *qend, uint32_t *sel_off,
-                                const WaveCtl *ctl, hipStream_t st)
+                                uint32_t *sel_box, const WaveCtl *ctl, hipStream_t st)
 {
-    k_box_ranges_scan<<<1, kBlock, 0, st>>>(s, seg_off, nq_cap, N, qstart, qend, sel_off, ctl);
+    k_box_ranges_scan<<<1, kBlock, 0, st>>>(s, seg_off, nq_cap, N, qstart, qend, sel_off, sel_box,
+                                            ctl);
 }
 
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
@@ -3272,7 +3276,7 @@ __global__ __launch_bounds__(64) void k_bsw(
     const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t match,
     int32_t mismatch, int32_t o1, int32_t ext, int32_t W, Align *__restrict__ out,
     unsigned long long *__restrict__ cells_q, unsigned long long *__restrict__ cells_box,
-    const WaveCtl *__restrict__ ctl)
+    const uint32_t *__restrict__ sel_box, const WaveCtl *__restrict__ ctl)
 {
     __shared__ uint8_t s_q[kBswStage];
     __shared__ uint8_t s_d[kBswStage];
@@ -3283,14 +3287,21 @@ __global__ __launch_bounds__(64) void k_bsw(
         total = nq > 0 ? sel_off[nq] : 0;
     }
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
-    int32_t lo = 0, hi = nq - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (sel_off[mid] <= b) lo = mid;
-        else hi = mid - 1;
+    int32_t q;
+    Box bx;
+    if (sel_box) {  // the b-th selected box named directly: one load before the box
+        bx = sorted[sel_box[b]];
+        q = bx.q;
+    } else {
+        int32_t lo = 0, hi = nq - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (sel_off[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        q = lo;
+        bx = sorted[qstart[q] + (b - sel_off[q])];
     }
-    const int32_t q = lo;
-    const Box bx = sorted[qstart[q] + (b - sel_off[q])];
     const int32_t R = bx.qe - bx.qs, C = bx.de - bx.ds;
     const int32_t d0 = floor_half(bx.dmin + bx.dmax);
     const int32_t c0 = d0 - (bx.ds - bx.qs);  // cell (i, j) in band iff |j - i - c0| <= W
@@ -3370,14 +3381,14 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
                 unsigned long long *cells_per_q, unsigned long long *cells_per_box, hipStream_t st,
-                const WaveCtl *ctl)
+                const WaveCtl *ctl, const uint32_t *sel_box)
 {
     // graph form: the wave's selection count is read on the device
     const uint32_t grid = ctl ? 8 * kStrideGrid : std::min<uint32_t>(nsel_total, kMaxGrid);
     if (grid == 0) return;
     k_bsw<<<grid, 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
                                seq_start, match, mismatch, gap_open + gap_extend, gap_extend, band,
-                               out, cells_per_q, cells_per_box, ctl);
+                               out, cells_per_q, cells_per_box, sel_box, ctl);
 }
 
 // ------------------------------------------------------------------ traceback

@@ -111,6 +111,7 @@ struct Workspace {
     DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
     DevBuf fkept, fkoff, fflag, ford;   // lone-diagonal filter (ford: largest query first)
     DevBuf tpos;                        // the position where each gather tile starts
+    DevBuf selbox;                      // the box index of each selection (replayed waves)
     // small pinned staging: [0] a wave's counts, [1] a batch's query offsets and hit
     // totals, [2] the replayed waves' plan, overflow flags and result counts
     void *pinned[3] = {nullptr, nullptr, nullptr};
@@ -141,7 +142,7 @@ struct Workspace {
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
-                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos};
+                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -1314,6 +1315,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         TRY(ensure(*b, sizeof(uint32_t) * (nq_cap + 1)));
     TRY(ensure(ws->aligns, sizeof(Align) * std::max<uint32_t>(sel_cap, 1)));
     TRY(ensure(ws->aligns2, sizeof(Align) * std::max<uint32_t>(sel_cap, 1)));
+    TRY(ensure(ws->selbox, sizeof(uint32_t) * std::max<uint32_t>(sel_cap, 1)));
     TRY(ensure(ws->gout, sizeof(gg_hit) * nq_out * std::max(cap, 1)));
     TRY(ensure(ws->gn, sizeof(int32_t) * nq_out));
     TRY(ensure(ws->gctl, sizeof(WaveCtl)));
@@ -1357,7 +1359,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                             &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
                             &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
                             &ws->gplan, &ws->gcursor, &ws->goflags, &ws->gtiles, &ws->fkept,
-                            &ws->fkoff, &ws->ford, &ws->tpos})
+                            &ws->fkoff, &ws->ford, &ws->tpos, &ws->selbox})
         key.push_back((uint64_t)(uintptr_t)b->p);
 
     if (!ws->gexec || ws->gkey != key) {
@@ -1409,7 +1411,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         if (nq_cap <= 4096) {  // ranges and their scan in one launch
             launch_box_ranges_scan_ctl(as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nq_cap, N,
                                        as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend),
-                                       as<uint32_t>(ws->sel_off), ctl, st);
+                                       as<uint32_t>(ws->sel_off), as<uint32_t>(ws->selbox), ctl,
+                                       st);
         } else {
             launch_box_ranges_ctl(as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nq_cap, N,
                                   as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend),
@@ -1420,7 +1423,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_bsw(as<Box>(ws->boxes2), as<uint32_t>(ws->qstart), as<uint32_t>(ws->sel_off), 0, 0,
                    as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0, ix->d_dbw, ix->d_seq_start,
                    p->match, p->mismatch, p->gap_open, p->gap_extend, p->band,
-                   as<Align>(ws->aligns), nullptr, nullptr, st, ctl);
+                   as<Align>(ws->aligns), nullptr, nullptr, st, ctl,
+                   nq_cap <= 4096 ? as<uint32_t>(ws->selbox) : nullptr);
         launch_report_seg(as<Align>(ws->aligns), as<Align>(ws->aligns2), as<uint32_t>(ws->sel_off),
                           nq_cap, as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend), 0, cap,
                           gout, gn, st, ctl);
