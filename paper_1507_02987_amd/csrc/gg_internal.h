@@ -111,7 +111,7 @@ struct KeyWord {
 void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
                          int32_t span, uint32_t mask, const uint32_t *list_off, uint8_t *qcode,
                          uint32_t *kcode, uint32_t *cnt, uint32_t *lhead, int32_t *qid,
-                         int32_t *err, hipStream_t st);
+                         int32_t *err, int32_t *bq, hipStream_t st);
 // out[i] = sum of in[0..i) for i in [0, n]; in is u32, out u64.
 void launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *partials,
                             hipStream_t st);

@@ -301,14 +301,20 @@ __global__ __launch_bounds__(kBlock) void k_encode_kmers(
     const uint8_t *__restrict__ ascii, const int64_t *__restrict__ qoff, int32_t nq, int64_t T,
     int32_t span, uint32_t mask, const uint32_t *__restrict__ list_off, uint8_t *__restrict__ qcode,
     uint32_t *__restrict__ kcode, uint32_t *__restrict__ cnt, uint32_t *__restrict__ lhead,
-    int32_t *__restrict__ qid, int32_t *__restrict__ err)
+    int32_t *__restrict__ qid, int32_t *__restrict__ err, const int32_t *__restrict__ bq)
 {
     // the block's bases and the span after them, coded once in LDS; the block's
-    // first and last queries found once
+    // first and last queries found once (bq: the query of each block's first base,
+    // so the next block's bounds this one's last)
     __shared__ uint8_t s_c[kBlock + 32];
     __shared__ int32_t s_q[2];
     const int64_t g0 = (int64_t)blockIdx.x * kBlock;
-    if (threadIdx.x < 2) {
+    if (bq) {
+        if (threadIdx.x < 2) {
+            const bool last = g0 + kBlock >= T;
+            s_q[threadIdx.x] = threadIdx.x == 0 ? bq[blockIdx.x] : (last ? nq - 1 : bq[blockIdx.x + 1]);
+        }
+    } else if (threadIdx.x < 2) {
         const int64_t x = min(g0 + (int64_t)(threadIdx.x ? kBlock - 1 : 0), T - 1);
         int32_t lo = 0, hi = nq - 1;  // last query whose first base is <= x
         while (lo < hi) {
@@ -350,16 +356,28 @@ __global__ __launch_bounds__(kBlock) void k_encode_kmers(
     lhead[g] = head;
 }
 
+// bq[b] = the query holding base b * kBlock, for every encode block b: each
+// non-empty query writes the blocks that start inside it.
+__global__ void k_block_query(const int64_t *__restrict__ qoff, int32_t nq,
+                              int32_t *__restrict__ bq)
+{
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    for (int64_t b = (qoff[q] + kBlock - 1) / kBlock; b * kBlock < qoff[q + 1]; ++b)
+        bq[b] = q;
+}
+
 void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, int64_t T,
                          int32_t span, uint32_t mask, const uint32_t *list_off, uint8_t *qcode,
                          uint32_t *kcode, uint32_t *cnt, uint32_t *lhead, int32_t *qid,
-                         int32_t *err, hipStream_t st)
+                         int32_t *err, int32_t *bq, hipStream_t st)
 {
     if (T <= 0) return;
     const int64_t nb = (T + kBlock - 1) / kBlock;
+    if (bq) k_block_query<<<(nq + kBlock - 1) / kBlock, kBlock, 0, st>>>(qoff, nq, bq);
     k_encode_kmers<<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(ascii, qoff, nq, T, span, mask,
                                                                 list_off, qcode, kcode, cnt, lhead,
-                                                                qid, err);
+                                                                qid, err, bq);
 }
 
 // ------------------------------------------------------------------ scans

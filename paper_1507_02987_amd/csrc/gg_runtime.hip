@@ -112,6 +112,7 @@ struct Workspace {
     DevBuf fkept, fkoff, fflag, ford;   // lone-diagonal filter (ford: largest query first)
     DevBuf tpos;                        // the position where each gather tile starts
     DevBuf selbox;                      // the box index of each selection (replayed waves)
+    DevBuf bq;                          // the query of each encode block's first base
     // small pinned staging: [0] a wave's counts, [1] a batch's query offsets and hit
     // totals, [2] the replayed waves' plan, overflow flags and result counts
     void *pinned[3] = {nullptr, nullptr, nullptr};
@@ -142,7 +143,7 @@ struct Workspace {
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
-                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox};
+                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox, &bq};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -1526,6 +1527,7 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(T, nq + 1))));
     TRY(ensure(ws->qtot, sizeof(uint64_t) * nq));
     TRY(ensure(ws->err, sizeof(int32_t) * 4));
+    TRY(ensure(ws->bq, sizeof(int32_t) * ((size_t)(T + kBlock - 1) / kBlock + 1)));
     if (T > 0 && !bo.device)
         HIPCHK(hipMemcpyAsync(ws->ascii.p, qbuf + qoff[0], T, hipMemcpyHostToDevice, st));
     // staging: query offsets [nq + 1] | hit totals [nq] | error flag
@@ -1544,7 +1546,7 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     launch_encode_kmers(ascii, as<int64_t>(ws->qoff), (int32_t)nq, T, ix->span, ix->mask,
                         ix->d_list_off, as<uint8_t>(ws->qcode), as<uint32_t>(ws->kcode),
                         as<uint32_t>(ws->cnt), as<uint32_t>(ws->lhead), as<int32_t>(ws->qid),
-                        as<int32_t>(ws->err), st);
+                        as<int32_t>(ws->err), as<int32_t>(ws->bq), st);
     prof.end(T);
     prof.begin("scan");
     launch_scan_u32_to_u64(as<uint32_t>(ws->cnt), as<uint64_t>(ws->hoff), T,
