@@ -1878,17 +1878,26 @@ __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict_
             }
             __syncthreads();
             if (w == 0) {  // slab-major, wave-minor exclusive scan of the counts
-                static_assert(kFiltItems * kFiltWaves == 128, "two counts per lane");
-                const uint32_t c0 = s_cnt[2 * lane], c1 = s_cnt[2 * lane + 1];
-                uint32_t x = c0 + c1;
+                constexpr int kPer = kFiltItems * kFiltWaves / 64;  // counts per lane
+                static_assert(kPer * 64 == kFiltItems * kFiltWaves, "whole counts per lane");
+                uint32_t c[kPer], x = 0;
+#pragma unroll
+                for (int e = 0; e < kPer; ++e) {
+                    c[e] = s_cnt[kPer * lane + e];
+                    x += c[e];
+                }
+                const uint32_t mine = x;
 #pragma unroll
                 for (int o = 1; o < 64; o <<= 1) {
                     const uint32_t y = __shfl_up(x, o, 64);
                     if ((int)lane >= o) x += y;
                 }
-                const uint32_t ex = x - c0 - c1;
-                s_pre[2 * lane] = ex;
-                s_pre[2 * lane + 1] = ex + c0;
+                uint32_t run = x - mine;
+#pragma unroll
+                for (int e = 0; e < kPer; ++e) {
+                    s_pre[kPer * lane + e] = run;
+                    run += c[e];
+                }
                 if (lane == 63) s_tot = x;
             }
             __syncthreads();
