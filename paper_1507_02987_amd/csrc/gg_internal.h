@@ -310,6 +310,10 @@ void launch_gather_boxes(const Box *in, const uint32_t *perm, uint32_t n, Box *o
                          hipStream_t st);
 void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Align *out,
                           hipStream_t st);
+// A replayed wave's merge (sort, sweep) and selection sort of each query's boxes
+// in one launch (in -> out, per-query segments seg_off; overflow as the LDS sorts).
+void launch_merge_select_seg(const Box *in, Box *out, const uint32_t *seg_off, int32_t nq_cap,
+                             WaveCtl *ctl, hipStream_t st);
 void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st,
                         const WaveCtl *ctl = nullptr);
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,

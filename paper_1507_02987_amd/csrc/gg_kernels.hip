@@ -2618,6 +2618,78 @@ void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_
     else k_seg_sort_box<1><<<nq, kBlock, 0, st>>>(in, out, seg_off, ctl);
 }
 
+// A replayed wave's merge and selection order for one query in one block: its
+// boxes sorted by merge order (s, qs, ds, qe, de) in LDS and put in that order,
+// each sequence's group swept in place as k_merge_sweep does (merged boxes from
+// the group's start, the rest marked empty), then sorted by selection order and
+// written out.  The same three steps as k_seg_sort_box<0>, k_merge_sweep and
+// k_seg_sort_box<1>, with the boxes kept in LDS between them.
+__global__ __launch_bounds__(kBlock) void k_merge_select_seg(const Box *__restrict__ in,
+                                                             Box *__restrict__ out,
+                                                             const uint32_t *__restrict__ seg_off,
+                                                             WaveCtl *__restrict__ ctl)
+{
+    __shared__ Box s_r[kSegCap];
+    __shared__ uint16_t s_ix[kSegCap];
+    if ((int32_t)blockIdx.x >= ctl->nqw) return;
+    const uint32_t a0 = seg_off[blockIdx.x], n = seg_off[blockIdx.x + 1] - a0;
+    if (n > (uint32_t)kSegCap) {
+        if (threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
+        return;
+    }
+    if (n == 0) return;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_r[i] = in[a0 + i];
+    lds_bitonic(s_r, s_ix, n, BoxLess<0>());  // starts and ends with a barrier
+    constexpr int kPer = kSegCap / kBlock;
+    Box tmp[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = threadIdx.x + k * kBlock;
+        if (i < n) tmp[k] = s_r[s_ix[i]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = threadIdx.x + k * kBlock;
+        if (i < n) s_r[i] = tmp[k];
+    }
+    __syncthreads();
+    // the thread at each group's first box sweeps it; a group's first slot always
+    // keeps a box of that sequence, so a neighbour's end test reads a valid s
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        if (i > 0 && s_r[i - 1].s == s_r[i].s) continue;
+        Box cur = s_r[i];
+        const int32_t sq = cur.s;
+        uint32_t w = i, j = i + 1;
+        for (; j < n; ++j) {
+            const Box h = s_r[j];
+            if (h.s != sq) break;
+            if (h.qs < cur.qe && h.ds < cur.de && cur.ds < h.de) {
+                cur.qs = min(cur.qs, h.qs);
+                cur.qe = max(cur.qe, h.qe);
+                cur.ds = min(cur.ds, h.ds);
+                cur.de = max(cur.de, h.de);
+                cur.dmin = min(cur.dmin, h.dmin);
+                cur.dmax = max(cur.dmax, h.dmax);
+            } else {
+                s_r[w++] = cur;
+                cur = h;
+            }
+        }
+        s_r[w++] = cur;
+        for (; w < j; ++w) s_r[w].q = -1;
+    }
+    __syncthreads();
+    lds_bitonic(s_r, s_ix, n, BoxLess<1>());
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[a0 + i] = s_r[s_ix[i]];
+}
+
+void launch_merge_select_seg(const Box *in, Box *out, const uint32_t *seg_off, int32_t nq_cap,
+                             WaveCtl *ctl, hipStream_t st)
+{
+    if (nq_cap > 0) k_merge_select_seg<<<nq_cap, kBlock, 0, st>>>(in, out, seg_off, ctl);
+}
+
 // Report order: alignments with score > 0 first, score descending, then seq,
 // q_start, d_start, q_end, d_end and the box.
 struct AlignLess {

@@ -1404,11 +1404,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                       ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop,
                       as<Box>(ws->boxes), ws->xqueue.p, steps, st, ctl, hits_cap,
                       /*count_cleared=*/true);
-        launch_seg_sort_box(0, as<Box>(ws->boxes), as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off),
-                            nq_cap, st, ctl);
-        launch_merge_sweep(as<Box>(ws->boxes2), 0, as<Box>(ws->boxes3), st, ctl);
-        launch_seg_sort_box(1, as<Box>(ws->boxes3), as<Box>(ws->boxes2),
-                            as<uint32_t>(ws->cand_off), nq_cap, st, ctl);
+        launch_merge_select_seg(as<Box>(ws->boxes), as<Box>(ws->boxes2),
+                                as<uint32_t>(ws->cand_off), nq_cap, ctl, st);
         if (nq_cap <= 4096) {  // ranges and their scan in one launch
             launch_box_ranges_scan_ctl(as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nq_cap, N,
                                        as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend),
