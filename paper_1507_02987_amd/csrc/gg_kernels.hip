@@ -3119,18 +3119,19 @@ void launch_cand_ranges_ctl(const Cand *c, int32_t nq_cap, uint32_t *qstart, uin
 }
 
 // The same ranges, with the exclusive scan of the capped counts (sel_off[0..nq_cap],
-// total last) in the same launch: one block walks the queries kBlock at a time.
-__global__ __launch_bounds__(kBlock) void k_box_ranges_scan(const Box *__restrict__ s,
-                                                            const uint32_t *__restrict__ seg_off,
-                                                            int32_t nq_cap, int32_t N,
-                                                            uint32_t *__restrict__ qstart,
-                                                            uint32_t *__restrict__ qend,
-                                                            uint32_t *__restrict__ sel_off,
-                                                            uint32_t *__restrict__ sel_box,
-                                                            const WaveCtl *__restrict__ ctl)
+// total last) in the same launch: one block of kRangeBlock threads, a query per
+// thread (looping when there are more), so the segments' searches run side by side.
+constexpr int kRangeBlock = 1024;
+
+__global__ __launch_bounds__(kRangeBlock) void k_box_ranges_scan(
+    const Box *__restrict__ s, const uint32_t *__restrict__ seg_off, int32_t nq_cap, int32_t N,
+    uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend, uint32_t *__restrict__ sel_off,
+    uint32_t *__restrict__ sel_box, const WaveCtl *__restrict__ ctl)
 {
+    __shared__ uint32_t s_w[kRangeBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t carry = 0;
-    for (int32_t q0 = 0; q0 < nq_cap; q0 += kBlock) {
+    for (int32_t q0 = 0; q0 < nq_cap; q0 += kRangeBlock) {
         const int32_t q = q0 + (int32_t)threadIdx.x;
         uint32_t a = 0, b = 0;
         if (q < nq_cap && q < ctl->nqw && !ctl->overflow) {
@@ -3144,14 +3145,29 @@ __global__ __launch_bounds__(kBlock) void k_box_ranges_scan(const Box *__restric
             b = lo;
         }
         const uint32_t cnt = (N > 0 && b - a > (uint32_t)N) ? (uint32_t)N : b - a;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<uint32_t>(cnt, &tot);
+        uint32_t x = cnt;  // block-wide exclusive scan of cnt
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < kRangeBlock / 64; ++i) {
+            const uint32_t t = s_w[i];
+            if (i < w) before += t;
+            tot += t;
+        }
+        __syncthreads();
+        const uint32_t ex = carry + before + x - cnt;
         if (q < nq_cap) {
             qstart[q] = a;
             qend[q] = b;
-            sel_off[q] = carry + ex;
+            sel_off[q] = ex;
             // the aligner's boxes, in selection order: the r-th is box a + r
-            for (uint32_t r = 0; r < cnt; ++r) sel_box[carry + ex + r] = a + r;
+            for (uint32_t r = 0; r < cnt; ++r) sel_box[ex + r] = a + r;
         }
         carry += tot;
     }
@@ -3170,8 +3186,8 @@ void launch_box_ranges_scan_ctl(const Box *s, const uint32_t *seg_off, int32_t n
                                 uint32_t *qstart, uint32_t *qend, uint32_t *sel_off,
                                 uint32_t *sel_box, const WaveCtl *ctl, hipStream_t st)
 {
-    k_box_ranges_scan<<<1, kBlock, 0, st>>>(s, seg_off, nq_cap, N, qstart, qend, sel_off, sel_box,
-                                            ctl);
+    k_box_ranges_scan<<<1, kRangeBlock, 0, st>>>(s, seg_off, nq_cap, N, qstart, qend, sel_off,
+                                                 sel_box, ctl);
 }
 
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
