@@ -110,8 +110,8 @@ def serve_leg(gix, db, prm, rate: float, n: int) -> dict:
     served results are checked against the one-query form."""
     import threading
 
-    qs = synth.config4_queries(db, n=n)
-    arr = synth.config4_arrivals(rate, n)
+    qs = synth.large_served_queries(db, n=n)
+    arr = synth.served_arrivals(rate, n)
     want = {}
     for i in range(min(32, n)):
         rc, h, _ = gix.search(qs.query(i), prm, cap=CAP)
@@ -195,25 +195,27 @@ def main() -> int:
         return 0
     t = time.perf_counter()
     if args.workload == "mid":
-        cfg, db = 1, synth.config1_db()
-        qs = synth.config1_queries(db, n=args.queries or 1000)
-        desc = "config1: 200,000-seq bank (~275 Mbp), 1,000 queries 80-10,000 bp, k=11, top 50"
+        cfg, db = 1, synth.mid_db()
+        qs = synth.mid_queries(db, n=args.queries or 1000)
+        desc = "mid-size: 200,000-seq bank (~275 Mbp), 1,000 queries 80-10,000 bp, k=11, top 50"
     else:
-        db = synth.config2_db()
+        db = synth.large_db()
         if args.workload == "large-batched":
-            cfg, qs = 3, synth.config3_queries(db, n=args.queries or 100_000)
-            desc = ("config3: 500,000-seq bank (~3 Gbp, repeats), 100,000 queries 100-250 bp, "
+            cfg, qs = 3, synth.large_short_queries(db, n=args.queries or 100_000)
+            desc = ("large bank, short queries: 500,000-seq bank (~3 Gbp, repeats), 100,000 "
+                    "queries 100-250 bp, "
                     "k=11, top 20")
         else:
-            cfg, qs = 4, synth.config4_queries(db, n=args.queries or 2000)
-            desc = ("config4: 500,000-seq bank (~3 Gbp, repeats), queries 50-20,000 bp, k=11, "
+            cfg, qs = 4, synth.large_served_queries(db, n=args.queries or 2000)
+            desc = ("large bank, served: 500,000-seq bank (~3 Gbp, repeats), queries 50-20,000 "
+                    "bp, k=11, "
                     "top 50, served at 50/200/1,000 per s")
     if args.queries:
         desc = desc.replace(f"{qs.n:,}", str(qs.n))
-    workload = f"config{cfg}"
+    workload = {1: "mid", 3: "large_short", 4: "large_served"}[cfg]
     log(f"workload: {db.n_seqs} seqs, {db.total_bp / 1e6:.1f} Mbp, {qs.n} queries, "
         f"{qs.lengths().sum()} query bp ({time.perf_counter() - t:.1f} s)")
-    max_hits = synth.CONFIG_TOP_N[cfg]
+    max_hits = synth.TOP_N[cfg]
     prm = gg.params(max_hits)
 
     t = time.perf_counter()

@@ -9,7 +9,7 @@ This module only draws random bytes.  It holds none of the search method's
 arithmetic: no base coding, no k-mers, no scoring.  The oracle tests and the GPU
 path both consume what it returns, so it imports nothing from either of them.
 
-Everything is a pure function of ``ROOT_SEED`` and the config id, through
+Everything is a pure function of ``ROOT_SEED`` and the workload's stream id, through
 ``numpy.random.Generator(PCG64(SeedSequence(ROOT_SEED)))`` children.
 """
 from __future__ import annotations
@@ -86,9 +86,9 @@ class QuerySet:
 # --------------------------------------------------------------------------- streams
 
 def _streams(cfg_id: int):
-    """Independent generators for (data bank, queries, arrivals) of one config.
+    """Independent generators for (data bank, queries, arrivals) of one workload.
 
-    Configs 3 and 4 search the config-2 data bank, so they take its stream.
+    The short-query and served sets search the large bank, so they take its stream.
     """
     root = np.random.SeedSequence(ROOT_SEED)
     per_cfg = root.spawn(5)
@@ -235,16 +235,16 @@ def _queries(rng, db: Database, lengths: np.ndarray, homolog: np.ndarray, ident:
                     np.array(src_end, np.int64), np.where(homolog, ident, 0.0))
 
 
-# --------------------------------------------------------------------------- config 0
+# --------------------------------------------------------------------------- small (stream 0)
 
-def config0_db(n_seqs: int = 2000) -> Database:
+def small_db(n_seqs: int = 2000) -> Database:
     """2,000 sequences, lengths uniform 200..2,000, i.i.d. uniform ACGT (about 2.2 Mbp)."""
     rng, _, _ = _streams(0)
     lengths = rng.integers(200, 2001, size=n_seqs).astype(np.int64)
-    return Database(_uniform_bases(rng, int(lengths.sum())), _offsets(lengths), "config0")
+    return Database(_uniform_bases(rng, int(lengths.sum())), _offsets(lengths), "small")
 
 
-def config0_queries(db: Database, n_homolog: int = 10, n_random: int = 10, L: int = 500) -> QuerySet:
+def small_queries(db: Database, n_homolog: int = 10, n_random: int = 10, L: int = 500) -> QuerySet:
     """Ten 500 bp data-bank regions with 5% substitutions and 1% indels, then ten
     uniform random 500 bp queries."""
     _, rng, _ = _streams(0)
@@ -254,19 +254,19 @@ def config0_queries(db: Database, n_homolog: int = 10, n_random: int = 10, L: in
     return _queries(rng, db, np.full(n, L, np.int64), homolog, ident, 0.01)
 
 
-# --------------------------------------------------------------------------- config 1
+# --------------------------------------------------------------------------- mid-size (stream 1)
 
-def config1_db(n_seqs: int = 200_000) -> Database:
+def mid_db(n_seqs: int = 200_000) -> Database:
     """Lengths clip(round(LogNormal(ln 1000, 0.8)), 100, 50,000); per-sequence GC
     fraction uniform in 0.35..0.65 (about 275 Mbp at 200,000 sequences)."""
     rng, _, _ = _streams(1)
     lengths = np.clip(np.rint(rng.lognormal(math.log(1000.0), 0.8, size=n_seqs)), 100, 50_000)
     lengths = lengths.astype(np.int64)
     gc = rng.uniform(0.35, 0.65, size=n_seqs)
-    return Database(_gc_bases(rng, lengths, gc), _offsets(lengths), "config1")
+    return Database(_gc_bases(rng, lengths, gc), _offsets(lengths), "mid")
 
 
-def config1_queries(db: Database, n: int = 1000, lmin: int = 80, lmax: int = 10_000) -> QuerySet:
+def mid_queries(db: Database, n: int = 1000, lmin: int = 80, lmax: int = 10_000) -> QuerySet:
     """Lengths log-uniform 80..10,000; half planted homologs at identity uniform in
     0.70..0.99 plus 1% indels, half uniform random, in a seeded shuffled order."""
     _, rng, _ = _streams(1)
@@ -278,11 +278,11 @@ def config1_queries(db: Database, n: int = 1000, lmin: int = 80, lmax: int = 10_
     return _queries(rng, db, lengths, homolog, ident, 0.01)
 
 
-# --------------------------------------------------------------------------- config 2
+# --------------------------------------------------------------------------- large bank (stream 2)
 
-def config2_db(n_seqs: int = 500_000, chunk_seqs: int = 25_000) -> Database:
+def large_db(n_seqs: int = 500_000, chunk_seqs: int = 25_000) -> Database:
     """Lengths clip(round(LogNormal(ln 4000, 0.9)), 100, 200,000) (about 3 Gbp at
-    500,000 sequences), per-sequence GC as config 1, then two repeat overlays:
+    500,000 sequences), per-sequence GC as the mid-size bank, then two repeat overlays:
 
     * interspersed repeats: 50 random 300 bp family consensi; each sequence of
       length n gets floor(0.05 n / 300) copies plus one more with probability of the
@@ -336,10 +336,10 @@ def config2_db(n_seqs: int = 500_000, chunk_seqs: int = 25_000) -> Database:
         t = np.arange(len(rid)) - rfirst[rid]
         letters = unit[rid, t % period[rid]]
         seqs[off[owner][rid] + start[rid] + t] = ASCII[letters]
-    return Database(seqs, off, "config2")
+    return Database(seqs, off, "large")
 
 
-def config2_queries(db: Database, n: int = 2000) -> QuerySet:
+def large_queries(db: Database, n: int = 2000) -> QuerySet:
     """Lengths log-uniform 500..5,000; half planted homologs at identity uniform in
     0.75..0.99 plus 1% indels, half uniform random."""
     _, rng, _ = _streams(2)
@@ -351,9 +351,9 @@ def config2_queries(db: Database, n: int = 2000) -> QuerySet:
     return _queries(rng, db, lengths, homolog, ident, 0.01)
 
 
-# --------------------------------------------------------------------------- config 3
+# --------------------------------------------------------------------------- large bank, short queries (stream 3)
 
-def config3_queries(db: Database, n: int = 100_000) -> QuerySet:
+def large_short_queries(db: Database, n: int = 100_000) -> QuerySet:
     """Lengths uniform 100..250; 80% data-bank regions with 1..3% substitutions and
     no indels, 20% uniform random."""
     _, rng, _ = _streams(3)
@@ -363,9 +363,9 @@ def config3_queries(db: Database, n: int = 100_000) -> QuerySet:
     return _queries(rng, db, lengths, homolog, ident, 0.0)
 
 
-# --------------------------------------------------------------------------- config 4
+# --------------------------------------------------------------------------- large bank, served (stream 4)
 
-def config4_queries(db: Database, n: int = 2000) -> QuerySet:
+def large_served_queries(db: Database, n: int = 2000) -> QuerySet:
     """Lengths log-uniform 50..20,000; 60% planted homologs at identity uniform in
     0.75..0.99 plus 1% indels, 40% uniform random."""
     _, rng, _ = _streams(4)
@@ -375,9 +375,9 @@ def config4_queries(db: Database, n: int = 2000) -> QuerySet:
     return _queries(rng, db, lengths, homolog, ident, 0.01)
 
 
-def config4_arrivals(rate_per_s: float, n: int = 2000) -> np.ndarray:
+def served_arrivals(rate_per_s: float, n: int = 2000) -> np.ndarray:
     """Open-loop Poisson arrival times (seconds from 0) at the given rate; each rate
-    has its own child of the config-4 arrivals stream."""
+    has its own child of the served set's arrivals stream."""
     ss = np.random.SeedSequence(ROOT_SEED).spawn(5)[4].spawn(3)[2]
     child = np.random.SeedSequence(ss.entropy, spawn_key=ss.spawn_key + (int(rate_per_s),))
     rng = np.random.Generator(np.random.PCG64(child))
@@ -422,4 +422,4 @@ def random_queries(seed: int, db: Database, n: int, lmin: int, lmax: int, frac_h
     return _queries(rng, db, lengths, homolog, ident, indel_rate)
 
 
-CONFIG_TOP_N = {0: 20, 1: 50, 2: 100, 3: 20, 4: 50}
+TOP_N = {0: 20, 1: 50, 2: 100, 3: 20, 4: 50}

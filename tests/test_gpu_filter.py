@@ -65,8 +65,8 @@ def test_filter_on_and_off_on_the_bank_workload(ggo, monkeypatch):
     G = gpu()
     monkeypatch.setenv("GG_GROUPING", "sort")
     monkeypatch.delenv("GG_GRAPH", raising=False)
-    db = synth.config1_db(n_seqs=20_000)
-    qs = synth.config1_queries(db, n=80)
+    db = synth.mid_db(n_seqs=20_000)
+    qs = synth.mid_queries(db, n=80)
     oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
     want, wst = oracle_all(oix, qs, ggo.params(50))
     prm = G.params(50)

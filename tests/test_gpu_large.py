@@ -34,7 +34,7 @@ def large(ggo):
 
     gg.lib()  # fails loudly when the library is not built
     note("drawing the bank")
-    db = synth.config2_db()
+    db = synth.large_db()
     note(f"bank: {db.n_seqs} sequences, {db.total_bp} bp; building the GPU index")
     gix = gg.Index(db.seqs, db.off, 11)
     note("building the oracle index")
@@ -71,7 +71,7 @@ def check_sampled(ggo, oix, qs, got, st, pick, top_n, cap):
 def test_long_queries_top100(ggo, large):
     """2,000 queries of 500-5,000 bp, half planted homologs at 75-99% identity."""
     G, db, gix, oix = large
-    qs = synth.config2_queries(db)
+    qs = synth.large_queries(db)
     note(f"{qs.n} long queries on the GPU")
     rc, got, n, st = gix.search_batch(qs.buf, qs.off, G.params(100), cap=100, stats=True)
     assert rc == 0
@@ -85,7 +85,7 @@ def test_short_queries_one_batch(ggo, large):
     batched call, top 20, against the oracle on a sample and against the
     one-query path on a smaller sample."""
     G, db, gix, oix = large
-    qs = synth.config3_queries(db).subset(np.arange(20_000))
+    qs = synth.large_short_queries(db).subset(np.arange(20_000))
     prm = G.params(20)
     note(f"{qs.n} short queries on the GPU")
     rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=20, stats=True)
@@ -109,7 +109,7 @@ def test_served_mixed_lengths(ggo, large):
     slots, under a 16 GB hit-buffer budget); each result equals the query searched
     alone, the batched form and, on a sample, the oracle."""
     G, db, gix, oix = large
-    qs = synth.config4_queries(db).subset(np.arange(300))
+    qs = synth.large_served_queries(db).subset(np.arange(300))
     prm = G.params(50)
     note(f"{qs.n} mixed queries one at a time")
     alone = [gix.search(qs.query(i), prm, cap=50) for i in range(qs.n)]
@@ -134,7 +134,7 @@ def test_served_set_over_budget_query(large):
     searched by ranges of sequences and equals the same query run in one piece
     under a budget big enough for it."""
     G, db, gix, oix = large
-    qs = synth.config4_queries(db)
+    qs = synth.large_served_queries(db)
     prm = G.params(50)
     gix.set_hit_budget(16_000_000_000)
     try:

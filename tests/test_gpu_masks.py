@@ -120,7 +120,7 @@ def test_masked_graph_and_served_forms(ggo, monkeypatch):
 
 def test_masked_exact_copy_and_edges(ggo):
     G = gpu()
-    db = synth.config0_db(n_seqs=200)
+    db = synth.small_db(n_seqs=200)
     gix = G.Index(db.seqs, db.off, mask=PAPER_MASK)
     oix = ggo.Index(db.seqs, db.off, mask=PAPER_MASK)
     src = next(s for s in range(db.n_seqs) if len(db.seq(s)) >= 700)
@@ -150,8 +150,8 @@ def test_paper_mask_on_the_bank_workload(ggo, monkeypatch, grouping):
     and with a hit budget that cuts the largest queries into sequence ranges."""
     G = gpu()
     monkeypatch.setenv("GG_GROUPING", grouping)
-    db = synth.config1_db(n_seqs=20_000)
-    qs = synth.config1_queries(db, n=60)
+    db = synth.mid_db(n_seqs=20_000)
+    qs = synth.mid_queries(db, n=60)
     oix = ggo.Index(db.seqs, db.off, mask=PAPER_MASK)
     gix = G.Index(db.seqs, db.off, mask=PAPER_MASK)
     for kw in (dict(), dict(max_gap=54, min_hsp_len=36)):

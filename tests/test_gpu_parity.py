@@ -45,12 +45,12 @@ def check_batch(G, gix, qs, prm_g, want, want_stats, cap=100000):
 @pytest.fixture(scope="module")
 def c0(ggo):
     G = gpu()
-    db = synth.config0_db()
-    qs = synth.config0_queries(db)
+    db = synth.small_db()
+    qs = synth.small_queries(db)
     return G, db, qs, G.Index(db.seqs, db.off, 11), ggo.Index(db.seqs, db.off, 11)
 
 
-def test_config0_batch_and_single(ggo, c0):
+def test_small_batch_and_single(ggo, c0):
     G, db, qs, gix, oix = c0
     want, wst = oracle_all(ggo, oix, qs, ggo.params(20))
     check_batch(G, gix, qs, G.params(20), want, wst)
@@ -95,8 +95,8 @@ def test_waves_under_small_budget(ggo, monkeypatch):
     must not change.  Only a single sequence over the budget is refused."""
     G = gpu()
     monkeypatch.setenv("GG_GROUPING", "sort")
-    db = synth.config1_db(n_seqs=20_000)
-    qs = synth.config1_queries(db, n=60)
+    db = synth.mid_db(n_seqs=20_000)
+    qs = synth.mid_queries(db, n=60)
     oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
     want, wst = oracle_all(ggo, oix, qs, ggo.params(50))
     check_batch(G, gix, qs, G.params(50), want, wst)
@@ -201,12 +201,12 @@ def test_server_matches_plain(c0):
 
 
 @pytest.mark.slow
-def test_config1_full_bank_sampled(ggo):
+def test_mid_full_bank_sampled(ggo):
     """The full 200,000-sequence bank and all 1,000 queries in one batched call (the
     benchmark's configuration); 60 sampled queries are checked against the oracle."""
     G = gpu()
-    db = synth.config1_db()
-    qs = synth.config1_queries(db)
+    db = synth.mid_db()
+    qs = synth.mid_queries(db)
     gix = G.Index(db.seqs, db.off, 11)
     rc, got, n, st = gix.search_batch(qs.buf, qs.off, G.params(50), cap=200, stats=True)
     assert rc == 0
@@ -266,8 +266,8 @@ def test_autotune_and_lane_steps(ggo, monkeypatch):
     oracle."""
     G = gpu()
     monkeypatch.delenv("GG_GROUPING", raising=False)
-    db = synth.config1_db(n_seqs=20_000)
-    qs = synth.config1_queries(db, n=80)
+    db = synth.mid_db(n_seqs=20_000)
+    qs = synth.mid_queries(db, n=80)
     oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
     want, wst = oracle_all(ggo, oix, qs, ggo.params(50))
     assert gix.tuning() == {"grouping": "sort", "lane_steps": 64}

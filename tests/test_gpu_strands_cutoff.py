@@ -134,8 +134,8 @@ def test_options_on_the_bank_workload(ggo, monkeypatch):
     G = gpu()
     monkeypatch.setenv("GG_GROUPING", "sort")
     monkeypatch.delenv("GG_GRAPH", raising=False)
-    db = synth.config1_db(n_seqs=20_000)
-    qs = flip_half(synth.config1_queries(db, n=60))
+    db = synth.mid_db(n_seqs=20_000)
+    qs = flip_half(synth.mid_queries(db, n=60))
     kw = dict(strands=2, max_posting=40)
     oix, gix = ggo.Index(db.seqs, db.off, 11, **kw), G.Index(db.seqs, db.off, 11, **kw)
     want, wst = oracle_all(oix, qs, ggo.params(50))

@@ -82,8 +82,8 @@ def test_long_alignments(ggo):
 
 def test_traceback_errors(ggo):
     G = gpu()
-    db = synth.config0_db(n_seqs=200)
-    qs = synth.config0_queries(db)
+    db = synth.small_db(n_seqs=200)
+    qs = synth.small_queries(db)
     gix = G.Index(db.seqs, db.off, 11)
     q = bytes(qs.query(0))
     prm = G.params(5)

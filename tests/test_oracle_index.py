@@ -65,8 +65,8 @@ def test_index_equals_brute_force(ggo, k, seed):
         assert got == want.get(c, []), c
 
 
-def test_index_invariants_config0(ggo):
-    db = synth.config0_db()
+def test_index_invariants_small(ggo):
+    db = synth.small_db()
     k = 11
     ix = ggo.Index(db.seqs, db.off, k)
     off = ix.list_off()

@@ -82,7 +82,7 @@ def test_masked_hits_brute_force(ggo, mask):
 
 
 def test_masked_exact_copy_found_whole(ggo):
-    db = synth.config0_db(n_seqs=200)
+    db = synth.small_db(n_seqs=200)
     ix = ggo.Index(db.seqs, db.off, mask=GOLD["paper_mask"])
     src = next(s for s in range(db.n_seqs) if len(db.seq(s)) >= 700)
     q = bytes(db.seq(src)[100:700])

@@ -16,8 +16,8 @@ from paper_1507_02987_amd import synth
 
 @pytest.fixture(scope="module")
 def c0(ggo):
-    db = synth.config0_db()
-    q = synth.config0_queries(db)
+    db = synth.small_db()
+    q = synth.small_queries(db)
     return db, q, ggo.Index(db.seqs, db.off, 11)
 
 

@@ -54,7 +54,7 @@ def test_both_strand_index_is_the_bank_plus_reverse_complements(ggo, k, mask):
 
 
 def test_reverse_complement_query_found_on_the_reverse_strand(ggo):
-    db = synth.config0_db(n_seqs=200)
+    db = synth.small_db(n_seqs=200)
     n = db.n_seqs
     ix2 = ggo.Index(db.seqs, db.off, 11, strands=2)
     ix1 = ggo.Index(db.seqs, db.off, 11)

@@ -110,8 +110,8 @@ def test_hand_worked_paths(ggo):
 
 
 def test_not_an_alignment_is_refused(ggo):
-    db = synth.config0_db(n_seqs=100)
-    qs = synth.config0_queries(db)
+    db = synth.small_db(n_seqs=100)
+    qs = synth.small_queries(db)
     ix = ggo.Index(db.seqs, db.off, 11)
     prm = ggo.params(5)
     q = bytes(qs.query(0))
