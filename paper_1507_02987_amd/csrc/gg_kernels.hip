@@ -2770,21 +2770,35 @@ void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int
 }
 
 // ------------------------------------------------------------------ S7: merge overlaps
-// Boxes sorted by (q, s, qs, ds, qe, de).  The thread at the start of each (q, s)
-// group sweeps it once, merging the next box into the open one when both their
-// query and data-bank intervals intersect; the merged boxes are written from the
-// group's start and its remaining slots are marked empty (q = -1).
+// Boxes sorted by (q, s, qs, ds, qe, de).  Each (q, s) group is swept once by one
+// thread, merging the next box into the open one when both their query and
+// data-bank intervals intersect; the merged boxes are written from the group's
+// start and its remaining slots are marked empty (q = -1).  Each thread owns a
+// chunk of kSweepChunk consecutive boxes and sweeps every group that starts in it
+// (a group may run on past the chunk), so all lanes have work however the groups
+// fall; the boxes before the chunk's first group start belong to a group owned by
+// an earlier chunk.
+constexpr uint32_t kSweepChunk = 32;
+
 __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__restrict__ out,
                               const WaveCtl *__restrict__ ctl)
 {
     if (ctl) n = ctl->overflow ? 0 : ctl->nc;  // an overflowed wave is run again later
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += gridDim.x * blockDim.x) {
-    const Box first = s[i];
+    const uint32_t nchunk = (n + kSweepChunk - 1) / kSweepChunk;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nchunk;
+         c += gridDim.x * blockDim.x) {
+    const uint32_t lo = c * kSweepChunk, hi = min(lo + kSweepChunk, n);
+    uint32_t i = lo;
     if (i > 0) {
         const Box p = s[i - 1];
-        if (p.q == first.q && p.s == first.s) continue;
+        while (i < hi) {
+            const Box b = s[i];
+            if (b.q != p.q || b.s != p.s) break;
+            ++i;
+        }
     }
+    while (i < hi) {  // i starts a group
+    const Box first = s[i];
     Box cur = first;
     uint32_t w = i, j = i + 1;
     bool open = true;
@@ -2818,6 +2832,8 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
     }
     out[w++] = cur;
     for (; w < j; ++w) out[w].q = -1;
+    i = j;  // the next group starts where this one ended
+    }
     }
 }
 
@@ -2827,8 +2843,9 @@ void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st,
     if (ctl)
         k_merge_sweep<<<kStrideGrid, kBlock, 0, st>>>(sorted, 0, out, ctl);
     else if (n)
-        k_merge_sweep<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
-            sorted, n, out, nullptr);
+        k_merge_sweep<<<std::min<uint32_t>((n + kSweepChunk * kBlock - 1) / (kSweepChunk * kBlock),
+                                           kMaxGrid),
+                        kBlock, 0, st>>>(sorted, n, out, nullptr);
 }
 
 // ------------------------------------------------------------------ S8: select
