@@ -2774,20 +2774,20 @@ void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int
 // thread, merging the next box into the open one when both their query and
 // data-bank intervals intersect; the merged boxes are written from the group's
 // start and its remaining slots are marked empty (q = -1).  Each thread owns a
-// chunk of kSweepChunk consecutive boxes and sweeps every group that starts in it
-// (a group may run on past the chunk), so all lanes have work however the groups
-// fall; the boxes before the chunk's first group start belong to a group owned by
-// an earlier chunk.
+// chunk of `chunk` consecutive boxes (up to kSweepChunk, fewer when there are few
+// boxes, down to one per thread) and sweeps every group that starts in it (a group
+// may run on past the chunk), so all lanes have work however the groups fall; the
+// boxes before the chunk's first group start belong to an earlier chunk's group.
 constexpr uint32_t kSweepChunk = 32;
 
 __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__restrict__ out,
-                              const WaveCtl *__restrict__ ctl)
+                              uint32_t chunk, const WaveCtl *__restrict__ ctl)
 {
     if (ctl) n = ctl->overflow ? 0 : ctl->nc;  // an overflowed wave is run again later
-    const uint32_t nchunk = (n + kSweepChunk - 1) / kSweepChunk;
+    const uint32_t nchunk = (n + chunk - 1) / chunk;
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nchunk;
          c += gridDim.x * blockDim.x) {
-    const uint32_t lo = c * kSweepChunk, hi = min(lo + kSweepChunk, n);
+    const uint32_t lo = c * chunk, hi = min(lo + chunk, n);
     uint32_t i = lo;
     if (i > 0) {
         const Box p = s[i - 1];
@@ -2840,12 +2840,15 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
 void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st,
                         const WaveCtl *ctl)
 {
-    if (ctl)
-        k_merge_sweep<<<kStrideGrid, kBlock, 0, st>>>(sorted, 0, out, ctl);
-    else if (n)
-        k_merge_sweep<<<std::min<uint32_t>((n + kSweepChunk * kBlock - 1) / (kSweepChunk * kBlock),
-                                           kMaxGrid),
-                        kBlock, 0, st>>>(sorted, n, out, nullptr);
+    if (ctl) {
+        k_merge_sweep<<<kStrideGrid, kBlock, 0, st>>>(sorted, 0, out, 1, ctl);
+    } else if (n) {
+        // about half a million threads fill the chip; longer chunks only past that
+        const uint32_t chunk = std::max<uint32_t>(1, std::min<uint32_t>(kSweepChunk, n >> 19));
+        const uint32_t threads = (n + chunk - 1) / chunk;
+        k_merge_sweep<<<std::min<uint32_t>((threads + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0,
+                        st>>>(sorted, n, out, chunk, nullptr);
+    }
 }
 
 // ------------------------------------------------------------------ S8: select
