@@ -290,7 +290,7 @@ void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t 
 // Per-query LDS sorts (segments of at most kSegCap records; longer ones are skipped).
 // mode 0: merge order, mode 1: selection order.
 void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_off, int32_t nq,
-                         hipStream_t st, WaveCtl *ctl = nullptr);
+                         hipStream_t st);
 void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int32_t nq,
                        uint32_t *rstart, uint32_t *rend, int32_t qa, int32_t cap, int32_t *dev_out,
                        int32_t *dev_n, hipStream_t st, WaveCtl *ctl = nullptr);
@@ -314,10 +314,9 @@ void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Ali
 // in one launch (in -> out, per-query segments seg_off; overflow as the LDS sorts).
 void launch_merge_select_seg(const Box *in, Box *out, const uint32_t *seg_off, int32_t nq_cap,
                              WaveCtl *ctl, hipStream_t st);
-void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st,
-                        const WaveCtl *ctl = nullptr);
+void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st);
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
-                         uint32_t *qend, hipStream_t st, const WaveCtl *ctl = nullptr);
+                         uint32_t *qend, hipStream_t st);
 void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
                            uint32_t *qend, hipStream_t st);
 // A replayed wave's per-query run ranges, counts and offsets (off[0..nq_cap]: runs
@@ -338,8 +337,7 @@ void launch_box_ranges_scan_ctl(const Box *s, const uint32_t *seg_off, int32_t n
                                 uint32_t *qstart, uint32_t *qend, uint32_t *sel_off,
                                 uint32_t *sel_box, const WaveCtl *ctl, hipStream_t st);
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
-                          int32_t max_hits, uint32_t *nsel, hipStream_t st,
-                          const WaveCtl *ctl = nullptr);
+                          int32_t max_hits, uint32_t *nsel, hipStream_t st);
 void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_off, int32_t nq,
                 uint32_t nsel_total, const uint8_t *qcode, const int64_t *qoff, int32_t qa,
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,

@@ -1595,11 +1595,6 @@ void launch_wave_end(const WaveCtl *ctl, uint32_t *cursor, uint32_t *oflags, hip
     k_wave_end<<<1, 1, 0, st>>>(ctl, cursor, oflags);
 }
 
-__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst)
-{
-    *dst = *src;
-}
-
 __global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -2164,10 +2159,8 @@ void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_
 // Runs come out in (q, s, diag) order: each query's runs are one range
 // [qstart, qend), found at its boundaries (no per-run counter, no atomics).
 __global__ void k_cand_segments(const Cand *__restrict__ c, uint32_t n,
-                                uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
-                                const WaveCtl *__restrict__ ctl)
+                                uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
 {
-    if (ctl) n = ctl->nc;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int32_t q = c[i].q;
         if (i == 0 || c[i - 1].q != q) qstart[q] = i;
@@ -2180,7 +2173,7 @@ void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t 
 {
     if (n)
         k_cand_segments<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
-            c, n, qstart, qend, nullptr);
+            c, n, qstart, qend);
 }
 
 uint32_t chain_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
@@ -2596,14 +2589,11 @@ struct BoxLess {
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_seg_sort_box(const Box *__restrict__ in,
                                                          Box *__restrict__ out,
-                                                         const uint32_t *__restrict__ seg_off,
-                                                         WaveCtl *__restrict__ ctl)
+                                                         const uint32_t *__restrict__ seg_off)
 {
     __shared__ Box s_r[kSegCap];
     __shared__ uint16_t s_ix[kSegCap];
-    if (ctl && ((int32_t)blockIdx.x >= ctl->nqw || (MODE == 1 && ctl->overflow))) return;
     const uint32_t a0 = seg_off[blockIdx.x], n = seg_off[blockIdx.x + 1] - a0;
-    if (ctl && n > (uint32_t)kSegCap && threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
     if (n == 0 || n > (uint32_t)kSegCap) return;  // longer segments take the global sort
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s_r[i] = in[a0 + i];
     lds_bitonic(s_r, s_ix, n, BoxLess<MODE>());
@@ -2611,11 +2601,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_sort_box(const Box *__restrict__
 }
 
 void launch_seg_sort_box(int mode, const Box *in, Box *out, const uint32_t *seg_off, int32_t nq,
-                         hipStream_t st, WaveCtl *ctl)
+                         hipStream_t st)
 {
     if (nq <= 0) return;
-    if (mode == 0) k_seg_sort_box<0><<<nq, kBlock, 0, st>>>(in, out, seg_off, ctl);
-    else k_seg_sort_box<1><<<nq, kBlock, 0, st>>>(in, out, seg_off, ctl);
+    if (mode == 0) k_seg_sort_box<0><<<nq, kBlock, 0, st>>>(in, out, seg_off);
+    else k_seg_sort_box<1><<<nq, kBlock, 0, st>>>(in, out, seg_off);
 }
 
 // A replayed wave's merge and selection order for one query in one block: its
@@ -2781,9 +2771,8 @@ void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int
 constexpr uint32_t kSweepChunk = 32;
 
 __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__restrict__ out,
-                              uint32_t chunk, const WaveCtl *__restrict__ ctl)
+                              uint32_t chunk)
 {
-    if (ctl) n = ctl->overflow ? 0 : ctl->nc;  // an overflowed wave is run again later
     const uint32_t nchunk = (n + chunk - 1) / chunk;
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nchunk;
          c += gridDim.x * blockDim.x) {
@@ -2837,30 +2826,22 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
     }
 }
 
-void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st,
-                        const WaveCtl *ctl)
+void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st)
 {
-    if (ctl) {
-        k_merge_sweep<<<kStrideGrid, kBlock, 0, st>>>(sorted, 0, out, 1, ctl);
-    } else if (n) {
+    if (n) {
         // about half a million threads fill the chip; longer chunks only past that
         const uint32_t chunk = std::max<uint32_t>(1, std::min<uint32_t>(kSweepChunk, n >> 19));
         const uint32_t threads = (n + chunk - 1) / chunk;
         k_merge_sweep<<<std::min<uint32_t>((threads + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0,
-                        st>>>(sorted, n, out, chunk, nullptr);
+                        st>>>(sorted, n, out, chunk);
     }
 }
 
 // ------------------------------------------------------------------ S8: select
 // Records sorted by query first (empty ones last): each query's run [qstart, qend).
 __global__ void k_segments_box(const Box *__restrict__ s, uint32_t n, int32_t nq,
-                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
-                               const WaveCtl *__restrict__ ctl)
+                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
 {
-    if (ctl) {
-        n = ctl->overflow ? 0 : ctl->nc;
-        nq = ctl->nqw;
-    }
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += gridDim.x * blockDim.x) {
         const int32_t q = s[i].q;
@@ -3025,13 +3006,11 @@ void launch_len_compact(const Box *b, uint32_t n, int shift, const uint32_t *thr
 }
 
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
-                         uint32_t *qend, hipStream_t st, const WaveCtl *ctl)
+                         uint32_t *qend, hipStream_t st)
 {
-    if (ctl)
-        k_segments_box<<<kStrideGrid, kBlock, 0, st>>>(sorted, 0, 0, qstart, qend, ctl);
-    else if (n)
+    if (n)
         k_segments_box<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
-            sorted, n, nq, qstart, qend, nullptr);
+            sorted, n, nq, qstart, qend);
 }
 
 __global__ void k_segments_align(const Align *__restrict__ s, uint32_t n, int32_t nq,
@@ -3054,11 +3033,10 @@ void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t
 
 __global__ void k_select_counts(const uint32_t *__restrict__ qstart,
                                 const uint32_t *__restrict__ qend, int32_t nq, int32_t N,
-                                uint32_t *__restrict__ nsel, const WaveCtl *__restrict__ ctl)
+                                uint32_t *__restrict__ nsel)
 {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ctl && (q >= ctl->nqw || ctl->overflow) && q < nq) nsel[q] = 0;  // nothing to select
-    if (q >= (ctl ? (ctl->overflow ? 0 : min(nq, ctl->nqw)) : nq)) return;
+    if (q >= nq) return;
     const uint32_t c = qend[q] - qstart[q];
     nsel[q] = (N > 0 && c > (uint32_t)N) ? (uint32_t)N : c;
 }
@@ -3211,11 +3189,11 @@ void launch_box_ranges_scan_ctl(const Box *s, const uint32_t *seg_off, int32_t n
 }
 
 void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t nq,
-                          int32_t max_hits, uint32_t *nsel, hipStream_t st, const WaveCtl *ctl)
+                          int32_t max_hits, uint32_t *nsel, hipStream_t st)
 {
     if (nq > 0)
         k_select_counts<<<(nq + kBlock - 1) / kBlock, kBlock, 0, st>>>(qstart, qend, nq, max_hits,
-                                                                        nsel, ctl);
+                                                                        nsel);
 }
 
 // ------------------------------------------------------------------ S9: banded Smith-Waterman
