@@ -424,6 +424,19 @@ SortKind sort_kind_from_env()
 // hits; GG_FILTER=0 turns the filter off.
 constexpr uint64_t kFiltMean = 1u << 17;
 
+// The filter's block order: a wave's nqw queries by decreasing hit count, to the
+// power of two (a counting sort on the count's bit length; the order within a
+// length is the query order).  Only rough order matters: the largest start first.
+void filter_order(const uint64_t *qtot, int32_t nqw, int32_t *order)
+{
+    // key 64 - bit length: the largest counts first; start[k] = first slot of key k
+    auto key = [&](int32_t x) { return qtot[x] ? __builtin_clzll(qtot[x]) : 64; };
+    uint32_t start[66] = {0};
+    for (int32_t x = 0; x < nqw; ++x) ++start[key(x) + 1];
+    for (int k = 1; k < 66; ++k) start[k] += start[k - 1];
+    for (int32_t x = 0; x < nqw; ++x) order[start[key(x)]++] = x;
+}
+
 bool filter_for(const gg_index *ix, const gg_params *p, uint64_t hits, int64_t nq)
 {
     const char *g = getenv("GG_FILTER");
@@ -723,10 +736,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             TRY(ensure(ws->ford, sizeof(int32_t) * nqw));
             int32_t *h_ord = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(h_cells) +
                                                          8 * (size_t)nqw);
-            for (int32_t ql = 0; ql < nqw; ++ql) h_ord[ql] = ql;
-            std::stable_sort(h_ord, h_ord + nqw, [&](int32_t x, int32_t y) {
-                return qtot[qa + x] > qtot[qa + y];
-            });
+            filter_order(qtot.data() + qa, nqw, h_ord);
             HIPCHK(hipMemcpyAsync(ws->ford.p, h_ord, sizeof(int32_t) * nqw, hipMemcpyHostToDevice,
                                   st));
         }
@@ -1269,12 +1279,20 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     lay.bq = bits_for((uint64_t)nq_cap);
     if (lay.bp + lay.bd + lay.bs + lay.bq > 64) return GG_OK;
     if ((uint64_t)maxL * (uint64_t)p->match >= (1ull << 30)) return GG_EINVAL;
-    // radix tiles within query segments, all waves in one table
+    uint64_t hsum = 0;
+    for (const WaveCtl &w : plan) hsum += w.H;
+    const bool filt = filter_for(ix, p, hsum, nq);
+    // radix tiles within query segments, all waves in one table (none when the
+    // lone-diagonal filter and the per-query LDS sorts replace the radix passes)
     std::vector<SortTile> tiles, wt;
     std::vector<uint64_t> qc;
     uint32_t ntile_max = 1;
     for (WaveCtl &w : plan) {
         w.lay = lay;
+        if (filt) {
+            w.tile0 = w.ntile = 0;
+            continue;
+        }
         qc.assign(qtot.begin() + w.qa, qtot.begin() + w.qa + w.nqw);
         seg_tiles(qc.data(), w.nqw, wt);
         w.tile0 = (uint32_t)tiles.size();
@@ -1326,9 +1344,6 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
 
     WaveCtl *ctl = as<WaveCtl>(ws->gctl);
     uint32_t *cursor = as<uint32_t>(ws->gcursor);
-    uint64_t hsum = 0;
-    for (const WaveCtl &w : plan) hsum += w.H;
-    const bool filt = filter_for(ix, p, hsum, nq);
     if (filt) {
         TRY(ensure(ws->fkept, sizeof(uint32_t) * (nq_cap + 1)));
         TRY(ensure(ws->fkoff, sizeof(uint32_t) * (nq_cap + 1)));
@@ -1456,11 +1471,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     if (filt) {  // each wave's queries, largest first, at the wave's own positions
         int32_t *h_ord = nout + nq;
         for (const WaveCtl &w : plan) {
-            int32_t *o = h_ord + w.qa;
-            for (int32_t r = 0; r < w.nqw; ++r) o[r] = r;
-            std::stable_sort(o, o + w.nqw, [&](int32_t x, int32_t y) {
-                return qtot[w.qa + x] > qtot[w.qa + y];
-            });
+            filter_order(qtot.data() + w.qa, w.nqw, h_ord + w.qa);
         }
         HIPCHK(hipMemcpyAsync(ws->ford.p, h_ord, sizeof(int32_t) * nq, hipMemcpyHostToDevice, st));
     }
