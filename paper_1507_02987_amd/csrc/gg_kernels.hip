@@ -3205,10 +3205,9 @@ void launch_select_counts(const uint32_t *qstart, const uint32_t *qend, int32_t 
 // diagonal neighbour (same t) is this lane's own cell of a - 2.
 //
 // Each lane walks a staircase: after a step of parity 0 it moves one column
-// right, after parity 1 one row down.  The data-bank base a lane needs next is
-// the one its right neighbour holds, and the query base the one its left
-// neighbour holds, so bases also flow by lane shifts; only lane W (columns) and
-// lane 0 (rows) take new bases, from 64-base windows loaded one window ahead.
+// right, after parity 1 one row down.  Every lane reads the query base and the
+// two bank bases of its next pair one pair ahead, from the box's bases staged in
+// LDS (or from global memory for boxes too long to stage).
 // Starts and best cells are packed as i * 128 + t.
 // Lanes without a source (lane 0, resp. lane 63) read 0; the kernel never uses them.
 __device__ __forceinline__ int32_t from_lower_lane(int32_t v)  // lane u gets lane u - 1
@@ -3235,7 +3234,11 @@ __device__ __forceinline__ unsigned long long band_cells(int32_t R, int32_t C, i
 // One cell of the affine recurrence with start tracking (see the oracle's O9):
 // E/F open from the left/upper cell when the open term is >= the extend term;
 // H > 0 takes its start from G (its diagonal predecessor's start, or itself if
-// that H <= 0), else from E, else from F.
+// that H <= 0), else from E, else from F.  The start of a cell with H <= 0 is
+// left as that rule gives it: no cell with H > 0 inherits it (the diagonal
+// successor takes its own position, and a gap opened from H <= 0 is negative
+// and stays so, as the penalties are >= 0), and only cells with H > 0 are
+// reported.
 struct CellOut {
     int32_t H, E, F, S, SE, SF;
 };
@@ -3258,7 +3261,7 @@ __device__ __forceinline__ CellOut sw_cell(int32_t hl, int32_t el, int32_t sl, i
     const int32_t g = hd + (same ? match : -mismatch);
     c.H = max(max(g, 0), max(c.E, c.F));
     const int32_t sg = hd > 0 ? sd : here;
-    c.S = (c.H > 0) ? ((g == c.H) ? sg : ((c.E == c.H) ? c.SE : c.SF)) : here;
+    c.S = (g == c.H) ? sg : ((c.E == c.H) ? c.SE : c.SF);
     return c;
 }
 
