@@ -364,3 +364,26 @@ def test_long_merge_groups(ggo):
         want, wst = oracle_all(ggo, oix, qs, ggo.params(n))
         assert max(s["n_cands"] for s in wst) > 2_000
         check_batch(G, gix, qs, G.params(n), want, wst)
+
+
+@pytest.mark.parametrize("band", [1, 5, 32])
+def test_tie_heavy_two_letter_banks(ggo, band):
+    """Banks and queries over two letters, scored +2/-1 with gaps 1 + g: many
+    local alignments tie in score, so the reported spans turn on the aligner's
+    tie rules (gap open before extend, start from the diagonal, then the left gap,
+    then the upper gap, first maximum in row-major order)."""
+    G = gpu()
+    fold = np.frombuffer(b"A" * 256, dtype=np.uint8).copy()
+    fold[ord("C")] = fold[ord("T")] = ord("C")
+    db0 = synth.random_db(40 + band, n_seqs=200, lmin=20, lmax=600)
+    qs0 = synth.random_queries(40 + band, db0, n=40, lmin=10, lmax=300, frac_homolog=0.8,
+                               ident_lo=0.75, ident_hi=0.95, indel_rate=0.05)
+    db = synth.Database(fold[db0.seqs], db0.off)
+    qs = qs0.subset(np.arange(qs0.n))
+    qs.buf = fold[qs.buf]
+    kw = dict(match=2, mismatch=1, gap_open=1, gap_extend=1, xdrop=6, band=band, max_gap=8,
+              min_hsp_len=12)
+    oix, gix = ggo.Index(db.seqs, db.off, 6), G.Index(db.seqs, db.off, 6)
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(30, **kw))
+    assert sum(len(w) for w in want) > 200
+    check_batch(G, gix, qs, G.params(30, **kw), want, wst)

@@ -179,3 +179,25 @@ def test_empty_box(ggo):
     prm = ggo.params(0)
     hit, cells = ggo.bsw(codes("ACGT"), codes("ACGT"), box_of(2, 2, 2, 2), prm)
     assert cells == 0 and hit["score"] == 0
+
+
+TIES = json.load(open(os.path.join(GOLD, "bsw_ties.json")))
+
+
+@pytest.mark.parametrize("case", TIES["cases"], ids=[c["name"] for c in TIES["cases"]])
+def test_tie_rules_hand_worked(ggo, case):
+    """Tied optima: the reported span is the one the tie rules pick (hand-worked
+    cells in the golden file), and it is one of several optimal spans that the
+    brute-force enumeration finds, so the case really turns on the rule."""
+    sc = TIES["scheme"]
+    q, s, W, d0 = case["q"], case["s"], case["band"], case["d0"]
+    prm = ggo.params(0, band=W, **sc)
+    hit, cells = ggo.bsw(codes(q), codes(s), box_of(0, len(q), 0, len(s), d0, d0), prm)
+    in_band = lambda i, j: abs(j - i - d0) <= W
+    assert cells == sum(in_band(i, j) for i in range(len(q)) for j in range(len(s)))
+    assert hit["score"] == case["score"]
+    assert [hit["q_start"], hit["q_end"], hit["d_start"], hit["d_end"]] == case["span"]
+    best, spans = enumerate_local(q, s, in_band=in_band, **sc)
+    assert best == case["score"]
+    assert tuple(case["span"]) in spans
+    assert (len(spans) > 1) == case["tied_optima"]
