@@ -311,6 +311,12 @@ gg_status gg_memcpy_to_host(void *dst, const void *src, uint64_t bytes);
 /* Device-to-device copy of `bytes` (the runtime's copy kernel); a transfer of known
  * size against which memory-traffic counters are calibrated. */
 gg_status gg_device_copy(void *dst, const void *src, uint64_t bytes);
+/* Read `bytes` (a multiple of 16) of device memory once with a hand-written
+ * streaming kernel (coalesced 16-byte loads, one 8-byte atomic per block) and
+ * return the 64-bit sum of its 32-bit words in *sum (host memory): a read of known
+ * size for calibrating memory-read counters.  GG_EINVAL for a null pointer or a
+ * size that is not a multiple of 16; GG_ENOMEM, GG_EDEVICE. */
+gg_status gg_device_read(const void *src, uint64_t bytes, uint64_t *sum);
 
 /*
  * Per-stage GPU timing of batched searches on this index, for roofline reports.
@@ -340,16 +346,23 @@ gg_status gg_profile_read(const gg_index *index, const char *stage, double *ms,
                           int64_t *launches, int64_t *units);
 
 /*
- * Served form: a request loop that admits queries as they arrive, within a
- * device hit-buffer budget and a number of in-flight slots, and runs the
- * admitted ones together on the GPU while new requests keep arriving.  Each
- * query's result equals its gg_search result.
- * hit_budget_bytes : device bytes for hit keys of all in-flight queries (0: default)
+ * Served form (the in-process counterpart of the paper's search services,
+ * Section 4): a request loop with continuous batching.  Each submitted query's
+ * index hits are counted exactly on the GPU; queries are then admitted in arrival
+ * order as in-flight slots and hit-buffer bytes (16 per hit) free up, and run in
+ * small batches on up to four streams at once, so requests arriving while others
+ * are on the GPU start as soon as room frees.  A query with more than 2^24 hits
+ * runs in a batch of its own; one whose hits exceed the whole budget runs when
+ * nothing else is in flight, searched in ranges of sequences.  Each query's result
+ * equals its gg_search result.
+ * hit_budget_bytes : device bytes for hit keys of all in-flight queries
+ *                    (0: the index's hit budget)
  * max_slots        : queries in flight at once (>= 1)
  */
 gg_status gg_server_create(const gg_index *index, const gg_params *params,
                            uint64_t hit_budget_bytes, int32_t max_slots, gg_server **out);
-/* Queue one query (copied before return); *ticket identifies it for gg_serve_poll. */
+/* Queue one query (copied before return); *ticket identifies it for gg_serve_poll.
+ * GG_EINVAL for a byte outside {A,C,G,T,U} (either case), with nothing queued. */
 gg_status gg_serve_submit(gg_server *server, const char *query, int64_t qlen, uint64_t *ticket);
 /*
  * Wait up to timeout_us (0: do not wait, < 0: wait until done) for a ticket.
@@ -358,7 +371,27 @@ gg_status gg_serve_submit(gg_server *server, const char *query, int64_t qlen, ui
  */
 gg_status gg_serve_poll(gg_server *server, uint64_t ticket, gg_hit *out, int32_t cap,
                         int32_t *n_out, int32_t timeout_us);
-/* Stop the loop; pending tickets are cancelled. */
+/*
+ * Admission record of a server since its creation: requests submitted and
+ * completed, batches started, the largest number of hit-key bytes and of requests
+ * in flight at once (the bytes never exceed budget_bytes), the most requests in
+ * one batch, the requests searched alone in sequence ranges because their hits
+ * exceed the budget, the bytes and requests in flight now, and the submit and
+ * poll calls inside the library now (a poll waiting for its ticket counts).
+ */
+typedef struct {
+    int64_t submitted, completed, batches;
+    uint64_t budget_bytes, peak_inflight_bytes, inflight_bytes;
+    int64_t peak_inflight_slots, inflight_slots, peak_batch_queries, over_budget;
+    int64_t calls_inside;
+} gg_server_stats;
+gg_status gg_server_info(gg_server *server, gg_server_stats *out);
+/*
+ * Stop the loop: batches on the GPU finish, queued requests are cancelled, and
+ * submit or poll calls already inside the library return first (a poll waiting on
+ * a cancelled ticket returns GG_ENOTFOUND).  No call may use the server once
+ * destroy has begun.
+ */
 void gg_server_destroy(gg_server *server);
 
 const char *gg_strerror(gg_status status);

@@ -230,6 +230,9 @@ void onesweep_pass(const uint64_t *kin, uint64_t *kout, uint32_t n, int lo, int 
                    void *scratch, hipStream_t st);
 const uint32_t *onesweep_fail_flag(const void *scratch);
 void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
+// Read `bytes` (a multiple of 16) once and add their 32-bit words into *sum
+// (memory-counter calibration).
+void launch_stream_read(const void *src, size_t bytes, unsigned long long *sum, hipStream_t st);
 void launch_fill2_u32(uint32_t *a, size_t na, uint32_t *b, size_t nb, uint32_t v, hipStream_t st);
 
 // ---- graph-replayed waves: the kernels below read the wave's sizes from ctl;

@@ -1609,6 +1609,38 @@ void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st)
     k_fill_u32<<<(uint32_t)nb, kBlock, 0, st>>>(p, n, v);
 }
 
+// Streaming read of `bytes` bytes (a multiple of 16) for memory-counter
+// calibration: every 16-byte vector is loaded once, coalesced, and folded into a
+// per-thread sum; each block adds its sum to *sum with one atomic, so the kernel
+// writes 8 bytes per block and reads exactly the buffer.
+__global__ void k_stream_read(const uint4 *__restrict__ src, size_t n16,
+                              unsigned long long *__restrict__ sum)
+{
+    __shared__ unsigned long long part[kBlock / 64];
+    unsigned long long acc = 0;
+    const size_t step = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += step) {
+        const uint4 v = src[i];
+        acc += (unsigned long long)v.x + v.y + v.z + v.w;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        atomicAdd(sum, t);
+    }
+}
+
+void launch_stream_read(const void *src, size_t bytes, unsigned long long *sum, hipStream_t st)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return;
+    const size_t nb = std::min<size_t>((n16 + kBlock - 1) / kBlock, 8192);
+    k_stream_read<<<(uint32_t)nb, kBlock, 0, st>>>(static_cast<const uint4 *>(src), n16, sum);
+}
+
 // Two arrays set to v in one launch (a graph node less than two fills).
 __global__ void k_fill2_u32(uint32_t *__restrict__ a, size_t na, uint32_t *__restrict__ b,
                             size_t nb, uint32_t v)

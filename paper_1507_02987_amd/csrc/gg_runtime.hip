@@ -1620,6 +1620,74 @@ namespace gg {
 
 uint64_t index_budget(const gg_index *ix) { return budget_of(ix); }
 
+// Index hits of each of n_q host queries (Section 2.2: the postings of every
+// query window), counted by the search's own encode and count kernels; the served
+// form admits queries on these exact counts.  GG_EINVAL for a byte outside the
+// alphabet anywhere in the batch.
+gg_status count_hits(const gg_index *ix, const char *qbuf, const int64_t *qoff, int64_t n_q,
+                     uint64_t *hits)
+{
+    if (!ix || n_q < 0 || (n_q > 0 && (!qoff || !hits))) return GG_EINVAL;
+    if (n_q == 0) return GG_OK;
+    const int64_t T = qoff[n_q] - qoff[0];
+    for (int64_t q = 0; q < n_q; ++q)
+        if (qoff[q + 1] < qoff[q]) return GG_EINVAL;
+    if (T > (int64_t)INT32_MAX || (T > 0 && !qbuf)) return GG_EINVAL;
+    if (hipSetDevice(ix->device) != hipSuccess) return GG_EDEVICE;
+    Workspace *ws = nullptr;
+    TRY(get_ws(ix, &ws));
+    auto run = [&]() -> gg_status {
+        hipStream_t st = ws->st;
+        TRY(ensure(ws->ascii, T));
+        TRY(ensure(ws->qoff, sizeof(int64_t) * (n_q + 1)));
+        TRY(ensure(ws->qcode, T));
+        TRY(ensure(ws->kcode, sizeof(uint32_t) * T));
+        TRY(ensure(ws->cnt, sizeof(uint32_t) * T));
+        TRY(ensure(ws->lhead, sizeof(uint32_t) * T));
+        TRY(ensure(ws->qid, sizeof(int32_t) * T));
+        TRY(ensure(ws->hoff, sizeof(uint64_t) * (T + 1)));
+        TRY(ensure(ws->partials,
+                   sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(T, n_q + 1))));
+        TRY(ensure(ws->qtot, sizeof(uint64_t) * n_q));
+        TRY(ensure(ws->err, sizeof(int32_t) * 4));
+        TRY(ensure(ws->bq, sizeof(int32_t) * ((size_t)(T + kBlock - 1) / kBlock + 1)));
+        void *pin;
+        TRY(pinned(ws, sizeof(int64_t) * (2 * (size_t)n_q + 2), &pin, 1));
+        int64_t *h_qoff = static_cast<int64_t *>(pin);
+        uint64_t *h_qtot = reinterpret_cast<uint64_t *>(h_qoff + n_q + 1);
+        int32_t *h_err = reinterpret_cast<int32_t *>(h_qtot + n_q);
+        for (int64_t q = 0; q <= n_q; ++q) h_qoff[q] = qoff[q] - qoff[0];
+        if (T > 0)
+            HIPCHK(hipMemcpyAsync(ws->ascii.p, qbuf + qoff[0], T, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ws->qoff.p, h_qoff, sizeof(int64_t) * (n_q + 1),
+                              hipMemcpyHostToDevice, st));
+        launch_fill_u32(as<uint32_t>(ws->err), 1, 0u, st);
+        launch_encode_kmers(as<uint8_t>(ws->ascii), as<int64_t>(ws->qoff), (int32_t)n_q, T,
+                            ix->span, ix->mask, ix->d_list_off, as<uint8_t>(ws->qcode),
+                            as<uint32_t>(ws->kcode), as<uint32_t>(ws->cnt),
+                            as<uint32_t>(ws->lhead), as<int32_t>(ws->qid), as<int32_t>(ws->err),
+                            as<int32_t>(ws->bq), st);
+        launch_scan_u32_to_u64(as<uint32_t>(ws->cnt), as<uint64_t>(ws->hoff), T,
+                               as<uint64_t>(ws->partials), st);
+        launch_query_totals(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), (int32_t)n_q,
+                            as<uint64_t>(ws->qtot), st);
+        HIPCHK(hipMemcpyAsync(h_qtot, ws->qtot.p, sizeof(uint64_t) * n_q, hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipMemcpyAsync(h_err, ws->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SYNC(st);
+        if (*h_err) return GG_EINVAL;
+        std::copy(h_qtot, h_qtot + n_q, hits);
+        return GG_OK;
+    };
+    gg_status s = run();
+    if (s != GG_OK) {
+        (void)hipStreamSynchronize(ws->st);
+        (void)hipGetLastError();
+    }
+    put_ws(ix, ws);
+    return s;
+}
+
 gg_status search_batch_budget(const gg_index *ix, const char *qbuf, const int64_t *qoff,
                               int64_t n_q, const gg_params *params, gg_hit *out, int32_t cap,
                               int32_t *n_out, gg_stats *stats, uint64_t budget, bool device)
@@ -2332,6 +2400,23 @@ gg_status gg_device_copy(void *dst, const void *src, uint64_t bytes)
     if (!dst || !src) return GG_EINVAL;
     if (hipMemcpy(dst, src, bytes, hipMemcpyDeviceToDevice) != hipSuccess) return GG_EDEVICE;
     return hipDeviceSynchronize() == hipSuccess ? GG_OK : GG_EDEVICE;
+}
+
+gg_status gg_device_read(const void *src, uint64_t bytes, uint64_t *sum)
+{
+    if (!src || !sum || bytes % 16 != 0) return GG_EINVAL;
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(unsigned long long)) != hipSuccess) return GG_ENOMEM;
+    gg_status s = GG_OK;
+    if (hipMemset(d, 0, sizeof(unsigned long long)) != hipSuccess) s = GG_EDEVICE;
+    if (s == GG_OK) {
+        gg::launch_stream_read(src, bytes, static_cast<unsigned long long *>(d), nullptr);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpy(sum, d, sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+            s = GG_EDEVICE;
+    }
+    (void)hipFree(d);
+    return s;
 }
 
 gg_status gg_memcpy_to_host(void *dst, const void *src, uint64_t bytes)

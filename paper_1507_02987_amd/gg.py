@@ -34,8 +34,10 @@ SYMBOLS = ("gg_index_build", "gg_index_build_masked", "gg_index_build_ex", "gg_i
            "gg_index_get_tuning", "gg_index_set_tuning", "gg_index_autotune",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
            "gg_device_free", "gg_memcpy_to_device", "gg_memcpy_to_host", "gg_device_copy",
+           "gg_device_read",
            "gg_profile_enable", "gg_profile_read",
-           "gg_server_create", "gg_serve_submit", "gg_serve_poll", "gg_server_destroy",
+           "gg_server_create", "gg_serve_submit", "gg_serve_poll", "gg_server_info",
+           "gg_server_destroy",
            "gg_strerror")
 
 
@@ -53,6 +55,14 @@ class Params(C.Structure):
 class IndexOptions(C.Structure):
     _fields_ = [("k", C.c_int32), ("mask", C.c_char_p), ("strands", C.c_int32),
                 ("max_posting", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("budget_bytes", C.c_uint64), ("peak_inflight_bytes", C.c_uint64),
+                ("inflight_bytes", C.c_uint64), ("peak_inflight_slots", C.c_int64),
+                ("inflight_slots", C.c_int64), ("peak_batch_queries", C.c_int64),
+                ("over_budget", C.c_int64), ("calls_inside", C.c_int64)]
 
 
 class Tuning(C.Structure):
@@ -126,11 +136,13 @@ def lib():
         L.gg_memcpy_to_device.argtypes = [vp, vp, u64]
         L.gg_memcpy_to_host.argtypes = [vp, vp, u64]
         L.gg_device_copy.argtypes = [vp, vp, u64]
+        L.gg_device_read.argtypes = [vp, u64, C.POINTER(u64)]
         L.gg_profile_enable.argtypes = [vp, i32]
         L.gg_profile_read.argtypes = [vp, C.c_char_p, vp, vp, vp]
         L.gg_server_create.argtypes = [vp, C.POINTER(Params), u64, i32, C.POINTER(vp)]
         L.gg_serve_submit.argtypes = [vp, vp, i64, vp]
         L.gg_serve_poll.argtypes = [vp, u64, vp, i32, vp, i32]
+        L.gg_server_info.argtypes = [vp, C.POINTER(ServerStats)]
         L.gg_server_destroy.argtypes = [vp]
         L.gg_server_destroy.restype = None
         L.gg_strerror.argtypes = [i32]
@@ -316,6 +328,16 @@ class Index:
         res = [out[i * cap: i * cap + min(int(nout[i]), cap)].copy() for i in range(nq)]
         return rc, res, nout[:nq].copy(), (st[:nq] if stats else None)
 
+    def search_batch_into(self, qbuf: np.ndarray, qoff: np.ndarray, prm: Params, out: np.ndarray,
+                          nout: np.ndarray, cap: int) -> int:
+        """gg_search_batch into caller-owned arrays (out: n_q * cap hits, nout: n_q
+        counts), with no per-query unpacking; returns the status."""
+        nq = len(qoff) - 1
+        assert qbuf.dtype == np.uint8 and qoff.dtype == np.int64 and out.dtype == HIT_DTYPE
+        assert nout.dtype == np.int32 and len(out) >= nq * cap and len(nout) >= nq
+        return lib().gg_search_batch(self._h, _ptr(qbuf) if len(qbuf) else None, _ptr(qoff), nq,
+                                     C.byref(prm), _ptr(out), cap, _ptr(nout), None)
+
     def search_batch_device(self, dq: "DeviceBuffer", qoff, prm: Params, dout: "DeviceBuffer",
                             dn: "DeviceBuffer", cap: int, stats: bool = False):
         """gg_search_batch_device on device-resident queries and result buffers."""
@@ -364,6 +386,14 @@ class DeviceBuffer:
             raise GGError(rc, "gg_memcpy_to_host")
         return a
 
+    def read_sum(self, nbytes: int) -> int:
+        """gg_device_read: stream the first nbytes once on the GPU; their word sum."""
+        v = C.c_uint64()
+        rc = lib().gg_device_read(self.ptr, int(nbytes), C.byref(v))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_device_read")
+        return v.value
+
     def copy_from(self, other: "DeviceBuffer", nbytes: int):
         rc = lib().gg_device_copy(self.ptr, other.ptr, int(nbytes))
         if rc != GG_OK:
@@ -409,6 +439,14 @@ class Server:
         if rc in (GG_OK, GG_ETRUNC):
             return rc, out[: min(n.value, cap)].copy(), n.value
         return rc, np.zeros(0, HIT_DTYPE), 0
+
+    def info(self) -> dict:
+        """gg_server_info: admission totals and peaks."""
+        t = ServerStats()
+        rc = lib().gg_server_info(self._h, C.byref(t))
+        if rc != GG_OK:
+            raise GGError(rc, "gg_server_info")
+        return {f: getattr(t, f) for f, _ in ServerStats._fields_}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -44,22 +44,35 @@ def large(ggo):
     return gg, db, gix, oix
 
 
-def sample(st, n_rand, n_heavy, seed, max_hits=20_000_000):
+def sample(st, n_rand, n_heavy, seed, max_hits=20_000_000, over=0):
     """n_rand queries drawn at random plus the n_heavy with the most hits among
-    those the oracle searches in a second or two (at most max_hits hits)."""
+    those the oracle searches in a second or two (at most max_hits hits), plus,
+    when over > 0, the query with the fewest hits above `over` (the oracle takes
+    about 30 s per 10^8 hits)."""
     hits = st["n_hits"].astype(np.int64)
     ok = np.flatnonzero(hits <= max_hits)
     heavy = ok[np.argsort(hits[ok], kind="stable")[-n_heavy:]]
     rng = np.random.default_rng(seed)
-    return np.unique(np.concatenate([heavy, rng.choice(ok, n_rand, replace=False)]))
+    parts = [heavy, rng.choice(ok, n_rand, replace=False)]
+    if over:
+        big = np.flatnonzero(hits > over)
+        assert len(big), "no query above the heavy threshold"
+        parts.append(big[np.argsort(hits[big], kind="stable")[:1]])
+    return np.unique(np.concatenate(parts))
 
 
 def check_sampled(ggo, oix, qs, got, st, pick, top_n, cap):
     def one(i):
         return oix.search(qs.query(i), ggo.params(top_n), cap=cap)
 
+    hits = st["n_hits"].astype(np.int64)
+    note(f"oracle on {len(pick)} queries, {int(hits[pick].sum())} hits, "
+         f"largest {int(hits[pick].max())}")
+    # heaviest first, so the longest oracle search overlaps the rest
+    order = [int(i) for i in sorted(pick, key=lambda i: -hits[int(i)])]
     with ThreadPoolExecutor(max_workers=8) as ex:
-        res = list(ex.map(one, [int(i) for i in pick]))
+        res = dict(zip(order, ex.map(one, order)))
+    res = [res[int(i)] for i in pick]
     for i, (orc, oh, on, ost) in zip(pick, res):
         i = int(i)
         assert orc == 0 and on == len(got[i]), i
@@ -68,16 +81,29 @@ def check_sampled(ggo, oix, qs, got, st, pick, top_n, cap):
             assert int(st[i][f]) == ost[f], (i, f)
 
 
+@pytest.mark.timeout(900)
 def test_long_queries_top100(ggo, large):
-    """2,000 queries of 500-5,000 bp, half planted homologs at 75-99% identity."""
+    """2,000 queries of 500-5,000 bp, half planted homologs at 75-99% identity, top
+    100, through the benchmark's call (host buffers in and out, no statistics);
+    the work counts come from a second call with statistics, which must return
+    the same hits.  The oracle checks a sample that holds a query of more than
+    10^8 hits."""
     G, db, gix, oix = large
     qs = synth.large_queries(db)
+    gix.set_tuning("sort", 16)
     note(f"{qs.n} long queries on the GPU")
+    out = np.zeros(qs.n * 100, G.HIT_DTYPE)
+    nout = np.zeros(qs.n, np.int32)
+    rc = gix.search_batch_into(qs.buf, qs.off, G.params(100), out, nout, 100)
+    assert rc == 0
     rc, got, n, st = gix.search_batch(qs.buf, qs.off, G.params(100), cap=100, stats=True)
     assert rc == 0
+    assert np.array_equal(n, nout)
+    for i in range(qs.n):
+        assert got[i].tobytes() == out[i * 100: i * 100 + int(n[i])].tobytes(), i
     note(f"done: {int(st['n_hits'].sum())} hits; checking a sample against the oracle")
     assert int(st["n_hits"].max()) > 1_000_000  # repeat-rich queries are in the set
-    check_sampled(ggo, oix, qs, got, st, sample(st, 30, 6, 2), 100, 100)
+    check_sampled(ggo, oix, qs, got, st, sample(st, 30, 6, 2, over=100_000_000), 100, 100)
 
 
 def test_short_queries_one_batch(ggo, large):
@@ -126,6 +152,56 @@ def test_served_mixed_lengths(ggo, large):
     rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=50, stats=True)
     assert rc == 0 and all(as_rows(got[i]) == as_rows(alone[i][1]) for i in range(qs.n))
     check_sampled(ggo, oix, qs, got, st, sample(st, 25, 5, 4), 50, 50)
+
+
+def test_served_poisson_mix(large):
+    """Served-workload queries arriving Poisson at 200 per second into a server with
+    a 16 GiB hit budget: each result equals the same query searched alone, and the
+    bytes in flight stay within the budget."""
+    G, db, gix, oix = large
+    qs = synth.large_served_queries(db).subset(np.arange(400))
+    prm = G.params(50)
+    arr = synth.served_arrivals(200.0, qs.n)
+    note(f"{qs.n} served queries alone")
+    alone = [gix.search(qs.query(i), prm, cap=50) for i in range(qs.n)]
+    assert all(a[0] == 0 for a in alone)
+    note("the same queries arriving Poisson at 200/s")
+    sv = G.Server(gix, prm, hit_budget_bytes=16 << 30, max_slots=256)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for i in range(qs.n):
+            while time.perf_counter() - t0 < arr[i]:
+                time.sleep(0.0002)
+            tickets.append(sv.submit(qs.query(i)))
+        for i, t in enumerate(tickets):
+            rc, h, n = sv.poll(t, cap=50, timeout_us=-1)
+            assert rc == 0 and as_rows(h) == as_rows(alone[i][1]), i
+        info = sv.info()
+        note(f"server: {info}")
+        assert info["peak_inflight_bytes"] <= 16 << 30 and info["completed"] == qs.n
+        assert info["peak_inflight_slots"] > 1  # requests overlapped on the device
+    finally:
+        sv.close()
+
+
+@pytest.mark.timeout(900)
+def test_served_heavy_query_oracle(ggo, large):
+    """The served workload's query with the fewest hits above 10^8 (a repeat-rich
+    homolog), searched alone on the GPU, equals the oracle in every field and
+    count."""
+    G, db, gix, oix = large
+    qs = synth.large_served_queries(db)
+    prm = G.params(50)
+    rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=50, stats=True)
+    assert rc == 0
+    hits = st["n_hits"].astype(np.int64)
+    big = np.flatnonzero(hits > 100_000_000)
+    i = int(big[np.argmin(hits[big])])
+    note(f"served query {i}: {int(hits[i])} hits, {qs.lengths()[i]} bp; the oracle on it")
+    rc1, h1, n1 = gix.search(qs.query(i), prm, cap=50)
+    assert rc1 == 0 and as_rows(h1) == as_rows(got[i])
+    check_sampled(ggo, oix, qs, got, st, np.array([i]), 50, 50)
 
 
 def test_served_set_over_budget_query(large):
