@@ -299,11 +299,13 @@ void launch_report_seg(const Align *in, Align *out, const uint32_t *sel_off, int
                        int32_t *dev_n, hipStream_t st, WaveCtl *ctl = nullptr);
 // queue_mem: extend_queue_bytes(n) bytes of device scratch.
 size_t extend_queue_bytes(uint32_t n);
-void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
-                   int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
-                   int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
+void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const uint32_t *qpack,
+                   const int64_t *qoff, int32_t qa, const uint32_t *dbw, const int64_t *seq_start,
+                   int32_t match, int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
                    int32_t lane_steps, hipStream_t st, const WaveCtl *ctl = nullptr,
                    uint32_t n_cap = 0, bool count_cleared = false);
+// The batch's T query codes packed 16 bases to a word ((T + 15) / 16 + 2 words).
+void launch_pack_query(const uint8_t *qcode, int64_t T, uint32_t *qpack, hipStream_t st);
 void launch_box_keys(const Box *b, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,
                      const uint32_t *perm, hipStream_t st);
 void launch_align_keys(const Align *a, uint32_t n, KeyWord w, int32_t q_invalid, uint64_t *out,

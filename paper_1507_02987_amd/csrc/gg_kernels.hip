@@ -2352,8 +2352,113 @@ __device__ __forceinline__ uint32_t queue_slot(bool need, uint32_t *__restrict__
     return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
+// The batch's query codes packed 16 to a word like the data bank (first base in
+// the top bits), for the extension's word compares; two spare words at the end.
+__global__ void k_pack_query(const uint8_t *__restrict__ qcode, int64_t T,
+                             uint32_t *__restrict__ qpack, int64_t nwords)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    uint32_t v = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int64_t g = 16 * w + t;
+        const uint32_t c = g < T ? (uint32_t)(qcode[g] & 3u) : 0u;
+        v |= c << (30 - 2 * t);
+    }
+    qpack[w] = v;
+}
+
+void launch_pack_query(const uint8_t *qcode, int64_t T, uint32_t *qpack, hipStream_t st)
+{
+    const int64_t nwords = (T + 15) / 16 + 2;
+    k_pack_query<<<(uint32_t)((nwords + kBlock - 1) / kBlock), kBlock, 0, st>>>(qcode, T, qpack,
+                                                                             nwords);
+}
+
+// 16 bases of a 2-bit packed array (first base in the top bits) starting at g,
+// first base in bits 31:30.  Reads words g / 16 and g / 16 + 1.
+__device__ __forceinline__ uint32_t bases16_from(const uint32_t *__restrict__ w, int64_t g)
+{
+    const int64_t wi = g >> 4;
+    const uint64_t v = ((uint64_t)w[wi] << 32) | (uint64_t)w[wi + 1];
+    return (uint32_t)(v >> (32u - ((uint32_t)(g & 15) << 1)));
+}
+
+// The 16 bases before position p (p - 16 .. p - 1), base p - 1 in bits 1:0.  Below
+// p = 16 the missing bases read as zero; a walk never consumes them.
+__device__ __forceinline__ uint32_t bases16_before(const uint32_t *__restrict__ w, int64_t p)
+{
+    if (p >= 16) return bases16_from(w, p - 16);
+    return p <= 0 ? 0u : (bases16_from(w, 0) >> (2u * (uint32_t)(16 - p)));
+}
+
+// X-drop walk of one lane, 16 steps per iteration.  The query and data-bank
+// bases of the next 16 steps are read as packed words, compared at once (a 2-bit
+// XOR), and the running sum moves from one mismatch to the next: between
+// mismatches it only rises, so its maximum over a stretch of matches is at the
+// stretch's end (the first step at that value), and it can only fall more than X
+// below the best at a mismatch.  This is the step-by-step rule exactly.
+// Returns true when the walk ended (drop over X, or T steps); otherwise it
+// stopped at or beyond `cap` steps with its state in (t, run, best, bl).
+template <bool RIGHT>
+__device__ __forceinline__ bool xdrop_words(const uint32_t *__restrict__ qpack, int64_t gq,
+                                            const uint32_t *__restrict__ dbw, int64_t gb,
+                                            int32_t T, int32_t match, int32_t mismatch, int32_t X,
+                                            int32_t cap, int32_t &t, int32_t &run, int32_t &best,
+                                            int32_t &bl)
+{
+    while (t < T) {
+        if (t >= cap) return false;
+        const int32_t nstep = min(16, T - t);
+        uint32_t mm;
+        if (RIGHT) {
+            const uint32_t x = bases16_from(qpack, gq + t) ^ bases16_from(dbw, gb + t);
+            // step i (0-based) is the base in bits 31-2i:30-2i; one flag bit per step
+            mm = (x | (x >> 1)) & 0x55555555u;
+            if (nstep < 16) mm &= ~(0xFFFFFFFFu >> (2 * nstep));
+        } else {
+            const uint32_t x = bases16_before(qpack, gq - t) ^ bases16_before(dbw, gb - t);
+            // step i is the base in bits 2i+1:2i
+            mm = (x | (x >> 1)) & 0x55555555u;
+            if (nstep < 16) mm &= (1u << (2 * nstep)) - 1u;
+        }
+        int32_t pos = 0;
+        for (;;) {
+            int32_t nx = nstep;  // step of the next mismatch in this chunk
+            if (mm) nx = RIGHT ? (int32_t)((__clz(mm) - 1) >> 1) : (int32_t)((__ffs(mm) - 1) >> 1);
+            const int32_t r = nx - pos;
+            if (r > 0) {
+                run += r * match;
+                if (run > best) {
+                    best = run;
+                    bl = t + nx;
+                }
+            }
+            if (nx >= nstep) break;
+            run -= mismatch;
+            if (best - run > X) {
+                t += nx + 1;
+                return true;
+            }
+            mm &= RIGHT ? ~(1u << (30 - 2 * nx)) : ~(1u << (2 * nx));
+            pos = nx + 1;
+        }
+        t += nstep;
+    }
+    return true;
+}
+
+// Extension of every run on both sides (Section 2.2 phase 3).  Each side of each
+// run is one walk; whole waves take contiguous ranges of walks, and a lane whose
+// walk ends takes the next one of its wave's range at once, so lanes do not idle
+// behind the longest walk of a group.  A walk still going after `lane_steps`
+// steps is queued (its state saved) and k_extend_long resumes it with a whole
+// wave; a full queue makes the lane finish the walk itself.  The right walk of a
+// run writes its box's run fields and right end, the left walk its left end; a
+// queued side is rewritten by k_extend_long.
 __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cands, uint32_t n,
-                                                   const uint8_t *__restrict__ qcode,
+                                                   const uint32_t *__restrict__ qpack,
                                                    const int64_t *__restrict__ qoff, int32_t qa,
                                                    const uint32_t *__restrict__ dbw,
                                                    const int64_t *__restrict__ seq_start,
@@ -2367,45 +2472,75 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
         qa = ctl->qa;
     }
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const uint32_t nwave = gridDim.x * (kBlock / 64);
-    // whole waves step through the runs together (the queue slots are per wave)
-    for (uint32_t i0 = wave * 64; i0 < n; i0 += nwave * 64) {
-        const uint32_t i = i0 + lane;
-        const bool valid = i < n;
-        Cand c{0, 0, 0, 0, 0};
-        if (valid) c = cands[i];
-        const int64_t q0 = qoff[qa + c.q];
-        const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
-        const uint8_t *__restrict__ q = qcode + q0;
-        const int64_t s0 = seq_start[c.s];
-        const int32_t ns = (int32_t)(seq_start[c.s + 1] - s0);
-        const int32_t d = c.d;
-        const int32_t tr = valid ? min(L - c.qe, ns - (c.qe + d)) : 0;
-        const int32_t tl = valid ? min(c.qs, c.qs + d) : 0;
-        int32_t t, run, best, bl;
-        bool done = xdrop_lane<true>(q, dbw, s0, c.qe, d, tr, match, mismatch, X, lane_steps, t,
-                                     run, best, bl);
-        uint32_t slot = queue_slot(!done, qcount, lane);
-        if (!done) {
-            if (slot < qcap) queue[slot] = XWalk{i, t, run, best, bl};
-            else xdrop_lane<true>(q, dbw, s0, c.qe, d, tr, match, mismatch, X, INT32_MAX, t, run,
-                                  best, bl);
+    const uint64_t nwave = (uint64_t)gridDim.x * (kBlock / 64);
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t items = 2ull * n;  // walk w: run w / 2, left side when w is odd
+    const uint64_t per = (items + nwave - 1) / nwave;
+    uint64_t next = wave * per;
+    const uint64_t stop = min(items, next + per);
+    const uint64_t below = (1ull << lane) - 1ull;
+    bool have = false, left = false;
+    uint32_t ri = 0;
+    Cand c{0, 0, 0, 0, 0};
+    int64_t gq = 0, gb = 0;
+    int32_t T = 0, t = 0, run = 0, best = 0, bl = 0, cap = 0;
+    for (;;) {
+        // lanes without a walk take the next walks of the wave's range
+        const uint64_t need = __ballot(!have);
+        if (need && next < stop) {
+            if (!have) {
+                const uint64_t w = next + (uint64_t)__popcll(need & below);
+                if (w < stop) {
+                    have = true;
+                    ri = (uint32_t)(w >> 1);
+                    left = (w & 1) != 0;
+                    c = cands[ri];
+                    const int64_t q0 = qoff[qa + c.q];
+                    const int32_t L = (int32_t)(qoff[qa + c.q + 1] - q0);
+                    const int64_t s0 = seq_start[c.s];
+                    const int32_t ns = (int32_t)(seq_start[c.s + 1] - s0);
+                    if (left) {
+                        T = min(c.qs, c.qs + c.d);
+                        gq = q0 + c.qs;
+                        gb = s0 + c.qs + c.d;
+                    } else {
+                        T = min(L - c.qe, ns - (c.qe + c.d));
+                        gq = q0 + c.qe;
+                        gb = s0 + c.qe + c.d;
+                    }
+                    t = run = best = bl = 0;
+                    cap = lane_steps;
+                }
+            }
+            next += (uint64_t)__popcll(need);
         }
-        const int32_t er = bl;
-        done = xdrop_lane<false>(q, dbw, s0, c.qs, d, tl, match, mismatch, X, lane_steps, t, run,
-                                 best, bl);
-        slot = queue_slot(!done, qcount, lane);
-        if (!done) {
-            if (slot < qcap) queue[slot] = XWalk{i | 0x80000000u, t, run, best, bl};
-            else xdrop_lane<false>(q, dbw, s0, c.qs, d, tl, match, mismatch, X, INT32_MAX, t, run,
-                                   best, bl);
-        }
-        const int32_t el = bl;
-        // a queued side is rewritten by k_extend_long (it owns qs/ds or qe/de)
-        if (valid) {
-            const int32_t qs = c.qs - el, qe = c.qe + er;
-            out[i] = Box{c.q, c.s, qs, qe, qs + d, qe + d, d, d};
+        if (__ballot(have) == 0) break;
+        bool done = false;
+        if (have)
+            done = left ? xdrop_words<false>(qpack, gq, dbw, gb, T, match, mismatch, X, cap, t,
+                                             run, best, bl)
+                        : xdrop_words<true>(qpack, gq, dbw, gb, T, match, mismatch, X, cap, t,
+                                            run, best, bl);
+        // a walk past the lane's cap goes to the queue for a whole wave
+        const bool park = have && !done;
+        const uint32_t slot = queue_slot(park, qcount, lane);
+        const bool queued = park && slot < qcap;
+        if (queued) queue[slot] = XWalk{ri | (left ? 0x80000000u : 0u), t, run, best, bl};
+        if (park && !queued) cap = INT32_MAX;  // queue full: this lane finishes the walk
+        if (done || queued) {
+            Box *b = out + ri;
+            if (left) {
+                b->qs = c.qs - bl;
+                b->ds = c.qs - bl + c.d;
+            } else {
+                b->q = c.q;
+                b->s = c.s;
+                b->qe = c.qe + bl;
+                b->de = c.qe + bl + c.d;
+                b->dmin = c.d;
+                b->dmax = c.d;
+            }
+            have = false;
         }
     }
 }
@@ -2464,9 +2599,9 @@ size_t extend_queue_bytes(uint32_t n)
            256;
 }
 
-void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_t *qoff,
-                   int32_t qa, const uint32_t *dbw, const int64_t *seq_start, int32_t match,
-                   int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
+void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const uint32_t *qpack,
+                   const int64_t *qoff, int32_t qa, const uint32_t *dbw, const int64_t *seq_start,
+                   int32_t match, int32_t mismatch, int32_t xdrop, Box *out, void *queue_mem,
                    int32_t lane_steps, hipStream_t st, const WaveCtl *ctl, uint32_t n_cap,
                    bool count_cleared)
 {
@@ -2477,8 +2612,11 @@ void launch_extend(const Cand *c, uint32_t n, const uint8_t *qcode, const int64_
     XWalk *queue = reinterpret_cast<XWalk *>(static_cast<char *>(queue_mem) + 256);
     const uint32_t qcap = (uint32_t)((extend_queue_bytes(nmax) - 256) / sizeof(XWalk));
     if (!count_cleared) launch_fill_u32(qcount, 1, 0u, st);
-    const uint32_t nb = ctl ? kStrideGrid : std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid);
-    k_extend<<<nb, kBlock, 0, st>>>(c, n, qcode, qoff, qa, dbw, seq_start, match, mismatch, xdrop,
+    // one wave per 64 walks up to 8 waves per SIMD on every CU; beyond that each
+    // wave's range grows
+    const uint32_t nb = ctl ? kStrideGrid
+                            : (uint32_t)std::min<uint64_t>((2ull * n + kBlock - 1) / kBlock, 8192);
+    k_extend<<<nb, kBlock, 0, st>>>(c, n, qpack, qoff, qa, dbw, seq_start, match, mismatch, xdrop,
                                     out, queue, qcap, qcount, std::max(lane_steps, 0), ctl);
     const uint64_t most = std::min<uint64_t>(2ull * nmax, qcap);  // queued walks at most
     const uint32_t lb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((most + 3) / 4, 1u << 16));

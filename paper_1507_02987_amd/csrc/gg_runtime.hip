@@ -100,7 +100,7 @@ struct StageTime {
 struct Workspace {
     int device = 0;
     hipStream_t st = nullptr;
-    DevBuf ascii, qoff, qcode, kcode, cnt, lhead, qid, hoff, partials, qtot, err;
+    DevBuf ascii, qoff, qcode, qpack, kcode, cnt, lhead, qid, hoff, partials, qtot, err;
     DevBuf hrel, pbase, akey, keys, keys_alt, hist, rs_partials;
     DevBuf cands, ccount, cand_q, cand_off, boxes, boxes2, boxes3, wkeys, wkeys_alt, perm, perm_alt;
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
@@ -134,7 +134,7 @@ struct Workspace {
     {
         if (st) (void)hipSetDevice(device);
         if (gexec) (void)hipGraphExecDestroy(gexec);
-        DevBuf *all[] = {&ascii, &qoff, &qcode, &kcode, &cnt, &lhead, &qid, &hoff, &partials, &qtot, &err,
+        DevBuf *all[] = {&ascii, &qoff, &qcode, &qpack, &kcode, &cnt, &lhead, &qid, &hoff, &partials, &qtot, &err,
                          &hrel, &pbase, &akey, &keys, &keys_alt, &hist, &rs_partials, &cands,
                          &ccount, &cand_q, &cand_off, &boxes, &boxes2, &boxes3, &wkeys, &wkeys_alt, &perm,
                          &perm_alt, &qstart, &qend, &nsel, &sel_off, &rstart, &rend, &aligns, &aligns2,
@@ -874,7 +874,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     TRY(ensure(ws->boxes3, sizeof(Box) * nc));
     TRY(ensure(ws->xqueue, extend_queue_bytes(nc)));
     prof.begin("extend");
-    launch_extend(as<Cand>(ws->cands), nc, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), qa,
+    launch_extend(as<Cand>(ws->cands), nc, as<uint8_t>(ws->qcode), as<uint32_t>(ws->qpack),
+                  as<int64_t>(ws->qoff), qa,
                   ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop, as<Box>(ws->boxes),
                   ws->xqueue.p, ix->tune_lane_steps.load(), st);
     prof.end(nc);
@@ -1368,7 +1369,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     int32_t *gn = bo.device ? bo.n_out : as<int32_t>(ws->gn);
     key.push_back((uint64_t)(uintptr_t)gout);
     key.push_back((uint64_t)(uintptr_t)gn);
-    for (const DevBuf *b : {&ws->hoff, &ws->qoff, &ws->kcode, &ws->qid, &ws->qcode, &ws->hrel,
+    for (const DevBuf *b : {&ws->hoff, &ws->qoff, &ws->kcode, &ws->qid, &ws->qcode, &ws->qpack,
+                            &ws->hrel,
                             &ws->pbase, &ws->akey, &ws->keys, &ws->keys_alt, &ws->hist,
                             &ws->rs_partials, &ws->ccount, &ws->partials, &ws->cands, &ws->boxes,
                             &ws->boxes2, &ws->boxes3, &ws->xqueue, &ws->qstart, &ws->qend,
@@ -1415,7 +1417,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                                as<uint32_t>(ws->qend), as<uint32_t>(ws->cand_q),
                                as<uint32_t>(ws->cand_off), static_cast<uint32_t *>(ws->xqueue.p),
                                ctl, st);
-        launch_extend(as<Cand>(ws->cands), 0, as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0,
+        launch_extend(as<Cand>(ws->cands), 0, as<uint8_t>(ws->qcode), as<uint32_t>(ws->qpack),
+                      as<int64_t>(ws->qoff), 0,
                       ix->d_dbw, ix->d_seq_start, p->match, p->mismatch, p->xdrop,
                       as<Box>(ws->boxes), ws->xqueue.p, steps, st, ctl, hits_cap,
                       /*count_cleared=*/true);
@@ -1562,6 +1565,8 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     launch_query_totals(as<uint64_t>(ws->hoff), as<int64_t>(ws->qoff), (int32_t)nq,
                         as<uint64_t>(ws->qtot), st);
     prof.end(T);
+    TRY(ensure(ws->qpack, sizeof(uint32_t) * ((size_t)(T + 15) / 16 + 2)));
+    launch_pack_query(as<uint8_t>(ws->qcode), T, as<uint32_t>(ws->qpack), st);
     HIPCHK(hipMemcpyAsync(h_qtot, ws->qtot.p, sizeof(uint64_t) * nq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_err, ws->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SYNC(st);
