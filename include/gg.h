@@ -38,7 +38,8 @@ typedef enum {
     GG_ETRUNC = 5,    /* more hits than `cap`: the first `cap` are written, *n_out is the count */
     GG_ENOTFOUND = 6, /* unknown or already collected ticket */
     GG_EBUDGET = 7,   /* one query's hits on one sequence do not fit the hit budget */
-    GG_EIO = 8        /* an index file cannot be opened, read or written, or is not one */
+    GG_EIO = 8,       /* an index file cannot be opened, read or written, or is not one */
+    GG_ESCRATCH = 9   /* the call needs more device scratch than gg_traceback_noalloc holds */
 } gg_status;
 
 typedef struct gg_index gg_index;   /* device-resident data bank and inverted index */
@@ -212,6 +213,23 @@ gg_status gg_index_load(const char *path, int32_t device, gg_index **out);
  */
 gg_status gg_karlin_altschul(int32_t match, int32_t mismatch, double *lambda, double *K,
                              double *H);
+/*
+ * gg_traceback without any device allocation, for callers that cannot allocate
+ * GPU memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, outputs and errors are those of gg_traceback, and
+ * so are the paths, byte for byte.  Its device scratch (the hits, the query,
+ * offsets, the operations and the direction rows, 64 bytes per query row of each
+ * hit) lives in one static array of GG_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds from the first call on that GPU until the process ends; it calls
+ * no hipMalloc or hipFree.  A call whose scratch would exceed the array returns
+ * GG_ESCRATCH with nothing computed (use gg_traceback).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU race and must be
+ * serialised by the caller.  The transfers go through the default stream.
+ */
+#define GG_NOALLOC_SCRATCH_BYTES (64u << 20)
+gg_status gg_traceback_noalloc(const gg_index *index, const char *query, int64_t qlen,
+                               const gg_params *params, const gg_hit *hits, int32_t n, char *ops,
+                               int64_t ops_cap, int64_t *ops_off, int32_t *ops_len);
 gg_status gg_hit_significance(const gg_hit *hits, int64_t n, int64_t query_len, int64_t bank_bases,
                               double lambda, double K, double *bit_score, double *evalue);
 gg_status gg_traceback(const gg_index *index, const char *query, int64_t qlen,

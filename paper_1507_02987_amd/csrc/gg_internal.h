@@ -349,6 +349,10 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
                 unsigned long long *cells_per_q, unsigned long long *cells_per_box,
                 hipStream_t st, const WaveCtl *ctl = nullptr, const uint32_t *sel_box = nullptr);
+// dir_off[h] = 64 * (sum of q_end - q_start over hits before h), h in [0, n].
+void launch_dir_offsets(const int32_t *hits, int32_t n, int64_t *dir_off, hipStream_t st);
+// ops_len[h] = -1 where status[h] != 0.
+void launch_fold_status(int32_t *ops_len, const int32_t *status, int32_t n, hipStream_t st);
 // Results of queries [qa, qa + nq) as gg_hit records (11 int32) in device memory.
 void launch_write_out(const Align *sorted, const uint32_t *rstart, const uint32_t *rend,
                       int32_t nq, int32_t qa, int32_t cap, int32_t *out, int32_t *n_out,

@@ -3899,6 +3899,41 @@ void launch_traceback(const int32_t *hits, int32_t n, const uint8_t *qascii, int
                                      dirs, ops_off, ops, ops_len, status);
 }
 
+// Offsets of each hit's direction rows (64 bytes per query row of its rectangle),
+// from the hits themselves, for callers that keep no host copy of them: one
+// thread walks the hits in order.
+__global__ void k_dir_offsets(const int32_t *__restrict__ hits, int32_t n,
+                              int64_t *__restrict__ dir_off)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int32_t h = 0; h < n; ++h) {
+        dir_off[h] = acc;
+        const int32_t *hr = hits + (size_t)h * kHitInts;
+        acc += 64 * (int64_t)max(hr[3] - hr[2], 0);
+    }
+    dir_off[n] = acc;
+}
+
+// ops_len[h] = -1 where the walk failed (status 1), so one array carries both.
+__global__ void k_fold_status(int32_t *__restrict__ ops_len, const int32_t *__restrict__ status,
+                              int32_t n)
+{
+    const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < n && status[h] != 0) ops_len[h] = -1;
+}
+
+void launch_dir_offsets(const int32_t *hits, int32_t n, int64_t *dir_off, hipStream_t st)
+{
+    k_dir_offsets<<<1, 64, 0, st>>>(hits, n, dir_off);
+}
+
+void launch_fold_status(int32_t *ops_len, const int32_t *status, int32_t n, hipStream_t st)
+{
+    if (n <= 0) return;
+    k_fold_status<<<(uint32_t)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(ops_len, status, n);
+}
+
 // ------------------------------------------------------------------ results to device memory
 // One block per query: its first min(cap, n) ordered alignments become gg_hit
 // records at out[q * cap], and its count goes to n_out[q].

@@ -1735,6 +1735,7 @@ const char *gg_strerror(gg_status s)
     case GG_ENOTFOUND: return "unknown ticket";
     case GG_EBUDGET: return "query exceeds the hit-buffer budget";
     case GG_EIO: return "index file cannot be read or written, or is damaged";
+    case GG_ESCRATCH: return "call needs more than the allocation-free scratch";
     default: return "unknown status";
     }
 }
@@ -2513,6 +2514,114 @@ gg_status gg_traceback(const gg_index *ix, const char *query, int64_t qlen, cons
         ops_len[h] = status[(size_t)h] == 0 ? len[(size_t)h] : 0;
         all_ok = all_ok && status[(size_t)h] == 0;
         memcpy(ops + ops_off[h], slots.data() + ops_off[h] + slot - ops_len[h], (size_t)ops_len[h]);
+    }
+    return all_ok ? GG_OK : GG_EINVAL;
+}
+
+}  // extern "C"
+
+// ---- allocation-free traceback
+// Device scratch of gg_traceback_noalloc: one file-scope array per GPU, held until
+// the process ends.  Host code never passes the array's name to a kernel or a copy
+// (on the host it is only a stand-in for the symbol): it looks up each device's
+// own address once, with that device current, and uses that address.
+namespace {
+
+static __device__ __align__(256) uint8_t scratch[GG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
+gg_status scratch_of(int device, uint8_t **out)
+{
+    if (device < 0 || device >= kMaxDevices) return GG_EDEVICE;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipSetDevice(device) != hipSuccess ||
+            hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return GG_EDEVICE;
+        }
+        scratch_ptr[device] = p;
+    }
+    *out = static_cast<uint8_t *>(scratch_ptr[device]);
+    return GG_OK;
+}
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+gg_status gg_traceback_noalloc(const gg_index *ix, const char *query, int64_t qlen,
+                               const gg_params *params, const gg_hit *hits, int32_t n, char *ops,
+                               int64_t ops_cap, int64_t *ops_off, int32_t *ops_len)
+{
+    if (!ix || qlen < 0 || qlen > INT32_MAX || (qlen > 0 && !query) || n < 0 ||
+        (n > 0 && (!hits || !ops_off || !ops_len)))
+        return GG_EINVAL;
+    TRY(check_params(params));
+    ops_off[0] = 0;
+    int64_t rows = 0;
+    for (int32_t h = 0; h < n; ++h) {
+        const gg_hit &x = hits[h];
+        if (x.seq_id < 0 || x.seq_id >= ix->n_seqs || x.q_start < 0 || x.q_end <= x.q_start ||
+            x.q_end > qlen || x.d_start < 0 || x.d_end <= x.d_start || x.score <= 0)
+            return GG_EINVAL;
+        const int64_t R = x.q_end - x.q_start, C = x.d_end - x.d_start;
+        ops_off[h + 1] = ops_off[h] + R + C;
+        rows += R;
+    }
+    if (n == 0) return GG_OK;
+    if (ops_cap < ops_off[n] || !ops) return GG_ETRUNC;
+    // scratch layout: hits | query | direction offsets | operation offsets |
+    // lengths | statuses | operations | direction rows
+    const size_t o_hits = 0;
+    const size_t o_q = o_hits + up256(sizeof(gg_hit) * (size_t)n);
+    const size_t o_doff = o_q + up256((size_t)qlen);
+    const size_t o_ooff = o_doff + up256(sizeof(int64_t) * ((size_t)n + 1));
+    const size_t o_len = o_ooff + up256(sizeof(int64_t) * ((size_t)n + 1));
+    const size_t o_st = o_len + up256(sizeof(int32_t) * (size_t)n);
+    const size_t o_ops = o_st + up256(sizeof(int32_t) * (size_t)n);
+    const size_t o_dir = o_ops + up256((size_t)ops_off[n]);
+    const size_t need = o_dir + 64 * (size_t)rows;
+    if (need > (size_t)GG_NOALLOC_SCRATCH_BYTES) return GG_ESCRATCH;
+    uint8_t *sp = nullptr;
+    TRY(scratch_of(ix->device, &sp));
+    if (hipSetDevice(ix->device) != hipSuccess) return GG_EDEVICE;
+    // every scratch byte a kernel reads is written earlier in this call, so what a
+    // previous call left there does not matter
+    hipStream_t st = nullptr;
+    HIPCHK(hipMemcpy(sp + o_hits, hits, sizeof(gg_hit) * (size_t)n, hipMemcpyHostToDevice));
+    if (qlen > 0) HIPCHK(hipMemcpy(sp + o_q, query, (size_t)qlen, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(sp + o_ooff, ops_off, sizeof(int64_t) * ((size_t)n + 1),
+                     hipMemcpyHostToDevice));
+    int32_t *d_len = reinterpret_cast<int32_t *>(sp + o_len);
+    launch_dir_offsets(reinterpret_cast<const int32_t *>(sp + o_hits), n,
+                       reinterpret_cast<int64_t *>(sp + o_doff), st);
+    launch_traceback(reinterpret_cast<const int32_t *>(sp + o_hits), n, sp + o_q, qlen, ix->d_dbw,
+                     ix->d_seq_start, (int32_t)ix->n_seqs, params->match, params->mismatch,
+                     params->gap_open, params->gap_extend, params->band,
+                     reinterpret_cast<const int64_t *>(sp + o_doff), sp + o_dir,
+                     reinterpret_cast<const int64_t *>(sp + o_ooff),
+                     reinterpret_cast<char *>(sp + o_ops), d_len,
+                     reinterpret_cast<int32_t *>(sp + o_st), st);
+    launch_fold_status(d_len, reinterpret_cast<const int32_t *>(sp + o_st), n, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(ops, sp + o_ops, (size_t)ops_off[n], hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ops_len, d_len, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost));
+    // each path was written right-aligned in its slot; move it to the slot's start
+    bool all_ok = true;
+    for (int32_t h = 0; h < n; ++h) {
+        if (ops_len[h] < 0) {
+            ops_len[h] = 0;
+            all_ok = false;
+        }
+        const int64_t slot = ops_off[h + 1] - ops_off[h];
+        memmove(ops + ops_off[h], ops + ops_off[h] + slot - ops_len[h], (size_t)ops_len[h]);
     }
     return all_ok ? GG_OK : GG_EINVAL;
 }

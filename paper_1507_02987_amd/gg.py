@@ -14,10 +14,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgg.so")
 
-GG_OK, GG_EINVAL, GG_ENOMEM, GG_EDEVICE, GG_EAGAIN, GG_ETRUNC, GG_ENOTFOUND, GG_EBUDGET, GG_EIO = \
-    range(9)
+(GG_OK, GG_EINVAL, GG_ENOMEM, GG_EDEVICE, GG_EAGAIN, GG_ETRUNC, GG_ENOTFOUND, GG_EBUDGET, GG_EIO,
+ GG_ESCRATCH) = range(10)
 STATUS = {0: "GG_OK", 1: "GG_EINVAL", 2: "GG_ENOMEM", 3: "GG_EDEVICE", 4: "GG_EAGAIN",
-          5: "GG_ETRUNC", 6: "GG_ENOTFOUND", 7: "GG_EBUDGET", 8: "GG_EIO"}
+          5: "GG_ETRUNC", 6: "GG_ENOTFOUND", 7: "GG_EBUDGET", 8: "GG_EIO", 9: "GG_ESCRATCH"}
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 HIT_FIELDS = ("seq_id", "score", "q_start", "q_end", "d_start", "d_end",
               "box_q_start", "box_q_end", "box_d_start", "box_d_end", "box_len",
@@ -29,7 +30,7 @@ STAT_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
 # Exported symbols of include/gg.h, in declaration order.
 SYMBOLS = ("gg_index_build", "gg_index_build_masked", "gg_index_build_ex", "gg_index_free",
            "gg_index_info", "gg_index_export", "gg_index_save", "gg_index_load",
-           "gg_karlin_altschul", "gg_hit_significance", "gg_traceback",
+           "gg_karlin_altschul", "gg_traceback_noalloc", "gg_hit_significance", "gg_traceback",
            "gg_index_set_hit_budget",
            "gg_index_get_tuning", "gg_index_set_tuning", "gg_index_autotune",
            "gg_search", "gg_search_batch", "gg_search_batch_device", "gg_device_alloc",
@@ -120,6 +121,8 @@ def lib():
         L.gg_karlin_altschul.argtypes = [i32, i32, dp, dp, dp]
         L.gg_hit_significance.argtypes = [vp, i64, i64, i64, C.c_double, C.c_double, vp, vp]
         L.gg_traceback.argtypes = [vp, vp, i64, C.POINTER(Params), vp, i32, vp, i64, vp, vp]
+        L.gg_traceback_noalloc.argtypes = [vp, vp, i64, C.POINTER(Params), vp, i32, vp, i64, vp,
+                                           vp]
         L.gg_index_load.argtypes = [C.c_char_p, i32, C.POINTER(vp)]
         L.gg_index_free.argtypes = [vp]
         L.gg_index_free.restype = None
@@ -255,8 +258,9 @@ class Index:
             raise GGError(rc, "gg_index_export")
         return heads, post[:n]
 
-    def traceback(self, query, prm: Params, hits: np.ndarray):
-        """gg_traceback: (status, list of operation strings, one per hit)."""
+    def traceback(self, query, prm: Params, hits: np.ndarray, noalloc: bool = False):
+        """gg_traceback (gg_traceback_noalloc when noalloc): (status, list of
+        operation strings, one per hit)."""
         q = _u8(query)
         h = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
         n = len(h)
@@ -265,8 +269,9 @@ class Index:
         spans = (h["q_end"].astype(np.int64) - h["q_start"]) + (h["d_end"] - h["d_start"])
         cap = int(spans.clip(min=0).sum()) if n else 0
         buf = np.zeros(max(cap, 1), np.uint8)
-        rc = lib().gg_traceback(self._h, _ptr(q) if len(q) else None, len(q), C.byref(prm),
-                                _ptr(h) if n else None, n, _ptr(buf), cap, _ptr(off), _ptr(ln))
+        fn = lib().gg_traceback_noalloc if noalloc else lib().gg_traceback
+        rc = fn(self._h, _ptr(q) if len(q) else None, len(q), C.byref(prm),
+                _ptr(h) if n else None, n, _ptr(buf), cap, _ptr(off), _ptr(ln))
         if rc not in (GG_OK, GG_EINVAL) or (rc == GG_EINVAL and n and off[n] == 0):
             return rc, []
         return rc, [buf[off[i]:off[i] + ln[i]].tobytes().decode() for i in range(n)]
