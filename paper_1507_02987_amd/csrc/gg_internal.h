@@ -320,6 +320,17 @@ void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Ali
 void launch_merge_select_seg(const Box *in, Box *out, const uint32_t *seg_off, int32_t nq_cap,
                              WaveCtl *ctl, hipStream_t st);
 void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st);
+// Merge (order and sweep) of boxes grouped by (query, sequence), fresh from the
+// extension, in windows of whole groups held in LDS; keys (group rank | qs |
+// d + bias | qe) take 12 + 2 bl + bd <= 64 bits.  Groups that may outgrow a
+// window are listed in big: big[0] = count, then (first, end) pairs, at most
+// big_cap of them; their positions in `out` are left for the global sort.
+void launch_merge_tiles(const Box *in, uint32_t n, int bl, int bd, int32_t bias, Box *out,
+                        uint32_t *big, uint32_t big_cap, hipStream_t st);
+// Boxes of ranges [ranges[2r], ranges[2r + 1]) to (to_packed) or from a packed
+// array starting at offs[r].
+void launch_copy_ranges(const Box *src, Box *dst, const uint32_t *ranges, const uint32_t *offs,
+                        uint32_t nr, bool to_packed, hipStream_t st);
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,
                          uint32_t *qend, hipStream_t st);
 void launch_segments_align(const Align *sorted, uint32_t n, int32_t nq, uint32_t *qstart,

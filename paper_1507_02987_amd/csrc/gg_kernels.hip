@@ -2996,6 +2996,204 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
     }
 }
 
+// S7 in windows of whole groups.  Boxes leave the extension grouped by (query,
+// sequence), and a merge only ever joins boxes of one group, so each group can be
+// ordered by (qs, ds, qe, de) and swept on its own.  Block b owns the groups that
+// start in positions [b W, b W + W) (W = kMergeWin); a group of at most W boxes
+// ends before b W + 2 W, so the block holds all its boxes.  Each box of an owned
+// group becomes one 64-bit key (group rank | qs | d + bias | qe): the boxes leave
+// the extension unmerged, so ds = qs + d and de = qe + d, and the key orders a
+// group exactly as (qs, ds, qe, de) does (equal keys are equal boxes).  The keys
+// are sorted in LDS (bitonic) and each owned group is then swept from its keys by
+// one thread, as k_merge_sweep does: merged boxes from the group's first
+// position, the rest marked empty.  A group that may not fit (the last one the
+// block owns, when no other group starts before the block's reach) is recorded
+// in big[1 ..] as (first, end) and left to the global sort; big[0] counts them.
+constexpr uint32_t kMergeWin = 1024;
+constexpr uint32_t kMergeSpan = 2 * kMergeWin;
+
+__global__ __launch_bounds__(kBlock) void k_merge_tiles(const Box *__restrict__ in, uint32_t n,
+                                                        int bl, int bd, int32_t bias,
+                                                        Box *__restrict__ out,
+                                                        uint32_t *__restrict__ big, uint32_t big_cap)
+{
+    __shared__ uint64_t s_key[kMergeSpan];
+    __shared__ uint16_t s_start[kMergeSpan + 1];
+    __shared__ uint16_t s_rank[kMergeSpan];
+    __shared__ uint32_t s_wc[kBlock / 64];
+    __shared__ uint32_t s_nw, s_end;
+    const uint32_t base = blockIdx.x * kMergeWin;
+    if (base >= n) return;
+    const uint32_t lim = min(base + kMergeSpan, n);
+    const uint32_t R = lim - base;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    // group starts in [base, lim), in order, and each position's group rank
+    uint32_t ns = 0;
+    for (uint32_t u = 0; u < kMergeSpan / kBlock; ++u) {
+        const uint32_t r = u * kBlock + threadIdx.x;
+        bool f = false;
+        if (r < R) {
+            const uint32_t p = base + r;
+            if (p == 0) {
+                f = true;
+            } else {
+                const int2 a = *reinterpret_cast<const int2 *>(in + p);
+                const int2 b = *reinterpret_cast<const int2 *>(in + p - 1);
+                f = a.x != b.x || a.y != b.y;
+            }
+        }
+        const uint64_t m = __ballot(f);
+        if (lane == 0) s_wc[wv] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = ns, round = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wv) before += s_wc[w];
+            round += s_wc[w];
+        }
+        const uint32_t at = before + (uint32_t)__popcll(m & below);
+        if (f) s_start[at] = (uint16_t)r;
+        // rank of r's group among the range's starts (positions before the first
+        // start belong to an earlier block's group and are never used)
+        if (r < R) s_rank[r] = (uint16_t)(at + (f ? 1u : 0u) - 1u);
+        ns += round;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        s_start[ns] = (uint16_t)R;
+        uint32_t nw = 0;  // owned groups: starts below kMergeWin
+        while (nw < ns && s_start[nw] < kMergeWin) ++nw;
+        s_nw = nw;
+    }
+    __syncthreads();
+    uint32_t nw = s_nw;
+    if (nw == 0) return;
+    if (nw == ns && lim < n) {
+        // the last owned group reaches past the range: find its end, leave it to
+        // the global sort
+        const uint32_t p0 = base + s_start[nw - 1];
+        if (wv == 0) {
+            const int2 g = *reinterpret_cast<const int2 *>(in + p0);
+            uint32_t end = n;
+            for (uint32_t p = lim; p < n; p += 64) {
+                const uint32_t pp = p + lane;
+                bool other = false;
+                if (pp < n) {
+                    const int2 a = *reinterpret_cast<const int2 *>(in + pp);
+                    other = a.x != g.x || a.y != g.y;
+                }
+                const uint64_t m = __ballot(other);
+                if (m) {
+                    end = p + (uint32_t)__ffsll((unsigned long long)m) - 1;
+                    break;
+                }
+            }
+            if (lane == 0) {
+                const uint32_t slot = atomicAdd(big, 1u);
+                if (slot < big_cap) {
+                    big[1 + 2 * slot] = p0;
+                    big[2 + 2 * slot] = end;
+                }
+            }
+        }
+        --nw;
+    }
+    if (nw == 0) return;
+    const uint32_t o = s_start[0], m = s_start[nw] - o;  // keys of the owned small groups
+    uint32_t n2 = 1;
+    while (n2 < m) n2 <<= 1;
+    const uint64_t mbl = (1ull << bl) - 1ull, mbd = (1ull << bd) - 1ull;
+    for (uint32_t j = threadIdx.x; j < n2; j += kBlock) {
+        uint64_t key = ~0ull;
+        if (j < m) {
+            const Box b = in[base + o + j];
+            const uint64_t rank = (uint64_t)(s_rank[o + j] - s_rank[o]);
+            const uint64_t d = (uint64_t)(uint32_t)(b.ds - b.qs + bias);
+            key = (rank << (2 * bl + bd)) | ((uint64_t)(uint32_t)b.qs << (bl + bd)) |
+                  ((d & mbd) << bl) | ((uint64_t)(uint32_t)b.qe & mbl);
+        }
+        s_key[j] = key;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += kBlock) {
+                const uint32_t l = i ^ jj;
+                if (l > i) {
+                    const uint64_t a = s_key[i], b = s_key[l];
+                    if (((i & k) == 0) ? (a > b) : (a < b)) {
+                        s_key[i] = b;
+                        s_key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // sweep each owned group from its keys
+    for (uint32_t g = threadIdx.x; g < nw; g += kBlock) {
+        const uint32_t j0 = s_start[g] - o, j1 = s_start[g + 1] - o;
+        const int2 qsid = *reinterpret_cast<const int2 *>(in + base + o + j0);
+        auto decode = [&](uint64_t key) {
+            const int32_t qe = (int32_t)(key & mbl);
+            const int32_t d = (int32_t)((key >> bl) & mbd) - bias;
+            const int32_t qs = (int32_t)((key >> (bl + bd)) & mbl);
+            return Box{qsid.x, qsid.y, qs, qe, qs + d, qe + d, d, d};
+        };
+        Box cur = decode(s_key[j0]);
+        uint32_t w = j0;
+        for (uint32_t j = j0 + 1; j < j1; ++j) {
+            const Box h = decode(s_key[j]);
+            if (h.qs < cur.qe && h.ds < cur.de && cur.ds < h.de) {
+                cur.qs = min(cur.qs, h.qs);
+                cur.qe = max(cur.qe, h.qe);
+                cur.ds = min(cur.ds, h.ds);
+                cur.de = max(cur.de, h.de);
+                cur.dmin = min(cur.dmin, h.dmin);
+                cur.dmax = max(cur.dmax, h.dmax);
+            } else {
+                out[base + o + w++] = cur;
+                cur = h;
+            }
+        }
+        out[base + o + w++] = cur;
+        for (; w < j1; ++w) out[base + o + w].q = -1;
+    }
+}
+
+// Copy the boxes of nr ranges [ranges[2r], ranges[2r + 1]) between their place
+// in `pos` and a packed array (to_packed: pos -> packed at offs[r]; else back).
+__global__ void k_copy_ranges(const Box *__restrict__ src, Box *__restrict__ dst,
+                              const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ offs,
+                              uint32_t nr, int to_packed)
+{
+    for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
+        const uint32_t a = ranges[2 * r], b = ranges[2 * r + 1], o = offs[r];
+        for (uint32_t i = threadIdx.x; i < b - a; i += blockDim.x) {
+            if (to_packed) dst[o + i] = src[a + i];
+            else dst[a + i] = src[o + i];
+        }
+    }
+}
+
+void launch_merge_tiles(const Box *in, uint32_t n, int bl, int bd, int32_t bias, Box *out,
+                        uint32_t *big, uint32_t big_cap, hipStream_t st)
+{
+    if (n == 0) return;
+    launch_fill_u32(big, 1, 0u, st);
+    const uint32_t nb = (n + kMergeWin - 1) / kMergeWin;
+    k_merge_tiles<<<nb, kBlock, 0, st>>>(in, n, bl, bd, bias, out, big, big_cap);
+}
+
+void launch_copy_ranges(const Box *src, Box *dst, const uint32_t *ranges, const uint32_t *offs,
+                        uint32_t nr, bool to_packed, hipStream_t st)
+{
+    if (nr == 0) return;
+    k_copy_ranges<<<std::min<uint32_t>(nr, 65536), kBlock, 0, st>>>(src, dst, ranges, offs, nr,
+                                                                    to_packed ? 1 : 0);
+}
+
 void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st)
 {
     if (n) {

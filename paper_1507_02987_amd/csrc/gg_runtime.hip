@@ -111,6 +111,7 @@ struct Workspace {
     DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
     DevBuf fkept, fkoff, fflag, ford;   // lone-diagonal filter (ford: largest query first)
     DevBuf tpos;                        // the position where each gather tile starts
+    DevBuf mbig, mranges;               // merge groups that may outgrow an LDS window
     DevBuf selbox;                      // the box index of each selection (replayed waves)
     DevBuf bq;                          // the query of each encode block's first base
     // small pinned staging: [0] a wave's counts, [1] a batch's query offsets and hit
@@ -143,7 +144,8 @@ struct Workspace {
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
-                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox, &bq};
+                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox, &bq,
+                         &mbig, &mranges};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -435,6 +437,15 @@ void filter_order(const uint64_t *qtot, int32_t nqw, int32_t *order)
     for (int32_t x = 0; x < nqw; ++x) ++start[key(x) + 1];
     for (int k = 1; k < 66; ++k) start[k] += start[k - 1];
     for (int32_t x = 0; x < nqw; ++x) order[start[key(x)]++] = x;
+}
+
+// The merge of large waves orders and sweeps each (query, sequence) group in LDS
+// windows (k_merge_tiles); GG_MERGE=global sends every box through the global
+// record sort instead.
+bool merge_windows_enabled()
+{
+    const char *e = std::getenv("GG_MERGE");
+    return !(e && std::strcmp(e, "global") == 0);
 }
 
 bool filter_for(const gg_index *ix, const gg_params *p, uint64_t hits, int64_t nq)
@@ -894,23 +905,79 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     // ---- S7 merge: order each query's boxes by (s, qs, ds, qe, de), sweep each (q, s)
     prof.begin("merge");
     Box *boxes = as<Box>(ws->boxes);
-    if (seg_path) {
-        launch_seg_sort_box(0, boxes, as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nqw, st);
-    } else {
+    const int bdm = bits_for((uint64_t)ix->max_seq_len + (uint64_t)maxL + 1);
+    // windows need each (query, sequence) group contiguous, as the sorted hits
+    // leave the runs; probing writes runs in no such order
+    const bool windows = !seg_path && grouping == kSort && merge_windows_enabled() &&
+                         12 + 2 * bl + bdm <= 64;
+    // global record sort of n boxes by merge order, then the sweep: src -> dst
+    auto global_merge = [&](Box *src, uint32_t n, Box *tmp, Box *dst) -> gg_status {
         TRY(make_words({{F_Q, bq, 0}, {F_S, bs, 0}, {F_QS, bl, 0}, {F_DS, bsl, 0}, {F_QE, bl, 0},
                         {F_DE, bsl, 0}},
                        words));
-        TRY(sort_records(ws, nc, words,
+        TRY(sort_records(ws, n, words,
                          [&](const KeyWord &w, const uint32_t *pm, uint64_t *out) {
-                             launch_box_keys(boxes, nc, w, nqw, out, pm, st);
+                             launch_box_keys(src, n, w, nqw, out, pm, st);
                          },
                          &perm));
-        launch_gather_boxes(boxes, perm, nc, as<Box>(ws->boxes2), st);
+        launch_gather_boxes(src, perm, n, tmp, st);
+        launch_merge_sweep(tmp, n, dst, st);
+        return GG_OK;
+    };
+    if (seg_path) {
+        launch_seg_sort_box(0, boxes, as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nqw, st);
+        prof.end(nc);
+        prof.begin("merge_sweep");
+        launch_merge_sweep(as<Box>(ws->boxes2), nc, as<Box>(ws->boxes3), st);
+        prof.end(nc);
+    } else if (windows) {
+        // groups in LDS windows; the few that may outgrow a window by the global sort
+        constexpr uint32_t kBigCap = 1u << 16;
+        TRY(ensure(ws->mbig, sizeof(uint32_t) * (1 + 2 * (size_t)kBigCap)));
+        launch_merge_tiles(boxes, nc, bl, bdm, (int32_t)maxL, as<Box>(ws->boxes3),
+                           as<uint32_t>(ws->mbig), kBigCap, st);
+        uint32_t nbig = 0;
+        HIPCHK(hipMemcpyAsync(h_nc, ws->mbig.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        SYNC(st);
+        nbig = h_nc[0];
+        if (nbig > kBigCap) {
+            TRY(global_merge(boxes, nc, as<Box>(ws->boxes2), as<Box>(ws->boxes3)));
+        } else if (nbig > 0) {
+            std::vector<uint32_t> ranges(2 * (size_t)nbig), offs((size_t)nbig + 1, 0);
+            HIPCHK(hipMemcpyAsync(ranges.data(), as<uint32_t>(ws->mbig) + 1,
+                                  sizeof(uint32_t) * 2 * nbig, hipMemcpyDeviceToHost, st));
+            SYNC(st);
+            // packed in position order, so the global sort keeps the groups' order
+            std::vector<uint32_t> order((size_t)nbig);
+            for (uint32_t r = 0; r < nbig; ++r) order[r] = r;
+            std::sort(order.begin(), order.end(),
+                      [&](uint32_t a, uint32_t b) { return ranges[2 * a] < ranges[2 * b]; });
+            std::vector<uint32_t> sr(2 * (size_t)nbig);
+            for (uint32_t r = 0; r < nbig; ++r) {
+                sr[2 * r] = ranges[2 * order[r]];
+                sr[2 * r + 1] = ranges[2 * order[r] + 1];
+                offs[r + 1] = offs[r] + (sr[2 * r + 1] - sr[2 * r]);
+            }
+            const uint32_t B = offs[nbig];
+            TRY(ensure(ws->mranges, sizeof(uint32_t) * (3 * (size_t)nbig + 1)));
+            uint32_t *d_ranges = as<uint32_t>(ws->mranges), *d_offs = d_ranges + 2 * nbig;
+            HIPCHK(hipMemcpyAsync(d_ranges, sr.data(), sizeof(uint32_t) * 2 * nbig,
+                                  hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(d_offs, offs.data(), sizeof(uint32_t) * nbig,
+                                  hipMemcpyHostToDevice, st));
+            // pack the big groups (boxes2), sort and sweep them (via boxes, no longer
+            // needed), and put them back in their places
+            launch_copy_ranges(boxes, as<Box>(ws->boxes2), d_ranges, d_offs, nbig, true, st);
+            TRY(global_merge(as<Box>(ws->boxes2), B, boxes, as<Box>(ws->boxes2) + 0));
+            launch_copy_ranges(as<Box>(ws->boxes2), as<Box>(ws->boxes3), d_ranges, d_offs, nbig,
+                               false, st);
+            SYNC(st);  // the host vectors above go out of scope
+        }
+        prof.end(nc);
+    } else {
+        TRY(global_merge(boxes, nc, as<Box>(ws->boxes2), as<Box>(ws->boxes3)));
+        prof.end(nc);
     }
-    prof.end(nc);
-    prof.begin("merge_sweep");
-    launch_merge_sweep(as<Box>(ws->boxes2), nc, as<Box>(ws->boxes3), st);
-    prof.end(nc);
 
     // ---- S8 select by length: (kept first, len desc, s, qs, ds, qe, de), first N per query
     prof.begin("select");
