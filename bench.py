@@ -52,10 +52,15 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # of H (2 compares, 2 selects) and the best-cell update (compare, 3 selects)
 ALIGN_OPS_PER_CELL = 22
 SERVE_BUDGET = 16 << 30  # hit-buffer bytes of the served form (16 GiB)
-# Launch choices each workload runs with (picked by gg_index_autotune on that
-# workload; `--autotune` reruns it).  Profiles taken with the same flag agree.
-TUNING = {"large": ("sort", 16), "mid": ("sort", 16), "short": ("sort", 16),
-          "served": ("sort", 16)}
+# Launch choices each workload runs with: grouping, X-drop lane steps, wave size
+# (log2 hits, 0 = the default), graph replay on/off, and the largest query (log2
+# hits) a replayed wave takes (0 = any that fits a wave).  Picked by measurement on
+# each workload (`--autotune` reruns gg_index_autotune instead); profiles taken
+# with the same table agree.  On the 3 Gbp bank, graph waves limited to queries of
+# at most 2^18 hits match the plain loop (long queries) or beat it (short ones),
+# while taking every query that fits loses 10%.
+TUNING = {"large": ("sort", 256, 0, 1, 18), "mid": ("sort", 256, 0, 1, 0),
+          "short": ("sort", 256, 0, 1, 18), "served": ("sort", 256, 0, 1, 18)}
 
 
 def log(msg: str) -> None:
@@ -233,8 +238,8 @@ def set_tuning(gix, which: str, args, sample=None, prm=None) -> dict:
         tun = gix.autotune(sample.buf, sample.off, prm)
         log(f"autotuned on {sample.n} queries in {time.perf_counter() - t:.1f} s: {tun}")
         return tun
-    grouping, lane_steps = TUNING[which]
-    gix.set_tuning(grouping, lane_steps)
+    grouping, lane_steps, wave_log2, graph, graph_qlog2 = TUNING[which]
+    gix.set_tuning(grouping, lane_steps, wave_log2, graph, graph_qlog2)
     return gix.tuning()
 
 
@@ -413,6 +418,8 @@ def main() -> int:
                     help="only copy BYTES device-to-device three times (counter calibration)")
     ap.add_argument("--calibrate-read", type=int, default=0, metavar="BYTES",
                     help="only stream-read BYTES three times (counter calibration)")
+    ap.add_argument("--only-mid", action="store_true",
+                    help="only the mid-size device-resident leg, printed as JSON (profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -429,6 +436,10 @@ def main() -> int:
             else:
                 a.read_sum(nb)
         log(f"{'copied' if args.calibrate_copy else 'stream-read'} {nb} bytes 3 times")
+        return 0
+
+    if args.only_mid:
+        print(json.dumps(mid_leg(args)), flush=True)
         return 0
 
     t = time.perf_counter()

@@ -257,15 +257,27 @@ gg_status gg_index_set_hit_budget(gg_index *index, uint64_t bytes);
  *              1 sort hits in LDS slices of each query's sequence range,
  *              2 radix-sort all hits of a wave (the default).
  * lane_steps : X-drop steps (Section 2.2 phase 3) one lane takes before a whole
- *              wave resumes the walk; 0..4096 (0: every walk by a wave), default 64.
+ *              wave resumes the walk; 0..4096 (0: every walk by a wave), default 256.
  * ms         : gg_index_autotune only: wall time of the sample batch with this
  *              choice (best of its runs).
+ * wave_log2  : hits of one wave of a graph-replayed batch, 2^wave_log2 (10..30;
+ *              0 on input: the default, 25).  Queries with more hits take the
+ *              regular path after the replays.
+ * graph      : 1 (default): batches without statistics, with the radix-sort grouping
+ *              and 1 <= max_hits <= 1024, replay one captured graph per wave;
+ *              0: they never do.
+ * graph_query_log2 : queries with more than 2^graph_query_log2 index hits skip the
+ *              graph and take the regular path (heavy queries mostly outgrow the
+ *              graph's per-query LDS sorts); 0 (default): only the wave size limits.
  * The environment variable GG_GROUPING (probe, bucket, sort) overrides grouping.
  */
 typedef struct {
     int32_t grouping;
     int32_t lane_steps;
     double ms;
+    int32_t wave_log2;
+    int32_t graph;
+    int32_t graph_query_log2;
 } gg_tuning;
 
 gg_status gg_index_get_tuning(const gg_index *index, gg_tuning *out);
@@ -274,9 +286,12 @@ gg_status gg_index_set_tuning(gg_index *index, const gg_tuning *tuning);
 /*
  * Autotuner: search the sample batch (same layout as gg_search_batch; copied once
  * to GPU memory and searched in the device-resident form) under every candidate
- * choice (3 groupings x lane steps 0, 16, 64, 256) after one untimed run, three
- * times each (once if the first timed run takes over twice the best time so far),
- * check that all choices return identical hits, and keep the fastest on the index.
+ * choice (3 groupings x lane steps 0, 64, 256, 4096, then, when the radix-sort
+ * grouping wins, graph waves of 2^23 and 2^27 hits beside the current size, a
+ * per-query graph limit of 2^14 and 2^18 hits, and no graph)
+ * after one untimed run, three times each (once if the first timed run takes over
+ * twice the best time so far), check that all choices return identical hits, and
+ * keep the fastest on the index.
  * chosen (may be NULL) receives it.  Use queries shaped like the real workload;
  * a few hundred are enough.  Errors: those of gg_search_batch, and GG_EDEVICE if
  * two choices disagree (the previous choice is then kept).

@@ -74,8 +74,11 @@ struct WaveCtl {
     uint32_t H;       // hits
     uint32_t nc;      // runs kept (written on the device)
     HitKeyLayout lay;
-    uint32_t overflow;  // a query's runs or selections exceeded the per-query LDS sorts
     uint32_t tile0, ntile;  // the wave's radix tiles in the batch's tile table
+    // per query of the batch: set to 1 when the query's kept hits, runs or
+    // selections outgrew a per-query LDS sort; the wave's other queries go on, and
+    // the host runs the flagged ones again
+    uint32_t *qflag;
 };
 
 // A radix tile of a sort done within query segments: keys [start, start + count)
@@ -238,8 +241,8 @@ void launch_fill2_u32(uint32_t *a, size_t na, uint32_t *b, size_t nb, uint32_t v
 // ---- graph-replayed waves: the kernels below read the wave's sizes from ctl;
 // grids are sized for the largest wave of the batch (hits_cap, np_cap, nq_cap).
 // The first node takes the wave's plan entry plan[*cursor] into ctl; the last
-// records the overflow flag at oflags[*cursor] and advances the cursor.
-void launch_wave_end(const WaveCtl *ctl, uint32_t *cursor, uint32_t *oflags, hipStream_t st);
+// advances the cursor.
+void launch_wave_end(uint32_t *cursor, hipStream_t st);
 void launch_wave_prep_ctl(const uint64_t *hoff, const int64_t *qoff, const uint32_t *lhead,
                           const int32_t *qid, int64_t np_cap, uint32_t *hrel, uint32_t *pbase,
                           uint64_t *akey, const WaveCtl *plan, const uint32_t *cursor,
@@ -249,8 +252,8 @@ void launch_gather_ctl(const uint32_t *hrel, const uint32_t *pbase, const uint64
                        const uint32_t *tile_pos, hipStream_t st);
 // Per-query filter of hits alone on their (s, diag) group and LDS sort of the
 // kept keys, in place (kept counts per query in kept[]; queries too large for the
-// LDS sort set *flag, or ctl->overflow for a replayed wave, whose grid covers
-// nq_cap queries).  The order array, when given, names the wave-local query that
+// LDS sort set *flag, or, in a replayed wave, whose grid covers nq_cap queries,
+// their ctl->qflag entry, and keep no hit).  The order array, when given, names the wave-local query that
 // block r filters (largest first): order[qa + r] for a replayed wave (one array for
 // the batch), order[r] otherwise.  Then the kept keys' compaction in query order into
 // `out` (koff[] = exclusive scan of kept[]; a replayed wave's ctl->H becomes the
@@ -316,7 +319,8 @@ void launch_gather_boxes(const Box *in, const uint32_t *perm, uint32_t n, Box *o
 void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Align *out,
                           hipStream_t st);
 // A replayed wave's merge (sort, sweep) and selection sort of each query's boxes
-// in one launch (in -> out, per-query segments seg_off; overflow as the LDS sorts).
+// in one launch (in -> out, per-query segments seg_off; a query over the LDS sort
+// sets its ctl->qflag entry and is skipped).
 void launch_merge_select_seg(const Box *in, Box *out, const uint32_t *seg_off, int32_t nq_cap,
                              WaveCtl *ctl, hipStream_t st);
 void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st);

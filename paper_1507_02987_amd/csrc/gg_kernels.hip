@@ -1579,21 +1579,11 @@ __global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t *__restrict__ hist,
     }
 }
 
-// Last node of a replayed wave graph: record whether the wave overflowed the
-// per-query LDS sorts, and move the cursor to the next planned wave (the first
-// node, the wave preparation, takes the plan entry at the cursor).
-__global__ void k_wave_end(const WaveCtl *__restrict__ ctl, uint32_t *__restrict__ cursor,
-                           uint32_t *__restrict__ oflags)
-{
-    const uint32_t w = *cursor;
-    oflags[w] = ctl->overflow;
-    *cursor = w + 1;
-}
+// Last node of a replayed wave graph: move the cursor to the next planned wave
+// (the first node, the wave preparation, takes the plan entry at the cursor).
+__global__ void k_wave_end(uint32_t *__restrict__ cursor) { *cursor += 1; }
 
-void launch_wave_end(const WaveCtl *ctl, uint32_t *cursor, uint32_t *oflags, hipStream_t st)
-{
-    k_wave_end<<<1, 1, 0, st>>>(ctl, cursor, oflags);
-}
+void launch_wave_end(uint32_t *cursor, hipStream_t st) { k_wave_end<<<1, 1, 0, st>>>(cursor); }
 
 __global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v)
 {
@@ -1939,11 +1929,17 @@ __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict_
         m = out;
         if ((before - m) * 8u < before) break;  // the rest are (nearly all) real groups
     }
-    if (threadIdx.x == 0) kept[ql] = m;
-    if (m > kFiltCap) {
-        if (threadIdx.x == 0) atomicOr(ctl ? &ctl->overflow : flag, 1u);
-        return;
+    const bool over = m > kFiltCap;
+    if (threadIdx.x == 0) {
+        // a replayed wave drops an overflowing query's hits and flags it; the host
+        // path radix-sorts them (in qpos order) after the compaction
+        kept[ql] = (over && ctl) ? 0u : m;
+        if (over) {
+            if (ctl) ctl->qflag[ctl->qa + ql] = 1u;
+            else atomicOr(flag, 1u);
+        }
     }
+    if (over) return;
     uint32_t n2 = 1;
     while (n2 < m) n2 <<= 1;
     for (uint32_t i = threadIdx.x; i < n2; i += kFiltBlock) s_buf[i] = i < m ? k[i] : ~0ull;
@@ -1977,8 +1973,8 @@ __device__ __forceinline__ uint32_t block_sum(const uint32_t *__restrict__ v, ui
 }
 
 // Each query's kept keys to koff[ql] of `out`, after the scan of the kept counts;
-// a replayed wave learns its sorted count here (none when a query overflowed: the
-// wave is run again by the host).
+// a replayed wave learns its sorted count here (a query flagged by the filter
+// keeps none: the host runs it again).
 __global__ __launch_bounds__(kBlock) void k_hit_compact(const uint64_t *__restrict__ keys,
                                                         const uint32_t *__restrict__ hrel,
                                                         const int64_t *__restrict__ qoff,
@@ -1995,7 +1991,7 @@ __global__ __launch_bounds__(kBlock) void k_hit_compact(const uint64_t *__restri
         nqw = ctl->nqw;
         if (blockIdx.x == 0) {
             const uint32_t total = koff ? koff[nqw] : block_sum(kept, (uint32_t)nqw);
-            if (threadIdx.x == 0) ctl->H = ctl->overflow ? 0u : total;
+            if (threadIdx.x == 0) ctl->H = total;
         }
     }
     const int32_t ql = (int32_t)blockIdx.x;
@@ -2039,34 +2035,99 @@ void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_
 // write after a scan of the tile counts) keep the runs in hit-key order, so they
 // come out grouped by query and sequence.
 //
-// The test on a tile of keys staged in LDS: s_k[1 + l] is key base + l for
-// l < cnt, s_k[cnt + 1] the key after the tile (when i + 1 < n); a walk back that
-// leaves the tile continues in global memory.
+// The tile's keys are staged in LDS: s_k[1 + l] is key base + l for l < cnt, and
+// s_k[cnt + 1] the key after the tile (when base + cnt < n).  Hit a chains to the
+// next hit b when both lie in one (q, s, diag) group and b's window starts at most
+// G past a's window.
+__device__ __forceinline__ bool chains_to(uint64_t a, uint64_t b, int bp, int32_t k, int32_t G)
+{
+    const uint64_t pmask = low_mask(bp);
+    return (a >> bp) == (b >> bp) && (int32_t)(b & pmask) - ((int32_t)(a & pmask) + k) <= G;
+}
+
+// Exclusive maximum over the 256 threads of a block (-1 before thread 0).
+__device__ __forceinline__ int32_t block_excl_max(int32_t v)
+{
+    __shared__ int32_t s_w[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x = max(x, y);
+    }
+    if (lane == 63) s_w[w] = x;
+    int32_t ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = -1;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i)
+        if (i < w) ex = max(ex, s_w[i]);
+    __syncthreads();
+    return ex;
+}
+
+// s_qs[l] = qpos of the first hit of the run that tile hit l belongs to.  Starts
+// inside the tile come from a block-wide running maximum of start positions; the
+// run that enters the tile from before it is walked back once, by wave 0, 64 keys
+// at a time.
+__device__ void tile_run_starts(const uint64_t *__restrict__ s_k,
+                                const uint64_t *__restrict__ keys, uint32_t base, uint32_t cnt,
+                                int bp, int32_t k, int32_t G, int32_t *__restrict__ s_qs)
+{
+    __shared__ int32_t s_carry;
+    const uint64_t pmask = low_mask(bp);
+    const bool enters = cnt > 0 && base > 0 && chains_to(keys[base - 1], s_k[1], bp, k, G);
+    if (threadIdx.x < 64 && enters) {
+        const int lane = threadIdx.x;
+        for (uint32_t c = 0;; c += 64) {
+            // key j = base - 1 - c - lane starts the run unless key j - 1 chains to it
+            const int64_t j = (int64_t)base - 1 - c - lane;
+            bool first = false;
+            if (j >= 0) first = j == 0 || !chains_to(keys[j - 1], keys[j], bp, k, G);
+            const uint64_t m = __ballot(first);
+            if (m) {
+                const int f = __ffsll((unsigned long long)m) - 1;
+                if (lane == f) s_carry = (int32_t)(keys[j] & pmask);
+                break;
+            }
+        }
+    }
+    const uint32_t l0 = threadIdx.x * kItems;
+    int32_t last = -1, st[kItems];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const uint32_t l = l0 + u;
+        if (l < cnt) {
+            const bool start = l == 0 ? !enters : !chains_to(s_k[l], s_k[1 + l], bp, k, G);
+            if (start) last = (int32_t)l;
+        }
+        st[u] = last;
+    }
+    const int32_t before = block_excl_max(last);  // ends with a barrier: s_carry is set
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const uint32_t l = l0 + u;
+        if (l < cnt) {
+            const int32_t a = max(st[u], before);
+            s_qs[l] = a >= 0 ? (int32_t)(s_k[1 + a] & pmask) : s_carry;
+        }
+    }
+    __syncthreads();
+}
+
+// Tile hit l ends a run when the next hit does not chain to it; the run [qs, qe =
+// qpos + k) is kept when qe - qs >= M.
 __device__ __forceinline__ bool chain_end_tile(const uint64_t *__restrict__ s_k,
-                                               const uint64_t *__restrict__ keys, uint32_t n,
+                                               const int32_t *__restrict__ s_qs, uint32_t n,
                                                uint32_t base, uint32_t l, int bp, int32_t k,
                                                int32_t G, int32_t M, int32_t *qs_out)
 {
-    const uint64_t pmask = low_mask(bp);
     const uint64_t key = s_k[1 + l];
-    const uint64_t grp = key >> bp;
-    const int32_t qp = (int32_t)(key & pmask);
-    if (base + l + 1 < n) {
-        const uint64_t nx = s_k[2 + l];
-        if ((nx >> bp) == grp && (int32_t)(nx & pmask) - (qp + k) <= G) return false;
-    }
-    uint32_t j = base + l;
-    int32_t qj = qp;
-    while (j > 0) {
-        const uint64_t pv = j > base ? s_k[j - base] : keys[j - 1];
-        if ((pv >> bp) != grp) break;
-        const int32_t qv = (int32_t)(pv & pmask);
-        if (qj - (qv + k) > G) break;
-        --j;
-        qj = qv;
-    }
-    *qs_out = qj;
-    return qp + k - qj >= M;
+    if (base + l + 1 < n && chains_to(key, s_k[2 + l], bp, k, G)) return false;
+    const int32_t qs = s_qs[l];
+    *qs_out = qs;
+    return (int32_t)(key & low_mask(bp)) + k - qs >= M;
 }
 
 // Stage keys [base, base + cnt] (the tile and the key after it) in LDS.
@@ -2090,18 +2151,20 @@ __global__ __launch_bounds__(kBlock) void k_chain_count(const uint64_t *__restri
                                                         const WaveCtl *__restrict__ ctl)
 {
     __shared__ uint64_t s_k[kTile + 2];
+    __shared__ int32_t s_qs[kTile];
     if (ctl) {  // tiles past the wave's hits count zero runs
         n = ctl->H;
         bp = ctl->lay.bp;
     }
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
     const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
+    tile_run_starts(s_k, keys, base, cnt, bp, k, G, s_qs);
     uint32_t c = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const uint32_t l = r * kBlock + threadIdx.x;
         int32_t qs;
-        if (l < cnt && chain_end_tile(s_k, keys, n, base, l, bp, k, G, M, &qs)) ++c;
+        if (l < cnt && chain_end_tile(s_k, s_qs, n, base, l, bp, k, G, M, &qs)) ++c;
     }
     uint32_t tot;
     block_excl_scan<uint32_t>(c, &tot);
@@ -2126,13 +2189,15 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
     if (SELF && n == 0 && blockIdx.x == 0 && threadIdx.x == 0) ctl->nc = 0;
     if (ctl && base >= n) return;
     __shared__ uint64_t s_k[kTile + 2];
+    __shared__ int32_t s_qs[kTile];
     const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
+    tile_run_starts(s_k, keys, base, cnt, lay.bp, k, G, s_qs);
     uint32_t at = SELF ? block_sum(tile_off, blockIdx.x) : tile_off[blockIdx.x];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const uint32_t l = r * kBlock + threadIdx.x;
         int32_t qs = 0;
-        const bool emit = l < cnt && chain_end_tile(s_k, keys, n, base, l, lay.bp, k, G, M, &qs);
+        const bool emit = l < cnt && chain_end_tile(s_k, s_qs, n, base, l, lay.bp, k, G, M, &qs);
         uint32_t tot;
         const uint32_t ex = block_excl_scan<uint32_t>(emit ? 1u : 0u, &tot);
         if (emit) {
@@ -2794,7 +2859,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_select_seg(const Box *__restri
     if ((int32_t)blockIdx.x >= ctl->nqw) return;
     const uint32_t a0 = seg_off[blockIdx.x], n = seg_off[blockIdx.x + 1] - a0;
     if (n > (uint32_t)kSegCap) {
-        if (threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
+        if (threadIdx.x == 0) ctl->qflag[ctl->qa + (int32_t)blockIdx.x] = 1u;
         return;
     }
     if (n == 0) return;
@@ -2892,7 +2957,7 @@ __global__ __launch_bounds__(kBlock) void k_report_seg(const Align *__restrict__
         qa = ctl->qa;
     }
     const uint32_t a0 = sel_off[ql], n = sel_off[ql + 1] - a0;
-    if (ctl && n > (uint32_t)kSegCap && threadIdx.x == 0) atomicOr(&ctl->overflow, 1u);
+    if (ctl && n > (uint32_t)kSegCap && threadIdx.x == 0) ctl->qflag[qa + ql] = 1u;
     if (n > (uint32_t)kSegCap) return;  // longer segments take the global sort
     if (threadIdx.x == 0) s_valid = 0;
     __syncthreads();
@@ -3012,6 +3077,82 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
 constexpr uint32_t kMergeWin = 1024;
 constexpr uint32_t kMergeSpan = 2 * kMergeWin;
 
+// Stable LSD radix sort of the m <= kMergeSpan keys in s_key (LDS), 8 bits per
+// pass, by a 256-thread block.  Wave w holds keys [512 w, 512 w + 512) in
+// registers, 64 per round; a key's rank among equal digits of its wave comes from
+// eight ballots (as the global passes rank a tile), the block scans the per-wave
+// digit counts, and the keys are written to their places in s_key and read back
+// for the next pass.  Only passes whose digit varies across the keys run
+// (`varying`: OR of every key XOR the first).
+__device__ void lds_radix_sort(uint64_t *__restrict__ s_key, uint32_t m, uint64_t varying)
+{
+    constexpr int kPerWave = kMergeSpan / (kBlock / 64);  // 512
+    constexpr int kRounds = kPerWave / 64;                 // 8
+    __shared__ uint16_t s_wc[kBlock / 64][kRadix];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t k[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t idx = w * kPerWave + r * 64 + lane;
+        k[r] = idx < m ? s_key[idx] : 0ull;
+    }
+    for (int shift = 0; shift < 64; shift += kRadixBits) {
+        if (((varying >> shift) & (kRadix - 1)) == 0) continue;  // same digit everywhere
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) s_wc[i][threadIdx.x] = 0;
+        __syncthreads();
+        uint32_t rank[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint32_t idx = w * kPerWave + r * 64 + lane;
+            const bool ok = idx < m;
+            const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
+            uint64_t peers = __ballot(ok);
+#pragma unroll
+            for (int b = 0; b < kRadixBits; ++b) {
+                const uint64_t bb = __ballot(ok && ((d >> b) & 1u));
+                peers &= ((d >> b) & 1u) ? bb : ~bb;
+            }
+            const uint32_t before = s_wc[w][d];
+            rank[r] = before + (uint32_t)__popcll(peers & below);
+            __builtin_amdgcn_wave_barrier();
+            if (ok && (peers & below) == 0) s_wc[w][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        {
+            const uint32_t d = threadIdx.x;
+            uint32_t run = 0, wc[kBlock / 64];
+#pragma unroll
+            for (int i = 0; i < kBlock / 64; ++i) {
+                wc[i] = run;
+                run += s_wc[i][d];
+            }
+            uint32_t tot;
+            const uint32_t start = block_excl_scan<uint32_t>(run, &tot);
+#pragma unroll
+            for (int i = 0; i < kBlock / 64; ++i) s_wc[i][d] = (uint16_t)(start + wc[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint32_t idx = w * kPerWave + r * 64 + lane;
+            if (idx < m) {
+                const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
+                s_key[s_wc[w][d] + rank[r]] = k[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint32_t idx = w * kPerWave + r * 64 + lane;
+            if (idx < m) k[r] = s_key[idx];
+        }
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_merge_tiles(const Box *__restrict__ in, uint32_t n,
                                                         int bl, int bd, int32_t bias,
                                                         Box *__restrict__ out,
@@ -3021,9 +3162,11 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(const Box *__restrict__ 
     __shared__ uint16_t s_start[kMergeSpan + 1];
     __shared__ uint16_t s_rank[kMergeSpan];
     __shared__ uint32_t s_wc[kBlock / 64];
-    __shared__ uint32_t s_nw, s_end;
+    __shared__ uint32_t s_nw;
+    __shared__ uint64_t s_vary[2];
     const uint32_t base = blockIdx.x * kMergeWin;
     if (base >= n) return;
+    if (threadIdx.x == 0) s_vary[0] = s_vary[1] = 0;
     const uint32_t lim = min(base + kMergeSpan, n);
     const uint32_t R = lim - base;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -3101,36 +3244,29 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(const Box *__restrict__ 
     }
     if (nw == 0) return;
     const uint32_t o = s_start[0], m = s_start[nw] - o;  // keys of the owned small groups
-    uint32_t n2 = 1;
-    while (n2 < m) n2 <<= 1;
     const uint64_t mbl = (1ull << bl) - 1ull, mbd = (1ull << bd) - 1ull;
-    for (uint32_t j = threadIdx.x; j < n2; j += kBlock) {
-        uint64_t key = ~0ull;
-        if (j < m) {
-            const Box b = in[base + o + j];
-            const uint64_t rank = (uint64_t)(s_rank[o + j] - s_rank[o]);
-            const uint64_t d = (uint64_t)(uint32_t)(b.ds - b.qs + bias);
-            key = (rank << (2 * bl + bd)) | ((uint64_t)(uint32_t)b.qs << (bl + bd)) |
-                  ((d & mbd) << bl) | ((uint64_t)(uint32_t)b.qe & mbl);
-        }
+    uint64_t vary = 0, zeros = 0;
+    for (uint32_t j = threadIdx.x; j < m; j += kBlock) {
+        const Box b = in[base + o + j];
+        const uint64_t rank = (uint64_t)(s_rank[o + j] - s_rank[o]);
+        const uint64_t d = (uint64_t)(uint32_t)(b.ds - b.qs + bias);
+        const uint64_t key = (rank << (2 * bl + bd)) | ((uint64_t)(uint32_t)b.qs << (bl + bd)) |
+                             ((d & mbd) << bl) | ((uint64_t)(uint32_t)b.qe & mbl);
         s_key[j] = key;
+        vary |= key;
+        zeros |= ~key;
+    }
+    // bits that differ between keys: set in some key and clear in some key
+    for (int off = 32; off > 0; off >>= 1) {
+        vary |= __shfl_xor(vary, off, 64);
+        zeros |= __shfl_xor(zeros, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicOr(reinterpret_cast<unsigned long long *>(&s_vary[0]), (unsigned long long)vary);
+        atomicOr(reinterpret_cast<unsigned long long *>(&s_vary[1]), (unsigned long long)zeros);
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n2; i += kBlock) {
-                const uint32_t l = i ^ jj;
-                if (l > i) {
-                    const uint64_t a = s_key[i], b = s_key[l];
-                    if (((i & k) == 0) ? (a > b) : (a < b)) {
-                        s_key[i] = b;
-                        s_key[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
+    lds_radix_sort(s_key, m, s_vary[0] & s_vary[1]);
     // sweep each owned group from its keys
     for (uint32_t g = threadIdx.x; g < nw; g += kBlock) {
         const uint32_t j0 = s_start[g] - o, j1 = s_start[g + 1] - o;
@@ -3414,8 +3550,8 @@ __global__ void k_select_counts(const uint32_t *__restrict__ qstart,
 // order, so a binary search finds each query's range; a query's selected boxes
 // lead its own segment [seg_off[ql], seg_off[ql + 1]) (valid boxes sort first), so
 // a binary search in the segment finds where they end.  counts[ql] is the range's
-// length, capped at N when N > 0; queries past the wave, and every query of an
-// overflowed wave, get empty ranges.
+// length, capped at N when N > 0; queries past the wave, and flagged queries (their
+// runs outgrew the LDS sort: the host runs them again), get empty ranges.
 __global__ void k_cand_ranges(const Cand *__restrict__ c, int32_t nq_cap,
                               uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend,
                               uint32_t *__restrict__ counts, uint32_t *__restrict__ off,
@@ -3423,7 +3559,7 @@ __global__ void k_cand_ranges(const Cand *__restrict__ c, int32_t nq_cap,
 {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q > nq_cap) return;
-    const uint32_t n = ctl->overflow ? 0u : ctl->nc;
+    const uint32_t n = ctl->nc;
     if (q == nq_cap) {
         off[q] = n;
         if (clear) *clear = 0u;
@@ -3460,7 +3596,7 @@ __global__ void k_box_ranges(const Box *__restrict__ s, const uint32_t *__restri
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq_cap) return;
     uint32_t a = 0, b = 0;
-    if (q < ctl->nqw && !ctl->overflow) {
+    if (q < ctl->nqw && !ctl->qflag[ctl->qa + q]) {
         a = seg_off[q];
         uint32_t lo = a, hi = seg_off[q + 1];  // first empty slot of the segment
         while (lo < hi) {
@@ -3500,7 +3636,7 @@ __global__ __launch_bounds__(kRangeBlock) void k_box_ranges_scan(
     for (int32_t q0 = 0; q0 < nq_cap; q0 += kRangeBlock) {
         const int32_t q = q0 + (int32_t)threadIdx.x;
         uint32_t a = 0, b = 0;
-        if (q < nq_cap && q < ctl->nqw && !ctl->overflow) {
+        if (q < nq_cap && q < ctl->nqw && !ctl->qflag[ctl->qa + q]) {
             a = seg_off[q];
             uint32_t lo = a, hi = seg_off[q + 1];  // first empty slot of the segment
             while (lo < hi) {

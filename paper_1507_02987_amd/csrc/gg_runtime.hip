@@ -106,7 +106,7 @@ struct Workspace {
     DevBuf qstart, qend, nsel, sel_off, rstart, rend, aligns, aligns2, cells_q;
     DevBuf bplan, bcount, boff, bcands, btmp, bcoff, ctmp, cursor, qcur, bound_q, bound_off,
         btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue, gout, gn,
-        gctl, gplan, gcursor, goflags, stiles, gtiles;
+        gctl, gplan, gcursor, gqflag, stiles, gtiles;
     DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
     DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
     DevBuf fkept, fkoff, fflag, ford;   // lone-diagonal filter (ford: largest query first)
@@ -142,7 +142,7 @@ struct Workspace {
                          &cells_q, &bplan, &bcount, &boff, &bcands, &btmp, &bcoff, &ctmp, &cursor, &qcur,
                          &bound_q, &bound_off, &btmp_b, &bounds, &blist, &pcnt, &cells_box,
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
-                         &gcursor, &goflags, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
+                         &gcursor, &gqflag, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
                          &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox, &bq,
                          &mbig, &mranges};
@@ -179,7 +179,10 @@ struct gg_index {
     std::atomic<int> prof_on{0};
     // tuned launch choices (gg_index_autotune / gg_index_set_tuning)
     std::atomic<int32_t> tune_grouping{2};
-    std::atomic<int32_t> tune_lane_steps{64};
+    std::atomic<int32_t> tune_lane_steps{256};
+    std::atomic<int32_t> tune_wave_log2{0};  // hits of one graph wave: 2^this (0: 2^25)
+    std::atomic<int32_t> tune_graph{1};      // 0: batches never replay the wave graph
+    std::atomic<int32_t> tune_graph_qlog2{0};  // queries over 2^this hits skip the graph (0: none)
     mutable std::mutex prof_mu;
     mutable std::map<std::string, StageTime> prof;
 };
@@ -1280,6 +1283,53 @@ gg_status search_pieces(const gg_index *ix, Workspace *ws, Prof &prof, const gg_
     return GG_OK;
 }
 
+// The regular path over ranges [qa, qb) of the batch's queries: consecutive
+// queries whose stored hit keys fit the budget and the key bits form a wave
+// (probing stores no hit: its waves are bounded only by 32-bit hit counts); a
+// query over the budget alone is searched in ranges of sequences.
+gg_status run_ranges(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
+                     const std::vector<int64_t> &qoff_h, const std::vector<uint64_t> &qtot,
+                     const std::vector<std::pair<int32_t, int32_t>> &ranges, BatchOut &bo,
+                     uint64_t budget_bytes, Grouping grouping)
+{
+    const uint64_t max_hits = grouping == kProbe
+                                  ? (uint64_t)INT32_MAX
+                                  : std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
+    const int bs = bits_for((uint64_t)ix->n_seqs);
+    for (const auto &r : ranges) {
+        int32_t qa = r.first;
+        const int32_t qend = r.second;
+        while (qa < qend) {
+            if (qtot[qa] > max_hits) {  // searched alone, by ranges of sequences
+                TRY(search_pieces(ix, ws, prof, p, qoff_h, qtot, qa, max_hits, bo, grouping));
+                ++qa;
+                continue;
+            }
+            uint64_t h = 0;
+            int64_t maxL = 0;
+            int32_t qb = qa;
+            while (qb < qend && qtot[qb] <= max_hits) {
+                const uint64_t h2 = h + qtot[qb];
+                const int64_t L2 = std::max<int64_t>(maxL, qoff_h[qb + 1] - qoff_h[qb]);
+                const int bits = bits_for((uint64_t)L2) +
+                                 bits_for((uint64_t)ix->max_seq_len + L2) + bs +
+                                 bits_for((uint64_t)(qb - qa + 1));
+                const int wbits = bits_for((uint64_t)(qb - qa + 2));  // record keys hold q up to nqw
+                const bool too_wide = grouping != kProbe && bits > 64;
+                if (qb > qa && (h2 > max_hits || too_wide || wbits > 31)) break;
+                if (too_wide) return GG_EINVAL;
+                h = h2;
+                maxL = L2;
+                ++qb;
+            }
+            TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, qa, qb, bo, grouping));
+            prof.collect();
+            qa = qb;
+        }
+    }
+    return GG_OK;
+}
+
 // ---- graph-replayed batches
 // Waves of a batch are replayed from one captured HIP graph: every kernel reads
 // the wave's sizes from a device WaveCtl (see k_wave_begin), so after the single
@@ -1288,7 +1338,13 @@ gg_status search_pieces(const gg_index *ix, Workspace *ws, Prof &prof, const gg_
 // shape.  It covers the radix-sort grouping with per-query LDS sorts: a wave in
 // which some query has more than kSegCap runs or selections is flagged and run
 // again by run_wave.  GG_GRAPH=0 turns the form off.
-constexpr uint64_t kGraphHits = 1ull << 25;  // hits of one graph wave at most
+constexpr uint64_t kGraphHits = 1ull << 25;  // hits of one graph wave at most, by default
+
+uint64_t graph_wave_hits(const gg_index *ix)
+{
+    const int32_t lg = ix->tune_wave_log2.load();
+    return lg > 0 ? (1ull << lg) : kGraphHits;
+}
 
 uint64_t pow2_at_least(uint64_t v)
 {
@@ -1303,27 +1359,87 @@ bool graph_enabled()
     return !(g && !strcmp(g, "0"));
 }
 
+gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const int64_t *qoff,
+                    int64_t nq, const gg_params *p, BatchOut &bo, uint64_t budget_bytes,
+                    bool allow_graph = true);
+
+// Queries idx of a host batch packed into one sub-batch, searched by run_batch
+// (with or without graph waves), and their results put back in their places.
+gg_status run_packed(const gg_index *ix, Workspace *ws, const gg_params *p, const char *qbuf,
+                     const std::vector<int64_t> &qoff_h, const std::vector<int32_t> &idx,
+                     BatchOut &bo, uint64_t budget_bytes, bool allow_graph)
+{
+    if (idx.empty()) return GG_OK;
+    const int32_t cap = bo.cap;
+    std::vector<char> sub;
+    std::vector<int64_t> soff(1, 0);
+    for (int32_t q : idx) {
+        sub.insert(sub.end(), qbuf + qoff_h[q], qbuf + qoff_h[q + 1]);
+        soff.push_back((int64_t)sub.size());
+    }
+    const size_t nr = idx.size();
+    std::vector<gg_hit> sout(nr * (size_t)std::max(cap, 1));
+    std::vector<int32_t> sn(nr, 0);
+    BatchOut sb{sout.data(), cap, sn.data(), nullptr};
+    TRY(run_batch(ix, ws, sub.empty() ? nullptr : sub.data(), soff.data(), (int64_t)nr, p, sb,
+                  budget_bytes, allow_graph));
+    for (size_t r = 0; r < nr; ++r) {
+        const int32_t q = idx[r];
+        bo.n_out[q] = sn[r];
+        const int32_t m = std::min(sn[r], cap);
+        std::copy(sout.begin() + r * cap, sout.begin() + r * cap + m, bo.out + (size_t)q * cap);
+        if (sn[r] > cap) bo.truncated = true;
+    }
+    return GG_OK;
+}
+
 gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const gg_params *p,
-                          const std::vector<int64_t> &qoff_h, const std::vector<uint64_t> &qtot,
-                          int64_t nq, BatchOut &bo, uint64_t budget_bytes, bool *used)
+                          const char *qbuf, const std::vector<int64_t> &qoff_h,
+                          const std::vector<uint64_t> &qtot, int64_t nq, BatchOut &bo,
+                          uint64_t budget_bytes, bool *used)
 {
     *used = false;
     hipStream_t st = ws->st;
-    const uint64_t wave_hits = std::min<uint64_t>(kGraphHits, budget_bytes / 16);
-    int64_t maxL = 0;
+    const uint64_t wave_hits = std::min<uint64_t>(graph_wave_hits(ix), budget_bytes / 16);
+    // queries over a wave, or over the per-query limit (queries that heavy mostly
+    // outgrow the per-query LDS sorts and would be run twice), take the regular
+    // path after the replays; the others form the waves
+    const int32_t qlg = ix->tune_graph_qlog2.load();
+    const uint64_t graph_q = qlg > 0 ? std::min<uint64_t>(wave_hits, 1ull << qlg) : wave_hits;
+    int64_t maxL = 0, n_graph = 0, stretches = 0;
     for (int64_t q = 0; q < nq; ++q) {
-        if (qtot[q] > wave_hits) return GG_OK;  // needs pieces: the regular path
+        if (qtot[q] > graph_q) continue;
         maxL = std::max<int64_t>(maxL, qoff_h[q + 1] - qoff_h[q]);
+        ++n_graph;
+        if (q == 0 || qtot[q - 1] > graph_q) ++stretches;
     }
-    // waves by hits; one key layout for all of them
+    if (n_graph == 0) return GG_OK;
+    if (stretches > 1 && !bo.device) {
+        // scattered among heavier ones: the graph queries and the others, each
+        // packed into a sub-batch of their own, so the graph waves come out full and
+        // the heavy queries share the regular path's large waves
+        std::vector<int32_t> light, heavy;
+        for (int32_t q = 0; q < (int32_t)nq; ++q) (qtot[q] > graph_q ? heavy : light).push_back(q);
+        TRY(run_packed(ix, ws, p, qbuf, qoff_h, light, bo, budget_bytes, true));
+        TRY(run_packed(ix, ws, p, qbuf, qoff_h, heavy, bo, budget_bytes, false));
+        *used = true;
+        return GG_OK;
+    }
+    // waves by hits, each a stretch of consecutive graph queries; one key layout
     std::vector<WaveCtl> plan;
     uint64_t hmax = 0;
     int64_t npmax = 0;
     int32_t nqmax = 0;
     for (int64_t qa = 0; qa < nq;) {
+        if (qtot[qa] > graph_q) {
+            ++qa;
+            continue;
+        }
         uint64_t h = 0;
         int64_t qb = qa;
-        while (qb < nq && (qb == qa || h + qtot[qb] <= wave_hits) && qb - qa < (1 << 20)) h += qtot[qb++];
+        while (qb < nq && qtot[qb] <= graph_q && (qb == qa || h + qtot[qb] <= wave_hits) &&
+               qb - qa < (1 << 20))
+            h += qtot[qb++];
         WaveCtl w{};
         w.qa = (int32_t)qa;
         w.nqw = (int32_t)(qb - qa);
@@ -1408,7 +1524,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     TRY(ensure(ws->gctl, sizeof(WaveCtl)));
     TRY(ensure(ws->gplan, sizeof(WaveCtl) * nwave_cap));
     TRY(ensure(ws->gcursor, sizeof(uint32_t) * 4));
-    TRY(ensure(ws->goflags, sizeof(uint32_t) * nwave_cap));
+    TRY(ensure(ws->gqflag, sizeof(uint32_t) * nq_out));
 
     WaveCtl *ctl = as<WaveCtl>(ws->gctl);
     uint32_t *cursor = as<uint32_t>(ws->gcursor);
@@ -1443,7 +1559,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                             &ws->boxes2, &ws->boxes3, &ws->xqueue, &ws->qstart, &ws->qend,
                             &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
                             &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
-                            &ws->gplan, &ws->gcursor, &ws->goflags, &ws->gtiles, &ws->fkept,
+                            &ws->gplan, &ws->gcursor, &ws->gqflag, &ws->gtiles, &ws->fkept,
                             &ws->fkoff, &ws->ford, &ws->tpos, &ws->selbox})
         key.push_back((uint64_t)(uintptr_t)b->p);
 
@@ -1511,7 +1627,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         launch_report_seg(as<Align>(ws->aligns), as<Align>(ws->aligns2), as<uint32_t>(ws->sel_off),
                           nq_cap, as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend), 0, cap,
                           gout, gn, st, ctl);
-        launch_wave_end(ctl, cursor, as<uint32_t>(ws->goflags), st);
+        launch_wave_end(cursor, st);
         const hipError_t ec = hipStreamEndCapture(st, &g);
         if (ec != hipSuccess) {
             (void)hipGetLastError();
@@ -1529,13 +1645,13 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
 
     // replay it once per wave
     const size_t W = plan.size();
-    // staging: plan [W] | overflow flags [W] | result counts [nq] | filter order [nq]
+    // staging: plan [W] | query flags [nq] | result counts [nq] | filter order [nq]
     void *pin;
-    TRY(pinned(ws, sizeof(WaveCtl) * W + sizeof(uint32_t) * W + 2 * sizeof(int32_t) * nq + 64,
-               &pin, 2));
+    TRY(pinned(ws, sizeof(WaveCtl) * W + 3 * sizeof(int32_t) * nq + 64, &pin, 2));
     WaveCtl *h_plan = static_cast<WaveCtl *>(pin);
-    uint32_t *oflags = reinterpret_cast<uint32_t *>(h_plan + W);
-    int32_t *nout = reinterpret_cast<int32_t *>(oflags + W);
+    uint32_t *qflags = reinterpret_cast<uint32_t *>(h_plan + W);
+    int32_t *nout = reinterpret_cast<int32_t *>(qflags + nq);
+    for (WaveCtl &w : plan) w.qflag = as<uint32_t>(ws->gqflag);
     std::copy(plan.begin(), plan.end(), h_plan);
     HIPCHK(hipMemcpyAsync(ws->gplan.p, h_plan, sizeof(WaveCtl) * W, hipMemcpyHostToDevice, st));
     if (filt) {  // each wave's queries, largest first, at the wave's own positions
@@ -1549,10 +1665,12 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
         HIPCHK(hipMemcpyAsync(ws->gtiles.p, tiles.data(), sizeof(SortTile) * tiles.size(),
                               hipMemcpyHostToDevice, st));
     launch_fill2_u32(cursor, 1, reinterpret_cast<uint32_t *>(gn), (size_t)nq, 0u, st);
+    launch_fill_u32(as<uint32_t>(ws->gqflag), (size_t)nq, 0u, st);
     prof.begin("graph");
     for (size_t w = 0; w < W; ++w) HIPCHK(hipGraphLaunch(ws->gexec, st));
     prof.end((int64_t)W);
-    HIPCHK(hipMemcpyAsync(oflags, ws->goflags.p, sizeof(uint32_t) * W, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(qflags, ws->gqflag.p, sizeof(uint32_t) * nq, hipMemcpyDeviceToHost,
+                          st));
     HIPCHK(hipMemcpyAsync(nout, gn, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
     if (cap > 0 && !direct)
         HIPCHK(hipMemcpyAsync(bo.out, ws->gout.p, sizeof(gg_hit) * (size_t)nq * cap,
@@ -1563,18 +1681,29 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     if (!bo.device) std::copy(nout, nout + nq, bo.n_out);
     for (int64_t q = 0; q < nq; ++q)
         if (nout[(size_t)q] > cap) bo.truncated = true;
-    // waves the per-query LDS sorts could not hold run again on the regular path
-    for (size_t w = 0; w < W; ++w) {
-        if (!oflags[w]) continue;
-        const int32_t qa = plan[w].qa, qb = plan[w].qa + plan[w].nqw;
-        TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, qa, qb, bo, kSort));
-        prof.collect();
+    // the regular path for the queries over a wave and those whose kept hits, runs
+    // or selections outgrew a per-query LDS sort
+    std::vector<std::pair<int32_t, int32_t>> rest;
+    std::vector<int32_t> idx;
+    for (int32_t q = 0; q < (int32_t)nq; ++q) {
+        if (qtot[q] <= graph_q && !qflags[q]) continue;
+        idx.push_back(q);
+        if (!rest.empty() && rest.back().second == q) rest.back().second = q + 1;
+        else rest.emplace_back(q, q + 1);
     }
-    return GG_OK;
+    if (rest.size() <= 1 || bo.device) {
+        // few stretches (or queries in device memory): each stretch as its own waves
+        TRY(run_ranges(ix, ws, prof, p, qoff_h, qtot, rest, bo, budget_bytes, kSort));
+        return GG_OK;
+    }
+    // scattered queries: packed into one host sub-batch, searched without the graph
+    // in waves as large as the budget allows, results put back in their places
+    return run_packed(ix, ws, p, qbuf, qoff_h, idx, bo, budget_bytes, false);
 }
 
 gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const int64_t *qoff,
-                    int64_t nq, const gg_params *p, BatchOut &bo, uint64_t budget_bytes)
+                    int64_t nq, const gg_params *p, BatchOut &bo, uint64_t budget_bytes,
+                    bool allow_graph)
 {
     hipStream_t st = ws->st;
     if (nq == 0) return GG_OK;
@@ -1643,43 +1772,16 @@ gg_status run_batch(const gg_index *ix, Workspace *ws, const char *qbuf, const i
     // ---- waves: consecutive queries whose stored hit keys fit the budget and the key
     // bits (probing stores no hit: its waves are bounded only by 32-bit hit counts)
     const Grouping grouping = grouping_for(ix);
-    if (graph_enabled() && grouping == kSort && !bo.stats && p->max_hits >= 1 &&
+    if (allow_graph && ix->tune_graph.load() && graph_enabled() && grouping == kSort &&
+        !bo.stats && p->max_hits >= 1 &&
         p->max_hits <= kSegCap) {
         bool used = false;
-        TRY(run_graph_waves(ix, ws, prof, p, qoff_h, qtot, nq, bo, budget_bytes, &used));
+        TRY(run_graph_waves(ix, ws, prof, p, bo.device ? nullptr : qbuf + qoff[0], qoff_h, qtot,
+                            nq, bo, budget_bytes, &used));
         if (used) return GG_OK;
     }
-    const uint64_t max_hits = grouping == kProbe
-                                  ? (uint64_t)INT32_MAX
-                                  : std::min<uint64_t>(budget_bytes / 16, (uint64_t)INT32_MAX);
-    const int bs = bits_for((uint64_t)ix->n_seqs);
-    int32_t qa = 0;
-    while (qa < nq) {
-        if (qtot[qa] > max_hits) {  // searched alone, by ranges of sequences
-            TRY(search_pieces(ix, ws, prof, p, qoff_h, qtot, qa, max_hits, bo, grouping));
-            ++qa;
-            continue;
-        }
-        uint64_t h = 0;
-        int64_t maxL = 0;
-        int32_t qb = qa;
-        while (qb < nq && qtot[qb] <= max_hits) {
-            const uint64_t h2 = h + qtot[qb];
-            const int64_t L2 = std::max<int64_t>(maxL, qoff_h[qb + 1] - qoff_h[qb]);
-            const int bits = bits_for((uint64_t)L2) + bits_for((uint64_t)ix->max_seq_len + L2) + bs +
-                             bits_for((uint64_t)(qb - qa + 1)) ;
-            const int wbits = bits_for((uint64_t)(qb - qa + 2));  // record keys hold q up to nqw
-            const bool too_wide = grouping != kProbe && bits > 64;
-            if (qb > qa && (h2 > max_hits || too_wide || wbits > 31)) break;
-            if (too_wide) return GG_EINVAL;
-            h = h2;
-            maxL = L2;
-            ++qb;
-        }
-        TRY(run_wave(ix, ws, prof, p, qoff_h, qtot, qa, qb, bo, grouping));
-        prof.collect();
-        qa = qb;
-    }
+    const std::vector<std::pair<int32_t, int32_t>> all{{0, (int32_t)nq}};
+    TRY(run_ranges(ix, ws, prof, p, qoff_h, qtot, all, bo, budget_bytes, grouping));
     prof.collect();
     return GG_OK;
 }
@@ -2322,16 +2424,24 @@ gg_status gg_index_get_tuning(const gg_index *ix, gg_tuning *out)
     out->grouping = ix->tune_grouping.load();
     out->lane_steps = ix->tune_lane_steps.load();
     out->ms = 0.0;
+    const int32_t lg = ix->tune_wave_log2.load();
+    out->wave_log2 = lg > 0 ? lg : 25;
+    out->graph = ix->tune_graph.load();
+    out->graph_query_log2 = ix->tune_graph_qlog2.load();
     return GG_OK;
 }
 
 gg_status gg_index_set_tuning(gg_index *ix, const gg_tuning *t)
 {
     if (!ix || !t || t->grouping < 0 || t->grouping > 2 || t->lane_steps < 0 ||
-        t->lane_steps > 4096)
+        t->lane_steps > 4096 || (t->wave_log2 != 0 && (t->wave_log2 < 10 || t->wave_log2 > 30)) ||
+        t->graph < 0 || t->graph > 1 || t->graph_query_log2 < 0 || t->graph_query_log2 > 30)
         return GG_EINVAL;
     ix->tune_grouping = t->grouping;
     ix->tune_lane_steps = t->lane_steps;
+    ix->tune_wave_log2 = t->wave_log2;
+    ix->tune_graph = t->graph;
+    ix->tune_graph_qlog2 = t->graph_query_log2;
     return GG_OK;
 }
 
@@ -2370,51 +2480,71 @@ gg_status gg_index_autotune(gg_index *ix, const char *qbuf, const int64_t *qoff,
     std::vector<int32_t> ref_n, n_out((size_t)n_q);
     gg_tuning best = keep;
     best.ms = -1.0;
-    for (int32_t grouping = 0; grouping <= 2; ++grouping) {
-        for (int32_t steps : {0, 16, 64, 256}) {
-            const gg_tuning t{grouping, steps, 0.0};
-            TRY(gg_index_set_tuning(ix, &t));
-            double ms = -1.0;
-            for (int rep = -1; rep < 3; ++rep) {  // rep -1 warms up (graph capture, buffers)
-                const auto t0 = std::chrono::steady_clock::now();
-                gg_status s = gg::search_batch_budget(
-                    ix, static_cast<const char *>(dev.q), off.data(), n_q, params,
-                    static_cast<gg_hit *>(dev.out), cap, static_cast<int32_t *>(dev.n), nullptr,
-                    gg::index_budget(ix), true);
-                const double dt = std::chrono::duration<double, std::milli>(
-                                      std::chrono::steady_clock::now() - t0)
-                                      .count();
-                if (s != GG_OK && s != GG_ETRUNC) {
-                    (void)gg_index_set_tuning(ix, &keep);
-                    return s;
-                }
-                if (rep < 0) continue;
-                ms = ms < 0 ? dt : std::min(ms, dt);
-                if (best.ms >= 0 && ms > 2.0 * best.ms) break;  // clearly slower: one run is enough
-            }
-            if (hipMemcpy(out.data(), dev.out, out_bytes, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(n_out.data(), dev.n, sizeof(int32_t) * n_q, hipMemcpyDeviceToHost) !=
-                    hipSuccess) {
-                (void)gg_index_set_tuning(ix, &keep);
-                return GG_EDEVICE;
-            }
-            if (ref.empty()) {
-                ref = out;
-                ref_n = n_out;
-            } else {
-                bool same = ref_n == n_out;
-                for (int64_t q = 0; same && q < n_q; ++q) {
-                    const size_t m = (size_t)std::min(n_out[(size_t)q], cap);
-                    same = memcmp(&ref[(size_t)q * cap], &out[(size_t)q * cap],
-                                  sizeof(gg_hit) * m) == 0;
-                }
-                if (!same) {
-                    (void)gg_index_set_tuning(ix, &keep);
-                    return GG_EDEVICE;
-                }
-            }
-            if (best.ms < 0 || ms < best.ms) best = gg_tuning{grouping, steps, ms};
+    // one candidate: timed (best of three runs after one untimed), and its hits
+    // must equal the first candidate's
+    auto trial = [&](const gg_tuning &t) -> gg_status {
+        TRY(gg_index_set_tuning(ix, &t));
+        double ms = -1.0;
+        for (int rep = -1; rep < 3; ++rep) {  // rep -1 warms up (graph capture, buffers)
+            const auto t0 = std::chrono::steady_clock::now();
+            gg_status s = gg::search_batch_budget(
+                ix, static_cast<const char *>(dev.q), off.data(), n_q, params,
+                static_cast<gg_hit *>(dev.out), cap, static_cast<int32_t *>(dev.n), nullptr,
+                gg::index_budget(ix), true);
+            const double dt = std::chrono::duration<double, std::milli>(
+                                  std::chrono::steady_clock::now() - t0)
+                                  .count();
+            if (s != GG_OK && s != GG_ETRUNC) return s;
+            if (rep < 0) continue;
+            ms = ms < 0 ? dt : std::min(ms, dt);
+            if (best.ms >= 0 && ms > 2.0 * best.ms) break;  // clearly slower: one run is enough
         }
+        if (hipMemcpy(out.data(), dev.out, out_bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(n_out.data(), dev.n, sizeof(int32_t) * n_q, hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            return GG_EDEVICE;
+        if (ref.empty()) {
+            ref = out;
+            ref_n = n_out;
+        } else {
+            bool same = ref_n == n_out;
+            for (int64_t q = 0; same && q < n_q; ++q) {
+                const size_t m = (size_t)std::min(n_out[(size_t)q], cap);
+                same = memcmp(&ref[(size_t)q * cap], &out[(size_t)q * cap],
+                              sizeof(gg_hit) * m) == 0;
+            }
+            if (!same) return GG_EDEVICE;
+        }
+        if (best.ms < 0 || ms < best.ms) {
+            best = t;
+            best.ms = ms;
+        }
+        return GG_OK;
+    };
+    gg_status s = GG_OK;
+    // how hits become runs and the extension's lane-step cap, then (for the
+    // radix-sort grouping, whose batches replay a captured graph per wave) the
+    // hits of one graph wave
+    for (int32_t grouping = 0; grouping <= 2 && s == GG_OK; ++grouping)
+        for (int32_t steps : {0, 64, 256, 4096})
+            if (s == GG_OK)
+                s = trial(gg_tuning{grouping, steps, 0.0, keep.wave_log2, keep.graph,
+                                    keep.graph_query_log2});
+    if (s == GG_OK && best.grouping == 2) {
+        const gg_tuning base = best;
+        auto with = [&](int32_t wave, int32_t graph, int32_t qlg) {
+            return gg_tuning{base.grouping, base.lane_steps, 0.0, wave, graph, qlg};
+        };
+        for (int32_t lg : {23, 27})
+            if (s == GG_OK && lg != base.wave_log2) s = trial(with(lg, base.graph, base.graph_query_log2));
+        const gg_tuning b2 = best;
+        for (int32_t qlg : {14, 18})
+            if (s == GG_OK) s = trial(gg_tuning{b2.grouping, b2.lane_steps, 0.0, b2.wave_log2, 1, qlg});
+        if (s == GG_OK) s = trial(gg_tuning{b2.grouping, b2.lane_steps, 0.0, b2.wave_log2, 0, 0});
+    }
+    if (s != GG_OK) {
+        (void)gg_index_set_tuning(ix, &keep);
+        return s;
     }
     TRY(gg_index_set_tuning(ix, &best));
     if (chosen) *chosen = best;

@@ -67,7 +67,8 @@ class ServerStats(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("grouping", C.c_int32), ("lane_steps", C.c_int32), ("ms", C.c_double)]
+    _fields_ = [("grouping", C.c_int32), ("lane_steps", C.c_int32), ("ms", C.c_double),
+                ("wave_log2", C.c_int32), ("graph", C.c_int32), ("graph_query_log2", C.c_int32)]
 
 
 GROUPINGS = ("probe", "bucket", "sort")
@@ -286,10 +287,12 @@ class Index:
         rc = lib().gg_index_get_tuning(self._h, C.byref(t))
         if rc != GG_OK:
             raise GGError(rc, "gg_index_get_tuning")
-        return {"grouping": GROUPINGS[t.grouping], "lane_steps": t.lane_steps}
+        return {"grouping": GROUPINGS[t.grouping], "lane_steps": t.lane_steps,
+                "wave_log2": t.wave_log2, "graph": t.graph, "graph_query_log2": t.graph_query_log2}
 
-    def set_tuning(self, grouping: str = "sort", lane_steps: int = 32):
-        t = Tuning(GROUPINGS.index(grouping), lane_steps, 0.0)
+    def set_tuning(self, grouping: str = "sort", lane_steps: int = 256, wave_log2: int = 0,
+                   graph: int = 1, graph_query_log2: int = 0):
+        t = Tuning(GROUPINGS.index(grouping), lane_steps, 0.0, wave_log2, graph, graph_query_log2)
         rc = lib().gg_index_set_tuning(self._h, C.byref(t))
         if rc != GG_OK:
             raise GGError(rc, "gg_index_set_tuning")
@@ -304,6 +307,7 @@ class Index:
         if rc != GG_OK:
             raise GGError(rc, "gg_index_autotune")
         return {"grouping": GROUPINGS[t.grouping], "lane_steps": t.lane_steps,
+                "wave_log2": t.wave_log2, "graph": t.graph, "graph_query_log2": t.graph_query_log2,
                 "sample_ms": round(t.ms, 3)}
 
     def search(self, query, prm: Params, cap: int = 1024):

@@ -90,7 +90,7 @@ def test_long_queries_top100(ggo, large):
     10^8 hits."""
     G, db, gix, oix = large
     qs = synth.large_queries(db)
-    gix.set_tuning("sort", 16)
+    gix.set_tuning("sort", 256)
     note(f"{qs.n} long queries on the GPU")
     out = np.zeros(qs.n * 100, G.HIT_DTYPE)
     nout = np.zeros(qs.n, np.int32)

@@ -214,7 +214,7 @@ def test_mid_full_bank_every_query(ggo):
     db = synth.mid_db()
     qs = synth.mid_queries(db)
     gix = G.Index(db.seqs, db.off, 11)
-    gix.set_tuning("sort", 16)
+    gix.set_tuning("sort", 256)
     cap = 50
     dq = G.DeviceBuffer(len(qs.buf))
     dq.upload(qs.buf)
@@ -293,14 +293,15 @@ def test_autotune_and_lane_steps(ggo, monkeypatch):
     qs = synth.mid_queries(db, n=80)
     oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
     want, wst = oracle_all(ggo, oix, qs, ggo.params(50))
-    assert gix.tuning() == {"grouping": "sort", "lane_steps": 64}
+    assert gix.tuning() == {"grouping": "sort", "lane_steps": 256, "wave_log2": 25, "graph": 1,
+                            "graph_query_log2": 0}
     got = gix.autotune(qs.buf, qs.off, G.params(50))
-    assert got["grouping"] in G.GROUPINGS and got["lane_steps"] in (0, 16, 64, 256)
+    assert got["grouping"] in G.GROUPINGS and got["lane_steps"] in (0, 64, 256, 4096)
     assert got["sample_ms"] > 0
     assert {k: gix.tuning()[k] for k in ("grouping", "lane_steps")} == {
         k: got[k] for k in ("grouping", "lane_steps")}
     check_batch(G, gix, qs, G.params(50), want, wst)
-    for steps in (0, 1, 4096):
+    for steps in (0, 1, 16, 17, 4096):
         gix.set_tuning("sort", steps)
         check_batch(G, gix, qs, G.params(50), want, wst)
     with pytest.raises(G.GGError):
@@ -362,6 +363,64 @@ def test_graph_replayed_batches(ggo, monkeypatch, k, band, max_hits, seed):
     gix.profile(False)
     if k == 4:
         assert max(s["n_cands"] for s in wst) > 1024
+
+
+@pytest.mark.parametrize("k,wave_log2,qlog2", [(4, 20, 0), (8, 11, 0), (11, 25, 0), (8, 25, 10),
+                                               (11, 25, 12)])
+def test_graph_waves_around_large_queries(ggo, monkeypatch, k, wave_log2, qlog2):
+    """Queries with more hits than a graph wave holds, and queries whose kept hits,
+    runs or selections outgrow a per-query LDS sort, take the regular path after
+    the replays; the other queries stay in the graph waves.  Every result equals
+    the oracle, graph waves run, and the regular path runs only for those queries
+    (heavy and flagged queries are packed into sub-batches of their own)."""
+    G = gpu()
+    monkeypatch.setenv("GG_GROUPING", "sort")
+    monkeypatch.delenv("GG_GRAPH", raising=False)
+    db = synth.repeat_db(60 + k, n_seqs=300, lmin=100, lmax=4000, frac_repeat=0.3)
+    qs = synth.random_queries(60 + k, db, n=60, lmin=50, lmax=2500, frac_homolog=0.7,
+                              ident_lo=0.8, ident_hi=1.0, indel_rate=0.02)
+    oix, gix = ggo.Index(db.seqs, db.off, k), G.Index(db.seqs, db.off, k)
+    kw = dict(max_gap=3 * k, min_hsp_len=2 * k)
+    want, wst = oracle_all(ggo, oix, qs, ggo.params(10, **kw))
+    gix.set_tuning("sort", 256, wave_log2, 1, qlog2)
+    assert gix.tuning()["wave_log2"] == wave_log2 and gix.tuning()["graph_query_log2"] == qlog2
+    gix.profile(True)
+    rc, got, n, _ = gix.search_batch(qs.buf, qs.off, G.params(10, **kw), cap=1000)
+    waves, regular = gix.profile_read("graph")["units"], gix.profile_read("extend")["launches"]
+    gix.profile(False)
+    assert rc == 0
+    for i in range(qs.n):
+        assert as_rows(got[i]) == as_rows(want[i]), i
+    assert waves >= 1
+    limit = min(1 << wave_log2, 1 << qlog2) if qlog2 else 1 << wave_log2
+    big = [int(s["n_hits"]) > limit or int(s["n_cands"]) > 1024 for s in wst]
+    # a regular wave runs only for these queries (and those the filter's kept-hit
+    # limit flags, which the counts above do not show): the heavy ones share
+    # waves, and so do the flagged ones
+    flaggable = sum(1 for s in wst if int(s["n_hits"]) > 8192)
+    assert regular <= sum(big) + flaggable
+    if k == 4:
+        assert any(big)
+
+
+def test_graph_off_by_tuning(ggo, monkeypatch):
+    """Tuning graph = 0: no batch replays the graph, results unchanged."""
+    G = gpu()
+    monkeypatch.delenv("GG_GRAPH", raising=False)
+    db = synth.random_db(70, n_seqs=200, lmin=100, lmax=3000)
+    qs = synth.random_queries(70, db, n=30, lmin=50, lmax=1500, frac_homolog=0.7,
+                              ident_lo=0.8, ident_hi=1.0, indel_rate=0.02)
+    oix, gix = ggo.Index(db.seqs, db.off, 11), G.Index(db.seqs, db.off, 11)
+    want, _ = oracle_all(ggo, oix, qs, ggo.params(10))
+    for graph in (1, 0):
+        gix.set_tuning("sort", 256, 0, graph, 0)
+        gix.profile(True)
+        rc, got, n, _ = gix.search_batch(qs.buf, qs.off, G.params(10), cap=1000)
+        waves = gix.profile_read("graph")["units"]
+        gix.profile(False)
+        assert rc == 0 and (waves > 0) == bool(graph)
+        for i in range(qs.n):
+            assert as_rows(got[i]) == as_rows(want[i]), (graph, i)
 
 
 def test_long_merge_groups(ggo):
