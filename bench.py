@@ -182,7 +182,8 @@ def cpu_baseline(db, qs, max_hits: int, cap: int, hits_per_query: np.ndarray):
 #  filter  - HBM: 8 B key read per hit (the kept few are written back)
 #  sort_*  - HBM: 16 B per key per scatter pass, 8 B per histogram pass
 #  align   - integer ALU: ALIGN_OPS_PER_CELL int32 operations per in-band cell
-KERNEL = {"gather": "k_gather", "filter": "k_hit_filter", "sort_scatter": "k_rs_scatter_seg",
+KERNEL = {"gather": "k_gather", "filter": "k_hit_filter", "gather_filter": "k_gather_filter",
+          "sort_scatter": "k_rs_scatter_seg",
           "sort_hist": "k_rs_hist_seg", "align": "k_bsw"}
 
 
@@ -190,6 +191,8 @@ def rooflines(stages: dict, cells: int, nprof: int, workload: str):
     model = {
         "gather": ("hbm", lambda st: 16 * st["units"]),
         "filter": ("hbm", lambda st: 8 * st["units"]),
+        # one posting entry read per hit; the kept keys it writes are a few per mille
+        "gather_filter": ("hbm", lambda st: 8 * st["units"]),
         "sort_scatter": ("hbm", lambda st: 16 * st["units"]),
         "sort_hist": ("hbm", lambda st: 8 * st["units"]),
         "align": ("alu", lambda st: ALIGN_OPS_PER_CELL * cells * nprof),
@@ -215,7 +218,8 @@ def rooflines(stages: dict, cells: int, nprof: int, workload: str):
     return [one(s) for s in order]
 
 
-STAGES = ("encode", "scan", "gather_prep", "probe", "gather_count", "gather", "group", "filter",
+STAGES = ("encode", "scan", "gather_prep", "probe", "gather_count", "gather", "group",
+          "gather_filter", "filter",
           "filter_compact", "sort_hist", "sort_scan", "sort_scatter", "chain", "chain_write",
           "extend", "merge", "merge_sweep", "select", "align", "report", "graph")
 

@@ -262,6 +262,14 @@ void launch_hit_filter(uint64_t *keys, const uint32_t *hrel, const int64_t *qoff
                        int64_t g0, int32_t nqw, int bp, const int32_t *order, uint32_t *kept,
                        uint32_t *flag, hipStream_t st, WaveCtl *ctl = nullptr,
                        int32_t nq_cap = 0);
+// The gather and the filter's first round in one kernel (no per-hit key stored):
+// one block per query reads its postings twice, to mark the (s, diag) slots and
+// to write the kept keys at the query's place in `keys`; then the same further
+// rounds, LDS sort and flags as launch_hit_filter.
+void launch_gather_filter(const uint32_t *hrel, const uint32_t *pbase, const int2 *post, const int64_t *qoff, int32_t qa, int64_t g0,
+                          int32_t nqw, HitKeyLayout lay, const int32_t *order, uint64_t *keys,
+                          uint32_t *kept, uint32_t *flag, hipStream_t st, WaveCtl *ctl = nullptr,
+                          int32_t nq_cap = 0);
 void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_t *qoff,
                         int32_t qa, int64_t g0, int32_t nqw, const uint32_t *kept, uint32_t *koff,
                         uint32_t *partials, uint64_t *out, hipStream_t st, WaveCtl *ctl = nullptr,
@@ -363,7 +371,8 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
                 unsigned long long *cells_per_q, unsigned long long *cells_per_box,
-                hipStream_t st, const WaveCtl *ctl = nullptr, const uint32_t *sel_box = nullptr);
+                hipStream_t st, const WaveCtl *ctl = nullptr, const uint32_t *sel_box = nullptr,
+                uint32_t *order_buf = nullptr);
 // dir_off[h] = 64 * (sum of q_end - q_start over hits before h), h in [0, n].
 void launch_dir_offsets(const int32_t *hits, int32_t n, int64_t *dir_off, hipStream_t st);
 // ops_len[h] = -1 where status[h] != 0.

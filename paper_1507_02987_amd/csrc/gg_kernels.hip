@@ -1816,10 +1816,184 @@ constexpr int kFiltItems = 8;     // keys per thread and batch, kFiltBlock apart
 constexpr uint32_t kFiltBatch = kFiltBlock * kFiltItems;
 constexpr int kFiltWaves = kFiltBlock / 64;
 
-// Hits of wave query ql: [hrel[qoff[qa + ql] - g0], hrel[qoff[qa + ql + 1] - g0]).
-// A batch is kFiltItems coalesced slabs of kFiltBlock keys whose loads are all in
-// flight together; kept keys are placed in input order by ballots per slab and
-// wave and one scan of those counts per batch.
+// The filter block's LDS: the two bit tables, later the kept keys; kept keys per
+// slab and wave and their exclusive scan.
+struct FiltLds {
+    uint64_t buf[kFiltCap];
+    uint32_t cnt[kFiltItems * kFiltWaves];
+    uint32_t pre[kFiltItems * kFiltWaves];
+    uint32_t tot;
+};
+
+// Stable compaction of one batch: keys v[j] (input index base + j * kFiltBlock +
+// thread) with keep[j] set go to dst + out, in input order, placed by ballots per
+// slab and wave and one scan of those counts.  Returns the batch's kept count.
+__device__ __forceinline__ uint32_t keep_batch(const uint64_t (&v)[kFiltItems],
+                                               const bool (&keep)[kFiltItems],
+                                               uint64_t *__restrict__ dst, uint32_t out,
+                                               FiltLds &L)
+{
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t mask[kFiltItems];
+#pragma unroll
+    for (int j = 0; j < kFiltItems; ++j) {
+        mask[j] = __ballot(keep[j]);
+        if (lane == 0) L.cnt[j * kFiltWaves + w] = (uint32_t)__popcll(mask[j]);
+    }
+    __syncthreads();
+    if (w == 0) {  // slab-major, wave-minor exclusive scan of the counts
+        constexpr int kPer = kFiltItems * kFiltWaves / 64;  // counts per lane
+        static_assert(kPer * 64 == kFiltItems * kFiltWaves, "whole counts per lane");
+        uint32_t c[kPer], x = 0;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            c[e] = L.cnt[kPer * lane + e];
+            x += c[e];
+        }
+        const uint32_t mine = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if ((int)lane >= o) x += y;
+        }
+        uint32_t run = x - mine;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            L.pre[kPer * lane + e] = run;
+            run += c[e];
+        }
+        if (lane == 63) L.tot = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kFiltItems; ++j)
+        if ((mask[j] >> lane) & 1ull)
+            dst[out + L.pre[j * kFiltWaves + w] + (uint32_t)__popcll(mask[j] & below)] = v[j];
+    // the next batch rewrites cnt only before its first barrier, which every wave
+    // reaches after reading pre and tot here
+    return L.tot;
+}
+
+// Marks slot diag_slot(key >> bp, round) of each valid key in the tables: seen
+// once, seen again.
+__device__ __forceinline__ void mark_batch(const uint64_t (&v)[kFiltItems],
+                                           const bool (&valid)[kFiltItems], int bp,
+                                           uint32_t round, uint32_t *__restrict__ seen,
+                                           uint32_t *__restrict__ again)
+{
+#pragma unroll
+    for (int j = 0; j < kFiltItems; ++j) {
+        if (valid[j]) {
+            const uint32_t h = diag_slot(v[j] >> bp, round), bit = 1u << (h & 31u);
+            if (atomicOr(&seen[h >> 5], bit) & bit) atomicOr(&again[h >> 5], bit);
+        }
+    }
+}
+
+__device__ __forceinline__ bool slot_again(uint64_t key, int bp, uint32_t round,
+                                           const uint32_t *__restrict__ again)
+{
+    const uint32_t h = diag_slot(key >> bp, round);
+    return (again[h >> 5] >> (h & 31u)) & 1u;
+}
+
+// Filter rounds `round`, round + 1, ... over the m keys at k, in place; each
+// round's compaction reads a batch before any of its keys move, and keys only
+// move down.  The rounds stop once one drops fewer than an eighth of the keys
+// (the rest are nearly all real groups).  Returns the kept count.
+__device__ uint32_t filter_rounds(uint64_t *__restrict__ k, uint32_t m, uint32_t round, int bp,
+                                  FiltLds &L)
+{
+    uint32_t *seen = reinterpret_cast<uint32_t *>(L.buf), *again = seen + kFiltWords;
+    for (; round < kFiltRounds && m >= kFiltSmall && m <= kFiltMax; ++round) {
+        for (uint32_t i = threadIdx.x; i < 2 * kFiltWords; i += kFiltBlock) seen[i] = 0u;
+        __syncthreads();
+        for (uint32_t base = 0; base < m; base += kFiltBatch) {
+            uint64_t v[kFiltItems];
+            bool in[kFiltItems];
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j) {
+                const uint32_t i = base + j * kFiltBlock + threadIdx.x;
+                in[j] = i < m;
+                v[j] = in[j] ? k[i] : 0ull;
+            }
+            mark_batch(v, in, bp, round, seen, again);
+        }
+        __syncthreads();
+        uint32_t out = 0;
+        for (uint32_t base = 0; base < m; base += kFiltBatch) {
+            uint64_t v[kFiltItems];
+            bool keep[kFiltItems];
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j) {
+                const uint32_t i = base + j * kFiltBlock + threadIdx.x;
+                v[j] = i < m ? k[i] : 0ull;
+            }
+#pragma unroll
+            for (int j = 0; j < kFiltItems; ++j)
+                keep[j] = base + j * kFiltBlock + threadIdx.x < m && slot_again(v[j], bp, round, again);
+            out += keep_batch(v, keep, k, out, L);
+        }
+        __syncthreads();
+        const uint32_t before = m;
+        m = out;
+        if ((before - m) * 8u < before) break;
+    }
+    return m;
+}
+
+// The m kept keys of wave query ql at k: sorted by the whole key in LDS (keys are
+// distinct: a query window meets a posting once), the order the stable radix sort
+// on (s, diag) gives.  A query over the LDS sort is left in qpos order and flagged;
+// a replayed wave drops its hits and flags the query for the host path, which
+// radix-sorts them after the compaction.
+__device__ void filter_finish(uint64_t *__restrict__ k, uint32_t m, int32_t ql,
+                              uint32_t *__restrict__ kept, uint32_t *__restrict__ flag,
+                              WaveCtl *__restrict__ ctl, FiltLds &L)
+{
+    const bool over = m > kFiltCap;
+    if (threadIdx.x == 0) {
+        kept[ql] = (over && ctl) ? 0u : m;
+        if (over) {
+            if (ctl) ctl->qflag[ctl->qa + ql] = 1u;
+            else atomicOr(flag, 1u);
+        }
+    }
+    if (over) return;
+    uint32_t n2 = 1;
+    while (n2 < m) n2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < n2; i += kFiltBlock) L.buf[i] = i < m ? k[i] : ~0ull;
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += kFiltBlock) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = L.buf[i], y = L.buf[l];
+                    if ((i & kk) == 0 ? y < x : x < y) {
+                        L.buf[i] = y;
+                        L.buf[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < m; i += kFiltBlock) k[i] = L.buf[i];
+}
+
+// Wave query `r`-th in the filter's order: blocks take the wave's queries largest
+// first, so the longest filters start early (a replayed wave's order array covers
+// the batch; a host-run wave's, the wave).
+__device__ __forceinline__ int32_t filter_query(const int32_t *__restrict__ order, int32_t qa,
+                                                const WaveCtl *ctl)
+{
+    return !order ? (int32_t)blockIdx.x : order[(ctl ? qa : 0) + (int32_t)blockIdx.x];
+}
+
+// Hits of wave query ql: [hrel[qoff[qa + ql] - g0], hrel[qoff[qa + ql + 1] - g0]),
+// already gathered as keys.
 __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict__ keys,
                                                            const uint32_t *__restrict__ hrel,
                                                            const int64_t *__restrict__ qoff,
@@ -1830,10 +2004,7 @@ __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict_
                                                            uint32_t *__restrict__ flag,
                                                            WaveCtl *__restrict__ ctl)
 {
-    __shared__ uint64_t s_buf[kFiltCap];  // the two bit tables, then the kept keys
-    __shared__ uint32_t s_cnt[kFiltItems * kFiltWaves];  // kept keys per slab and wave
-    __shared__ uint32_t s_pre[kFiltItems * kFiltWaves];  // their exclusive scan
-    __shared__ uint32_t s_tot;
+    __shared__ FiltLds L;
     if (ctl) {
         qa = ctl->qa;
         g0 = ctl->g0;
@@ -1844,122 +2015,212 @@ __global__ __launch_bounds__(kFiltBlock) void k_hit_filter(uint64_t *__restrict_
         if (threadIdx.x == 0) kept[blockIdx.x] = 0;
         return;
     }
-    // blocks take the wave's queries largest first, so the longest filters start early
-    // (a replayed wave's order array covers the batch; a host-run wave's, the wave)
-    const int32_t ql = !order ? (int32_t)blockIdx.x
-                              : order[(ctl ? qa : 0) + (int32_t)blockIdx.x];
-    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-    const uint64_t below = (1ull << lane) - 1ull;
+    const int32_t ql = filter_query(order, qa, ctl);
     const uint32_t a = hrel[qoff[qa + ql] - g0];
-    uint32_t m = hrel[qoff[qa + ql + 1] - g0] - a;
     uint64_t *k = keys + a;
-    uint32_t *seen = reinterpret_cast<uint32_t *>(s_buf), *again = seen + kFiltWords;
-    for (uint32_t round = 0; round < kFiltRounds && m >= kFiltSmall && m <= kFiltMax; ++round) {
-        for (uint32_t i = threadIdx.x; i < 2 * kFiltWords; i += kFiltBlock) seen[i] = 0u;
-        __syncthreads();
-        for (uint32_t base = 0; base < m; base += kFiltBatch) {
-            uint64_t v[kFiltItems];
-#pragma unroll
-            for (int j = 0; j < kFiltItems; ++j) {
-                const uint32_t i = base + j * kFiltBlock + threadIdx.x;
-                v[j] = i < m ? k[i] : 0ull;
-            }
-#pragma unroll
-            for (int j = 0; j < kFiltItems; ++j) {
-                if (base + j * kFiltBlock + threadIdx.x < m) {
-                    const uint32_t h = diag_slot(v[j] >> bp, round), bit = 1u << (h & 31u);
-                    if (atomicOr(&seen[h >> 5], bit) & bit) atomicOr(&again[h >> 5], bit);
-                }
-            }
-        }
-        __syncthreads();
-        // stable compaction in place: a batch is read before any of its keys move,
-        // and keys only move down
-        uint32_t out = 0;
-        for (uint32_t base = 0; base < m; base += kFiltBatch) {
-            uint64_t v[kFiltItems], mask[kFiltItems];
-#pragma unroll
-            for (int j = 0; j < kFiltItems; ++j) {
-                const uint32_t i = base + j * kFiltBlock + threadIdx.x;
-                v[j] = i < m ? k[i] : 0ull;
-            }
-#pragma unroll
-            for (int j = 0; j < kFiltItems; ++j) {
-                bool keep = false;
-                if (base + j * kFiltBlock + threadIdx.x < m) {
-                    const uint32_t h = diag_slot(v[j] >> bp, round);
-                    keep = (again[h >> 5] >> (h & 31u)) & 1u;
-                }
-                mask[j] = __ballot(keep);
-                if (lane == 0) s_cnt[j * kFiltWaves + w] = (uint32_t)__popcll(mask[j]);
-            }
-            __syncthreads();
-            if (w == 0) {  // slab-major, wave-minor exclusive scan of the counts
-                constexpr int kPer = kFiltItems * kFiltWaves / 64;  // counts per lane
-                static_assert(kPer * 64 == kFiltItems * kFiltWaves, "whole counts per lane");
-                uint32_t c[kPer], x = 0;
-#pragma unroll
-                for (int e = 0; e < kPer; ++e) {
-                    c[e] = s_cnt[kPer * lane + e];
-                    x += c[e];
-                }
-                const uint32_t mine = x;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const uint32_t y = __shfl_up(x, o, 64);
-                    if ((int)lane >= o) x += y;
-                }
-                uint32_t run = x - mine;
-#pragma unroll
-                for (int e = 0; e < kPer; ++e) {
-                    s_pre[kPer * lane + e] = run;
-                    run += c[e];
-                }
-                if (lane == 63) s_tot = x;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kFiltItems; ++j)
-                if ((mask[j] >> lane) & 1ull)
-                    k[out + s_pre[j * kFiltWaves + w] + (uint32_t)__popcll(mask[j] & below)] = v[j];
-            out += s_tot;
-        }
-        __syncthreads();
-        const uint32_t before = m;
-        m = out;
-        if ((before - m) * 8u < before) break;  // the rest are (nearly all) real groups
+    const uint32_t m = filter_rounds(k, hrel[qoff[qa + ql + 1] - g0] - a, 0, bp, L);
+    filter_finish(k, m, ql, kept, flag, ctl, L);
+}
+
+// The gather and the first filter round in one pass per query, no key stored
+// before it: each block (one query) builds its hits' keys from the postings, marks
+// their (s, diag) slots, then writes only the keys whose slot was seen again, at
+// the query's place in `keys`; a query of one batch keeps its keys in registers
+// between the two steps, a longer one builds them again.  A query with fewer hits
+// than kFiltSmall or more than kFiltMax is written whole.
+//
+// A batch of kFiltBatch consecutive hits covers the positions pa..pb.  Each position
+// that starts inside the batch marks its first hit's slot with its index, and a
+// forward fill (block max-scan) gives every hit its position; the hit's posting is
+// then the position's list start plus its rank in the position.  A query of at most
+// kFusePos positions has its hit offsets and list starts staged in LDS, and the
+// block finds pa and pb by testing kFiltBlock positions at once.  A longer one has
+// every 2^sb-th offset staged: one thread searches pa and pb, and the batch's
+// offsets and list starts are read from global memory (or, over more than
+// kFusePosBatch positions, each hit searches its own position).
+constexpr int32_t kFusePos = 3832;       // positions whose offsets and list starts are staged
+constexpr int32_t kFusePosBatch = 3832;  // positions one batch may span for the forward fill
+
+__global__ __launch_bounds__(kFiltBlock) void k_gather_filter(
+    const uint32_t *__restrict__ hrel, const uint32_t *__restrict__ pbase,
+    const int2 *__restrict__ post, const int64_t *__restrict__ qoff, int32_t qa, int64_t g0,
+    int32_t nqw, HitKeyLayout lay, const int32_t *__restrict__ order,
+    uint64_t *__restrict__ keys, uint32_t *__restrict__ kept, uint32_t *__restrict__ flag,
+    WaveCtl *__restrict__ ctl)
+{
+    __shared__ FiltLds L;
+    __shared__ uint32_t s_h[kFusePos + 1];  // hit offsets (every 2^sb-th position)
+    __shared__ uint32_t s_b[kFusePos + 1];  // list starts (sb = 0), or the batch's list start
+                                            // minus first hit per position (sb > 0)
+    __shared__ uint16_t s_pos[kFiltBatch];  // batch hit -> position - pa
+    __shared__ int32_t s_wmax[kFiltWaves];
+    __shared__ int32_t s_pab[2];
+    static_assert(kFusePosBatch <= kFusePos + 1, "a batch's list starts fit s_b");
+    if (ctl) {
+        qa = ctl->qa;
+        g0 = ctl->g0;
+        nqw = ctl->nqw;
+        lay = ctl->lay;
     }
-    const bool over = m > kFiltCap;
-    if (threadIdx.x == 0) {
-        // a replayed wave drops an overflowing query's hits and flags it; the host
-        // path radix-sorts them (in qpos order) after the compaction
-        kept[ql] = (over && ctl) ? 0u : m;
-        if (over) {
-            if (ctl) ctl->qflag[ctl->qa + ql] = 1u;
-            else atomicOr(flag, 1u);
-        }
+    if ((int32_t)blockIdx.x >= nqw) {
+        if (threadIdx.x == 0) kept[blockIdx.x] = 0;
+        return;
     }
-    if (over) return;
-    uint32_t n2 = 1;
-    while (n2 < m) n2 <<= 1;
-    for (uint32_t i = threadIdx.x; i < n2; i += kFiltBlock) s_buf[i] = i < m ? k[i] : ~0ull;
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const int bp = lay.bp, sh_s = lay.bp + lay.bd, sh_q = lay.bp + lay.bd + lay.bs;
+    const int32_t ql = filter_query(order, qa, ctl);
+    const uint64_t qpart = sh_q >= 64 ? 0ull : ((uint64_t)(uint32_t)ql << sh_q);
+    const int64_t p0 = qoff[qa + ql] - g0;
+    const int32_t P = (int32_t)(qoff[qa + ql + 1] - g0 - p0);  // positions of the query
+    const uint32_t a = hrel[p0];
+    const uint32_t m = hrel[p0 + P] - a;
+    uint64_t *k = keys + a;
+    int sb = 0;
+    while (((P + (1 << sb) - 1) >> sb) > kFusePos) ++sb;
+    const int32_t Pc = (P + (1 << sb) - 1) >> sb;  // staged offsets: positions c << sb
+    for (int32_t c = threadIdx.x; c < Pc; c += kFiltBlock) {
+        s_h[c] = hrel[p0 + ((int64_t)c << sb)] - a;
+        if (sb == 0) s_b[c] = pbase[p0 + c];
+    }
+    if (sb == 0 && threadIdx.x == 0) s_h[P] = m;
+    int32_t top = 1;
+    while (2 * top < Pc) top <<= 1;
     __syncthreads();
-    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
-        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n2; i += kFiltBlock) {
-                const uint32_t l = i ^ j;
-                if (l > i) {
-                    const uint64_t x = s_buf[i], y = s_buf[l];
-                    if ((i & kk) == 0 ? y < x : x < y) {
-                        s_buf[i] = y;
-                        s_buf[l] = x;
-                    }
+    // position of hit j < m: the last one whose first hit is <= j (positions without
+    // hits share their offset with the next one)
+    auto locate = [&](uint32_t j) -> int32_t {
+        int32_t x = 0;
+        for (int32_t s = top; s > 0; s >>= 1) {
+            const int32_t t = min(x + s, Pc - 1);
+            x = s_h[t] <= j ? t : x;
+        }
+        x <<= sb;
+        for (int32_t s = (1 << sb) >> 1; s > 0; s >>= 1) {
+            const int32_t t = min(x + s, P - 1);
+            if (hrel[p0 + t] - a <= j) x = t;
+        }
+        return x;
+    };
+    auto key_at = [&](int32_t x, const int2 e) -> uint64_t {
+        return qpart + ((uint64_t)(uint32_t)(lay.bias - x + e.y) << bp) + (uint64_t)(uint32_t)x +
+               ((uint64_t)(uint32_t)e.x << sh_s);
+    };
+    int32_t pnext = 0;  // no later batch starts before this position
+    // keys of hits base + r * kFiltBlock + thread (an index past m stands for hit m - 1)
+    auto build = [&](uint32_t base, uint64_t (&v)[kFiltItems]) {
+        const uint32_t nb = min((uint32_t)kFiltBatch, m - base), last = base + nb - 1;
+        __syncthreads();  // the previous batch is done with s_pos, s_b and s_pab
+        if (sb == 0) {
+            if (threadIdx.x == 0) s_pab[0] = s_pab[1] = pnext;
+            __syncthreads();
+            for (int32_t x0 = pnext;; x0 += kFiltBlock) {  // block-uniform
+                const int32_t x = x0 + (int32_t)threadIdx.x;
+                if (x < P) {
+                    const uint32_t f = s_h[x];
+                    if (f <= base) atomicMax(&s_pab[0], x);
+                    if (f <= last) atomicMax(&s_pab[1], x);
                 }
+                __syncthreads();
+                if (s_pab[1] < x0 + kFiltBlock - 1 || x0 + kFiltBlock >= P) break;
+            }
+        } else if (threadIdx.x == 0) {
+            s_pab[0] = locate(base);
+            s_pab[1] = locate(last);
+        }
+        __syncthreads();
+        const int32_t pa = s_pab[0], pb = s_pab[1];
+        pnext = pb;
+        if (sb == 0 || pb - pa < kFusePosBatch) {
+            for (uint32_t i = threadIdx.x; i < nb; i += kFiltBlock) s_pos[i] = 0;
+            __syncthreads();
+            for (int32_t x = pa + (int32_t)threadIdx.x; x <= pb; x += kFiltBlock) {
+                uint32_t f, n;
+                if (sb == 0) {
+                    f = s_h[x];
+                    n = s_h[x + 1] - f;
+                } else {
+                    f = hrel[p0 + x] - a;
+                    n = hrel[p0 + x + 1] - a - f;
+                    s_b[x - pa] = pbase[p0 + x] - f;
+                }
+                if (n > 0 && f > base) s_pos[f - base] = (uint16_t)(x - pa);
             }
             __syncthreads();
+            // forward fill: a block max-scan, kFiltItems consecutive hits per thread
+            int32_t run[kFiltItems], mx = 0;
+#pragma unroll
+            for (int e = 0; e < kFiltItems; ++e) {
+                const uint32_t i = threadIdx.x * kFiltItems + e;
+                mx = max(mx, i < nb ? (int32_t)s_pos[i] : 0);
+                run[e] = mx;
+            }
+            int32_t x = mx;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(x, o, 64);
+                if ((int)lane >= o) x = max(x, y);
+            }
+            if (lane == 63) s_wmax[w] = x;
+            int32_t ex = __shfl_up(x, 1, 64);
+            __syncthreads();
+            if (lane == 0) ex = 0;
+            for (uint32_t i = 0; i < w; ++i) ex = max(ex, s_wmax[i]);
+#pragma unroll
+            for (int e = 0; e < kFiltItems; ++e) {
+                const uint32_t i = threadIdx.x * kFiltItems + e;
+                if (i < nb) s_pos[i] = (uint16_t)max(ex, run[e]);
+            }
+            __syncthreads();
+            uint32_t jj[kFiltItems], idx[kFiltItems];
+            int32_t xs[kFiltItems];
+#pragma unroll
+            for (int r = 0; r < kFiltItems; ++r) {
+                jj[r] = min(base + r * kFiltBlock + threadIdx.x, m - 1);
+                const int32_t rel = s_pos[jj[r] - base];
+                xs[r] = pa + rel;
+                idx[r] = sb == 0 ? s_b[xs[r]] + (jj[r] - s_h[xs[r]]) : jj[r] + s_b[rel];
+            }
+#pragma unroll
+            for (int r = 0; r < kFiltItems; ++r) v[r] = key_at(xs[r], post[idx[r]]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < kFiltItems; ++r) {
+                const uint32_t j = min(base + r * kFiltBlock + threadIdx.x, m - 1);
+                const int32_t x = locate(j);
+                v[r] = key_at(x, post[pbase[p0 + x] + (j - (hrel[p0 + x] - a))]);
+            }
         }
+    };
+    const bool filter = m >= kFiltSmall && m <= kFiltMax;
+    uint32_t *seen = reinterpret_cast<uint32_t *>(L.buf), *again = seen + kFiltWords;
+    uint64_t v[kFiltItems];
+    bool in[kFiltItems];
+    if (filter) {
+        for (uint32_t i = threadIdx.x; i < 2 * kFiltWords; i += kFiltBlock) seen[i] = 0u;
+        for (uint32_t base = 0; base < m; base += kFiltBatch) {
+            build(base, v);
+#pragma unroll
+            for (int r = 0; r < kFiltItems; ++r) in[r] = base + r * kFiltBlock + threadIdx.x < m;
+            mark_batch(v, in, bp, 0, seen, again);
+        }
+        __syncthreads();
+        pnext = 0;
     }
-    for (uint32_t i = threadIdx.x; i < m; i += kFiltBlock) k[i] = s_buf[i];
+    uint32_t out = 0;
+    for (uint32_t base = 0; base < m; base += kFiltBatch) {
+        if (!filter || m > kFiltBatch) build(base, v);  // one batch: the keys are still here
+        bool keep[kFiltItems];
+#pragma unroll
+        for (int r = 0; r < kFiltItems; ++r) {
+            keep[r] = base + r * kFiltBlock + threadIdx.x < m;
+            if (filter) keep[r] = keep[r] && slot_again(v[r], bp, 0, again);
+        }
+        out += keep_batch(v, keep, k, out, L);
+    }
+    __syncthreads();
+    uint32_t n = out;
+    if (filter && (m - n) * 8u >= m) n = filter_rounds(k, n, 1, bp, L);
+    filter_finish(k, n, ql, kept, flag, ctl, L);
 }
 
 // Sum of v[0..n) over the block (kBlock threads); every thread gets it.
@@ -2010,6 +2271,17 @@ void launch_hit_filter(uint64_t *keys, const uint32_t *hrel, const int64_t *qoff
     if (nb > 0)
         k_hit_filter<<<nb, kFiltBlock, 0, st>>>(keys, hrel, qoff, qa, g0, nqw, bp, order, kept,
                                                 flag, ctl);
+}
+
+void launch_gather_filter(const uint32_t *hrel, const uint32_t *pbase, const int2 *post, const int64_t *qoff, int32_t qa, int64_t g0,
+                          int32_t nqw, HitKeyLayout lay, const int32_t *order, uint64_t *keys,
+                          uint32_t *kept, uint32_t *flag, hipStream_t st, WaveCtl *ctl,
+                          int32_t nq_cap)
+{
+    const int32_t nb = ctl ? nq_cap : nqw;
+    if (nb > 0)
+        k_gather_filter<<<nb, kFiltBlock, 0, st>>>(hrel, pbase, post, qoff, qa, g0, nqw, lay,
+                                                   order, keys, kept, flag, ctl);
 }
 
 void launch_hit_compact(const uint64_t *keys, const uint32_t *hrel, const int64_t *qoff,
@@ -3769,15 +4041,55 @@ __device__ __forceinline__ CellOut sw_cell(int32_t hl, int32_t el, int32_t sl, i
     return c;
 }
 
+// Cell with every value offset by kBswBias (the rest of the sweep after the border
+// pairs, staged boxes): minus infinity is any value <= 0, so the zero that a DPP
+// lane shift brings into lane 0 and lane 63 is one, and the shift can feed the
+// subtraction or select that uses it.  The H floor is kBswBias; the score terms and
+// gap costs come in as VGPRs.  The same rules as sw_cell otherwise.
+constexpr int32_t kBswBias = 1 << 29;
+
+__device__ __forceinline__ CellOut sw_cell_b(int32_t hl, int32_t el, int32_t sl, int32_t sel,
+                                             int32_t hu, int32_t fu, int32_t su, int32_t sfu,
+                                             int32_t hd, int32_t sd, bool same, int32_t here,
+                                             int32_t vmatch, int32_t vmis, int32_t vo1,
+                                             int32_t vext)
+{
+    CellOut c;
+    const int32_t eo = hl - vo1, ee = el - vext;
+    const bool eop = eo >= ee;
+    c.E = eop ? eo : ee;
+    c.SE = eop ? sl : sel;
+    const int32_t fo = hu - vo1, fe = fu - vext;
+    const bool fop = fo >= fe;
+    c.F = fop ? fo : fe;
+    c.SF = fop ? su : sfu;
+    const int32_t g = hd + (same ? vmatch : vmis);
+    c.H = max(max(g, kBswBias), max(c.E, c.F));
+    const int32_t sg = hd > kBswBias ? sd : here;
+    c.S = (g == c.H) ? sg : ((c.E == c.H) ? c.SE : c.SF);
+    return c;
+}
+
+// A uniform value in a VGPR of its own (the compiler would otherwise rebuild it
+// from its SGPR inside the loop, where two SGPR operands cannot meet in one select).
+__device__ __forceinline__ int32_t in_vgpr(int32_t s)
+{
+    int32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
 // The sweep over anti-diagonals [a0, a1] in pairs: X = the lane's cell of even
 // parity (t = 2u) on a, Y = its cell of odd parity (t = 2u + 1) on a + 1, one
 // column to the right.  X's left neighbour is the lower lane's previous Y, its
 // upper neighbour this lane's previous Y, its diagonal this lane's previous X;
 // Y's left neighbour is this lane's X, its upper the upper lane's X, its diagonal
-// this lane's previous Y.
+// this lane's previous Y.  Lanes past the band (u > W) follow lane W's cells, so
+// every base they read is in the box; no band cell reads their values.
+// Staged bank bases come in pairs: sd2[x] holds base x and base min(x + 1, C - 1).
 template <bool STAGED>
 __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
-                                          const uint8_t *__restrict__ sd,
+                                          const uint16_t *__restrict__ sd2,
                                           const uint8_t *__restrict__ qp,
                                           const uint32_t *__restrict__ dbw, int64_t dbase,
                                           int32_t R, int32_t C, int32_t c0, int32_t W, int32_t a0,
@@ -3787,7 +4099,8 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
 {
     const int32_t tX = 2 * lane, tY = tX + 1;
     const bool laneX = tX <= 2 * W, laneY = tY <= 2 * W;
-    int32_t i = (a0 - (tX - W + c0)) >> 1;
+    const int32_t dXl = min(tX, 2 * W) - W + c0;  // the lane's X diagonal j - i
+    int32_t i = (a0 - dXl) >> 1;
     int32_t j = a0 - i;
     int32_t hereX = i * 128 + tX;
     // the pair before the first, (i - 1, j - 1) and (i - 1, j), by the rule below: no
@@ -3801,8 +4114,8 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
         const int32_t jc = min(max(jj, 0), C - 1), jc1 = min(max(jj + 1, 0), C - 1);
         if (STAGED) {
             qb = sq[ic];
-            dX = sd[jc];
-            dY = sd[jc1];
+            dX = sd2[jc] & 0xff;
+            dY = sd2[jc1] & 0xff;
         } else {
             qb = qp[ic];
             dX = db_base(dbw, dbase + jc);
@@ -3819,12 +4132,14 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
     // no lane holds, left of slot 0, is the border in column 0 and -inf elsewhere.
     // The first pairs hold cells before the box (row or column < 0); once every
     // band lane has reached row and column 0 (after `edge` pairs) no cell is, and
-    // the rest of the sweep drops the border tests.  There only the one lane whose
-    // Y slot lies past the band (t = 2W + 1) is still forced to -inf, since its X
-    // reads it; other slots past the band are read by no in-band cell.
+    // after one pair more slot 0's left neighbour is -inf for good: the rest of the
+    // sweep drops the border tests.  There only the one lane whose Y slot lies past
+    // the band (t = 2W + 1) is still forced to -inf, since its X reads it; other
+    // slots past the band are read by no in-band cell.
     int32_t edge = (lane <= W) ? max(0, max(-i, -j)) : 0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) edge = max(edge, __shfl_xor(edge, off, 64));
+    edge = __builtin_amdgcn_readfirstlane(edge) + 1;
     auto pair = [&](auto edge_tag) {
         constexpr bool EDGE = decltype(edge_tag)::value;
         const int32_t qb = nqb, dX = ndX, dY = ndY;
@@ -3884,11 +4199,181 @@ __device__ __forceinline__ void bsw_sweep(const uint8_t *__restrict__ sq,
     int32_t a = a0;
     for (const int32_t a_edge = a0 + 2 * edge; a <= a1 && a < a_edge; a += 2, ++i, ++j, hereX += 128)
         pair(std::true_type{});
-    for (; a <= a1; a += 2, ++i, ++j, hereX += 128) pair(std::false_type{});
+    if constexpr (!STAGED) {
+        for (; a <= a1; a += 2, ++i, ++j, hereX += 128) pair(std::false_type{});
+    } else {
+        // In the box's interior every band lane's row and column are >= 1, so the
+        // bases need only the upper clamps, and X (resp. Y) lies in the box while a <
+        // limX (limY): i < R and j < C (j + 1 < C) with i = (a - d) / 2, j = (a + d) / 2.
+        const int32_t limX = laneX ? min(2 * R + dXl, 2 * C - dXl) : INT32_MIN;
+        const int32_t limY = laneY ? min(2 * R + dXl, 2 * C - dXl - 2) : INT32_MIN;
+        const int32_t vmatch = in_vgpr(match), vmis = in_vgpr(-mismatch), vo1 = in_vgpr(o1),
+                      vext = in_vgpr(ext);
+        HX += kBswBias; EX += kBswBias; FX += kBswBias;
+        HY += kBswBias; EY += kBswBias; FY += kBswBias;
+        int32_t bestb = best + kBswBias;
+        // Bases two pairs ahead, in two sets that the pairs use in turn (even pairs
+        // set 0, odd pairs set 1), so a read lands in the register its pair reads two
+        // pairs later, with no copy waiting for it in between.
+        // Bases two pairs ahead, in two sets that the pairs use in turn (even pairs
+        // set 0, odd pairs set 1), so a read lands in the register its pair reads two
+        // pairs later, with no copy waiting for it in between.
+        auto fast_pair = [&](int32_t &nq, uint32_t &nd) {
+            const int32_t qb = nq;
+            const uint32_t dd = nd;
+            nq = sq[min(i + 2, R - 1)];
+            nd = sd2[min(j + 2, C - 1)];
+            // keeps the reads here: without it the compiler moves them down to the pair
+            // that uses them (nothing in the loop writes LDS) and waits for them there
+            asm volatile("" ::: "memory");
+            {  // X
+                const CellOut c = sw_cell_b(from_lower_lane(HY), from_lower_lane(EY),
+                                            from_lower_lane(SY), from_lower_lane(SEY), HY, FY, SY,
+                                            SFY, HX, SX, qb == (int32_t)(dd & 0xffu), hereX,
+                                            vmatch, vmis, vo1, vext);
+                HX = c.H; EX = c.E; FX = c.F;
+                SX = c.S; SEX = c.SE; SFX = c.SF;
+                if (a < limX && c.H > bestb) {
+                    bestb = c.H;
+                    bcell = hereX;
+                    bstart = c.S;
+                }
+            }
+            {  // Y
+                const CellOut c = sw_cell_b(HX, EX, SX, SEX, from_upper_lane(HX),
+                                            from_upper_lane(FX), from_upper_lane(SX),
+                                            from_upper_lane(SFX), HY, SY,
+                                            qb == (int32_t)(dd >> 8), hereX + 1, vmatch, vmis,
+                                            vo1, vext);
+                HY = laneY ? c.H : 0;
+                EY = c.E;
+                FY = laneY ? c.F : 0;
+                SY = c.S; SEY = c.SE; SFY = c.SF;
+                if (a < limY && c.H > bestb) {
+                    bestb = c.H;
+                    bcell = hereX + 1;
+                    bstart = c.S;
+                }
+            }
+            a += 2;
+            ++i;
+            ++j;
+            hereX += 128;
+        };
+        int32_t nq0 = sq[min(max(i, 0), R - 1)], nq1 = sq[min(max(i + 1, 0), R - 1)];
+        uint32_t nd0 = sd2[min(max(j, 0), C - 1)], nd1 = sd2[min(max(j + 1, 0), C - 1)];
+        // pairs in twos; an odd count ends with one pair past the box, whose cells
+        // are out of it (a >= limX, limY) and read no base outside the staged ones
+        while (a <= a1) {
+            fast_pair(nq0, nd0);
+            fast_pair(nq1, nd1);
+        }
+        best = bestb - kBswBias;
+    }
+}
+
+// The b-th selected box and its wave query: named directly by sel_box, or the
+// (b - sel_off[q])-th of query q's selection, q found by binary search.
+__device__ __forceinline__ Box bsw_box(uint32_t b, const Box *__restrict__ sorted,
+                                       const uint32_t *__restrict__ qstart,
+                                       const uint32_t *__restrict__ sel_off, int32_t nq,
+                                       const uint32_t *__restrict__ sel_box, int32_t &q)
+{
+    if (sel_box) {
+        const Box bx = sorted[sel_box[b]];
+        q = bx.q;
+        return bx;
+    }
+    int32_t lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (sel_off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    q = lo;
+    return sorted[qstart[q] + (b - sel_off[q])];
+}
+
+// Launch order of the aligner's boxes, longest first.  A box's sweep is one serial
+// chain of about R + C anti-diagonals, so the longest boxes bound the kernel's
+// time; listed first, they start at once and the short ones fill in around them.
+// Boxes are classed by floor(log2(R + C)) (order within a class is arbitrary: each
+// box writes its own output slot).  cnt[0..32) counts the classes, cnt[32..64)
+// hands out slots within them; both start at zero.
+constexpr int kOrderBlocks = 64;
+
+__device__ __forceinline__ uint32_t bsw_class(const Box &bx)
+{
+    const uint32_t n = (uint32_t)max(bx.qe - bx.qs, 0) + (uint32_t)max(bx.de - bx.ds, 0);
+    return n ? 31u - (uint32_t)__clz(n) : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bsw_classes(
+    const Box *__restrict__ sorted, const uint32_t *__restrict__ qstart,
+    const uint32_t *__restrict__ sel_off, int32_t nq, uint32_t total,
+    const uint32_t *__restrict__ sel_box, uint32_t *__restrict__ cnt,
+    const WaveCtl *__restrict__ ctl)
+{
+    __shared__ uint32_t s_c[32];
+    if (ctl) {
+        nq = ctl->nqw;
+        total = nq > 0 ? sel_off[nq] : 0;
+    }
+    if (threadIdx.x < 32) s_c[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t b = blockIdx.x * kBlock + threadIdx.x; b < total; b += gridDim.x * kBlock) {
+        int32_t q;
+        atomicAdd(&s_c[bsw_class(bsw_box(b, sorted, qstart, sel_off, nq, sel_box, q))], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && s_c[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], s_c[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bsw_order(
+    const Box *__restrict__ sorted, const uint32_t *__restrict__ qstart,
+    const uint32_t *__restrict__ sel_off, int32_t nq, uint32_t total,
+    const uint32_t *__restrict__ sel_box, uint32_t *__restrict__ cnt,
+    uint32_t *__restrict__ order, const WaveCtl *__restrict__ ctl)
+{
+    __shared__ uint32_t s_c[32], s_base[32];
+    if (ctl) {
+        nq = ctl->nqw;
+        total = nq > 0 ? sel_off[nq] : 0;
+    }
+    const uint32_t stride = gridDim.x * kBlock;
+    if (threadIdx.x < 32) s_c[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t cls[8], rank[8];  // a block's boxes: at most 8 per thread per sweep
+    for (uint32_t b0 = blockIdx.x * kBlock; b0 < total; b0 += 8 * stride) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint32_t b = b0 + r * stride + threadIdx.x;
+            cls[r] = 32;
+            if (b < total) {
+                int32_t q;
+                cls[r] = bsw_class(bsw_box(b, sorted, qstart, sel_off, nq, sel_box, q));
+                rank[r] = atomicAdd(&s_c[cls[r]], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 32) {  // the block's slots in each class, classes longest first
+            uint32_t above = 0;
+            for (uint32_t c = 31; c > threadIdx.x; --c) above += cnt[c];
+            const uint32_t n = s_c[threadIdx.x];
+            s_base[threadIdx.x] = n ? above + atomicAdd(&cnt[32 + threadIdx.x], n) : 0u;
+            s_c[threadIdx.x] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (cls[r] < 32) order[s_base[cls[r]] + rank[r]] = b0 + r * stride + threadIdx.x;
+        __syncthreads();
+    }
 }
 
 // One wave (one block) per selected box; boxes whose bases fit kBswStage each
-// for query and data bank are first staged in LDS.
+// for query and data bank are first staged in LDS.  Block i takes the order[i]-th
+// box (the i-th without an order), then every gridDim.x-th after it.
 __global__ __launch_bounds__(64) void k_bsw(
     const Box *__restrict__ sorted, const uint32_t *__restrict__ qstart,
     const uint32_t *__restrict__ sel_off, int32_t nq, uint32_t total,
@@ -3896,32 +4381,21 @@ __global__ __launch_bounds__(64) void k_bsw(
     const uint32_t *__restrict__ dbw, const int64_t *__restrict__ seq_start, int32_t match,
     int32_t mismatch, int32_t o1, int32_t ext, int32_t W, Align *__restrict__ out,
     unsigned long long *__restrict__ cells_q, unsigned long long *__restrict__ cells_box,
-    const uint32_t *__restrict__ sel_box, const WaveCtl *__restrict__ ctl)
+    const uint32_t *__restrict__ sel_box, const uint32_t *__restrict__ order,
+    const WaveCtl *__restrict__ ctl)
 {
     __shared__ uint8_t s_q[kBswStage];
-    __shared__ uint8_t s_d[kBswStage];
+    __shared__ uint16_t s_d2[kBswStage];  // bank bases x and min(x + 1, C - 1)
     const int32_t lane = threadIdx.x;
     if (ctl) {
         nq = ctl->nqw;
         qa = ctl->qa;
         total = nq > 0 ? sel_off[nq] : 0;
     }
-    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+    for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+    const uint32_t b = order ? order[i] : i;
     int32_t q;
-    Box bx;
-    if (sel_box) {  // the b-th selected box named directly: one load before the box
-        bx = sorted[sel_box[b]];
-        q = bx.q;
-    } else {
-        int32_t lo = 0, hi = nq - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (sel_off[mid] <= b) lo = mid;
-            else hi = mid - 1;
-        }
-        q = lo;
-        bx = sorted[qstart[q] + (b - sel_off[q])];
-    }
+    const Box bx = bsw_box(b, sorted, qstart, sel_off, nq, sel_box, q);
     const int32_t R = bx.qe - bx.qs, C = bx.de - bx.ds;
     const int32_t d0 = floor_half(bx.dmin + bx.dmax);
     const int32_t c0 = d0 - (bx.ds - bx.qs);  // cell (i, j) in band iff |j - i - c0| <= W
@@ -3947,12 +4421,14 @@ __global__ __launch_bounds__(64) void k_bsw(
         else if (span > 256) __builtin_amdgcn_s_setprio(1);
         if (R <= kBswStage && C <= kBswStage) {
             for (int32_t x = lane; x < R; x += 64) s_q[x] = qp[x];
-            for (int32_t x = lane; x < C; x += 64) s_d[x] = (uint8_t)db_base(dbw, dbase + x);
+            for (int32_t x = lane; x < C; x += 64)
+                s_d2[x] = (uint16_t)(db_base(dbw, dbase + x) |
+                                     (db_base(dbw, dbase + min(x + 1, C - 1)) << 8));
             __syncthreads();
-            bsw_sweep<true>(s_q, s_d, qp, dbw, dbase, R, C, c0, W, a0, a1, match, mismatch, o1,
+            bsw_sweep<true>(s_q, s_d2, qp, dbw, dbase, R, C, c0, W, a0, a1, match, mismatch, o1,
                             ext, lane, best, bcell, bstart);
         } else {
-            bsw_sweep<false>(s_q, s_d, qp, dbw, dbase, R, C, c0, W, a0, a1, match, mismatch, o1,
+            bsw_sweep<false>(s_q, s_d2, qp, dbw, dbase, R, C, c0, W, a0, a1, match, mismatch, o1,
                              ext, lane, best, bcell, bstart);
         }
     }
@@ -3992,7 +4468,7 @@ __global__ __launch_bounds__(64) void k_bsw(
         if (cells_q) atomicAdd(&cells_q[q], cells);
         if (cells_box) cells_box[b] = cells;
     }
-    __syncthreads();  // the next box restages s_q and s_d
+    __syncthreads();  // the next box restages s_q and s_d2
     }
 }
 
@@ -4001,14 +4477,24 @@ void launch_bsw(const Box *sorted, const uint32_t *qstart, const uint32_t *sel_o
                 const uint32_t *dbw, const int64_t *seq_start, int32_t match, int32_t mismatch,
                 int32_t gap_open, int32_t gap_extend, int32_t band, Align *out,
                 unsigned long long *cells_per_q, unsigned long long *cells_per_box, hipStream_t st,
-                const WaveCtl *ctl, const uint32_t *sel_box)
+                const WaveCtl *ctl, const uint32_t *sel_box, uint32_t *order_buf)
 {
     // graph form: the wave's selection count is read on the device
     const uint32_t grid = ctl ? 8 * kStrideGrid : std::min<uint32_t>(nsel_total, kMaxGrid);
     if (grid == 0) return;
+    uint32_t *order = nullptr;
+    if (order_buf) {
+        uint32_t *cnt = order_buf;
+        order = order_buf + 64;
+        launch_fill_u32(cnt, 64, 0u, st);
+        k_bsw_classes<<<kOrderBlocks, kBlock, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total,
+                                                       sel_box, cnt, ctl);
+        k_bsw_order<<<kOrderBlocks, kBlock, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total,
+                                                     sel_box, cnt, order, ctl);
+    }
     k_bsw<<<grid, 64, 0, st>>>(sorted, qstart, sel_off, nq, nsel_total, qcode, qoff, qa, dbw,
                                seq_start, match, mismatch, gap_open + gap_extend, gap_extend, band,
-                               out, cells_per_q, cells_per_box, sel_box, ctl);
+                               out, cells_per_q, cells_per_box, sel_box, order, ctl);
 }
 
 // ------------------------------------------------------------------ traceback

@@ -113,6 +113,7 @@ struct Workspace {
     DevBuf tpos;                        // the position where each gather tile starts
     DevBuf mbig, mranges;               // merge groups that may outgrow an LDS window
     DevBuf selbox;                      // the box index of each selection (replayed waves)
+    DevBuf bsw_order;                   // the aligner's class counts and box order
     DevBuf bq;                          // the query of each encode block's first base
     // small pinned staging: [0] a wave's counts, [1] a batch's query offsets and hit
     // totals, [2] the replayed waves' plan, overflow flags and result counts
@@ -145,7 +146,7 @@ struct Workspace {
                          &gcursor, &gqflag, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
                          &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox, &bq,
-                         &mbig, &mranges};
+                         &mbig, &mranges, &bsw_order};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -451,6 +452,17 @@ bool merge_windows_enabled()
     return !(e && std::strcmp(e, "global") == 0);
 }
 
+// The filter runs after the gather (k_gather writes every key, k_hit_filter reads
+// them) unless GG_FUSE=1, which builds the keys inside the filter from the postings
+// (k_gather_filter: no key stored before the filter, a quarter of the HBM traffic,
+// but one block per query with block-wide steps between its batches, which on the
+// mid-size bank takes longer than the two kernels apart).
+bool fused_filter_enabled()
+{
+    const char *e = std::getenv("GG_FUSE");
+    return e && std::strcmp(e, "1") == 0;
+}
+
 bool filter_for(const gg_index *ix, const gg_params *p, uint64_t hits, int64_t nq)
 {
     const char *g = getenv("GG_FILTER");
@@ -742,6 +754,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                    sizeof(uint64_t) * scan_partials_needed(std::max<int64_t>(ntile, nqw) + 1)));
         const bool lookback = sort_kind_from_env() == kOneSweep;
         const bool filt = !lookback && !piece && filter_for(ix, p, H, nqw);
+        const bool fused = fused_filter_enabled();
         if (lookback) TRY(ensure(ws->os_scratch, onesweep_scratch_bytes(H)));
         if (filt) {
             TRY(ensure(ws->fkept, sizeof(uint32_t) * (nqw + 1)));
@@ -794,18 +807,29 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             // with one-sweep passes, a look-back wait that ran out sends the wave
             // back to the gather and the per-pass histogram sort
             const bool os = lookback && attempt == 0;
-            prof.begin("gather");
-            launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
-                          np, ix->d_post, H, lay, as<uint64_t>(ws->keys),
-                          piece ? nullptr : as<uint32_t>(ws->tpos), st);
-            prof.end(H);
             uint64_t *kcur = as<uint64_t>(ws->keys), *knext = as<uint64_t>(ws->keys_alt);
+            if (!(filt && fused)) {
+                prof.begin("gather");
+                launch_gather(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase),
+                              as<uint64_t>(ws->akey), np, ix->d_post, H, lay, kcur,
+                              piece ? nullptr : as<uint32_t>(ws->tpos), st);
+                prof.end(H);
+            }
             if (filt) {
                 HIPCHK(hipMemsetAsync(ws->fflag.p, 0, sizeof(uint32_t), st));
-                prof.begin("filter");
-                launch_hit_filter(kcur, as<uint32_t>(ws->hrel), as<int64_t>(ws->qoff), qa, g0, nqw,
-                                  lay.bp, as<int32_t>(ws->ford), as<uint32_t>(ws->fkept),
-                                  as<uint32_t>(ws->fflag), st);
+                if (fused) {
+                    prof.begin("gather_filter");
+                    launch_gather_filter(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase),
+                                         ix->d_post,
+                                         as<int64_t>(ws->qoff), qa, g0, nqw, lay,
+                                         as<int32_t>(ws->ford), kcur, as<uint32_t>(ws->fkept),
+                                         as<uint32_t>(ws->fflag), st);
+                } else {
+                    prof.begin("filter");
+                    launch_hit_filter(kcur, as<uint32_t>(ws->hrel), as<int64_t>(ws->qoff), qa,
+                                      g0, nqw, lay.bp, as<int32_t>(ws->ford),
+                                      as<uint32_t>(ws->fkept), as<uint32_t>(ws->fflag), st);
+                }
                 prof.end(H);
                 prof.begin("filter_compact");
                 launch_hit_compact(kcur, as<uint32_t>(ws->hrel), as<int64_t>(ws->qoff), qa, g0,
@@ -1062,12 +1086,14 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     TRY(ensure(ws->cells_q, sizeof(unsigned long long) * nqw));
     HIPCHK(hipMemsetAsync(ws->cells_q.p, 0, sizeof(unsigned long long) * nqw, st));
     if (piece) TRY(ensure(ws->cells_box, sizeof(unsigned long long) * nsel));
+    TRY(ensure(ws->bsw_order, sizeof(uint32_t) * ((size_t)nsel + 64)));
     prof.begin("align");
     launch_bsw(as<Box>(ws->boxes2), as<uint32_t>(ws->qstart), as<uint32_t>(ws->sel_off), nqw, nsel,
                as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), qa, ix->d_dbw, ix->d_seq_start,
                p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, as<Align>(ws->aligns),
                as<unsigned long long>(ws->cells_q),
-               piece ? as<unsigned long long>(ws->cells_box) : nullptr, st);
+               piece ? as<unsigned long long>(ws->cells_box) : nullptr, st, nullptr, nullptr,
+               as<uint32_t>(ws->bsw_order));
     prof.end(nsel);
     if (piece) {  // the piece's selection, in selection order, is its whole result
         piece->sel.resize(nsel);
@@ -1466,6 +1492,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     uint64_t hsum = 0;
     for (const WaveCtl &w : plan) hsum += w.H;
     const bool filt = filter_for(ix, p, hsum, nq);
+    const bool fused = fused_filter_enabled();
     // radix tiles within query segments, all waves in one table (none when the
     // lone-diagonal filter and the per-query LDS sorts replace the radix passes)
     std::vector<SortTile> tiles, wt;
@@ -1519,6 +1546,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
     TRY(ensure(ws->aligns, sizeof(Align) * std::max<uint32_t>(sel_cap, 1)));
     TRY(ensure(ws->aligns2, sizeof(Align) * std::max<uint32_t>(sel_cap, 1)));
     TRY(ensure(ws->selbox, sizeof(uint32_t) * std::max<uint32_t>(sel_cap, 1)));
+    TRY(ensure(ws->bsw_order, sizeof(uint32_t) * ((size_t)sel_cap + 64)));
     TRY(ensure(ws->gout, sizeof(gg_hit) * nq_out * std::max(cap, 1)));
     TRY(ensure(ws->gn, sizeof(int32_t) * nq_out));
     TRY(ensure(ws->gctl, sizeof(WaveCtl)));
@@ -1542,7 +1570,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                                  (uint64_t)lay.bq, (uint64_t)(uint32_t)lay.bias, (uint64_t)cap,
                                  (uint64_t)(uint32_t)steps, (uint64_t)ix->span,
                                  (uint64_t)ix->mask,
-                                 (uint64_t)(uintptr_t)ix->d_post, (uint64_t)filt};
+                                 (uint64_t)(uintptr_t)ix->d_post, (uint64_t)filt,
+                                 (uint64_t)fused};
     for (int32_t v : {p->match, p->mismatch, p->gap_open, p->gap_extend, p->band, p->xdrop,
                       p->max_gap, p->min_hsp_len, p->max_hits})
         key.push_back((uint64_t)(uint32_t)v);
@@ -1560,7 +1589,7 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                             &ws->cand_q, &ws->cand_off, &ws->nsel, &ws->sel_off, &ws->rstart,
                             &ws->rend, &ws->aligns, &ws->aligns2, &ws->gout, &ws->gn, &ws->gctl,
                             &ws->gplan, &ws->gcursor, &ws->gqflag, &ws->gtiles, &ws->fkept,
-                            &ws->fkoff, &ws->ford, &ws->tpos, &ws->selbox})
+                            &ws->fkoff, &ws->ford, &ws->tpos, &ws->selbox, &ws->bsw_order})
         key.push_back((uint64_t)(uintptr_t)b->p);
 
     if (!ws->gexec || ws->gkey != key) {
@@ -1574,13 +1603,21 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                              as<int32_t>(ws->qid), np_cap, as<uint32_t>(ws->hrel),
                              as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
                              as<WaveCtl>(ws->gplan), cursor, ctl, as<uint32_t>(ws->tpos), st);
-        launch_gather_ctl(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase), as<uint64_t>(ws->akey),
-                          ix->d_post, hits_cap, as<uint64_t>(ws->keys), ctl,
-                          as<uint32_t>(ws->tpos), st);
+        if (!(filt && fused))
+            launch_gather_ctl(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase),
+                              as<uint64_t>(ws->akey), ix->d_post, hits_cap,
+                              as<uint64_t>(ws->keys), ctl, as<uint32_t>(ws->tpos), st);
         if (filt) {
-            launch_hit_filter(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
-                              as<int64_t>(ws->qoff), 0, 0, 0, 0, as<int32_t>(ws->ford),
-                              as<uint32_t>(ws->fkept), nullptr, st, ctl, nq_cap);
+            if (fused)
+                launch_gather_filter(as<uint32_t>(ws->hrel), as<uint32_t>(ws->pbase),
+                                     ix->d_post, as<int64_t>(ws->qoff), 0,
+                                     0, 0, HitKeyLayout{}, as<int32_t>(ws->ford),
+                                     as<uint64_t>(ws->keys), as<uint32_t>(ws->fkept), nullptr, st,
+                                     ctl, nq_cap);
+            else
+                launch_hit_filter(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
+                                  as<int64_t>(ws->qoff), 0, 0, 0, 0, as<int32_t>(ws->ford),
+                                  as<uint32_t>(ws->fkept), nullptr, st, ctl, nq_cap);
             launch_hit_compact(as<uint64_t>(ws->keys), as<uint32_t>(ws->hrel),
                                as<int64_t>(ws->qoff), 0, 0, 0, as<uint32_t>(ws->fkept),
                                as<uint32_t>(ws->fkoff), as<uint32_t>(ws->partials),
@@ -1623,7 +1660,8 @@ gg_status run_graph_waves(const gg_index *ix, Workspace *ws, Prof &prof, const g
                    as<uint8_t>(ws->qcode), as<int64_t>(ws->qoff), 0, ix->d_dbw, ix->d_seq_start,
                    p->match, p->mismatch, p->gap_open, p->gap_extend, p->band,
                    as<Align>(ws->aligns), nullptr, nullptr, st, ctl,
-                   nq_cap <= 4096 ? as<uint32_t>(ws->selbox) : nullptr);
+                   nq_cap <= 4096 ? as<uint32_t>(ws->selbox) : nullptr,
+                   as<uint32_t>(ws->bsw_order));
         launch_report_seg(as<Align>(ws->aligns), as<Align>(ws->aligns2), as<uint32_t>(ws->sel_off),
                           nq_cap, as<uint32_t>(ws->rstart), as<uint32_t>(ws->rend), 0, cap,
                           gout, gn, st, ctl);

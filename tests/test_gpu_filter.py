@@ -8,7 +8,9 @@ equal the oracle's with the filter on and off, in the host-driven and the
 graph-replayed forms; a query whose real diagonal groups hold more hits than the
 LDS sort takes (a 50 kb copy of a bank sequence) goes through the radix sort
 instead, and its graph-replayed wave is run again by the host; with M at or below
-the span the filter stays off and runs of one hit are kept.
+the span the filter stays off and runs of one hit are kept.  Each case runs with
+the two kernels apart (the default, GG_FUSE=0) and with the filter fused into the
+gather (GG_FUSE=1: keys built from the postings, no key stored before the filter).
 """
 import numpy as np
 import pytest
@@ -58,11 +60,16 @@ def check_graph(G, gix, qs, prm, want, cap=1000):
 
 
 def filter_units(gix):
-    return gix.profile_read("filter")["units"]
+    return gix.profile_read("filter")["units"] + gix.profile_read("gather_filter")["units"]
 
 
-def test_filter_on_and_off_on_the_bank_workload(ggo, monkeypatch):
+FUSE = pytest.mark.parametrize("fuse", ["1", "0"])
+
+
+@FUSE
+def test_filter_on_and_off_on_the_bank_workload(ggo, monkeypatch, fuse):
     G = gpu()
+    monkeypatch.setenv("GG_FUSE", fuse)
     monkeypatch.setenv("GG_GROUPING", "sort")
     monkeypatch.delenv("GG_GRAPH", raising=False)
     db = synth.mid_db(n_seqs=20_000)
@@ -73,6 +80,8 @@ def test_filter_on_and_off_on_the_bank_workload(ggo, monkeypatch):
     gix.profile(True)
     check_stats(G, gix, qs, prm, want, wst)
     assert filter_units(gix) > 0  # the filter ran
+    assert gix.profile_read("gather_filter")["units"] > 0 if fuse == "1" else True
+    assert qs.lengths().max() > 2 * 3832  # queries whose offsets are staged sparsely
     check_graph(G, gix, qs, prm, want)
     assert gix.profile_read("graph")["units"] >= 1
     gix.profile(False)
@@ -108,8 +117,10 @@ def copy_bank(seed):
     return seqs, off, qs
 
 
-def test_query_over_the_lds_sort(ggo, monkeypatch):
+@FUSE
+def test_query_over_the_lds_sort(ggo, monkeypatch, fuse):
     G = gpu()
+    monkeypatch.setenv("GG_FUSE", fuse)
     monkeypatch.setenv("GG_GROUPING", "sort")
     monkeypatch.delenv("GG_GRAPH", raising=False)
     seqs, off, qs = copy_bank(61)
