@@ -1361,12 +1361,14 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t active)
     return x * q + min(x, r) + slot;
 }
 
+constexpr int kHistCopies = 16;
+
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys, uint32_t n,
                                                     int shift, uint32_t *__restrict__ hist,
                                                     uint32_t nb, const WaveCtl *__restrict__ ctl,
                                                     const SortTile *__restrict__ tiles)
 {
-    __shared__ uint32_t h[kRadix];
+    __shared__ uint32_t h[kHistCopies * (kRadix + 1)];
     uint32_t ntile = nb;
     if (ctl) {  // shift holds the pass number; tiles past the wave's keys count zeros
         n = ctl->H;
@@ -1378,15 +1380,24 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
     }
     const uint32_t active = tiles ? ntile : (n + kSortTile - 1) / kSortTile;
     const TileView tv = tile_view(xcd_tile(blockIdx.x, active), n, nb, tiles, ntile);
-    h[threadIdx.x] = 0;
+    // kHistCopies counters per digit (lane l adds to copy l % kHistCopies, copies
+    // kRadix + 1 words apart so that they sit in different banks): keys of one digit
+    // are common in a tile (repeats, and the digits above the ones already sorted),
+    // and lanes adding to one address take turns
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) h[c * (kRadix + 1) + threadIdx.x] = 0;
     __syncthreads();
+    uint32_t *mine = h + (threadIdx.x % kHistCopies) * (kRadix + 1);
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t i = r * kBlock + threadIdx.x;
-        if (i < tv.cnt) atomicAdd(&h[(uint32_t)(keys[tv.base + i] >> shift) & (kRadix - 1)], 1u);
+        if (i < tv.cnt) atomicAdd(&mine[(uint32_t)(keys[tv.base + i] >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
-    hist[(size_t)tv.hidx + (size_t)threadIdx.x * tv.stride] = h[threadIdx.x];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) tot += h[c * (kRadix + 1) + threadIdx.x];
+    hist[(size_t)tv.hidx + (size_t)threadIdx.x * tv.stride] = tot;
 }
 
 // One-sweep passes (no per-pass histogram kernel): a tile learns how many keys of
@@ -1902,7 +1913,7 @@ __device__ __forceinline__ bool slot_again(uint64_t key, int bp, uint32_t round,
 // round's compaction reads a batch before any of its keys move, and keys only
 // move down.  The rounds stop once one drops fewer than an eighth of the keys
 // (the rest are nearly all real groups).  Returns the kept count.
-__device__ uint32_t filter_rounds(uint64_t *__restrict__ k, uint32_t m, uint32_t round, int bp,
+__device__ __forceinline__ uint32_t filter_rounds(uint64_t *__restrict__ k, uint32_t m, uint32_t round, int bp,
                                   FiltLds &L)
 {
     uint32_t *seen = reinterpret_cast<uint32_t *>(L.buf), *again = seen + kFiltWords;
@@ -1948,7 +1959,7 @@ __device__ uint32_t filter_rounds(uint64_t *__restrict__ k, uint32_t m, uint32_t
 // on (s, diag) gives.  A query over the LDS sort is left in qpos order and flagged;
 // a replayed wave drops its hits and flags the query for the host path, which
 // radix-sorts them after the compaction.
-__device__ void filter_finish(uint64_t *__restrict__ k, uint32_t m, int32_t ql,
+__device__ __forceinline__ void filter_finish(uint64_t *__restrict__ k, uint32_t m, int32_t ql,
                               uint32_t *__restrict__ kept, uint32_t *__restrict__ flag,
                               WaveCtl *__restrict__ ctl, FiltLds &L)
 {

@@ -86,11 +86,12 @@ def test_long_queries_top100(ggo, large):
     """2,000 queries of 500-5,000 bp, half planted homologs at 75-99% identity, top
     100, through the benchmark's call (host buffers in and out, no statistics);
     the work counts come from a second call with statistics, which must return
-    the same hits.  The oracle checks a sample that holds a query of more than
-    10^8 hits."""
+    the same hits.  The launch choices are the benchmark's for this workload (graph
+    waves for queries of at most 2^18 hits).  The oracle checks a sample that holds
+    a query of more than 10^8 hits."""
     G, db, gix, oix = large
     qs = synth.large_queries(db)
-    gix.set_tuning("sort", 256)
+    gix.set_tuning("sort", 256, 0, 1, 18)
     note(f"{qs.n} long queries on the GPU")
     out = np.zeros(qs.n * 100, G.HIT_DTYPE)
     nout = np.zeros(qs.n, np.int32)
@@ -119,6 +120,20 @@ def test_short_queries_one_batch(ggo, large):
     note(f"done: {int(st['n_hits'].sum())} hits; checking a sample against the oracle")
     pick = sample(st, 150, 10, 3)
     check_sampled(ggo, oix, qs, got, st, pick, 20, 20)
+    # the benchmark's call and launch choices (graph waves for queries of at most
+    # 2^18 hits, host buffers, no statistics) return the same hits for every query
+    gix.set_tuning("sort", 256, 0, 1, 18)
+    out = np.zeros(qs.n * 20, G.HIT_DTYPE)
+    nout = np.zeros(qs.n, np.int32)
+    gix.profile(True)
+    assert gix.search_batch_into(qs.buf, qs.off, prm, out, nout, 20) == 0
+    waves = gix.profile_read("graph")["units"]
+    gix.profile(False)
+    note(f"graph waves in the benchmark's call: {waves}")
+    assert waves > 0
+    assert np.array_equal(nout, n)
+    for i in range(qs.n):
+        assert out[i * 20: i * 20 + int(n[i])].tobytes() == got[i].tobytes(), i
     for i in pick[:40]:
         rc1, h1, n1 = gix.search(qs.query(int(i)), prm, cap=20)
         assert rc1 == 0 and as_rows(h1) == as_rows(got[int(i)])
