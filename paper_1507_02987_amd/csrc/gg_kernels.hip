@@ -2863,14 +2863,18 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
             next += (uint64_t)__popcll(need);
         }
         if (__ballot(have) == 0) break;
+        // one 16-step chunk of every walk per round, so that a lane whose walk ends
+        // takes its next walk without waiting for the longest walk of the wave
         bool done = false;
-        if (have)
-            done = left ? xdrop_words<false>(qpack, gq, dbw, gb, T, match, mismatch, X, cap, t,
+        if (have) {
+            const int32_t lim = min(cap, t + 16);
+            done = left ? xdrop_words<false>(qpack, gq, dbw, gb, T, match, mismatch, X, lim, t,
                                              run, best, bl)
-                        : xdrop_words<true>(qpack, gq, dbw, gb, T, match, mismatch, X, cap, t,
+                        : xdrop_words<true>(qpack, gq, dbw, gb, T, match, mismatch, X, lim, t,
                                             run, best, bl);
+        }
         // a walk past the lane's cap goes to the queue for a whole wave
-        const bool park = have && !done;
+        const bool park = have && !done && t >= cap;
         const uint32_t slot = queue_slot(park, qcount, lane);
         const bool queued = park && slot < qcap;
         if (queued) queue[slot] = XWalk{ri | (left ? 0x80000000u : 0u), t, run, best, bl};
