@@ -2741,60 +2741,57 @@ __device__ __forceinline__ uint32_t bases16_before(const uint32_t *__restrict__ 
     return p <= 0 ? 0u : (bases16_from(w, 0) >> (2u * (uint32_t)(16 - p)));
 }
 
-// X-drop walk of one lane, 16 steps per iteration.  The query and data-bank
-// bases of the next 16 steps are read as packed words, compared at once (a 2-bit
-// XOR), and the running sum moves from one mismatch to the next: between
-// mismatches it only rises, so its maximum over a stretch of matches is at the
-// stretch's end (the first step at that value), and it can only fall more than X
-// below the best at a mismatch.  This is the step-by-step rule exactly.
-// Returns true when the walk ended (drop over X, or T steps); otherwise it
-// stopped at or beyond `cap` steps with its state in (t, run, best, bl).
+// X-drop walk of one lane, 16 steps per chunk.  The query and data-bank bases of
+// the chunk's 16 steps are read as packed words, compared at once (a 2-bit XOR),
+// and the running sum moves from one mismatch to the next: between mismatches it
+// only rises, so its maximum over a stretch of matches is at the stretch's end
+// (the first step at that value), and it can only fall more than X below the best
+// at a mismatch.  This is the step-by-step rule exactly.  xdrop_x reads a chunk's
+// XOR word (t < T: the walk's own bases).
 template <bool RIGHT>
-__device__ __forceinline__ bool xdrop_words(const uint32_t *__restrict__ qpack, int64_t gq,
+__device__ __forceinline__ uint32_t xdrop_x(const uint32_t *__restrict__ qpack, int64_t gq,
                                             const uint32_t *__restrict__ dbw, int64_t gb,
-                                            int32_t T, int32_t match, int32_t mismatch, int32_t X,
-                                            int32_t cap, int32_t &t, int32_t &run, int32_t &best,
-                                            int32_t &bl)
+                                            int32_t t)
 {
-    while (t < T) {
-        if (t >= cap) return false;
-        const int32_t nstep = min(16, T - t);
-        uint32_t mm;
-        if (RIGHT) {
-            const uint32_t x = bases16_from(qpack, gq + t) ^ bases16_from(dbw, gb + t);
-            // step i (0-based) is the base in bits 31-2i:30-2i; one flag bit per step
-            mm = (x | (x >> 1)) & 0x55555555u;
-            if (nstep < 16) mm &= ~(0xFFFFFFFFu >> (2 * nstep));
-        } else {
-            const uint32_t x = bases16_before(qpack, gq - t) ^ bases16_before(dbw, gb - t);
-            // step i is the base in bits 2i+1:2i
-            mm = (x | (x >> 1)) & 0x55555555u;
-            if (nstep < 16) mm &= (1u << (2 * nstep)) - 1u;
-        }
-        int32_t pos = 0;
-        for (;;) {
-            int32_t nx = nstep;  // step of the next mismatch in this chunk
-            if (mm) nx = RIGHT ? (int32_t)((__clz(mm) - 1) >> 1) : (int32_t)((__ffs(mm) - 1) >> 1);
-            const int32_t r = nx - pos;
-            if (r > 0) {
-                run += r * match;
-                if (run > best) {
-                    best = run;
-                    bl = t + nx;
-                }
+    // RIGHT: step i (0-based) is the base in bits 31-2i:30-2i; otherwise in bits 2i+1:2i
+    return RIGHT ? bases16_from(qpack, gq + t) ^ bases16_from(dbw, gb + t)
+                 : bases16_before(qpack, gq - t) ^ bases16_before(dbw, gb - t);
+}
+
+// One chunk of a walk (t < T): the up to 16 steps from t, whose query and bank
+// bases differ where the 2-bit XOR x is non-zero.  Returns true when the walk
+// ended (drop over X, or T steps); otherwise t has moved 16 steps on.
+template <bool RIGHT>
+__device__ __forceinline__ bool xdrop_chunk(uint32_t x, int32_t T, int32_t match,
+                                            int32_t mismatch, int32_t X, int32_t &t, int32_t &run,
+                                            int32_t &best, int32_t &bl)
+{
+    const int32_t nstep = min(16, T - t);
+    uint32_t mm = (x | (x >> 1)) & 0x55555555u;  // one flag bit per step
+    if (nstep < 16) mm &= RIGHT ? ~(0xFFFFFFFFu >> (2 * nstep)) : (1u << (2 * nstep)) - 1u;
+    int32_t pos = 0;
+    for (;;) {
+        int32_t nx = nstep;  // step of the next mismatch in this chunk
+        if (mm) nx = RIGHT ? (int32_t)((__clz(mm) - 1) >> 1) : (int32_t)((__ffs(mm) - 1) >> 1);
+        const int32_t r = nx - pos;
+        if (r > 0) {
+            run += r * match;
+            if (run > best) {
+                best = run;
+                bl = t + nx;
             }
-            if (nx >= nstep) break;
-            run -= mismatch;
-            if (best - run > X) {
-                t += nx + 1;
-                return true;
-            }
-            mm &= RIGHT ? ~(1u << (30 - 2 * nx)) : ~(1u << (2 * nx));
-            pos = nx + 1;
         }
-        t += nstep;
+        if (nx >= nstep) break;
+        run -= mismatch;
+        if (best - run > X) {
+            t += nx + 1;
+            return true;
+        }
+        mm &= RIGHT ? ~(1u << (30 - 2 * nx)) : ~(1u << (2 * nx));
+        pos = nx + 1;
     }
-    return true;
+    t += nstep;
+    return t >= T;
 }
 
 // Extension of every run on both sides (Section 2.2 phase 3).  Each side of each
@@ -2832,6 +2829,8 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
     Cand c{0, 0, 0, 0, 0};
     int64_t gq = 0, gb = 0;
     int32_t T = 0, t = 0, run = 0, best = 0, bl = 0, cap = 0;
+    uint32_t xn = 0;   // the bases' XOR of a going walk's next chunk, when xok
+    bool xok = false;
     for (;;) {
         // lanes without a walk take the next walks of the wave's range
         const uint64_t need = __ballot(!have);
@@ -2864,21 +2863,32 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
         }
         if (__ballot(have) == 0) break;
         // one 16-step chunk of every walk per round, so that a lane whose walk ends
-        // takes its next walk without waiting for the longest walk of the wave
-        bool done = false;
+        // takes its next walk without waiting for the longest walk of the wave; a
+        // walk that goes on has its next chunk's bases read at the end of the round,
+        // so the reads overlap the other lanes' refills
+        bool done = false, park = false;
         if (have) {
-            const int32_t lim = min(cap, t + 16);
-            done = left ? xdrop_words<false>(qpack, gq, dbw, gb, T, match, mismatch, X, lim, t,
-                                             run, best, bl)
-                        : xdrop_words<true>(qpack, gq, dbw, gb, T, match, mismatch, X, lim, t,
-                                            run, best, bl);
+            if (t >= T) {
+                done = true;
+            } else if (t >= cap) {
+                park = true;  // past the lane's cap: to the queue for a whole wave
+            } else {
+                const uint32_t x = xok ? xn
+                                       : (left ? xdrop_x<false>(qpack, gq, dbw, gb, t)
+                                               : xdrop_x<true>(qpack, gq, dbw, gb, t));
+                done = left ? xdrop_chunk<false>(x, T, match, mismatch, X, t, run, best, bl)
+                            : xdrop_chunk<true>(x, T, match, mismatch, X, t, run, best, bl);
+            }
         }
-        // a walk past the lane's cap goes to the queue for a whole wave
-        const bool park = have && !done && t >= cap;
+        xok = false;
         const uint32_t slot = queue_slot(park, qcount, lane);
         const bool queued = park && slot < qcap;
         if (queued) queue[slot] = XWalk{ri | (left ? 0x80000000u : 0u), t, run, best, bl};
         if (park && !queued) cap = INT32_MAX;  // queue full: this lane finishes the walk
+        if (have && !done && !queued && t < cap) {
+            xn = left ? xdrop_x<false>(qpack, gq, dbw, gb, t) : xdrop_x<true>(qpack, gq, dbw, gb, t);
+            xok = true;
+        }
         if (done || queued) {
             Box *b = out + ri;
             if (left) {
