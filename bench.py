@@ -293,6 +293,24 @@ def mid_leg(args) -> dict:
     return out
 
 
+def aligner_probe(L: int) -> None:
+    """One query copying L bases of a random bank sequence, with substitutions at
+    2% of its positions: the search ends in one L x L box, whose banded DP is one
+    serial chain of about L pair steps (the aligner's time per pair step)."""
+    rng = np.random.default_rng(3)
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    bank = acgt[rng.integers(0, 4, L + 1000)]
+    q = bank[500:500 + L].copy()
+    pos = rng.choice(L, L // 50, replace=False)
+    q[pos] = acgt[(np.searchsorted(acgt, q[pos]) + 1) % 4]
+    gix = gg.Index(bank, np.array([0, len(bank)], np.int64), 11, device=0)
+    prm = gg.params(10)
+    for _ in range(5):
+        rc, hits, n = gix.search(q.tobytes(), prm, cap=10)
+    log(f"aligner probe: status {rc}, {n} hit(s), first box "
+        f"{(int(hits[0]['box_q_end']) - int(hits[0]['box_q_start'])) if n else 0} query bases")
+
+
 def short_leg(db, gix, args) -> dict:
     """100,000 short queries against the large bank in one batched call, beside
     the plain one-query-at-a-time loop over 2,000 of them."""
@@ -424,6 +442,9 @@ def main() -> int:
                     help="only stream-read BYTES three times (counter calibration)")
     ap.add_argument("--only-mid", action="store_true",
                     help="only the mid-size device-resident leg, printed as JSON (profiler runs)")
+    ap.add_argument("--aligner-probe", type=int, default=0, metavar="L",
+                    help="only search, 5 times, one query copying L bases of a bank sequence "
+                         "with 2%% substitutions: one L x L box for the aligner (profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -444,6 +465,9 @@ def main() -> int:
 
     if args.only_mid:
         print(json.dumps(mid_leg(args)), flush=True)
+        return 0
+    if args.aligner_probe:
+        aligner_probe(args.aligner_probe)
         return 0
 
     t = time.perf_counter()

@@ -3576,18 +3576,27 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(const Box *__restrict__ 
         };
         Box cur = decode(s_key[j0]);
         uint32_t w = j0;
-        for (uint32_t j = j0 + 1; j < j1; ++j) {
-            const Box h = decode(s_key[j]);
-            if (h.qs < cur.qe && h.ds < cur.de && cur.ds < h.de) {
-                cur.qs = min(cur.qs, h.qs);
-                cur.qe = max(cur.qe, h.qe);
-                cur.ds = min(cur.ds, h.ds);
-                cur.de = max(cur.de, h.de);
-                cur.dmin = min(cur.dmin, h.dmin);
-                cur.dmax = max(cur.dmax, h.dmax);
-            } else {
-                out[base + o + w++] = cur;
-                cur = h;
+        // keys read eight at a time ahead of the fold, which is serial in the group
+        constexpr uint32_t kAheadKeys = 8;
+        for (uint32_t j = j0 + 1; j < j1; j += kAheadKeys) {
+            uint64_t hk[kAheadKeys];
+#pragma unroll
+            for (uint32_t x = 0; x < kAheadKeys; ++x) hk[x] = s_key[min(j + x, j1 - 1)];
+#pragma unroll
+            for (uint32_t x = 0; x < kAheadKeys; ++x) {
+                if (j + x >= j1) break;
+                const Box h = decode(hk[x]);
+                if (h.qs < cur.qe && h.ds < cur.de && cur.ds < h.de) {
+                    cur.qs = min(cur.qs, h.qs);
+                    cur.qe = max(cur.qe, h.qe);
+                    cur.ds = min(cur.ds, h.ds);
+                    cur.de = max(cur.de, h.de);
+                    cur.dmin = min(cur.dmin, h.dmin);
+                    cur.dmax = max(cur.dmax, h.dmax);
+                } else {
+                    out[base + o + w++] = cur;
+                    cur = h;
+                }
             }
         }
         out[base + o + w++] = cur;
