@@ -504,9 +504,11 @@ def main() -> int:
         if (i + 1) % 5 == 0:
             log(f"timed step {i + 1}/{args.steps}")
     dt = time.perf_counter() - t0
+    # --steps 0 (profiler runs): only the per-stage step below runs on the GPU
     qps = qs.n * args.steps / dt
     gbp_kbp = (db.total_bp / 1e9) * (qs.lengths().sum() / 1e3) * args.steps / dt
-    log(f"timed {args.steps} steps: {dt * 1e3 / args.steps:.1f} ms/step, {qps:.1f} queries/s")
+    log(f"timed {args.steps} steps: {dt * 1e3 / max(args.steps, 1):.1f} ms/step, "
+        f"{qps:.1f} queries/s")
 
     # per-stage GPU time over one more step, with per-query work counts
     def run(stats=False):
@@ -545,7 +547,8 @@ def main() -> int:
 
     line = {
         "metric": METRIC, "value": round(qps, 2), "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 2),
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / max(args.steps, 1), 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": desc, "db_bp": db.total_bp, "queries": qs.n,
