@@ -2328,41 +2328,23 @@ __device__ __forceinline__ bool chains_to(uint64_t a, uint64_t b, int bp, int32_
     return (a >> bp) == (b >> bp) && (int32_t)(b & pmask) - ((int32_t)(a & pmask) + k) <= G;
 }
 
-// Exclusive maximum over the 256 threads of a block (-1 before thread 0).
-__device__ __forceinline__ int32_t block_excl_max(int32_t v)
-{
-    __shared__ int32_t s_w[kBlock / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x = max(x, y);
-    }
-    if (lane == 63) s_w[w] = x;
-    int32_t ex = __shfl_up(x, 1, 64);
-    if (lane == 0) ex = -1;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i)
-        if (i < w) ex = max(ex, s_w[i]);
-    __syncthreads();
-    return ex;
-}
-
 // s_qs[l] = qpos of the first hit of the run that tile hit l belongs to.  Starts
-// inside the tile come from a block-wide running maximum of start positions; the
+// inside the tile come from a running maximum of start positions over the tile's
+// 32 chunks of 64 hits (chunk 4 r + w is wave w's r-th row of the block's items,
+// so each wave scans its own rows and the chunks' maxima are combined once); the
 // run that enters the tile from before it is walked back once, by wave 0, 64 keys
 // at a time.
 __device__ void tile_run_starts(const uint64_t *__restrict__ s_k,
                                 const uint64_t *__restrict__ keys, uint32_t base, uint32_t cnt,
                                 int bp, int32_t k, int32_t G, int32_t *__restrict__ s_qs)
 {
+    constexpr int kChunks = kItems * (kBlock / 64);
     __shared__ int32_t s_carry;
+    __shared__ int32_t s_cm[kChunks];
     const uint64_t pmask = low_mask(bp);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const bool enters = cnt > 0 && base > 0 && chains_to(keys[base - 1], s_k[1], bp, k, G);
     if (threadIdx.x < 64 && enters) {
-        const int lane = threadIdx.x;
         for (uint32_t c = 0;; c += 64) {
             // key j = base - 1 - c - lane starts the run unless key j - 1 chains to it
             const int64_t j = (int64_t)base - 1 - c - lane;
@@ -2376,23 +2358,37 @@ __device__ void tile_run_starts(const uint64_t *__restrict__ s_k,
             }
         }
     }
-    const uint32_t l0 = threadIdx.x * kItems;
-    int32_t last = -1, st[kItems];
+    int32_t st[kItems];
 #pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-        const uint32_t l = l0 + u;
-        if (l < cnt) {
-            const bool start = l == 0 ? !enters : !chains_to(s_k[l], s_k[1 + l], bp, k, G);
-            if (start) last = (int32_t)l;
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t l = r * kBlock + threadIdx.x;
+        bool start = false;
+        if (l < cnt) start = l == 0 ? !enters : !chains_to(s_k[l], s_k[1 + l], bp, k, G);
+        int32_t x = start ? (int32_t)l : -1;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x = max(x, y);
         }
-        st[u] = last;
+        st[r] = x;
+        if (lane == 63) s_cm[r * (kBlock / 64) + w] = x;
     }
-    const int32_t before = block_excl_max(last);  // ends with a barrier: s_carry is set
+    __syncthreads();  // s_cm and s_carry are set
+    // exclusive maximum of the chunk maxima, chunk c in lane c
+    int32_t cm = lane < kChunks ? s_cm[lane] : -1;
 #pragma unroll
-    for (int u = 0; u < kItems; ++u) {
-        const uint32_t l = l0 + u;
+    for (int o = 1; o < kChunks; o <<= 1) {
+        const int32_t y = __shfl_up(cm, o, 64);
+        if (lane >= o) cm = max(cm, y);
+    }
+    int32_t ex = __shfl_up(cm, 1, 64);
+    if (lane == 0) ex = -1;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t l = r * kBlock + threadIdx.x;
+        const int32_t before = __shfl(ex, r * (kBlock / 64) + w, 64);
         if (l < cnt) {
-            const int32_t a = max(st[u], before);
+            const int32_t a = max(st[r], before);
             s_qs[l] = a >= 0 ? (int32_t)(s_k[1 + a] & pmask) : s_carry;
         }
     }
@@ -2476,26 +2472,49 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
     const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
     tile_run_starts(s_k, keys, base, cnt, lay.bp, k, G, s_qs);
     uint32_t at = SELF ? block_sum(tile_off, blockIdx.x) : tile_off[blockIdx.x];
+    // runs in hit order: row r of wave w is chunk 4 r + w; one scan of the chunks'
+    // run counts places every run
+    constexpr int kChunks = kItems * (kBlock / 64);
+    __shared__ uint32_t s_cc[kChunks];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t em[kItems];
+    int32_t qsv[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const uint32_t l = r * kBlock + threadIdx.x;
-        int32_t qs = 0;
-        const bool emit = l < cnt && chain_end_tile(s_k, s_qs, n, base, l, lay.bp, k, G, M, &qs);
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<uint32_t>(emit ? 1u : 0u, &tot);
-        if (emit) {
+        qsv[r] = 0;
+        const bool emit = l < cnt && chain_end_tile(s_k, s_qs, n, base, l, lay.bp, k, G, M, &qsv[r]);
+        em[r] = __ballot(emit);
+        if (lane == 0) s_cc[r * (kBlock / 64) + w] = (uint32_t)__popcll(em[r]);
+    }
+    __syncthreads();
+    uint32_t cc = lane < kChunks ? s_cc[lane] : 0u;
+#pragma unroll
+    for (int o = 1; o < kChunks; o <<= 1) {
+        const uint32_t y = __shfl_up(cc, o, 64);
+        if (lane >= o) cc += y;
+    }
+    const uint32_t total = __shfl(cc, kChunks - 1, 64);
+    uint32_t ex = __shfl_up(cc, 1, 64);
+    if (lane == 0) ex = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t l = r * kBlock + threadIdx.x;
+        const uint32_t chunk_at = __shfl(ex, r * (kBlock / 64) + w, 64);
+        if ((em[r] >> lane) & 1ull) {
             const uint64_t key = s_k[1 + l];
             const uint64_t grp = key >> lay.bp;
             Cand c;
             c.d = (int32_t)(grp & low_mask(lay.bd)) - lay.bias;
             c.s = (int32_t)(shr64(grp, lay.bd) & low_mask(lay.bs));
             c.q = (int32_t)shr64(grp, lay.bd + lay.bs);
-            c.qs = qs;
+            c.qs = qsv[r];
             c.qe = (int32_t)(key & low_mask(lay.bp)) + k;
-            out[at + ex] = c;
+            out[at + chunk_at + (uint32_t)__popcll(em[r] & below)] = c;
         }
-        at += tot;
     }
+    at += total;
     if (SELF && base + kTile >= n && threadIdx.x == 0) ctl->nc = at;  // the last tile
 }
 
