@@ -2777,6 +2777,21 @@ __device__ __forceinline__ uint32_t xdrop_x(const uint32_t *__restrict__ qpack, 
                  : bases16_before(qpack, gq - t) ^ bases16_before(dbw, gb - t);
 }
 
+// The chunk's XOR word for a walk of either side, step i in bits 31-2i:30-2i: a
+// left walk's word is read like a right walk's, 16 positions lower, and bit-
+// reversed (its first step is the base nearest the run).  Both sides of a wave's
+// walks then take one code path.
+__device__ __forceinline__ uint32_t xdrop_xw(const uint32_t *__restrict__ qpack, int64_t gq,
+                                             const uint32_t *__restrict__ dbw, int64_t gb,
+                                             int32_t t, bool left)
+{
+    const int64_t pq = left ? gq - t - 16 : gq + t, pb = left ? gb - t - 16 : gb + t;
+    uint32_t x;
+    if (pq >= 0 && pb >= 0) x = bases16_from(qpack, pq) ^ bases16_from(dbw, pb);
+    else x = xdrop_x<false>(qpack, gq, dbw, gb, t);  // a left walk near the arrays' starts
+    return left ? __brev(x) : x;
+}
+
 // One chunk of a walk (t < T): the up to 16 steps from t, whose query and bank
 // bases differ where the 2-bit XOR x is non-zero.  Returns true when the walk
 // ended (drop over X, or T steps); otherwise t has moved 16 steps on.
@@ -2892,11 +2907,8 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
             } else if (t >= cap) {
                 park = true;  // past the lane's cap: to the queue for a whole wave
             } else {
-                const uint32_t x = xok ? xn
-                                       : (left ? xdrop_x<false>(qpack, gq, dbw, gb, t)
-                                               : xdrop_x<true>(qpack, gq, dbw, gb, t));
-                done = left ? xdrop_chunk<false>(x, T, match, mismatch, X, t, run, best, bl)
-                            : xdrop_chunk<true>(x, T, match, mismatch, X, t, run, best, bl);
+                const uint32_t x = xok ? xn : xdrop_xw(qpack, gq, dbw, gb, t, left);
+                done = xdrop_chunk<true>(x, T, match, mismatch, X, t, run, best, bl);
             }
         }
         xok = false;
@@ -2905,7 +2917,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
         if (queued) queue[slot] = XWalk{ri | (left ? 0x80000000u : 0u), t, run, best, bl};
         if (park && !queued) cap = INT32_MAX;  // queue full: this lane finishes the walk
         if (have && !done && !queued && t < cap) {
-            xn = left ? xdrop_x<false>(qpack, gq, dbw, gb, t) : xdrop_x<true>(qpack, gq, dbw, gb, t);
+            xn = xdrop_xw(qpack, gq, dbw, gb, t, left);
             xok = true;
         }
         if (done || queued) {
