@@ -401,17 +401,41 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI *__restrict__ i
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// One block scans the tile sums in place, kTile at a time (read coalesced into
+// LDS, kItems consecutive sums per thread, one block scan per kTile).
 template <typename TO>
 __global__ __launch_bounds__(kBlock) void k_scan_partials(TO *__restrict__ partials, int64_t nb)
 {
+    __shared__ TO s_v[kTile];
     TO carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
-        const int64_t i = b0 + threadIdx.x;
-        const TO v = (i < nb) ? partials[i] : (TO)0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kTile) {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t i = b0 + r * kBlock + threadIdx.x;
+            s_v[r * kBlock + threadIdx.x] = i < nb ? partials[i] : (TO)0;
+        }
+        __syncthreads();
+        TO v[kItems], sum = 0;
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            v[r] = s_v[threadIdx.x * kItems + r];
+            sum += v[r];
+        }
         TO tot;
-        const TO ex = block_excl_scan<TO>(v, &tot);
-        if (i < nb) partials[i] = carry + ex;
+        TO run = block_excl_scan<TO>(sum, &tot) + carry;
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            s_v[threadIdx.x * kItems + r] = run;
+            run += v[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t i = b0 + r * kBlock + threadIdx.x;
+            if (i < nb) partials[i] = s_v[r * kBlock + threadIdx.x];
+        }
         carry += tot;
+        __syncthreads();  // the next chunk refills s_v
     }
     if (threadIdx.x == 0) partials[nb] = carry;
 }
