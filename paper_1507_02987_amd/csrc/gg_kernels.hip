@@ -1387,6 +1387,10 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t active)
 
 constexpr int kHistCopies = 16;
 
+// Two keys read by one 16-byte load from an address that is only 8-byte aligned
+// (global loads need dword alignment only).
+typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys, uint32_t n,
                                                     int shift, uint32_t *__restrict__ hist,
                                                     uint32_t nb, const WaveCtl *__restrict__ ctl,
@@ -1410,12 +1414,21 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
     // and lanes adding to one address take turns
 #pragma unroll
     for (int c = 0; c < kHistCopies; ++c) h[c * (kRadix + 1) + threadIdx.x] = 0;
+    // keys read two per 16-byte load (tile starts are only 8-byte aligned)
+    u64x2_a8 k[kSortItems / 2];
+#pragma unroll
+    for (int r = 0; r < kSortItems / 2; ++r) {
+        const uint32_t i = 2 * (r * kBlock + threadIdx.x);
+        if (i + 1 < tv.cnt) k[r] = *reinterpret_cast<const u64x2_a8 *>(keys + tv.base + i);
+        else if (i < tv.cnt) k[r].x = keys[tv.base + i];
+    }
     __syncthreads();
     uint32_t *mine = h + (threadIdx.x % kHistCopies) * (kRadix + 1);
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t i = r * kBlock + threadIdx.x;
-        if (i < tv.cnt) atomicAdd(&mine[(uint32_t)(keys[tv.base + i] >> shift) & (kRadix - 1)], 1u);
+    for (int r = 0; r < kSortItems / 2; ++r) {
+        const uint32_t i = 2 * (r * kBlock + threadIdx.x);
+        if (i < tv.cnt) atomicAdd(&mine[(uint32_t)(k[r].x >> shift) & (kRadix - 1)], 1u);
+        if (i + 1 < tv.cnt) atomicAdd(&mine[(uint32_t)(k[r].y >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
     uint32_t tot = 0;
@@ -2438,10 +2451,17 @@ __device__ __forceinline__ uint32_t stage_chain_tile(const uint64_t *__restrict_
                                                      uint32_t base, uint64_t *__restrict__ s_k)
 {
     const uint32_t cnt = base < n ? min((uint32_t)kTile, n - base) : 0u;
+    // two keys per 16-byte load (tile starts are multiples of kTile keys)
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const uint32_t l = r * kBlock + threadIdx.x;
-        if (l < cnt) s_k[1 + l] = keys[base + l];
+    for (int r = 0; r < kItems / 2; ++r) {
+        const uint32_t l = 2 * (r * kBlock + threadIdx.x);
+        if (l + 1 < cnt) {
+            const u64x2_a8 v = *reinterpret_cast<const u64x2_a8 *>(keys + base + l);
+            s_k[1 + l] = v.x;
+            s_k[2 + l] = v.y;
+        } else if (l < cnt) {
+            s_k[1 + l] = keys[base + l];
+        }
     }
     if (threadIdx.x == 0 && base + cnt < n) s_k[cnt + 1] = keys[base + cnt];
     __syncthreads();
