@@ -385,57 +385,137 @@ void launch_encode_kmers(const uint8_t *ascii, const int64_t *qoff, int32_t nq, 
 // sums.  Up to kScanFuse tiles, each tile adds the earlier sums up itself (they are
 // few and cached); beyond that one block first scans the tile sums.
 constexpr int64_t kScanFuse = 2048;
+
+// Four or two values read or written by one 16-byte access at an address that is
+// only aligned to the value size (global accesses need dword alignment only).
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+
+// v[0 .. kItems) = p[i0 .. i0 + kItems), zeros past n; 16-byte loads when the
+// thread's kItems values are all in range.
+template <typename T>
+__device__ __forceinline__ void load_items(const T *__restrict__ p, int64_t i0, int64_t n,
+                                           T (&v)[kItems])
+{
+    if (i0 + kItems <= n) {
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int r = 0; r < kItems / 4; ++r) {
+                const u32x4_a4 x = *reinterpret_cast<const u32x4_a4 *>(p + i0 + 4 * r);
+                v[4 * r] = x.x;
+                v[4 * r + 1] = x.y;
+                v[4 * r + 2] = x.z;
+                v[4 * r + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kItems / 2; ++r) {
+                const u64x2_a8 x = *reinterpret_cast<const u64x2_a8 *>(p + i0 + 2 * r);
+                v[2 * r] = x.x;
+                v[2 * r + 1] = x.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) v[r] = i0 + r < n ? p[i0 + r] : (T)0;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_items(T *__restrict__ p, int64_t i0, int64_t n,
+                                            const T (&v)[kItems])
+{
+    if (i0 + kItems <= n) {
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int r = 0; r < kItems / 4; ++r) {
+                u32x4_a4 x;
+                x.x = v[4 * r];
+                x.y = v[4 * r + 1];
+                x.z = v[4 * r + 2];
+                x.w = v[4 * r + 3];
+                *reinterpret_cast<u32x4_a4 *>(p + i0 + 4 * r) = x;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kItems / 2; ++r) {
+                u64x2_a8 x;
+                x.x = v[2 * r];
+                x.y = v[2 * r + 1];
+                *reinterpret_cast<u64x2_a8 *>(p + i0 + 2 * r) = x;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r)
+            if (i0 + r < n) p[i0 + r] = v[r];
+    }
+}
+
+// Scans of n values in tiles of kTile: thread t of a tile holds values
+// [t kItems, t kItems + kItems) of it (16-byte accesses, adjacent threads on
+// adjacent 32-byte pieces).  k_scan_reduce sums each tile; one block scans the
+// tile sums; k_scan_down scans each tile from its offset.  Up to kScanFuse tiles,
+// each tile adds the earlier sums up itself (they are few and cached).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI *__restrict__ in, int64_t n,
                                                         TO *__restrict__ partials)
 {
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    TI v[kItems];
+    load_items<TI>(in, (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems, n, v);
     TO s = 0;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + r * kBlock + threadIdx.x;
-        if (i < n) s += (TO)in[i];
-    }
+    for (int r = 0; r < kItems; ++r) s += (TO)v[r];
     TO tot;
     block_excl_scan<TO>(s, &tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// One block scans the tile sums in place, kTile at a time (read coalesced into
-// LDS, kItems consecutive sums per thread, one block scan per kTile).
+// One block of kPartBlock threads scans the nb tile sums in place and stores the
+// total at partials[nb].  A chunk of kPartBlock * kItems sums is read at once,
+// kItems consecutive sums per thread, so a few hundred thousand tiles take a few
+// chunks, each one round trip to memory.
+constexpr int kPartBlock = 1024;
+
 template <typename TO>
-__global__ __launch_bounds__(kBlock) void k_scan_partials(TO *__restrict__ partials, int64_t nb)
+__global__ __launch_bounds__(kPartBlock) void k_scan_partials(TO *__restrict__ partials, int64_t nb)
 {
-    __shared__ TO s_v[kTile];
+    constexpr int kWaves = kPartBlock / 64;
+    __shared__ TO s_w[kWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     TO carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += kTile) {
+    for (int64_t b0 = 0; b0 < nb; b0 += (int64_t)kPartBlock * kItems) {
+        const int64_t i0 = b0 + (int64_t)threadIdx.x * kItems;
+        TO v[kItems];
+        load_items<TO>(partials, i0, nb, v);
+        TO sum = 0;
 #pragma unroll
-        for (int r = 0; r < kItems; ++r) {
-            const int64_t i = b0 + r * kBlock + threadIdx.x;
-            s_v[r * kBlock + threadIdx.x] = i < nb ? partials[i] : (TO)0;
+        for (int r = 0; r < kItems; ++r) sum += v[r];
+        TO x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const TO y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
+        if (lane == 63) s_w[w] = x;
         __syncthreads();
-        TO v[kItems], sum = 0;
+        TO before = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i) {
+            const TO t = s_w[i];
+            if (i < w) before += t;
+            tot += t;
+        }
+        TO run = carry + before + x - sum;
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
-            v[r] = s_v[threadIdx.x * kItems + r];
-            sum += v[r];
+            const TO t = v[r];
+            v[r] = run;
+            run += t;
         }
-        TO tot;
-        TO run = block_excl_scan<TO>(sum, &tot) + carry;
-#pragma unroll
-        for (int r = 0; r < kItems; ++r) {
-            s_v[threadIdx.x * kItems + r] = run;
-            run += v[r];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kItems; ++r) {
-            const int64_t i = b0 + r * kBlock + threadIdx.x;
-            if (i < nb) partials[i] = s_v[r * kBlock + threadIdx.x];
-        }
+        store_items<TO>(partials, i0, nb, v);
         carry += tot;
-        __syncthreads();  // the next chunk refills s_v
+        __syncthreads();  // s_w is rewritten by the next chunk
     }
     if (threadIdx.x == 0) partials[nb] = carry;
 }
@@ -446,7 +526,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in,
                                                       TO *__restrict__ out, int64_t nb,
                                                       TO *__restrict__ total_copy)
 {
-    __shared__ TO s_v[kTile];
     // FUSED: partials holds each earlier tile's sum; this tile's offset is their sum
     // (a single tile reads none)
     TO pre = 0, all = 0;
@@ -458,34 +537,22 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const TI *__restrict__ in,
         pre = partials[blockIdx.x];
         all = partials[nb];
     }
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + r * kBlock + threadIdx.x;
-        s_v[r * kBlock + threadIdx.x] = (i < n) ? (TO)in[i] : (TO)0;
-    }
-    __syncthreads();
-    TO v[kItems];
+    const int64_t i0 = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    TI v[kItems];
+    load_items<TI>(in, i0, n, v);
     TO s = 0;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        v[r] = s_v[threadIdx.x * kItems + r];
-        s += v[r];
-    }
+    for (int r = 0; r < kItems; ++r) s += (TO)v[r];
     TO tot;
     TO run = block_excl_scan<TO>(s, &tot) + pre;
     if (FUSED) all = pre + tot;
+    TO o[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        s_v[threadIdx.x * kItems + r] = run;
-        run += v[r];
+        o[r] = run;
+        run += (TO)v[r];
     }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + r * kBlock + threadIdx.x;
-        if (i < n) out[i] = s_v[r * kBlock + threadIdx.x];
-    }
+    store_items<TO>(out, i0, n, o);
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
         out[n] = all;
         if (total_copy) *total_copy = all;
@@ -511,7 +578,7 @@ static void scan_impl(const TI *in, TO *out, int64_t n, TO *partials, hipStream_
         k_scan_down<TI, TO, true><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(in, n, partials,
                                                                                out, nb, total_copy);
     } else {
-        k_scan_partials<TO><<<1, kBlock, 0, st>>>(partials, nb);
+        k_scan_partials<TO><<<1, kPartBlock, 0, st>>>(partials, nb);
         k_scan_down<TI, TO, false><<<dim3((uint32_t)nb), dim3(kBlock), 0, st>>>(
             in, n, partials, out, nb, total_copy);
     }
@@ -1386,10 +1453,6 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t active)
 }
 
 constexpr int kHistCopies = 16;
-
-// Two keys read by one 16-byte load from an address that is only 8-byte aligned
-// (global loads need dword alignment only).
-typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys, uint32_t n,
                                                     int shift, uint32_t *__restrict__ hist,
@@ -2821,10 +2884,10 @@ __device__ __forceinline__ uint32_t xdrop_x(const uint32_t *__restrict__ qpack, 
                  : bases16_before(qpack, gq - t) ^ bases16_before(dbw, gb - t);
 }
 
-// The chunk's XOR word for a walk of either side, step i in bits 31-2i:30-2i: a
-// left walk's word is read like a right walk's, 16 positions lower, and bit-
-// reversed (its first step is the base nearest the run).  Both sides of a wave's
-// walks then take one code path.
+// The chunk's XOR word for a walk of either side, step i in bits 2i+1:2i.  A left
+// walk's word is read 16 positions lower, its first step (the base nearest the
+// run) in the low bits; a right walk's word is bit-reversed into the same order.
+// Both sides of a wave's walks then take one code path.
 __device__ __forceinline__ uint32_t xdrop_xw(const uint32_t *__restrict__ qpack, int64_t gq,
                                              const uint32_t *__restrict__ dbw, int64_t gb,
                                              int32_t t, bool left)
@@ -2833,43 +2896,42 @@ __device__ __forceinline__ uint32_t xdrop_xw(const uint32_t *__restrict__ qpack,
     uint32_t x;
     if (pq >= 0 && pb >= 0) x = bases16_from(qpack, pq) ^ bases16_from(dbw, pb);
     else x = xdrop_x<false>(qpack, gq, dbw, gb, t);  // a left walk near the arrays' starts
-    return left ? __brev(x) : x;
+    return left ? x : __brev(x);
 }
 
 // One chunk of a walk (t < T): the up to 16 steps from t, whose query and bank
-// bases differ where the 2-bit XOR x is non-zero.  Returns true when the walk
-// ended (drop over X, or T steps); otherwise t has moved 16 steps on.
-template <bool RIGHT>
+// bases differ where the 2-bit XOR x is non-zero (step i in bits 2i+1:2i).  Each
+// turn of the loop takes the stretch of matches up to the next mismatch (the
+// running sum's maximum over it is at its end) and then that mismatch, whose drop
+// is tested; past the chunk's last mismatch the stretch runs to the chunk's end.
+// Returns true when the walk ended (drop over X, or T steps); otherwise t has
+// moved 16 steps on.
 __device__ __forceinline__ bool xdrop_chunk(uint32_t x, int32_t T, int32_t match,
                                             int32_t mismatch, int32_t X, int32_t &t, int32_t &run,
                                             int32_t &best, int32_t &bl)
 {
     const int32_t nstep = min(16, T - t);
     uint32_t mm = (x | (x >> 1)) & 0x55555555u;  // one flag bit per step
-    if (nstep < 16) mm &= RIGHT ? ~(0xFFFFFFFFu >> (2 * nstep)) : (1u << (2 * nstep)) - 1u;
-    int32_t pos = 0;
-    for (;;) {
-        int32_t nx = nstep;  // step of the next mismatch in this chunk
-        if (mm) nx = RIGHT ? (int32_t)((__clz(mm) - 1) >> 1) : (int32_t)((__ffs(mm) - 1) >> 1);
-        const int32_t r = nx - pos;
-        if (r > 0) {
-            run += r * match;
-            if (run > best) {
-                best = run;
-                bl = t + nx;
-            }
-        }
-        if (nx >= nstep) break;
-        run -= mismatch;
-        if (best - run > X) {
-            t += nx + 1;
-            return true;
-        }
-        mm &= RIGHT ? ~(1u << (30 - 2 * nx)) : ~(1u << (2 * nx));
+    if (nstep < 16) mm &= (1u << (2 * nstep)) - 1u;
+    int32_t pos = 0, nx;
+    bool drop;
+    do {
+        nx = mm ? (int32_t)(__builtin_ctz(mm) >> 1) : nstep;  // the next mismatch
+        run += (nx - pos) * match;
+        bl = run > best ? t + nx : bl;  // first step at a new best
+        best = max(best, run);
+        run -= mismatch;  // undone below when the chunk had no mismatch left
+        drop = best - run > X;
+        mm &= mm - 1u;
         pos = nx + 1;
+    } while (nx < nstep && !drop);
+    if (nx >= nstep) {
+        run += mismatch;
+        t += nstep;
+        return t >= T;
     }
-    t += nstep;
-    return t >= T;
+    t += nx + 1;
+    return true;
 }
 
 // Extension of every run on both sides (Section 2.2 phase 3).  Each side of each
@@ -2952,7 +3014,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
                 park = true;  // past the lane's cap: to the queue for a whole wave
             } else {
                 const uint32_t x = xok ? xn : xdrop_xw(qpack, gq, dbw, gb, t, left);
-                done = xdrop_chunk<true>(x, T, match, mismatch, X, t, run, best, bl);
+                done = xdrop_chunk(x, T, match, mismatch, X, t, run, best, bl);
             }
         }
         xok = false;
