@@ -3587,7 +3587,192 @@ __device__ void lds_radix_sort(uint64_t *__restrict__ s_key, uint32_t m, uint64_
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_merge_tiles(const Box *__restrict__ in, uint32_t n,
+// The running union of a sweep's merged boxes: query start, end, bank start, end,
+// extreme diagonals.
+struct MAgg {
+    int32_t qs, qe, ds, de, dmin, dmax;
+};
+
+__device__ __forceinline__ MAgg magg_none()
+{
+    return MAgg{INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN};
+}
+
+__device__ __forceinline__ MAgg magg_join(const MAgg &a, const MAgg &b)
+{
+    return MAgg{min(a.qs, b.qs), max(a.qe, b.qe), min(a.ds, b.ds),
+                max(a.de, b.de), min(a.dmin, b.dmin), max(a.dmax, b.dmax)};
+}
+
+// The sweep's test: box (qs, ds, de) joins the running union cur.
+__device__ __forceinline__ bool magg_takes(const MAgg &cur, int32_t qs, int32_t ds, int32_t de)
+{
+    return qs < cur.qe && ds < cur.de && cur.ds < de;
+}
+
+__device__ __forceinline__ MAgg magg_shfl_up(const MAgg &a, int o)
+{
+    return MAgg{__shfl_up(a.qs, o, 64), __shfl_up(a.qe, o, 64), __shfl_up(a.ds, o, 64),
+                __shfl_up(a.de, o, 64), __shfl_up(a.dmin, o, 64), __shfl_up(a.dmax, o, 64)};
+}
+
+// Exclusive segmented scan over the block's threads: thread t holds (f, a) = (a
+// segment starts in its items, union of its items from its last start on); it
+// receives the union over the items before its own back to the last start (the
+// union of the segment its first item continues).  Pairs combine as (f1, a1) then
+// (f2, a2) -> (f1 | f2, f2 ? a2 : a1 + a2).
+__device__ MAgg seg_excl_union(bool f, const MAgg &a)
+{
+    __shared__ int32_t s_wf[kBlock / 64];
+    __shared__ MAgg s_wa[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t fi = f ? 1 : 0;
+    MAgg x = a;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t yf = __shfl_up(fi, o, 64);
+        const MAgg y = magg_shfl_up(x, o);
+        if (lane >= o) {
+            if (!fi) x = magg_join(y, x);
+            fi |= yf;
+        }
+    }
+    if (lane == 63) {
+        s_wf[w] = fi;
+        s_wa[w] = x;
+    }
+    int32_t ef = __shfl_up(fi, 1, 64);
+    MAgg ex = magg_shfl_up(x, 1);
+    if (lane == 0) {
+        ef = 0;
+        ex = magg_none();
+    }
+    __syncthreads();
+    MAgg pre = magg_none();
+    for (int i = 0; i < w; ++i) pre = s_wf[i] ? s_wa[i] : magg_join(pre, s_wa[i]);
+    __syncthreads();  // s_wf and s_wa are rewritten by the next call
+    return ef ? ex : magg_join(pre, ex);
+}
+
+// Parallel form of the sweep of a window's owned groups (keys [0, m) sorted in
+// s_key, group g's keys [s_start[g] - o, s_start[g + 1] - o)).  Thread t takes keys
+// [8 t, 8 t + 8).  A key starts a merged box when it starts its group or the sweep
+// does not join it to the union before it.  Tentative starts: group starts and
+// the keys that do not join the one box before them (a box that joins its
+// predecessor joins any union holding it).  Each round scans the unions of the
+// tentative segments and drops the starts that join the union before them; the
+// test only gets easier as unions grow, and tentative segments are never larger
+// than the sweep's, so a dropped start is never a start of the sweep, and when a
+// round drops nothing every key's union is the sweep's and the starts are
+// exactly its.  Returns false (nothing written) when kMergeRounds rounds did not
+// settle; the caller then sweeps group by group.
+constexpr int kMergeRounds = 12;
+
+__device__ bool merge_sweep_parallel(const uint64_t *__restrict__ s_key, uint32_t m,
+                                     const uint16_t *__restrict__ s_start, uint32_t o,
+                                     uint32_t nw, uint16_t *__restrict__ s_pg,
+                                     uint8_t *__restrict__ s_f8, int bl, int bd, int32_t bias,
+                                     const Box *__restrict__ in, Box *__restrict__ out,
+                                     uint32_t at)
+{
+    constexpr int kPer = kMergeSpan / kBlock;  // 8 keys per thread
+    const uint64_t mbl = (1ull << bl) - 1ull, mbd = (1ull << bd) - 1ull;
+    const int gsh = 2 * bl + bd;
+    const uint32_t j0 = threadIdx.x * kPer;
+    // key j's box (read from LDS on each pass rather than held in registers)
+    auto box_of = [&](uint64_t key) {
+        const int32_t qe = (int32_t)(key & mbl);
+        const int32_t d = (int32_t)((key >> bl) & mbd) - bias;
+        const int32_t qs = (int32_t)((key >> (bl + bd)) & mbl);
+        return MAgg{qs, qe, qs + d, qe + d, d, d};
+    };
+    uint32_t V = 0, F = 0, GS = 0;  // valid keys, tentative starts, group starts
+    {
+        uint64_t prev = j0 > 0 && j0 < m ? s_key[j0 - 1] : 0ull;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const uint32_t j = j0 + r;
+            if (j >= m) break;
+            const uint64_t key = s_key[j];
+            const bool gs = j == 0 || (prev >> gsh) != (key >> gsh);
+            bool st = gs;
+            if (!gs) {
+                const MAgg a = box_of(prev), b = box_of(key);
+                st = !magg_takes(a, b.qs, b.ds, b.de);
+            }
+            V |= 1u << r;
+            if (gs) GS |= 1u << r;
+            if (st) F |= 1u << r;
+            prev = key;
+        }
+    }
+    MAgg carry;
+    for (int round = 0;; ++round) {
+        if (round == kMergeRounds) return false;
+        bool sf = false;
+        MAgg sa = magg_none();
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            if (!((V >> r) & 1u)) continue;
+            const MAgg b = box_of(s_key[j0 + r]);
+            if ((F >> r) & 1u) {
+                sf = true;
+                sa = b;
+            } else {
+                sa = magg_join(sa, b);
+            }
+        }
+        carry = seg_excl_union(sf, sa);
+        MAgg run = carry;
+        bool changed = false;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            if (!((V >> r) & 1u)) continue;
+            const uint32_t bit = 1u << r;
+            const MAgg b = box_of(s_key[j0 + r]);
+            if ((F & bit) && !(GS & bit) && magg_takes(run, b.qs, b.ds, b.de)) {
+                F &= ~bit;
+                changed = true;
+            }
+            run = (F & bit) ? b : magg_join(run, b);
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    // merged box k of group g goes to the group's k-th position: k is its rank
+    // among the group's starts, P(j) - P(first key of g) with P(j) the starts in
+    // [0, j]; the group's remaining positions are marked empty
+    uint32_t tot;
+    const uint32_t before = block_excl_scan<uint32_t>((uint32_t)__popc(F), &tot);
+    s_f8[threadIdx.x] = (uint8_t)F;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+        if ((GS >> r) & 1u)
+            s_pg[(uint32_t)(s_key[j0 + r] >> gsh)] = (uint16_t)(before + __popc(F & ((2u << r) - 1u)));
+    __syncthreads();
+    MAgg run = carry;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        if (!((V >> r) & 1u)) continue;
+        const uint32_t j = j0 + r;
+        const uint64_t key = s_key[j];
+        const uint32_t g = (uint32_t)(key >> gsh);
+        const MAgg b = box_of(key);
+        run = ((F >> r) & 1u) ? b : magg_join(run, b);
+        const uint32_t first = (uint32_t)s_start[g] - o;
+        const uint32_t p0 = s_pg[g];
+        const uint32_t nseg = (g + 1 < nw ? (uint32_t)s_pg[g + 1] - 1u : tot) - p0 + 1u;
+        if (j - first >= nseg) out[at + j].q = -1;
+        const bool last = j + 1 >= m || (r + 1 < kPer ? ((F >> (r + 1)) & 1u) != 0
+                                                        : (s_f8[threadIdx.x + 1] & 1u) != 0);
+        if (!last) continue;
+        const uint32_t rank = before + __popc(F & ((2u << r) - 1u)) - p0;
+        const int2 qsid = *reinterpret_cast<const int2 *>(in + at + j);
+        out[at + first + rank] = Box{qsid.x, qsid.y, run.qs, run.qe, run.ds, run.de, run.dmin, run.dmax};
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock, 6) void k_merge_tiles(const Box *__restrict__ in, uint32_t n,
                                                         int bl, int bd, int32_t bias,
                                                         Box *__restrict__ out,
                                                         uint32_t *__restrict__ big, uint32_t big_cap)
@@ -3701,6 +3886,12 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(const Box *__restrict__ 
     }
     __syncthreads();
     lds_radix_sort(s_key, m, s_vary[0] & s_vary[1]);
+    // the key-building ranks are no longer needed: their space holds the
+    // parallel sweep's per-group counts
+    if (merge_sweep_parallel(s_key, m, s_start, o, nw, s_rank,
+                             reinterpret_cast<uint8_t *>(s_rank + kMergeWin), bl, bd, bias, in, out,
+                             base + o))
+        return;
     // sweep each owned group from its keys
     for (uint32_t g = threadIdx.x; g < nw; g += kBlock) {
         const uint32_t j0 = s_start[g] - o, j1 = s_start[g + 1] - o;
