@@ -147,14 +147,26 @@ void launch_traceback(const int32_t *hits, int32_t n, const uint8_t *qascii, int
                       int32_t mismatch, int32_t gap_open, int32_t gap_extend, int32_t band,
                       const int64_t *dir_off, uint8_t *dirs, const int64_t *ops_off, char *ops,
                       int32_t *ops_len, int32_t *status, hipStream_t st);
-// Selection prefilter over n boxes in query order: per-query length histograms
+// Selection prefilter over n box slots in query order.  Each slot has a length
+// record binq[i] = (q << 10) | length bin (kNoBin: empty slot), written where the
+// boxes are merged (LenSel) or by launch_len_records[_ranges] over the slots.
+// From the records alone the prefilter takes the per-query length histograms
 // (hist: nq * kLenBins, cleared here), the threshold bin thr[q] and box count
 // nvalid[q], and per-tile kept counts scanned in place (kept total at
-// tile_counts[tiles]); then the kept boxes, in order, to out.
-void launch_len_prefilter(const Box *b, uint32_t n, int32_t nq, int32_t N, int shift,
-                          uint32_t *hist, uint32_t *thr, uint32_t *nvalid, uint32_t *tile_counts,
+// tile_counts[tiles]); launch_len_compact then writes the kept boxes, in order, to
+// out.
+constexpr uint32_t kNoBin = 0xFFFFFFFFu;
+struct LenSel {
+    uint32_t *binq = nullptr;  // per-slot records (nullptr: no prefilter)
+    int shift = 0;             // length >> shift is the bin (clamped to kLenBins - 1)
+};
+void launch_len_records(const Box *b, uint32_t n, LenSel ls, hipStream_t st);
+void launch_len_records_ranges(const Box *b, const uint32_t *ranges, uint32_t nr, LenSel ls,
+                               hipStream_t st);
+void launch_len_prefilter(const uint32_t *binq, uint32_t n, int32_t nq, int32_t N, uint32_t *hist,
+                          uint32_t *thr, uint32_t *nvalid, uint32_t *tile_counts,
                           uint32_t *partials, hipStream_t st);
-void launch_len_compact(const Box *b, uint32_t n, int shift, const uint32_t *thr,
+void launch_len_compact(const Box *b, const uint32_t *binq, uint32_t n, const uint32_t *thr,
                         const uint32_t *tile_off, Box *out, hipStream_t st);
 // Both strands: dst holds each sequence's reverse complement at the sequence's own
 // start (start: n_seqs + 1 forward starts).
@@ -336,9 +348,14 @@ void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st)
 // extension, in windows of whole groups held in LDS; keys (group rank | qs |
 // d + bias | qe) take 12 + 2 bl + bd <= 64 bits.  Groups that may outgrow a
 // window are listed in big: big[0] = count, then (first, end) pairs, at most
-// big_cap of them; their positions in `out` are left for the global sort.
+// big_cap of them; their positions in `out` are left for the global sort.  A
+// window's sweep runs in parallel over its boxes for at most `rounds` rounds of
+// segmented scans; a window that has not settled by then (every window when
+// rounds = 0) is swept group by group, one thread per group.  With ls.binq the
+// owned groups' slots get their length records.
+constexpr int kMergeRounds = 12;
 void launch_merge_tiles(const Box *in, uint32_t n, int bl, int bd, int32_t bias, Box *out,
-                        uint32_t *big, uint32_t big_cap, hipStream_t st);
+                        uint32_t *big, uint32_t big_cap, int rounds, LenSel ls, hipStream_t st);
 // Boxes of ranges [ranges[2r], ranges[2r + 1]) to (to_packed) or from a packed
 // array starting at offs[r].
 void launch_copy_ranges(const Box *src, Box *dst, const uint32_t *ranges, const uint32_t *offs,

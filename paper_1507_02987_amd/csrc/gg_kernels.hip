@@ -3503,9 +3503,10 @@ __global__ void k_merge_sweep(const Box *__restrict__ s, uint32_t n, Box *__rest
 // group becomes one 64-bit key (group rank | qs | d + bias | qe): the boxes leave
 // the extension unmerged, so ds = qs + d and de = qe + d, and the key orders a
 // group exactly as (qs, ds, qe, de) does (equal keys are equal boxes).  The keys
-// are sorted in LDS (bitonic) and each owned group is then swept from its keys by
-// one thread, as k_merge_sweep does: merged boxes from the group's first
-// position, the rest marked empty.  A group that may not fit (the last one the
+// are sorted in LDS (radix passes) and the owned groups are then swept from their
+// keys with the result of k_merge_sweep's one-thread sweep, in parallel over the
+// window (merge_sweep_parallel) or, when that has not settled, one thread per
+// group: merged boxes from the group's first position, the rest marked empty.  A group that may not fit (the last one the
 // block owns, when no other group starts before the block's reach) is recorded
 // in big[1 ..] as (first, end) and left to the global sort; big[0] counts them.
 constexpr uint32_t kMergeWin = 1024;
@@ -3517,8 +3518,9 @@ constexpr uint32_t kMergeSpan = 2 * kMergeWin;
 // eight ballots (as the global passes rank a tile), the block scans the per-wave
 // digit counts, and the keys are written to their places in s_key and read back
 // for the next pass.  Only passes whose digit varies across the keys run
-// (`varying`: OR of every key XOR the first).
-__device__ void lds_radix_sort(uint64_t *__restrict__ s_key, uint32_t m, uint64_t varying)
+// (`varying`: OR of every key XOR the first), digits from bit `lo` up (keys equal
+// from bit lo up keep their order).
+__device__ void lds_radix_sort(uint64_t *__restrict__ s_key, uint32_t m, uint64_t varying, int lo)
 {
     constexpr int kPerWave = kMergeSpan / (kBlock / 64);  // 512
     constexpr int kRounds = kPerWave / 64;                 // 8
@@ -3531,7 +3533,7 @@ __device__ void lds_radix_sort(uint64_t *__restrict__ s_key, uint32_t m, uint64_
         const uint32_t idx = w * kPerWave + r * 64 + lane;
         k[r] = idx < m ? s_key[idx] : 0ull;
     }
-    for (int shift = 0; shift < 64; shift += kRadixBits) {
+    for (int shift = lo; shift < 64; shift += kRadixBits) {
         if (((varying >> shift) & (kRadix - 1)) == 0) continue;  // same digit everywhere
 #pragma unroll
         for (int i = 0; i < kBlock / 64; ++i) s_wc[i][threadIdx.x] = 0;
@@ -3585,6 +3587,88 @@ __device__ void lds_radix_sort(uint64_t *__restrict__ s_key, uint32_t m, uint64_
         }
     }
     __syncthreads();
+}
+
+// Orders each run of the m keys in s_key that are equal from bit lo up by the
+// whole key, after a sort that left such runs in their input order: odd-even
+// transposition rounds over adjacent keys of one run, until a round swaps none
+// (true) or `rounds` rounds have passed (false; the runs may be out of order).
+// Runs are short (boxes that start on one diagonal at one query position), so
+// one round that swaps nothing is the usual cost.
+constexpr int kTieRounds = 8;
+
+__device__ bool lds_order_ties(uint64_t *__restrict__ s_key, uint32_t m, int lo, int rounds)
+{
+    for (int round = 0; round < rounds; ++round) {
+        bool swapped = false;
+#pragma unroll
+        for (int phase = 0; phase < 2; ++phase) {
+            for (uint32_t i = 2 * threadIdx.x + phase; i + 1 < m; i += 2 * kBlock) {
+                const uint64_t a = s_key[i], b = s_key[i + 1];
+                if ((a >> lo) == (b >> lo) && a > b) {
+                    s_key[i] = b;
+                    s_key[i + 1] = a;
+                    swapped = true;
+                }
+            }
+            __syncthreads();
+        }
+        if (!__syncthreads_or(swapped)) return true;
+    }
+    return false;
+}
+
+// Length bin of a box for the selection prefilter (length >> shift, clamped) and
+// its slot record (q << 10) | bin.
+__device__ __forceinline__ uint32_t len_bin(const Box &b, int shift)
+{
+    return min((uint32_t)min(b.qe - b.qs, b.de - b.ds) >> shift, (uint32_t)(kLenBins - 1));
+}
+
+__device__ __forceinline__ uint32_t len_record(const Box &b, int shift)
+{
+    return ((uint32_t)b.q << 10) | len_bin(b, shift);
+}
+
+static_assert(kLenBins == 1024, "length records keep the bin in 10 bits");
+
+// Adds a block's length records (up to kPer per thread, kNoBin for none) to the
+// per-query histograms: in LDS (s_h, kLenBins words) and one global atomic per
+// bin in use when they all belong to one query, else one global atomic each.
+template <int kPer>
+__device__ __forceinline__ void len_hist_block(const uint32_t (&rec)[kPer], uint32_t *__restrict__ s_h,
+                               uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_lo, s_hi;
+    if (threadIdx.x == 0) {
+        s_lo = UINT32_MAX;
+        s_hi = 0;
+    }
+    for (int i = threadIdx.x; i < kLenBins; i += kBlock) s_h[i] = 0;
+    __syncthreads();
+    uint32_t lo = UINT32_MAX, hi = 0;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        if (rec[r] == kNoBin) continue;
+        lo = min(lo, rec[r] >> 10);
+        hi = max(hi, rec[r] >> 10);
+    }
+    if (lo != UINT32_MAX) {
+        atomicMin(&s_lo, lo);
+        atomicMax(&s_hi, hi);
+    }
+    __syncthreads();
+    const bool one = s_lo == s_hi;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        if (rec[r] == kNoBin) continue;
+        if (one) atomicAdd(&s_h[rec[r] & (kLenBins - 1)], 1u);
+        else atomicAdd(&hist[(size_t)(rec[r] >> 10) * kLenBins + (rec[r] & (kLenBins - 1))], 1u);
+    }
+    __syncthreads();
+    if (one)
+        for (int i = threadIdx.x; i < kLenBins; i += kBlock)
+            if (s_h[i]) atomicAdd(&hist[(size_t)s_lo * kLenBins + i], s_h[i]);
 }
 
 // The running union of a sweep's merged boxes: query start, end, bank start, end,
@@ -3664,16 +3748,14 @@ __device__ MAgg seg_excl_union(bool f, const MAgg &a)
 // test only gets easier as unions grow, and tentative segments are never larger
 // than the sweep's, so a dropped start is never a start of the sweep, and when a
 // round drops nothing every key's union is the sweep's and the starts are
-// exactly its.  Returns false (nothing written) when kMergeRounds rounds did not
+// exactly its.  Returns false (nothing written) when `rounds` rounds did not
 // settle; the caller then sweeps group by group.
-constexpr int kMergeRounds = 12;
-
 __device__ bool merge_sweep_parallel(const uint64_t *__restrict__ s_key, uint32_t m,
                                      const uint16_t *__restrict__ s_start, uint32_t o,
                                      uint32_t nw, uint16_t *__restrict__ s_pg,
                                      uint8_t *__restrict__ s_f8, int bl, int bd, int32_t bias,
                                      const Box *__restrict__ in, Box *__restrict__ out,
-                                     uint32_t at)
+                                     uint32_t at, int rounds, LenSel ls)
 {
     constexpr int kPer = kMergeSpan / kBlock;  // 8 keys per thread
     const uint64_t mbl = (1ull << bl) - 1ull, mbd = (1ull << bd) - 1ull;
@@ -3708,7 +3790,7 @@ __device__ bool merge_sweep_parallel(const uint64_t *__restrict__ s_key, uint32_
     }
     MAgg carry;
     for (int round = 0;; ++round) {
-        if (round == kMergeRounds) return false;
+        if (round == rounds) return false;
         bool sf = false;
         MAgg sa = magg_none();
 #pragma unroll
@@ -3761,13 +3843,18 @@ __device__ bool merge_sweep_parallel(const uint64_t *__restrict__ s_key, uint32_
         const uint32_t first = (uint32_t)s_start[g] - o;
         const uint32_t p0 = s_pg[g];
         const uint32_t nseg = (g + 1 < nw ? (uint32_t)s_pg[g + 1] - 1u : tot) - p0 + 1u;
-        if (j - first >= nseg) out[at + j].q = -1;
+        if (j - first >= nseg) {
+            out[at + j].q = -1;
+            if (ls.binq) ls.binq[at + j] = kNoBin;
+        }
         const bool last = j + 1 >= m || (r + 1 < kPer ? ((F >> (r + 1)) & 1u) != 0
                                                         : (s_f8[threadIdx.x + 1] & 1u) != 0);
         if (!last) continue;
         const uint32_t rank = before + __popc(F & ((2u << r) - 1u)) - p0;
         const int2 qsid = *reinterpret_cast<const int2 *>(in + at + j);
-        out[at + first + rank] = Box{qsid.x, qsid.y, run.qs, run.qe, run.ds, run.de, run.dmin, run.dmax};
+        const Box bx{qsid.x, qsid.y, run.qs, run.qe, run.ds, run.de, run.dmin, run.dmax};
+        out[at + first + rank] = bx;
+        if (ls.binq) ls.binq[at + first + rank] = len_record(bx, ls.shift);
     }
     return true;
 }
@@ -3775,7 +3862,8 @@ __device__ bool merge_sweep_parallel(const uint64_t *__restrict__ s_key, uint32_
 __global__ __launch_bounds__(kBlock, 6) void k_merge_tiles(const Box *__restrict__ in, uint32_t n,
                                                         int bl, int bd, int32_t bias,
                                                         Box *__restrict__ out,
-                                                        uint32_t *__restrict__ big, uint32_t big_cap)
+                                                        uint32_t *__restrict__ big, uint32_t big_cap,
+                                                        int rounds, LenSel ls)
 {
     __shared__ uint64_t s_key[kMergeSpan];
     __shared__ uint16_t s_start[kMergeSpan + 1];
@@ -3885,12 +3973,16 @@ __global__ __launch_bounds__(kBlock, 6) void k_merge_tiles(const Box *__restrict
         atomicOr(reinterpret_cast<unsigned long long *>(&s_vary[1]), (unsigned long long)zeros);
     }
     __syncthreads();
-    lds_radix_sort(s_key, m, s_vary[0] & s_vary[1]);
+    // sorted by (rank, qs, d) in passes over the bits above qe; keys equal there
+    // (one start on one diagonal) are then put in qe order, or, when there are
+    // too many of them, the keys are sorted again over every bit
+    lds_radix_sort(s_key, m, s_vary[0] & s_vary[1], bl);
+    if (!lds_order_ties(s_key, m, bl, kTieRounds)) lds_radix_sort(s_key, m, s_vary[0] & s_vary[1], 0);
     // the key-building ranks are no longer needed: their space holds the
     // parallel sweep's per-group counts
     if (merge_sweep_parallel(s_key, m, s_start, o, nw, s_rank,
                              reinterpret_cast<uint8_t *>(s_rank + kMergeWin), bl, bd, bias, in, out,
-                             base + o))
+                             base + o, rounds, ls))
         return;
     // sweep each owned group from its keys
     for (uint32_t g = threadIdx.x; g < nw; g += kBlock) {
@@ -3901,6 +3993,11 @@ __global__ __launch_bounds__(kBlock, 6) void k_merge_tiles(const Box *__restrict
             const int32_t d = (int32_t)((key >> bl) & mbd) - bias;
             const int32_t qs = (int32_t)((key >> (bl + bd)) & mbl);
             return Box{qsid.x, qsid.y, qs, qe, qs + d, qe + d, d, d};
+        };
+        // a merged box to its slot, with its length record
+        auto emit = [&](uint32_t slot, const Box &bx) {
+            out[base + o + slot] = bx;
+            if (ls.binq) ls.binq[base + o + slot] = len_record(bx, ls.shift);
         };
         Box cur = decode(s_key[j0]);
         uint32_t w = j0;
@@ -3922,13 +4019,16 @@ __global__ __launch_bounds__(kBlock, 6) void k_merge_tiles(const Box *__restrict
                     cur.dmin = min(cur.dmin, h.dmin);
                     cur.dmax = max(cur.dmax, h.dmax);
                 } else {
-                    out[base + o + w++] = cur;
+                    emit(w++, cur);
                     cur = h;
                 }
             }
         }
-        out[base + o + w++] = cur;
-        for (; w < j1; ++w) out[base + o + w].q = -1;
+        emit(w++, cur);
+        for (; w < j1; ++w) {
+            out[base + o + w].q = -1;
+            if (ls.binq) ls.binq[base + o + w] = kNoBin;
+        }
     }
 }
 
@@ -3948,12 +4048,12 @@ __global__ void k_copy_ranges(const Box *__restrict__ src, Box *__restrict__ dst
 }
 
 void launch_merge_tiles(const Box *in, uint32_t n, int bl, int bd, int32_t bias, Box *out,
-                        uint32_t *big, uint32_t big_cap, hipStream_t st)
+                        uint32_t *big, uint32_t big_cap, int rounds, LenSel ls, hipStream_t st)
 {
     if (n == 0) return;
     launch_fill_u32(big, 1, 0u, st);
     const uint32_t nb = (n + kMergeWin - 1) / kMergeWin;
-    k_merge_tiles<<<nb, kBlock, 0, st>>>(in, n, bl, bd, bias, out, big, big_cap);
+    k_merge_tiles<<<nb, kBlock, 0, st>>>(in, n, bl, bd, bias, out, big, big_cap, rounds, ls);
 }
 
 void launch_copy_ranges(const Box *src, Box *dst, const uint32_t *ranges, const uint32_t *offs,
@@ -3996,60 +4096,42 @@ __global__ void k_segments_box(const Box *__restrict__ s, uint32_t n, int32_t nq
 // at least N; every box in or above that bin is kept (a superset of the N longest,
 // ties included) and the full order is applied to those alone.  Boxes are in
 // query order; empty slots (q < 0) are dropped.
-__device__ __forceinline__ uint32_t len_bin(const Box &b, int shift)
+
+// Length records of n box slots: binq[i] for every slot.
+__global__ void k_len_records(const Box *__restrict__ b, uint32_t n, LenSel ls)
 {
-    return min((uint32_t)min(b.qe - b.qs, b.de - b.ds) >> shift, (uint32_t)(kLenBins - 1));
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int32_t q = b[i].q;
+        ls.binq[i] = q >= 0 ? len_record(b[i], ls.shift) : kNoBin;
+    }
 }
 
-// Tile of kTile boxes: counts into hist[q * kLenBins + bin]; a tile whose boxes
-// all belong to one query adds its LDS counts (one global atomic per bin in use),
-// a mixed tile counts every box in global memory.
-__global__ __launch_bounds__(kBlock) void k_len_hist(const Box *__restrict__ b, uint32_t n,
-                                                     int shift, uint32_t *__restrict__ hist)
+// The same for the slots of nr ranges [ranges[2r], ranges[2r + 1]) (a block per range).
+__global__ void k_len_records_ranges(const Box *__restrict__ b, const uint32_t *__restrict__ ranges,
+                                     uint32_t nr, LenSel ls)
 {
-    __shared__ uint32_t h[kLenBins];
-    __shared__ int32_t s_lo, s_hi;
-    const uint32_t base = blockIdx.x * (uint32_t)kTile;
-    if (threadIdx.x == 0) {
-        s_lo = INT32_MAX;
-        s_hi = -1;
-    }
-    for (int i = threadIdx.x; i < kLenBins; i += kBlock) h[i] = 0;
-    __syncthreads();
-    int32_t qv[kItems];
-    uint32_t bin[kItems];
-    int32_t lo = INT32_MAX, hi = -1;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const uint32_t i = base + r * kBlock + threadIdx.x;
-        qv[r] = -1;
-        bin[r] = 0;
-        if (i < n) {
-            const Box x = b[i];
-            qv[r] = x.q;
-            if (x.q >= 0) {
-                bin[r] = len_bin(x, shift);
-                lo = min(lo, x.q);
-                hi = max(hi, x.q);
-            }
+    for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
+        const uint32_t a = ranges[2 * r], e = ranges[2 * r + 1];
+        for (uint32_t i = a + threadIdx.x; i < e; i += blockDim.x) {
+            const int32_t q = b[i].q;
+            ls.binq[i] = q >= 0 ? len_record(b[i], ls.shift) : kNoBin;
         }
     }
-    if (hi >= 0) {
-        atomicMin(&s_lo, lo);
-        atomicMax(&s_hi, hi);
-    }
-    __syncthreads();
-    const bool one = s_lo == s_hi;
+}
+
+// Per-query length histograms from n slot records (tiles of kTile, thread t of a
+// tile reading records [8 t, 8 t + 8) of it): hist[q * kLenBins + bin].
+__global__ __launch_bounds__(kBlock) void k_len_hist(const uint32_t *__restrict__ binq, uint32_t n,
+                                                     uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[kLenBins];
+    const int64_t i0 = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t rec[kItems];
+    load_items<uint32_t>(binq, i0, n, rec);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        if (qv[r] < 0) continue;
-        if (one) atomicAdd(&h[bin[r]], 1u);
-        else atomicAdd(&hist[(size_t)qv[r] * kLenBins + bin[r]], 1u);
-    }
-    __syncthreads();
-    if (one)
-        for (int i = threadIdx.x; i < kLenBins; i += kBlock)
-            if (h[i]) atomicAdd(&hist[(size_t)s_lo * kLenBins + i], h[i]);
+    for (int r = 0; r < kItems; ++r)
+        if (i0 + r >= (int64_t)n) rec[r] = kNoBin;
+    len_hist_block<kItems>(rec, h, hist);
 }
 
 // One block per query: its box count (all bins) and the highest bin whose boxes
@@ -4088,59 +4170,73 @@ __global__ __launch_bounds__(kBlock) void k_len_threshold(const uint32_t *__rest
 }
 
 // Stable compaction of the kept boxes, in two passes over tiles (count; write at
-// the scanned tile offsets), so the kept boxes stay in query order.
-__global__ __launch_bounds__(kBlock) void k_len_keep(const Box *__restrict__ b, uint32_t n,
-                                                     int shift, const uint32_t *__restrict__ thr,
+// the scanned tile offsets), so the kept boxes stay in query order.  Both passes
+// decide from the slots' length records; only the write pass reads the boxes it
+// keeps.
+__global__ __launch_bounds__(kBlock) void k_len_keep(const Box *__restrict__ b,
+                                                     const uint32_t *__restrict__ binq, uint32_t n,
+                                                     const uint32_t *__restrict__ thr,
                                                      const uint32_t *__restrict__ tile_off,
                                                      uint32_t *__restrict__ counts,
                                                      Box *__restrict__ out)
 {
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
     uint32_t at = tile_off ? tile_off[blockIdx.x] : 0u, c = 0;
+    uint32_t rec[kItems];
+    load_items<uint32_t>(binq, (int64_t)base + (int64_t)threadIdx.x * kItems, n, rec);
+    // thread t holds slots base + t kItems .. + kItems - 1
+    bool keep[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const uint32_t i = base + r * kBlock + threadIdx.x;
-        Box x{};
-        bool keep = false;
-        if (i < n) {
-            x = b[i];
-            keep = x.q >= 0 && len_bin(x, shift) >= thr[x.q];
-        }
-        if (tile_off) {
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan<uint32_t>(keep ? 1u : 0u, &tot);
-            if (keep) out[at + ex] = x;
-            at += tot;
-        } else {
-            c += keep ? 1u : 0u;
-        }
+        const uint32_t i = base + threadIdx.x * kItems + r;
+        keep[r] = i < n && rec[r] != kNoBin && (rec[r] & (kLenBins - 1)) >= thr[rec[r] >> 10];
+        c += keep[r] ? 1u : 0u;
     }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t>(c, &tot);
     if (!tile_off) {
-        uint32_t tot;
-        block_excl_scan<uint32_t>(c, &tot);
         if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+        return;
     }
+    at += ex;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+        if (keep[r]) out[at++] = b[base + threadIdx.x * kItems + r];
 }
 
-void launch_len_prefilter(const Box *b, uint32_t n, int32_t nq, int32_t N, int shift,
-                          uint32_t *hist, uint32_t *thr, uint32_t *nvalid, uint32_t *tile_counts,
-                          uint32_t *partials, hipStream_t st)
+void launch_len_records(const Box *b, uint32_t n, LenSel ls, hipStream_t st)
+{
+    if (n == 0) return;
+    k_len_records<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(b, n,
+                                                                                          ls);
+}
+
+void launch_len_records_ranges(const Box *b, const uint32_t *ranges, uint32_t nr, LenSel ls,
+                               hipStream_t st)
+{
+    if (nr == 0) return;
+    k_len_records_ranges<<<std::min<uint32_t>(nr, 65536), kBlock, 0, st>>>(b, ranges, nr, ls);
+}
+
+void launch_len_prefilter(const uint32_t *binq, uint32_t n, int32_t nq, int32_t N,
+                          uint32_t *hist, uint32_t *thr, uint32_t *nvalid,
+                          uint32_t *tile_counts, uint32_t *partials, hipStream_t st)
 {
     if (n == 0 || nq <= 0) return;
     const uint32_t tiles = (n + kTile - 1) / kTile;
     launch_fill_u32(hist, (size_t)nq * kLenBins, 0u, st);
-    k_len_hist<<<tiles, kBlock, 0, st>>>(b, n, shift, hist);
+    k_len_hist<<<tiles, kBlock, 0, st>>>(binq, n, hist);
     k_len_threshold<<<std::min<uint32_t>((uint32_t)nq, kMaxGrid), kBlock, 0, st>>>(hist, nq, N, thr,
                                                                                    nvalid);
-    k_len_keep<<<tiles, kBlock, 0, st>>>(b, n, shift, thr, nullptr, tile_counts, nullptr);
+    k_len_keep<<<tiles, kBlock, 0, st>>>(nullptr, binq, n, thr, nullptr, tile_counts, nullptr);
     launch_scan_u32(tile_counts, tile_counts, tiles, partials, st);  // kept total at [tiles]
 }
 
-void launch_len_compact(const Box *b, uint32_t n, int shift, const uint32_t *thr,
+void launch_len_compact(const Box *b, const uint32_t *binq, uint32_t n, const uint32_t *thr,
                         const uint32_t *tile_off, Box *out, hipStream_t st)
 {
     if (n == 0) return;
-    k_len_keep<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(b, n, shift, thr, tile_off, nullptr, out);
+    k_len_keep<<<(n + kTile - 1) / kTile, kBlock, 0, st>>>(b, binq, n, thr, tile_off, nullptr, out);
 }
 
 void launch_segments_box(const Box *sorted, uint32_t n, int32_t nq, uint32_t *qstart,

@@ -108,7 +108,7 @@ struct Workspace {
         btmp_b, bounds, blist, pcnt, cells_box, rbounds, rbelow, os_scratch, xqueue, gout, gn,
         gctl, gplan, gcursor, gqflag, stiles, gtiles;
     DevBuf tb_hits, tb_q, tb_dir, tb_dir_off, tb_ops_off, tb_ops, tb_len, tb_status;  // traceback
-    DevBuf lhist, lthr, lvalid, ltile;  // selection prefilter
+    DevBuf lhist, lthr, lvalid, ltile, lbinq;  // selection prefilter
     DevBuf fkept, fkoff, fflag, ford;   // lone-diagonal filter (ford: largest query first)
     DevBuf tpos;                        // the position where each gather tile starts
     DevBuf mbig, mranges;               // merge groups that may outgrow an LDS window
@@ -145,7 +145,7 @@ struct Workspace {
                          &rbounds, &rbelow, &os_scratch, &xqueue, &gout, &gn, &gctl, &gplan,
                          &gcursor, &gqflag, &stiles, &gtiles, &tb_hits, &tb_q, &tb_dir,
                          &tb_dir_off, &tb_ops_off, &tb_ops, &tb_len, &tb_status, &lhist, &lthr,
-                         &lvalid, &ltile, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox, &bq,
+                         &lvalid, &ltile, &lbinq, &fkept, &fkoff, &fflag, &ford, &tpos, &selbox, &bq,
                          &mbig, &mranges, &bsw_order};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
@@ -444,12 +444,19 @@ void filter_order(const uint64_t *qtot, int32_t nqw, int32_t *order)
 }
 
 // The merge of large waves orders and sweeps each (query, sequence) group in LDS
-// windows (k_merge_tiles); GG_MERGE=global sends every box through the global
-// record sort instead.
+// windows (k_merge_tiles), whose sweep runs in parallel over a window's boxes;
+// GG_MERGE=serial sweeps each group in one thread instead, and GG_MERGE=global
+// sends every box through the global record sort.
 bool merge_windows_enabled()
 {
     const char *e = std::getenv("GG_MERGE");
     return !(e && std::strcmp(e, "global") == 0);
+}
+
+int merge_sweep_rounds()
+{
+    const char *e = std::getenv("GG_MERGE");
+    return e && std::strcmp(e, "serial") == 0 ? 0 : kMergeRounds;
 }
 
 // The filter runs after the gather (k_gather writes every key, k_hit_filter reads
@@ -951,6 +958,14 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         launch_merge_sweep(tmp, n, dst, st);
         return GG_OK;
     };
+    // the selection prefilter's length records (one per box slot, the query in
+    // 22 bits), written where the boxes are merged; the per-query segment path
+    // selects in LDS and needs none
+    LenSel ls;
+    if (!seg_path && p->max_hits > 0 && nc > 0 && nqw < (1 << 22)) {
+        TRY(ensure(ws->lbinq, sizeof(uint32_t) * (size_t)nc));
+        ls = LenSel{as<uint32_t>(ws->lbinq), std::max(0, bits_for((uint64_t)maxL + 1) - 10)};
+    }
     if (seg_path) {
         launch_seg_sort_box(0, boxes, as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nqw, st);
         prof.end(nc);
@@ -962,13 +977,14 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
         constexpr uint32_t kBigCap = 1u << 16;
         TRY(ensure(ws->mbig, sizeof(uint32_t) * (1 + 2 * (size_t)kBigCap)));
         launch_merge_tiles(boxes, nc, bl, bdm, (int32_t)maxL, as<Box>(ws->boxes3),
-                           as<uint32_t>(ws->mbig), kBigCap, st);
+                           as<uint32_t>(ws->mbig), kBigCap, merge_sweep_rounds(), ls, st);
         uint32_t nbig = 0;
         HIPCHK(hipMemcpyAsync(h_nc, ws->mbig.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         SYNC(st);
         nbig = h_nc[0];
         if (nbig > kBigCap) {
             TRY(global_merge(boxes, nc, as<Box>(ws->boxes2), as<Box>(ws->boxes3)));
+            if (ls.binq) launch_len_records(as<Box>(ws->boxes3), nc, ls, st);  // all anew
         } else if (nbig > 0) {
             std::vector<uint32_t> ranges(2 * (size_t)nbig), offs((size_t)nbig + 1, 0);
             HIPCHK(hipMemcpyAsync(ranges.data(), as<uint32_t>(ws->mbig) + 1,
@@ -998,11 +1014,13 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             TRY(global_merge(as<Box>(ws->boxes2), B, boxes, as<Box>(ws->boxes2) + 0));
             launch_copy_ranges(as<Box>(ws->boxes2), as<Box>(ws->boxes3), d_ranges, d_offs, nbig,
                                false, st);
+            if (ls.binq) launch_len_records_ranges(as<Box>(ws->boxes3), d_ranges, nbig, ls, st);
             SYNC(st);  // the host vectors above go out of scope
         }
         prof.end(nc);
     } else {
         TRY(global_merge(boxes, nc, as<Box>(ws->boxes2), as<Box>(ws->boxes3)));
+        if (ls.binq) launch_len_records(as<Box>(ws->boxes3), nc, ls, st);
         prof.end(nc);
     }
 
@@ -1014,20 +1032,20 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     if (seg_path) {
         launch_seg_sort_box(1, merged, as<Box>(ws->boxes2), as<uint32_t>(ws->cand_off), nqw, st);
     } else {
-        if (p->max_hits > 0) {
+        if (ls.binq) {
             // only boxes at least as long as a query's N-th longest can be selected
-            const int shift = std::max(0, bits_for((uint64_t)maxL + 1) - 10);
             const uint32_t tiles = (nc + kTile - 1) / kTile;
             TRY(ensure(ws->lhist, sizeof(uint32_t) * (size_t)nqw * kLenBins));
             TRY(ensure(ws->lthr, sizeof(uint32_t) * nqw));
             TRY(ensure(ws->lvalid, sizeof(uint32_t) * nqw));
             TRY(ensure(ws->ltile, sizeof(uint32_t) * (tiles + 1)));
             TRY(ensure(ws->partials, sizeof(uint64_t) * scan_partials_needed(tiles + 1)));
-            launch_len_prefilter(merged, nc, nqw, p->max_hits, shift, as<uint32_t>(ws->lhist),
-                                 as<uint32_t>(ws->lthr), as<uint32_t>(ws->lvalid),
-                                 as<uint32_t>(ws->ltile), as<uint32_t>(ws->partials), st);
-            launch_len_compact(merged, nc, shift, as<uint32_t>(ws->lthr), as<uint32_t>(ws->ltile),
-                               as<Box>(ws->boxes), st);
+            launch_len_prefilter(ls.binq, nc, nqw, p->max_hits, as<uint32_t>(ws->lhist),
+                                 as<uint32_t>(ws->lthr),
+                                 as<uint32_t>(ws->lvalid), as<uint32_t>(ws->ltile),
+                                 as<uint32_t>(ws->partials), st);
+            launch_len_compact(merged, ls.binq, nc, as<uint32_t>(ws->lthr),
+                               as<uint32_t>(ws->ltile), as<Box>(ws->boxes), st);
             nvalid_h.resize((size_t)nqw);
             HIPCHK(hipMemcpyAsync(&nbox, as<uint32_t>(ws->ltile) + tiles, sizeof(uint32_t),
                                   hipMemcpyDeviceToHost, st));

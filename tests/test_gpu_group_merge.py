@@ -5,7 +5,10 @@ bit-exact against the oracle.
 Tandem repeats of one short unit, two tracts to a bank sequence, and one tract
 in a query give each (query, sequence) pair as many runs as the tracts allow, in
 two or more merged boxes: groups of up to 256 runs (sorted and swept by one wave
-each), up to 1,024 (one block each) and beyond (the global record sort).  Every grouping strategy is run: the
+each), up to 1,024 (one block each) and beyond (the global record sort).  The
+windowed merge of the sort grouping is also run with its sweep one thread per
+group (GG_MERGE=serial) and with every box through the global sort
+(GG_MERGE=global).  Every grouping strategy is run: the
 sort and bucket groupings emit runs in (query, sequence) order, and any order that
 is not falls back to the global sort.  Both the host-driven batch (with per-query
 counts) and the graph-replayed one (whose waves overflow the LDS sorts and run
@@ -90,3 +93,22 @@ def test_merge_groups_of_every_size(ggo, bank, monkeypatch, grouping, N):
         assert rc == 0, G.STATUS[rc]
         for i in range(qs.n):
             assert as_rows(got[i]) == as_rows(want[i]), f"query {i}"
+
+
+@pytest.mark.parametrize("merge", ["serial", "global"])
+@pytest.mark.parametrize("N", [20, 0])
+def test_merge_sweep_forms(ggo, bank, monkeypatch, merge, N):
+    G = gpu()
+    seqs, off, qs, oix = bank
+    monkeypatch.setenv("GG_GROUPING", "sort")
+    monkeypatch.setenv("GG_MERGE", merge)
+    monkeypatch.delenv("GG_GRAPH", raising=False)
+    gix = G.Index(seqs, off, 11)
+    prm = G.params(N)
+    rc, got, n, st = gix.search_batch(qs.buf, qs.off, prm, cap=100000, stats=True)
+    assert rc == 0, G.STATUS[rc]
+    for i in range(qs.n):
+        rc, h, _, wst = oix.search(qs.query(i), ggo.params(N), cap=100000)
+        assert rc == 0
+        assert int(st[i]["n_merged"]) == wst["n_merged"], (i, merge)
+        assert as_rows(got[i]) == as_rows(h), f"query {i}, GG_MERGE={merge}"
