@@ -2905,7 +2905,9 @@ __device__ __forceinline__ uint32_t xdrop_xw(const uint32_t *__restrict__ qpack,
 // running sum's maximum over it is at its end) and then that mismatch, whose drop
 // is tested; past the chunk's last mismatch the stretch runs to the chunk's end.
 // Returns true when the walk ended (drop over X, or T steps); otherwise t has
-// moved 16 steps on.
+// moved 16 steps on.  SMALL: match < 2^24, so a stretch's gain (at most 16
+// matches) takes a 24-bit multiply.
+template <bool SMALL>
 __device__ __forceinline__ bool xdrop_chunk(uint32_t x, int32_t T, int32_t match,
                                             int32_t mismatch, int32_t X, int32_t &t, int32_t &run,
                                             int32_t &best, int32_t &bl)
@@ -2913,18 +2915,19 @@ __device__ __forceinline__ bool xdrop_chunk(uint32_t x, int32_t T, int32_t match
     const int32_t nstep = min(16, T - t);
     uint32_t mm = (x | (x >> 1)) & 0x55555555u;  // one flag bit per step
     if (nstep < 16) mm &= (1u << (2 * nstep)) - 1u;
-    int32_t pos = 0, nx;
+    int32_t pos = 0, nx, blx = -1;  // blx: the chunk's step at a new best, if any
     bool drop;
     do {
         nx = mm ? (int32_t)(__builtin_ctz(mm) >> 1) : nstep;  // the next mismatch
-        run += (nx - pos) * match;
-        bl = run > best ? t + nx : bl;  // first step at a new best
+        run += SMALL ? (int32_t)__umul24((uint32_t)(nx - pos), (uint32_t)match) : (nx - pos) * match;
+        blx = run > best ? nx : blx;  // first step at a new best
         best = max(best, run);
         run -= mismatch;  // undone below when the chunk had no mismatch left
         drop = best - run > X;
         mm &= mm - 1u;
         pos = nx + 1;
     } while (nx < nstep && !drop);
+    if (blx >= 0) bl = t + blx;
     if (nx >= nstep) {
         run += mismatch;
         t += nstep;
@@ -3014,7 +3017,9 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Cand *__restrict__ cand
                 park = true;  // past the lane's cap: to the queue for a whole wave
             } else {
                 const uint32_t x = xok ? xn : xdrop_xw(qpack, gq, dbw, gb, t, left);
-                done = xdrop_chunk(x, T, match, mismatch, X, t, run, best, bl);
+                done = match < (1 << 24)
+                           ? xdrop_chunk<true>(x, T, match, mismatch, X, t, run, best, bl)
+                           : xdrop_chunk<false>(x, T, match, mismatch, X, t, run, best, bl);
             }
         }
         xok = false;
