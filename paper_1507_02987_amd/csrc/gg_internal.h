@@ -311,7 +311,8 @@ void launch_chain_count(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int3
 void launch_chain_write(const uint64_t *keys, uint32_t n, HitKeyLayout lay, int32_t k,
                         int32_t max_gap, int32_t min_len, const uint32_t *tile_off, Cand *out,
                         hipStream_t st);
-void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t *qend,
+// Each query's range of runs [qstart[q], qend[q]) in n runs in query order, q < nq.
+void launch_cand_segments(const Cand *c, uint32_t n, int32_t nq, uint32_t *qstart, uint32_t *qend,
                           hipStream_t st);
 // Per-query LDS sorts (segments of at most kSegCap records; longer ones are skipped).
 // mode 0: merge order, mode 1: selection order.

@@ -2664,22 +2664,33 @@ void launch_chain_ctl(const uint64_t *keys, uint32_t hits_cap, int32_t k, int32_
 
 // Runs come out in (q, s, diag) order: each query's runs are one range
 // [qstart, qend), found at its boundaries (no per-run counter, no atomics).
-__global__ void k_cand_segments(const Cand *__restrict__ c, uint32_t n,
+// Query q's runs are [qstart[q], qend[q]): the first run of a query >= q and of a
+// query >= q + 1, by binary search over the runs' query fields (one thread per
+// query; a query without runs gets an empty range).
+__global__ void k_cand_segments(const Cand *__restrict__ c, uint32_t n, int32_t nq,
                                 uint32_t *__restrict__ qstart, uint32_t *__restrict__ qend)
 {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int32_t q = c[i].q;
-        if (i == 0 || c[i - 1].q != q) qstart[q] = i;
-        if (i + 1 == n || c[i + 1].q != q) qend[q] = i + 1;
-    }
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    auto first_at_least = [&](int32_t v) {
+        uint32_t a = 0, b = n;
+        while (a < b) {
+            const uint32_t mid = a + ((b - a) >> 1);
+            if (c[mid].q < v) a = mid + 1;
+            else b = mid;
+        }
+        return a;
+    };
+    qstart[q] = first_at_least(q);
+    qend[q] = first_at_least(q + 1);
 }
 
-void launch_cand_segments(const Cand *c, uint32_t n, uint32_t *qstart, uint32_t *qend,
+void launch_cand_segments(const Cand *c, uint32_t n, int32_t nq, uint32_t *qstart, uint32_t *qend,
                           hipStream_t st)
 {
-    if (n)
-        k_cand_segments<<<std::min<uint32_t>((n + kBlock - 1) / kBlock, kMaxGrid), kBlock, 0, st>>>(
-            c, n, qstart, qend);
+    if (nq > 0)
+        k_cand_segments<<<(uint32_t)((nq + kBlock - 1) / kBlock), kBlock, 0, st>>>(c, n, nq, qstart,
+                                                                                qend);
 }
 
 uint32_t chain_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
@@ -3637,45 +3648,6 @@ __device__ __forceinline__ uint32_t len_record(const Box &b, int shift)
 
 static_assert(kLenBins == 1024, "length records keep the bin in 10 bits");
 
-// Adds a block's length records (up to kPer per thread, kNoBin for none) to the
-// per-query histograms: in LDS (s_h, kLenBins words) and one global atomic per
-// bin in use when they all belong to one query, else one global atomic each.
-template <int kPer>
-__device__ __forceinline__ void len_hist_block(const uint32_t (&rec)[kPer], uint32_t *__restrict__ s_h,
-                               uint32_t *__restrict__ hist)
-{
-    __shared__ uint32_t s_lo, s_hi;
-    if (threadIdx.x == 0) {
-        s_lo = UINT32_MAX;
-        s_hi = 0;
-    }
-    for (int i = threadIdx.x; i < kLenBins; i += kBlock) s_h[i] = 0;
-    __syncthreads();
-    uint32_t lo = UINT32_MAX, hi = 0;
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        if (rec[r] == kNoBin) continue;
-        lo = min(lo, rec[r] >> 10);
-        hi = max(hi, rec[r] >> 10);
-    }
-    if (lo != UINT32_MAX) {
-        atomicMin(&s_lo, lo);
-        atomicMax(&s_hi, hi);
-    }
-    __syncthreads();
-    const bool one = s_lo == s_hi;
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        if (rec[r] == kNoBin) continue;
-        if (one) atomicAdd(&s_h[rec[r] & (kLenBins - 1)], 1u);
-        else atomicAdd(&hist[(size_t)(rec[r] >> 10) * kLenBins + (rec[r] & (kLenBins - 1))], 1u);
-    }
-    __syncthreads();
-    if (one)
-        for (int i = threadIdx.x; i < kLenBins; i += kBlock)
-            if (s_h[i]) atomicAdd(&hist[(size_t)s_lo * kLenBins + i], s_h[i]);
-}
-
 // The running union of a sweep's merged boxes: query start, end, bank start, end,
 // extreme diagonals.
 struct MAgg {
@@ -3883,21 +3855,19 @@ __global__ __launch_bounds__(kBlock, 6) void k_merge_tiles(const Box *__restrict
     const uint32_t R = lim - base;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
-    // group starts in [base, lim), in order, and each position's group rank
-    uint32_t ns = 0;
+    // group starts in [base, lim), in order, and each position's group rank; past
+    // the window's first kMergeWin positions only up to the first start found (it
+    // ends the last owned group)
+    uint32_t ns = 0, nwin = 0;
     for (uint32_t u = 0; u < kMergeSpan / kBlock; ++u) {
         const uint32_t r = u * kBlock + threadIdx.x;
-        bool f = false;
-        if (r < R) {
-            const uint32_t p = base + r;
-            if (p == 0) {
-                f = true;
-            } else {
-                const int2 a = *reinterpret_cast<const int2 *>(in + p);
-                const int2 b = *reinterpret_cast<const int2 *>(in + p - 1);
-                f = a.x != b.x || a.y != b.y;
-            }
-        }
+        const uint32_t p = base + r;
+        int2 a = make_int2(-1, -1);
+        if (r < R) a = *reinterpret_cast<const int2 *>(in + p);
+        // the position before: the lane below holds it; lane 0 reads it
+        int2 b = make_int2(__shfl_up(a.x, 1, 64), __shfl_up(a.y, 1, 64));
+        if (lane == 0 && r < R && p > 0) b = *reinterpret_cast<const int2 *>(in + p - 1);
+        const bool f = r < R && (p == 0 || a.x != b.x || a.y != b.y);
         const uint64_t m = __ballot(f);
         if (lane == 0) s_wc[wv] = (uint32_t)__popcll(m);
         __syncthreads();
@@ -3913,7 +3883,9 @@ __global__ __launch_bounds__(kBlock, 6) void k_merge_tiles(const Box *__restrict
         // start belong to an earlier block's group and are never used)
         if (r < R) s_rank[r] = (uint16_t)(at + (f ? 1u : 0u) - 1u);
         ns += round;
+        if (u < kMergeWin / kBlock) nwin = ns;  // starts below kMergeWin
         __syncthreads();
+        if (u + 1 >= kMergeWin / kBlock && ns > nwin) break;
     }
     if (threadIdx.x == 0) {
         s_start[ns] = (uint16_t)R;
@@ -4124,19 +4096,53 @@ __global__ void k_len_records_ranges(const Box *__restrict__ b, const uint32_t *
     }
 }
 
-// Per-query length histograms from n slot records (tiles of kTile, thread t of a
-// tile reading records [8 t, 8 t + 8) of it): hist[q * kLenBins + bin].
+// Per-query length histograms from n slot records: hist[q * kLenBins + bin].  A
+// block counts kLenHistTiles tiles of kTile records (thread t reading records
+// [8 t, 8 t + 8) of each), so that the blocks of one query add their LDS counts to
+// the query's kLenBins counters less often.  Records are in query order: those of
+// the block's first query are counted in LDS, any others in global memory.
+constexpr int kLenHistTiles = 8;
+
 __global__ __launch_bounds__(kBlock) void k_len_hist(const uint32_t *__restrict__ binq, uint32_t n,
                                                      uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[kLenBins];
-    const int64_t i0 = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
-    uint32_t rec[kItems];
-    load_items<uint32_t>(binq, i0, n, rec);
+    __shared__ uint32_t s_q0;
+    if (threadIdx.x == 0) s_q0 = UINT32_MAX;
+    for (int i = threadIdx.x; i < kLenBins; i += kBlock) h[i] = 0;
+    const int64_t b0 = (int64_t)blockIdx.x * kLenHistTiles * kTile;
+    // the block's first query: the smallest query of its records
+    uint32_t q0 = UINT32_MAX;
+#pragma unroll 2
+    for (int t = 0; t < kLenHistTiles; ++t) {
+        uint32_t v[kItems];
+        const int64_t i0 = b0 + (int64_t)t * kTile + (int64_t)threadIdx.x * kItems;
+        load_items<uint32_t>(binq, i0, n, v);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r)
-        if (i0 + r >= (int64_t)n) rec[r] = kNoBin;
-    len_hist_block<kItems>(rec, h, hist);
+        for (int r = 0; r < kItems; ++r)
+            if (i0 + r < (int64_t)n && v[r] != kNoBin) q0 = min(q0, v[r] >> 10);
+    }
+    __syncthreads();
+    if (q0 != UINT32_MAX) atomicMin(&s_q0, q0);
+    __syncthreads();
+    q0 = s_q0;
+#pragma unroll 2
+    for (int t = 0; t < kLenHistTiles; ++t) {
+        uint32_t v[kItems];
+        const int64_t i0 = b0 + (int64_t)t * kTile + (int64_t)threadIdx.x * kItems;
+        load_items<uint32_t>(binq, i0, n, v);
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            if (i0 + r >= (int64_t)n || v[r] == kNoBin) continue;
+            const uint32_t bin = v[r] & (kLenBins - 1);
+            if ((v[r] >> 10) == q0) atomicAdd(&h[bin], 1u);
+            else atomicAdd(&hist[(size_t)(v[r] >> 10) * kLenBins + bin], 1u);
+        }
+    }
+    __syncthreads();
+    if (q0 != UINT32_MAX)
+        for (int i = threadIdx.x; i < kLenBins; i += kBlock)
+            if (h[i]) atomicAdd(&hist[(size_t)q0 * kLenBins + i], h[i]);
 }
 
 // One block per query: its box count (all bins) and the highest bin whose boxes
@@ -4230,7 +4236,7 @@ void launch_len_prefilter(const uint32_t *binq, uint32_t n, int32_t nq, int32_t 
     if (n == 0 || nq <= 0) return;
     const uint32_t tiles = (n + kTile - 1) / kTile;
     launch_fill_u32(hist, (size_t)nq * kLenBins, 0u, st);
-    k_len_hist<<<tiles, kBlock, 0, st>>>(binq, n, hist);
+    k_len_hist<<<(tiles + kLenHistTiles - 1) / kLenHistTiles, kBlock, 0, st>>>(binq, n, hist);
     k_len_threshold<<<std::min<uint32_t>((uint32_t)nq, kMaxGrid), kBlock, 0, st>>>(hist, nq, N, thr,
                                                                                    nvalid);
     k_len_keep<<<tiles, kBlock, 0, st>>>(nullptr, binq, n, thr, nullptr, tile_counts, nullptr);

@@ -899,9 +899,7 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             prof.begin("chain_write");
             launch_chain_write(sorted, Hs, lay, ix->span, p->max_gap, p->min_hsp_len,
                                as<uint32_t>(ws->ccount), as<Cand>(ws->cands), st);
-            HIPCHK(hipMemsetAsync(ws->qstart.p, 0, sizeof(uint32_t) * nqw, st));
-            HIPCHK(hipMemsetAsync(ws->qend.p, 0, sizeof(uint32_t) * nqw, st));
-            launch_cand_segments(as<Cand>(ws->cands), nc, as<uint32_t>(ws->qstart),
+            launch_cand_segments(as<Cand>(ws->cands), nc, nqw, as<uint32_t>(ws->qstart),
                                  as<uint32_t>(ws->qend), st);
             launch_select_counts(as<uint32_t>(ws->qstart), as<uint32_t>(ws->qend), nqw, 0,
                                  as<uint32_t>(ws->cand_q), st);
