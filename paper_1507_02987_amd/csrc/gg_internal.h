@@ -345,6 +345,11 @@ void launch_gather_aligns(const Align *in, const uint32_t *perm, uint32_t n, Ali
 void launch_merge_select_seg(const Box *in, Box *out, const uint32_t *seg_off, int32_t nq_cap,
                              WaveCtl *ctl, hipStream_t st);
 void launch_merge_sweep(const Box *sorted, uint32_t n, Box *out, hipStream_t st);
+// The same sweep of ngroup whole groups, boxes [offs[g], offs[g + 1]) of sorted,
+// one block per group sweeping in parallel for at most `rounds` rounds per chunk
+// of boxes, else one thread (groups too big for a merge window).
+void launch_merge_groups(const Box *sorted, const uint32_t *offs, uint32_t ngroup, Box *out,
+                         int rounds, hipStream_t st);
 // Merge (order and sweep) of boxes grouped by (query, sequence), fresh from the
 // extension, in windows of whole groups held in LDS; keys (group rank | qs |
 // d + bias | qe) take 12 + 2 bl + bd <= 64 bits.  Groups that may outgrow a

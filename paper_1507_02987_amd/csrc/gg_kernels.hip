@@ -3682,7 +3682,7 @@ __device__ __forceinline__ MAgg magg_shfl_up(const MAgg &a, int o)
 // receives the union over the items before its own back to the last start (the
 // union of the segment its first item continues).  Pairs combine as (f1, a1) then
 // (f2, a2) -> (f1 | f2, f2 ? a2 : a1 + a2).
-__device__ MAgg seg_excl_union(bool f, const MAgg &a)
+__device__ MAgg seg_excl_union(bool f, const MAgg &a, bool *start_before = nullptr)
 {
     __shared__ int32_t s_wf[kBlock / 64];
     __shared__ MAgg s_wa[kBlock / 64];
@@ -3710,8 +3710,13 @@ __device__ MAgg seg_excl_union(bool f, const MAgg &a)
     }
     __syncthreads();
     MAgg pre = magg_none();
-    for (int i = 0; i < w; ++i) pre = s_wf[i] ? s_wa[i] : magg_join(pre, s_wa[i]);
+    int32_t pf = 0;
+    for (int i = 0; i < w; ++i) {
+        pre = s_wf[i] ? s_wa[i] : magg_join(pre, s_wa[i]);
+        pf |= s_wf[i];
+    }
     __syncthreads();  // s_wf and s_wa are rewritten by the next call
+    if (start_before) *start_before = (ef | pf) != 0;
     return ef ? ex : magg_join(pre, ex);
 }
 
@@ -4022,6 +4027,166 @@ __global__ void k_copy_ranges(const Box *__restrict__ src, Box *__restrict__ dst
             else dst[a + i] = src[o + i];
         }
     }
+}
+
+// The sweep of whole groups too big for a window, in parallel: block g takes
+// group g, boxes [offs[g], offs[g + 1]) of s (sorted in merge order), in chunks of
+// kMergeSpan boxes, eight per thread, as merge_sweep_parallel does a window.  The
+// union of the segment still open at a chunk's end is carried into the next
+// chunk, where it is the union before every box that no start in the chunk
+// precedes.  Merged boxes go to the group's first positions in out, the rest are
+// marked empty.  A chunk that has not settled in `rounds` rounds is swept by one
+// thread; the results are the same.
+__global__ __launch_bounds__(kBlock) void k_merge_groups(const Box *__restrict__ s,
+                                                         const uint32_t *__restrict__ offs,
+                                                         uint32_t ngroup, Box *__restrict__ out,
+                                                         int rounds)
+{
+    constexpr int kPer = kMergeSpan / kBlock;
+    __shared__ MAgg s_open;
+    __shared__ uint32_t s_nseg;
+    __shared__ uint8_t s_f8[kBlock + 1];
+    auto item = [&](uint32_t i) {
+        const Box b = s[i];
+        return MAgg{b.qs, b.qe, b.ds, b.de, b.dmin, b.dmax};
+    };
+    for (uint32_t g = blockIdx.x; g < ngroup; g += gridDim.x) {
+        const uint32_t a = offs[g], e = offs[g + 1];
+        const int2 qsid = *reinterpret_cast<const int2 *>(s + a);
+        MAgg open = magg_none();  // union of the segment open before the chunk
+        uint32_t nseg = 0;        // merged boxes that start before the chunk
+        for (uint32_t c0 = a; c0 < e; c0 += kMergeSpan) {
+            const uint32_t m = min((uint32_t)kMergeSpan, e - c0);
+            const uint32_t j0 = threadIdx.x * kPer;
+            uint32_t V = 0, F = 0;
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const uint32_t j = j0 + r;
+                if (j >= m) break;
+                V |= 1u << r;
+                const uint32_t i = c0 + j;
+                bool st = i == a;  // the group's first box
+                if (!st) {
+                    const MAgg p = item(i - 1), b = item(i);
+                    st = !magg_takes(p, b.qs, b.ds, b.de);
+                }
+                if (st) F |= 1u << r;
+            }
+            const uint32_t GS = (c0 == a && threadIdx.x == 0) ? 1u : 0u;
+            MAgg carry = magg_none();
+            bool settled = false;
+            for (int round = 0; round < rounds; ++round) {
+                bool sf = false;
+                MAgg sa = magg_none();
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    if (!((V >> r) & 1u)) continue;
+                    const MAgg b = item(c0 + j0 + r);
+                    if ((F >> r) & 1u) {
+                        sf = true;
+                        sa = b;
+                    } else {
+                        sa = magg_join(sa, b);
+                    }
+                }
+                bool before = false;
+                carry = seg_excl_union(sf, sa, &before);
+                if (!before) carry = magg_join(open, carry);
+                MAgg run = carry;
+                bool changed = false;
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    if (!((V >> r) & 1u)) continue;
+                    const uint32_t bit = 1u << r;
+                    const MAgg b = item(c0 + j0 + r);
+                    if ((F & bit) && !(GS & bit) && magg_takes(run, b.qs, b.ds, b.de)) {
+                        F &= ~bit;
+                        changed = true;
+                    }
+                    run = (F & bit) ? b : magg_join(run, b);
+                }
+                if (!__syncthreads_or(changed)) {
+                    settled = true;
+                    break;
+                }
+            }
+            if (!settled) {
+                // one thread sweeps the chunk from the open union
+                if (threadIdx.x == 0) {
+                    MAgg cur = open;
+                    uint32_t k = nseg;
+                    for (uint32_t j = 0; j < m; ++j) {
+                        const MAgg b = item(c0 + j);
+                        if (c0 + j == a) {
+                            cur = b;
+                            k = 1;
+                        } else if (magg_takes(cur, b.qs, b.ds, b.de)) {
+                            cur = magg_join(cur, b);
+                        } else {
+                            out[a + k - 1] = Box{qsid.x, qsid.y, cur.qs, cur.qe, cur.ds, cur.de,
+                                                 cur.dmin, cur.dmax};
+                            cur = b;
+                            ++k;
+                        }
+                    }
+                    if (c0 + m == e)
+                        out[a + k - 1] =
+                            Box{qsid.x, qsid.y, cur.qs, cur.qe, cur.ds, cur.de, cur.dmin, cur.dmax};
+                    s_open = cur;
+                    s_nseg = k;
+                }
+            } else {
+                // a segment ends at its last box in the chunk when the next box
+                // starts one, or at the group's end; merged box nseg - 1 + P(j), P(j)
+                // the chunk's starts up to box j.  The segment open at the chunk's
+                // end is carried, and written by the chunk that closes it.
+                uint32_t tot;
+                const uint32_t pre = block_excl_scan<uint32_t>((uint32_t)__popc(F), &tot);
+                s_f8[threadIdx.x] = (uint8_t)F;
+                if (threadIdx.x == 0) {
+                    s_f8[kBlock] = 0;
+                    // a start at the chunk's first box closes the segment carried in
+                    if (c0 > a && (F & 1u))
+                        out[a + nseg - 1u] = Box{qsid.x, qsid.y, open.qs, open.qe, open.ds, open.de,
+                                                 open.dmin, open.dmax};
+                }
+                __syncthreads();
+                MAgg run = carry;
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    if (!((V >> r) & 1u)) continue;
+                    const uint32_t j = j0 + r;
+                    run = ((F >> r) & 1u) ? item(c0 + j) : magg_join(run, item(c0 + j));
+                    const uint32_t k = nseg - 1u + pre + (uint32_t)__popc(F & ((2u << r) - 1u));
+                    if (j + 1 >= m) {
+                        if (c0 + m == e)
+                            out[a + k] = Box{qsid.x, qsid.y, run.qs, run.qe, run.ds, run.de,
+                                             run.dmin, run.dmax};
+                        s_open = run;
+                        s_nseg = k + 1u;
+                    } else if (r + 1 < kPer ? ((F >> (r + 1)) & 1u) != 0
+                                            : (s_f8[threadIdx.x + 1] & 1u) != 0) {
+                        out[a + k] = Box{qsid.x, qsid.y, run.qs, run.qe, run.ds, run.de, run.dmin,
+                                         run.dmax};
+                    }
+                }
+            }
+            __syncthreads();
+            open = s_open;
+            nseg = s_nseg;
+            __syncthreads();  // s_open, s_nseg and s_f8 are rewritten by the next chunk
+        }
+        for (uint32_t i = a + nseg + threadIdx.x; i < e; i += kBlock) out[i].q = -1;
+        __syncthreads();
+    }
+}
+
+void launch_merge_groups(const Box *sorted, const uint32_t *offs, uint32_t ngroup, Box *out,
+                         int rounds, hipStream_t st)
+{
+    if (ngroup == 0) return;
+    k_merge_groups<<<std::min<uint32_t>(ngroup, 65536), kBlock, 0, st>>>(sorted, offs, ngroup, out,
+                                                                         rounds);
 }
 
 void launch_merge_tiles(const Box *in, uint32_t n, int bl, int bd, int32_t bias, Box *out,

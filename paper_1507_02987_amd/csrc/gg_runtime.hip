@@ -942,8 +942,11 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
     // leave the runs; probing writes runs in no such order
     const bool windows = !seg_path && grouping == kSort && merge_windows_enabled() &&
                          12 + 2 * bl + bdm <= 64;
-    // global record sort of n boxes by merge order, then the sweep: src -> dst
-    auto global_merge = [&](Box *src, uint32_t n, Box *tmp, Box *dst) -> gg_status {
+    // global record sort of n boxes by merge order, then the sweep: src -> dst (with
+    // goffs, the boxes are ngroup whole groups starting at goffs[0 .. ngroup] on the
+    // device, each swept in parallel by a block)
+    auto global_merge = [&](Box *src, uint32_t n, Box *tmp, Box *dst,
+                            const uint32_t *goffs = nullptr, uint32_t ngroup = 0) -> gg_status {
         TRY(make_words({{F_Q, bq, 0}, {F_S, bs, 0}, {F_QS, bl, 0}, {F_DS, bsl, 0}, {F_QE, bl, 0},
                         {F_DE, bsl, 0}},
                        words));
@@ -953,7 +956,8 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
                          },
                          &perm));
         launch_gather_boxes(src, perm, n, tmp, st);
-        launch_merge_sweep(tmp, n, dst, st);
+        if (goffs) launch_merge_groups(tmp, goffs, ngroup, dst, merge_sweep_rounds(), st);
+        else launch_merge_sweep(tmp, n, dst, st);
         return GG_OK;
     };
     // the selection prefilter's length records (one per box slot, the query in
@@ -1004,12 +1008,12 @@ gg_status run_wave(const gg_index *ix, Workspace *ws, Prof &prof, const gg_param
             uint32_t *d_ranges = as<uint32_t>(ws->mranges), *d_offs = d_ranges + 2 * nbig;
             HIPCHK(hipMemcpyAsync(d_ranges, sr.data(), sizeof(uint32_t) * 2 * nbig,
                                   hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(d_offs, offs.data(), sizeof(uint32_t) * nbig,
+            HIPCHK(hipMemcpyAsync(d_offs, offs.data(), sizeof(uint32_t) * (nbig + 1),
                                   hipMemcpyHostToDevice, st));
             // pack the big groups (boxes2), sort and sweep them (via boxes, no longer
             // needed), and put them back in their places
             launch_copy_ranges(boxes, as<Box>(ws->boxes2), d_ranges, d_offs, nbig, true, st);
-            TRY(global_merge(as<Box>(ws->boxes2), B, boxes, as<Box>(ws->boxes2) + 0));
+            TRY(global_merge(as<Box>(ws->boxes2), B, boxes, as<Box>(ws->boxes2) + 0, d_offs, nbig));
             launch_copy_ranges(as<Box>(ws->boxes2), as<Box>(ws->boxes3), d_ranges, d_offs, nbig,
                                false, st);
             if (ls.binq) launch_len_records_ranges(as<Box>(ws->boxes3), d_ranges, nbig, ls, st);
