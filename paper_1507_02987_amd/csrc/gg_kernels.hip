@@ -2428,7 +2428,8 @@ __device__ __forceinline__ bool chains_to(uint64_t a, uint64_t b, int bp, int32_
     return (a >> bp) == (b >> bp) && (int32_t)(b & pmask) - ((int32_t)(a & pmask) + k) <= G;
 }
 
-// s_qs[l] = qpos of the first hit of the run that tile hit l belongs to.  Starts
+// qs[r] = qpos of the first hit of the run that tile hit l = r kBlock + t (thread
+// t's r-th item) belongs to, in the thread's registers.  Starts
 // inside the tile come from a running maximum of start positions over the tile's
 // 32 chunks of 64 hits (chunk 4 r + w is wave w's r-th row of the block's items,
 // so each wave scans its own rows and the chunks' maxima are combined once); the
@@ -2436,7 +2437,7 @@ __device__ __forceinline__ bool chains_to(uint64_t a, uint64_t b, int bp, int32_
 // at a time.
 __device__ void tile_run_starts(const uint64_t *__restrict__ s_k,
                                 const uint64_t *__restrict__ keys, uint32_t base, uint32_t cnt,
-                                int bp, int32_t k, int32_t G, int32_t *__restrict__ s_qs)
+                                int bp, int32_t k, int32_t G, int32_t (&qs)[kItems])
 {
     constexpr int kChunks = kItems * (kBlock / 64);
     __shared__ int32_t s_carry;
@@ -2487,9 +2488,10 @@ __device__ void tile_run_starts(const uint64_t *__restrict__ s_k,
     for (int r = 0; r < kItems; ++r) {
         const uint32_t l = r * kBlock + threadIdx.x;
         const int32_t before = __shfl(ex, r * (kBlock / 64) + w, 64);
+        qs[r] = 0;
         if (l < cnt) {
             const int32_t a = max(st[r], before);
-            s_qs[l] = a >= 0 ? (int32_t)(s_k[1 + a] & pmask) : s_carry;
+            qs[r] = a >= 0 ? (int32_t)(s_k[1 + a] & pmask) : s_carry;
         }
     }
     __syncthreads();
@@ -2497,15 +2499,12 @@ __device__ void tile_run_starts(const uint64_t *__restrict__ s_k,
 
 // Tile hit l ends a run when the next hit does not chain to it; the run [qs, qe =
 // qpos + k) is kept when qe - qs >= M.
-__device__ __forceinline__ bool chain_end_tile(const uint64_t *__restrict__ s_k,
-                                               const int32_t *__restrict__ s_qs, uint32_t n,
-                                               uint32_t base, uint32_t l, int bp, int32_t k,
-                                               int32_t G, int32_t M, int32_t *qs_out)
+__device__ __forceinline__ bool chain_end_tile(const uint64_t *__restrict__ s_k, int32_t qs,
+                                               uint32_t n, uint32_t base, uint32_t l, int bp,
+                                               int32_t k, int32_t G, int32_t M)
 {
     const uint64_t key = s_k[1 + l];
     if (base + l + 1 < n && chains_to(key, s_k[2 + l], bp, k, G)) return false;
-    const int32_t qs = s_qs[l];
-    *qs_out = qs;
     return (int32_t)(key & low_mask(bp)) + k - qs >= M;
 }
 
@@ -2537,20 +2536,19 @@ __global__ __launch_bounds__(kBlock) void k_chain_count(const uint64_t *__restri
                                                         const WaveCtl *__restrict__ ctl)
 {
     __shared__ uint64_t s_k[kTile + 2];
-    __shared__ int32_t s_qs[kTile];
     if (ctl) {  // tiles past the wave's hits count zero runs
         n = ctl->H;
         bp = ctl->lay.bp;
     }
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
     const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
-    tile_run_starts(s_k, keys, base, cnt, bp, k, G, s_qs);
+    int32_t qs[kItems];
+    tile_run_starts(s_k, keys, base, cnt, bp, k, G, qs);
     uint32_t c = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const uint32_t l = r * kBlock + threadIdx.x;
-        int32_t qs;
-        if (l < cnt && chain_end_tile(s_k, s_qs, n, base, l, bp, k, G, M, &qs)) ++c;
+        if (l < cnt && chain_end_tile(s_k, qs[r], n, base, l, bp, k, G, M)) ++c;
     }
     uint32_t tot;
     block_excl_scan<uint32_t>(c, &tot);
@@ -2575,9 +2573,9 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
     if (SELF && n == 0 && blockIdx.x == 0 && threadIdx.x == 0) ctl->nc = 0;
     if (ctl && base >= n) return;
     __shared__ uint64_t s_k[kTile + 2];
-    __shared__ int32_t s_qs[kTile];
     const uint32_t cnt = stage_chain_tile(keys, n, base, s_k);
-    tile_run_starts(s_k, keys, base, cnt, lay.bp, k, G, s_qs);
+    int32_t qsv[kItems];
+    tile_run_starts(s_k, keys, base, cnt, lay.bp, k, G, qsv);
     uint32_t at = SELF ? block_sum(tile_off, blockIdx.x) : tile_off[blockIdx.x];
     // runs in hit order: row r of wave w is chunk 4 r + w; one scan of the chunks'
     // run counts places every run
@@ -2586,12 +2584,10 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(const uint64_t *__restri
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
     uint64_t em[kItems];
-    int32_t qsv[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const uint32_t l = r * kBlock + threadIdx.x;
-        qsv[r] = 0;
-        const bool emit = l < cnt && chain_end_tile(s_k, s_qs, n, base, l, lay.bp, k, G, M, &qsv[r]);
+        const bool emit = l < cnt && chain_end_tile(s_k, qsv[r], n, base, l, lay.bp, k, G, M);
         em[r] = __ballot(emit);
         if (lane == 0) s_cc[r * (kBlock / 64) + w] = (uint32_t)__popcll(em[r]);
     }
