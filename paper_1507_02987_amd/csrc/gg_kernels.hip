@@ -1605,10 +1605,13 @@ __global__ __launch_bounds__(kBlock, (VALS || LB) ? 4 : 8) void k_rs_scatter(
         if (VALS) v[r] = ok ? vin[tv.base + idx] : 0u;
         const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
         uint64_t peers = __ballot(ok);
+        // lanes past the tile hold key 0 (digit 0), so they are clear in every
+        // bit's ballot, and peers never holds them
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
-            const uint64_t bb = __ballot(ok && ((d >> b) & 1u));
-            peers &= ((d >> b) & 1u) ? bb : ~bb;
+            const int32_t mk = (int32_t)(d << (31 - b)) >> 31;  // all ones when bit b is set
+            const uint64_t bb = __ballot(mk != 0);
+            peers &= ~(bb ^ (((uint64_t)(uint32_t)mk << 32) | (uint32_t)mk));
         }
         const uint32_t before = s_wc[w][d];
         rank[r] = before + (uint32_t)__popcll(peers & below);
@@ -3557,10 +3560,12 @@ __device__ void lds_radix_sort(uint64_t *__restrict__ s_key, uint32_t m, uint64_
             const bool ok = idx < m;
             const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
             uint64_t peers = __ballot(ok);
+            // keys past m read as 0 (digit 0): clear in every bit's ballot
 #pragma unroll
             for (int b = 0; b < kRadixBits; ++b) {
-                const uint64_t bb = __ballot(ok && ((d >> b) & 1u));
-                peers &= ((d >> b) & 1u) ? bb : ~bb;
+                const int32_t mk = (int32_t)(d << (31 - b)) >> 31;  // all ones when bit b is set
+                const uint64_t bb = __ballot(mk != 0);
+                peers &= ~(bb ^ (((uint64_t)(uint32_t)mk << 32) | (uint32_t)mk));
             }
             const uint32_t before = s_wc[w][d];
             rank[r] = before + (uint32_t)__popcll(peers & below);
